@@ -1,0 +1,207 @@
+/*
+ * helm.h -- C ABI of the MI355X Helmholtz solver library (libhelm.so).
+ *
+ * The library computes the scattered field of the discretised Helmholtz
+ * equation of Hong, Pham, Treister and Unser, "Diffraction Tomography with
+ * Helmholtz Equation: Efficient and Robust Multigrid-Based Solver"
+ * (arXiv 2107.03679):
+ *
+ *     A_Hel u_sc = b,  b = f u_in,  f = k0^2 (eta^2 - eta_b^2)
+ *
+ * (Sec. II-A eq. HelmScatterRightIncident; Sec. IV-A eq. discretizedHelm and
+ * the first-order Sommerfeld ghost rows), one solve per incident plane wave,
+ * batched over all waves of a scan, by restarted flexible GMRES preconditioned
+ * with one multigrid V-cycle on the shifted operator
+ * K_kappa = -Lap - kappa k0^2 eta^2 (Sec. IV-B/IV-C, Alg. 2), and the adjoint
+ * solves and refractive-index gradient of Sec. V (Prop. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Fields are complex64, interleaved {re, im} (helm_c32), on the EXTENDED
+ *    grid Omega_e (interior Omega plus the absorbing layer), laid out
+ *    [B][n_e][n_e] (2D) or [B][n_e][n_e][n_e] (3D), x fastest: point (m, n)
+ *    of right-hand side q is element q*n_e^2 + n*n_e + m (row order of
+ *    eq. discretizedHelm).  Omega is indices [w, w+n) per axis, w = the layer
+ *    width; n_e comes from helm_extended_size().
+ *  - Field pointers are DEVICE pointers (hipMalloc'd or torch tensors) unless
+ *    the name ends in _host.  The caller owns every buffer it passes and keeps
+ *    it alive until the call returns; calls are stream-ordered on the stream
+ *    given to helm_setup and return after that stream has finished the work.
+ *  - All operator semantics refer to the UNSCALED matrix A_Hel of
+ *    eq. discretizedHelm (1/h^2 Laplacian).  Internally the library solves the
+ *    h^2-scaled system, which has the same solution.
+ *  - Return codes: 0 = OK; HELM_NOT_CONVERGED (> 0) is soft: outputs hold the
+ *    best iterate and the per-RHS stats are valid; negative codes are hard
+ *    errors (outputs undefined), described by helm_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - One context per stream; calls on one context are not thread-safe.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_OK 0
+#define HELM_NOT_CONVERGED 1
+#define HELM_EINVAL (-1)
+#define HELM_EHIP (-2)
+#define HELM_ENOMEM (-3)
+#define HELM_ESTATE (-4)
+
+/* per-RHS status in helm_stats.status */
+#define HELM_STATUS_CONVERGED 0
+#define HELM_STATUS_NOT_CONVERGED 1
+#define HELM_STATUS_BREAKDOWN 2 /* non-finite data or a Krylov breakdown */
+
+typedef struct {
+  float re, im;
+} helm_c32;
+
+/* Grid (Sec. IV-A).  dim = 2 or 3; n = interior points per axis; abl_width =
+ * low-side absorbing-layer width in cells (the high side gets at least as
+ * many; see helm_extended_size); h = mesh size in the unit of 1/k0, or <= 0
+ * for the paper's normalisation of Omega_e to the unit square/cube,
+ * h = 1/(n_e - 1). */
+typedef struct {
+  int dim;
+  int n;
+  int abl_width;
+  double h;
+} helm_grid;
+
+/* Absorbing layer (Sec. IV-A): k0^2 eta^2 is multiplied on Omega_e \ Omega by
+ * alpha = 1 + j*sign*beta*|x - P_Omega(x)|^2 / L, L = abl_width*h.  sign = +1
+ * (default) is the dissipative reading under the e^{-j w t} convention;
+ * sign = -1 reproduces the printed sign.  profile 0 = the printed form
+ * (distances in the mesh's unit); profile 1 = beta*(|x - P x| / L)^2. */
+typedef struct {
+  double beta;
+  int sign;
+  int profile;
+} helm_abl;
+
+/* Solver options.  helm_default_opts() fills the defaults quoted here. */
+typedef struct {
+  double n_b;       /* background refractive index eta_b (1.333) */
+  double kappa_re;  /* shift of the preconditioning operator K_kappa (1.0) */
+  double kappa_im;  /*   ... imaginary part (0.5) */
+  double omega_jac; /* damped-Jacobi factor omega_S, eq. dampedJ (0.8) */
+  double rtol;      /* stop when ||b - A x|| <= rtol ||b||, true residual (1e-6) */
+  int levels;       /* multigrid levels incl. the exactly solved coarsest (4) */
+  int nu1, nu2;     /* pre/post relaxations (1, 1) */
+  int cycle;        /* 1 = V-cycle, 2 = W-cycle (Alg. 2 CycleType) (1) */
+  int restart;      /* FGMRES restart length m (10) */
+  int max_iters;    /* max preconditioner applications per RHS (4000) */
+  int max_batch;    /* largest B accepted by the solve calls (64) */
+  int reorth;       /* 1 = one re-orthogonalisation pass (CGS2) (0) */
+  int fused;        /* 1 = fused multigrid leg kernels when nu1 = nu2 = 1 (1) */
+  int use_graph;    /* 1 = replay each restart cycle as a captured hipGraph (1) */
+} helm_opts;
+
+typedef struct {
+  int iters;            /* preconditioner applications */
+  int status;           /* HELM_STATUS_* */
+  double rel_res_true;  /* ||b - A x|| / ||b|| of the returned x (float-float evaluation) */
+} helm_stats;
+
+typedef struct {
+  int dim, n, abl_width, n_e, levels, coarsest_n;
+  double h, k0, n_b;
+  size_t workspace_bytes;
+} helm_info;
+
+typedef struct helm_ctx helm_ctx;
+
+/* Defaults of helm_opts (see the field comments). */
+void helm_default_opts(helm_opts* opts);
+
+/* Extended grid size n_e for n interior points, a low-side layer of
+ * abl_width cells and `levels` multigrid levels: the smallest odd
+ * n_e >= n + 2*abl_width with (n_e - 1) divisible by 2^(levels-1), which the
+ * vertex-centred coarsening of Sec. IV-C needs.  Returns -1 on bad input. */
+int helm_extended_size(int n, int abl_width, int levels);
+
+/* Create a context: coefficient c = (k0 h)^2 eta^2 alpha on Omega_e and its
+ * restrictions per level (Sec. IV-C: full weighting, background ring), the
+ * exact inverse of the coarsest K_kappa (factorised on the host in FP64),
+ * the Krylov workspace for opts->max_batch right-hand sides.
+ *   n_map_dev : device float[n^dim], the refractive index on Omega (copied)
+ *   k0        : free-space wavenumber omega/c in the unit of 1/h
+ *   abl, opts : NULL = defaults (beta 0.15, sign +1, profile 0)
+ *   hip_stream: hipStream_t the context issues all work on (NULL = default)
+ * Errors: HELM_EINVAL for bad sizes, HELM_ENOMEM, HELM_EHIP. */
+int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const helm_abl* abl,
+               const helm_opts* opts, void* hip_stream, helm_ctx** out);
+
+/* Replace the refractive index (FBS iterations): recompute coefficients and
+ * the coarsest inverse; no reallocation. */
+int helm_update_n(helm_ctx* ctx, const float* n_map_dev);
+
+int helm_get_info(const helm_ctx* ctx, helm_info* info);
+
+/* Plane-wave right-hand sides (Sec. II-A): for q < B and unit directions
+ * dirs_host[q*dim .. q*dim+dim) (x, y[, z]),
+ *   u_in = exp(j k0 eta_b <d, x - x_c>) with x_c the centre of Omega,
+ *   rhs  = f * u_in, f = k0^2 (eta^2 - eta_b^2) on Omega, 0 in the layer.
+ * rhs: device [B][grid] (written).  u_in: device [B][grid] or NULL. */
+int helm_plane_wave_rhs(helm_ctx* ctx, int B, const double* dirs_host, helm_c32* rhs, helm_c32* u_in);
+
+/* Solve A_Hel x_q = rhs_q for q < B (B <= max_batch), x0 = 0, to
+ * ||rhs - A x|| <= rtol ||rhs|| (true residual, evaluated in float-float).
+ * rhs and x must not alias.  stats_host: B entries or NULL.
+ * Returns HELM_NOT_CONVERGED if any RHS did not converge. */
+int helm_solve_batch(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats_host);
+
+/* Adjoint solves A_Hel^H lam_q = rhs_q.  A_Hel is complex symmetric (the
+ * Sommerfeld terms only touch the diagonal), so lam = conj(A^-1 conj(rhs)):
+ * the forward solver with conjugated input and output. */
+int helm_adjoint_batch(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* lam, helm_stats* stats_host);
+
+/* Refractive-index gradient of a real loss through Prop. 1 (Sec. V):
+ *   grad_n[i] = sum_q 2 k0^2 eta_i Re(conj(u_q,i) lam_q,i) on Omega,
+ * with u_q the TOTAL field (u_in + u_sc) and lam_q = A^-H (dL/du_sc)^*-form
+ * adjoint states.  grad_n: device float[n^dim] (overwritten, Omega only). */
+int helm_grad_n(helm_ctx* ctx, int B, const helm_c32* u_total, const helm_c32* lam, float* grad_n);
+
+/* ---- building blocks, exposed for verification and custom solvers ---- */
+
+/* y = A_Hel x (unscaled), complex64 arithmetic. */
+int helm_apply_A(helm_ctx* ctx, int B, const helm_c32* x, helm_c32* y);
+
+/* r = rhs - A_Hel x evaluated in float-float (compensated FP32) with x
+ * given as x_hi + x_lo (x_lo may be NULL). */
+int helm_residual(helm_ctx* ctx, int B, const helm_c32* rhs, const helm_c32* x_hi, const helm_c32* x_lo,
+                  helm_c32* r);
+
+/* y = K'_level x: the h_level^2-scaled shifted operator of multigrid level
+ * `level` (0 = finest), fields on that level's grid [B][n_l]^dim. */
+int helm_apply_K(helm_ctx* ctx, int level, int B, const helm_c32* x, helm_c32* y);
+
+/* coarse = 4 R fine (full weighting, scaled coarse right-hand side) from
+ * level `level` to level+1. */
+int helm_restrict(helm_ctx* ctx, int level, int B, const helm_c32* fine, helm_c32* coarse);
+
+/* fine += P coarse (bilinear/trilinear prolongation) from level+1 to level. */
+int helm_prolong_add(helm_ctx* ctx, int level, int B, const helm_c32* coarse, helm_c32* fine);
+
+/* z = K'_coarsest^-1 r on the coarsest grid (explicit inverse). */
+int helm_coarse_solve(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
+
+/* z = M^-1 r: one multigrid cycle from a zero initial guess for the
+ * h^2-scaled fine system K'_0 z = r (the FGMRES preconditioner). */
+int helm_precondition(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
+
+/* Last error message of ctx (or of the last failed helm_setup if ctx is NULL). */
+const char* helm_last_error(const helm_ctx* ctx);
+
+void helm_destroy(helm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */
