@@ -156,6 +156,14 @@ int helm_plane_wave_rhs(helm_ctx* ctx, int B, const double* dirs_host, helm_c32*
  * Returns HELM_NOT_CONVERGED if any RHS did not converge. */
 int helm_solve_batch(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats_host);
 
+/* Low-order part of the float-float iterate of the last solve on ctx:
+ * the returned complex64 field x is x_hi, and x_hi + x_lo is the iterate whose
+ * residual helm_stats.rel_res_true reports (the complex64 rounding of the
+ * exact solution alone leaves a relative residual of order 1e-6..1e-5, so
+ * x_lo is what certifies tolerances near 1e-6).  For an adjoint solve the
+ * conjugation is applied.  x_lo: device [B][grid], B <= the last call's B. */
+int helm_solution_lo(helm_ctx* ctx, int B, helm_c32* x_lo);
+
 /* Adjoint solves A_Hel^H lam_q = rhs_q.  A_Hel is complex symmetric (the
  * Sommerfeld terms only touch the diagonal), so lam = conj(A^-1 conj(rhs)):
  * the forward solver with conjugated input and output. */
@@ -163,8 +171,10 @@ int helm_adjoint_batch(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* lam,
 
 /* Refractive-index gradient of a real loss through Prop. 1 (Sec. V):
  *   grad_n[i] = sum_q 2 k0^2 eta_i Re(conj(u_q,i) lam_q,i) on Omega,
- * with u_q the TOTAL field (u_in + u_sc) and lam_q = A^-H (dL/du_sc)^*-form
- * adjoint states.  grad_n: device float[n^dim] (overwritten, Omega only). */
+ * with u_q the TOTAL field (u_in + u_sc) and lam_q the adjoint states; for
+ * the quadratic data term 1/2 ||S u_sc,q - y_q||^2 on receiver samples S,
+ * lam_q = A^-H S^T (S u_sc,q - y_q).  grad_n: device float[n^dim]
+ * (overwritten, Omega only). */
 int helm_grad_n(helm_ctx* ctx, int B, const helm_c32* u_total, const helm_c32* lam, float* grad_n);
 
 /* ---- building blocks, exposed for verification and custom solvers ---- */

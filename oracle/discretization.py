@@ -12,9 +12,11 @@ Readings (where the paper is silent, ambiguous or inconsistent):
       Im(alpha) >= 0.  The printed alpha = 1 - j beta |x - P(x)|^2 / L is
       amplifying, so the default is alpha = 1 + j beta |x - P(x)|^2 / L;
       ``abl_sign=-1`` gives the printed sign.
-* A4  the layer profile uses the paper's normalised coordinates literally:
-      distances in units of h (= 1/(n_e - 1) of [0,1]) times h, and L = w h
-      with w the low-side layer width in cells.
+* A4  the layer profile uses the paper's normalisation of Omega_e to the
+      unit square literally (whatever the physical mesh size): distances
+      d = d_cells / (n_e - 1) and L = w / (n_e - 1) with w the low-side layer
+      width in cells, so gamma = beta d_cells^2 / (w (n_e - 1)) (profile 0).
+      Profile 1 is the alternative beta (d / L)^2 = beta d_cells^2 / w^2.
 * A5  vertex-centred coarsening needs n_e odd with (n_e - 1) divisible by
       2^(levels-1); n_e is the smallest such value >= n + 2 w and the extra
       cells go to the high-side layer.  Omega is indices [w, w + n).
@@ -60,6 +62,7 @@ class Problem:
     w: int = 20
     beta: float = 0.15
     abl_sign: int = +1
+    abl_profile: int = 0
     levels: int = 4
     kappa: complex = 1.0 + 0.5j
     omega_jac: float = 0.8
@@ -117,16 +120,20 @@ class Problem:
         ``idx_axes`` is a list of d index arrays broadcastable to a grid
         (level-ell indices are fine indices / 2^ell, so pass stride 2^ell).
         """
-        h = self.h
-        lo = self.w * h
-        hi = (self.w + self.n - 1) * h
+        lo = float(self.w)
+        hi = float(self.w + self.n - 1)
         dist2 = 0.0
         for ia in idx_axes:
-            x = np.asarray(ia, dtype=np.float64) * stride * h
+            x = np.asarray(ia, dtype=np.float64) * stride
             dx = np.maximum(0.0, np.maximum(lo - x, x - hi))
             dist2 = dist2 + dx * dx
-        L = self.w * h
-        gamma = self.beta * dist2 / L if L > 0 else 0.0 * dist2
+        if self.w <= 0:
+            gamma = 0.0 * dist2
+        elif self.abl_profile == 1:
+            gamma = self.beta * dist2 / float(self.w) ** 2
+        else:
+            unit = 1.0 / (self.n_e - 1)          # Omega_e normalised to [0, 1]
+            gamma = self.beta * (dist2 * unit * unit) / (self.w * unit)
         return 1.0 + 1j * self.abl_sign * gamma
 
     def alpha(self) -> np.ndarray:

@@ -1,0 +1,643 @@
+// C ABI of libhelm (declared in include/helm.h) and the host side of the
+// batched solver: level hierarchy, multigrid-cycle orchestration (Alg. 2),
+// the restarted FGMRES driver with a float-float outer iterate, and the
+// per-restart-cycle hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "kernels.h"
+#include "setup_host.h"
+
+using helm_host::cd;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct Level {
+  int n = 0;
+  long long N = 0;
+  c32* kc = nullptr;  // kappa * c_l
+  c32 ghost{};
+  c32* rc = nullptr;  // [maxB][N] right-hand side (levels >= 1)
+  c32* e = nullptr;   // [maxB][N] solution (levels >= 1)
+  c32* t = nullptr;   // [maxB][N] scratch of the generic path
+};
+
+struct HipError {
+  hipError_t code;
+  const char* what;
+};
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+
+c32 to_c32(cd v) { return make_float2((float)v.real(), (float)v.imag()); }
+
+}  // namespace
+
+struct helm_ctx {
+  helm_grid grid{};
+  helm_abl abl{};
+  helm_opts o{};
+  helm_host::Geometry geo{};
+  int dim = 2, n = 0, w = 0, ne = 0, L = 0;
+  double h = 0, k0 = 0, k0h = 0, kbh = 0;
+  long long N0 = 0;
+  hipStream_t s = nullptr;       // the context's own stream (graphs cannot capture the null stream)
+  hipStream_t user_s = nullptr;  // the caller's stream: work starts after it
+  std::string err;
+
+  // fine-level data
+  float* d_nmap = nullptr;   // interior index (for the gradient)
+  float* d_f = nullptr;      // f = k0^2 (eta^2 - eta_b^2) on Omega_e (0 in the layer), unscaled
+  c32* d_chi = nullptr;      // c = (k0 h)^2 eta^2 alpha, hi part
+  c32* d_clo = nullptr;      // ... lo part (float-float)
+  c32 g0_hi{}, g0_lo{};      // fine ghost factor, float-float
+  float h2_hi = 0, h2_lo = 0;
+  std::vector<Level> lv;
+  c32* d_minvT = nullptr;
+  int Nc = 0;
+
+  // Krylov workspace
+  KrylovArgs k{};
+  c32* d_xhi = nullptr;  // internal x (hi), [maxB][N0]
+  c32* d_xlo = nullptr;  // internal x (lo)
+  c32* d_rhs = nullptr;  // internal copy of the right-hand sides
+  c32* d_T0 = nullptr;   // generic-path scratch on the fine level
+  c32* d_tables = nullptr;
+  int* d_ones = nullptr;
+  int* h_status = nullptr;  // pinned
+  int* h_iters = nullptr;
+  double* h_relres = nullptr;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+
+  hipGraphExec_t graph = nullptr;
+  int graph_B = 0;
+  int last_B = 0;
+  int last_conj = 0;
+
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    check(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)), "hipMalloc");
+    allocs.push_back(p);
+    bytes += count * sizeof(T);
+    return (T*)p;
+  }
+};
+
+namespace {
+
+LevelArgs fine_A(const helm_ctx* c) { return LevelArgs{c->ne, c->N0, c->d_chi, c->g0_hi}; }
+LevelArgs level_K(const helm_ctx* c, int l) { return LevelArgs{c->lv[l].n, c->lv[l].N, c->lv[l].kc, c->lv[l].ghost}; }
+
+long long npts(int n, int dim) { return dim == 2 ? (long long)n * n : (long long)n * n * n; }
+
+// Copy B vectors of N elements between two strided vector sets.
+void copy_set(helm_ctx* c, int B, VecSet src, VecSet dst, long long N) {
+  check(hipMemcpy2DAsync(dst.p, dst.stride * sizeof(c32), src.p, src.stride * sizeof(c32), N * sizeof(c32), B,
+                         hipMemcpyDeviceToDevice, c->s),
+        "hipMemcpy2DAsync");
+}
+
+// nu Jacobi sweeps on level l: v <- v + w D^-1 (r - K v), ping-ponging through the level scratch.
+void relax(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet v, int sweeps, const int* act) {
+  const Level& L = c->lv[l];
+  VecSet t{l == 0 ? c->d_T0 : L.t, L.N};
+  for (int i = 0; i < sweeps; ++i) {
+    launch_jacobi(c->s, c->dim, B, r, rs, level_K(c, l), (float)c->o.omega_jac, v, t, act);
+    copy_set(c, B, t, v, L.N);
+  }
+}
+
+// Alg. 2 on level l for K'_l v = r, result in `out` (which holds the initial
+// guess when zero_guess is false).  Fused 2D legs serve the common case.
+void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act) {
+  const int dim = c->dim;
+  if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
+    launch_coarse_solve(c->s, B, c->d_minvT, c->Nc, r, out, act);
+    return;
+  }
+  Level& fine = c->lv[l];
+  Level& crs = c->lv[l + 1];
+  VecSet rc{crs.rc, crs.N}, ec{crs.e, crs.N};
+  const float om = (float)c->o.omega_jac;
+  const bool fused = c->o.fused && dim == 2 && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
+  if (fused) {
+    launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act);
+  } else {
+    int sweeps = c->o.nu1;
+    if (zero_guess) {
+      if (sweeps > 0) {
+        launch_jacobi_zero(c->s, dim, B, r, rs, level_K(c, l), om, out, act);
+        --sweeps;
+      } else {
+        launch_jacobi_zero(c->s, dim, B, r, rs, level_K(c, l), 0.0f, out, act);  // out = 0
+      }
+    }
+    relax(c, B, l, r, rs, out, sweeps, act);
+    launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
+  }
+  const bool next_is_coarsest = (l + 1 == c->L - 1);
+  for (int cyc = 0; cyc < std::max(1, c->o.cycle); ++cyc) {
+    if (cyc > 0 && next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
+    mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, cyc == 0, act);
+  }
+  if (fused) {
+    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ec, crs.n, out, act);
+  } else {
+    launch_prolong_add(c->s, dim, B, ec, crs.n, out, fine.n, act);
+    relax(c, B, l, r, rs, out, c->o.nu2, act);
+  }
+}
+
+// One Arnoldi step j for all active right-hand sides.
+void arnoldi_step(helm_ctx* c, int B, int j) {
+  KrylovArgs& k = c->k;
+  const long long N0 = c->N0;
+  VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
+  VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
+  ScaleSet sj{k.vs + j, k.m + 1};
+  mg_cycle(c, B, 0, vj, sj, zj, true, k.active);
+  const LevelArgs A = fine_A(c);
+  launch_arnoldi_dots(c->s, B, k, j, &A, 1);
+  launch_arnoldi_reduce(c->s, B, k, j, 0);
+  launch_arnoldi_update(c->s, B, k, j);
+  if (c->o.reorth) {
+    launch_arnoldi_dots(c->s, B, k, j, &A, 0);
+    launch_arnoldi_reduce(c->s, B, k, j, 1);
+    launch_arnoldi_update(c->s, B, k, j);
+  }
+  launch_givens(c->s, B, k, j);
+}
+
+void true_residual(helm_ctx* c, int B, int first, int conj_rhs) {
+  KrylovArgs& k = c->k;
+  launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_chi, c->d_clo, c->g0_hi,
+                     c->g0_lo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
+  launch_finalize(c->s, B, k, first);
+}
+
+// The body of one restart cycle: m Arnoldi steps, x update, true residual, decision.
+void restart_cycle(helm_ctx* c, int B, int conj_rhs) {
+  for (int j = 0; j < c->k.m; ++j) arnoldi_step(c, B, j);
+  launch_x_update(c->s, B, c->k, c->d_xhi, c->d_xlo);
+  true_residual(c, B, 0, conj_rhs);
+}
+
+int fail(helm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_setup_error = msg;
+  return code;
+}
+
+int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats, int conj) {
+  if (!c) return fail(nullptr, HELM_EINVAL, "null context");
+  if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
+  if (!rhs || !x) return fail(c, HELM_EINVAL, "null field pointer");
+  const long long N0 = c->N0;
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    check(hipMemcpyAsync(c->d_rhs, rhs, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy rhs");
+    launch_status_init(c->s, B, c->k);
+    launch_zero(c->s, (long long)B * N0, c->d_xhi);
+    launch_zero(c->s, (long long)B * N0, c->d_xlo);
+    true_residual(c, B, 1, conj);
+    const int max_cycles = c->o.max_iters / std::max(1, c->k.m) + 4;
+    // restart cycles, replayed from a graph captured on first use per (B, conj)
+    const bool use_graph = c->o.use_graph != 0;
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+      if (use_graph) {
+        if (c->graph == nullptr || c->graph_B != B * 2 + conj) {
+          if (c->graph) {
+            hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+          }
+          hipGraph_t g;
+          check(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+          restart_cycle(c, B, conj);
+          check(hipStreamEndCapture(c->s, &g), "hipStreamEndCapture");
+          check(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+          hipGraphDestroy(g);
+          c->graph_B = B * 2 + conj;
+        }
+        check(hipGraphLaunch(c->graph, c->s), "hipGraphLaunch");
+      } else {
+        restart_cycle(c, B, conj);
+      }
+      check(hipGetLastError(), "kernel launch");
+      check(hipMemcpyAsync(c->h_status, c->k.status, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "status D2H");
+      check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+      bool running = false;
+      for (int b = 0; b < B; ++b) running = running || c->h_status[b] == HELM_RUNNING;
+      if (!running) break;
+    }
+    c->last_B = B;
+    c->last_conj = conj;
+    if (conj) launch_conj_copy(c->s, (long long)B * N0, c->d_xhi, (c32*)x);
+    else check(hipMemcpyAsync(x, c->d_xhi, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy x");
+    check(hipMemcpyAsync(c->h_status, c->k.status, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "status");
+    check(hipMemcpyAsync(c->h_iters, c->k.iters, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "iters");
+    check(hipMemcpyAsync(c->h_relres, c->k.relres, B * sizeof(double), hipMemcpyDeviceToHost, c->s), "relres");
+    check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+    check(hipGetLastError(), "kernel launch");
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  }
+  int rc = HELM_OK;
+  for (int b = 0; b < B; ++b) {
+    int st = c->h_status[b];
+    if (st == HELM_RUNNING) st = HELM_STATUS_NOT_CONVERGED;
+    if (st != HELM_STATUS_CONVERGED) rc = HELM_NOT_CONVERGED;
+    if (stats) {
+      stats[b].iters = c->h_iters[b];
+      stats[b].status = st;
+      stats[b].rel_res_true = c->h_relres[b];
+    }
+  }
+  return rc;
+}
+
+// Host set-up of coefficients and the coarsest inverse, uploaded to the device.
+void upload_medium(helm_ctx* c, const float* n_map_dev) {
+  const long long Ni = npts(c->n, c->dim);
+  std::vector<float> nf(Ni);
+  check(hipMemcpy(nf.data(), n_map_dev, Ni * sizeof(float), hipMemcpyDeviceToHost), "copy n_map");
+  check(hipMemcpy(c->d_nmap, n_map_dev, Ni * sizeof(float), hipMemcpyDeviceToDevice), "copy n_map");
+  std::vector<double> nm(nf.begin(), nf.end());
+  const helm_host::Geometry& g = c->geo;
+  std::vector<cd> cf = helm_host::fine_coefficient(g, nm);
+  const long long N0 = c->N0;
+  std::vector<c32> hi(N0), lo(N0);
+  for (long long p = 0; p < N0; ++p) {
+    const float hr = (float)cf[p].real(), hm = (float)cf[p].imag();
+    hi[p] = make_float2(hr, hm);
+    lo[p] = make_float2((float)(cf[p].real() - hr), (float)(cf[p].imag() - hm));
+  }
+  check(hipMemcpy(c->d_chi, hi.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload c");
+  check(hipMemcpy(c->d_clo, lo.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload c");
+  // unscaled scattering potential f = k0^2 (eta^2 - eta_b^2) on Omega
+  std::vector<float> fpl(N0, 0.0f);
+  const double k02 = c->k0 * c->k0;
+  for (long long q = 0; q < Ni; ++q) {
+    const int ix = (int)(q % c->n), iy = (int)((q / c->n) % c->n), iz = c->dim == 3 ? (int)(q / ((long long)c->n * c->n)) : 0;
+    const long long p = c->dim == 2 ? (long long)(iy + c->w) * c->ne + (ix + c->w)
+                                    : ((long long)(iz + c->w) * c->ne + (iy + c->w)) * c->ne + (ix + c->w);
+    fpl[p] = (float)(k02 * (nm[q] * nm[q] - c->o.n_b * c->o.n_b));
+  }
+  check(hipMemcpy(c->d_f, fpl.data(), N0 * sizeof(float), hipMemcpyHostToDevice), "upload f");
+  const cd kappa(c->o.kappa_re, c->o.kappa_im);
+  std::vector<cd> cl = cf;
+  for (int l = 0; l < c->L; ++l) {
+    if (l > 0) cl = helm_host::coarse_coefficient(g, cl, c->lv[l - 1].n, l);
+    std::vector<c32> kc(cl.size());
+    for (size_t p = 0; p < cl.size(); ++p) kc[p] = to_c32(kappa * cl[p]);
+    check(hipMemcpy(c->lv[l].kc, kc.data(), kc.size() * sizeof(c32), hipMemcpyHostToDevice), "upload kc");
+  }
+  std::vector<cd> inv;
+  if (!helm_host::dense_inverse_transposed(g, cl, c->lv[c->L - 1].n, c->L - 1, kappa, inv))
+    throw HipError{hipErrorInvalidValue, "coarsest operator is singular"};
+  std::vector<c32> inv32(inv.size());
+  for (size_t p = 0; p < inv.size(); ++p) inv32[p] = to_c32(inv[p]);
+  check(hipMemcpy(c->d_minvT, inv32.data(), inv32.size() * sizeof(c32), hipMemcpyHostToDevice), "upload inverse");
+}
+
+void free_ctx(helm_ctx* c) {
+  if (!c) return;
+  if (c->graph) hipGraphExecDestroy(c->graph);
+  for (void* p : c->allocs) hipFree(p);
+  if (c->h_status) hipHostFree(c->h_status);
+  if (c->h_iters) hipHostFree(c->h_iters);
+  if (c->h_relres) hipHostFree(c->h_relres);
+  if (c->s) hipStreamDestroy(c->s);
+  delete c;
+}
+
+}  // namespace
+
+#define HELM_GUARD_BEGIN \
+  try {                  \
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+#define HELM_GUARD_END(name)                                                       \
+  check(hipGetLastError(), name);                                                  \
+  check(hipStreamSynchronize(c->s), "sync");                                       \
+  }                                                                                \
+  catch (const HipError& e) {                                                      \
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code)); \
+  }                                                                                \
+  return HELM_OK;
+
+extern "C" {
+
+void helm_default_opts(helm_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n_b = 1.333;
+  o->kappa_re = 1.0;
+  o->kappa_im = 0.5;
+  o->omega_jac = 0.8;
+  o->rtol = 1e-6;
+  o->levels = 4;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->cycle = 1;
+  o->restart = 10;
+  o->max_iters = 4000;
+  o->max_batch = 64;
+  o->reorth = 0;
+  o->fused = 1;
+  o->use_graph = 1;
+}
+
+int helm_extended_size(int n, int abl_width, int levels) { return helm_host::extended_size(n, abl_width, levels); }
+
+int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const helm_abl* abl, const helm_opts* opts,
+               void* hip_stream, helm_ctx** out) {
+  if (!out) return fail(nullptr, HELM_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!grid || !n_map_dev) return fail(nullptr, HELM_EINVAL, "null grid or n_map");
+  if (grid->dim != 2 && grid->dim != 3) return fail(nullptr, HELM_EINVAL, "dim must be 2 or 3");
+  if (grid->n < 1 || grid->abl_width < 0) return fail(nullptr, HELM_EINVAL, "bad interior size or layer width");
+  if (!(k0 > 0.0) || !std::isfinite(k0)) return fail(nullptr, HELM_EINVAL, "k0 must be positive");
+  helm_opts o;
+  helm_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.levels < 2 || o.levels > 12) return fail(nullptr, HELM_EINVAL, "levels must be in [2, 12]");
+  if (o.restart < 1 || o.restart > krylov_max_restart()) return fail(nullptr, HELM_EINVAL, "restart must be in [1, 64]");
+  if (o.max_batch < 1 || o.nu1 < 0 || o.nu2 < 0 || o.cycle < 1 || o.cycle > 2 || o.max_iters < 1 || !(o.rtol > 0))
+    return fail(nullptr, HELM_EINVAL, "bad solver options");
+  helm_abl a{0.15, 1, 0};
+  if (abl) a = *abl;
+  if (a.sign != 1 && a.sign != -1) return fail(nullptr, HELM_EINVAL, "abl sign must be +1 or -1");
+  const int ne = helm_host::extended_size(grid->n, grid->abl_width, o.levels);
+  if (ne < 3) return fail(nullptr, HELM_EINVAL, "grid too small");
+  const int nc = (ne - 1) / (1 << (o.levels - 1)) + 1;
+  if (nc < 2) return fail(nullptr, HELM_EINVAL, "too many levels for this grid");
+  const long long Nc = npts(nc, grid->dim);
+  if (Nc > 4096) return fail(nullptr, HELM_EINVAL, "coarsest grid too large for the dense inverse: add levels");
+
+  helm_ctx* c = new (std::nothrow) helm_ctx();
+  if (!c) return fail(nullptr, HELM_ENOMEM, "out of host memory");
+  try {
+    c->grid = *grid;
+    c->abl = a;
+    c->o = o;
+    c->dim = grid->dim;
+    c->n = grid->n;
+    c->w = grid->abl_width;
+    c->ne = ne;
+    c->L = o.levels;
+    c->h = grid->h > 0 ? grid->h : 1.0 / (ne - 1);
+    c->k0 = k0;
+    c->k0h = k0 * c->h;
+    c->kbh = c->k0h * o.n_b;
+    c->N0 = npts(ne, c->dim);
+    c->user_s = (hipStream_t)hip_stream;
+    check(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking), "hipStreamCreate");
+    c->geo = helm_host::Geometry{c->dim, c->n, c->w, ne, c->k0h, o.n_b, a.beta, a.sign, a.profile};
+    const double h2 = c->h * c->h;
+    c->h2_hi = (float)h2;
+    c->h2_lo = (float)(h2 - (double)c->h2_hi);
+    c->g0_hi = make_float2(1.0f, (float)c->kbh);
+    c->g0_lo = make_float2(0.0f, (float)(c->kbh - (double)(float)c->kbh));
+    const int maxB = o.max_batch, m = o.restart;
+    const long long N0 = c->N0;
+    c->lv.resize(c->L);
+    for (int l = 0; l < c->L; ++l) {
+      Level& L = c->lv[l];
+      L.n = (ne - 1) / (1 << l) + 1;
+      L.N = npts(L.n, c->dim);
+      L.ghost = make_float2(1.0f, (float)(c->kbh * std::ldexp(1.0, l)));
+      L.kc = c->alloc<c32>(L.N);
+      if (l > 0) {
+        L.rc = c->alloc<c32>((size_t)maxB * L.N);
+        L.e = c->alloc<c32>((size_t)maxB * L.N);
+        L.t = c->alloc<c32>((size_t)maxB * L.N);
+      }
+    }
+    c->Nc = (int)c->lv[c->L - 1].N;
+    c->d_minvT = c->alloc<c32>((size_t)c->Nc * c->Nc);
+    c->d_nmap = c->alloc<float>(npts(c->n, c->dim));
+    c->d_f = c->alloc<float>(N0);
+    c->d_chi = c->alloc<c32>(N0);
+    c->d_clo = c->alloc<c32>(N0);
+    c->d_xhi = c->alloc<c32>((size_t)maxB * N0);
+    c->d_xlo = c->alloc<c32>((size_t)maxB * N0);
+    c->d_rhs = c->alloc<c32>((size_t)maxB * N0);
+    c->d_T0 = c->alloc<c32>((size_t)maxB * N0);
+    c->d_tables = c->alloc<c32>((size_t)maxB * c->dim * ne);
+    c->d_ones = c->alloc<int>(maxB);
+    KrylovArgs& k = c->k;
+    k.dim = c->dim;
+    k.n = ne;
+    k.N = N0;
+    k.m = m;
+    k.nblk = krylov_blocks_per_rhs(N0);
+    k.V = c->alloc<c32>((size_t)maxB * (m + 1) * N0);
+    k.Z = c->alloc<c32>((size_t)maxB * m * N0);
+    k.vs = c->alloc<float>((size_t)maxB * (m + 1));
+    k.P1 = c->alloc<c32>((size_t)maxB * k.nblk * (m + 1));
+    k.P2 = c->alloc<float>((size_t)maxB * k.nblk);
+    k.H = c->alloc<double2>((size_t)maxB * (m + 1) * m);
+    k.cs = c->alloc<double>((size_t)maxB * m);
+    k.sn = c->alloc<double2>((size_t)maxB * m);
+    k.g = c->alloc<double2>((size_t)maxB * (m + 1));
+    k.coef = c->alloc<c32>((size_t)maxB * (m + 1));
+    k.y = c->alloc<c32>((size_t)maxB * m);
+    k.active = c->alloc<int>(maxB);
+    k.status = c->alloc<int>(maxB);
+    k.jcount = c->alloc<int>(maxB);
+    k.iters = c->alloc<int>(maxB);
+    k.bnorm = c->alloc<double>(maxB);
+    k.tol = c->alloc<double>(maxB);
+    k.relres = c->alloc<double>(maxB);
+    k.max_iters = o.max_iters;
+    k.rtol = o.rtol;
+    k.inner_factor = 0.5;
+    check(hipHostMalloc((void**)&c->h_status, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    check(hipHostMalloc((void**)&c->h_iters, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    check(hipHostMalloc((void**)&c->h_relres, maxB * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    std::vector<int> ones(maxB, 1);
+    check(hipMemcpy(c->d_ones, ones.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload ones");
+    upload_medium(c, n_map_dev);
+    check(hipDeviceSynchronize(), "setup");
+  } catch (const HipError& e) {
+    std::string msg = std::string(e.what) + ": " + hipGetErrorString(e.code);
+    free_ctx(c);
+    return fail(nullptr, e.code == hipErrorOutOfMemory ? HELM_ENOMEM : HELM_EHIP, msg);
+  } catch (const std::bad_alloc&) {
+    free_ctx(c);
+    return fail(nullptr, HELM_ENOMEM, "out of host memory");
+  }
+  *out = c;
+  return HELM_OK;
+}
+
+int helm_update_n(helm_ctx* c, const float* n_map_dev) {
+  if (!c || !n_map_dev) return fail(c, HELM_EINVAL, "null argument");
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    check(hipStreamSynchronize(c->s), "sync");
+    upload_medium(c, n_map_dev);
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  } catch (const std::bad_alloc&) {
+    return fail(c, HELM_ENOMEM, "out of host memory");
+  }
+  return HELM_OK;
+}
+
+int helm_get_info(const helm_ctx* c, helm_info* info) {
+  if (!c || !info) return HELM_EINVAL;
+  info->dim = c->dim;
+  info->n = c->n;
+  info->abl_width = c->w;
+  info->n_e = c->ne;
+  info->levels = c->L;
+  info->coarsest_n = c->lv[c->L - 1].n;
+  info->h = c->h;
+  info->k0 = c->k0;
+  info->n_b = c->o.n_b;
+  info->workspace_bytes = c->bytes;
+  return HELM_OK;
+}
+
+int helm_plane_wave_rhs(helm_ctx* c, int B, const double* dirs, helm_c32* rhs, helm_c32* u_in) {
+  if (!c || !dirs || !rhs) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
+  const int ne = c->ne, dim = c->dim;
+  std::vector<c32> tab((size_t)B * dim * ne);
+  const double centre = c->w + 0.5 * (c->n - 1);
+  for (int b = 0; b < B; ++b)
+    for (int a = 0; a < dim; ++a) {
+      const double d = dirs[b * dim + a];
+      for (int i = 0; i < ne; ++i) {
+        const double ph = c->kbh * d * (i - centre);
+        tab[((size_t)b * dim + a) * ne + i] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+      }
+    }
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    check(hipMemcpyAsync(c->d_tables, tab.data(), tab.size() * sizeof(c32), hipMemcpyHostToDevice, c->s), "tables");
+    launch_plane_wave(c->s, dim, B, ne, c->d_f, c->d_tables, (c32*)rhs, (c32*)u_in);
+    check(hipGetLastError(), "plane wave");
+    check(hipStreamSynchronize(c->s), "sync");
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  }
+  return HELM_OK;
+}
+
+int helm_solve_batch(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats) {
+  return run_solve(c, B, rhs, x, stats, 0);
+}
+
+int helm_adjoint_batch(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* lam, helm_stats* stats) {
+  return run_solve(c, B, rhs, lam, stats, 1);
+}
+
+int helm_solution_lo(helm_ctx* c, int B, helm_c32* x_lo) {
+  if (!c || !x_lo) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1 || B > c->last_B) return fail(c, HELM_EINVAL, "B must be in [1, B of the last solve]");
+  HELM_GUARD_BEGIN
+  if (c->last_conj) launch_conj_copy(c->s, (long long)B * c->N0, c->d_xlo, (c32*)x_lo);
+  else check(hipMemcpyAsync(x_lo, c->d_xlo, (size_t)B * c->N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy");
+  HELM_GUARD_END("solution_lo")
+}
+
+int helm_grad_n(helm_ctx* c, int B, const helm_c32* u_total, const helm_c32* lam, float* grad_n) {
+  if (!c || !u_total || !lam || !grad_n) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_total, (const c32*)lam, c->d_nmap,
+                  (float)(2.0 * c->k0 * c->k0), grad_n);
+    check(hipGetLastError(), "grad_n");
+    check(hipStreamSynchronize(c->s), "sync");
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  }
+  return HELM_OK;
+}
+
+
+int helm_apply_A(helm_ctx* c, int B, const helm_c32* x, helm_c32* y) {
+  if (!c || !x || !y || B < 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_apply(c->s, c->dim, B, VecSet{(c32*)x, c->N0}, ScaleSet{nullptr, 0}, fine_A(c), (float)(1.0 / (c->h * c->h)),
+               VecSet{(c32*)y, c->N0}, nullptr);
+  HELM_GUARD_END("apply_A")
+}
+
+int helm_residual(helm_ctx* c, int B, const helm_c32* rhs, const helm_c32* x_hi, const helm_c32* x_lo, helm_c32* r) {
+  if (!c || !rhs || !x_hi || !r || B < 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  KrylovArgs k = c->k;
+  k.status = nullptr;
+  k.P2 = nullptr;
+  launch_residual_ff(c->s, B, k, (const c32*)rhs, c->N0, 0, (const c32*)x_hi, (const c32*)x_lo, 0, c->d_chi,
+                     c->d_clo, c->g0_hi, c->g0_lo, c->h2_hi, c->h2_lo, (c32*)r, c->N0, (float)(1.0 / (c->h * c->h)));
+  HELM_GUARD_END("residual")
+}
+
+int helm_apply_K(helm_ctx* c, int level, int B, const helm_c32* x, helm_c32* y) {
+  if (!c || !x || !y || B < 1 || level < 0 || level >= c->L) return fail(c, HELM_EINVAL, "bad argument");
+  const long long N = c->lv[level].N;
+  HELM_GUARD_BEGIN
+  launch_apply(c->s, c->dim, B, VecSet{(c32*)x, N}, ScaleSet{nullptr, 0}, level_K(c, level), 1.0f, VecSet{(c32*)y, N},
+               nullptr);
+  HELM_GUARD_END("apply_K")
+}
+
+int helm_restrict(helm_ctx* c, int level, int B, const helm_c32* fine, helm_c32* coarse) {
+  if (!c || !fine || !coarse || B < 1 || level < 0 || level >= c->L - 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_restrict_residual(c->s, c->dim, B, VecSet{(c32*)fine, c->lv[level].N}, ScaleSet{nullptr, 0},
+                           VecSet{nullptr, 0}, level_K(c, level), VecSet{(c32*)coarse, c->lv[level + 1].N},
+                           c->lv[level + 1].n, nullptr);
+  HELM_GUARD_END("restrict")
+}
+
+int helm_prolong_add(helm_ctx* c, int level, int B, const helm_c32* coarse, helm_c32* fine) {
+  if (!c || !fine || !coarse || B < 1 || level < 0 || level >= c->L - 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_prolong_add(c->s, c->dim, B, VecSet{(c32*)coarse, c->lv[level + 1].N}, c->lv[level + 1].n,
+                     VecSet{(c32*)fine, c->lv[level].N}, c->lv[level].n, nullptr);
+  HELM_GUARD_END("prolong")
+}
+
+int helm_coarse_solve(helm_ctx* c, int B, const helm_c32* r, helm_c32* z) {
+  if (!c || !r || !z || B < 1) return fail(c, HELM_EINVAL, "bad argument");
+  const long long N = c->lv[c->L - 1].N;
+  HELM_GUARD_BEGIN
+  launch_coarse_solve(c->s, B, c->d_minvT, c->Nc, VecSet{(c32*)r, N}, VecSet{(c32*)z, N}, nullptr);
+  HELM_GUARD_END("coarse_solve")
+}
+
+int helm_precondition(helm_ctx* c, int B, const helm_c32* r, helm_c32* z) {
+  if (!c || !r || !z || B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  mg_cycle(c, B, 0, VecSet{(c32*)r, c->N0}, ScaleSet{nullptr, 0}, VecSet{(c32*)z, c->N0}, true, c->d_ones);
+  HELM_GUARD_END("precondition")
+}
+
+const char* helm_last_error(const helm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void helm_destroy(helm_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->s);
+  free_ctx(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Device helpers shared by the HIP kernels: complex64 arithmetic, float-float
+// (double-float) arithmetic built from error-free transforms, wavefront and
+// block reductions, and grid geometry of the vertex-centred levels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+#define HELM_WAVE 64
+
+
+// ---------------------------------------------------------------- complex64
+__host__ __device__ __forceinline__ c32 cadd(c32 a, c32 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ c32 csub(c32 a, c32 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ c32 cscale(c32 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// conj(a) * b
+__host__ __device__ __forceinline__ c32 cconjmul(c32 a, c32 b) {
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x));
+}
+// acc + a * b
+__host__ __device__ __forceinline__ c32 cfma(c32 a, c32 b, c32 acc) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+// 1 / d via conj(d) / |d|^2
+__host__ __device__ __forceinline__ c32 crcp(c32 d) {
+  float inv = 1.0f / fmaf(d.x, d.x, d.y * d.y);
+  return make_float2(d.x * inv, -d.y * inv);
+}
+__host__ __device__ __forceinline__ c32 cconj(c32 a) { return make_float2(a.x, -a.y); }
+
+// ------------------------------------------------------------- float-float
+// A value hi + lo with |lo| <= ulp(hi)/2.  TwoSum (Knuth) and TwoProd (FMA)
+// are error-free; the compound operations follow the usual double-float
+// algorithms (Dekker 1971; Hida, Li and Bailey 2001) with ~2^-44 relative
+// error, far below what the residual test needs.
+// Device code is compiled with FP contraction enabled and the AMDGPU backend
+// fuses aggressively (a product feeding several adds becomes FMAs); that
+// would break the error-free transforms, so contraction is switched off
+// inside every float-float routine.
+#define HELM_NO_CONTRACT _Pragma("clang fp contract(off)")
+
+struct ff {
+  float hi, lo;
+};
+
+__host__ __device__ __forceinline__ ff two_sum(float a, float b) {
+  HELM_NO_CONTRACT
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__host__ __device__ __forceinline__ ff fast_two_sum(float a, float b) {
+  HELM_NO_CONTRACT
+  float s = a + b;
+  float e = b - (s - a);
+  return {s, e};
+}
+__host__ __device__ __forceinline__ ff two_prod(float a, float b) {
+  HELM_NO_CONTRACT
+  float p = a * b;
+  float e = fmaf(a, b, -p);
+  return {p, e};
+}
+__host__ __device__ __forceinline__ ff ff_add(ff a, ff b) {
+  HELM_NO_CONTRACT
+  ff s = two_sum(a.hi, b.hi);
+  ff t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__host__ __device__ __forceinline__ ff ff_neg(ff a) {
+  HELM_NO_CONTRACT return {-a.hi, -a.lo}; }
+__host__ __device__ __forceinline__ ff ff_sub(ff a, ff b) {
+  HELM_NO_CONTRACT return ff_add(a, ff_neg(b)); }
+__host__ __device__ __forceinline__ ff ff_mul(ff a, ff b) {
+  HELM_NO_CONTRACT
+  ff p = two_prod(a.hi, b.hi);
+  p.lo = fmaf(a.hi, b.lo, fmaf(a.lo, b.hi, p.lo));
+  return fast_two_sum(p.hi, p.lo);
+}
+__host__ __device__ __forceinline__ ff ff_from(float a) { return {a, 0.0f}; }
+
+struct cff {
+  ff re, im;
+};
+__host__ __device__ __forceinline__ cff cff_add(cff a, cff b) {
+  HELM_NO_CONTRACT return {ff_add(a.re, b.re), ff_add(a.im, b.im)}; }
+__host__ __device__ __forceinline__ cff cff_sub(cff a, cff b) {
+  HELM_NO_CONTRACT return {ff_sub(a.re, b.re), ff_sub(a.im, b.im)}; }
+__host__ __device__ __forceinline__ cff cff_mul(cff a, cff b) {
+  HELM_NO_CONTRACT
+  return {ff_sub(ff_mul(a.re, b.re), ff_mul(a.im, b.im)), ff_add(ff_mul(a.re, b.im), ff_mul(a.im, b.re))};
+}
+__host__ __device__ __forceinline__ cff cff_make(c32 hi, c32 lo) { return {{hi.x, lo.x}, {hi.y, lo.y}}; }
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = HELM_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, HELM_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = HELM_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, HELM_WAVE);
+  return v;
+}
+
+// -------------------------------------------------------------- geometry
+// Number of Sommerfeld ghost neighbours of point (x, y[, z]) on an n^d grid.
+__host__ __device__ __forceinline__ int ghosts2(int x, int y, int n) {
+  return (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+}
+__host__ __device__ __forceinline__ int ghosts3(int x, int y, int z, int n) {
+  return (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
+}
+
+__device__ __forceinline__ float scale_of(ScaleSet s, int b) { return s.p ? s.p[(long long)b * s.stride] : 1.0f; }
+
+// diagonal of the level operator: 2d - coef - g * #ghosts
+__device__ __forceinline__ c32 diag_at(const LevelArgs& lv, long long p, int ng, int dim) {
+  c32 c = lv.coef[p];
+  return make_float2(2.0f * dim - c.x - ng * lv.ghost.x, -c.y - ng * lv.ghost.y);
+}
+
+struct Coord {
+  int x, y, z;
+};
+__host__ __device__ __forceinline__ Coord coord_of(long long p, int n, int dim) {
+  Coord c;
+  c.x = (int)(p % n);
+  long long q = p / n;
+  if (dim == 2) {
+    c.y = (int)q;
+    c.z = 0;
+  } else {
+    c.y = (int)(q % n);
+    c.z = (int)(q / n);
+  }
+  return c;
+}
+__host__ __device__ __forceinline__ int ghosts_of(const Coord& c, int n, int dim) {
+  return dim == 2 ? ghosts2(c.x, c.y, n) : ghosts3(c.x, c.y, c.z, n);
+}
+// sum of the in-grid neighbours of point p
+__device__ __forceinline__ c32 neighbour_sum(const c32* v, long long p, const Coord& c, int n, int dim) {
+  c32 s = make_float2(0.f, 0.f);
+  if (c.x > 0) s = cadd(s, v[p - 1]);
+  if (c.x < n - 1) s = cadd(s, v[p + 1]);
+  if (c.y > 0) s = cadd(s, v[p - n]);
+  if (c.y < n - 1) s = cadd(s, v[p + n]);
+  if (dim == 3) {
+    const long long n2 = (long long)n * n;
+    if (c.z > 0) s = cadd(s, v[p - n2]);
+    if (c.z < n - 1) s = cadd(s, v[p + n2]);
+  }
+  return s;
+}
+

@@ -1,0 +1,58 @@
+// Per-point float-float residual r = h^2 b - A'(x_hi + x_lo), shared by the
+// GPU kernel and host-side verification builds (all arithmetic is FP32
+// error-free transforms; no FP64).
+#pragma once
+
+#include "dev_common.h"
+
+struct FFArgs {
+  const c32* rhs;
+  long long rhs_stride;
+  int conj_rhs;
+  const c32* x_hi;
+  const c32* x_lo;
+  int x_zero;
+  const c32* c_hi;
+  const c32* c_lo;
+  c32 g_hi, g_lo;
+  float h2_hi, h2_lo;
+  c32* r_out;
+  long long r_stride;
+  float out_scale;
+};
+
+__host__ __device__ __forceinline__ cff ff_load_x(const c32* xh, const c32* xl, long long p) {
+  return cff_make(xh[p], xl ? xl[p] : make_float2(0.f, 0.f));
+}
+
+// rb, xh, xl point at this right-hand side's vectors (xh == NULL: x = 0).
+__host__ __device__ inline c32 ff_residual_point(const FFArgs& a, const c32* rb, const c32* xh, const c32* xl,
+                                                 long long p, int n, int dim) {
+  const ff h2 = {a.h2_hi, a.h2_lo};
+  c32 bv = rb[p];
+  if (a.conj_rhs) bv.y = -bv.y;
+  cff r = {ff_mul(ff_from(bv.x), h2), ff_mul(ff_from(bv.y), h2)};
+  if (xh) {
+    const Coord c = coord_of(p, n, dim);
+    const int ng = ghosts_of(c, n, dim);
+    // D = 2d - c - ng g, in float-float
+    const cff cc = cff_make(a.c_hi[p], a.c_lo[p]);
+    const cff gg = cff_make(a.g_hi, a.g_lo);
+    const cff ngg = {ff_mul(ff_from((float)ng), gg.re), ff_mul(ff_from((float)ng), gg.im)};
+    const cff D = cff_sub(cff_sub({ff_from(2.0f * dim), ff_from(0.f)}, cc), ngg);
+    cff ax = cff_mul(D, ff_load_x(xh, xl, p));
+    cff nb = {ff_from(0.f), ff_from(0.f)};
+    if (c.x > 0) nb = cff_add(nb, ff_load_x(xh, xl, p - 1));
+    if (c.x < n - 1) nb = cff_add(nb, ff_load_x(xh, xl, p + 1));
+    if (c.y > 0) nb = cff_add(nb, ff_load_x(xh, xl, p - n));
+    if (c.y < n - 1) nb = cff_add(nb, ff_load_x(xh, xl, p + n));
+    if (dim == 3) {
+      const long long n2 = (long long)n * n;
+      if (c.z > 0) nb = cff_add(nb, ff_load_x(xh, xl, p - n2));
+      if (c.z < n - 1) nb = cff_add(nb, ff_load_x(xh, xl, p + n2));
+    }
+    ax = cff_sub(ax, nb);
+    r = cff_sub(r, ax);
+  }
+  return make_float2(r.re.hi + r.re.lo, r.im.hi + r.im.lo);
+}

@@ -1,0 +1,396 @@
+// Batched restarted FGMRES kernels (right preconditioning) with a float-float
+// outer iterate.  Every kernel takes all B right-hand sides of a scan; a
+// per-RHS `active` flag makes converged systems skip their work.
+//
+// One Arnoldi step j for right-hand side q:
+//   z_j = M(v_j)                       (multigrid kernels)
+//   w   = A z_j,  d_i = <V_i, w>       (k_arnoldi_dots, fused matvec + dots)
+//   h_i = vs_i d_i                     (k_arnoldi_reduce, FP64)
+//   w  -= sum_i h_i v_i, ||w||^2       (k_arnoldi_update)
+//   Givens update of column j, residual estimate, v_{j+1} = w / h_{j+1,j}
+//                                      (k_givens, FP64, one wavefront per RHS)
+// The basis is stored unnormalised with a scale per vector (v_i = vs_i V_i),
+// which saves the normalisation pass.  <a, b> = a^H b.
+#include "dev_common.h"
+#include "ff_residual.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int NT = 256;       // threads per block of the flat kernels
+constexpr int PPT = 8;        // points per thread
+constexpr int CH = NT * PPT;  // points per block
+constexpr int NWAVE = NT / HELM_WAVE;
+constexpr int MAXM = 64;
+
+__device__ __forceinline__ long long vidx(const KrylovArgs& k, int b, int i) {
+  return ((long long)b * (k.m + 1) + i) * k.N;
+}
+__device__ __forceinline__ long long zidx(const KrylovArgs& k, int b, int i) {
+  return ((long long)b * k.m + i) * k.N;
+}
+
+// A' z at point p (complex64): (2d - c - g #ghosts) z_p - sum of neighbours
+__device__ __forceinline__ c32 apply_point(const LevelArgs& lv, int dim, const c32* z, long long p) {
+  const Coord c = coord_of(p, lv.n, dim);
+  const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
+  return csub(cmul(D, z[p]), neighbour_sum(z, p, c, lv.n, dim));
+}
+
+__global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelArgs fine, int with_matvec) {
+  __shared__ c32 red[NWAVE][MAXM + 1];
+  const int b = blockIdx.y;
+  if (!k.active[b]) return;
+  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  c32* w_out = k.V + vidx(k, b, j + 1);
+  c32 w[PPT];
+  if (with_matvec) {
+    const c32* z = k.Z + zidx(k, b, j);
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      w[t] = make_float2(0.f, 0.f);
+      if (p < k.N) {
+        w[t] = apply_point(fine, k.dim, z, p);
+        w_out[p] = w[t];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      w[t] = p < k.N ? w_out[p] : make_float2(0.f, 0.f);
+    }
+  }
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  for (int i = 0; i <= j; ++i) {
+    const c32* vi = k.V + vidx(k, b, i);
+    c32 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      if (p < k.N) acc = cadd(acc, cconjmul(vi[p], w[t]));
+    }
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) red[wave][i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += NT) {
+    c32 s = red[0][i];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) s = cadd(s, red[q][i]);
+    k.P1[((long long)b * k.nblk + blockIdx.x) * (k.m + 1) + i] = s;
+  }
+}
+
+// h_i = vs_i * sum over blocks of the partial dots (FP64, fixed order: deterministic)
+__global__ __launch_bounds__(NT) void k_arnoldi_reduce(KrylovArgs k, int j, int accumulate) {
+  const int b = blockIdx.x;
+  if (!k.active[b]) return;
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  for (int i = wave; i <= j; i += NWAVE) {
+    double sx = 0.0, sy = 0.0;
+    for (int blk = lane; blk < k.nblk; blk += HELM_WAVE) {
+      const c32 v = k.P1[((long long)b * k.nblk + blk) * (k.m + 1) + i];
+      sx += v.x;
+      sy += v.y;
+    }
+    sx = wave_sum_d(sx);
+    sy = wave_sum_d(sy);
+    if (lane == 0) {
+      const double vsi = k.vs[b * (k.m + 1) + i];
+      const double hx = sx * vsi, hy = sy * vsi;
+      double2* hij = &k.H[((long long)b * (k.m + 1) + i) * k.m + j];
+      if (accumulate) {
+        hij->x += hx;
+        hij->y += hy;
+      } else {
+        *hij = make_double2(hx, hy);
+      }
+      k.coef[b * (k.m + 1) + i] = make_float2((float)(hx * vsi), (float)(hy * vsi));
+    }
+  }
+}
+
+// w -= sum_i coef_i V_i; partial ||w||^2
+__global__ __launch_bounds__(NT) void k_arnoldi_update(KrylovArgs k, int j) {
+  __shared__ float red[NWAVE];
+  const int b = blockIdx.y;
+  if (!k.active[b]) return;
+  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  c32* wv = k.V + vidx(k, b, j + 1);
+  c32 w[PPT];
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    w[t] = p < k.N ? wv[p] : make_float2(0.f, 0.f);
+  }
+  for (int i = 0; i <= j; ++i) {
+    const c32 ci = k.coef[b * (k.m + 1) + i];
+    const c32 nci = make_float2(-ci.x, -ci.y);
+    const c32* vi = k.V + vidx(k, b, i);
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      if (p < k.N) w[t] = cfma(nci, vi[p], w[t]);
+    }
+  }
+  float nrm = 0.f;
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p < k.N) {
+      wv[p] = w[t];
+      nrm = fmaf(w[t].x, w[t].x, fmaf(w[t].y, w[t].y, nrm));
+    }
+  }
+  nrm = wave_sum(nrm);
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  if (lane == 0) red[wave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) s += red[q];
+    k.P2[(long long)b * k.nblk + blockIdx.x] = s;
+  }
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double zabs(double2 a) { return hypot(a.x, a.y); }
+
+// Back-substitution y = H(0:kk, 0:kk)^-1 g(0:kk) for right-hand side b (FP64, one thread).
+__device__ void back_substitute(const KrylovArgs& k, int b, int kk) {
+  double2 yd[MAXM];
+  const double2* H = k.H + (long long)b * (k.m + 1) * k.m;
+  const double2* g = k.g + (long long)b * (k.m + 1);
+  for (int i = kk - 1; i >= 0; --i) {
+    double2 s = g[i];
+    for (int l = i + 1; l < kk; ++l) {
+      const double2 t = zmul(H[i * k.m + l], yd[l]);
+      s.x -= t.x;
+      s.y -= t.y;
+    }
+    const double2 d = H[i * k.m + i];
+    const double den = d.x * d.x + d.y * d.y;
+    yd[i] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+  }
+  for (int i = 0; i < k.m; ++i)
+    k.y[b * k.m + i] = i < kk ? make_float2((float)yd[i].x, (float)yd[i].y) : make_float2(0.f, 0.f);
+}
+
+// Givens update of column j (FP64), residual estimate, stop decision, least squares at cycle end.
+__global__ __launch_bounds__(HELM_WAVE) void k_givens(KrylovArgs k, int j) {
+  const int b = blockIdx.x;
+  if (!k.active[b]) return;
+  double s = 0.0;
+  for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) s += k.P2[(long long)b * k.nblk + blk];
+  s = wave_sum_d(s);
+  if (threadIdx.x != 0) return;
+  const int m = k.m;
+  double2* H = k.H + (long long)b * (m + 1) * m;
+  double* cs = k.cs + (long long)b * m;
+  double2* sn = k.sn + (long long)b * m;
+  double2* g = k.g + (long long)b * (m + 1);
+  const double hj1 = sqrt(s);
+  // previous rotations G_i = [[c, s], [-conj(s), c]] on rows i, i+1
+  for (int i = 0; i < j; ++i) {
+    const double2 a = H[i * m + j], c2 = H[(i + 1) * m + j];
+    const double2 t1 = zmul(sn[i], c2);
+    const double2 t2 = zmul(zconj(sn[i]), a);
+    H[i * m + j] = make_double2(cs[i] * a.x + t1.x, cs[i] * a.y + t1.y);
+    H[(i + 1) * m + j] = make_double2(cs[i] * c2.x - t2.x, cs[i] * c2.y - t2.y);
+  }
+  const double2 a = H[j * m + j];
+  const double aa = zabs(a);
+  double c;
+  double2 sv;
+  if (hj1 == 0.0) {
+    c = 1.0;
+    sv = make_double2(0.0, 0.0);
+  } else if (aa == 0.0) {
+    c = 0.0;
+    sv = make_double2(1.0, 0.0);
+  } else {
+    const double rho = hypot(aa, hj1);
+    c = aa / rho;
+    sv = make_double2(a.x / aa * hj1 / rho, a.y / aa * hj1 / rho);  // (a/|a|) conj(hj1) / rho, hj1 real
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  H[j * m + j] = make_double2(c * a.x + sv.x * hj1, c * a.y + sv.y * hj1);
+  H[(j + 1) * m + j] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  const double2 t = zmul(zconj(sv), gj);
+  g[j + 1] = make_double2(-t.x, -t.y);
+  g[j] = make_double2(c * gj.x, c * gj.y);
+  const double est = zabs(g[j + 1]);
+  const int it = ++k.iters[b];
+  k.jcount[b] = j + 1;
+  if (!isfinite(est) || !isfinite(hj1) || !isfinite(zabs(H[j * m + j]))) {
+    // discard this step: the last good least-squares solution is the previous column set
+    k.status[b] = HELM_STATUS_BREAKDOWN_DEV;
+    k.active[b] = 0;
+    k.jcount[b] = 0;
+    return;
+  }
+  k.vs[b * (m + 1) + j + 1] = hj1 > 0.0 ? (float)(1.0 / hj1) : 0.0f;
+  const bool stop = est <= k.tol[b] || hj1 == 0.0 || it >= k.max_iters;
+  if (stop) k.active[b] = 0;
+  if (stop || j == m - 1) back_substitute(k, b, j + 1);
+}
+
+// x += sum_{i < jcount} y_i Z_i, accumulated into the float-float pair (x_hi, x_lo)
+__global__ __launch_bounds__(NT) void k_x_update(KrylovArgs k, c32* x_hi, c32* x_lo) {
+  const int b = blockIdx.y;
+  const int kk = k.jcount[b];
+  if (kk == 0) return;
+  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  c32 d[PPT];
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) d[t] = make_float2(0.f, 0.f);
+  for (int i = 0; i < kk; ++i) {
+    const c32 yi = k.y[b * k.m + i];
+    const c32* zi = k.Z + zidx(k, b, i);
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      if (p < k.N) d[t] = cfma(yi, zi[p], d[t]);
+    }
+  }
+  c32* xh = x_hi + (long long)b * k.N;
+  c32* xl = x_lo + (long long)b * k.N;
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p < k.N) {
+      const c32 h = xh[p], l = xl[p];
+      ff re = ff_add({h.x, l.x}, ff_from(d[t].x));
+      ff im = ff_add({h.y, l.y}, ff_from(d[t].y));
+      xh[p] = make_float2(re.hi, im.hi);
+      xl[p] = make_float2(re.lo, im.lo);
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
+  __shared__ float red[NWAVE];
+  const int b = blockIdx.y;
+  if (k.status && k.status[b] != HELM_RUNNING) return;
+  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  const int n = k.n, dim = k.dim;
+  const c32* rb = a.rhs + (long long)b * a.rhs_stride;
+  const c32* xh = a.x_zero ? nullptr : a.x_hi + (long long)b * k.N;
+  const c32* xl = (a.x_zero || !a.x_lo) ? nullptr : a.x_lo + (long long)b * k.N;
+  c32* ro = a.r_out + (long long)b * a.r_stride;
+  float nrm = 0.f;
+#pragma unroll 2
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p >= k.N) continue;
+    const c32 rv = ff_residual_point(a, rb, xh, xl, p, n, dim);
+    ro[p] = cscale(rv, a.out_scale);
+    nrm = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, nrm));
+  }
+  if (!k.P2) return;
+  nrm = wave_sum(nrm);
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  if (lane == 0) red[wave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) s += red[q];
+    k.P2[(long long)b * k.nblk + blockIdx.x] = s;
+  }
+}
+
+// After a true residual: decide convergence, else restart the cycle from r.
+__global__ __launch_bounds__(HELM_WAVE) void k_finalize(KrylovArgs k, int first) {
+  const int b = blockIdx.x;
+  if (k.status[b] != HELM_RUNNING) return;
+  double s = 0.0;
+  for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) s += k.P2[(long long)b * k.nblk + blk];
+  s = wave_sum_d(s);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(s);
+  k.jcount[b] = 0;
+  k.active[b] = 0;
+  if (first) {
+    k.bnorm[b] = rn;
+    k.tol[b] = k.rtol * k.inner_factor * rn;
+  }
+  const double bn = k.bnorm[b];
+  if (!isfinite(rn) || !isfinite(bn)) {
+    k.status[b] = HELM_STATUS_BREAKDOWN_DEV;
+    k.relres[b] = rn / bn;
+    return;
+  }
+  const double rel = bn > 0.0 ? rn / bn : 0.0;
+  k.relres[b] = rel;
+  if (rel <= k.rtol) {
+    k.status[b] = HELM_STATUS_CONVERGED_DEV;
+    return;
+  }
+  if (k.iters[b] >= k.max_iters) {
+    k.status[b] = HELM_STATUS_NOT_CONVERGED_DEV;
+    return;
+  }
+  k.active[b] = 1;
+  k.vs[b * (k.m + 1)] = (float)(1.0 / rn);
+  double2* g = k.g + (long long)b * (k.m + 1);
+  g[0] = make_double2(rn, 0.0);
+  for (int i = 1; i <= k.m; ++i) g[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_status_init(KrylovArgs k, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  k.status[b] = HELM_RUNNING;
+  k.active[b] = 0;
+  k.jcount[b] = 0;
+  k.iters[b] = 0;
+  k.relres[b] = 0.0;
+}
+
+inline unsigned nblk_of(long long N) { return (unsigned)((N + CH - 1) / CH); }
+
+}  // namespace
+
+int krylov_blocks_per_rhs(long long N) { return (int)nblk_of(N); }
+int krylov_max_restart() { return MAXM; }
+
+void launch_arnoldi_dots(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs* fine, int with_matvec) {
+  LevelArgs lv = fine ? *fine : LevelArgs{};
+  hipLaunchKernelGGL(k_arnoldi_dots, dim3(k.nblk, B), dim3(NT), 0, s, k, j, lv, with_matvec);
+}
+void launch_arnoldi_reduce(hipStream_t s, int B, const KrylovArgs& k, int j, int accumulate) {
+  hipLaunchKernelGGL(k_arnoldi_reduce, dim3(B), dim3(NT), 0, s, k, j, accumulate);
+}
+void launch_arnoldi_update(hipStream_t s, int B, const KrylovArgs& k, int j) {
+  hipLaunchKernelGGL(k_arnoldi_update, dim3(k.nblk, B), dim3(NT), 0, s, k, j);
+}
+void launch_givens(hipStream_t s, int B, const KrylovArgs& k, int j) {
+  hipLaunchKernelGGL(k_givens, dim3(B), dim3(HELM_WAVE), 0, s, k, j);
+}
+void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo) {
+  hipLaunchKernelGGL(k_x_update, dim3(k.nblk, B), dim3(NT), 0, s, k, x_hi, x_lo);
+}
+void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
+                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* c_hi,
+                        const c32* c_lo, c32 ghost_hi, c32 ghost_lo, float h2_hi, float h2_lo, c32* r_out,
+                        long long r_stride, float out_scale) {
+  FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, c_hi, c_lo, ghost_hi, ghost_lo, h2_hi, h2_lo, r_out,
+           r_stride, out_scale};
+  hipLaunchKernelGGL(k_residual_ff, dim3(k.nblk, B), dim3(NT), 0, s, k, a);
+}
+void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
+  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);
+}
+void launch_status_init(hipStream_t s, int B, const KrylovArgs& k) {
+  hipLaunchKernelGGL(k_status_init, dim3((B + 63) / 64), dim3(64), 0, s, k, B);
+}

@@ -1,0 +1,329 @@
+// Multigrid kernels for the shifted operator K'_l = -Lap'_l - kappa c_l
+// (h_l^2-scaled, Sec. IV-B/IV-C):
+//  * fused 2D legs of a V-cycle started from a zero guess with one pre- and
+//    one post-relaxation (the paper's nu1 = nu2 = 1, omega_S = 0.8):
+//      down: v1 = w D^-1 r;  rc = 4 R (r - K v1)          (LDS tile, 2-cell halo)
+//      up:   v2 = w D^-1 r + P e;  z = v2 + w D^-1 (r - K v2)
+//    v1 is recomputed by the up-leg instead of being stored.
+//  * generic kernels (any dimension, any nu, W-cycles): Jacobi sweeps
+//    (eq. dampedJ), residual + full-weighting restriction, prolongation.
+//  * the exact coarsest solve as a product with the explicit inverse.
+// D = diag(K) includes the Sommerfeld ghost terms: D = 2d - coef - g * #ghosts.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace {
+
+
+// ------------------------------------------------------------ fused 2D legs
+template <int TCX, int TCY>
+__global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                           VecSet rc, int nc, const int* active) {
+  constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3;
+  constexpr int SX = 2 * TCX + 1, SY = 2 * TCY + 1;
+  __shared__ c32 sR[RY][RX];
+  __shared__ c32 sV[RY][RX];
+  __shared__ c32 sS[SY][SX];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int n = lv.n;
+  const int tiles_x = (nc + TCX - 1) / TCX;
+  const int cx0 = (blockIdx.x % tiles_x) * TCX;
+  const int cy0 = (blockIdx.x / tiles_x) * TCY;
+  const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  for (int idx = threadIdx.x; idx < RX * RY; idx += TCX * TCY) {
+    const int lx = idx % RX, ly = idx / RX;
+    const int gx = fx0 + lx, gy = fy0 + ly;
+    c32 rv = make_float2(0.f, 0.f), vv = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const long long p = (long long)gy * n + gx;
+      rv = cscale(rb[p], sc);
+      vv = cscale(cmul(rv, crcp(diag_at(lv, p, ghosts2(gx, gy, n), 2))), omega);
+    }
+    sR[ly][lx] = rv;
+    sV[ly][lx] = vv;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < SX * SY; idx += TCX * TCY) {
+    const int sx = idx % SX, sy = idx / SX;
+    const int lx = sx + 1, ly = sy + 1;
+    const int gx = fx0 + lx, gy = fy0 + ly;
+    c32 s = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      // s = r - K v1 = (1 - w) r + sum of in-grid neighbours of v1 (D v1 = w r)
+      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+      s = cadd(cscale(sR[ly][lx], 1.0f - omega), nb);
+    }
+    sS[sy][sx] = s;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  const int I = cx0 + tx, J = cy0 + ty;
+  if (I < nc && J < nc) {
+    const int sx = 2 * tx + 1, sy = 2 * ty + 1;
+    c32 acc = cscale(sS[sy][sx], 4.0f);
+    acc = cadd(acc, cscale(cadd(cadd(sS[sy][sx - 1], sS[sy][sx + 1]), cadd(sS[sy - 1][sx], sS[sy + 1][sx])), 2.0f));
+    acc = cadd(acc, cadd(cadd(sS[sy - 1][sx - 1], sS[sy - 1][sx + 1]), cadd(sS[sy + 1][sx - 1], sS[sy + 1][sx + 1])));
+    // scaled coarse right-hand side: 4 * (1/16) * stencil sum
+    rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
+  }
+}
+
+template <int TX, int TY, int PY>
+__global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                             VecSet ec, int nc, VecSet z, const int* active) {
+  constexpr int HX = TX + 2, HY = TY + 2;
+  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2;
+  constexpr int NT = TX * (TY / PY);
+  __shared__ c32 sE[CY][CX];
+  __shared__ c32 sV[HY][HX];
+  __shared__ c32 sR[HY][HX];
+  __shared__ c32 sW[HY][HX];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int n = lv.n;
+  const int tiles_x = (n + TX - 1) / TX;
+  const int fx0 = (blockIdx.x % tiles_x) * TX;
+  const int fy0 = (blockIdx.x / tiles_x) * TY;
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
+    const int lx = idx % CX, ly = idx / CX;
+    const int I = cxs + lx, J = cys + ly;
+    c32 e = make_float2(0.f, 0.f);
+    if (I >= 0 && I < nc && J >= 0 && J < nc) e = eb[(long long)J * nc + I];
+    sE[ly][lx] = e;
+  }
+  __syncthreads();
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  for (int idx = threadIdx.x; idx < HX * HY; idx += NT) {
+    const int lx = idx % HX, ly = idx / HX;
+    const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
+    c32 v2 = make_float2(0.f, 0.f), rv = v2, wv = v2;
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const long long p = (long long)gy * n + gx;
+      rv = cscale(rb[p], sc);
+      wv = cscale(crcp(diag_at(lv, p, ghosts2(gx, gy, n), 2)), omega);
+      // bilinear prolongation (printed formula of Sec. IV-C)
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys;
+      const int ox = gx & 1, oy = gy & 1;
+      c32 pe = sE[J][I];
+      if (ox && oy) {
+        pe = cscale(cadd(cadd(pe, sE[J][I + 1]), cadd(sE[J + 1][I], sE[J + 1][I + 1])), 0.25f);
+      } else if (ox) {
+        pe = cscale(cadd(pe, sE[J][I + 1]), 0.5f);
+      } else if (oy) {
+        pe = cscale(cadd(pe, sE[J + 1][I]), 0.5f);
+      }
+      v2 = cadd(cmul(rv, wv), pe);
+    }
+    sV[ly][lx] = v2;
+    sR[ly][lx] = rv;
+    sW[ly][lx] = wv;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty0 = (threadIdx.x / TX) * PY;
+  c32* zb = z.p + (long long)b * z.stride;
+#pragma unroll
+  for (int k = 0; k < PY; ++k) {
+    const int lx = tx + 1, ly = ty0 + k + 1;
+    const int gx = fx0 + tx, gy = fy0 + ty0 + k;
+    if (gx < n && gy < n) {
+      // z = v2 + w D^-1 (r - K v2) = (1 - w) v2 + (w / D)(r + sum of neighbours of v2)
+      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+      const c32 zz = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(sW[ly][lx], cadd(sR[ly][lx], nb)));
+      zb[(long long)gy * n + gx] = zz;
+    }
+  }
+}
+
+// ------------------------------------------------------------ generic (2D/3D)
+__global__ void k_jacobi_zero(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
+                              const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= lv.N) return;
+  const Coord c = coord_of(p, lv.n, dim);
+  const c32 rv = cscale(r.p[(long long)b * r.stride + p], scale_of(rs, b));
+  v.p[(long long)b * v.stride + p] = cscale(cmul(rv, crcp(diag_at(lv, p, ghosts_of(c, lv.n, dim), dim))), omega);
+}
+
+__global__ void k_jacobi(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v, VecSet vout,
+                         const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= lv.N) return;
+  const Coord c = coord_of(p, lv.n, dim);
+  const c32* vb = v.p + (long long)b * v.stride;
+  const c32 rv = cscale(r.p[(long long)b * r.stride + p], scale_of(rs, b));
+  const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
+  // v + w D^-1 (r - K v), K v = D v - sum of neighbours
+  const c32 res = csub(cadd(rv, neighbour_sum(vb, p, c, lv.n, dim)), cmul(D, vb[p]));
+  vout.p[(long long)b * vout.stride + p] = cadd(vb[p], cscale(cmul(res, crcp(D)), omega));
+}
+
+__global__ void k_restrict_residual(int dim, VecSet r, ScaleSet rs, VecSet v, LevelArgs lv, VecSet rc, int nc,
+                                    const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long ncN = dim == 2 ? (long long)nc * nc : (long long)nc * nc * nc;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ncN) return;
+  const Coord C = coord_of(q, nc, dim);
+  const int n = lv.n;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const c32* vb = v.p ? v.p + (long long)b * v.stride : nullptr;
+  const float w1[3] = {0.25f, 0.5f, 0.25f};
+  c32 acc = make_float2(0.f, 0.f);
+  const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        Coord f{2 * C.x + dx, 2 * C.y + dy, dim == 3 ? 2 * C.z + dz : 0};
+        if (f.x < 0 || f.x >= n || f.y < 0 || f.y >= n || f.z < 0 || f.z >= n) continue;
+        const long long p = ((long long)f.z * n + f.y) * n + f.x;
+        c32 s = cscale(rb[p], sc);
+        if (vb) {
+          const c32 D = diag_at(lv, p, ghosts_of(f, n, dim), dim);
+          s = cadd(csub(s, cmul(D, vb[p])), neighbour_sum(vb, p, f, n, dim));
+        }
+        const float wgt = w1[dx + 1] * w1[dy + 1] * (dim == 3 ? w1[dz + 1] : 1.0f);
+        acc = cadd(acc, cscale(s, wgt));
+      }
+  rc.p[(long long)b * rc.stride + q] = cscale(acc, 4.0f);
+}
+
+__global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, int n, long long N, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const Coord f = coord_of(p, n, dim);
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  c32 acc = make_float2(0.f, 0.f);
+  const int oz = dim == 3 ? (f.z & 1) : 0;
+  for (int kz = 0; kz <= oz; ++kz)
+    for (int ky = 0; ky <= (f.y & 1); ++ky)
+      for (int kx = 0; kx <= (f.x & 1); ++kx) {
+        const int I = (f.x >> 1) + kx, J = (f.y >> 1) + ky, K = dim == 3 ? (f.z >> 1) + kz : 0;
+        float wgt = ((f.x & 1) ? 0.5f : 1.0f) * ((f.y & 1) ? 0.5f : 1.0f) * (oz ? 0.5f : 1.0f);
+        acc = cadd(acc, cscale(eb[((long long)K * nc + J) * nc + I], wgt));
+      }
+  c32* vb = v.p + (long long)b * v.stride;
+  vb[p] = cadd(vb[p], acc);
+}
+
+// y = out_scale * (D x - sum of neighbours), D = 2d - coef - g #ghosts
+__global__ void k_apply(int dim, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
+                        const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= lv.N) return;
+  const Coord c = coord_of(p, lv.n, dim);
+  const c32* xb = x.p + (long long)b * x.stride;
+  const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
+  const c32 out = csub(cmul(D, xb[p]), neighbour_sum(xb, p, c, lv.n, dim));
+  y.p[(long long)b * y.stride + p] = cscale(out, out_scale * scale_of(xs, b));
+}
+
+// z_b = M r_b with M given transposed (minvT[k * Nc + row] = M[row][k]); one
+// thread per row, right-hand sides in chunks staged through LDS.
+constexpr int CS_RHS = 4;
+constexpr int CS_K = 512;
+__global__ __launch_bounds__(256) void k_coarse_solve(const c32* minvT, int Nc, int B, VecSet r, VecSet z,
+                                                      const int* active) {
+  __shared__ c32 sr[CS_RHS][CS_K];
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b0 = blockIdx.y * CS_RHS;
+  c32 acc[CS_RHS];
+#pragma unroll
+  for (int q = 0; q < CS_RHS; ++q) acc[q] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < Nc; k0 += CS_K) {
+    const int kn = min(CS_K, Nc - k0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < CS_RHS * kn; idx += blockDim.x) {
+      const int q = idx / kn, k = idx % kn;
+      const int b = b0 + q;
+      c32 v = make_float2(0.f, 0.f);
+      if (b < B && (!active || active[b])) v = r.p[(long long)b * r.stride + k0 + k];
+      sr[q][k] = v;
+    }
+    __syncthreads();
+    if (row < Nc) {
+      for (int k = 0; k < kn; ++k) {
+        const c32 mv = minvT[(long long)(k0 + k) * Nc + row];
+#pragma unroll
+        for (int q = 0; q < CS_RHS; ++q) acc[q] = cfma(mv, sr[q][k], acc[q]);
+      }
+    }
+  }
+  if (row < Nc) {
+#pragma unroll
+    for (int q = 0; q < CS_RHS; ++q) {
+      const int b = b0 + q;
+      if (b < B && (!active || active[b])) z.p[(long long)b * z.stride + row] = acc[q];
+    }
+  }
+}
+
+inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// fused-leg tile shapes: coarse 32 x 8 per block (down), fine 64 x 16 per block (up)
+constexpr int DN_TCX = 32, DN_TCY = 8;
+constexpr int UP_TX = 64, UP_TY = 16, UP_PY = 4;
+
+void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
+                        const int* active) {
+  const int tiles = ((nc + DN_TCX - 1) / DN_TCX) * ((nc + DN_TCY - 1) / DN_TCY);
+  hipLaunchKernelGGL((k_down_fused2<DN_TCX, DN_TCY>), dim3(tiles, B), dim3(DN_TCX * DN_TCY), 0, s, r, rs, lv, omega,
+                     rc, nc, active);
+}
+
+void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
+                      VecSet z, const int* active) {
+  const int tiles = ((lv.n + UP_TX - 1) / UP_TX) * ((lv.n + UP_TY - 1) / UP_TY);
+  hipLaunchKernelGGL((k_up_fused2<UP_TX, UP_TY, UP_PY>), dim3(tiles, B), dim3(UP_TX * (UP_TY / UP_PY)), 0, s, r,
+                     rs, lv, omega, ec, nc, z, active);
+}
+
+void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
+                        const int* active) {
+  hipLaunchKernelGGL(k_jacobi_zero, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, r, rs, lv, omega, v, active);
+}
+
+void launch_jacobi(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
+                   VecSet vout, const int* active) {
+  hipLaunchKernelGGL(k_jacobi, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, r, rs, lv, omega, v, vout,
+                     active);
+}
+
+void launch_restrict_residual(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, VecSet v, LevelArgs lv,
+                              VecSet rc, int nc, const int* active) {
+  const long long ncN = dim == 2 ? (long long)nc * nc : (long long)nc * nc * nc;
+  hipLaunchKernelGGL(k_restrict_residual, dim3(nblocks(ncN, 256), B), dim3(256), 0, s, dim, r, rs, v, lv, rc, nc,
+                     active);
+}
+
+void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active) {
+  const long long N = dim == 2 ? (long long)n * n : (long long)n * n * n;
+  hipLaunchKernelGGL(k_prolong_add, dim3(nblocks(N, 256), B), dim3(256), 0, s, dim, ec, nc, v, n, N, active);
+}
+
+void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3(nblocks(Nc, 256), (B + CS_RHS - 1) / CS_RHS), dim3(256), 0, s, minvT, Nc,
+                     B, r, z, active);
+}
+
+void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
+                  const int* active) {
+  hipLaunchKernelGGL(k_apply, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, x, xs, lv, out_scale, y, active);
+}

@@ -1,0 +1,102 @@
+// Kernel argument types and launcher declarations shared by the HIP sources
+// and the host engine.  All fields are complex64 (float2) arrays.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+typedef float2 c32;
+
+// A set of per-right-hand-side vectors: vector q starts at p + q * stride.
+struct VecSet {
+  c32* p;
+  long long stride;
+};
+// Optional per-right-hand-side scale factors: factor of q is p[q * stride] (p = NULL -> 1).
+struct ScaleSet {
+  const float* p;
+  int stride;
+};
+// One multigrid level of the vertex-centred hierarchy.
+struct LevelArgs {
+  int n;            // points per side
+  long long N;      // n^dim
+  const c32* coef;  // operator coefficient: kappa * c_l (K_kappa) or c (A)
+  c32 ghost;        // Sommerfeld ghost factor 1 + j k_b h_l
+};
+
+// per-RHS solver status on the device (the final values match helm.h's HELM_STATUS_*)
+enum {
+  HELM_RUNNING = -1,
+  HELM_STATUS_CONVERGED_DEV = 0,
+  HELM_STATUS_NOT_CONVERGED_DEV = 1,
+  HELM_STATUS_BREAKDOWN_DEV = 2
+};
+
+// ---- multigrid legs (2D) ----
+void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
+                        const int* active);
+void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
+                      VecSet z, const int* active);
+void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
+                        const int* active);
+void launch_jacobi(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
+                   VecSet vout, const int* active);
+void launch_restrict_residual(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, VecSet v, LevelArgs lv,
+                              VecSet rc, int nc, const int* active);
+void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active);
+void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active);
+void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
+                  const int* active);
+
+// ---- Krylov (FGMRES / float-float outer loop), flat over the fine grid ----
+struct KrylovArgs {
+  int dim;
+  int n;
+  long long N;
+  int m;          // restart length
+  int nblk;       // partial-reduction blocks per right-hand side
+  c32* V;         // [B][m+1][N] basis (unnormalised; v_i = vs[i] * V_i)
+  c32* Z;         // [B][m][N] preconditioned vectors
+  float* vs;      // [B][m+1] scale of each basis vector
+  c32* P1;        // [B][nblk][m+1] partial dots
+  float* P2;      // [B][nblk] partial squared norms
+  double2* H;     // [B][m+1][m] Hessenberg (rotated in place)
+  double* cs;     // [B][m]
+  double2* sn;    // [B][m]
+  double2* g;     // [B][m+1]
+  c32* coef;      // [B][m+1] h_i * vs_i for the update pass
+  c32* y;         // [B][m] least-squares solution of the cycle
+  int* active;    // [B] 1 while the current cycle iterates
+  int* status;    // [B] HELM_RUNNING or a final status
+  int* jcount;    // [B] steps taken in the current cycle
+  int* iters;     // [B] total preconditioner applications
+  double* bnorm;  // [B] ||h^2 b||
+  double* tol;    // [B] absolute stop level of the Givens estimate
+  double* relres; // [B] true relative residual of the last evaluation
+  int max_iters;
+  double rtol;
+  double inner_factor;
+};
+
+void launch_arnoldi_dots(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs* fine, int with_matvec);
+void launch_arnoldi_reduce(hipStream_t s, int B, const KrylovArgs& k, int j, int accumulate);
+void launch_arnoldi_update(hipStream_t s, int B, const KrylovArgs& k, int j);
+void launch_givens(hipStream_t s, int B, const KrylovArgs& k, int j);
+void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo);
+void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
+                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* c_hi,
+                        const c32* c_lo, c32 ghost_hi, c32 ghost_lo, float h2_hi, float h2_lo, c32* r_out,
+                        long long r_stride, float out_scale);
+void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
+
+// ---- model kernels ----
+void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane, const c32* tables, c32* rhs,
+                       c32* uin);
+void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* u, const c32* lam,
+                   const float* nmap, float scale, float* grad);
+void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out);
+void launch_zero(hipStream_t s, long long count, c32* p);
+void launch_status_init(hipStream_t s, int B, const KrylovArgs& k);
+int krylov_blocks_per_rhs(long long N);
+int krylov_max_restart();

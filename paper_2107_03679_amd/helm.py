@@ -1,0 +1,286 @@
+"""Python binding of libhelm (include/helm.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch
+tensors (device memory, complex64 = interleaved float pairs) to pointers and
+C structs.  It raises if the shared library has not been built; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhelm.so")
+
+HELM_OK = 0
+HELM_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "converged", 1: "not_converged", 2: "breakdown"}
+
+
+class HelmGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("abl_width", ctypes.c_int), ("h", ctypes.c_double)]
+
+
+class HelmAbl(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("sign", ctypes.c_int), ("profile", ctypes.c_int)]
+
+
+class HelmOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_b", ctypes.c_double), ("kappa_re", ctypes.c_double), ("kappa_im", ctypes.c_double),
+        ("omega_jac", ctypes.c_double), ("rtol", ctypes.c_double),
+        ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("cycle", ctypes.c_int),
+        ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
+        ("reorth", ctypes.c_int), ("fused", ctypes.c_int), ("use_graph", ctypes.c_int),
+    ]
+
+
+class HelmStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+
+
+class HelmInfo(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int), ("abl_width", ctypes.c_int), ("n_e", ctypes.c_int),
+        ("levels", ctypes.c_int), ("coarsest_n", ctypes.c_int),
+        ("h", ctypes.c_double), ("k0", ctypes.c_double), ("n_b", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+EXPORTS = [
+    "helm_default_opts", "helm_extended_size", "helm_setup", "helm_update_n", "helm_get_info",
+    "helm_plane_wave_rhs", "helm_solve_batch", "helm_adjoint_batch", "helm_grad_n", "helm_apply_A",
+    "helm_residual", "helm_apply_K", "helm_restrict", "helm_prolong_add", "helm_coarse_solve",
+    "helm_precondition", "helm_solution_lo", "helm_last_error", "helm_destroy",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhelm.so once; raise if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2107_03679_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.helm_default_opts.argtypes = [ctypes.POINTER(HelmOpts)]
+    lib.helm_default_opts.restype = None
+    lib.helm_extended_size.argtypes = [i, i, i]
+    lib.helm_setup.argtypes = [ctypes.POINTER(HelmGrid), vp, d, ctypes.POINTER(HelmAbl), ctypes.POINTER(HelmOpts), vp,
+                               ctypes.POINTER(vp)]
+    lib.helm_update_n.argtypes = [vp, vp]
+    lib.helm_get_info.argtypes = [vp, ctypes.POINTER(HelmInfo)]
+    lib.helm_plane_wave_rhs.argtypes = [vp, i, vp, vp, vp]
+    lib.helm_solve_batch.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats)]
+    lib.helm_adjoint_batch.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats)]
+    lib.helm_grad_n.argtypes = [vp, i, vp, vp, vp]
+    lib.helm_apply_A.argtypes = [vp, i, vp, vp]
+    lib.helm_residual.argtypes = [vp, i, vp, vp, vp, vp]
+    lib.helm_apply_K.argtypes = [vp, i, i, vp, vp]
+    lib.helm_restrict.argtypes = [vp, i, i, vp, vp]
+    lib.helm_prolong_add.argtypes = [vp, i, i, vp, vp]
+    lib.helm_coarse_solve.argtypes = [vp, i, vp, vp]
+    lib.helm_precondition.argtypes = [vp, i, vp, vp]
+    lib.helm_solution_lo.argtypes = [vp, i, vp]
+    lib.helm_last_error.argtypes = [vp]
+    lib.helm_last_error.restype = ctypes.c_char_p
+    lib.helm_destroy.argtypes = [vp]
+    lib.helm_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("helm_default_opts", "helm_last_error", "helm_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def extended_size(n: int, abl_width: int, levels: int) -> int:
+    return load_library().helm_extended_size(n, abl_width, levels)
+
+
+def default_opts() -> HelmOpts:
+    o = HelmOpts()
+    load_library().helm_default_opts(ctypes.byref(o))
+    return o
+
+
+class HelmError(RuntimeError):
+    pass
+
+
+@dataclass
+class SolveStats:
+    iters: np.ndarray
+    status: np.ndarray
+    rel_res_true: np.ndarray
+
+    @property
+    def converged(self) -> bool:
+        return bool(np.all(self.status == 0))
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise HelmError("tensors passed to libhelm must live on the GPU")
+    if not t.is_contiguous():
+        raise HelmError("tensors passed to libhelm must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """One medium on one GPU stream: wraps helm_setup ... helm_destroy.
+
+    n_map    torch float32 tensor [n]*dim on the GPU: refractive index on Omega
+    k0       free-space wavenumber in units of 1/h (k0 h = k0 * h)
+    h        mesh size (None: the paper's unit normalisation, h = 1/(n_e - 1))
+    other keywords: fields of helm_opts (levels, restart, kappa=complex, ...)
+    """
+
+    def __init__(self, n_map: torch.Tensor, k0: float, abl_width: int = 20, h: float | None = None,
+                 beta: float = 0.15, abl_sign: int = 1, abl_profile: int = 0, kappa: complex | None = None,
+                 stream: torch.cuda.Stream | None = None, **opts):
+        self.lib = load_library()
+        n_map = n_map.to(torch.float32).contiguous()
+        dim = n_map.dim()
+        grid = HelmGrid(dim, n_map.shape[0], abl_width, -1.0 if h is None else float(h))
+        abl = HelmAbl(beta, abl_sign, abl_profile)
+        o = default_opts()
+        if kappa is not None:
+            o.kappa_re, o.kappa_im = float(np.real(kappa)), float(np.imag(kappa))
+        for key, val in opts.items():
+            if not hasattr(o, key):
+                raise HelmError(f"unknown option {key}")
+            setattr(o, key, val)
+        self.opts = o
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = ctypes.c_void_p()
+        rc = self.lib.helm_setup(ctypes.byref(grid), _ptr(n_map), float(k0), ctypes.byref(abl), ctypes.byref(o),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
+        if rc != HELM_OK:
+            raise HelmError(f"helm_setup failed ({rc}): {self.lib.helm_last_error(None).decode()}")
+        self._h = handle
+        info = HelmInfo()
+        self.lib.helm_get_info(self._h, ctypes.byref(info))
+        self.info = info
+        self.dim = dim
+        self.n_e = info.n_e
+        self.levels = info.levels
+        self.device = n_map.device
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc: int, what: str, soft_ok: bool = False):
+        if rc == HELM_OK or (soft_ok and rc == HELM_NOT_CONVERGED):
+            return
+        raise HelmError(f"{what} failed ({rc}): {self.lib.helm_last_error(self._h).decode()}")
+
+    def grid_shape(self, level: int = 0):
+        n = (self.n_e - 1) // (2 ** level) + 1
+        return (n,) * self.dim
+
+    def empty_fields(self, B: int, level: int = 0) -> torch.Tensor:
+        return torch.empty((B, *self.grid_shape(level)), dtype=torch.complex64, device=self.device)
+
+    @staticmethod
+    def _stats(st) -> SolveStats:
+        return SolveStats(np.array([s.iters for s in st]), np.array([s.status for s in st]),
+                          np.array([s.rel_res_true for s in st]))
+
+    # -- entry points --------------------------------------------------------
+    def update_n(self, n_map: torch.Tensor):
+        self._check(self.lib.helm_update_n(self._h, _ptr(n_map.to(torch.float32).contiguous())), "helm_update_n")
+
+    def plane_wave_rhs(self, dirs, with_uin: bool = False):
+        dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, self.dim))
+        B = dirs.shape[0]
+        rhs = self.empty_fields(B)
+        uin = self.empty_fields(B) if with_uin else None
+        rc = self.lib.helm_plane_wave_rhs(self._h, B, dirs.ctypes.data_as(ctypes.c_void_p), _ptr(rhs), _ptr(uin))
+        self._check(rc, "helm_plane_wave_rhs")
+        return (rhs, uin) if with_uin else rhs
+
+    def solve(self, rhs: torch.Tensor, out: torch.Tensor | None = None, adjoint: bool = False):
+        B = rhs.shape[0]
+        x = self.empty_fields(B) if out is None else out
+        st = (HelmStats * B)()
+        fn = self.lib.helm_adjoint_batch if adjoint else self.lib.helm_solve_batch
+        rc = fn(self._h, B, _ptr(rhs), _ptr(x), st)
+        self._check(rc, "helm_adjoint_batch" if adjoint else "helm_solve_batch", soft_ok=True)
+        return x, self._stats(st)
+
+    def solution_lo(self, B: int) -> torch.Tensor:
+        """Low part of the float-float iterate of the last solve (x = x_hi + x_lo)."""
+        lo = self.empty_fields(B)
+        self._check(self.lib.helm_solution_lo(self._h, B, _ptr(lo)), "helm_solution_lo")
+        return lo
+
+    def adjoint(self, rhs: torch.Tensor, out: torch.Tensor | None = None):
+        return self.solve(rhs, out, adjoint=True)
+
+    def grad_n(self, u_total: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+        grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
+        self._check(self.lib.helm_grad_n(self._h, u_total.shape[0], _ptr(u_total), _ptr(lam), _ptr(grad)),
+                    "helm_grad_n")
+        return grad
+
+    def apply_A(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        self._check(self.lib.helm_apply_A(self._h, x.shape[0], _ptr(x), _ptr(y)), "helm_apply_A")
+        return y
+
+    def residual(self, rhs: torch.Tensor, x_hi: torch.Tensor, x_lo: torch.Tensor | None = None) -> torch.Tensor:
+        r = torch.empty_like(rhs)
+        self._check(self.lib.helm_residual(self._h, rhs.shape[0], _ptr(rhs), _ptr(x_hi), _ptr(x_lo), _ptr(r)),
+                    "helm_residual")
+        return r
+
+    def apply_K(self, level: int, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        self._check(self.lib.helm_apply_K(self._h, level, x.shape[0], _ptr(x), _ptr(y)), "helm_apply_K")
+        return y
+
+    def restrict(self, level: int, fine: torch.Tensor) -> torch.Tensor:
+        coarse = self.empty_fields(fine.shape[0], level + 1)
+        self._check(self.lib.helm_restrict(self._h, level, fine.shape[0], _ptr(fine), _ptr(coarse)), "helm_restrict")
+        return coarse
+
+    def prolong_add(self, level: int, coarse: torch.Tensor, fine: torch.Tensor) -> torch.Tensor:
+        self._check(self.lib.helm_prolong_add(self._h, level, coarse.shape[0], _ptr(coarse), _ptr(fine)),
+                    "helm_prolong_add")
+        return fine
+
+    def coarse_solve(self, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty_like(r)
+        self._check(self.lib.helm_coarse_solve(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_coarse_solve")
+        return z
+
+    def precondition(self, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty_like(r)
+        self._check(self.lib.helm_precondition(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_precondition")
+        return z
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.helm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

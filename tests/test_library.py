@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every symbol include/helm.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2107_03679_amd", "lib", "libhelm.so")
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "helm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(helm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("helm_setup", "helm_solve_batch", "helm_adjoint_batch", "helm_grad_n", "helm_destroy"):
+        assert name in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_host_only_entry_points():
+    from paper_2107_03679_amd import helm
+
+    assert helm.extended_size(128, 20, 4) == 169
+    assert helm.extended_size(512, 20, 7) == 577
+    assert helm.extended_size(-1, 20, 4) == -1
+    o = helm.default_opts()
+    assert (o.levels, o.nu1, o.nu2, o.cycle) == (4, 1, 1, 1)
+    assert o.omega_jac == pytest.approx(0.8) and o.rtol == pytest.approx(1e-6)
+    assert (o.kappa_re, o.kappa_im) == (1.0, 0.5)
+    assert set(helm.EXPORTS) == set(declared_symbols()) | {"helm_default_opts"} - set()
+
+
+def test_product_path_has_no_oracle_import():
+    pkg = os.path.join(ROOT, "paper_2107_03679_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
