@@ -205,6 +205,20 @@ int helm_coarse_solve(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
  * h^2-scaled fine system K'_0 z = r (the FGMRES preconditioner). */
 int helm_precondition(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
 
+/* ---- per-launch profiler (measurement support) ----
+ * While enabled, every kernel launch of the context is bracketed by HIP events
+ * on the context's stream (restart cycles are then launched one kernel at a
+ * time instead of from the captured graph).  Entries are grouped by kernel
+ * name (multigrid kernels per level, e.g. "up_fused_l0"); `bytes` is the
+ * algorithmic HBM traffic of the launches (minimum reads + writes of the
+ * fields and coefficients they touch, counted for the right-hand sides still
+ * iterating at the start of each restart cycle). */
+int helm_profile_enable(helm_ctx* ctx, int on);
+int helm_profile_reset(helm_ctx* ctx);
+int helm_profile_count(const helm_ctx* ctx);
+int helm_profile_get(const helm_ctx* ctx, int i, char* name, int name_len, double* total_ms, long long* launches,
+                     double* bytes);
+
 /* Last error message of ctx (or of the last failed helm_setup if ctx is NULL). */
 const char* helm_last_error(const helm_ctx* ctx);
 

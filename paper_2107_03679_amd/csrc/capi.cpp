@@ -84,6 +84,23 @@ struct helm_ctx {
 
   hipGraphExec_t graph = nullptr;
   int graph_B = 0;
+
+  // opt-in per-launch profiler (HIP events on the context stream, no graph replay while on)
+  struct ProfEntry {
+    std::string name;
+    double ms = 0.0, bytes = 0.0;
+    long long launches = 0;
+  };
+  struct Pending {
+    int idx;
+    hipEvent_t e0, e1;
+    double bytes;
+  };
+  bool prof_on = false;
+  int prof_B = 0;  // right-hand sides still iterating (algorithmic byte model)
+  std::vector<ProfEntry> prof;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
   int last_B = 0;
   int last_conj = 0;
 
@@ -104,6 +121,58 @@ LevelArgs level_K(const helm_ctx* c, int l) { return LevelArgs{c->lv[l].n, c->lv
 
 long long npts(int n, int dim) { return dim == 2 ? (long long)n * n : (long long)n * n * n; }
 
+hipEvent_t prof_event(helm_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+// Times the launches made in its scope when profiling is on.
+struct ProfScope {
+  helm_ctx* c;
+  int idx = -1;
+  hipEvent_t e0 = nullptr;
+  double bytes;
+  ProfScope(helm_ctx* ctx, const std::string& name, double b) : c(ctx), bytes(b) {
+    if (!c->prof_on) return;
+    for (size_t i = 0; i < c->prof.size(); ++i)
+      if (c->prof[i].name == name) idx = (int)i;
+    if (idx < 0) {
+      c->prof.push_back({name});
+      idx = (int)c->prof.size() - 1;
+    }
+    e0 = prof_event(c);
+    check(hipEventRecord(e0, c->s), "hipEventRecord");
+  }
+  ~ProfScope() {
+    if (idx < 0) return;
+    hipEvent_t e1 = prof_event(c);
+    if (hipEventRecord(e1, c->s) == hipSuccess) c->pending.push_back({idx, e0, e1, bytes});
+  }
+};
+
+// Accumulate the finished event pairs (after a stream synchronisation).
+void prof_resolve(helm_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      c->prof[p.idx].ms += ms;
+      c->prof[p.idx].bytes += p.bytes;
+      c->prof[p.idx].launches += 1;
+    }
+    c->event_pool.push_back(p.e0);
+    c->event_pool.push_back(p.e1);
+  }
+  c->pending.clear();
+}
+
+std::string lvl_name(const char* base, int l) { return std::string(base) + "_l" + std::to_string(l); }
+
 // Copy B vectors of N elements between two strided vector sets.
 void copy_set(helm_ctx* c, int B, VecSet src, VecSet dst, long long N) {
   check(hipMemcpy2DAsync(dst.p, dst.stride * sizeof(c32), src.p, src.stride * sizeof(c32), N * sizeof(c32), B,
@@ -116,7 +185,11 @@ void relax(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet v, int sweep
   const Level& L = c->lv[l];
   VecSet t{l == 0 ? c->d_T0 : L.t, L.N};
   for (int i = 0; i < sweeps; ++i) {
-    launch_jacobi(c->s, c->dim, B, r, rs, level_K(c, l), (float)c->o.omega_jac, v, t, act);
+    {
+      ProfScope ps(c, lvl_name("jacobi", l), c->prof_B * 24.0 * L.N + 8.0 * L.N);
+      launch_jacobi(c->s, c->dim, B, r, rs, level_K(c, l), (float)c->o.omega_jac, v, t, act);
+    }
+    ProfScope ps(c, lvl_name("copy", l), c->prof_B * 16.0 * L.N);
     copy_set(c, B, t, v, L.N);
   }
 }
@@ -126,6 +199,7 @@ void relax(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet v, int sweep
 void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act) {
   const int dim = c->dim;
   if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
+    ProfScope ps(c, "coarse_solve", 8.0 * c->Nc * c->Nc + c->prof_B * 16.0 * c->Nc);
     launch_coarse_solve(c->s, B, c->d_minvT, c->Nc, r, out, act);
     return;
   }
@@ -134,11 +208,14 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   VecSet rc{crs.rc, crs.N}, ec{crs.e, crs.N};
   const float om = (float)c->o.omega_jac;
   const bool fused = c->o.fused && dim == 2 && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
+  const double Nf = (double)fine.N, Nc1 = (double)crs.N, Bp = c->prof_B;
   if (fused) {
+    ProfScope ps(c, lvl_name("down_fused", l), Bp * 8.0 * (Nf + Nc1) + 8.0 * Nf);
     launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act);
   } else {
     int sweeps = c->o.nu1;
     if (zero_guess) {
+      ProfScope ps(c, lvl_name("jacobi_zero", l), Bp * 16.0 * Nf + 8.0 * Nf);
       if (sweeps > 0) {
         launch_jacobi_zero(c->s, dim, B, r, rs, level_K(c, l), om, out, act);
         --sweeps;
@@ -147,6 +224,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
       }
     }
     relax(c, B, l, r, rs, out, sweeps, act);
+    ProfScope ps(c, lvl_name("restrict_residual", l), Bp * (16.0 * Nf + 8.0 * Nc1) + 8.0 * Nf);
     launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
   }
   const bool next_is_coarsest = (l + 1 == c->L - 1);
@@ -155,9 +233,13 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, cyc == 0, act);
   }
   if (fused) {
+    ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
     launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ec, crs.n, out, act);
   } else {
-    launch_prolong_add(c->s, dim, B, ec, crs.n, out, fine.n, act);
+    {
+      ProfScope ps(c, lvl_name("prolong_add", l), Bp * (16.0 * Nf + 8.0 * Nc1));
+      launch_prolong_add(c->s, dim, B, ec, crs.n, out, fine.n, act);
+    }
     relax(c, B, l, r, rs, out, c->o.nu2, act);
   }
 }
@@ -171,28 +253,54 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
   ScaleSet sj{k.vs + j, k.m + 1};
   mg_cycle(c, B, 0, vj, sj, zj, true, k.active);
   const LevelArgs A = fine_A(c);
-  launch_arnoldi_dots(c->s, B, k, j, &A, 1);
-  launch_arnoldi_reduce(c->s, B, k, j, 0);
-  launch_arnoldi_update(c->s, B, k, j);
-  if (c->o.reorth) {
-    launch_arnoldi_dots(c->s, B, k, j, &A, 0);
-    launch_arnoldi_reduce(c->s, B, k, j, 1);
+  const double Bp = c->prof_B, N = (double)N0, nv = j + 1.0;
+  const double red_bytes = Bp * k.nblk * nv * 8.0;
+  {
+    ProfScope ps(c, "arnoldi_matvec_dots", Bp * (16.0 + 8.0 * nv) * N + 8.0 * N);
+    launch_arnoldi_dots(c->s, B, k, j, &A, 1);
+  }
+  {
+    ProfScope ps(c, "arnoldi_reduce", red_bytes);
+    launch_arnoldi_reduce(c->s, B, k, j, 0);
+  }
+  {
+    ProfScope ps(c, "arnoldi_update", Bp * (16.0 + 8.0 * nv) * N);
     launch_arnoldi_update(c->s, B, k, j);
   }
+  if (c->o.reorth) {
+    {
+      ProfScope ps(c, "arnoldi_dots_reorth", Bp * (8.0 + 8.0 * nv) * N);
+      launch_arnoldi_dots(c->s, B, k, j, &A, 0);
+    }
+    {
+      ProfScope ps(c, "arnoldi_reduce", red_bytes);
+      launch_arnoldi_reduce(c->s, B, k, j, 1);
+    }
+    ProfScope ps(c, "arnoldi_update", Bp * (16.0 + 8.0 * nv) * N);
+    launch_arnoldi_update(c->s, B, k, j);
+  }
+  ProfScope ps(c, "givens", Bp * k.nblk * 4.0);
   launch_givens(c->s, B, k, j);
 }
 
 void true_residual(helm_ctx* c, int B, int first, int conj_rhs) {
   KrylovArgs& k = c->k;
-  launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_chi, c->d_clo, c->g0_hi,
-                     c->g0_lo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
+  {
+    ProfScope ps(c, "residual_ff", c->prof_B * (first ? 16.0 : 32.0) * c->N0 + (first ? 0.0 : 16.0 * c->N0));
+    launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_chi, c->d_clo,
+                       c->g0_hi, c->g0_lo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
+  }
+  ProfScope ps(c, "finalize", c->prof_B * k.nblk * 4.0);
   launch_finalize(c->s, B, k, first);
 }
 
 // The body of one restart cycle: m Arnoldi steps, x update, true residual, decision.
 void restart_cycle(helm_ctx* c, int B, int conj_rhs) {
   for (int j = 0; j < c->k.m; ++j) arnoldi_step(c, B, j);
-  launch_x_update(c->s, B, c->k, c->d_xhi, c->d_xlo);
+  {
+    ProfScope ps(c, "x_update", c->prof_B * (8.0 * c->k.m + 32.0) * c->N0);
+    launch_x_update(c->s, B, c->k, c->d_xhi, c->d_xlo);
+  }
   true_residual(c, B, 0, conj_rhs);
 }
 
@@ -213,10 +321,11 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     launch_status_init(c->s, B, c->k);
     launch_zero(c->s, (long long)B * N0, c->d_xhi);
     launch_zero(c->s, (long long)B * N0, c->d_xlo);
+    c->prof_B = B;
     true_residual(c, B, 1, conj);
     const int max_cycles = c->o.max_iters / std::max(1, c->k.m) + 4;
     // restart cycles, replayed from a graph captured on first use per (B, conj)
-    const bool use_graph = c->o.use_graph != 0;
+    const bool use_graph = c->o.use_graph != 0 && !c->prof_on;
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
       if (use_graph) {
         if (c->graph == nullptr || c->graph_B != B * 2 + conj) {
@@ -239,8 +348,10 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
       check(hipGetLastError(), "kernel launch");
       check(hipMemcpyAsync(c->h_status, c->k.status, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "status D2H");
       check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
-      bool running = false;
-      for (int b = 0; b < B; ++b) running = running || c->h_status[b] == HELM_RUNNING;
+      int running = 0;
+      for (int b = 0; b < B; ++b) running += c->h_status[b] == HELM_RUNNING;
+      if (c->prof_on) prof_resolve(c);
+      c->prof_B = running;
       if (!running) break;
     }
     c->last_B = B;
@@ -316,6 +427,11 @@ void upload_medium(helm_ctx* c, const float* n_map_dev) {
 void free_ctx(helm_ctx* c) {
   if (!c) return;
   if (c->graph) hipGraphExecDestroy(c->graph);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.e0);
+    hipEventDestroy(p.e1);
+  }
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   for (void* p : c->allocs) hipFree(p);
   if (c->h_status) hipHostFree(c->h_status);
   if (c->h_iters) hipHostFree(c->h_iters);
@@ -332,6 +448,7 @@ void free_ctx(helm_ctx* c) {
 #define HELM_GUARD_END(name)                                                       \
   check(hipGetLastError(), name);                                                  \
   check(hipStreamSynchronize(c->s), "sync");                                       \
+  if (c->prof_on) prof_resolve(c);                                                 \
   }                                                                                \
   catch (const HipError& e) {                                                      \
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code)); \
@@ -630,6 +747,34 @@ int helm_precondition(helm_ctx* c, int B, const helm_c32* r, helm_c32* z) {
   HELM_GUARD_BEGIN
   mg_cycle(c, B, 0, VecSet{(c32*)r, c->N0}, ScaleSet{nullptr, 0}, VecSet{(c32*)z, c->N0}, true, c->d_ones);
   HELM_GUARD_END("precondition")
+}
+
+int helm_profile_enable(helm_ctx* c, int on) {
+  if (!c) return HELM_EINVAL;
+  c->prof_on = on != 0;
+  return HELM_OK;
+}
+
+int helm_profile_reset(helm_ctx* c) {
+  if (!c) return HELM_EINVAL;
+  c->prof.clear();
+  return HELM_OK;
+}
+
+int helm_profile_count(const helm_ctx* c) { return c ? (int)c->prof.size() : HELM_EINVAL; }
+
+int helm_profile_get(const helm_ctx* c, int i, char* name, int name_len, double* total_ms, long long* launches,
+                     double* bytes) {
+  if (!c || i < 0 || i >= (int)c->prof.size()) return HELM_EINVAL;
+  const auto& e = c->prof[i];
+  if (name && name_len > 0) {
+    std::strncpy(name, e.name.c_str(), name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (total_ms) *total_ms = e.ms;
+  if (launches) *launches = e.launches;
+  if (bytes) *bytes = e.bytes;
+  return HELM_OK;
 }
 
 const char* helm_last_error(const helm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }

@@ -57,7 +57,8 @@ EXPORTS = [
     "helm_default_opts", "helm_extended_size", "helm_setup", "helm_update_n", "helm_get_info",
     "helm_plane_wave_rhs", "helm_solve_batch", "helm_adjoint_batch", "helm_grad_n", "helm_apply_A",
     "helm_residual", "helm_apply_K", "helm_restrict", "helm_prolong_add", "helm_coarse_solve",
-    "helm_precondition", "helm_solution_lo", "helm_last_error", "helm_destroy",
+    "helm_precondition", "helm_solution_lo", "helm_profile_enable", "helm_profile_reset", "helm_profile_count",
+    "helm_profile_get", "helm_last_error", "helm_destroy",
 ]
 
 _lib = None
@@ -91,6 +92,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_coarse_solve.argtypes = [vp, i, vp, vp]
     lib.helm_precondition.argtypes = [vp, i, vp, vp]
     lib.helm_solution_lo.argtypes = [vp, i, vp]
+    lib.helm_profile_enable.argtypes = [vp, i]
+    lib.helm_profile_reset.argtypes = [vp]
+    lib.helm_profile_count.argtypes = [vp]
+    lib.helm_profile_get.argtypes = [vp, i, ctypes.c_char_p, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(d)]
     lib.helm_last_error.argtypes = [vp]
     lib.helm_last_error.restype = ctypes.c_char_p
     lib.helm_destroy.argtypes = [vp]
@@ -267,6 +273,22 @@ class Context:
         z = torch.empty_like(r)
         self._check(self.lib.helm_precondition(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_precondition")
         return z
+
+    def profile(self, on: bool = True, reset: bool = True):
+        """Enable/disable per-launch HIP-event timing of every kernel of this context."""
+        if reset:
+            self.lib.helm_profile_reset(self._h)
+        self._check(self.lib.helm_profile_enable(self._h, int(on)), "helm_profile_enable")
+
+    def profile_report(self) -> dict:
+        """{kernel name: (total ms, launches, algorithmic bytes)} since the last reset."""
+        out = {}
+        buf = ctypes.create_string_buffer(128)
+        for i in range(self.lib.helm_profile_count(self._h)):
+            ms, n, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+            self.lib.helm_profile_get(self._h, i, buf, 128, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by))
+            out[buf.value.decode()] = (ms.value, n.value, by.value)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
