@@ -26,6 +26,7 @@ struct Level {
   int n = 0;
   long long N = 0;
   c32* kc = nullptr;  // kappa * c_l
+  c32* wd = nullptr;  // omega / diag(K_kappa,l)
   c32 ghost{};
   c32* rc = nullptr;  // [maxB][N] right-hand side (levels >= 1)
   c32* e = nullptr;   // [maxB][N] solution (levels >= 1)
@@ -116,8 +117,10 @@ struct helm_ctx {
 
 namespace {
 
-LevelArgs fine_A(const helm_ctx* c) { return LevelArgs{c->ne, c->N0, c->d_chi, c->g0_hi}; }
-LevelArgs level_K(const helm_ctx* c, int l) { return LevelArgs{c->lv[l].n, c->lv[l].N, c->lv[l].kc, c->lv[l].ghost}; }
+LevelArgs fine_A(const helm_ctx* c) { return LevelArgs{c->ne, c->N0, c->d_chi, c->g0_hi, nullptr}; }
+LevelArgs level_K(const helm_ctx* c, int l) {
+  return LevelArgs{c->lv[l].n, c->lv[l].N, c->lv[l].kc, c->lv[l].ghost, c->lv[l].wd};
+}
 
 long long npts(int n, int dim) { return dim == 2 ? (long long)n * n : (long long)n * n * n; }
 
@@ -412,9 +415,19 @@ void upload_medium(helm_ctx* c, const float* n_map_dev) {
   std::vector<cd> cl = cf;
   for (int l = 0; l < c->L; ++l) {
     if (l > 0) cl = helm_host::coarse_coefficient(g, cl, c->lv[l - 1].n, l);
-    std::vector<c32> kc(cl.size());
-    for (size_t p = 0; p < cl.size(); ++p) kc[p] = to_c32(kappa * cl[p]);
+    std::vector<c32> kc(cl.size()), wd(cl.size());
+    const int nl = c->lv[l].n;
+    const cd gl(1.0, c->kbh * std::ldexp(1.0, l));
+    for (size_t p = 0; p < cl.size(); ++p) {
+      kc[p] = to_c32(kappa * cl[p]);
+      const int x = (int)(p % nl), y = (int)((p / nl) % nl), z = c->dim == 3 ? (int)(p / ((size_t)nl * nl)) : 0;
+      int ng = (x == 0) + (x == nl - 1) + (y == 0) + (y == nl - 1);
+      if (c->dim == 3) ng += (z == 0) + (z == nl - 1);
+      const cd D = 2.0 * c->dim - kappa * cl[p] - (double)ng * gl;
+      wd[p] = to_c32(c->o.omega_jac / D);
+    }
     check(hipMemcpy(c->lv[l].kc, kc.data(), kc.size() * sizeof(c32), hipMemcpyHostToDevice), "upload kc");
+    check(hipMemcpy(c->lv[l].wd, wd.data(), wd.size() * sizeof(c32), hipMemcpyHostToDevice), "upload wd");
   }
   std::vector<cd> inv;
   if (!helm_host::dense_inverse_transposed(g, cl, c->lv[c->L - 1].n, c->L - 1, kappa, inv))
@@ -537,6 +550,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
       L.N = npts(L.n, c->dim);
       L.ghost = make_float2(1.0f, (float)(c->kbh * std::ldexp(1.0, l)));
       L.kc = c->alloc<c32>(L.N);
+      L.wd = c->alloc<c32>(L.N);
       if (l > 0) {
         L.rc = c->alloc<c32>((size_t)maxB * L.N);
         L.e = c->alloc<c32>((size_t)maxB * L.N);

@@ -133,18 +133,48 @@ __device__ __forceinline__ c32 diag_at(const LevelArgs& lv, long long p, int ng,
 struct Coord {
   int x, y, z;
 };
-__host__ __device__ __forceinline__ Coord coord_of(long long p, int n, int dim) {
+// Coordinates of flat index p (< 2^31) on an n^dim grid, 32-bit arithmetic.
+__host__ __device__ __forceinline__ Coord coord_of32(unsigned p, unsigned n, int dim) {
   Coord c;
-  c.x = (int)(p % n);
-  long long q = p / n;
+  const unsigned q = p / n;
+  c.x = (int)(p - q * n);
   if (dim == 2) {
     c.y = (int)q;
     c.z = 0;
   } else {
-    c.y = (int)(q % n);
-    c.z = (int)(q / n);
+    const unsigned r = q / n;
+    c.y = (int)(q - r * n);
+    c.z = (int)r;
   }
   return c;
+}
+// Advance coordinates by `step` points along the flat index (step >= 0).
+__host__ __device__ __forceinline__ void coord_advance(Coord& c, int step, int n, int dim) {
+  c.x += step;
+  while (c.x >= n) {
+    c.x -= n;
+    if (++c.y == n && dim == 3) {
+      c.y = 0;
+      ++c.z;
+    }
+  }
+}
+// A' v at point p with branch-free, always in-bounds neighbour loads:
+// out-of-grid neighbours load v[p] and are multiplied by 0.
+__host__ __device__ __forceinline__ c32 stencil_point(const c32* v, long long p, const Coord& c, int n, int dim,
+                                                      c32 D) {
+  const long long n2 = (long long)n * n;
+  const int xm = c.x > 0, xp = c.x < n - 1, ym = c.y > 0, yp = c.y < n - 1;
+  const c32 vc = v[p];
+  const c32 a = v[p - xm], b = v[p + xp], cc = v[p - (long long)ym * n], d = v[p + (long long)yp * n];
+  c32 nb = make_float2(xm * a.x + xp * b.x + ym * cc.x + yp * d.x, xm * a.y + xp * b.y + ym * cc.y + yp * d.y);
+  if (dim == 3) {
+    const int zm = c.z > 0, zp = c.z < n - 1;
+    const c32 e = v[p - zm * n2], f = v[p + zp * n2];
+    nb.x += zm * e.x + zp * f.x;
+    nb.y += zm * e.y + zp * f.y;
+  }
+  return csub(cmul(D, vc), nb);
 }
 __host__ __device__ __forceinline__ int ghosts_of(const Coord& c, int n, int dim) {
   return dim == 2 ? ghosts2(c.x, c.y, n) : ghosts3(c.x, c.y, c.z, n);

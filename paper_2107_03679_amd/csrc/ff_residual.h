@@ -27,13 +27,12 @@ __host__ __device__ __forceinline__ cff ff_load_x(const c32* xh, const c32* xl, 
 
 // rb, xh, xl point at this right-hand side's vectors (xh == NULL: x = 0).
 __host__ __device__ inline c32 ff_residual_point(const FFArgs& a, const c32* rb, const c32* xh, const c32* xl,
-                                                 long long p, int n, int dim) {
+                                                 long long p, const Coord& c, int n, int dim) {
   const ff h2 = {a.h2_hi, a.h2_lo};
   c32 bv = rb[p];
   if (a.conj_rhs) bv.y = -bv.y;
   cff r = {ff_mul(ff_from(bv.x), h2), ff_mul(ff_from(bv.y), h2)};
   if (xh) {
-    const Coord c = coord_of(p, n, dim);
     const int ng = ghosts_of(c, n, dim);
     // D = 2d - c - ng g, in float-float
     const cff cc = cff_make(a.c_hi[p], a.c_lo[p]);

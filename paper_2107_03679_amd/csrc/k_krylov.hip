@@ -22,6 +22,7 @@ constexpr int PPT = 8;        // points per thread
 constexpr int CH = NT * PPT;  // points per block
 constexpr int NWAVE = NT / HELM_WAVE;
 constexpr int MAXM = 64;
+constexpr int VCH = 4;        // basis vectors streamed together
 
 __device__ __forceinline__ long long vidx(const KrylovArgs& k, int b, int i) {
   return ((long long)b * (k.m + 1) + i) * k.N;
@@ -30,12 +31,6 @@ __device__ __forceinline__ long long zidx(const KrylovArgs& k, int b, int i) {
   return ((long long)b * k.m + i) * k.N;
 }
 
-// A' z at point p (complex64): (2d - c - g #ghosts) z_p - sum of neighbours
-__device__ __forceinline__ c32 apply_point(const LevelArgs& lv, int dim, const c32* z, long long p) {
-  const Coord c = coord_of(p, lv.n, dim);
-  const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
-  return csub(cmul(D, z[p]), neighbour_sum(z, p, c, lv.n, dim));
-}
 
 __global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelArgs fine, int with_matvec) {
   __shared__ c32 red[NWAVE][MAXM + 1];
@@ -46,14 +41,17 @@ __global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelA
   c32 w[PPT];
   if (with_matvec) {
     const c32* z = k.Z + zidx(k, b, j);
+    Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
       const long long p = p0 + (long long)t * NT;
       w[t] = make_float2(0.f, 0.f);
       if (p < k.N) {
-        w[t] = apply_point(fine, k.dim, z, p);
+        const c32 D = diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim);
+        w[t] = stencil_point(z, p, c, fine.n, k.dim, D);
         w_out[p] = w[t];
       }
+      coord_advance(c, NT, fine.n, k.dim);
     }
   } else {
 #pragma unroll
@@ -63,17 +61,31 @@ __global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelA
     }
   }
   const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
-  for (int i = 0; i <= j; ++i) {
-    const c32* vi = k.V + vidx(k, b, i);
-    c32 acc = make_float2(0.f, 0.f);
+  // basis vectors in chunks of VCH: VCH * PPT independent loads in flight per thread
+  for (int i0 = 0; i0 <= j; i0 += VCH) {
+    c32 acc[VCH];
 #pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      const long long p = p0 + (long long)t * NT;
-      if (p < k.N) acc = cadd(acc, cconjmul(vi[p], w[t]));
+    for (int q = 0; q < VCH; ++q) {
+      acc[q] = make_float2(0.f, 0.f);
+      if (i0 + q <= j) {
+        const c32* vi = k.V + vidx(k, b, i0 + q);
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+          const long long p = p0 + (long long)t * NT;
+          if (p < k.N) acc[q] = cadd(acc[q], cconjmul(vi[p], w[t]));
+        }
+      }
     }
-    acc.x = wave_sum(acc.x);
-    acc.y = wave_sum(acc.y);
-    if (lane == 0) red[wave][i] = acc;
+#pragma unroll
+    for (int q = 0; q < VCH; ++q) {
+      acc[q].x = wave_sum(acc[q].x);
+      acc[q].y = wave_sum(acc[q].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < VCH; ++q)
+        if (i0 + q <= j) red[wave][i0 + q] = acc[q];
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += NT) {
@@ -126,14 +138,19 @@ __global__ __launch_bounds__(NT) void k_arnoldi_update(KrylovArgs k, int j) {
     const long long p = p0 + (long long)t * NT;
     w[t] = p < k.N ? wv[p] : make_float2(0.f, 0.f);
   }
-  for (int i = 0; i <= j; ++i) {
-    const c32 ci = k.coef[b * (k.m + 1) + i];
-    const c32 nci = make_float2(-ci.x, -ci.y);
-    const c32* vi = k.V + vidx(k, b, i);
+  for (int i0 = 0; i0 <= j; i0 += VCH) {
 #pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      const long long p = p0 + (long long)t * NT;
-      if (p < k.N) w[t] = cfma(nci, vi[p], w[t]);
+    for (int q = 0; q < VCH; ++q) {
+      if (i0 + q <= j) {
+        const c32 ci = k.coef[b * (k.m + 1) + i0 + q];
+        const c32 nci = make_float2(-ci.x, -ci.y);
+        const c32* vi = k.V + vidx(k, b, i0 + q);
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+          const long long p = p0 + (long long)t * NT;
+          if (p < k.N) w[t] = cfma(nci, vi[p], w[t]);
+        }
+      }
     }
   }
   float nrm = 0.f;
@@ -253,13 +270,18 @@ __global__ __launch_bounds__(NT) void k_x_update(KrylovArgs k, c32* x_hi, c32* x
   c32 d[PPT];
 #pragma unroll
   for (int t = 0; t < PPT; ++t) d[t] = make_float2(0.f, 0.f);
-  for (int i = 0; i < kk; ++i) {
-    const c32 yi = k.y[b * k.m + i];
-    const c32* zi = k.Z + zidx(k, b, i);
+  for (int i0 = 0; i0 < kk; i0 += VCH) {
 #pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      const long long p = p0 + (long long)t * NT;
-      if (p < k.N) d[t] = cfma(yi, zi[p], d[t]);
+    for (int q = 0; q < VCH; ++q) {
+      if (i0 + q < kk) {
+        const c32 yi = k.y[b * k.m + i0 + q];
+        const c32* zi = k.Z + zidx(k, b, i0 + q);
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+          const long long p = p0 + (long long)t * NT;
+          if (p < k.N) d[t] = cfma(yi, zi[p], d[t]);
+        }
+      }
     }
   }
   c32* xh = x_hi + (long long)b * k.N;
@@ -288,11 +310,14 @@ __global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
   const c32* xl = (a.x_zero || !a.x_lo) ? nullptr : a.x_lo + (long long)b * k.N;
   c32* ro = a.r_out + (long long)b * a.r_stride;
   float nrm = 0.f;
+  Coord c = coord_of32((unsigned)p0, (unsigned)n, dim);
 #pragma unroll 2
   for (int t = 0; t < PPT; ++t) {
     const long long p = p0 + (long long)t * NT;
+    const Coord ct = c;
+    coord_advance(c, NT, n, dim);
     if (p >= k.N) continue;
-    const c32 rv = ff_residual_point(a, rb, xh, xl, p, n, dim);
+    const c32 rv = ff_residual_point(a, rb, xh, xl, p, ct, n, dim);
     ro[p] = cscale(rv, a.out_scale);
     nrm = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, nrm));
   }

@@ -13,7 +13,7 @@ __global__ void k_plane_wave(int dim, int n, long long N, const float* fplane, c
   const int b = blockIdx.y;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
-  const Coord c = coord_of(p, n, dim);
+  const Coord c = coord_of32((unsigned)p, (unsigned)n, dim);
   const c32* t = tables + (long long)b * dim * n;
   c32 u = cmul(t[c.x], t[n + c.y]);
   if (dim == 3) u = cmul(u, t[2 * n + c.z]);
@@ -27,7 +27,7 @@ __global__ void k_grad_n(int dim, int B, int ne, int w, int n, const c32* u, con
   const long long Ni = dim == 2 ? (long long)n * n : (long long)n * n * n;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Ni) return;
-  const Coord c = coord_of(i, n, dim);
+  const Coord c = coord_of32((unsigned)i, (unsigned)n, dim);
   const long long Ne = dim == 2 ? (long long)ne * ne : (long long)ne * ne * ne;
   const long long p = dim == 2 ? (long long)(c.y + w) * ne + (c.x + w)
                                : ((long long)(c.z + w) * ne + (c.y + w)) * ne + (c.x + w);

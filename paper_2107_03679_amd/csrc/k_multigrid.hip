@@ -33,17 +33,28 @@ __global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs,
   const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  for (int idx = threadIdx.x; idx < RX * RY; idx += TCX * TCY) {
+  // stage 1: r and v1 = W r on the (2 TCX + 3) x (2 TCY + 3) halo region; every load of
+  // the stage is issued before any is used
+  constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
+  c32 rv[IT], wv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
     const int lx = idx % RX, ly = idx / RX;
     const int gx = fx0 + lx, gy = fy0 + ly;
-    c32 rv = make_float2(0.f, 0.f), vv = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const long long p = (long long)gy * n + gx;
-      rv = cscale(rb[p], sc);
-      vv = cscale(cmul(rv, crcp(diag_at(lv, p, ghosts2(gx, gy, n), 2))), omega);
+    const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx < NR) {
+      const c32 r1 = cscale(rv[it], sc);
+      sR[idx / RX][idx % RX] = r1;
+      sV[idx / RX][idx % RX] = cmul(r1, wv[it]);
     }
-    sR[ly][lx] = rv;
-    sV[ly][lx] = vv;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < SX * SY; idx += TCX * TCY) {
@@ -89,24 +100,43 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
   const int fy0 = (blockIdx.x / tiles_x) * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
-  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
-    const int lx = idx % CX, ly = idx / CX;
-    const int I = cxs + lx, J = cys + ly;
-    c32 e = make_float2(0.f, 0.f);
-    if (I >= 0 && I < nc && J >= 0 && J < nc) e = eb[(long long)J * nc + I];
-    sE[ly][lx] = e;
-  }
-  __syncthreads();
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  for (int idx = threadIdx.x; idx < HX * HY; idx += NT) {
+  // all global loads of both stages are issued up front
+  constexpr int NE = CX * CY, ITE = (NE + NT - 1) / NT;
+  constexpr int NH = HX * HY, ITH = (NH + NT - 1) / NT;
+  c32 ev[ITE], rv[ITH], wv[ITH];
+#pragma unroll
+  for (int it = 0; it < ITE; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = idx < NE && I >= 0 && I < nc && J >= 0 && J < nc;
+    ev[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < ITH; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
+    const bool ok = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < ITE; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx < NE) sE[idx / CX][idx % CX] = ev[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITH; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NH) continue;
     const int lx = idx % HX, ly = idx / HX;
     const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
-    c32 v2 = make_float2(0.f, 0.f), rv = v2, wv = v2;
+    c32 v2 = make_float2(0.f, 0.f), r1 = v2;
     if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const long long p = (long long)gy * n + gx;
-      rv = cscale(rb[p], sc);
-      wv = cscale(crcp(diag_at(lv, p, ghosts2(gx, gy, n), 2)), omega);
+      r1 = cscale(rv[it], sc);
       // bilinear prolongation (printed formula of Sec. IV-C)
       const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys;
       const int ox = gx & 1, oy = gy & 1;
@@ -118,11 +148,11 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
       } else if (oy) {
         pe = cscale(cadd(pe, sE[J + 1][I]), 0.5f);
       }
-      v2 = cadd(cmul(rv, wv), pe);
+      v2 = cadd(cmul(r1, wv[it]), pe);
     }
     sV[ly][lx] = v2;
-    sR[ly][lx] = rv;
-    sW[ly][lx] = wv;
+    sR[ly][lx] = r1;
+    sW[ly][lx] = wv[it];
   }
   __syncthreads();
   const int tx = threadIdx.x % TX, ty0 = (threadIdx.x / TX) * PY;
@@ -147,7 +177,7 @@ __global__ void k_jacobi_zero(int dim, VecSet r, ScaleSet rs, LevelArgs lv, floa
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= lv.N) return;
-  const Coord c = coord_of(p, lv.n, dim);
+  const Coord c = coord_of32((unsigned)p, (unsigned)lv.n, dim);
   const c32 rv = cscale(r.p[(long long)b * r.stride + p], scale_of(rs, b));
   v.p[(long long)b * v.stride + p] = cscale(cmul(rv, crcp(diag_at(lv, p, ghosts_of(c, lv.n, dim), dim))), omega);
 }
@@ -158,7 +188,7 @@ __global__ void k_jacobi(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float ome
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= lv.N) return;
-  const Coord c = coord_of(p, lv.n, dim);
+  const Coord c = coord_of32((unsigned)p, (unsigned)lv.n, dim);
   const c32* vb = v.p + (long long)b * v.stride;
   const c32 rv = cscale(r.p[(long long)b * r.stride + p], scale_of(rs, b));
   const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
@@ -174,7 +204,7 @@ __global__ void k_restrict_residual(int dim, VecSet r, ScaleSet rs, VecSet v, Le
   const long long ncN = dim == 2 ? (long long)nc * nc : (long long)nc * nc * nc;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ncN) return;
-  const Coord C = coord_of(q, nc, dim);
+  const Coord C = coord_of32((unsigned)q, (unsigned)nc, dim);
   const int n = lv.n;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
@@ -204,7 +234,7 @@ __global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, int n, long 
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
-  const Coord f = coord_of(p, n, dim);
+  const Coord f = coord_of32((unsigned)p, (unsigned)n, dim);
   const c32* eb = ec.p + (long long)b * ec.stride;
   c32 acc = make_float2(0.f, 0.f);
   const int oz = dim == 3 ? (f.z & 1) : 0;
@@ -226,51 +256,35 @@ __global__ void k_apply(int dim, VecSet x, ScaleSet xs, LevelArgs lv, float out_
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= lv.N) return;
-  const Coord c = coord_of(p, lv.n, dim);
+  const Coord c = coord_of32((unsigned)p, (unsigned)lv.n, dim);
   const c32* xb = x.p + (long long)b * x.stride;
   const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
   const c32 out = csub(cmul(D, xb[p]), neighbour_sum(xb, p, c, lv.n, dim));
   y.p[(long long)b * y.stride + p] = cscale(out, out_scale * scale_of(xs, b));
 }
 
-// z_b = M r_b with M given transposed (minvT[k * Nc + row] = M[row][k]); one
-// thread per row, right-hand sides in chunks staged through LDS.
-constexpr int CS_RHS = 4;
-constexpr int CS_K = 512;
-__global__ __launch_bounds__(256) void k_coarse_solve(const c32* minvT, int Nc, int B, VecSet r, VecSet z,
+// z_b = M r_b with M given transposed (minvT[k * Nc + row] = M[row][k]):
+// one thread per (row, right-hand side); r_b is staged in LDS and broadcast,
+// rows are read coalesced from the transposed inverse.
+constexpr int CS_MAX = 4096;
+__global__ __launch_bounds__(256) void k_coarse_solve(const c32* minvT, int Nc, VecSet r, VecSet z,
                                                       const int* active) {
-  __shared__ c32 sr[CS_RHS][CS_K];
+  __shared__ c32 sr[CS_MAX];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const c32* rb = r.p + (long long)b * r.stride;
+  for (int k = threadIdx.x; k < Nc; k += blockDim.x) sr[k] = rb[k];
+  __syncthreads();
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b0 = blockIdx.y * CS_RHS;
-  c32 acc[CS_RHS];
-#pragma unroll
-  for (int q = 0; q < CS_RHS; ++q) acc[q] = make_float2(0.f, 0.f);
-  for (int k0 = 0; k0 < Nc; k0 += CS_K) {
-    const int kn = min(CS_K, Nc - k0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < CS_RHS * kn; idx += blockDim.x) {
-      const int q = idx / kn, k = idx % kn;
-      const int b = b0 + q;
-      c32 v = make_float2(0.f, 0.f);
-      if (b < B && (!active || active[b])) v = r.p[(long long)b * r.stride + k0 + k];
-      sr[q][k] = v;
-    }
-    __syncthreads();
-    if (row < Nc) {
-      for (int k = 0; k < kn; ++k) {
-        const c32 mv = minvT[(long long)(k0 + k) * Nc + row];
-#pragma unroll
-        for (int q = 0; q < CS_RHS; ++q) acc[q] = cfma(mv, sr[q][k], acc[q]);
-      }
-    }
+  if (row >= Nc) return;
+  c32 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
+  int k = 0;
+  for (; k + 1 < Nc; k += 2) {
+    acc0 = cfma(minvT[(long long)k * Nc + row], sr[k], acc0);
+    acc1 = cfma(minvT[(long long)(k + 1) * Nc + row], sr[k + 1], acc1);
   }
-  if (row < Nc) {
-#pragma unroll
-    for (int q = 0; q < CS_RHS; ++q) {
-      const int b = b0 + q;
-      if (b < B && (!active || active[b])) z.p[(long long)b * z.stride + row] = acc[q];
-    }
-  }
+  if (k < Nc) acc0 = cfma(minvT[(long long)k * Nc + row], sr[k], acc0);
+  z.p[(long long)b * z.stride + row] = cadd(acc0, acc1);
 }
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -319,8 +333,7 @@ void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet
 }
 
 void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active) {
-  hipLaunchKernelGGL(k_coarse_solve, dim3(nblocks(Nc, 256), (B + CS_RHS - 1) / CS_RHS), dim3(256), 0, s, minvT, Nc,
-                     B, r, z, active);
+  hipLaunchKernelGGL(k_coarse_solve, dim3(nblocks(Nc, 256), B), dim3(256), 0, s, minvT, Nc, r, z, active);
 }
 
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,

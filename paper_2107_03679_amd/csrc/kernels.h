@@ -23,6 +23,7 @@ struct LevelArgs {
   long long N;      // n^dim
   const c32* coef;  // operator coefficient: kappa * c_l (K_kappa) or c (A)
   c32 ghost;        // Sommerfeld ghost factor 1 + j k_b h_l
+  const c32* wd;    // omega_S / diag(K_kappa) per point (multigrid levels only)
 };
 
 // per-RHS solver status on the device (the final values match helm.h's HELM_STATUS_*)
