@@ -207,6 +207,28 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     return;
   }
   Level& fine = c->lv[l];
+  const bool vcycle11 = c->o.fused && zero_guess && c->o.cycle == 1 && c->o.nu1 == 1 && c->o.nu2 == 1;
+  const long long small = dim == 2 ? 48LL * 48 : 16LL * 16 * 16;
+  if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr &&
+      r.p == fine.rc && out.p == fine.e) {
+    // levels l .. L-1 in one launch, one workgroup per right-hand side
+    CoarseCycleArgs a{};
+    a.dim = dim;
+    a.lp = l;
+    a.L = c->L;
+    a.omega = (float)c->o.omega_jac;
+    a.minvT = c->d_minvT;
+    a.active = act;
+    double by = 8.0 * c->Nc * c->Nc;
+    for (int q = l; q < c->L; ++q) {
+      const Level& Lq = c->lv[q];
+      a.lv[q] = CoarseLevel{Lq.n, Lq.N, Lq.wd, Lq.rc, Lq.e, Lq.t};
+      by += c->prof_B * 40.0 * Lq.N + 8.0 * Lq.N;
+    }
+    ProfScope ps(c, lvl_name("coarse_cycle", l), by);
+    launch_coarse_cycle(c->s, B, a);
+    return;
+  }
   Level& crs = c->lv[l + 1];
   VecSet rc{crs.rc, crs.N}, ec{crs.e, crs.N};
   const float om = (float)c->o.omega_jac;
@@ -488,6 +510,7 @@ void helm_default_opts(helm_opts* o) {
   o->reorth = 0;
   o->fused = 1;
   o->use_graph = 1;
+  o->coarse_single_launch = 1;
 }
 
 int helm_extended_size(int n, int abl_width, int levels) { return helm_host::extended_size(n, abl_width, levels); }

@@ -34,9 +34,10 @@ __device__ __forceinline__ long long zidx(const KrylovArgs& k, int b, int i) {
 
 __global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelArgs fine, int with_matvec) {
   __shared__ c32 red[NWAVE][MAXM + 1];
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;  // right-hand side fastest: the coefficient chunk is shared in L2
+  const int blk = blockIdx.y;
   if (!k.active[b]) return;
-  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  const long long p0 = (long long)blk * CH + threadIdx.x;
   c32* w_out = k.V + vidx(k, b, j + 1);
   c32 w[PPT];
   if (with_matvec) {
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelA
     c32 s = red[0][i];
 #pragma unroll
     for (int q = 1; q < NWAVE; ++q) s = cadd(s, red[q][i]);
-    k.P1[((long long)b * k.nblk + blockIdx.x) * (k.m + 1) + i] = s;
+    k.P1[((long long)b * k.nblk + blk) * (k.m + 1) + i] = s;
   }
 }
 
@@ -301,9 +302,10 @@ __global__ __launch_bounds__(NT) void k_x_update(KrylovArgs k, c32* x_hi, c32* x
 
 __global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
   __shared__ float red[NWAVE];
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;  // right-hand side fastest: the coefficient chunk is shared in L2
+  const int blk = blockIdx.y;
   if (k.status && k.status[b] != HELM_RUNNING) return;
-  const long long p0 = (long long)blockIdx.x * CH + threadIdx.x;
+  const long long p0 = (long long)blk * CH + threadIdx.x;
   const int n = k.n, dim = k.dim;
   const c32* rb = a.rhs + (long long)b * a.rhs_stride;
   const c32* xh = a.x_zero ? nullptr : a.x_hi + (long long)b * k.N;
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
     float s = 0.f;
 #pragma unroll
     for (int q = 0; q < NWAVE; ++q) s += red[q];
-    k.P2[(long long)b * k.nblk + blockIdx.x] = s;
+    k.P2[(long long)b * k.nblk + blk] = s;
   }
 }
 
@@ -391,7 +393,7 @@ int krylov_max_restart() { return MAXM; }
 
 void launch_arnoldi_dots(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs* fine, int with_matvec) {
   LevelArgs lv = fine ? *fine : LevelArgs{};
-  hipLaunchKernelGGL(k_arnoldi_dots, dim3(k.nblk, B), dim3(NT), 0, s, k, j, lv, with_matvec);
+  hipLaunchKernelGGL(k_arnoldi_dots, dim3(B, k.nblk), dim3(NT), 0, s, k, j, lv, with_matvec);
 }
 void launch_arnoldi_reduce(hipStream_t s, int B, const KrylovArgs& k, int j, int accumulate) {
   hipLaunchKernelGGL(k_arnoldi_reduce, dim3(B), dim3(NT), 0, s, k, j, accumulate);
@@ -411,7 +413,7 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
                         long long r_stride, float out_scale) {
   FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, c_hi, c_lo, ghost_hi, ghost_lo, h2_hi, h2_lo, r_out,
            r_stride, out_scale};
-  hipLaunchKernelGGL(k_residual_ff, dim3(k.nblk, B), dim3(NT), 0, s, k, a);
+  hipLaunchKernelGGL(k_residual_ff, dim3(B, k.nblk), dim3(NT), 0, s, k, a);
 }
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);

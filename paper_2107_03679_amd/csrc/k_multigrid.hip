@@ -16,32 +16,34 @@ namespace {
 
 
 // ------------------------------------------------------------ fused 2D legs
+// Down-leg on a TCX x TCY tile of coarse points (fine footprint 2 TCX + 1 wide):
+//   stage 1: r and v1 = W r on the (2 TCX + 3) x (2 TCY + 3) halo region, v1 -> LDS
+//   stage 2: s = r - K v1 = (1 - w) r + sum of in-grid neighbours of v1 (D v1 = w r)
+//            on the (2 TCX + 1) x (2 TCY + 1) interior, by the thread that holds r
+//   stage 3: rc = 4 R s (scaled coarse right-hand side)
 template <int TCX, int TCY>
 __global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
                                                            VecSet rc, int nc, const int* active) {
   constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3;
   constexpr int SX = 2 * TCX + 1, SY = 2 * TCY + 1;
-  __shared__ c32 sR[RY][RX];
+  constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
   __shared__ c32 sV[RY][RX];
   __shared__ c32 sS[SY][SX];
-  const int b = blockIdx.y;
+  // right-hand side fastest: the blocks of one tile run together and share its W in L2
+  const int b = blockIdx.x;
   if (active && !active[b]) return;
   const int n = lv.n;
   const int tiles_x = (nc + TCX - 1) / TCX;
-  const int cx0 = (blockIdx.x % tiles_x) * TCX;
-  const int cy0 = (blockIdx.x / tiles_x) * TCY;
+  const int cx0 = (blockIdx.y % tiles_x) * TCX;
+  const int cy0 = (blockIdx.y / tiles_x) * TCY;
   const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  // stage 1: r and v1 = W r on the (2 TCX + 3) x (2 TCY + 3) halo region; every load of
-  // the stage is issued before any is used
-  constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
   c32 rv[IT], wv[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int idx = threadIdx.x + it * NT;
-    const int lx = idx % RX, ly = idx / RX;
-    const int gx = fx0 + lx, gy = fy0 + ly;
+    const int gx = fx0 + idx % RX, gy = fy0 + idx / RX;
     const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
     const long long p = ok ? (long long)gy * n + gx : 0;
     rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
@@ -50,24 +52,22 @@ __global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs,
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int idx = threadIdx.x + it * NT;
-    if (idx < NR) {
-      const c32 r1 = cscale(rv[it], sc);
-      sR[idx / RX][idx % RX] = r1;
-      sV[idx / RX][idx % RX] = cmul(r1, wv[it]);
-    }
+    rv[it] = cscale(rv[it], sc);
+    if (idx < NR) sV[idx / RX][idx % RX] = cmul(rv[it], wv[it]);
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < SX * SY; idx += TCX * TCY) {
-    const int sx = idx % SX, sy = idx / SX;
-    const int lx = sx + 1, ly = sy + 1;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int lx = idx % RX, ly = idx / RX;
+    if (idx >= NR || lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1) continue;
     const int gx = fx0 + lx, gy = fy0 + ly;
     c32 s = make_float2(0.f, 0.f);
     if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      // s = r - K v1 = (1 - w) r + sum of in-grid neighbours of v1 (D v1 = w r)
       const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-      s = cadd(cscale(sR[ly][lx], 1.0f - omega), nb);
+      s = cadd(cscale(rv[it], 1.0f - omega), nb);
     }
-    sS[sy][sx] = s;
+    sS[ly - 1][lx - 1] = s;
   }
   __syncthreads();
   const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
@@ -82,30 +82,65 @@ __global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs,
   }
 }
 
+// bilinear prolongation at fine point (gx, gy) from the LDS coarse tile whose
+// origin is coarse point (cxs, cys) (printed formula of Sec. IV-C)
+template <int CX>
+__device__ __forceinline__ c32 prolong_lds(const c32 (*sE)[CX], int gx, int gy, int cxs, int cys) {
+  const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys;
+  const int ox = gx & 1, oy = gy & 1;
+  c32 pe = sE[J][I];
+  if (ox && oy) return cscale(cadd(cadd(pe, sE[J][I + 1]), cadd(sE[J + 1][I], sE[J + 1][I + 1])), 0.25f);
+  if (ox) return cscale(cadd(pe, sE[J][I + 1]), 0.5f);
+  if (oy) return cscale(cadd(pe, sE[J + 1][I]), 0.5f);
+  return pe;
+}
+
+// Up-leg on a TX x TY tile of fine points; thread (tx, ty0..ty0+PY) owns a
+// column segment and keeps r and W of its own points in registers:
+//   v2 = W r + P e on the (TX + 2) x (TY + 2) halo region (own points + a ring) -> LDS
+//   z  = v2 + W (r - K v2) = (1 - w) v2 + W (r + sum of in-grid neighbours of v2)
 template <int TX, int TY, int PY>
 __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
                                                              VecSet ec, int nc, VecSet z, const int* active) {
   constexpr int HX = TX + 2, HY = TY + 2;
   constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2;
   constexpr int NT = TX * (TY / PY);
+  constexpr int NRING = 2 * HX + 2 * TY;
+  static_assert(NRING <= NT, "one ring point per thread");
   __shared__ c32 sE[CY][CX];
   __shared__ c32 sV[HY][HX];
-  __shared__ c32 sR[HY][HX];
-  __shared__ c32 sW[HY][HX];
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;  // right-hand side fastest (see k_down_fused2)
   if (active && !active[b]) return;
   const int n = lv.n;
   const int tiles_x = (n + TX - 1) / TX;
-  const int fx0 = (blockIdx.x % tiles_x) * TX;
-  const int fy0 = (blockIdx.x / tiles_x) * TY;
+  const int fx0 = (blockIdx.y % tiles_x) * TX;
+  const int fy0 = (blockIdx.y / tiles_x) * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  // all global loads of both stages are issued up front
+  const int tx = threadIdx.x % TX, ty0 = (threadIdx.x / TX) * PY;
+  // ring point of this thread (halo-local coordinates), if any
+  int rlx = -1, rly = -1;
+  {
+    const int t = threadIdx.x;
+    if (t < HX) {
+      rlx = t;
+      rly = 0;
+    } else if (t < 2 * HX) {
+      rlx = t - HX;
+      rly = HY - 1;
+    } else if (t < 2 * HX + TY) {
+      rlx = 0;
+      rly = t - 2 * HX + 1;
+    } else if (t < NRING) {
+      rlx = HX - 1;
+      rly = t - 2 * HX - TY + 1;
+    }
+  }
+  // issue every global load first
   constexpr int NE = CX * CY, ITE = (NE + NT - 1) / NT;
-  constexpr int NH = HX * HY, ITH = (NH + NT - 1) / NT;
-  c32 ev[ITE], rv[ITH], wv[ITH];
+  c32 ev[ITE], rv[PY + 1], wv[PY + 1];
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
     const int idx = threadIdx.x + it * NT;
@@ -114,13 +149,13 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
     ev[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
   }
 #pragma unroll
-  for (int it = 0; it < ITH; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
-    const bool ok = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n;
+  for (int k = 0; k <= PY; ++k) {
+    const int gx = k < PY ? fx0 + tx : fx0 - 1 + rlx;
+    const int gy = k < PY ? fy0 + ty0 + k : fy0 - 1 + rly;
+    const bool ok = (k < PY || rlx >= 0) && gx >= 0 && gx < n && gy >= 0 && gy < n;
     const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    rv[k] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    wv[k] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
   }
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
@@ -128,44 +163,26 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
     if (idx < NE) sE[idx / CX][idx % CX] = ev[it];
   }
   __syncthreads();
+  c32 v2own[PY];
 #pragma unroll
-  for (int it = 0; it < ITH; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NH) continue;
-    const int lx = idx % HX, ly = idx / HX;
+  for (int k = 0; k <= PY; ++k) {
+    const int lx = k < PY ? tx + 1 : rlx, ly = k < PY ? ty0 + k + 1 : rly;
+    if (k == PY && rlx < 0) continue;
     const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
-    c32 v2 = make_float2(0.f, 0.f), r1 = v2;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      r1 = cscale(rv[it], sc);
-      // bilinear prolongation (printed formula of Sec. IV-C)
-      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys;
-      const int ox = gx & 1, oy = gy & 1;
-      c32 pe = sE[J][I];
-      if (ox && oy) {
-        pe = cscale(cadd(cadd(pe, sE[J][I + 1]), cadd(sE[J + 1][I], sE[J + 1][I + 1])), 0.25f);
-      } else if (ox) {
-        pe = cscale(cadd(pe, sE[J][I + 1]), 0.5f);
-      } else if (oy) {
-        pe = cscale(cadd(pe, sE[J + 1][I]), 0.5f);
-      }
-      v2 = cadd(cmul(r1, wv[it]), pe);
-    }
+    c32 v2 = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) v2 = cadd(cmul(rv[k], wv[k]), prolong_lds<CX>(sE, gx, gy, cxs, cys));
+    if (k < PY) v2own[k] = v2;
     sV[ly][lx] = v2;
-    sR[ly][lx] = r1;
-    sW[ly][lx] = wv[it];
   }
   __syncthreads();
-  const int tx = threadIdx.x % TX, ty0 = (threadIdx.x / TX) * PY;
   c32* zb = z.p + (long long)b * z.stride;
 #pragma unroll
   for (int k = 0; k < PY; ++k) {
     const int lx = tx + 1, ly = ty0 + k + 1;
     const int gx = fx0 + tx, gy = fy0 + ty0 + k;
     if (gx < n && gy < n) {
-      // z = v2 + w D^-1 (r - K v2) = (1 - w) v2 + (w / D)(r + sum of neighbours of v2)
       const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-      const c32 zz = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(sW[ly][lx], cadd(sR[ly][lx], nb)));
-      zb[(long long)gy * n + gx] = zz;
+      zb[(long long)gy * n + gx] = cadd(cscale(v2own[k], 1.0f - omega), cmul(wv[k], cadd(rv[k], nb)));
     }
   }
 }
@@ -298,14 +315,14 @@ constexpr int UP_TX = 64, UP_TY = 16, UP_PY = 4;
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active) {
   const int tiles = ((nc + DN_TCX - 1) / DN_TCX) * ((nc + DN_TCY - 1) / DN_TCY);
-  hipLaunchKernelGGL((k_down_fused2<DN_TCX, DN_TCY>), dim3(tiles, B), dim3(DN_TCX * DN_TCY), 0, s, r, rs, lv, omega,
+  hipLaunchKernelGGL((k_down_fused2<DN_TCX, DN_TCY>), dim3(B, tiles), dim3(DN_TCX * DN_TCY), 0, s, r, rs, lv, omega,
                      rc, nc, active);
 }
 
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active) {
   const int tiles = ((lv.n + UP_TX - 1) / UP_TX) * ((lv.n + UP_TY - 1) / UP_TY);
-  hipLaunchKernelGGL((k_up_fused2<UP_TX, UP_TY, UP_PY>), dim3(tiles, B), dim3(UP_TX * (UP_TY / UP_PY)), 0, s, r,
+  hipLaunchKernelGGL((k_up_fused2<UP_TX, UP_TY, UP_PY>), dim3(B, tiles), dim3(UP_TX * (UP_TY / UP_PY)), 0, s, r,
                      rs, lv, omega, ec, nc, z, active);
 }
 

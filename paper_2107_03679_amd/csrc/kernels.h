@@ -50,6 +50,25 @@ void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet 
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active);
 
+// ---- coarse levels of a V-cycle in one launch (one workgroup per right-hand side) ----
+struct CoarseLevel {
+  int n;
+  long long N;
+  const c32* wd;  // omega / diag(K_l)
+  c32* rc;        // [B][N] right-hand side
+  c32* e;         // [B][N] solution
+  c32* t;         // [B][N] scratch
+};
+constexpr int HELM_MAX_LEVELS = 12;
+struct CoarseCycleArgs {
+  int dim, lp, L;  // levels lp .. L-1 are handled; lp's rc is the input, its e the output
+  float omega;
+  const c32* minvT;
+  const int* active;
+  CoarseLevel lv[HELM_MAX_LEVELS];
+};
+void launch_coarse_cycle(hipStream_t s, int B, const CoarseCycleArgs& a);
+
 // ---- Krylov (FGMRES / float-float outer loop), flat over the fine grid ----
 struct KrylovArgs {
   int dim;

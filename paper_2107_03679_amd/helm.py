@@ -37,6 +37,7 @@ class HelmOpts(ctypes.Structure):
         ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("cycle", ctypes.c_int),
         ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("reorth", ctypes.c_int), ("fused", ctypes.c_int), ("use_graph", ctypes.c_int),
+        ("coarse_single_launch", ctypes.c_int),
     ]
 
 

@@ -92,7 +92,7 @@ def test_vcycle_fused_matches_oracle(pair):
     assert rel(z, ref) < 1e-5
 
 
-@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle"])
+@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle", "per_level_launch"])
 def test_cycle_variants_match_oracle(variant):
     n, w, levels = CASES["ragged"]
     nmap = medium(n, seed=3)
@@ -102,7 +102,7 @@ def test_cycle_variants_match_oracle(variant):
     prob = oracle_problem(nmap, w=w, levels=levels, nu=nu)
     hier = Hierarchy(prob)
     ctx = gpu_context(nmap, w=w, levels=levels, nu=nu, cycle=cyc, fused=0 if variant == "generic_v" else 1,
-                      max_batch=2)
+                      coarse_single_launch=0 if variant == "per_level_launch" else 1, max_batch=2)
     r = fields(prob.shape, 2, 61)
     z = to_np(ctx.precondition(to_dev(r)))
     ref = np.stack([hier.cycle(ri.ravel(), None, 0, cyc).reshape(prob.shape) for ri in r])
