@@ -173,11 +173,28 @@ int helm_adjoint_batch(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* lam,
 
 /* Refractive-index gradient of a real loss through Prop. 1 (Sec. V):
  *   grad_n[i] = sum_q 2 k0^2 eta_i Re(conj(u_q,i) lam_q,i) on Omega,
- * with u_q the TOTAL field (u_in + u_sc) and lam_q the adjoint states; for
- * the quadratic data term 1/2 ||S u_sc,q - y_q||^2 on receiver samples S,
- * lam_q = A^-H S^T (S u_sc,q - y_q).  grad_n: device float[n^dim]
- * (overwritten, Omega only). */
-int helm_grad_n(helm_ctx* ctx, int B, const helm_c32* u_total, const helm_c32* lam, float* grad_n);
+ * with u_q = u_in,q + u_sc,q the TOTAL field and lam_q the adjoint states;
+ * for the quadratic data term 1/2 ||S u_sc,q - y_q||^2 on receiver samples S,
+ * lam_q = A^-H S^T (S u_sc,q - y_q).  u_in may be NULL (u_sc is then taken
+ * as the total field).  grad_n: device float[n^dim] (overwritten, Omega). */
+int helm_grad_n(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                float* grad_n);
+
+/* Receiver sampling S of the data term (Sec. V, eq. DataFidelityExplicit,
+ * with on-grid receivers): y[q][i] = u[q][idx[i]] for M receiver flat indices
+ * idx_dev (device int[M], distinct, on the extended grid). */
+int helm_sample(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* u, helm_c32* y);
+
+/* S^T: u = 0 except u[q][idx[i]] = y[q][i]. */
+int helm_sample_adjoint(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* y, helm_c32* u);
+
+/* Smoothed isotropic total variation of an interior map (the regulariser of
+ * Sec. V, smoothed so that it is differentiable):
+ *   TV = sum_i sqrt(sum_axis (n_{i+e_axis} - n_i)^2 + eps^2), forward
+ * differences, zero difference across the last row/column/plane.
+ * grad_dev (device float[n^dim], overwritten) = scale * dTV/dn;
+ * value_host = TV (FP64 sum of FP32 per-block partial sums). */
+int helm_tv(helm_ctx* ctx, const float* n_map_dev, double eps, double scale, float* grad_dev, double* value_host);
 
 /* ---- building blocks, exposed for verification and custom solvers ---- */
 

@@ -77,6 +77,8 @@ struct helm_ctx {
   c32* d_T0 = nullptr;   // generic-path scratch on the fine level
   c32* d_tables = nullptr;
   int* d_ones = nullptr;
+  float* d_tv_mag = nullptr;   // [n^dim] TV magnitudes
+  float* d_tv_part = nullptr;  // per-block TV partial sums
   int* h_status = nullptr;  // pinned
   int* h_iters = nullptr;
   double* h_relres = nullptr;
@@ -592,6 +594,8 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     c->d_T0 = c->alloc<c32>((size_t)maxB * N0);
     c->d_tables = c->alloc<c32>((size_t)maxB * c->dim * ne);
     c->d_ones = c->alloc<int>(maxB);
+    c->d_tv_mag = c->alloc<float>(npts(c->n, c->dim));
+    c->d_tv_part = c->alloc<float>(tv_partials(c->dim, c->n));
     KrylovArgs& k = c->k;
     k.dim = c->dim;
     k.n = ne;
@@ -710,13 +714,14 @@ int helm_solution_lo(helm_ctx* c, int B, helm_c32* x_lo) {
   HELM_GUARD_END("solution_lo")
 }
 
-int helm_grad_n(helm_ctx* c, int B, const helm_c32* u_total, const helm_c32* lam, float* grad_n) {
-  if (!c || !u_total || !lam || !grad_n) return fail(c, HELM_EINVAL, "null argument");
+int helm_grad_n(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                float* grad_n) {
+  if (!c || !u_sc || !lam || !grad_n) return fail(c, HELM_EINVAL, "null argument");
   if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
   try {
     check(hipStreamSynchronize(c->user_s), "caller stream");
-    launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_total, (const c32*)lam, c->d_nmap,
-                  (float)(2.0 * c->k0 * c->k0), grad_n);
+    launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_in, (const c32*)u_sc, (const c32*)lam,
+                  c->d_nmap, (float)(2.0 * c->k0 * c->k0), grad_n);
     check(hipGetLastError(), "grad_n");
     check(hipStreamSynchronize(c->s), "sync");
   } catch (const HipError& e) {
@@ -812,6 +817,37 @@ int helm_profile_get(const helm_ctx* c, int i, char* name, int name_len, double*
   if (launches) *launches = e.launches;
   if (bytes) *bytes = e.bytes;
   return HELM_OK;
+}
+
+int helm_sample(helm_ctx* c, int B, int M, const int* idx, const helm_c32* u, helm_c32* y) {
+  if (!c || !idx || !u || !y || B < 1 || M < 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_gather(c->s, B, M, c->N0, idx, (const c32*)u, (c32*)y);
+  HELM_GUARD_END("sample")
+}
+
+int helm_sample_adjoint(helm_ctx* c, int B, int M, const int* idx, const helm_c32* y, helm_c32* u) {
+  if (!c || !idx || !u || !y || B < 1 || M < 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_zero(c->s, (long long)B * c->N0, (c32*)u);
+  launch_scatter(c->s, B, M, c->N0, idx, (const c32*)y, (c32*)u);
+  HELM_GUARD_END("sample_adjoint")
+}
+
+int helm_tv(helm_ctx* c, const float* n_map, double eps, double scale, float* grad, double* value) {
+  if (!c || !n_map || !grad) return fail(c, HELM_EINVAL, "bad argument");
+  const int np = tv_partials(c->dim, c->n);
+  HELM_GUARD_BEGIN
+  launch_tv(c->s, c->dim, c->n, n_map, (float)eps, (float)scale, c->d_tv_mag, c->d_tv_part, grad);
+  if (value) {
+    std::vector<float> part(np);
+    check(hipMemcpyAsync(part.data(), c->d_tv_part, np * sizeof(float), hipMemcpyDeviceToHost, c->s), "tv");
+    check(hipStreamSynchronize(c->s), "sync");
+    double v = 0.0;
+    for (float x : part) v += x;
+    *value = v;
+  }
+  HELM_GUARD_END("tv")
 }
 
 const char* helm_last_error(const helm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }

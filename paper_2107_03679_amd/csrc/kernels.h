@@ -113,9 +113,14 @@ void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
 // ---- model kernels ----
 void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane, const c32* tables, c32* rhs,
                        c32* uin);
-void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* u, const c32* lam,
-                   const float* nmap, float scale, float* grad);
+void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* uin, const c32* u,
+                   const c32* lam, const float* nmap, float scale, float* grad);
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out);
+void launch_gather(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, c32* y);
+void launch_scatter(hipStream_t s, int B, int M, long long N, const int* idx, const c32* y, c32* u);
+int tv_partials(int dim, int n);
+void launch_tv(hipStream_t s, int dim, int n, const float* nm, float eps, float scale, float* mag, float* part,
+               float* grad);
 void launch_zero(hipStream_t s, long long count, c32* p);
 void launch_status_init(hipStream_t s, int B, const KrylovArgs& k);
 int krylov_blocks_per_rhs(long long N);

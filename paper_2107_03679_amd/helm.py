@@ -58,7 +58,7 @@ EXPORTS = [
     "helm_default_opts", "helm_extended_size", "helm_setup", "helm_update_n", "helm_get_info",
     "helm_plane_wave_rhs", "helm_solve_batch", "helm_adjoint_batch", "helm_grad_n", "helm_apply_A",
     "helm_residual", "helm_apply_K", "helm_restrict", "helm_prolong_add", "helm_coarse_solve",
-    "helm_precondition", "helm_solution_lo", "helm_profile_enable", "helm_profile_reset", "helm_profile_count",
+    "helm_precondition", "helm_solution_lo", "helm_sample", "helm_sample_adjoint", "helm_tv", "helm_profile_enable", "helm_profile_reset", "helm_profile_count",
     "helm_profile_get", "helm_last_error", "helm_destroy",
 ]
 
@@ -84,7 +84,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_plane_wave_rhs.argtypes = [vp, i, vp, vp, vp]
     lib.helm_solve_batch.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats)]
     lib.helm_adjoint_batch.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats)]
-    lib.helm_grad_n.argtypes = [vp, i, vp, vp, vp]
+    lib.helm_grad_n.argtypes = [vp, i, vp, vp, vp, vp]
+    lib.helm_sample.argtypes = [vp, i, i, vp, vp, vp]
+    lib.helm_sample_adjoint.argtypes = [vp, i, i, vp, vp, vp]
+    lib.helm_tv.argtypes = [vp, vp, d, d, vp, ctypes.POINTER(d)]
     lib.helm_apply_A.argtypes = [vp, i, vp, vp]
     lib.helm_residual.argtypes = [vp, i, vp, vp, vp, vp]
     lib.helm_apply_K.argtypes = [vp, i, i, vp, vp]
@@ -233,11 +236,34 @@ class Context:
     def adjoint(self, rhs: torch.Tensor, out: torch.Tensor | None = None):
         return self.solve(rhs, out, adjoint=True)
 
-    def grad_n(self, u_total: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+    def grad_n(self, u_sc: torch.Tensor, lam: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
+        """sum_q 2 k0^2 n Re(conj(u_in + u_sc) lam) on Omega (u_in None: u_sc is the total field)."""
         grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
-        self._check(self.lib.helm_grad_n(self._h, u_total.shape[0], _ptr(u_total), _ptr(lam), _ptr(grad)),
+        self._check(self.lib.helm_grad_n(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(grad)),
                     "helm_grad_n")
         return grad
+
+    def sample(self, idx: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+        """S u: values at receiver flat indices idx (int32 on the GPU) -> [B, M]."""
+        y = torch.empty((u.shape[0], idx.numel()), dtype=torch.complex64, device=self.device)
+        self._check(self.lib.helm_sample(self._h, u.shape[0], idx.numel(), _ptr(idx), _ptr(u), _ptr(y)),
+                    "helm_sample")
+        return y
+
+    def sample_adjoint(self, idx: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        """S^T y on the extended grid."""
+        u = self.empty_fields(y.shape[0])
+        self._check(self.lib.helm_sample_adjoint(self._h, y.shape[0], idx.numel(), _ptr(idx), _ptr(y), _ptr(u)),
+                    "helm_sample_adjoint")
+        return u
+
+    def tv(self, n_map: torch.Tensor, eps: float = 1e-4, scale: float = 1.0):
+        """(smoothed TV value, scale * gradient) of an interior map."""
+        n_map = n_map.to(torch.float32).contiguous()
+        grad = torch.empty_like(n_map)
+        val = ctypes.c_double()
+        self._check(self.lib.helm_tv(self._h, _ptr(n_map), eps, scale, _ptr(grad), ctypes.byref(val)), "helm_tv")
+        return val.value, grad
 
     def apply_A(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

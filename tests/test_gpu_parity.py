@@ -180,9 +180,13 @@ def test_grad_n_kernel(pair):
     prob, ctx, _ = pair
     u = fields(prob.shape, 3, 80).astype(np.complex64)
     lam = fields(prob.shape, 3, 81).astype(np.complex64)
+    uin = fields(prob.shape, 3, 82).astype(np.complex64)
     g = ctx.grad_n(to_dev(u), to_dev(lam)).cpu().numpy().astype(np.float64)
     ref = model.scalar_field_gradient(prob, u.astype(np.complex128), lam.astype(np.complex128))
     assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < 1e-5
+    g2 = ctx.grad_n(to_dev(u), to_dev(lam), u_in=to_dev(uin)).cpu().numpy().astype(np.float64)
+    ref2 = model.scalar_field_gradient(prob, u.astype(np.complex128) + uin, lam.astype(np.complex128))
+    assert np.linalg.norm(g2 - ref2) / np.linalg.norm(ref2) < 1e-5
 
 
 def test_solve_is_deterministic(pair):
