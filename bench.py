@@ -34,8 +34,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="blobs512x60")
     p.add_argument("--levels", type=int, default=7)
-    p.add_argument("--restart", type=int, default=10)
-    p.add_argument("--cycle", type=int, default=1)
+    p.add_argument("--restart", type=int, default=5)
+    p.add_argument("--cycle", type=int, default=3, help="1 = V, 2 = W, 3 = two coarse corrections on the finest "
+                                                          "level and V-cycles below")
     p.add_argument("--reorth", type=int, default=0)
     p.add_argument("--rhs", type=int, default=None, help="override the number of plane waves")
     p.add_argument("--no-profile", action="store_true")
@@ -62,7 +63,8 @@ def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
         hier = Hierarchy(prob)
         a = helmholtz_matrix(prob)
         b = (prob.h ** 2 * rhs(prob, synth.directions_2d(1, 0.0, 0.0)[0])).ravel()
-        pc = (lambda r: hier.cycle(r, None, 0, cycle))
+        ct = [2] + [1] * (levels - 2) if cycle == 3 else cycle
+        pc = (lambda r: hier.cycle(r, None, 0, ct))
         t0 = time.perf_counter()
         fgmres(lambda v: a @ v, pc, b, rtol=1e-30, restart=restart, max_iters=2)
         per_iter = (time.perf_counter() - t0) / 2
@@ -145,7 +147,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload, "interior": wl["n"], "grid": ne, "rhs": B, "levels": args.levels,
-            "coarsest": ctx.info.coarsest_n, "restart": args.restart, "cycle": "V" if args.cycle == 1 else "W",
+            "coarsest": ctx.info.coarsest_n, "restart": args.restart, "cycle": {1: "V", 2: "W", 3: "W at the finest level, V below"}[args.cycle],
             "kappa": "1+0.5j", "nu": [1, 1], "omega_jac": 0.8, "rtol": 1e-6, "preconditioner": "multigrid",
             "krylov": "FGMRES" + ("(CGS2)" if args.reorth else "(CGS1)"),
         },

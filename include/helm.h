@@ -93,7 +93,8 @@ typedef struct {
   double rtol;      /* stop when ||b - A x|| <= rtol ||b||, true residual (1e-6) */
   int levels;       /* multigrid levels incl. the exactly solved coarsest (4) */
   int nu1, nu2;     /* pre/post relaxations (1, 1) */
-  int cycle;        /* 1 = V-cycle, 2 = W-cycle (Alg. 2 CycleType) (1) */
+  int cycle;        /* 1 = V-cycle, 2 = W-cycle (Alg. 2 CycleType); 3 = two coarse-grid
+                       corrections on the finest level and V-cycles below (1) */
   int restart;      /* FGMRES restart length m (10) */
   int max_iters;    /* max preconditioner applications per RHS (4000) */
   int max_batch;    /* largest B accepted by the solve calls (64) */

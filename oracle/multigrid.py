@@ -129,17 +129,24 @@ class Hierarchy:
             v = v - w * self.Dinv[l] * (self.K[l] @ v - b)
         return v
 
-    def cycle(self, b: np.ndarray, v: np.ndarray | None = None, l: int = 0, cycle_type: int = 1) -> np.ndarray:
-        """Alg. 2 on level l for the scaled system K'_l v = b (v = 0 when None)."""
+    def cycle(self, b: np.ndarray, v: np.ndarray | None = None, l: int = 0, cycle_type=1) -> np.ndarray:
+        """Alg. 2 on level l for the scaled system K'_l v = b (v = 0 when None).
+
+        ``cycle_type`` is Alg. 2's CycleType (1 = V, 2 = W) or a per-level
+        sequence of them (e.g. [2, 1, 1, ...]: two coarse-grid corrections on
+        the finest level only, V-cycles below -- a per-level choice outside the
+        paper, analogous to its per-level smoothing counts).
+        """
         if v is None:
             v = np.zeros_like(b)
         if l == self.levels - 1:
             return self.coarse_lu.solve(b)
+        gamma = cycle_type if np.isscalar(cycle_type) else cycle_type[l]
         v = self.jacobi(l, b, v, self.prob.nu1)
         r = b - self.K[l] @ v
         rc = 4.0 * (self.R[l] @ r)
         e = np.zeros_like(rc)
-        for _ in range(cycle_type):
+        for _ in range(gamma):
             e = self.cycle(rc, e, l + 1, cycle_type)
         v = v + self.P[l] @ e
         return self.jacobi(l, b, v, self.prob.nu2)

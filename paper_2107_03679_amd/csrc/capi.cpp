@@ -31,6 +31,8 @@ struct Level {
   c32* rc = nullptr;  // [maxB][N] right-hand side (levels >= 1)
   c32* e = nullptr;   // [maxB][N] solution (levels >= 1)
   c32* t = nullptr;   // [maxB][N] scratch of the generic path
+  c32* rr = nullptr;  // [maxB][N] right-hand side of a repeated visit (b - K e)
+  c32* d = nullptr;   // [maxB][N] correction of a repeated visit
 };
 
 struct HipError {
@@ -209,10 +211,14 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     return;
   }
   Level& fine = c->lv[l];
-  const bool vcycle11 = c->o.fused && zero_guess && c->o.cycle == 1 && c->o.nu1 == 1 && c->o.nu2 == 1;
+  // coarse-grid corrections per visit of level l: Alg. 2's CycleType, or for
+  // cycle = 3 two on the finest level and one below
+  const int gamma = c->o.cycle == 3 ? (l == 0 ? 2 : 1) : c->o.cycle;
+  const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
+  const bool vcycle11 = c->o.fused && zero_guess && v_below && c->o.nu1 == 1 && c->o.nu2 == 1;
   const long long small = dim == 2 ? 48LL * 48 : 16LL * 16 * 16;
-  if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr &&
-      r.p == fine.rc && out.p == fine.e) {
+  if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr && r.stride == fine.N &&
+      out.stride == fine.N) {
     // levels l .. L-1 in one launch, one workgroup per right-hand side
     CoarseCycleArgs a{};
     a.dim = dim;
@@ -227,6 +233,8 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
       a.lv[q] = CoarseLevel{Lq.n, Lq.N, Lq.wd, Lq.rc, Lq.e, Lq.t};
       by += c->prof_B * 40.0 * Lq.N + 8.0 * Lq.N;
     }
+    a.lv[l].rc = r.p;  // this visit's right-hand side and result buffers
+    a.lv[l].e = out.p;
     ProfScope ps(c, lvl_name("coarse_cycle", l), by);
     launch_coarse_cycle(c->s, B, a);
     return;
@@ -255,9 +263,21 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
   }
   const bool next_is_coarsest = (l + 1 == c->L - 1);
-  for (int cyc = 0; cyc < std::max(1, c->o.cycle); ++cyc) {
-    if (cyc > 0 && next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
-    mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, cyc == 0, act);
+  for (int cyc = 0; cyc < gamma; ++cyc) {
+    if (cyc == 0) {
+      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, true, act);
+      continue;
+    }
+    if (next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
+    // repeated visit from the current e: MG(rc, e) = e + MG(rc - K e, 0)
+    VecSet rr{crs.rr, crs.N}, dd{crs.d, crs.N};
+    {
+      ProfScope ps(c, lvl_name("level_residual", l + 1), Bp * 24.0 * Nc1 + 8.0 * Nc1);
+      launch_level_residual(c->s, dim, B, rc, ec, level_K(c, l + 1), rr, act);
+    }
+    mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, dd, true, act);
+    ProfScope ps(c, lvl_name("add", l + 1), Bp * 24.0 * Nc1);
+    launch_add(c->s, B, dd, ec, crs.N, act);
   }
   if (fused) {
     ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
@@ -530,7 +550,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
   if (opts) o = *opts;
   if (o.levels < 2 || o.levels > 12) return fail(nullptr, HELM_EINVAL, "levels must be in [2, 12]");
   if (o.restart < 1 || o.restart > krylov_max_restart()) return fail(nullptr, HELM_EINVAL, "restart must be in [1, 64]");
-  if (o.max_batch < 1 || o.nu1 < 0 || o.nu2 < 0 || o.cycle < 1 || o.cycle > 2 || o.max_iters < 1 || !(o.rtol > 0))
+  if (o.max_batch < 1 || o.nu1 < 0 || o.nu2 < 0 || o.cycle < 1 || o.cycle > 3 || o.max_iters < 1 || !(o.rtol > 0))
     return fail(nullptr, HELM_EINVAL, "bad solver options");
   helm_abl a{0.15, 1, 0};
   if (abl) a = *abl;
@@ -580,6 +600,10 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
         L.rc = c->alloc<c32>((size_t)maxB * L.N);
         L.e = c->alloc<c32>((size_t)maxB * L.N);
         L.t = c->alloc<c32>((size_t)maxB * L.N);
+        if (o.cycle >= 2) {
+          L.rr = c->alloc<c32>((size_t)maxB * L.N);
+          L.d = c->alloc<c32>((size_t)maxB * L.N);
+        }
       }
     }
     c->Nc = (int)c->lv[c->L - 1].N;

@@ -266,6 +266,30 @@ __global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, int n, long 
   vb[p] = cadd(vb[p], acc);
 }
 
+// out = b - K v on a level (the right-hand side of a repeated coarse visit:
+// MG(b, v) = v + MG(b - K v, 0) for the affine multigrid cycle)
+__global__ void k_level_residual(int dim, VecSet bvec, VecSet v, LevelArgs lv, VecSet out, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= lv.N) return;
+  const Coord c = coord_of32((unsigned)p, (unsigned)lv.n, dim);
+  const c32* vb = v.p + (long long)b * v.stride;
+  const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
+  const c32 kv = csub(cmul(D, vb[p]), neighbour_sum(vb, p, c, lv.n, dim));
+  out.p[(long long)b * out.stride + p] = csub(bvec.p[(long long)b * bvec.stride + p], kv);
+}
+
+// y += x for every active right-hand side
+__global__ void k_add(VecSet x, VecSet y, long long N, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  c32* yb = y.p + (long long)b * y.stride;
+  yb[p] = cadd(yb[p], x.p[(long long)b * x.stride + p]);
+}
+
 // y = out_scale * (D x - sum of neighbours), D = 2d - coef - g #ghosts
 __global__ void k_apply(int dim, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                         const int* active) {
@@ -356,4 +380,13 @@ void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet 
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active) {
   hipLaunchKernelGGL(k_apply, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, x, xs, lv, out_scale, y, active);
+}
+
+void launch_level_residual(hipStream_t s, int dim, int B, VecSet bvec, VecSet v, LevelArgs lv, VecSet out,
+                           const int* active) {
+  hipLaunchKernelGGL(k_level_residual, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, bvec, v, lv, out, active);
+}
+
+void launch_add(hipStream_t s, int B, VecSet x, VecSet y, long long N, const int* active) {
+  hipLaunchKernelGGL(k_add, dim3(nblocks(N, 256), B), dim3(256), 0, s, x, y, N, active);
 }

@@ -49,6 +49,9 @@ void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet
 void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active);
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active);
+void launch_level_residual(hipStream_t s, int dim, int B, VecSet bvec, VecSet v, LevelArgs lv, VecSet out,
+                           const int* active);
+void launch_add(hipStream_t s, int B, VecSet x, VecSet y, long long N, const int* active);
 
 // ---- coarse levels of a V-cycle in one launch (one workgroup per right-hand side) ----
 struct CoarseLevel {

@@ -75,7 +75,7 @@ def test_adjoint_gradient_matches_oracle(inverse_case):
     loss.backward()
     g = n_t.grad.detach().cpu().numpy().astype(np.float64)
     ref_loss, ref_grad = model.loss_and_gradient(c["p_eval"], c["dirs"], c["data"], tau=1e-3, tv_eps=1e-4)
-    assert float(loss) == pytest.approx(ref_loss, rel=1e-4)
+    assert float(loss.detach()) == pytest.approx(ref_loss, rel=1e-4)
     assert np.linalg.norm(g - ref_grad) / np.linalg.norm(ref_grad) < 1e-3
 
 

@@ -92,20 +92,21 @@ def test_vcycle_fused_matches_oracle(pair):
     assert rel(z, ref) < 1e-5
 
 
-@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle", "per_level_launch"])
+@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle", "per_level_launch", "top_w", "generic_w"])
 def test_cycle_variants_match_oracle(variant):
     n, w, levels = CASES["ragged"]
     nmap = medium(n, seed=3)
     nu = 2 if variant == "generic_nu2" else 1
-    cyc = 2 if variant == "w_cycle" else 1
+    cyc = {"w_cycle": 2, "generic_w": 2, "top_w": 3}.get(variant, 1)
     print(f"\n[cycle variant {variant}]", flush=True)
     prob = oracle_problem(nmap, w=w, levels=levels, nu=nu)
     hier = Hierarchy(prob)
-    ctx = gpu_context(nmap, w=w, levels=levels, nu=nu, cycle=cyc, fused=0 if variant == "generic_v" else 1,
+    ctx = gpu_context(nmap, w=w, levels=levels, nu=nu, cycle=cyc, fused=0 if variant.startswith("generic") else 1,
                       coarse_single_launch=0 if variant == "per_level_launch" else 1, max_batch=2)
     r = fields(prob.shape, 2, 61)
     z = to_np(ctx.precondition(to_dev(r)))
-    ref = np.stack([hier.cycle(ri.ravel(), None, 0, cyc).reshape(prob.shape) for ri in r])
+    oracle_ct = [2] + [1] * (levels - 2) if cyc == 3 else cyc
+    ref = np.stack([hier.cycle(ri.ravel(), None, 0, oracle_ct).reshape(prob.shape) for ri in r])
     ctx.close()
     assert rel(z, ref) < 1e-5
 

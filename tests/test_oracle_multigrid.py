@@ -150,3 +150,31 @@ def test_coarsest_lu_residual():
     assert np.linalg.norm(hier.K[-1] @ x - b) < 1e-13 * np.linalg.norm(b)
     x2 = spla.spsolve(hier.K[-1].tocsc(), b)
     assert np.allclose(x, x2, atol=1e-12)
+
+
+def test_cycle_from_a_guess_is_guess_plus_zero_guess_cycle():
+    # every step of Alg. 2 is affine and consistent: MG(b, v0) = v0 + MG(b - K v0, 0)
+    prob = prob2d(n=12, w=4, levels=3)
+    hier = Hierarchy(prob)
+    b = synth.complex_field(prob.size, 12)
+    v0 = synth.complex_field(prob.size, 13)
+    for ct in (1, 2, [2, 1, 1]):
+        lhs = hier.cycle(b, v0.copy(), 0, ct)
+        rhs = v0 + hier.cycle(b - hier.K[0] @ v0, None, 0, ct)
+        assert np.allclose(lhs, rhs, atol=1e-12 * np.abs(lhs).max())
+
+
+def test_per_level_cycle_type_sits_between_v_and_w():
+    prob = prob2d(n=12, w=4, levels=4)
+    hier = Hierarchy(prob)
+    calls = []
+    lu = hier.coarse_lu
+
+    class Counting:
+        def solve(self, b):
+            calls.append(1)
+            return lu.solve(b)
+
+    hier.coarse_lu = Counting()
+    hier.cycle(synth.complex_field(prob.size, 7), None, 0, [2, 1, 1])
+    assert len(calls) == 2
