@@ -1,0 +1,154 @@
+"""FP64 reference of the learned preconditioner network (forward and backward).
+
+Not part of the paper (its method uses multigrid only); this is the
+reference the BF16-MFMA kernels are checked against.  Parity with the paper
+is unpinned for this part; its pins are finite differences and closed-form
+special cases.
+
+Network (2D U-Net, 4 levels, channels 16/32/64/64, 3x3 convolutions,
+zero padding, ReLU after every convolution but the last):
+    e0 = relu(conv(x, A0))                        4 -> 16   level 0
+    e1 = relu(conv(pool(e0), A1))                16 -> 32   level 1
+    e2 = relu(conv(pool(e1), A2))                32 -> 64   level 2
+    e3 = relu(conv(pool(e2), A3))                64 -> 64   level 3
+    d2 = relu(conv(cat(up(e3), e2), B2))        128 -> 64
+    d1 = relu(conv(cat(up(d2), e1), B1))         96 -> 32
+    d0 = relu(conv(cat(up(d1), e0), B0))         48 -> 16
+    y  = conv(d0, O)                             16 -> 2
+pool: 2x2 sum / 4 with zero padding (output ceil(H/2)); up: nearest
+neighbour back to the skip's size; cat: channel concatenation (up first).
+Arrays are [image][y][x][channel]; weights [3][3][cin][cout] (tap (dy+1, dx+1)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CH = (16, 32, 64, 64)
+LAYERS = [  # name, cin, cout, relu
+    ("A0", 4, 16, True), ("A1", 16, 32, True), ("A2", 32, 64, True), ("A3", 64, 64, True),
+    ("B2", 128, 64, True), ("B1", 96, 32, True), ("B0", 48, 16, True), ("O", 16, 2, False),
+]
+
+
+def init_params(seed: int = 0, dtype=np.float64) -> dict:
+    """He-normal weights, zero biases (the same recipe the library uses given the same numbers)."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, cin, cout, _ in LAYERS:
+        std = np.sqrt(2.0 / (9 * cin))
+        p[name + ".w"] = (rng.standard_normal((3, 3, cin, cout)) * std).astype(dtype)
+        p[name + ".b"] = np.zeros(cout, dtype=dtype)
+    return p
+
+
+def conv3x3(x, w, b):
+    """out[i, y, x, o] = b[o] + sum_{dy, dx, c} x[i, y+dy, x+dx, c] w[dy+1, dx+1, c, o] (zero padding)."""
+    n, h, wd, _ = x.shape
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    out = np.zeros((n, h, wd, w.shape[3]), dtype=np.result_type(x, w))
+    for ky in range(3):
+        for kx in range(3):
+            out += xp[:, ky:ky + h, kx:kx + wd, :] @ w[ky, kx]
+    return out + b
+
+
+def conv3x3_backward(x, w, g):
+    """Gradients of sum(g * conv3x3(x, w, b)) with respect to x, w and b."""
+    n, h, wd, _ = x.shape
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    gx_p = np.zeros_like(xp)
+    gw = np.zeros_like(w)
+    for ky in range(3):
+        for kx in range(3):
+            patch = xp[:, ky:ky + h, kx:kx + wd, :]
+            gw[ky, kx] = np.einsum("nyxc,nyxo->co", patch, g)
+            gx_p[:, ky:ky + h, kx:kx + wd, :] += g @ w[ky, kx].T
+    return gx_p[:, 1:h + 1, 1:wd + 1, :], gw, g.sum(axis=(0, 1, 2))
+
+
+def pool(x):
+    n, h, w, c = x.shape
+    hp, wp = (h + 1) // 2, (w + 1) // 2
+    xp = np.zeros((n, 2 * hp, 2 * wp, c), dtype=x.dtype)
+    xp[:, :h, :w] = x
+    return 0.25 * (xp[:, 0::2, 0::2] + xp[:, 1::2, 0::2] + xp[:, 0::2, 1::2] + xp[:, 1::2, 1::2])
+
+
+def pool_backward(g, shape):
+    n, h, w, c = shape
+    up = np.repeat(np.repeat(g, 2, axis=1), 2, axis=2)[:, :h, :w]
+    return 0.25 * up
+
+
+def upsample(x, shape):
+    """Nearest neighbour to spatial size shape[1:3]: out[y, x] = in[y // 2, x // 2]."""
+    h, w = shape[1], shape[2]
+    return np.repeat(np.repeat(x, 2, axis=1), 2, axis=2)[:, :h, :w]
+
+
+def upsample_backward(g, shape):
+    n, hc, wc, c = shape
+    h, w = g.shape[1], g.shape[2]
+    gp = np.zeros((n, 2 * hc, 2 * wc, c), dtype=g.dtype)
+    gp[:, :h, :w] = g
+    return gp[:, 0::2, 0::2] + gp[:, 1::2, 0::2] + gp[:, 0::2, 1::2] + gp[:, 1::2, 1::2]
+
+
+def forward(p: dict, x: np.ndarray):
+    """Returns the output and the activations the backward pass needs."""
+    t = {}
+
+    def layer(name, inp, relu):
+        z = conv3x3(inp, p[name + ".w"], p[name + ".b"])
+        t[name + ".in"] = inp
+        out = np.maximum(z, 0) if relu else z
+        t[name + ".out"] = out
+        return out
+
+    e0 = layer("A0", x, True)
+    e1 = layer("A1", pool(e0), True)
+    e2 = layer("A2", pool(e1), True)
+    e3 = layer("A3", pool(e2), True)
+    d2 = layer("B2", np.concatenate([upsample(e3, e2.shape), e2], axis=3), True)
+    d1 = layer("B1", np.concatenate([upsample(d2, e1.shape), e1], axis=3), True)
+    d0 = layer("B0", np.concatenate([upsample(d1, e0.shape), e0], axis=3), True)
+    y = layer("O", d0, False)
+    t.update(e0=e0, e1=e1, e2=e2, e3=e3, d2=d2, d1=d1, d0=d0)
+    return y, t
+
+
+def backward(p: dict, t: dict, gy: np.ndarray) -> dict:
+    """Gradients of sum(gy * y) with respect to every parameter."""
+    grads = {}
+
+    def layer_back(name, gout, relu):
+        if relu:
+            gout = gout * (t[name + ".out"] > 0)
+        gin, gw, gb = conv3x3_backward(t[name + ".in"], p[name + ".w"], gout)
+        grads[name + ".w"], grads[name + ".b"] = gw, gb
+        return gin
+
+    c = CH
+    g_d0 = layer_back("O", gy, False)
+    g_cat0 = layer_back("B0", g_d0, True)
+    g_d1 = upsample_backward(g_cat0[..., :c[1]], t["d1"].shape)
+    g_e0 = g_cat0[..., c[1]:].copy()
+    g_cat1 = layer_back("B1", g_d1, True)
+    g_d2 = upsample_backward(g_cat1[..., :c[2]], t["d2"].shape)
+    g_e1 = g_cat1[..., c[2]:].copy()
+    g_cat2 = layer_back("B2", g_d2, True)
+    g_e3 = upsample_backward(g_cat2[..., :c[3]], t["e3"].shape)
+    g_e2 = g_cat2[..., c[3]:].copy()
+    g_e2 += pool_backward(layer_back("A3", g_e3, True), t["e2"].shape)
+    g_e1 += pool_backward(layer_back("A2", g_e2, True), t["e1"].shape)
+    g_e0 += pool_backward(layer_back("A1", g_e1, True), t["e0"].shape)
+    layer_back("A0", g_e0, True)
+    return grads
+
+
+def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray):
+    """L = 1/2 sum (y - target)^2 / n_images and its parameter gradients."""
+    y, t = forward(p, x)
+    r = (y - target) / x.shape[0]
+    loss = 0.5 * float(np.sum((y - target) ** 2)) / x.shape[0]
+    return loss, backward(p, t, r), y
