@@ -109,6 +109,7 @@ typedef struct {
   int iters;            /* preconditioner applications */
   int status;           /* HELM_STATUS_* */
   double rel_res_true;  /* ||b - A x|| / ||b|| of the returned x (float-float evaluation) */
+  int fallbacks;        /* learned-preconditioner outputs rejected for the V-cycle (0 without a network) */
 } helm_stats;
 
 typedef struct {
@@ -118,6 +119,7 @@ typedef struct {
 } helm_info;
 
 typedef struct helm_ctx helm_ctx;
+typedef struct helm_net helm_net;
 
 /* Defaults of helm_opts (see the field comments). */
 void helm_default_opts(helm_opts* opts);
@@ -224,6 +226,58 @@ int helm_coarse_solve(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
 /* z = M^-1 r: one multigrid cycle from a zero initial guess for the
  * h^2-scaled fine system K'_0 z = r (the FGMRES preconditioner). */
 int helm_precondition(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
+
+/* ---- learned preconditioner (not part of the paper's method) ----
+ * A 2D convolutional U-Net used as the FGMRES preconditioner in place of the
+ * V-cycle: 4 levels with 16/32/64/64 channels, 3x3 convolutions (zero
+ * padding), ReLU after every convolution but the last, 2x2 average pooling
+ * (zero padding, output ceil(n/2)), nearest-neighbour upsampling and skip
+ * concatenation; layers A0..A3 (encoder), B2, B1, B0 (decoder), O (output).
+ * BF16 weights and activations with FP32 accumulation on the matrix cores,
+ * FP32 master weights and Adam.  Inputs: 4 channels (Re, Im of the
+ * normalised residual, Re, Im of the coefficient contrast (c - c_b) / c_b);
+ * outputs: 2 channels (Re, Im of the normalised correction).
+ * Tensors are FP32 NHWC [nimg][H][W][channels] device arrays. */
+
+int helm_net_layers(void);                                 /* 8 */
+int helm_net_layer_shape(int layer, int* cin, int* cout);  /* real channel counts */
+/* He-normal initial weights from `seed`, zero biases; work runs on hip_stream. */
+int helm_net_create(unsigned long long seed, void* hip_stream, helm_net** out);
+void helm_net_destroy(helm_net* net);
+const char* helm_net_last_error(const helm_net* net);
+/* Weights as host float[3][3][cin][cout] (tap (dy+1, dx+1)) and bias float[cout]. */
+int helm_net_set_layer(helm_net* net, int layer, const float* w_host, const float* b_host);
+int helm_net_get_layer(helm_net* net, int layer, float* w_host, float* b_host);
+/* Gradient of the last helm_net_backward, same layout. */
+int helm_net_get_grad(helm_net* net, int layer, float* dw_host, float* db_host);
+/* y = network(x): x [nimg][H][W][4], y [nimg][H][W][2]. */
+int helm_net_forward(helm_net* net, int nimg, int H, int W, const float* x_dev, float* y_dev);
+/* Loss 1/2 sum (y - target)^2 / nimg and its parameter gradients. */
+int helm_net_backward(helm_net* net, int nimg, int H, int W, const float* x_dev, const float* target_dev,
+                      double* loss_host);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the gradients of the last backward. */
+int helm_net_adam_step(helm_net* net, double lr);
+
+/* Use `net` (NULL: multigrid only) as the preconditioner of ctx: for basis
+ * vector v_j (unit norm) the network sees sqrt(N) v_j and its output, times
+ * gamma / sqrt(N), is z_j; right-hand sides with ||v_j - A' z_j|| > accept_tol
+ * fall back to the multigrid cycle for that step (FGMRES allows a different
+ * preconditioner per step).  The context keeps the pointer (not owned). */
+int helm_set_preconditioner(helm_ctx* ctx, helm_net* net, double accept_tol, double gamma);
+
+/* helm_solve_batch that also copies the iterate x_hi after every
+ * `every_cycles` restart cycles into snaps_dev[k] (device [max_snaps][B][grid]);
+ * *n_snaps = snapshots taken.  Used to build training pairs from the method's
+ * own solves: the error of snapshot k is x_final - x_k, its residual b - A x_k. */
+int helm_solve_snapshots(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats_host,
+                         int every_cycles, int max_snaps, helm_c32* snaps_dev, int* n_snaps);
+
+/* Training examples from (residual r = b - A x_k, x_final, x_k) fields [B][grid]:
+ * crop i = (rhs, y0, x0) from crops_host[3 i ..], S x S points; features
+ * feat [ncrop][S][S][4] = (h^2 r / rms_crop(h^2 r), contrast), targets
+ * tgt [ncrop][S][S][2] = (x_final - x_k) / rms_crop(h^2 r) / gamma. */
+int helm_net_examples(helm_ctx* ctx, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,
+                      const int* crops_host, int S, double gamma, float* feat_dev, float* tgt_dev);
 
 /* ---- per-launch profiler (measurement support) ----
  * While enabled, every kernel launch of the context is bracketed by HIP events

@@ -14,6 +14,7 @@
 
 #include "../../include/helm.h"
 #include "kernels.h"
+#include "net_internal.h"
 #include "setup_host.h"
 
 using helm_host::cd;
@@ -79,6 +80,7 @@ struct helm_ctx {
   c32* d_T0 = nullptr;   // generic-path scratch on the fine level
   c32* d_tables = nullptr;
   int* d_ones = nullptr;
+  int* d_zero_ints = nullptr;
   float* d_tv_mag = nullptr;   // [n^dim] TV magnitudes
   float* d_tv_part = nullptr;  // per-block TV partial sums
   int* h_status = nullptr;  // pinned
@@ -89,6 +91,14 @@ struct helm_ctx {
 
   hipGraphExec_t graph = nullptr;
   int graph_B = 0;
+
+  // learned preconditioner (NULL: multigrid only)
+  helm_net* net = nullptr;
+  double accept_tol = 0.9;
+  double net_gamma = 1.0;
+  int* d_mg_mask = nullptr;    // [maxB] RHS whose learned output was rejected
+  int* d_fallbacks = nullptr;  // [maxB] rejections during the current solve
+  int* h_fallbacks = nullptr;  // pinned
 
   // opt-in per-launch profiler (HIP events on the context stream, no graph replay while on)
   struct ProfEntry {
@@ -298,8 +308,24 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
   VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
   VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
   ScaleSet sj{k.vs + j, k.m + 1};
-  mg_cycle(c, B, 0, vj, sj, zj, true, k.active);
   const LevelArgs A = fine_A(c);
+  if (c->net) {
+    // z_j = network(v_j); RHS whose output fails ||v_j - A z_j|| <= tol ||v_j|| fall back to the V-cycle
+    const double rootN = std::sqrt((double)N0);
+    const c32 cb = make_float2((float)(c->kbh * c->kbh), 0.0f);
+    {
+      ProfScope ps(c, "net_apply", 0.0);
+      net_apply(c->net, c->s, B, c->ne, vj.p, vj.stride, sj.p, sj.stride, (float)rootN, c->d_chi, cb,
+                (float)(c->net_gamma / rootN), zj.p, zj.stride, k.active);
+    }
+    {
+      ProfScope ps(c, "accept", c->prof_B * 24.0 * N0);
+      launch_accept(c->s, B, k, j, A, c->accept_tol, c->d_mg_mask, c->d_fallbacks);
+    }
+    mg_cycle(c, B, 0, vj, sj, zj, true, c->d_mg_mask);
+  } else {
+    mg_cycle(c, B, 0, vj, sj, zj, true, k.active);
+  }
   const double Bp = c->prof_B, N = (double)N0, nv = j + 1.0;
   const double red_bytes = Bp * k.nblk * nv * 8.0;
   {
@@ -357,7 +383,8 @@ int fail(helm_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
-int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats, int conj) {
+int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats, int conj, int snap_every = 0,
+              int max_snaps = 0, helm_c32* snaps = nullptr, int* n_snaps = nullptr) {
   if (!c) return fail(nullptr, HELM_EINVAL, "null context");
   if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
   if (!rhs || !x) return fail(c, HELM_EINVAL, "null field pointer");
@@ -366,6 +393,7 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     check(hipStreamSynchronize(c->user_s), "caller stream");
     check(hipMemcpyAsync(c->d_rhs, rhs, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy rhs");
     launch_status_init(c->s, B, c->k);
+    check(hipMemcpyAsync(c->d_fallbacks, c->d_zero_ints, B * sizeof(int), hipMemcpyDeviceToDevice, c->s), "reset");
     launch_zero(c->s, (long long)B * N0, c->d_xhi);
     launch_zero(c->s, (long long)B * N0, c->d_xlo);
     c->prof_B = B;
@@ -397,6 +425,12 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
       check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
       int running = 0;
       for (int b = 0; b < B; ++b) running += c->h_status[b] == HELM_RUNNING;
+      if (snaps && running && (cyc + 1) % snap_every == 0 && *n_snaps < max_snaps) {
+        check(hipMemcpyAsync(snaps + (size_t)(*n_snaps) * B * N0, c->d_xhi, (size_t)B * N0 * sizeof(c32),
+                             hipMemcpyDeviceToDevice, c->s),
+              "snapshot");
+        ++*n_snaps;
+      }
       if (c->prof_on) prof_resolve(c);
       c->prof_B = running;
       if (!running) break;
@@ -408,6 +442,7 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     check(hipMemcpyAsync(c->h_status, c->k.status, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "status");
     check(hipMemcpyAsync(c->h_iters, c->k.iters, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "iters");
     check(hipMemcpyAsync(c->h_relres, c->k.relres, B * sizeof(double), hipMemcpyDeviceToHost, c->s), "relres");
+    check(hipMemcpyAsync(c->h_fallbacks, c->d_fallbacks, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "fallbacks");
     check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
     check(hipGetLastError(), "kernel launch");
   } catch (const HipError& e) {
@@ -422,6 +457,7 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
       stats[b].iters = c->h_iters[b];
       stats[b].status = st;
       stats[b].rel_res_true = c->h_relres[b];
+      stats[b].fallbacks = c->net ? c->h_fallbacks[b] : 0;
     }
   }
   return rc;
@@ -493,6 +529,7 @@ void free_ctx(helm_ctx* c) {
   if (c->h_status) hipHostFree(c->h_status);
   if (c->h_iters) hipHostFree(c->h_iters);
   if (c->h_relres) hipHostFree(c->h_relres);
+  if (c->h_fallbacks) hipHostFree(c->h_fallbacks);
   if (c->s) hipStreamDestroy(c->s);
   delete c;
 }
@@ -618,6 +655,9 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     c->d_T0 = c->alloc<c32>((size_t)maxB * N0);
     c->d_tables = c->alloc<c32>((size_t)maxB * c->dim * ne);
     c->d_ones = c->alloc<int>(maxB);
+    c->d_zero_ints = c->alloc<int>(maxB);
+    c->d_mg_mask = c->alloc<int>(maxB);
+    c->d_fallbacks = c->alloc<int>(maxB);
     c->d_tv_mag = c->alloc<float>(npts(c->n, c->dim));
     c->d_tv_part = c->alloc<float>(tv_partials(c->dim, c->n));
     KrylovArgs& k = c->k;
@@ -650,8 +690,10 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     check(hipHostMalloc((void**)&c->h_status, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     check(hipHostMalloc((void**)&c->h_iters, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     check(hipHostMalloc((void**)&c->h_relres, maxB * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
-    std::vector<int> ones(maxB, 1);
+    std::vector<int> ones(maxB, 1), zeros(maxB, 0);
     check(hipMemcpy(c->d_ones, ones.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload ones");
+    check(hipMemcpy(c->d_zero_ints, zeros.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload zeros");
+    check(hipHostMalloc((void**)&c->h_fallbacks, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     upload_medium(c, n_map_dev);
     check(hipDeviceSynchronize(), "setup");
   } catch (const HipError& e) {
@@ -723,6 +765,60 @@ int helm_plane_wave_rhs(helm_ctx* c, int B, const double* dirs, helm_c32* rhs, h
 
 int helm_solve_batch(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats) {
   return run_solve(c, B, rhs, x, stats, 0);
+}
+
+int helm_solve_snapshots(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* stats, int every_cycles,
+                         int max_snaps, helm_c32* snaps, int* n_snaps) {
+  if (!n_snaps || !snaps || every_cycles < 1 || max_snaps < 1) return fail(c, HELM_EINVAL, "bad snapshot arguments");
+  *n_snaps = 0;
+  return run_solve(c, B, rhs, x, stats, 0, every_cycles, max_snaps, snaps, n_snaps);
+}
+
+int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, double gamma) {
+  if (!c) return HELM_EINVAL;
+  if (net && c->dim != 2) return fail(c, HELM_EINVAL, "the learned preconditioner is two-dimensional");
+  try {
+    check(hipStreamSynchronize(c->s), "sync");
+    if (net) net_reserve(net, c->o.max_batch, c->ne);
+    if (c->graph) {
+      hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+      c->graph_B = 0;
+    }
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  } catch (...) {
+    return fail(c, HELM_ENOMEM, "could not reserve the network buffers");
+  }
+  c->net = net;
+  c->accept_tol = accept_tol;
+  c->net_gamma = gamma;
+  return HELM_OK;
+}
+
+int helm_net_examples(helm_ctx* c, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,
+                      const int* crops_host, int S, double gamma, float* feat, float* tgt) {
+  if (!c || !r || !x_final || !x_k || !crops_host || !feat || !tgt || ncrop < 1 || S < 1 || S > c->ne)
+    return fail(c, HELM_EINVAL, "bad argument");
+  for (int i = 0; i < ncrop; ++i) {
+    const int b = crops_host[3 * i], y0 = crops_host[3 * i + 1], x0 = crops_host[3 * i + 2];
+    if (b < 0 || b >= B || y0 < 0 || x0 < 0 || y0 + S > c->ne || x0 + S > c->ne)
+      return fail(c, HELM_EINVAL, "crop outside the grid");
+  }
+  struct DevFree {
+    void* p = nullptr;
+    ~DevFree() {
+      if (p) hipFree(p);
+    }
+  } crops_mem;
+  HELM_GUARD_BEGIN
+  check(hipMalloc(&crops_mem.p, (size_t)ncrop * 3 * sizeof(int)), "hipMalloc");
+  int* d_crops = (int*)crops_mem.p;
+  check(hipMemcpyAsync(d_crops, crops_host, (size_t)ncrop * 3 * sizeof(int), hipMemcpyHostToDevice, c->s), "crops");
+  launch_examples(c->s, ncrop, S, c->ne, d_crops, (const c32*)r, (const c32*)x_final, (const c32*)x_k, c->N0,
+                  c->d_chi, make_float2((float)(c->kbh * c->kbh), 0.0f), (float)(c->h * c->h), (float)(1.0 / gamma),
+                  feat, tgt);
+  HELM_GUARD_END("net_examples")
 }
 
 int helm_adjoint_batch(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* lam, helm_stats* stats) {

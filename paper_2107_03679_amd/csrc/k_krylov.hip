@@ -336,6 +336,57 @@ __global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
   }
 }
 
+// Acceptance test of a learned preconditioner output z_j: partial sums of
+// |v_j - A' z_j|^2 (v_j = vs_j V_j has unit norm).
+__global__ __launch_bounds__(NT) void k_accept_partials(KrylovArgs k, int j, LevelArgs fine) {
+  __shared__ float red[NWAVE];
+  const int b = blockIdx.x, blk = blockIdx.y;
+  if (!k.active[b]) return;
+  const long long p0 = (long long)blk * CH + threadIdx.x;
+  const c32* z = k.Z + zidx(k, b, j);
+  const c32* v = k.V + vidx(k, b, j);
+  const float vsj = k.vs[b * (k.m + 1) + j];
+  Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p < k.N) {
+      const c32 D = diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim);
+      const c32 d = csub(cscale(v[p], vsj), stencil_point(z, p, c, fine.n, k.dim, D));
+      s = fmaf(d.x, d.x, fmaf(d.y, d.y, s));
+    }
+    coord_advance(c, NT, fine.n, k.dim);
+  }
+  s = wave_sum(s);
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) t += red[q];
+    k.P2[(long long)b * k.nblk + blk] = t;
+  }
+}
+
+// mg_mask[b] = 1 where the learned output is rejected (||v - A z|| > tol or not finite)
+__global__ __launch_bounds__(HELM_WAVE) void k_accept_decide(KrylovArgs k, double tol, int* mg_mask, int* fallbacks) {
+  const int b = blockIdx.x;
+  if (!k.active[b]) {
+    if (threadIdx.x == 0) mg_mask[b] = 0;
+    return;
+  }
+  double s = 0.0;
+  for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) s += k.P2[(long long)b * k.nblk + blk];
+  s = wave_sum_d(s);
+  if (threadIdx.x != 0) return;
+  const double ratio = sqrt(s);
+  const int reject = !(ratio <= tol);
+  mg_mask[b] = reject;
+  fallbacks[b] += reject;
+}
+
 // After a true residual: decide convergence, else restart the cycle from r.
 __global__ __launch_bounds__(HELM_WAVE) void k_finalize(KrylovArgs k, int first) {
   const int b = blockIdx.x;
@@ -417,6 +468,11 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
 }
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);
+}
+void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
+                   int* fallbacks) {
+  hipLaunchKernelGGL(k_accept_partials, dim3(B, k.nblk), dim3(NT), 0, s, k, j, fine);
+  hipLaunchKernelGGL(k_accept_decide, dim3(B), dim3(HELM_WAVE), 0, s, k, tol, mg_mask, fallbacks);
 }
 void launch_status_init(hipStream_t s, int B, const KrylovArgs& k) {
   hipLaunchKernelGGL(k_status_init, dim3((B + 63) / 64), dim3(64), 0, s, k, B);

@@ -112,6 +112,8 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
                         const c32* c_lo, c32 ghost_hi, c32 ghost_lo, float h2_hi, float h2_lo, c32* r_out,
                         long long r_stride, float out_scale);
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
+void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
+                   int* fallbacks);
 
 // ---- model kernels ----
 void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane, const c32* tables, c32* rhs,

@@ -1,0 +1,61 @@
+// Learned-preconditioner network: kernel argument types and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+typedef __bf16 bf16;
+
+struct ConvArgs {
+  const bf16* in;  // NHWC input
+  int in_ct, in_off, cin;  // channel stride, offset, channels (multiple of 8)
+  int nimg, H, W;
+  const bf16* wt;  // [cout_pad][kpad] packed weights
+  int kpad;
+  const float* bias;  // [cout] or NULL
+  int cout;           // channels written (<= 16 * NCO)
+  int relu;
+  bf16* out;     // NHWC output (bf16) ...
+  float* out32;  // ... or FP32 output when non-NULL
+  int out_ct, out_off;
+};
+
+struct WgradArgs {
+  const bf16* in;  // layer input
+  int in_ct, in_off, cin;
+  int nimg, H, W;
+  const bf16* g;  // masked output gradient [P][g_ct]
+  int g_ct;
+  int kpad, cout_pad;
+  int chunk;    // pixels per block (multiple of 128)
+  float* part;  // [nchunk][cout_pad][kpad]
+};
+
+void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco);
+void launch_wgrad(hipStream_t s, const WgradArgs& a, int nchunk, float* dw, const bf16* g_for_bias, float* db,
+                  int cout_real);
+void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int g_off, const bf16* act, int act_ct,
+                      int act_off, int creal, int cpad, bf16* gm);
+void launch_pool(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, int in_off, bf16* out,
+                 int out_ct, int out_off);
+void launch_pool_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
+                      int gin_off);
+void launch_upsample(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, bf16* out, int out_ct,
+                     int out_off);
+void launch_upsample_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, int g_off,
+                          float* gc);
+int loss_partials(long long n);
+void launch_loss(hipStream_t s, long long n, const float* y, const float* tgt, float inv_nimg, float* gy, float* part);
+void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
+                 float lr, float b1, float b2, float eps, float c1, float c2);
+void launch_pack(hipStream_t s, int cout_pad, int cin, int kpad, int cob, int kbpad, const float* w, bf16* wt,
+                 bf16* wb);
+void launch_net_input(hipStream_t s, int B, long long N, const c32* v, long long v_stride, const float* vscale,
+                      int vs_stride, float gain, const c32* coef, c32 cb, bf16* x, int x_ct);
+void launch_net_output(hipStream_t s, int B, long long N, const float* y, float gain, c32* z, long long z_stride,
+                       const int* mask);
+void launch_to_bf16_pad(hipStream_t s, long long P, int cin, const float* x, int cpad, bf16* out);
+void launch_examples(hipStream_t s, int ncrop, int S, int n_e, const int* crops, const c32* r, const c32* xfin,
+                     const c32* xk, long long N, const c32* coef, c32 cb, float r_scale, float inv_gamma,
+                     float* feat, float* tgt);

@@ -1,0 +1,25 @@
+// Network internals shared by net.cpp and the solver (capi.cpp).
+#pragma once
+
+#include "net.h"
+
+#define HELM_NET_LAYERS 8
+
+struct NetLayer {
+  int cin, cout, relu;
+  int cin_pad, cout_pad, kpad;  // forward implicit GEMM
+  int cob, kbpad;               // backward-data implicit GEMM (input channels, K)
+  float *w, *b, *dw, *db, *mw, *vw, *mb, *vb;
+  unsigned char* mask;  // 1 for real (non-padding) weights
+  bf16 *wt, *wb;
+};
+
+struct helm_net;
+
+// Preconditioner application on B solver-grid images (n x n, 2D): features from
+// the basis vectors v (scaled by vscale and in_gain) and the coefficient
+// contrast, z = out_gain * network output for the right-hand sides in `mask`.
+void net_reserve(helm_net* n, int B, int ngrid);
+void net_apply(helm_net* n, hipStream_t s, int B, int ngrid, const c32* v, long long v_stride, const float* vscale,
+               int vs_stride, float in_gain, const c32* coef, c32 cb, float out_gain, c32* z, long long z_stride,
+               const int* mask);

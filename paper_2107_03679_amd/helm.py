@@ -42,7 +42,8 @@ class HelmOpts(ctypes.Structure):
 
 
 class HelmStats(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("fallbacks", ctypes.c_int)]
 
 
 class HelmInfo(ctypes.Structure):
@@ -60,6 +61,9 @@ EXPORTS = [
     "helm_residual", "helm_apply_K", "helm_restrict", "helm_prolong_add", "helm_coarse_solve",
     "helm_precondition", "helm_solution_lo", "helm_sample", "helm_sample_adjoint", "helm_tv", "helm_profile_enable", "helm_profile_reset", "helm_profile_count",
     "helm_profile_get", "helm_last_error", "helm_destroy",
+    "helm_net_layers", "helm_net_layer_shape", "helm_net_create", "helm_net_destroy", "helm_net_last_error",
+    "helm_net_set_layer", "helm_net_get_layer", "helm_net_get_grad", "helm_net_forward", "helm_net_backward",
+    "helm_net_adam_step", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
 ]
 
 _lib = None
@@ -101,12 +105,28 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_profile_count.argtypes = [vp]
     lib.helm_profile_get.argtypes = [vp, i, ctypes.c_char_p, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.POINTER(d)]
+    lib.helm_net_layer_shape.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.helm_net_create.argtypes = [ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+    lib.helm_net_destroy.argtypes = [vp]
+    lib.helm_net_destroy.restype = None
+    lib.helm_net_last_error.argtypes = [vp]
+    lib.helm_net_last_error.restype = ctypes.c_char_p
+    lib.helm_net_set_layer.argtypes = [vp, i, vp, vp]
+    lib.helm_net_get_layer.argtypes = [vp, i, vp, vp]
+    lib.helm_net_get_grad.argtypes = [vp, i, vp, vp]
+    lib.helm_net_forward.argtypes = [vp, i, i, i, vp, vp]
+    lib.helm_net_backward.argtypes = [vp, i, i, i, vp, vp, ctypes.POINTER(d)]
+    lib.helm_net_adam_step.argtypes = [vp, d]
+    lib.helm_set_preconditioner.argtypes = [vp, vp, d, d]
+    lib.helm_solve_snapshots.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats), i, i, vp, ctypes.POINTER(i)]
+    lib.helm_net_examples.argtypes = [vp, i, vp, vp, vp, i, vp, i, d, vp, vp]
     lib.helm_last_error.argtypes = [vp]
     lib.helm_last_error.restype = ctypes.c_char_p
     lib.helm_destroy.argtypes = [vp]
     lib.helm_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("helm_default_opts", "helm_last_error", "helm_destroy"):
+        if name not in ("helm_default_opts", "helm_last_error", "helm_destroy", "helm_net_destroy",
+                        "helm_net_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -131,6 +151,7 @@ class SolveStats:
     iters: np.ndarray
     status: np.ndarray
     rel_res_true: np.ndarray
+    fallbacks: np.ndarray | None = None
 
     @property
     def converged(self) -> bool:
@@ -203,7 +224,7 @@ class Context:
     @staticmethod
     def _stats(st) -> SolveStats:
         return SolveStats(np.array([s.iters for s in st]), np.array([s.status for s in st]),
-                          np.array([s.rel_res_true for s in st]))
+                          np.array([s.rel_res_true for s in st]), np.array([s.fallbacks for s in st]))
 
     # -- entry points --------------------------------------------------------
     def update_n(self, n_map: torch.Tensor):
@@ -301,6 +322,36 @@ class Context:
         self._check(self.lib.helm_precondition(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_precondition")
         return z
 
+    def set_preconditioner(self, net: "Net | None", accept_tol: float = 0.9, gamma: float = 1.0):
+        """Use a learned network (None: multigrid) as the FGMRES preconditioner, with V-cycle fallback."""
+        self._net = net  # keep the network alive while the context uses it
+        self._check(self.lib.helm_set_preconditioner(self._h, net._h if net is not None else None, accept_tol, gamma),
+                    "helm_set_preconditioner")
+
+    def solve_snapshots(self, rhs: torch.Tensor, every_cycles: int, max_snaps: int):
+        """Solve and keep the iterate after every `every_cycles` restart cycles: (x, stats, snaps[k])."""
+        B = rhs.shape[0]
+        x = self.empty_fields(B)
+        snaps = torch.empty((max_snaps, B, *self.grid_shape()), dtype=torch.complex64, device=self.device)
+        st = (HelmStats * B)()
+        ns = ctypes.c_int()
+        rc = self.lib.helm_solve_snapshots(self._h, B, _ptr(rhs), _ptr(x), st, every_cycles, max_snaps, _ptr(snaps),
+                                           ctypes.byref(ns))
+        self._check(rc, "helm_solve_snapshots", soft_ok=True)
+        return x, self._stats(st), snaps[: ns.value]
+
+    def net_examples(self, r: torch.Tensor, x_final: torch.Tensor, x_k: torch.Tensor, crops: np.ndarray, size: int,
+                     gamma: float):
+        """Training examples (features [n][S][S][4], targets [n][S][S][2]) from solver snapshots."""
+        crops = np.ascontiguousarray(np.asarray(crops, dtype=np.int32).reshape(-1, 3))
+        n = crops.shape[0]
+        feat = torch.empty((n, size, size, 4), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((n, size, size, 2), dtype=torch.float32, device=self.device)
+        rc = self.lib.helm_net_examples(self._h, r.shape[0], _ptr(r), _ptr(x_final), _ptr(x_k), n,
+                                        crops.ctypes.data_as(ctypes.c_void_p), size, gamma, _ptr(feat), _ptr(tgt))
+        self._check(rc, "helm_net_examples")
+        return feat, tgt
+
     def profile(self, on: bool = True, reset: bool = True):
         """Enable/disable per-launch HIP-event timing of every kernel of this context."""
         if reset:
@@ -333,3 +384,79 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Net:
+    """The learned-preconditioner U-Net (helm_net_*): BF16 MFMA kernels, FP32 master weights."""
+
+    def __init__(self, seed: int = 0, stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.helm_net_create(seed, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != HELM_OK:
+            raise HelmError(f"helm_net_create failed ({rc})")
+        self._h = h
+        self.shapes = []
+        for i in range(self.lib.helm_net_layers()):
+            ci, co = ctypes.c_int(), ctypes.c_int()
+            self.lib.helm_net_layer_shape(i, ctypes.byref(ci), ctypes.byref(co))
+            self.shapes.append((ci.value, co.value))
+
+    NAMES = ("A0", "A1", "A2", "A3", "B2", "B1", "B0", "O")
+
+    def _check(self, rc, what):
+        if rc != HELM_OK:
+            raise HelmError(f"{what} failed ({rc}): {self.lib.helm_net_last_error(self._h).decode()}")
+
+    def set_params(self, params: dict):
+        """params: {name + '.w': [3][3][cin][cout], name + '.b': [cout]} (any float dtype)."""
+        for i, name in enumerate(self.NAMES):
+            w = np.ascontiguousarray(params[name + ".w"], dtype=np.float32)
+            b = np.ascontiguousarray(params[name + ".b"], dtype=np.float32)
+            self._check(self.lib.helm_net_set_layer(self._h, i, w.ctypes.data_as(ctypes.c_void_p),
+                                                    b.ctypes.data_as(ctypes.c_void_p)), "helm_net_set_layer")
+
+    def _get(self, fn):
+        out = {}
+        for i, name in enumerate(self.NAMES):
+            ci, co = self.shapes[i]
+            w = np.zeros((3, 3, ci, co), dtype=np.float32)
+            b = np.zeros(co, dtype=np.float32)
+            self._check(fn(self._h, i, w.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p)),
+                        "helm_net_get")
+            out[name + ".w"], out[name + ".b"] = w, b
+        return out
+
+    def params(self) -> dict:
+        return self._get(self.lib.helm_net_get_layer)
+
+    def grads(self) -> dict:
+        return self._get(self.lib.helm_net_get_grad)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        n, h, w, _ = x.shape
+        y = torch.empty((n, h, w, 2), dtype=torch.float32, device=x.device)
+        self._check(self.lib.helm_net_forward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(y)), "helm_net_forward")
+        return y
+
+    def backward(self, x: torch.Tensor, target: torch.Tensor) -> float:
+        n, h, w, _ = x.shape
+        loss = ctypes.c_double()
+        self._check(self.lib.helm_net_backward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(target.contiguous()),
+                                               ctypes.byref(loss)), "helm_net_backward")
+        return loss.value
+
+    def adam_step(self, lr: float):
+        self._check(self.lib.helm_net_adam_step(self._h, lr), "helm_net_adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.helm_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
