@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
+    p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
     return p.parse_args()
 
 
@@ -82,6 +85,75 @@ def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
         "sample": (f"FP64 oracle MG-FGMRES({restart}) on 1 of the RHS (theta=0), {info.iters} iterations in "
                    f"{el:.1f} s on 1 host thread, scaled by {iters_per_solve:.0f} iterations per solve "
                    f"(the GPU's mean at the same parameters); set-up excluded"),
+    }
+
+
+def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
+    """Learned-FGMRES on the same workload: the network is trained on the GPU on residual/error
+    pairs from MG-FGMRES solves of training media (blob seeds 1000 + i, random angles), then
+    used as z = net(v) + V(v - A net(v)) with the acceptance test and V-cycle fallback."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2107_03679_amd import learned
+
+    dev = torch.device("cuda:0")
+    kind, kw = wl["medium"]
+    B = dirs.shape[0]
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    sets = []
+    for i in range(args.learned_media + 1):  # the last medium only validates
+        m = synth.blob_map(wl["n"], kw["n_blobs"], kw["sigma_range"], kw["amp_hi"], 1000 + i,
+                           max_dn=kw.get("max_dn"))
+        ctx.update_n(torch.tensor(m, dtype=torch.float32, device=dev))
+        th = np.radians(rng.uniform(-60.0, 60.0, B))
+        rhs = ctx.plane_wave_rhs(np.stack([np.sin(th), np.cos(th)], 1))
+        val_medium = i == args.learned_media
+        sets.append(learned.collect(ctx, [rhs], size=128, crops_per_snapshot=1 if val_medium else 4,
+                                    every_cycles=8, max_snaps=12, seed=1000 + i,
+                                    out=None if (val_medium or not sets) else sets.pop()))
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device=dev))
+    tr, val = sets
+    val = learned.Examples(val.feat, val.tgt * val.gamma / tr.gamma, tr.gamma, tr.cb)
+    net = learned.new_network(11)
+    log = learned.train(net, tr, steps=args.learned_steps, batch=16, lr=1e-4, seed=3, err_weight=0.0,
+                        res_weight=1.0)
+    ratio = learned.residual_ratio(ctx, net, val)
+    ctx.set_preconditioner(net, accept_tol=1.0, gamma=tr.gamma, mode="then_mg")
+    x = ctx.empty_fields(B)
+    # profiled warm-up solve: the network's MFMA rate
+    ctx.profile(True)
+    ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+    rep = ctx.profile_report()
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_preconditioner(None)
+    ne = ctx.info.n_e
+    net_ms, net_launches, _ = rep.get("net_apply", (0.0, 0, 0.0))
+    fl = learned.flops_per_image(ne, ne) * B
+    achieved = fl * net_launches / (net_ms * 1e-3) / 1e12 if net_ms > 0 else 0.0
+    net.close()
+    value = B / el
+    return {
+        "value": value, "unit": "solves/s", "vs_multigrid": value / mg_value,
+        "iters_mean": float(st.iters.mean()), "iters_max": int(st.iters.max()),
+        "iters_vs_multigrid": float(st.iters.mean()) / mg_iters_mean,
+        "all_converged": bool(st.converged), "rel_res_true_max": float(st.rel_res_true.max()),
+        "accepted_frac": float(1.0 - st.fallbacks.sum() / max(1, st.iters.sum())),
+        "pairs": int(tr.feat.shape[0]), "crop": 128, "train_steps": log.steps, "train_s": log.seconds,
+        "collect_s": t_collect, "heldout_residual_ratio": ratio, "training_media": args.learned_media,
+        "mode": "z = net(v) + V-cycle(v - A net(v)), V-cycle alone where ||v - A net(v)|| > ||v||",
+        "mfma": {"kernel": "net_apply (all convolutions of one application)", "achieved": achieved,
+                 "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "flops_per_launch": fl,
+                 "ms_per_launch": net_ms / max(1, net_launches)},
     }
 
 
@@ -132,7 +204,8 @@ def main():
     value = B * args.steps / el
 
     out = {
-        "metric": "Helmholtz solves/s at rel. residual 1e-6 (512^2, 60 RHS)" if args.workload == "blobs512x60"
+        "metric": "Helmholtz solves/s at rel. residual 1e-6 (512\u00b2, 60 RHS); learned vs MG-GMRES"
+        if args.workload == "blobs512x60"
         else f"Helmholtz solves/s at rel. residual 1e-6 ({args.workload})",
         "value": value,
         "unit": "solves/s",
@@ -176,6 +249,8 @@ def main():
             k: {"ms": round(v[0], 3), "launches": v[1], "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0}
             for k, v in sorted(rep.items(), key=lambda kv: -kv[1][0])
         }
+    if not args.no_learned and wl["d"] == 2:
+        out["learned"] = learned_leg(ctx, args, wl, nmap, dirs, float(iters.mean()), value)
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nmap, args.levels, args.restart, args.cycle, float(iters.mean()),

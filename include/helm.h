@@ -255,15 +255,33 @@ int helm_net_forward(helm_net* net, int nimg, int H, int W, const float* x_dev, 
 /* Loss 1/2 sum (y - target)^2 / nimg and its parameter gradients. */
 int helm_net_backward(helm_net* net, int nimg, int H, int W, const float* x_dev, const float* target_dev,
                       double* loss_host);
+/* Training loss of helm_net_backward, per image:
+ *   err_weight / 2 sum (y - target)^2
+ * + res_weight / 2 sum over the image interior |r - gamma A' y|^2,
+ * with r = x[..0] + j x[..1], y read as complex, and A' the scaled 5-point
+ * operator (4 - c) y - (sum of the 4 neighbours), c = cb (1 + x[..2] + j x[..3])
+ * (the coefficient the features encode; cb = (k_b h)^2).  The one-pixel border
+ * of every image is left out of the residual term.  Defaults: 1, 0.
+ * Errors: HELM_EINVAL for negative weights or gamma, cb <= 0. */
+int helm_net_set_loss(helm_net* net, double err_weight, double res_weight, double gamma, double cb);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the gradients of the last backward. */
 int helm_net_adam_step(helm_net* net, double lr);
 
-/* Use `net` (NULL: multigrid only) as the preconditioner of ctx: for basis
+/* Learned preconditioner modes. */
+#define HELM_NET_REPLACE 0 /* z_j = net(v_j); multigrid cycle where rejected */
+#define HELM_NET_THEN_MG 1 /* z_j = net(v_j) + MG(v_j - A' net(v_j)); net term dropped where rejected */
+
+/* Use `net` (NULL: multigrid only) in the preconditioner of ctx.  For basis
  * vector v_j (unit norm) the network sees sqrt(N) v_j and its output, times
- * gamma / sqrt(N), is z_j; right-hand sides with ||v_j - A' z_j|| > accept_tol
- * fall back to the multigrid cycle for that step (FGMRES allows a different
- * preconditioner per step).  The context keeps the pointer (not owned). */
-int helm_set_preconditioner(helm_ctx* ctx, helm_net* net, double accept_tol, double gamma);
+ * gamma / sqrt(N), is z_net.  A right-hand side whose ||v_j - A' z_net|| >
+ * accept_tol (or is not finite) drops the network output for that step and
+ * uses the multigrid cycle alone (FGMRES allows a different preconditioner per
+ * step; the per-RHS count is helm_stats.fallbacks).  HELM_NET_THEN_MG follows
+ * the network with a multigrid cycle of its residual and needs two extra
+ * [max_batch][N] work vectors, allocated here on first use.  The context
+ * keeps the pointer (not owned).  Errors: HELM_EINVAL for a 3D context, an
+ * unknown mode or gamma <= 0. */
+int helm_set_preconditioner(helm_ctx* ctx, helm_net* net, double accept_tol, double gamma, int mode);
 
 /* helm_solve_batch that also copies the iterate x_hi after every
  * `every_cycles` restart cycles into snaps_dev[k] (device [max_snaps][B][grid]);
@@ -274,8 +292,10 @@ int helm_solve_snapshots(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x,
 
 /* Training examples from (residual r = b - A x_k, x_final, x_k) fields [B][grid]:
  * crop i = (rhs, y0, x0) from crops_host[3 i ..], S x S points; features
- * feat [ncrop][S][S][4] = (h^2 r / rms_crop(h^2 r), contrast), targets
- * tgt [ncrop][S][S][2] = (x_final - x_k) / rms_crop(h^2 r) / gamma. */
+ * feat [ncrop][S][S][4] = (h^2 r / rms, Re and Im of (c - c_b) / c_b), targets
+ * tgt [ncrop][S][S][2] = (x_final - x_k) / rms / gamma, where rms is the root
+ * mean square of h^2 r over the whole grid of that right-hand side (the scale
+ * the solver gives the network: sqrt(N) times a unit-norm vector). */
 int helm_net_examples(helm_ctx* ctx, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,
                       const int* crops_host, int S, double gamma, float* feat_dev, float* tgt_dev);
 

@@ -146,9 +146,46 @@ def backward(p: dict, t: dict, gy: np.ndarray) -> dict:
     return grads
 
 
-def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray):
-    """L = 1/2 sum (y - target)^2 / n_images and its parameter gradients."""
+def scaled_operator(y: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """A' y = (4 - c) y - (sum of the 4 neighbours) per image, neighbours outside the image = 0."""
+    out = (4.0 - c) * y
+    out[:, 1:, :] -= y[:, :-1, :]
+    out[:, :-1, :] -= y[:, 1:, :]
+    out[:, :, 1:] -= y[:, :, :-1]
+    out[:, :, :-1] -= y[:, :, 1:]
+    return out
+
+
+def residual_term(x: np.ndarray, y: np.ndarray, gamma: float, cb: float):
+    """1/2 sum over image interiors of |r - gamma A' y|^2 and its gradient w.r.t. y (real pairs).
+
+    r = x[..., 0] + j x[..., 1]; c = cb (1 + x[..., 2] + j x[..., 3]); the
+    one-pixel border of each image is left out.  For a real function of a
+    complex vector the gradient (d/dRe + j d/dIm) of 1/2 |q|^2, q = r - gamma A' y,
+    is -gamma A'^H q; A' is complex symmetric, so A'^H is A' with c conjugated.
+    """
+    r = x[..., 0] + 1j * x[..., 1]
+    c = cb * (1.0 + x[..., 2] + 1j * x[..., 3])
+    yc = y[..., 0] + 1j * y[..., 1]
+    q = r - gamma * scaled_operator(yc, c)
+    mask = np.zeros(q.shape, dtype=bool)
+    mask[:, 1:-1, 1:-1] = True
+    q = np.where(mask, q, 0.0)
+    loss = 0.5 * float(np.sum(np.abs(q) ** 2))
+    g = -gamma * scaled_operator(q, np.conj(c))
+    return loss, np.stack([g.real, g.imag], axis=-1)
+
+
+def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray, err_w: float = 1.0, res_w: float = 0.0,
+                   gamma: float = 1.0, cb: float = 1.0):
+    """L = (err_w/2 sum (y - target)^2 + res_w/2 sum_interior |r - gamma A' y|^2) / n_images
+    and its parameter gradients."""
     y, t = forward(p, x)
-    r = (y - target) / x.shape[0]
-    loss = 0.5 * float(np.sum((y - target) ** 2)) / x.shape[0]
-    return loss, backward(p, t, r), y
+    nimg = x.shape[0]
+    gy = err_w * (y - target) / nimg
+    loss = err_w * 0.5 * float(np.sum((y - target) ** 2)) / nimg
+    if res_w:
+        lr, gr = residual_term(x, y, gamma, cb)
+        loss += res_w * lr / nimg
+        gy = gy + res_w * gr / nimg
+    return loss, backward(p, t, gy), y

@@ -96,6 +96,9 @@ struct helm_ctx {
   helm_net* net = nullptr;
   double accept_tol = 0.9;
   double net_gamma = 1.0;
+  int net_mode = HELM_NET_REPLACE;
+  c32* d_net_res = nullptr;    // [maxB][N0] v_j - A' z_net (HELM_NET_THEN_MG)
+  c32* d_net_cor = nullptr;    // [maxB][N0] multigrid correction of that residual
   int* d_mg_mask = nullptr;    // [maxB] RHS whose learned output was rejected
   int* d_fallbacks = nullptr;  // [maxB] rejections during the current solve
   int* h_fallbacks = nullptr;  // pinned
@@ -318,11 +321,24 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
       net_apply(c->net, c->s, B, c->ne, vj.p, vj.stride, sj.p, sj.stride, (float)rootN, c->d_chi, cb,
                 (float)(c->net_gamma / rootN), zj.p, zj.stride, k.active);
     }
-    {
-      ProfScope ps(c, "accept", c->prof_B * 24.0 * N0);
-      launch_accept(c->s, B, k, j, A, c->accept_tol, c->d_mg_mask, c->d_fallbacks);
+    if (c->net_mode == HELM_NET_REPLACE) {
+      {
+        ProfScope ps(c, "accept", c->prof_B * 16.0 * N0);
+        launch_accept(c->s, B, k, j, A, c->accept_tol, c->d_mg_mask, c->d_fallbacks, VecSet{nullptr, 0});
+      }
+      mg_cycle(c, B, 0, vj, sj, zj, true, c->d_mg_mask);
+    } else {
+      // z_j = z_net + MG(v_j - A' z_net), with z_net = 0 where the network output was rejected
+      const VecSet res{c->d_net_res, N0}, cor{c->d_net_cor, N0};
+      {
+        ProfScope ps(c, "accept", c->prof_B * 24.0 * N0);
+        launch_accept(c->s, B, k, j, A, c->accept_tol, c->d_mg_mask, c->d_fallbacks, res);
+      }
+      launch_reject_reset(c->s, B, k, j, c->d_mg_mask, res);
+      mg_cycle(c, B, 0, res, ScaleSet{nullptr, 0}, cor, true, k.active);
+      ProfScope ps(c, "add", c->prof_B * 24.0 * N0);
+      launch_add(c->s, B, cor, zj, N0, k.active);
     }
-    mg_cycle(c, B, 0, vj, sj, zj, true, c->d_mg_mask);
   } else {
     mg_cycle(c, B, 0, vj, sj, zj, true, k.active);
   }
@@ -774,12 +790,18 @@ int helm_solve_snapshots(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, h
   return run_solve(c, B, rhs, x, stats, 0, every_cycles, max_snaps, snaps, n_snaps);
 }
 
-int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, double gamma) {
+int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, double gamma, int mode) {
   if (!c) return HELM_EINVAL;
   if (net && c->dim != 2) return fail(c, HELM_EINVAL, "the learned preconditioner is two-dimensional");
+  if (mode != HELM_NET_REPLACE && mode != HELM_NET_THEN_MG) return fail(c, HELM_EINVAL, "unknown mode");
+  if (!(gamma > 0.0)) return fail(c, HELM_EINVAL, "gamma must be positive");
   try {
     check(hipStreamSynchronize(c->s), "sync");
     if (net) net_reserve(net, c->o.max_batch, c->ne);
+    if (net && mode == HELM_NET_THEN_MG && !c->d_net_res) {
+      c->d_net_res = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
+      c->d_net_cor = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
+    }
     if (c->graph) {
       hipGraphExecDestroy(c->graph);
       c->graph = nullptr;
@@ -793,6 +815,7 @@ int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, doubl
   c->net = net;
   c->accept_tol = accept_tol;
   c->net_gamma = gamma;
+  c->net_mode = mode;
   return HELM_OK;
 }
 
@@ -812,10 +835,12 @@ int helm_net_examples(helm_ctx* c, int B, const helm_c32* r, const helm_c32* x_f
     }
   } crops_mem;
   HELM_GUARD_BEGIN
-  check(hipMalloc(&crops_mem.p, (size_t)ncrop * 3 * sizeof(int)), "hipMalloc");
+  const size_t crop_bytes = ((size_t)ncrop * 3 * sizeof(int) + 255) / 256 * 256;
+  check(hipMalloc(&crops_mem.p, crop_bytes + (size_t)B * sizeof(float)), "hipMalloc");
   int* d_crops = (int*)crops_mem.p;
+  float* d_ss = (float*)((char*)crops_mem.p + crop_bytes);
   check(hipMemcpyAsync(d_crops, crops_host, (size_t)ncrop * 3 * sizeof(int), hipMemcpyHostToDevice, c->s), "crops");
-  launch_examples(c->s, ncrop, S, c->ne, d_crops, (const c32*)r, (const c32*)x_final, (const c32*)x_k, c->N0,
+  launch_examples(c->s, B, ncrop, S, c->ne, d_crops, d_ss, (const c32*)r, (const c32*)x_final, (const c32*)x_k, c->N0,
                   c->d_chi, make_float2((float)(c->kbh * c->kbh), 0.0f), (float)(c->h * c->h), (float)(1.0 / gamma),
                   feat, tgt);
   HELM_GUARD_END("net_examples")

@@ -337,8 +337,9 @@ __global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
 }
 
 // Acceptance test of a learned preconditioner output z_j: partial sums of
-// |v_j - A' z_j|^2 (v_j = vs_j V_j has unit norm).
-__global__ __launch_bounds__(NT) void k_accept_partials(KrylovArgs k, int j, LevelArgs fine) {
+// |v_j - A' z_j|^2 (v_j = vs_j V_j has unit norm); the residual itself is
+// stored in resid[b] when resid is non-null.
+__global__ __launch_bounds__(NT) void k_accept_partials(KrylovArgs k, int j, LevelArgs fine, VecSet resid) {
   __shared__ float red[NWAVE];
   const int b = blockIdx.x, blk = blockIdx.y;
   if (!k.active[b]) return;
@@ -354,6 +355,7 @@ __global__ __launch_bounds__(NT) void k_accept_partials(KrylovArgs k, int j, Lev
     if (p < k.N) {
       const c32 D = diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim);
       const c32 d = csub(cscale(v[p], vsj), stencil_point(z, p, c, fine.n, k.dim, D));
+      if (resid.p) resid.p[(long long)b * resid.stride + p] = d;
       s = fmaf(d.x, d.x, fmaf(d.y, d.y, s));
     }
     coord_advance(c, NT, fine.n, k.dim);
@@ -385,6 +387,19 @@ __global__ __launch_bounds__(HELM_WAVE) void k_accept_decide(KrylovArgs k, doubl
   const int reject = !(ratio <= tol);
   mg_mask[b] = reject;
   fallbacks[b] += reject;
+}
+
+// Where the learned output was rejected: z_j = 0 and resid = v_j, so that the
+// multigrid correction that follows is the plain cycle of v_j.
+__global__ void k_reject_reset(KrylovArgs k, int j, const int* mg_mask, VecSet resid) {
+  const int b = blockIdx.x;
+  if (!k.active[b] || !mg_mask[b]) return;
+  const float vsj = k.vs[b * (k.m + 1) + j];
+  for (long long p = (long long)blockIdx.y * blockDim.x + threadIdx.x; p < k.N;
+       p += (long long)gridDim.y * blockDim.x) {
+    k.Z[zidx(k, b, j) + p] = make_float2(0.f, 0.f);
+    resid.p[(long long)b * resid.stride + p] = cscale(k.V[vidx(k, b, j) + p], vsj);
+  }
 }
 
 // After a true residual: decide convergence, else restart the cycle from r.
@@ -470,9 +485,13 @@ void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);
 }
 void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
-                   int* fallbacks) {
-  hipLaunchKernelGGL(k_accept_partials, dim3(B, k.nblk), dim3(NT), 0, s, k, j, fine);
+                   int* fallbacks, VecSet resid) {
+  hipLaunchKernelGGL(k_accept_partials, dim3(B, k.nblk), dim3(NT), 0, s, k, j, fine, resid);
   hipLaunchKernelGGL(k_accept_decide, dim3(B), dim3(HELM_WAVE), 0, s, k, tol, mg_mask, fallbacks);
+}
+void launch_reject_reset(hipStream_t s, int B, const KrylovArgs& k, int j, const int* mg_mask, VecSet resid) {
+  const long long nb = (k.N + 255) / 256;
+  hipLaunchKernelGGL(k_reject_reset, dim3(B, (unsigned)(nb < 65535 ? nb : 65535)), dim3(256), 0, s, k, j, mg_mask, resid);
 }
 void launch_status_init(hipStream_t s, int B, const KrylovArgs& k) {
   hipLaunchKernelGGL(k_status_init, dim3((B + 63) / 64), dim3(64), 0, s, k, B);

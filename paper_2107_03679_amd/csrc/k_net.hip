@@ -256,6 +256,62 @@ __global__ void k_loss(long long n, const float* y, const float* tgt, float inv_
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Residual term of the training loss.  With r = (x0 + j x1), c = cb (1 + x2 + j x3)
+// taken from the FP32 network input x [P][4] and the output y [P][2] read as
+// complex, q = r - gamma A' y on the interior of every image (one-pixel
+// border excluded: the crop's neighbours outside it are unknown), where
+// A' y = (4 - c) y - (sum of the 4 neighbours).  part[block] = w/2 sum |q|^2.
+__global__ void k_res_q(int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb, float w,
+                        float2* q, float* part) {
+  __shared__ float red[256];
+  const long long P = (long long)nimg * H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float s = 0.f;
+  if (p < P) {
+    const int px = (int)(p % W), py = (int)((p / W) % H);
+    float2 qq = make_float2(0.f, 0.f);
+    if (px > 0 && px < W - 1 && py > 0 && py < H - 1) {
+      const float* xp = x + p * 4;
+      const c32 f = make_float2(xp[2], xp[3]);
+      const c32 c = cmul(cb, make_float2(1.f + f.x, f.y));
+      const c32 yc = make_float2(y[p * 2], y[p * 2 + 1]);
+      const c32 nbs = make_float2(y[(p - 1) * 2] + y[(p + 1) * 2] + y[(p - W) * 2] + y[(p + W) * 2],
+                                  y[(p - 1) * 2 + 1] + y[(p + 1) * 2 + 1] + y[(p - W) * 2 + 1] + y[(p + W) * 2 + 1]);
+      const c32 ay = csub(cmul(make_float2(4.f - c.x, -c.y), yc), nbs);
+      qq = make_float2(xp[0] - gamma * ay.x, xp[1] - gamma * ay.y);
+      s = 0.5f * w * (qq.x * qq.x + qq.y * qq.y);
+    }
+    q[p] = qq;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int t = 128; t > 0; t >>= 1) {
+    if (threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// gy += -w gamma A'^H q, A'^H q = (4 - conj c) q - (sum of the neighbours of q); q is zero
+// on the border, and neighbours outside the image count as zero.
+__global__ void k_res_grad(int nimg, int H, int W, const float* x, const float2* q, float gamma, c32 cb, float w,
+                           float* gy) {
+  const long long P = (long long)nimg * H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int px = (int)(p % W), py = (int)((p / W) % H);
+  const float* xp = x + p * 4;
+  const c32 c = cmul(cb, make_float2(1.f + xp[2], xp[3]));
+  float2 nbs = make_float2(0.f, 0.f);
+  if (px > 0) nbs = cadd(nbs, q[p - 1]);
+  if (px < W - 1) nbs = cadd(nbs, q[p + 1]);
+  if (py > 0) nbs = cadd(nbs, q[p - W]);
+  if (py < H - 1) nbs = cadd(nbs, q[p + W]);
+  const c32 g = csub(cmul(make_float2(4.f - c.x, c.y), q[p]), nbs);
+  gy[p * 2] -= w * gamma * g.x;
+  gy[p * 2 + 1] -= w * gamma * g.y;
+}
+
 // Adam on the FP32 master weights (entries with mask 0 -- the padding -- stay 0)
 __global__ void k_adam(int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask, float lr,
                        float b1, float b2, float eps, float c1, float c2) {
@@ -331,18 +387,15 @@ __global__ void k_to_bf16_pad(long long P, int cin, const float* x, int cpad, bf
 // Training examples from solver snapshots: crop c = (rhs b, y0, x0) of size S x S;
 // r' = r_scale * r (the scaled residual), e = x_final - x_k; features are r' / rms_crop(r')
 // and the coefficient contrast, targets e / rms_crop(r') / gamma.
-__global__ __launch_bounds__(256) void k_examples(int S, int n_e, const int* crops, const c32* r, const c32* xfin,
-                                                  const c32* xk, long long N, const c32* coef, c32 cb, float r_scale,
-                                                  float inv_gamma, float* feat, float* tgt) {
+// ss[b] = sum over the grid of |r_scale r[b]|^2 (one block per right-hand side, fixed order)
+__global__ __launch_bounds__(256) void k_field_sumsq(long long N, const c32* r, float r_scale, float* ss) {
   __shared__ float red[256];
-  const int c = blockIdx.x;
-  const int b = crops[3 * c], y0 = crops[3 * c + 1], x0 = crops[3 * c + 2];
-  const long long base = (long long)b * N;
+  const int b = blockIdx.x;
+  const c32* rb = r + (long long)b * N;
   float s = 0.f;
-  for (int t = threadIdx.x; t < S * S; t += 256) {
-    const long long p = (long long)(y0 + t / S) * n_e + (x0 + t % S);
-    const c32 v = cscale(r[base + p], r_scale);
-    s += v.x * v.x + v.y * v.y;
+  for (long long p = threadIdx.x; p < N; p += 256) {
+    const c32 v = cscale(rb[p], r_scale);
+    s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -350,7 +403,18 @@ __global__ __launch_bounds__(256) void k_examples(int S, int n_e, const int* cro
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const float rms = sqrtf(red[0] / (float)(S * S));
+  if (threadIdx.x == 0) ss[b] = red[0];
+}
+
+// One block per crop: features (r_scale r / rms, contrast) and target (x* - x_k) / rms / gamma,
+// with rms the root mean square of r_scale r[b] over the whole grid of its right-hand side.
+__global__ __launch_bounds__(256) void k_examples(int S, int n_e, const int* crops, const float* ss, const c32* r,
+                                                  const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb,
+                                                  float r_scale, float inv_gamma, float* feat, float* tgt) {
+  const int c = blockIdx.x;
+  const int b = crops[3 * c], y0 = crops[3 * c + 1], x0 = crops[3 * c + 2];
+  const long long base = (long long)b * N;
+  const float rms = sqrtf(ss[b] / (float)N);
   const float inv = rms > 0.f ? 1.f / rms : 0.f;
   const float invc = 1.f / (cb.x * cb.x + cb.y * cb.y);
   for (int t = threadIdx.x; t < S * S; t += 256) {
@@ -377,10 +441,11 @@ inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 void launch_to_bf16_pad(hipStream_t s, long long P, int cin, const float* x, int cpad, bf16* out) {
   hipLaunchKernelGGL(k_to_bf16_pad, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, cin, x, cpad, out);
 }
-void launch_examples(hipStream_t s, int ncrop, int S, int n_e, const int* crops, const c32* r, const c32* xfin,
-                     const c32* xk, long long N, const c32* coef, c32 cb, float r_scale, float inv_gamma,
-                     float* feat, float* tgt) {
-  hipLaunchKernelGGL(k_examples, dim3(ncrop), dim3(256), 0, s, S, n_e, crops, r, xfin, xk, N, coef, cb, r_scale,
+void launch_examples(hipStream_t s, int B, int ncrop, int S, int n_e, const int* crops, float* ss, const c32* r,
+                     const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb, float r_scale,
+                     float inv_gamma, float* feat, float* tgt) {
+  hipLaunchKernelGGL(k_field_sumsq, dim3(B), dim3(256), 0, s, N, r, r_scale, ss);
+  hipLaunchKernelGGL(k_examples, dim3(ncrop), dim3(256), 0, s, S, n_e, crops, ss, r, xfin, xk, N, coef, cb, r_scale,
                      inv_gamma, feat, tgt);
 }
 
@@ -437,6 +502,12 @@ int loss_partials(long long n) { return (int)nb(n, 256); }
 void launch_loss(hipStream_t s, long long n, const float* y, const float* tgt, float inv_nimg, float* gy,
                  float* part) {
   hipLaunchKernelGGL(k_loss, dim3(nb(n, 256)), dim3(256), 0, s, n, y, tgt, inv_nimg, gy, part);
+}
+void launch_res_loss(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
+                     float w, float2* q, float* part, float* gy) {
+  const long long P = (long long)nimg * H * W;
+  hipLaunchKernelGGL(k_res_q, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, y, gamma, cb, w, q, part);
+  hipLaunchKernelGGL(k_res_grad, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, q, gamma, cb, w, gy);
 }
 void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
                  float lr, float b1, float b2, float eps, float c1, float c2) {

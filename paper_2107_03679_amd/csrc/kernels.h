@@ -113,7 +113,8 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
                         long long r_stride, float out_scale);
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
 void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
-                   int* fallbacks);
+                   int* fallbacks, VecSet resid);
+void launch_reject_reset(hipStream_t s, int B, const KrylovArgs& k, int j, const int* mg_mask, VecSet resid);
 
 // ---- model kernels ----
 void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane, const c32* tables, c32* rhs,

@@ -62,6 +62,8 @@ struct NetBufs {
   std::vector<void*> bufs;
   bf16 *x0 = nullptr, *cat0 = nullptr, *p0 = nullptr, *cat1 = nullptr, *p1 = nullptr, *cat2 = nullptr,
        *p2 = nullptr, *e3 = nullptr, *d2 = nullptr, *d1 = nullptr, *d0 = nullptr, *gm = nullptr;
+  float2* q = nullptr;  // residual of the residual loss term
+  float* rpart = nullptr;
   float *y = nullptr, *gy = nullptr, *g_d0 = nullptr, *g_cat0 = nullptr, *g_d1 = nullptr, *g_cat1 = nullptr,
         *g_d2 = nullptr, *g_cat2 = nullptr, *g_e3 = nullptr, *g_p = nullptr, *part = nullptr, *lpart = nullptr;
   long long part_n = 0;
@@ -77,6 +79,8 @@ struct helm_net {
   std::vector<void*> allocs;
   std::string err;
   int step = 0;
+  // training loss: err_w / 2 sum (y - t)^2 + res_w / 2 sum |r - gamma A' y|^2, per image
+  double err_w = 1.0, res_w = 0.0, gamma = 1.0, cb = 0.0;
   NetBufs tb;              // buffers of the user calls (forward / backward)
   NetBufs sb;              // buffers of the solver's preconditioner applications
   NetBufs* cur = &tb;      // the set the kernels of the current call use
@@ -151,6 +155,8 @@ void ensure(helm_net* n, int nimg, int H0, int W0, bool train) {
     n->cur->part = n->alloc<float>(pn, B);
     n->cur->part_n = pn;
     n->cur->lpart = n->alloc<float>(loss_partials(P[0] * 2), B);
+    n->cur->q = n->alloc<float2>(P[0], B);
+    n->cur->rpart = n->alloc<float>(loss_partials(P[0]), B);
   }
   n->cur->capP0 = P0;
   n->cur->cap_nimg = nimg;
@@ -478,19 +484,36 @@ int helm_net_backward(helm_net* n, int nimg, int H, int W, const float* x, const
   launch_to_bf16_pad(n->s, n->cur->P[0], 4, x, 8, n->cur->x0);
   forward(n);
   const long long ny = n->cur->P[0] * 2;
-  launch_loss(n->s, ny, n->cur->y, target, 1.0f / nimg, n->cur->gy, n->cur->lpart);
+  launch_loss(n->s, ny, n->cur->y, target, (float)(n->err_w / nimg), n->cur->gy, n->cur->lpart);
+  const bool res = n->res_w > 0.0;
+  if (res)
+    launch_res_loss(n->s, nimg, H, W, x, n->cur->y, (float)n->gamma, make_float2((float)n->cb, 0.f),
+                    (float)(n->res_w / nimg), n->cur->q, n->cur->rpart, n->cur->gy);
   backward(n);
   ck(hipGetLastError(), "launch");
   if (loss) {
-    std::vector<float> part(loss_partials(ny));
+    std::vector<float> part(loss_partials(ny)), rpart(res ? loss_partials(n->cur->P[0]) : 0);
     ck(hipMemcpyAsync(part.data(), n->cur->lpart, part.size() * 4, hipMemcpyDeviceToHost, n->s), "loss");
+    if (res)
+      ck(hipMemcpyAsync(rpart.data(), n->cur->rpart, rpart.size() * 4, hipMemcpyDeviceToHost, n->s), "loss");
     ck(hipStreamSynchronize(n->s), "sync");
     double sum = 0.0;
     for (float v : part) sum += v;
+    for (float v : rpart) sum += v;
     *loss = sum;
   }
   ck(hipStreamSynchronize(n->s), "sync");
   NET_CATCH
+  return HELM_OK;
+}
+
+int helm_net_set_loss(helm_net* n, double err_weight, double res_weight, double gamma, double cb) {
+  if (!n || !(err_weight >= 0.0) || !(res_weight >= 0.0) || !(gamma > 0.0) || !(cb > 0.0))
+    return fail(n, HELM_EINVAL, "bad argument");
+  n->err_w = err_weight;
+  n->res_w = res_weight;
+  n->gamma = gamma;
+  n->cb = cb;
   return HELM_OK;
 }
 

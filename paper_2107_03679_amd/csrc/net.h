@@ -47,6 +47,10 @@ void launch_upsample_back(hipStream_t s, int nimg, int H, int W, int C, const fl
                           float* gc);
 int loss_partials(long long n);
 void launch_loss(hipStream_t s, long long n, const float* y, const float* tgt, float inv_nimg, float* gy, float* part);
+// residual loss term w/2 sum |r - gamma A' y|^2 over image interiors; adds its gradient to gy
+// (part: loss_partials(P) block sums)
+void launch_res_loss(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
+                     float w, float2* q, float* part, float* gy);
 void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
                  float lr, float b1, float b2, float eps, float c1, float c2);
 void launch_pack(hipStream_t s, int cout_pad, int cin, int kpad, int cob, int kbpad, const float* w, bf16* wt,
@@ -56,6 +60,6 @@ void launch_net_input(hipStream_t s, int B, long long N, const c32* v, long long
 void launch_net_output(hipStream_t s, int B, long long N, const float* y, float gain, c32* z, long long z_stride,
                        const int* mask);
 void launch_to_bf16_pad(hipStream_t s, long long P, int cin, const float* x, int cpad, bf16* out);
-void launch_examples(hipStream_t s, int ncrop, int S, int n_e, const int* crops, const c32* r, const c32* xfin,
-                     const c32* xk, long long N, const c32* coef, c32 cb, float r_scale, float inv_gamma,
-                     float* feat, float* tgt);
+void launch_examples(hipStream_t s, int B, int ncrop, int S, int n_e, const int* crops, float* ss, const c32* r,
+                     const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb, float r_scale,
+                     float inv_gamma, float* feat, float* tgt);

@@ -63,7 +63,7 @@ EXPORTS = [
     "helm_profile_get", "helm_last_error", "helm_destroy",
     "helm_net_layers", "helm_net_layer_shape", "helm_net_create", "helm_net_destroy", "helm_net_last_error",
     "helm_net_set_layer", "helm_net_get_layer", "helm_net_get_grad", "helm_net_forward", "helm_net_backward",
-    "helm_net_adam_step", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
+    "helm_net_adam_step", "helm_net_set_loss", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
 ]
 
 _lib = None
@@ -117,7 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_net_forward.argtypes = [vp, i, i, i, vp, vp]
     lib.helm_net_backward.argtypes = [vp, i, i, i, vp, vp, ctypes.POINTER(d)]
     lib.helm_net_adam_step.argtypes = [vp, d]
-    lib.helm_set_preconditioner.argtypes = [vp, vp, d, d]
+    lib.helm_net_set_loss.argtypes = [vp, d, d, d, d]
+    lib.helm_set_preconditioner.argtypes = [vp, vp, d, d, i]
     lib.helm_solve_snapshots.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats), i, i, vp, ctypes.POINTER(i)]
     lib.helm_net_examples.argtypes = [vp, i, vp, vp, vp, i, vp, i, d, vp, vp]
     lib.helm_last_error.argtypes = [vp]
@@ -322,11 +323,19 @@ class Context:
         self._check(self.lib.helm_precondition(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_precondition")
         return z
 
-    def set_preconditioner(self, net: "Net | None", accept_tol: float = 0.9, gamma: float = 1.0):
-        """Use a learned network (None: multigrid) as the FGMRES preconditioner, with V-cycle fallback."""
+    NET_MODES = {"replace": 0, "then_mg": 1}
+
+    def set_preconditioner(self, net: "Net | None", accept_tol: float = 0.9, gamma: float = 1.0,
+                           mode: str = "replace"):
+        """Use a learned network (None: multigrid only) in the FGMRES preconditioner.
+
+        mode "replace": z = net(v), the V-cycle where the output is rejected;
+        mode "then_mg": z = net(v) + V(v - A net(v)), the network term dropped where rejected.
+        """
         self._net = net  # keep the network alive while the context uses it
-        self._check(self.lib.helm_set_preconditioner(self._h, net._h if net is not None else None, accept_tol, gamma),
-                    "helm_set_preconditioner")
+        rc = self.lib.helm_set_preconditioner(self._h, net._h if net is not None else None, accept_tol, gamma,
+                                              self.NET_MODES[mode])
+        self._check(rc, "helm_set_preconditioner")
 
     def solve_snapshots(self, rhs: torch.Tensor, every_cycles: int, max_snaps: int):
         """Solve and keep the iterate after every `every_cycles` restart cycles: (x, stats, snaps[k])."""
@@ -446,6 +455,10 @@ class Net:
         self._check(self.lib.helm_net_backward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(target.contiguous()),
                                                ctypes.byref(loss)), "helm_net_backward")
         return loss.value
+
+    def set_loss(self, err_weight: float = 1.0, res_weight: float = 0.0, gamma: float = 1.0, cb: float = 1.0):
+        """Training loss weights: error term and residual term |r - gamma A' y|^2 (cb = (k_b h)^2)."""
+        self._check(self.lib.helm_net_set_loss(self._h, err_weight, res_weight, gamma, cb), "helm_net_set_loss")
 
     def adam_step(self, lr: float):
         self._check(self.lib.helm_net_adam_step(self._h, lr), "helm_net_adam_step")
