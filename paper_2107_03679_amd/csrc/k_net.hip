@@ -11,6 +11,8 @@
 //     A[i][k]: i = l % 16, k = 8 g + v (v = 0..7)      (16 pixels x 32 k)
 //     B[k][j]: j = l % 16, k = 8 g + v                 (32 k x 16 channels)
 //     D[i][j]: j = l % 16, i = 4 g + r (r = 0..3)
+// The forward / backward-data convolution passes the weights as A and the
+// activations as B, so that D is [output channel][pixel].
 #include <algorithm>
 
 #include "dev_common.h"
@@ -29,53 +31,203 @@ __device__ __forceinline__ bf16x8 zero8() {
   return z;
 }
 
-// ---------------------------------------------------------------- conv (MFMA)
-// One wavefront computes 16 consecutive pixels of one image row for all
-// output channels (NCO tiles of 16); four wavefronts per block.
-template <int NCO>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+// ---------------------------------------------------------------- layer inputs
+// 8 input channels [ci0, ci0 + 8) of pixel (img, y, x) of an H x W layer.
+// Address of 8 input channels [ci0, ci0 + 8) of pixel (img, y, x) for the convolution's
+// halo staging (MODE 0: plain, 2: upsample + skip), with (y, x) clamped into the image;
+// for MODE 1 (pool) the first of the 2 x 2 source pixels, clamped likewise.
+template <int MODE>
+__device__ __forceinline__ const bf16* src_addr(const NetSrc& s, long long img, int H, int W, int y, int x, int ci0) {
+  const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
+  if (MODE == 1) return s.in + ((img * s.Hs + 2 * yc) * s.Ws + 2 * xc) * s.in_ct + s.in_off + ci0;
+  if (MODE == 2 && ci0 < s.cup) {
+    const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+    return s.up + ((img * Hu + (yc >> 1)) * Wu + (xc >> 1)) * s.up_ct + ci0;
+  }
+  return s.in + ((img * H + yc) * W + xc) * s.in_ct + s.in_off + (ci0 - s.cup);
+}
+
+// one input channel ci of pixel (img, y, x) inside the image, the same value fetch8_clamped gives
+__device__ __forceinline__ float fetch1(const NetSrc& s, long long img, int H, int W, int y, int x, int ci) {
+  if (ci < s.cup) {
+    const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+    return (float)s.up[((img * Hu + (y >> 1)) * Wu + (x >> 1)) * s.up_ct + ci];
+  }
+  const int c = ci - s.cup;
+  if (!s.pool) return (float)s.in[((img * H + y) * W + x) * s.in_ct + s.in_off + c];
+  float acc = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int yy = 2 * y + a, xx = 2 * x + b;
+      if (yy < s.Hs && xx < s.Ws) acc += (float)s.in[((img * s.Hs + yy) * s.Ws + xx) * s.in_ct + s.in_off + c];
+    }
+  return (float)(bf16)(0.25f * acc);
+}
+
+// ---------------------------------------------------------------- conv, LDS-tiled (MFMA)
+// Block = TH x TW output pixels of one image, all output channels (NCO tiles of
+// 16).  The (TH + 2) x (TW + 2) input halo tile, all cin channels, is staged
+// once in LDS (pixel stride PS channels, padded so that the 16-byte reads of
+// 8 consecutive lanes hit distinct bank groups); the four wavefronts then
+// take MT = TH TW / 64 row segments of 16 pixels each and run the implicit
+// GEMM over k = tap * cin + ci with A from LDS and B (weights) from global
+// memory (small, cache resident).  Pixels outside the image read zeros.
+__device__ __forceinline__ int conv_pixel_stride(int cin) { return cin == 8 ? 8 : cin + 8; }
+
+template <int NCO, int TH, int TW, int MODE>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+  extern __shared__ __align__(16) bf16 tile[];
+  constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64;
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64, g = l / 16, i16 = l % 16;
-  const int xt = (a.W + 15) / 16;
-  const long long tile = (long long)blockIdx.x * 4 + wave;
-  const long long ntiles = (long long)a.nimg * a.H * xt;
-  if (tile >= ntiles) return;
-  const int x0 = (int)(tile % xt) * 16;
-  const long long rowid = tile / xt;  // image * H + y
-  const int y = (int)(rowid % a.H);
-  const long long img = rowid / a.H;
-  const int x = x0 + i16;
-  f32x4 acc[NCO];
+  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const long long img = blockIdx.z;
+  const int cin = a.cin, ps = conv_pixel_stride(cin), cg8 = cin / 8;
+  // stage the halo tile: (TH + 2)(TW + 2) pixels x cin / 8 chunks of 16 bytes; a batch of
+  // loads is in flight per thread before any is used (points outside the image store 0)
+  constexpr int BATCH = MODE == 1 ? 2 : 8, NSRC = MODE == 1 ? 4 : 1;
+  const int nchunk = (TH + 2) * TW2 * cg8;
+  for (int tb = 0; tb < nchunk; tb += 256 * BATCH) {
+    const int t0 = tb + threadIdx.x;
+    const int nslot = min(BATCH, (nchunk - tb + 255) / 256);  // uniform over the block
+    bf16x8 v[BATCH][NSRC];
 #pragma unroll
-  for (int t = 0; t < NCO; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < a.kpad; kc += 32) {
-    const int k0 = kc + 8 * g;
-    const int tap = k0 / a.cin, ci0 = k0 - tap * a.cin;
-    bf16x8 av = zero8();
-    if (tap < 9) {
-      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (x < a.W && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-        av = load8(a.in + ((img * a.H + yy) * a.W + xx) * a.in_ct + a.in_off + ci0);
+    for (int u = 0; u < BATCH; ++u) {
+      if (u < nslot) {
+        const int t = min(t0 + 256 * u, nchunk - 1);
+        const int q = t / cg8, cg = t - q * cg8;
+        const int r = q / TW2, c = q - r * TW2;
+        const bf16* p = src_addr<MODE>(a.src, img, a.H, a.W, y0 - 1 + r, x0 - 1 + c, cg * 8);
+        if (MODE == 1) {
+          // the 2 x 2 children, clamped into the source (weights applied below)
+          const int yc = min(max(y0 - 1 + r, 0), a.H - 1), xc = min(max(x0 - 1 + c, 0), a.W - 1);
+          const long long dx = (2 * xc + 1 < a.src.Ws) ? a.src.in_ct : 0;
+          const long long dy = (2 * yc + 1 < a.src.Hs) ? (long long)a.src.Ws * a.src.in_ct : 0;
+          v[u][0] = load8(p);
+          v[u][NSRC > 1 ? 1 : 0] = load8(p + dx);
+          v[u][NSRC > 2 ? 2 : 0] = load8(p + dy);
+          v[u][NSRC > 3 ? 3 : 0] = load8(p + dy + dx);
+        } else {
+          v[u][0] = load8(p);
+        }
+      }
     }
 #pragma unroll
-    for (int t = 0; t < NCO; ++t) {
-      const bf16x8 bv = load8(a.wt + (long long)(t * 16 + i16) * a.kpad + k0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+    for (int u = 0; u < BATCH; ++u) {
+      const int t = t0 + 256 * u;
+      if (u < nslot && t < nchunk) {
+        const int q = t / cg8, cg = t - q * cg8;
+        const int r = q / TW2, c = q - r * TW2;
+        const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+        const bool valid = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        bf16x8 o = zero8();
+        if (MODE == 1) {
+          // 2 x 2 average with zero padding: children past the source edge count 0
+          const bool hx = 2 * xx + 1 < a.src.Ws, hy = 2 * yy + 1 < a.src.Hs;
+          const float w1 = hx ? 1.f : 0.f, w2 = hy ? 1.f : 0.f, w3 = (hx && hy) ? 1.f : 0.f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float acc = (float)v[u][0][e];
+            acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
+            acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
+            acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
+            o[e] = (bf16)(0.25f * acc);
+          }
+        } else {
+          o = v[u][0];
+        }
+        *reinterpret_cast<bf16x8*>(tile + q * ps + cg * 8) = valid ? o : zero8();
+      }
     }
   }
+  __syncthreads();
+  f32x4 acc[MT][NCO];
 #pragma unroll
-  for (int t = 0; t < NCO; ++t) {
-    const int co = t * 16 + i16;
-    if (co >= a.cout) continue;
-    const float bias = a.bias ? a.bias[co] : 0.f;
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int xo = x0 + 4 * g + r;
-      if (xo >= a.W) continue;
-      float v = acc[t][r] + bias;
-      if (a.relu) v = fmaxf(v, 0.f);
-      const long long p = (img * a.H + y) * a.W + xo;
-      if (a.out32) a.out32[p * a.out_ct + a.out_off + co] = v;
-      else a.out[p * a.out_ct + a.out_off + co] = (bf16)v;
+    for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // LDS offset of this lane's pixel in segment m (tap (0, 0) = top-left of the 3 x 3 window)
+  int base[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int seg = wave * MT + m, r = seg / SEG, c = (seg - r * SEG) * 16 + i16;
+    base[m] = (r * TW2 + c) * ps;
+  }
+  // Two register sets, two k-steps per iteration: the operands of one step are read
+  // (A from LDS, B = weights from global memory) while the MFMAs of the other run.
+  // Steps past the last tap (k >= 9 cin, up to the even step count) read A = 0.
+  int tap = (8 * g) / cin, ci0 = 8 * g - tap * cin;  // k = 8 g at the first step
+  const int dtap = cin < 32 ? 32 / cin : 0, dci = cin < 32 ? 0 : 32;
+  const bf16* wrow = a.wt + (long long)i16 * a.kpad + 8 * g;
+  const long long wstride = 16LL * a.kpad;
+  auto read_step = [&](int kc, bf16x8* A, bf16x8* Bw) {
+    const int tc = min(tap, 8), dy = tc / 3, dx = tc - 3 * dy;
+    const int off = (dy * TW2 + dx) * ps + ci0;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
+      A[m] = tap < 9 ? v : zero8();
+    }
+    const int kw = min(kc, a.kpad - 32);
+#pragma unroll
+    for (int t = 0; t < NCO; ++t) Bw[t] = load8(wrow + t * wstride + kw);
+    // advance k by 32: cin < 32 divides 32 (whole taps), else at most one wrap
+    ci0 += dci;
+    const int wrap = ci0 >= cin;
+    ci0 -= wrap * cin;
+    tap += dtap + wrap;
+  };
+  auto mfma_step = [&](const bf16x8* A, const bf16x8* Bw) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[t], A[m], acc[m][t], 0, 0, 0);
+  };
+  bf16x8 a0[MT], b0[NCO], a1[MT], b1[NCO];
+  read_step(0, a0, b0);
+  for (int kc = 0; kc < a.kpad; kc += 64) {
+    read_step(kc + 32, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs that do not need them
+    mfma_step(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_step(kc + 64, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // epilogue: with the weights as the MFMA's first operand, acc[m][t][r] is output
+  // channel t * 16 + 4 g + r of pixel i16 of segment m, so each lane writes four
+  // consecutive channels of one pixel (8 bytes in BF16, 16 in FP32)
+  const int cout = a.cout;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int seg = wave * MT + m, r = seg / SEG;
+    const int y = y0 + r, xo = x0 + (seg - r * SEG) * 16 + i16;
+    if (y >= a.H || xo >= a.W) continue;
+    const long long p = (img * a.H + y) * a.W + xo;
+#pragma unroll
+    for (int t = 0; t < NCO; ++t) {
+      const int c0 = t * 16 + 4 * g;
+      if (c0 >= cout) continue;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float bias = (a.bias && c0 + q < cout) ? a.bias[c0 + q] : 0.f;
+        v[q] = acc[m][t][q] + bias;
+        if (a.relu) v[q] = fmaxf(v[q], 0.f);
+      }
+      if (a.out32) {
+        float* dst = a.out32 + p * a.out_ct + a.out_off + c0;
+        if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        else
+          for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
+      } else {
+        // BF16 outputs have a multiple of 8 channels
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
+        *reinterpret_cast<bf16x4*>(a.out + p * a.out_ct + a.out_off + c0) = o;
+      }
     }
   }
 }
@@ -108,8 +260,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         const long long r = p / a.W;
         const int py = (int)(r % a.H);
         const int yy = py + dy, xx = px + dx;
-        if (tap < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          xa = (float)a.in[(p + (long long)dy * a.W + dx) * a.in_ct + a.in_off + ci];
+        if (tap < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) xa = fetch1(a.src, r / a.H, a.H, a.W, yy, xx, ci);
         gb = (float)a.g[p * a.g_ct + co];
       }
       av[v] = (__bf16)xa;
@@ -165,27 +316,6 @@ __global__ void k_grad_prep(long long P, const float* g, int g_ct, int g_off, co
   gm[t] = (bf16)v;
 }
 
-// out[P'][off + c] = 1/4 sum of the 2x2 window of in (zero padding), C channels
-__global__ void k_pool(int nimg, int H, int W, int C, const bf16* in, int in_ct, int in_off, bf16* out, int out_ct,
-                       int out_off) {
-  const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nimg * Hc * Wc * C) return;
-  const int c = (int)(t % C);
-  const long long q = t / C;
-  const int X = (int)(q % Wc);
-  const long long r = q / Wc;
-  const int Y = (int)(r % Hc);
-  const long long img = r / Hc;
-  float s = 0.f;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int yy = 2 * Y + a, xx = 2 * X + b;
-      if (yy < H && xx < W) s += (float)in[((img * H + yy) * W + xx) * in_ct + in_off + c];
-    }
-  out[q * out_ct + out_off + c] = (bf16)(0.25f * s);
-}
-
 // gin[p][off + c] += 1/4 g[parent(p)][c]   (fp32)
 __global__ void k_pool_back(int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
                             int gin_off) {
@@ -200,21 +330,6 @@ __global__ void k_pool_back(int nimg, int H, int W, int C, const float* g, int g
   const long long img = r / H;
   const long long q = (img * Hc + y / 2) * Wc + x / 2;
   gin[p * gin_ct + gin_off + c] += 0.25f * g[q * g_ct + c];
-}
-
-// out[p][off + c] = in[parent(p)][c]   (nearest neighbour up to H x W)
-__global__ void k_upsample(int nimg, int H, int W, int C, const bf16* in, int in_ct, bf16* out, int out_ct,
-                           int out_off) {
-  const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nimg * H * W * C) return;
-  const int c = (int)(t % C);
-  const long long p = t / C;
-  const int x = (int)(p % W);
-  const long long r = p / W;
-  const int y = (int)(r % H);
-  const long long img = r / H;
-  out[p * out_ct + out_off + c] = in[((img * Hc + y / 2) * Wc + x / 2) * in_ct + c];
 }
 
 // gc[q][c] = sum over the children p of q of g[p][off + c]   (fp32)
@@ -449,16 +564,26 @@ void launch_examples(hipStream_t s, int B, int ncrop, int S, int n_e, const int*
                      inv_gamma, feat, tgt);
 }
 
+template <int NCO, int TH, int TW>
+void conv_lds(hipStream_t s, const ConvArgs& a) {
+  const size_t lds = (size_t)(TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
+  const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg);
+  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1>), grid, dim3(256), lds, s, a);
+  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2>), grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0>), grid, dim3(256), lds, s, a);
+}
+
+// Tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile
+// stays within 50 KB of LDS and the accumulators within 64 registers, else 4 x 32.
 void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco) {
-  const long long tiles = (long long)a.nimg * a.H * ((a.W + 15) / 16);
-  const unsigned blocks = nb(tiles, 4);
+  const bool big = a.cin > 64 || nco > 4;
   switch (nco) {
-    case 1: hipLaunchKernelGGL(k_conv3x3<1>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_conv3x3<2>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_conv3x3<3>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_conv3x3<4>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_conv3x3<6>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_conv3x3<8>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: big ? conv_lds<1, 4, 32>(s, a) : conv_lds<1, 8, 32>(s, a); break;
+    case 2: big ? conv_lds<2, 4, 32>(s, a) : conv_lds<2, 8, 32>(s, a); break;
+    case 3: big ? conv_lds<3, 4, 32>(s, a) : conv_lds<3, 8, 32>(s, a); break;
+    case 4: big ? conv_lds<4, 4, 32>(s, a) : conv_lds<4, 8, 32>(s, a); break;
+    case 6: conv_lds<6, 4, 32>(s, a); break;
+    case 8: conv_lds<8, 4, 32>(s, a); break;
     default: break;
   }
 }
@@ -477,21 +602,10 @@ void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int 
   hipLaunchKernelGGL(k_grad_prep, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, g, g_ct, g_off, act, act_ct, act_off,
                      creal, cpad, gm);
 }
-void launch_pool(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, int in_off, bf16* out,
-                 int out_ct, int out_off) {
-  const long long n = (long long)nimg * ((H + 1) / 2) * ((W + 1) / 2) * C;
-  hipLaunchKernelGGL(k_pool, dim3(nb(n, 256)), dim3(256), 0, s, nimg, H, W, C, in, in_ct, in_off, out, out_ct,
-                     out_off);
-}
 void launch_pool_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
                       int gin_off) {
   const long long n = (long long)nimg * H * W * C;
   hipLaunchKernelGGL(k_pool_back, dim3(nb(n, 256)), dim3(256), 0, s, nimg, H, W, C, g, g_ct, gin, gin_ct, gin_off);
-}
-void launch_upsample(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, bf16* out, int out_ct,
-                     int out_off) {
-  const long long n = (long long)nimg * H * W * C;
-  hipLaunchKernelGGL(k_upsample, dim3(nb(n, 256)), dim3(256), 0, s, nimg, H, W, C, in, in_ct, out, out_ct, out_off);
 }
 void launch_upsample_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, int g_off,
                           float* gc) {

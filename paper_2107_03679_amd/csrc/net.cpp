@@ -60,8 +60,8 @@ struct NetBufs {
   int cur_nimg = 0;  // images of the current call (<= cap_nimg)
   bool cap_train = false;
   std::vector<void*> bufs;
-  bf16 *x0 = nullptr, *cat0 = nullptr, *p0 = nullptr, *cat1 = nullptr, *p1 = nullptr, *cat2 = nullptr,
-       *p2 = nullptr, *e3 = nullptr, *d2 = nullptr, *d1 = nullptr, *d0 = nullptr, *gm = nullptr;
+  bf16 *x0 = nullptr, *e0 = nullptr, *e1 = nullptr, *e2 = nullptr, *e3 = nullptr, *d2 = nullptr, *d1 = nullptr,
+       *d0 = nullptr, *gm = nullptr;
   float2* q = nullptr;  // residual of the residual loss term
   float* rpart = nullptr;
   float *y = nullptr, *gy = nullptr, *g_d0 = nullptr, *g_cat0 = nullptr, *g_d1 = nullptr, *g_cat1 = nullptr,
@@ -124,12 +124,9 @@ void ensure(helm_net* n, int nimg, int H0, int W0, bool train) {
   auto& B = n->cur->bufs;  // (allocations of this set)
   const long long *P = n->cur->P;
   n->cur->x0 = n->alloc<bf16>(P[0] * 8, B);
-  n->cur->cat0 = n->alloc<bf16>(P[0] * 48, B);
-  n->cur->p0 = n->alloc<bf16>(P[1] * 16, B);
-  n->cur->cat1 = n->alloc<bf16>(P[1] * 96, B);
-  n->cur->p1 = n->alloc<bf16>(P[2] * 32, B);
-  n->cur->cat2 = n->alloc<bf16>(P[2] * 128, B);
-  n->cur->p2 = n->alloc<bf16>(P[3] * 64, B);
+  n->cur->e0 = n->alloc<bf16>(P[0] * 16, B);
+  n->cur->e1 = n->alloc<bf16>(P[1] * 32, B);
+  n->cur->e2 = n->alloc<bf16>(P[2] * 64, B);
   n->cur->e3 = n->alloc<bf16>(P[3] * 64, B);
   n->cur->d2 = n->alloc<bf16>(P[2] * 64, B);
   n->cur->d1 = n->alloc<bf16>(P[1] * 32, B);
@@ -175,13 +172,19 @@ void pack(helm_net* n, int i) {
   launch_pack(n->s, L.cout_pad, L.cin_pad, L.kpad, L.cob, L.kbpad, L.w, L.wt, L.wb);
 }
 
-void conv(helm_net* n, int i, const bf16* in, int in_ct, int in_off, int lvl, bf16* out, float* out32, int out_ct,
-          int out_off) {
+// plain input: in[p][0, ct)
+NetSrc src_of(const bf16* in, int ct) { return NetSrc{in, ct, 0, nullptr, 0, 0, 0, 0, 0}; }
+// 2 x 2 average of a layer at level lvl - 1
+NetSrc src_pool(helm_net* n, const bf16* in, int ct, int lvl) {
+  return NetSrc{in, ct, 0, nullptr, 0, 0, 1, n->cur->H[lvl - 1], n->cur->W[lvl - 1]};
+}
+// [upsampled `up` (cup channels), skip (ct channels)]
+NetSrc src_cat(const bf16* up, int cup, const bf16* skip, int ct) { return NetSrc{skip, ct, 0, up, cup, cup, 0, 0, 0}; }
+
+void conv(helm_net* n, int i, const NetSrc& src, int lvl, bf16* out, float* out32, int out_ct, int out_off) {
   const NetLayer& L = n->L[i];
   ConvArgs a{};
-  a.in = in;
-  a.in_ct = in_ct;
-  a.in_off = in_off;
+  a.src = src;
   a.cin = L.cin_pad;
   a.nimg = n->cur->cur_nimg;
   a.H = n->cur->H[lvl];
@@ -202,9 +205,7 @@ void conv(helm_net* n, int i, const bf16* in, int in_ct, int in_off, int lvl, bf
 void conv_back(helm_net* n, int i, int lvl, float* gin, int g_ct) {
   const NetLayer& L = n->L[i];
   ConvArgs a{};
-  a.in = n->cur->gm;
-  a.in_ct = L.cob;
-  a.in_off = 0;
+  a.src = src_of(n->cur->gm, L.cob);
   a.cin = L.cob;
   a.nimg = n->cur->cur_nimg;
   a.H = n->cur->H[lvl];
@@ -221,12 +222,10 @@ void conv_back(helm_net* n, int i, int lvl, float* gin, int g_ct) {
   launch_conv3x3(n->s, a, L.cin_pad / 16);
 }
 
-void wgrad(helm_net* n, int i, const bf16* in, int in_ct, int in_off, int lvl) {
+void wgrad(helm_net* n, int i, const NetSrc& src, int lvl) {
   NetLayer& L = n->L[i];
   WgradArgs a{};
-  a.in = in;
-  a.in_ct = in_ct;
-  a.in_off = in_off;
+  a.src = src;
   a.cin = L.cin_pad;
   a.nimg = n->cur->cur_nimg;
   a.H = n->cur->H[lvl];
@@ -242,59 +241,56 @@ void wgrad(helm_net* n, int i, const bf16* in, int in_ct, int in_off, int lvl) {
 }
 
 void forward(helm_net* n) {
-  const int N = n->cur->cur_nimg;
-  conv(n, A0, n->cur->x0, 8, 0, 0, n->cur->cat0, nullptr, 48, 32);
-  launch_pool(n->s, N, n->cur->H[0], n->cur->W[0], 16, n->cur->cat0, 48, 32, n->cur->p0, 16, 0);
-  conv(n, A1, n->cur->p0, 16, 0, 1, n->cur->cat1, nullptr, 96, 64);
-  launch_pool(n->s, N, n->cur->H[1], n->cur->W[1], 32, n->cur->cat1, 96, 64, n->cur->p1, 32, 0);
-  conv(n, A2, n->cur->p1, 32, 0, 2, n->cur->cat2, nullptr, 128, 64);
-  launch_pool(n->s, N, n->cur->H[2], n->cur->W[2], 64, n->cur->cat2, 128, 64, n->cur->p2, 64, 0);
-  conv(n, A3, n->cur->p2, 64, 0, 3, n->cur->e3, nullptr, 64, 0);
-  launch_upsample(n->s, N, n->cur->H[2], n->cur->W[2], 64, n->cur->e3, 64, n->cur->cat2, 128, 0);
-  conv(n, B2, n->cur->cat2, 128, 0, 2, n->cur->d2, nullptr, 64, 0);
-  launch_upsample(n->s, N, n->cur->H[1], n->cur->W[1], 64, n->cur->d2, 64, n->cur->cat1, 96, 0);
-  conv(n, B1, n->cur->cat1, 96, 0, 1, n->cur->d1, nullptr, 32, 0);
-  launch_upsample(n->s, N, n->cur->H[0], n->cur->W[0], 32, n->cur->d1, 32, n->cur->cat0, 48, 0);
-  conv(n, B0, n->cur->cat0, 48, 0, 0, n->cur->d0, nullptr, 16, 0);
-  conv(n, OUT, n->cur->d0, 16, 0, 0, nullptr, n->cur->y, 2, 0);
+  NetBufs& b = *n->cur;
+  conv(n, A0, src_of(b.x0, 8), 0, b.e0, nullptr, 16, 0);
+  conv(n, A1, src_pool(n, b.e0, 16, 1), 1, b.e1, nullptr, 32, 0);
+  conv(n, A2, src_pool(n, b.e1, 32, 2), 2, b.e2, nullptr, 64, 0);
+  conv(n, A3, src_pool(n, b.e2, 64, 3), 3, b.e3, nullptr, 64, 0);
+  conv(n, B2, src_cat(b.e3, 64, b.e2, 64), 2, b.d2, nullptr, 64, 0);
+  conv(n, B1, src_cat(b.d2, 64, b.e1, 32), 1, b.d1, nullptr, 32, 0);
+  conv(n, B0, src_cat(b.d1, 32, b.e0, 16), 0, b.d0, nullptr, 16, 0);
+  conv(n, OUT, src_of(b.d0, 16), 0, nullptr, b.y, 2, 0);
 }
 
+// Concatenation gradients g_cat{l} hold [upsampled part, skip part]; the skip part
+// also collects the pooled-path gradient of the encoder.
 void backward(helm_net* n) {
-  const int N = n->cur->cur_nimg;
-  const long long* P = n->cur->P;
+  NetBufs& b = *n->cur;
+  const int N = b.cur_nimg;
+  const long long* P = b.P;
   hipStream_t s = n->s;
   // output layer (no ReLU): gy is the loss gradient of y
-  launch_grad_prep(s, P[0], n->cur->gy, 2, 0, nullptr, 0, 0, 2, 16, n->cur->gm);
-  wgrad(n, OUT, n->cur->d0, 16, 0, 0);
-  conv_back(n, OUT, 0, n->cur->g_d0, 16);
+  launch_grad_prep(s, P[0], b.gy, 2, 0, nullptr, 0, 0, 2, 16, b.gm);
+  wgrad(n, OUT, src_of(b.d0, 16), 0);
+  conv_back(n, OUT, 0, b.g_d0, 16);
   // decoder
-  launch_grad_prep(s, P[0], n->cur->g_d0, 16, 0, n->cur->d0, 16, 0, 16, 16, n->cur->gm);
-  wgrad(n, B0, n->cur->cat0, 48, 0, 0);
-  conv_back(n, B0, 0, n->cur->g_cat0, 48);
-  launch_upsample_back(s, N, n->cur->H[0], n->cur->W[0], 32, n->cur->g_cat0, 48, 0, n->cur->g_d1);
-  launch_grad_prep(s, P[1], n->cur->g_d1, 32, 0, n->cur->d1, 32, 0, 32, 32, n->cur->gm);
-  wgrad(n, B1, n->cur->cat1, 96, 0, 1);
-  conv_back(n, B1, 1, n->cur->g_cat1, 96);
-  launch_upsample_back(s, N, n->cur->H[1], n->cur->W[1], 64, n->cur->g_cat1, 96, 0, n->cur->g_d2);
-  launch_grad_prep(s, P[2], n->cur->g_d2, 64, 0, n->cur->d2, 64, 0, 64, 64, n->cur->gm);
-  wgrad(n, B2, n->cur->cat2, 128, 0, 2);
-  conv_back(n, B2, 2, n->cur->g_cat2, 128);
-  launch_upsample_back(s, N, n->cur->H[2], n->cur->W[2], 64, n->cur->g_cat2, 128, 0, n->cur->g_e3);
-  // encoder (skip gradients accumulate into the concatenation gradients)
-  launch_grad_prep(s, P[3], n->cur->g_e3, 64, 0, n->cur->e3, 64, 0, 64, 64, n->cur->gm);
-  wgrad(n, A3, n->cur->p2, 64, 0, 3);
-  conv_back(n, A3, 3, n->cur->g_p, 64);
-  launch_pool_back(s, N, n->cur->H[2], n->cur->W[2], 64, n->cur->g_p, 64, n->cur->g_cat2, 128, 64);
-  launch_grad_prep(s, P[2], n->cur->g_cat2, 128, 64, n->cur->cat2, 128, 64, 64, 64, n->cur->gm);
-  wgrad(n, A2, n->cur->p1, 32, 0, 2);
-  conv_back(n, A2, 2, n->cur->g_p, 32);
-  launch_pool_back(s, N, n->cur->H[1], n->cur->W[1], 32, n->cur->g_p, 32, n->cur->g_cat1, 96, 64);
-  launch_grad_prep(s, P[1], n->cur->g_cat1, 96, 64, n->cur->cat1, 96, 64, 32, 32, n->cur->gm);
-  wgrad(n, A1, n->cur->p0, 16, 0, 1);
-  conv_back(n, A1, 1, n->cur->g_p, 16);
-  launch_pool_back(s, N, n->cur->H[0], n->cur->W[0], 16, n->cur->g_p, 16, n->cur->g_cat0, 48, 32);
-  launch_grad_prep(s, P[0], n->cur->g_cat0, 48, 32, n->cur->cat0, 48, 32, 16, 16, n->cur->gm);
-  wgrad(n, A0, n->cur->x0, 8, 0, 0);
+  launch_grad_prep(s, P[0], b.g_d0, 16, 0, b.d0, 16, 0, 16, 16, b.gm);
+  wgrad(n, B0, src_cat(b.d1, 32, b.e0, 16), 0);
+  conv_back(n, B0, 0, b.g_cat0, 48);
+  launch_upsample_back(s, N, b.H[0], b.W[0], 32, b.g_cat0, 48, 0, b.g_d1);
+  launch_grad_prep(s, P[1], b.g_d1, 32, 0, b.d1, 32, 0, 32, 32, b.gm);
+  wgrad(n, B1, src_cat(b.d2, 64, b.e1, 32), 1);
+  conv_back(n, B1, 1, b.g_cat1, 96);
+  launch_upsample_back(s, N, b.H[1], b.W[1], 64, b.g_cat1, 96, 0, b.g_d2);
+  launch_grad_prep(s, P[2], b.g_d2, 64, 0, b.d2, 64, 0, 64, 64, b.gm);
+  wgrad(n, B2, src_cat(b.e3, 64, b.e2, 64), 2);
+  conv_back(n, B2, 2, b.g_cat2, 128);
+  launch_upsample_back(s, N, b.H[2], b.W[2], 64, b.g_cat2, 128, 0, b.g_e3);
+  // encoder
+  launch_grad_prep(s, P[3], b.g_e3, 64, 0, b.e3, 64, 0, 64, 64, b.gm);
+  wgrad(n, A3, src_pool(n, b.e2, 64, 3), 3);
+  conv_back(n, A3, 3, b.g_p, 64);
+  launch_pool_back(s, N, b.H[2], b.W[2], 64, b.g_p, 64, b.g_cat2, 128, 64);
+  launch_grad_prep(s, P[2], b.g_cat2, 128, 64, b.e2, 64, 0, 64, 64, b.gm);
+  wgrad(n, A2, src_pool(n, b.e1, 32, 2), 2);
+  conv_back(n, A2, 2, b.g_p, 32);
+  launch_pool_back(s, N, b.H[1], b.W[1], 32, b.g_p, 32, b.g_cat1, 96, 64);
+  launch_grad_prep(s, P[1], b.g_cat1, 96, 64, b.e1, 32, 0, 32, 32, b.gm);
+  wgrad(n, A1, src_pool(n, b.e0, 16, 1), 1);
+  conv_back(n, A1, 1, b.g_p, 16);
+  launch_pool_back(s, N, b.H[0], b.W[0], 16, b.g_p, 16, b.g_cat0, 48, 32);
+  launch_grad_prep(s, P[0], b.g_cat0, 48, 32, b.e0, 16, 0, 16, 16, b.gm);
+  wgrad(n, A0, src_of(b.x0, 8), 0);
 }
 
 int fail(helm_net* n, int code, const std::string& msg) {

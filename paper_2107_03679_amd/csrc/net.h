@@ -7,9 +7,22 @@
 
 typedef __bf16 bf16;
 
+// Input of a convolution: channels [0, cup) are the nearest-neighbour upsampling
+// of `up` (half resolution, up_ct channels per pixel), channels [cup, cin) come
+// from `in` at channel offset in_off (in_ct per pixel): at the convolution's
+// resolution, or, with pool = 1, as the 2 x 2 average (zero padding) of `in`
+// at resolution Hs x Ws.  Channel strides and offsets are multiples of 8.
+struct NetSrc {
+  const bf16* in;
+  int in_ct, in_off;
+  const bf16* up;
+  int up_ct, cup;
+  int pool, Hs, Ws;
+};
+
 struct ConvArgs {
-  const bf16* in;  // NHWC input
-  int in_ct, in_off, cin;  // channel stride, offset, channels (multiple of 8)
+  NetSrc src;
+  int cin;  // channels (multiple of 8)
   int nimg, H, W;
   const bf16* wt;  // [cout_pad][kpad] packed weights
   int kpad;
@@ -22,8 +35,8 @@ struct ConvArgs {
 };
 
 struct WgradArgs {
-  const bf16* in;  // layer input
-  int in_ct, in_off, cin;
+  NetSrc src;  // layer input
+  int cin;
   int nimg, H, W;
   const bf16* g;  // masked output gradient [P][g_ct]
   int g_ct;
@@ -37,12 +50,8 @@ void launch_wgrad(hipStream_t s, const WgradArgs& a, int nchunk, float* dw, cons
                   int cout_real);
 void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int g_off, const bf16* act, int act_ct,
                       int act_off, int creal, int cpad, bf16* gm);
-void launch_pool(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, int in_off, bf16* out,
-                 int out_ct, int out_off);
 void launch_pool_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
                       int gin_off);
-void launch_upsample(hipStream_t s, int nimg, int H, int W, int C, const bf16* in, int in_ct, bf16* out, int out_ct,
-                     int out_off);
 void launch_upsample_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, int g_off,
                           float* gc);
 int loss_partials(long long n);
