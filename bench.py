@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--reorth", type=int, default=0)
     p.add_argument("--rhs", type=int, default=None, help="override the number of plane waves")
     p.add_argument("--no-profile", action="store_true")
+    p.add_argument("--no-tune", action="store_true", help="keep the default multigrid launch shapes")
+    p.add_argument("--tune-cache", default=None, help="JSON-lines cache of the autotuner's choices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
@@ -183,6 +185,11 @@ def main():
                        max_iters=20000)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
+    tune = None
+    if not args.no_tune:
+        t_tune = time.perf_counter()
+        tune = ctx.autotune(B, cache=args.tune_cache)
+        tune["tune_s"] = time.perf_counter() - t_tune
     x = ctx.empty_fields(B)
 
     def step():
@@ -223,6 +230,9 @@ def main():
             "coarsest": ctx.info.coarsest_n, "restart": args.restart, "cycle": {1: "V", 2: "W", 3: "W at the finest level, V below"}[args.cycle],
             "kappa": "1+0.5j", "nu": [1, 1], "omega_jac": 0.8, "rtol": 1e-6, "preconditioner": "multigrid",
             "krylov": "FGMRES" + ("(CGS2)" if args.reorth else "(CGS1)"),
+            "launch_shapes": "default" if tune is None else {
+                "down_tiles": tune["down_tiles"], "up_tiles": tune["up_tiles"],
+                "coarse_single_launch_max_points": tune["coarse_single_launch_max_points"]},
         },
         "solver": {
             "all_converged": bool(all(s.converged for s in stats)),
@@ -230,6 +240,8 @@ def main():
             "rel_res_true_max": float(max(s.rel_res_true.max() for s in stats)),
             "setup_s": t_setup,
         },
+        "autotune": None if tune is None else {
+            k: tune[k] for k in ("from_cache", "vcycle_ms", "vcycle_default_ms", "tune_s")},
     }
 
     if not args.no_profile:

@@ -299,6 +299,31 @@ int helm_solve_snapshots(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x,
 int helm_net_examples(helm_ctx* ctx, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,
                       const int* crops_host, int S, double gamma, float* feat_dev, float* tgt_dev);
 
+/* Launch shapes chosen by helm_autotune. */
+#define HELM_TUNE_MAX_LEVELS 12
+typedef struct {
+  int from_cache;                       /* 1: taken from the cache file, not re-timed */
+  int levels;
+  int down[HELM_TUNE_MAX_LEVELS][2];    /* fused down-leg tile per level: coarse TCX x TCY points */
+  int up[HELM_TUNE_MAX_LEVELS][3];      /* fused up-leg tile per level: fine TX x TY, PY points per thread */
+  long long coarse_max;                 /* levels with at most this many points run in one launch */
+  double vcycle_ms;                     /* one preconditioner cycle for B right-hand sides, chosen shapes */
+  double vcycle_default_ms;             /* ... with the default shapes (0 when from_cache) */
+} helm_tune;
+
+/* Autotuner of the batched multigrid cycle (the batching / launch-shape part of
+ * the method's many-right-hand-side solves): times every tile shape of the
+ * fused 2D down- and up-legs on each level with B right-hand sides, then the
+ * threshold below which the coarse levels run as one launch, and keeps the
+ * fastest for the following solves of this context (results do not depend on
+ * the shapes: every point is computed by the same arithmetic).  cache_path
+ * (nullable) is a JSON-lines file keyed by GPU architecture, dimension, grid,
+ * levels, B, smoothing steps and cycle type: a matching entry is applied
+ * without timing, a new result is appended.  Uses the Krylov workspace as
+ * scratch (do not call during a solve on the same context); invalidates the
+ * captured graph.  Errors: HELM_EINVAL (B outside [1, max_batch]), HELM_EHIP. */
+int helm_autotune(helm_ctx* ctx, int B, const char* cache_path, helm_tune* out_host);
+
 /* ---- per-launch profiler (measurement support) ----
  * While enabled, every kernel launch of the context is bracketed by HIP events
  * on the context's stream (restart cycles are then launched one kernel at a

@@ -92,6 +92,11 @@ struct helm_ctx {
   hipGraphExec_t graph = nullptr;
   int graph_B = 0;
 
+  // launch shapes (helm_autotune): fused-leg tile per level, single-launch coarse threshold
+  int tune_down[HELM_MAX_LEVELS] = {0};
+  int tune_up[HELM_MAX_LEVELS] = {0};
+  long long coarse_max = -1;  // points; -1: default (48^2 in 2D, 16^3 in 3D), 0: never
+
   // learned preconditioner (NULL: multigrid only)
   helm_net* net = nullptr;
   double accept_tol = 0.9;
@@ -229,7 +234,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const int gamma = c->o.cycle == 3 ? (l == 0 ? 2 : 1) : c->o.cycle;
   const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
   const bool vcycle11 = c->o.fused && zero_guess && v_below && c->o.nu1 == 1 && c->o.nu2 == 1;
-  const long long small = dim == 2 ? 48LL * 48 : 16LL * 16 * 16;
+  const long long small = c->coarse_max >= 0 ? c->coarse_max : (dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
   if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr && r.stride == fine.N &&
       out.stride == fine.N) {
     // levels l .. L-1 in one launch, one workgroup per right-hand side
@@ -259,7 +264,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const double Nf = (double)fine.N, Nc1 = (double)crs.N, Bp = c->prof_B;
   if (fused) {
     ProfScope ps(c, lvl_name("down_fused", l), Bp * 8.0 * (Nf + Nc1) + 8.0 * Nf);
-    launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act);
+    launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act, c->tune_down[l]);
   } else {
     int sweeps = c->o.nu1;
     if (zero_guess) {
@@ -294,7 +299,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   }
   if (fused) {
     ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
-    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ec, crs.n, out, act);
+    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ec, crs.n, out, act, c->tune_up[l]);
   } else {
     {
       ProfScope ps(c, lvl_name("prolong_add", l), Bp * (16.0 * Nf + 8.0 * Nc1));
@@ -564,6 +569,90 @@ void free_ctx(helm_ctx* c) {
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code)); \
   }                                                                                \
   return HELM_OK;
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+std::string tune_key(const helm_ctx* c, int B) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.gcnArchName[0] = 0;
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s d%d n%d L%d B%d nu%d%d cycle%d", arch.c_str(), c->dim, c->ne, c->L, B,
+                c->o.nu1, c->o.nu2, c->o.cycle);
+  return buf;
+}
+
+// one cache entry per line: {"key": "...", "down": [..], "up": [..], "coarse_max": N}
+bool tune_load(helm_ctx* c, const char* path, const std::string& key) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string tag = "\"key\": \"" + key + "\"";
+  while (!found && std::fgets(line, sizeof line, f)) {
+    if (!std::strstr(line, tag.c_str())) continue;
+    int down[HELM_MAX_LEVELS] = {0}, up[HELM_MAX_LEVELS] = {0};
+    long long cm = -1;
+    const char* p = std::strstr(line, "\"down\": [");
+    const char* q = std::strstr(line, "\"up\": [");
+    const char* m = std::strstr(line, "\"coarse_max\": ");
+    if (!p || !q || !m || std::sscanf(m + 14, "%lld", &cm) != 1) break;
+    p += 9;
+    q += 7;
+    bool ok = true;
+    for (int l = 0; l < c->L && ok; ++l) {
+      int nd = 0, nu = 0;
+      ok = std::sscanf(p, "%d%n", &down[l], &nd) == 1 && std::sscanf(q, "%d%n", &up[l], &nu) == 1 && down[l] >= 0 &&
+           down[l] < mg_down_variants() && up[l] >= 0 && up[l] < mg_up_variants();
+      p += nd;
+      q += nu;
+      while (*p == ',' || *p == ' ') ++p;
+      while (*q == ',' || *q == ' ') ++q;
+    }
+    if (!ok) break;
+    std::memcpy(c->tune_down, down, sizeof down);
+    std::memcpy(c->tune_up, up, sizeof up);
+    c->coarse_max = cm;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_save(const helm_ctx* c, const char* path, const std::string& key) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: an unwritable path only costs a re-tune
+  std::fprintf(f, "{\"key\": \"%s\", \"down\": [", key.c_str());
+  for (int l = 0; l < c->L; ++l) std::fprintf(f, "%s%d", l ? ", " : "", c->tune_down[l]);
+  std::fprintf(f, "], \"up\": [");
+  for (int l = 0; l < c->L; ++l) std::fprintf(f, "%s%d", l ? ", " : "", c->tune_up[l]);
+  std::fprintf(f, "], \"coarse_max\": %lld}\n", c->coarse_max);
+  std::fclose(f);
+}
+
+// mean duration (ms) of `reps` back-to-back calls of f on the context stream, after one warm-up call
+template <class F>
+double time_ms(helm_ctx* c, F&& f, int reps) {
+  f();
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "event");
+  check(hipEventCreate(&e1), "event");
+  check(hipEventRecord(e0, c->s), "event");
+  for (int i = 0; i < reps; ++i) f();
+  check(hipEventRecord(e1, c->s), "event");
+  check(hipEventSynchronize(e1), "event");
+  float ms = 0.f;
+  check(hipEventElapsedTime(&ms, e0, e1), "event");
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  check(hipGetLastError(), "tuning launch");
+  return ms / reps;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -934,6 +1023,85 @@ int helm_precondition(helm_ctx* c, int B, const helm_c32* r, helm_c32* z) {
   HELM_GUARD_BEGIN
   mg_cycle(c, B, 0, VecSet{(c32*)r, c->N0}, ScaleSet{nullptr, 0}, VecSet{(c32*)z, c->N0}, true, c->d_ones);
   HELM_GUARD_END("precondition")
+}
+
+int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
+  if (!c) return HELM_EINVAL;
+  if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
+  HELM_GUARD_BEGIN
+  const std::string key = tune_key(c, B);
+  if (c->graph) {  // a captured graph holds the old launch shapes
+    hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_B = 0;
+  }
+  struct ProfOff {  // no per-launch events while timing; restored on every exit
+    helm_ctx* c;
+    bool was;
+    ~ProfOff() { c->prof_on = was; }
+  } prof_off{c, c->prof_on};
+  c->prof_on = false;
+  helm_tune t{};
+  t.from_cache = cache_path && tune_load(c, cache_path, key);
+  // the default shapes' V-cycle time, for the report
+  const long long N0 = c->N0;
+  const VecSet r0{c->k.V, N0}, z0{c->k.Z, N0};
+  check(hipMemsetAsync(c->k.V, 0, (size_t)B * N0 * sizeof(c32), c->s), "memset");
+  auto vcycle = [&] { mg_cycle(c, B, 0, r0, ScaleSet{nullptr, 0}, z0, true, nullptr); };
+  if (!t.from_cache) {
+    for (int l = 0; l < HELM_MAX_LEVELS; ++l) c->tune_down[l] = c->tune_up[l] = 0;
+    c->coarse_max = -1;
+    t.vcycle_default_ms = time_ms(c, vcycle, 3);
+    // 1. fused-leg tiles, level by level, on the level's own buffers
+    if (c->dim == 2 && c->o.fused) {
+      const float om = (float)c->o.omega_jac;
+      for (int l = 0; l + 1 < c->L; ++l) {
+        Level& f = c->lv[l];
+        Level& cr = c->lv[l + 1];
+        const VecSet r = l == 0 ? r0 : VecSet{f.rc, f.N};
+        const VecSet out = l == 0 ? z0 : VecSet{f.t, f.N};
+        const LevelArgs K = level_K(c, l);
+        if (l > 0) check(hipMemsetAsync(f.rc, 0, (size_t)B * f.N * sizeof(c32), c->s), "memset");
+        check(hipMemsetAsync(cr.e, 0, (size_t)B * cr.N * sizeof(c32), c->s), "memset");
+        double best = 1e30;
+        for (int v = 0; v < mg_down_variants(); ++v) {
+          const double ms = time_ms(
+              c, [&] { launch_down_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.rc, cr.N}, cr.n, nullptr, v); }, 5);
+          if (ms < best) best = ms, c->tune_down[l] = v;
+        }
+        best = 1e30;
+        for (int v = 0; v < mg_up_variants(); ++v) {
+          const double ms = time_ms(
+              c, [&] { launch_up_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.e, cr.N}, cr.n, out, nullptr, v); }, 5);
+          if (ms < best) best = ms, c->tune_up[l] = v;
+        }
+      }
+    }
+    // 2. the single-launch threshold for the coarse levels, on whole V-cycles
+    if (c->o.coarse_single_launch) {
+      const long long cand2[] = {0, 24LL * 24, 48LL * 48, 96LL * 96};
+      const long long cand3[] = {0, 8LL * 8 * 8, 16LL * 16 * 16, 24LL * 24 * 24};
+      const long long* cand = c->dim == 2 ? cand2 : cand3;
+      double best = 1e30;
+      long long pick = -1;
+      for (int i = 0; i < 4; ++i) {
+        c->coarse_max = cand[i];
+        const double ms = time_ms(c, vcycle, 3);
+        if (ms < best) best = ms, pick = cand[i];
+      }
+      c->coarse_max = pick;
+    }
+    if (cache_path) tune_save(c, cache_path, key);
+  }
+  t.vcycle_ms = time_ms(c, vcycle, 3);
+  t.levels = c->L;
+  for (int l = 0; l < c->L && l < HELM_TUNE_MAX_LEVELS; ++l) {
+    mg_down_shape(c->tune_down[l], &t.down[l][0], &t.down[l][1]);
+    mg_up_shape(c->tune_up[l], &t.up[l][0], &t.up[l][1], &t.up[l][2]);
+  }
+  t.coarse_max = c->coarse_max >= 0 ? c->coarse_max : (c->dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
+  if (out) *out = t;
+  HELM_GUARD_END("autotune")
 }
 
 int helm_profile_enable(helm_ctx* c, int on) {

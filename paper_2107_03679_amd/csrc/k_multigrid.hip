@@ -332,22 +332,66 @@ inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / 
 
 }  // namespace
 
-// fused-leg tile shapes: coarse 32 x 8 per block (down), fine 64 x 16 per block (up)
-constexpr int DN_TCX = 32, DN_TCY = 8;
-constexpr int UP_TX = 64, UP_TY = 16, UP_PY = 4;
+// Tile shapes of the fused legs the autotuner chooses from (index 0 = default):
+// down-leg coarse TCX x TCY per block, up-leg fine TX x TY with PY points per thread.
+namespace {
+struct DownTile {
+  int tcx, tcy;
+};
+struct UpTile {
+  int tx, ty, py;
+};
+constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}};
+constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}};
+
+template <int TCX, int TCY>
+void down_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
+               const int* active) {
+  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+  hipLaunchKernelGGL((k_down_fused2<TCX, TCY>), dim3(B, tiles), dim3(TCX * TCY), 0, s, r, rs, lv, omega, rc, nc,
+                     active);
+}
+template <int TX, int TY, int PY>
+void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc, VecSet z,
+             const int* active) {
+  const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+  hipLaunchKernelGGL((k_up_fused2<TX, TY, PY>), dim3(B, tiles), dim3(TX * (TY / PY)), 0, s, r, rs, lv, omega, ec,
+                     nc, z, active);
+}
+}  // namespace
+
+int mg_down_variants() { return (int)(sizeof(kDown) / sizeof(kDown[0])); }
+int mg_up_variants() { return (int)(sizeof(kUp) / sizeof(kUp[0])); }
+void mg_down_shape(int cfg, int* tcx, int* tcy) {
+  *tcx = kDown[cfg].tcx;
+  *tcy = kDown[cfg].tcy;
+}
+void mg_up_shape(int cfg, int* tx, int* ty, int* py) {
+  *tx = kUp[cfg].tx;
+  *ty = kUp[cfg].ty;
+  *py = kUp[cfg].py;
+}
 
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
-                        const int* active) {
-  const int tiles = ((nc + DN_TCX - 1) / DN_TCX) * ((nc + DN_TCY - 1) / DN_TCY);
-  hipLaunchKernelGGL((k_down_fused2<DN_TCX, DN_TCY>), dim3(B, tiles), dim3(DN_TCX * DN_TCY), 0, s, r, rs, lv, omega,
-                     rc, nc, active);
+                        const int* active, int cfg) {
+  switch (cfg) {
+    case 1: down_tile<16, 16>(s, B, r, rs, lv, omega, rc, nc, active); break;
+    case 2: down_tile<64, 4>(s, B, r, rs, lv, omega, rc, nc, active); break;
+    case 3: down_tile<32, 4>(s, B, r, rs, lv, omega, rc, nc, active); break;
+    case 4: down_tile<16, 8>(s, B, r, rs, lv, omega, rc, nc, active); break;
+    default: down_tile<32, 8>(s, B, r, rs, lv, omega, rc, nc, active); break;
+  }
 }
 
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active) {
-  const int tiles = ((lv.n + UP_TX - 1) / UP_TX) * ((lv.n + UP_TY - 1) / UP_TY);
-  hipLaunchKernelGGL((k_up_fused2<UP_TX, UP_TY, UP_PY>), dim3(B, tiles), dim3(UP_TX * (UP_TY / UP_PY)), 0, s, r,
-                     rs, lv, omega, ec, nc, z, active);
+                      VecSet z, const int* active, int cfg) {
+  switch (cfg) {
+    case 1: up_tile<32, 16, 2>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+    case 2: up_tile<64, 8, 2>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+    case 3: up_tile<32, 32, 4>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+    case 4: up_tile<64, 32, 8>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+    default: up_tile<64, 16, 4>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+  }
 }
 
 void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,

@@ -35,10 +35,15 @@ enum {
 };
 
 // ---- multigrid legs (2D) ----
+// fused 2D legs; cfg selects one of the tile shapes (0 = default, see mg_*_shape)
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
-                        const int* active);
+                        const int* active, int cfg);
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active);
+                      VecSet z, const int* active, int cfg);
+int mg_down_variants();
+int mg_up_variants();
+void mg_down_shape(int cfg, int* tcx, int* tcy);
+void mg_up_shape(int cfg, int* tx, int* ty, int* py);
 void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
                         const int* active);
 void launch_jacobi(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,

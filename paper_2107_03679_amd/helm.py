@@ -46,6 +46,14 @@ class HelmStats(ctypes.Structure):
                 ("fallbacks", ctypes.c_int)]
 
 
+class HelmTune(ctypes.Structure):
+    _fields_ = [
+        ("from_cache", ctypes.c_int), ("levels", ctypes.c_int),
+        ("down", (ctypes.c_int * 2) * 12), ("up", (ctypes.c_int * 3) * 12),
+        ("coarse_max", ctypes.c_longlong), ("vcycle_ms", ctypes.c_double), ("vcycle_default_ms", ctypes.c_double),
+    ]
+
+
 class HelmInfo(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int), ("n", ctypes.c_int), ("abl_width", ctypes.c_int), ("n_e", ctypes.c_int),
@@ -63,7 +71,7 @@ EXPORTS = [
     "helm_profile_get", "helm_last_error", "helm_destroy",
     "helm_net_layers", "helm_net_layer_shape", "helm_net_create", "helm_net_destroy", "helm_net_last_error",
     "helm_net_set_layer", "helm_net_get_layer", "helm_net_get_grad", "helm_net_forward", "helm_net_backward",
-    "helm_net_adam_step", "helm_net_set_loss", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
+    "helm_net_adam_step", "helm_net_set_loss", "helm_autotune", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
 ]
 
 _lib = None
@@ -118,6 +126,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_net_backward.argtypes = [vp, i, i, i, vp, vp, ctypes.POINTER(d)]
     lib.helm_net_adam_step.argtypes = [vp, d]
     lib.helm_net_set_loss.argtypes = [vp, d, d, d, d]
+    lib.helm_autotune.argtypes = [vp, i, ctypes.c_char_p, ctypes.POINTER(HelmTune)]
     lib.helm_set_preconditioner.argtypes = [vp, vp, d, d, i]
     lib.helm_solve_snapshots.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats), i, i, vp, ctypes.POINTER(i)]
     lib.helm_net_examples.argtypes = [vp, i, vp, vp, vp, i, vp, i, d, vp, vp]
@@ -360,6 +369,21 @@ class Context:
                                         crops.ctypes.data_as(ctypes.c_void_p), size, gamma, _ptr(feat), _ptr(tgt))
         self._check(rc, "helm_net_examples")
         return feat, tgt
+
+    def autotune(self, B: int, cache: str | None = None) -> dict:
+        """Time the multigrid launch shapes for B right-hand sides and keep the fastest
+        (optionally through a JSON-lines cache file); returns the choice."""
+        t = HelmTune()
+        path = cache.encode() if cache else None
+        self._check(self.lib.helm_autotune(self._h, B, path, ctypes.byref(t)), "helm_autotune")
+        L = t.levels
+        return {
+            "from_cache": bool(t.from_cache),
+            "down_tiles": [tuple(t.down[l]) for l in range(L - 1)],
+            "up_tiles": [tuple(t.up[l]) for l in range(L - 1)],
+            "coarse_single_launch_max_points": int(t.coarse_max),
+            "vcycle_ms": t.vcycle_ms, "vcycle_default_ms": t.vcycle_default_ms,
+        }
 
     def profile(self, on: bool = True, reset: bool = True):
         """Enable/disable per-launch HIP-event timing of every kernel of this context."""

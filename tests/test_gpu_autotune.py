@@ -1,0 +1,122 @@
+"""Autotuner of the batched multigrid cycle (launch shapes of the fused legs,
+single-launch threshold of the coarse levels).
+
+Every tile shape computes each point with the same arithmetic, so the cycle
+must be bit-identical whatever the tuner picks; the coarse-level threshold
+switches between two kernels, which are compared with the FP64 oracle.  The
+JSON-lines cache is checked by re-applying a stored choice, and every tile
+variant is forced through an edited cache line.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.multigrid import Hierarchy
+
+from .helpers import gpu_context, medium, oracle_problem, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+N, W, LEVELS, B = 150, 20, 4, 4
+DEFAULT_COARSE_MAX = 48 * 48
+
+
+@pytest.fixture(scope="module")
+def case():
+    print(f"\n[autotune n={N} w={W} levels={LEVELS} B={B}]", flush=True)
+    nmap = medium(N, seed=3)
+    prob = oracle_problem(nmap, w=W, levels=LEVELS)
+    hier = Hierarchy(prob)
+    r = synth.complex_field((B, *prob.shape), 91)
+    ref = np.stack([hier.vcycle(ri.ravel()).reshape(prob.shape) for ri in r])
+    return nmap, prob, r, ref
+
+
+def _edit(line: str, levels: int, down: int, up: int, coarse_max: int) -> str:
+    e = json.loads(line)
+    e["down"] = [down] * levels
+    e["up"] = [up] * levels
+    e["coarse_max"] = coarse_max
+    return json.dumps(e) + "\n"
+
+
+def test_autotune_keeps_results_and_caches(case, tmp_path):
+    nmap, prob, r, ref = case
+    cache = tmp_path / "tune.jsonl"
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    rd = to_dev(r)
+    z0 = ctx.precondition(rd)
+    assert rel(to_np(z0), ref) < 1e-5
+    t = ctx.autotune(B, cache=str(cache))
+    print(f"[autotune] {t}", flush=True)
+    assert not t["from_cache"]
+    assert len(t["down_tiles"]) == LEVELS - 1 and len(t["up_tiles"]) == LEVELS - 1
+    assert t["vcycle_ms"] > 0 and t["vcycle_default_ms"] > 0
+    z1 = ctx.precondition(rd)
+    assert rel(to_np(z1), ref) < 1e-5
+    if t["coarse_single_launch_max_points"] == DEFAULT_COARSE_MAX:
+        assert bool((z1 == z0).all())
+    # the solve with the tuned shapes reaches the target and matches the untuned solve's accuracy
+    rhs = ctx.plane_wave_rhs(synth.directions_2d(B))
+    x, st = ctx.solve(rhs)
+    assert st.converged and np.all(st.rel_res_true <= 1e-6)
+    ctx.close()
+    # a fresh context on the same problem takes the cached choice without timing
+    ctx2 = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    t2 = ctx2.autotune(B, cache=str(cache))
+    assert t2["from_cache"]
+    for k in ("down_tiles", "up_tiles", "coarse_single_launch_max_points"):
+        assert t2[k] == t[k]
+    assert bool((ctx2.precondition(rd) == z1).all())
+    x2, st2 = ctx2.solve(rhs)
+    assert bool((x2 == x).all()) and np.array_equal(st2.iters, st.iters)
+    ctx2.close()
+    assert len(cache.read_text().splitlines()) == 1
+
+
+@pytest.mark.parametrize("variant", range(5))
+def test_every_tile_variant_is_bit_identical(case, tmp_path, variant):
+    nmap, prob, r, ref = case
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    rd = to_dev(r)
+    z0 = ctx.precondition(rd)
+    first = tmp_path / "first.jsonl"
+    ctx.autotune(B, cache=str(first))
+    line = first.read_text().splitlines()[0]
+    forced = tmp_path / "forced.jsonl"
+    forced.write_text(_edit(line, LEVELS, variant, variant, DEFAULT_COARSE_MAX))
+    t = ctx.autotune(B, cache=str(forced))
+    assert t["from_cache"], "the forced cache line was not accepted"
+    z = ctx.precondition(rd)
+    assert bool((z == z0).all()), f"tile variant {variant} changed the cycle"
+    ctx.close()
+
+
+def test_coarse_threshold_variants_match_oracle(case, tmp_path):
+    nmap, prob, r, ref = case
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    rd = to_dev(r)
+    first = tmp_path / "first.jsonl"
+    ctx.autotune(B, cache=str(first))
+    line = first.read_text().splitlines()[0]
+    for cm in (0, 24 * 24, 96 * 96):
+        forced = tmp_path / f"cm{cm}.jsonl"
+        forced.write_text(_edit(line, LEVELS, 0, 0, cm))
+        t = ctx.autotune(B, cache=str(forced))
+        assert t["from_cache"] and t["coarse_single_launch_max_points"] == cm
+        assert rel(to_np(ctx.precondition(rd)), ref) < 1e-5, cm
+    ctx.close()
+
+
+def test_autotune_rejects_bad_batch(case):
+    from paper_2107_03679_amd.helm import HelmError
+
+    nmap = case[0]
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    with pytest.raises(HelmError):
+        ctx.autotune(B + 1)
+    with pytest.raises(HelmError):
+        ctx.autotune(0)
+    ctx.close()
