@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--cycle", type=int, default=3, help="1 = V, 2 = W, 3 = two coarse corrections on the finest "
                                                           "level and V-cycles below")
     p.add_argument("--reorth", type=int, default=0)
+    p.add_argument("--krylov", choices=("sstep", "fgmres", "bicgstab"), default="sstep",
+                   help="GMRES(m) in s-step form (Gram matrix + Cholesky QR), as FGMRES (Arnoldi), or the "
+                        "paper's Bi-CGSTAB (restart = iterations between status checks)")
     p.add_argument("--rhs", type=int, default=None, help="override the number of plane waves")
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--no-tune", action="store_true", help="keep the default multigrid launch shapes")
@@ -47,7 +50,30 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
+    p.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (for counter collection)")
+    p.add_argument("--copy-probe", type=float, default=256.0,
+                   help="MiB of a plain device-to-device copy timed before the solve (0: skip); the same copy "
+                        "calibrates the HBM byte counters")
     return p.parse_args()
+
+
+def copy_probe(mib):
+    """Plain device copy of `mib` MiB, three times: achievable HBM bandwidth (read + write bytes / time)."""
+    import torch
+
+    n = int(mib * 2 ** 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    return {"bytes_per_copy": 2 * 4 * n, "ms": ms, "GB/s": 2 * 4 * n / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
@@ -182,7 +208,9 @@ def main():
     t_setup = time.perf_counter()
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
                        levels=args.levels, restart=args.restart, cycle=args.cycle, reorth=args.reorth, max_batch=B,
-                       max_iters=20000)
+                       max_iters=20000, use_graph=0 if args.no_graph else 1,
+                       krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
+                               "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     tune = None
@@ -191,6 +219,7 @@ def main():
         tune = ctx.autotune(B, cache=args.tune_cache)
         tune["tune_s"] = time.perf_counter() - t_tune
     x = ctx.empty_fields(B)
+    probe = copy_probe(args.copy_probe) if args.copy_probe > 0 else None
 
     def step():
         rhs = ctx.plane_wave_rhs(dirs)
@@ -229,7 +258,9 @@ def main():
             "workload": args.workload, "interior": wl["n"], "grid": ne, "rhs": B, "levels": args.levels,
             "coarsest": ctx.info.coarsest_n, "restart": args.restart, "cycle": {1: "V", 2: "W", 3: "W at the finest level, V below"}[args.cycle],
             "kappa": "1+0.5j", "nu": [1, 1], "omega_jac": 0.8, "rtol": 1e-6, "preconditioner": "multigrid",
-            "krylov": "FGMRES" + ("(CGS2)" if args.reorth else "(CGS1)"),
+            "krylov": {"sstep": f"GMRES({args.restart}), s-step form (Gram + Cholesky QR)",
+                       "fgmres": f"FGMRES({args.restart})" + (", CGS2" if args.reorth else ", CGS1"),
+                       "bicgstab": "Bi-CGSTAB (Alg. 3)"}[args.krylov],
             "launch_shapes": "default" if tune is None else {
                 "down_tiles": tune["down_tiles"], "up_tiles": tune["up_tiles"],
                 "coarse_single_launch_max_points": tune["coarse_single_launch_max_points"]},
@@ -257,6 +288,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "avg_launch_us": 1000.0 * ms / n, "bytes_per_launch": by / n, "share_of_step": ms / total,
         }
+        if probe is not None:
+            out["roofline"]["copy_probe"] = probe
         out["kernels"] = {
             k: {"ms": round(v[0], 3), "launches": v[1], "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0}
             for k, v in sorted(rep.items(), key=lambda kv: -kv[1][0])

@@ -103,7 +103,31 @@ typedef struct {
   int use_graph;    /* 1 = replay each restart cycle as a captured hipGraph (1) */
   int coarse_single_launch; /* 1 = V-cycle levels with <= 48^2 (2D) / 16^3 (3D) points run
                                in one launch, one workgroup per right-hand side (1) */
+  int krylov;       /* HELM_KRYLOV_SSTEP (default), HELM_KRYLOV_FGMRES or HELM_KRYLOV_BICGSTAB */
 } helm_opts;
+
+/* Krylov forms (helm_opts.krylov).  Both minimise the residual over the same
+ * space (GMRES(m) right-preconditioned by the multigrid cycle: the Krylov
+ * part of the Krylov + multigrid scheme of Sec. IV-C) and restart from a
+ * float-float true residual.
+ *   HELM_KRYLOV_FGMRES  flexible GMRES, Arnoldi with classical Gram-Schmidt
+ *                       (reorth = 1: twice); admits a nonlinear preconditioner.
+ *   HELM_KRYLOV_SSTEP   s-step form: the basis W_{j+1} = A M(W_j) is built by
+ *                       plain matvecs, one Gram pass per cycle and an FP64
+ *                       Cholesky QR give the least squares; restart <= 12;
+ *                       needs a linear preconditioner, so a context with a
+ *                       learned network (helm_set_preconditioner) runs FGMRES. */
+#define HELM_KRYLOV_FGMRES 0
+#define HELM_KRYLOV_SSTEP 1
+/*   HELM_KRYLOV_BICGSTAB  the paper's Alg. 3 (Bi-CGSTAB, two multigrid cycles per
+ *                       iteration; sigma is van der Vorst's omega), batched, with
+ *                       the float-float solution; `restart` (>= 4) is the number of
+ *                       iterations between status checks, not a restart: the
+ *                       recurrence restarts from the true residual only when its
+ *                       own residual met the tolerance and the true one did not.
+ *                       helm_stats.iters counts multigrid cycles (2 per iteration).
+ *                       A context with a learned network runs FGMRES instead. */
+#define HELM_KRYLOV_BICGSTAB 2
 
 typedef struct {
   int iters;            /* preconditioner applications */
@@ -226,6 +250,72 @@ int helm_coarse_solve(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
 /* z = M^-1 r: one multigrid cycle from a zero initial guess for the
  * h^2-scaled fine system K'_0 z = r (the FGMRES preconditioner). */
 int helm_precondition(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* z);
+
+/* ---- inverse problem (Sec. V, eq. MAPInverse with on-grid receivers S) ----
+ * Unknown: the scattering potential f = k0^2 (eta^2 - eta_b^2) on Omega
+ * (device float [n^dim], x fastest; k0 as given to helm_setup), f >= lo. */
+
+/* Medium from f: eta = sqrt(eta_b^2 + f / k0^2) (0 where the radicand is
+ * negative), then exactly helm_update_n. */
+int helm_update_f(helm_ctx* ctx, const float* f_dev);
+
+/* Data-fidelity gradient with respect to f through Prop. 1:
+ *   grad_f[i] = sum_q Re(conj(u_q,i) lam_q,i) on Omega   (helm_grad_n without the
+ * chain factor 2 k0^2 eta_i); arguments as for helm_grad_n. */
+int helm_grad_f(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                float* grad_f);
+
+/* Residual of the quadratic data term (eq. DataFidelityExplicit) at M on-grid
+ * receivers: res[q][i] = u[q][idx[i]] - y[q][i] for q < B (u: device [B][grid],
+ * y, res: device [B][M]); *loss_host = 1/2 sum |res|^2 (FP64) when non-NULL.
+ * idx (device int [M]) is checked on the host: HELM_EINVAL for an index
+ * outside the grid. */
+int helm_data_residual(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* u, const helm_c32* y,
+                       helm_c32* res, double* loss_host);
+
+/* Proximal operator of eq. proximalOpt with isotropic TV (forward
+ * differences, zero across the last index of each axis) and a lower bound:
+ *   w = argmin_{w >= lo} 1/2 ||w - v||^2 + lam TV(w),
+ * by `iters` steps of fast gradient projection on the dual (the method the
+ * paper names).  v, w: device float [n^dim], must not alias.  lam = 0 or
+ * iters = 0 gives max(v, lo). */
+int helm_tv_prox(helm_ctx* ctx, const float* v_dev, double lam, double lo, int iters, float* w_dev);
+
+/* One update of Alg. 4 (accelerated forward-backward splitting) after its
+ * gradient grad = sum over the selected illuminations of grad_f at fbar:
+ *   f' = prox_{gamma tau}(fbar - gamma grad)  (helm_tv_prox with lower bound lo)
+ *   alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2
+ *   fbar' = f' + (alpha - 1) / alpha' (f' - f)
+ * f and fbar (device float [n^dim]) are updated in place; *alpha_host (>= 1,
+ * 1 at the start) is advanced. */
+int helm_fbs_step(helm_ctx* ctx, float* f_dev, float* fbar_dev, const float* grad_dev, double gamma, double tau,
+                  double lo, int prox_iters, double* alpha_host);
+
+/* ---- sensor operator G~ (eq. DiscreteForward / DiscreteForwardHelm) ----
+ * Sensors outside Omega record the scattered field of the induced source
+ * s = f u (u = u_in + u_sc the total field) through the Lippmann-Schwinger
+ * integral (eq. LSIntegral) with the free-space Green's function (eq. green):
+ *   y_m = sum_{z in Omega} g(x_m - z) f(z) u(z) h^d,
+ *   g(x) = (j/4) H0^(1)(k0 eta_b |x|) in 2D,  e^{j k0 eta_b |x|} / (4 pi |x|) in 3D.
+ * With these sensors the data term of eq. MAPInverse has the gradient (Prop. 1)
+ *   grad_f = sum_q Re(conj(u_q) (s_q + lam_q)),  s_q = G~^H r_q,  lam_q = A^-H (f s_q),
+ * r_q = y_q(f) - y_q^meas: helm_farfield_adjoint gives s_q and f s_q, helm_adjoint_batch
+ * lam_q, helm_grad_f_farfield the sum. */
+
+/* Sensor positions sensors_host[M][dim] (x, y[, z]) in grid cells relative to the
+ * centre of Omega; each must lie at least one cell outside Omega (HELM_EINVAL).
+ * Builds G~ [M][n^dim] on the device (2D: H0^(1) by cubic Hermite interpolation
+ * in a host FP64 table of H0^(1) and H0^(1)' at spacing 1/256 in k_b r). */
+int helm_farfield_set(helm_ctx* ctx, int M, const double* sensors_host);
+/* y[q][m] (device [B][M]) for fields u_in, u_sc (device [B][grid]; u_in may be NULL:
+ * u_sc is then the total field).  HELM_ESTATE without sensors. */
+int helm_farfield(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, helm_c32* y);
+/* s_ext = G~^H r on Omega, 0 in the layer (device [B][grid], overwritten); rhs_ext
+ * (or NULL) = f s_ext, the right-hand side of the adjoint solve. r: device [B][M]. */
+int helm_farfield_adjoint(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* s_ext, helm_c32* rhs_ext);
+/* grad_f[i] = sum_q Re(conj(u_in + u_sc) (lam + s_ext)) on Omega. */
+int helm_grad_f_farfield(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                         const helm_c32* s_ext, float* grad_f);
 
 /* ---- learned preconditioner (not part of the paper's method) ----
  * A 2D convolutional U-Net used as the FGMRES preconditioner in place of the

@@ -7,6 +7,14 @@
                paper's idea (Sec. IV-C: a Krylov method corrects the
                deviations of an MG preconditioner) must also admit a
                nonlinear preconditioner.
+* ``sstep_gmres`` the same GMRES(m) iterates computed in s-step form: per
+               cycle the basis W_0 = r/||r||, W_{j+1} = A M W_j is built
+               without orthogonalisation; its Gram matrix G = W^H W gives a
+               Cholesky factor R (G = R^H R, i.e. W = Q R), and the cycle's
+               least-squares problem min ||r - A M W_{0:m} y|| is
+               min || ||r|| R_00 e_0 - R[:, 1:] y ||, solved here with a
+               library least-squares routine.  In exact arithmetic this is
+               GMRES(m) (the Krylov space and the minimised norm are the same).
 * ``bicgstab`` Alg. 3 of the paper (MG-preconditioned Bi-CGSTAB).  Readings:
                the printed sigma plays the role of van der Vorst's omega, the
                stop test is relative, ||r|| <= eps ||b|| (Sec. VI states
@@ -102,6 +110,58 @@ def fgmres(apply_a, precond, b: np.ndarray, rtol: float = 1e-6, restart: int = 2
         for i in range(k - 1, -1, -1):
             y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
         x = x + (y @ Z[:k]).reshape(b.shape)
+        r = b - apply_a(x)
+        info.restarts += 1
+
+
+def sstep_gmres(apply_a, precond, b: np.ndarray, rtol: float = 1e-6, restart: int = 5, max_iters: int = 2000,
+                x0: np.ndarray | None = None) -> tuple[np.ndarray, SolveInfo]:
+    """GMRES(restart) in s-step form (module doc) until ||b - A x|| <= rtol ||b||.
+
+    Every cycle performs `restart` preconditioner applications (info.iters
+    counts them); the update uses the smallest leading basis whose residual
+    estimate meets the tolerance.  history holds the estimate after each
+    basis size of each cycle.
+    """
+    info = SolveInfo()
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bnorm = _norm(b)
+    if bnorm == 0.0:
+        info.converged, info.rel_res_true = True, 0.0
+        return x, info
+    r = b - apply_a(x) if x0 is not None else b.copy()
+    m = restart
+    while True:
+        beta = _norm(r)
+        info.rel_res_true = beta / bnorm
+        if info.rel_res_true <= rtol:
+            info.converged = True
+            return x, info
+        if info.iters >= max_iters:
+            return x, info
+        W = [r.ravel() / beta]
+        Z = []
+        for _ in range(m):
+            Z.append(precond(W[-1].reshape(b.shape)).ravel())
+            W.append(apply_a(Z[-1].reshape(b.shape)).ravel())
+        Wm = np.array(W)
+        G = Wm.conj() @ Wm.T
+        R = np.linalg.cholesky(G).conj().T  # G = R^H R, R upper triangular
+        info.iters += m
+        k_use = m
+        for k in range(1, m + 1):
+            g = np.zeros(k + 1, dtype=np.complex128)
+            g[0] = beta * R[0, 0]
+            y, *_ = np.linalg.lstsq(R[:k + 1, 1:k + 1], g, rcond=None)
+            est = np.linalg.norm(g - R[:k + 1, 1:k + 1] @ y)
+            info.history.append(est / bnorm)
+            if est <= rtol * bnorm:
+                k_use = k
+                break
+        g = np.zeros(k_use + 1, dtype=np.complex128)
+        g[0] = beta * R[0, 0]
+        y, *_ = np.linalg.lstsq(R[:k_use + 1, 1:k_use + 1], g, rcond=None)
+        x = x + (y @ np.array(Z[:k_use])).reshape(b.shape)
         r = b - apply_a(x)
         info.restarts += 1
 

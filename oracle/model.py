@@ -26,7 +26,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .discretization import Problem, helmholtz_matrix
-from .krylov import fgmres
+from .krylov import bicgstab, fgmres
 from .multigrid import Hierarchy
 
 
@@ -80,6 +80,17 @@ def mg_fgmres_solve(prob: Problem, b: np.ndarray, rtol: float = 1e-6, restart: i
     shape = b.shape
     bs = (prob.h ** 2) * b.ravel()
     x, info = fgmres(lambda v: a_scaled @ v, hier.vcycle, bs, rtol=rtol, restart=restart, max_iters=max_iters)
+    return x.reshape(shape), info
+
+
+def mg_bicgstab_solve(prob: Problem, b: np.ndarray, rtol: float = 1e-6, max_iters: int = 4000,
+                      hierarchy: Hierarchy | None = None):
+    """u = A^-1 b by Alg. 3 (Bi-CGSTAB, one V-cycle on K_kappa per preconditioner application)."""
+    hier = Hierarchy(prob) if hierarchy is None else hierarchy
+    a_scaled = helmholtz_matrix(prob, scaled=True)
+    shape = b.shape
+    bs = (prob.h ** 2) * b.ravel()
+    x, info = bicgstab(lambda v: a_scaled @ v, hier.vcycle, bs, rtol=rtol, max_iters=max_iters)
     return x.reshape(shape), info
 
 

@@ -83,6 +83,22 @@ struct helm_ctx {
   int* d_zero_ints = nullptr;
   float* d_tv_mag = nullptr;   // [n^dim] TV magnitudes
   float* d_tv_part = nullptr;  // per-block TV partial sums
+  double2* d_gram = nullptr;   // [maxB][nblk][(m+1)(m+2)/2] Gram partials of the s-step form
+  // inverse-problem workspace (allocated on first use): FGP dual p and its
+  // extrapolation r [dim][n^dim], primal w, prox input v, index map from f
+  float* d_inv_p = nullptr;
+  float* d_inv_r = nullptr;
+  float* d_inv_w = nullptr;
+  float* d_inv_v = nullptr;
+  float* d_inv_n = nullptr;
+  double* d_inv_part = nullptr;
+  int inv_part_len = 0;
+  // sensor operator G~ [M][n^dim] and its work buffers (helm_farfield_set)
+  int ff_M = 0;
+  c32* d_ffG = nullptr;
+  c32* d_ff_src = nullptr;   // [maxB][n^dim] induced source
+  c32* d_ff_part = nullptr;  // [splits][maxB][M]
+  int ff_active_M = 0;       // sensors of the current set
   int* h_status = nullptr;  // pinned
   int* h_iters = nullptr;
   double* h_relres = nullptr;
@@ -219,9 +235,26 @@ void relax(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet v, int sweep
   }
 }
 
+long long coarse_small(const helm_ctx* c) {
+  return c->coarse_max >= 0 ? c->coarse_max : (c->dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
+}
+
+// True when a zero-guess visit of level l on the level's own (unscaled) buffers
+// runs the fused 2D legs (not the coarsest solve, not the single-launch coarse cycle).
+bool legs_fused(const helm_ctx* c, int l) {
+  if (l >= c->L - 1 || !c->o.fused || c->dim != 2 || c->o.nu1 != 1 || c->o.nu2 != 1) return false;
+  const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
+  const bool single = v_below && l >= 1 && c->o.coarse_single_launch && c->lv[l].N <= coarse_small(c);
+  return !single;
+}
+
 // Alg. 2 on level l for K'_l v = r, result in `out` (which holds the initial
 // guess when zero_guess is false).  Fused 2D legs serve the common case.
-void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act) {
+// With eres.p set (only where legs_fused(l)), the visit starts from the
+// solution eres instead: out = eres + MG(r - K eres, 0), the residual formed
+// inside the legs; out must not alias eres.
+void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act,
+              VecSet eres = VecSet{nullptr, 0}) {
   const int dim = c->dim;
   if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
     ProfScope ps(c, "coarse_solve", 8.0 * c->Nc * c->Nc + c->prof_B * 16.0 * c->Nc);
@@ -234,9 +267,9 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const int gamma = c->o.cycle == 3 ? (l == 0 ? 2 : 1) : c->o.cycle;
   const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
   const bool vcycle11 = c->o.fused && zero_guess && v_below && c->o.nu1 == 1 && c->o.nu2 == 1;
-  const long long small = c->coarse_max >= 0 ? c->coarse_max : (dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
+  const long long small = coarse_small(c);
   if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr && r.stride == fine.N &&
-      out.stride == fine.N) {
+      out.stride == fine.N && eres.p == nullptr) {
     // levels l .. L-1 in one launch, one workgroup per right-hand side
     CoarseCycleArgs a{};
     a.dim = dim;
@@ -262,7 +295,11 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const float om = (float)c->o.omega_jac;
   const bool fused = c->o.fused && dim == 2 && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
   const double Nf = (double)fine.N, Nc1 = (double)crs.N, Bp = c->prof_B;
-  if (fused) {
+  if (eres.p && !fused) throw HipError{hipErrorInvalidValue, "repeated visit outside the fused legs"};
+  if (fused && eres.p) {
+    ProfScope ps(c, lvl_name("down_fused_res", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 16.0 * Nf);
+    launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act, c->tune_down[l], eres);
+  } else if (fused) {
     ProfScope ps(c, lvl_name("down_fused", l), Bp * 8.0 * (Nf + Nc1) + 8.0 * Nf);
     launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act, c->tune_down[l]);
   } else {
@@ -281,6 +318,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
   }
   const bool next_is_coarsest = (l + 1 == c->L - 1);
+  VecSet ecur = ec;  // the coarse solution after the visits so far (e or d of level l + 1)
   for (int cyc = 0; cyc < gamma; ++cyc) {
     if (cyc == 0) {
       mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, true, act);
@@ -288,22 +326,31 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     }
     if (next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
     // repeated visit from the current e: MG(rc, e) = e + MG(rc - K e, 0)
-    VecSet rr{crs.rr, crs.N}, dd{crs.d, crs.N};
+    VecSet other{ecur.p == crs.e ? crs.d : crs.e, crs.N};
+    if (legs_fused(c, l + 1)) {
+      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, other, true, act, ecur);
+      ecur = other;
+      continue;
+    }
+    VecSet rr{crs.rr, crs.N};
     {
       ProfScope ps(c, lvl_name("level_residual", l + 1), Bp * 24.0 * Nc1 + 8.0 * Nc1);
-      launch_level_residual(c->s, dim, B, rc, ec, level_K(c, l + 1), rr, act);
+      launch_level_residual(c->s, dim, B, rc, ecur, level_K(c, l + 1), rr, act);
     }
-    mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, dd, true, act);
+    mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, other, true, act);
     ProfScope ps(c, lvl_name("add", l + 1), Bp * 24.0 * Nc1);
-    launch_add(c->s, B, dd, ec, crs.N, act);
+    launch_add(c->s, B, other, ecur, crs.N, act);
   }
-  if (fused) {
+  if (fused && eres.p) {
+    ProfScope ps(c, lvl_name("up_fused_res", l), Bp * 8.0 * (3.0 * Nf + Nc1) + 16.0 * Nf);
+    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l], eres);
+  } else if (fused) {
     ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
-    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ec, crs.n, out, act, c->tune_up[l]);
+    launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l]);
   } else {
     {
       ProfScope ps(c, lvl_name("prolong_add", l), Bp * (16.0 * Nf + 8.0 * Nc1));
-      launch_prolong_add(c->s, dim, B, ec, crs.n, out, fine.n, act);
+      launch_prolong_add(c->s, dim, B, ecur, crs.n, out, fine.n, act);
     }
     relax(c, B, l, r, rs, out, c->o.nu2, act);
   }
@@ -377,20 +424,92 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
   launch_givens(c->s, B, k, j);
 }
 
+bool use_bicg(const helm_ctx* c) { return c->o.krylov == HELM_KRYLOV_BICGSTAB && c->net == nullptr; }
+
 void true_residual(helm_ctx* c, int B, int first, int conj_rhs) {
   KrylovArgs& k = c->k;
+  k.bicg = use_bicg(c) ? 1 : 0;
   {
     ProfScope ps(c, "residual_ff", c->prof_B * (first ? 16.0 : 32.0) * c->N0 + (first ? 0.0 : 16.0 * c->N0));
     launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_chi, c->d_clo,
                        c->g0_hi, c->g0_lo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
   }
   ProfScope ps(c, "finalize", c->prof_B * k.nblk * 4.0);
-  launch_finalize(c->s, B, k, first);
+  if (k.bicg) launch_bicg_finalize(c->s, B, k, first);
+  else launch_finalize(c->s, B, k, first);
 }
 
-// The body of one restart cycle: m Arnoldi steps, x update, true residual, decision.
+// `restart` Bi-CGSTAB iterations (Alg. 3), two multigrid cycles each; the
+// solution is updated inside the iteration.
+void bicg_iterations(helm_ctx* c, int B) {
+  KrylovArgs& k = c->k;
+  const long long N0 = c->N0;
+  const LevelArgs A = fine_A(c);
+  const double Bp = c->prof_B, N = (double)N0;
+  const long long vst = (long long)(k.m + 1) * N0, zst = (long long)k.m * N0;
+  for (int it = 0; it < k.m; ++it) {
+    {
+      ProfScope ps(c, "bicg_dir", Bp * 32.0 * N);
+      launch_bicg_dir(c->s, B, k);
+    }
+    mg_cycle(c, B, 0, VecSet{k.V + 2 * N0, vst}, ScaleSet{nullptr, 0}, VecSet{k.Z, zst}, true, k.active);
+    {
+      ProfScope ps(c, "bicg_apply", Bp * 24.0 * N + 8.0 * N);
+      launch_bicg_apply(c->s, B, k, 0, 3, A, 0);
+    }
+    launch_bicg_alpha(c->s, B, k);
+    {
+      ProfScope ps(c, "bicg_s", Bp * 24.0 * N);
+      launch_bicg_s(c->s, B, k);
+    }
+    mg_cycle(c, B, 0, VecSet{k.V, vst}, ScaleSet{nullptr, 0}, VecSet{k.Z + N0, zst}, true, k.active);
+    {
+      ProfScope ps(c, "bicg_apply", Bp * 24.0 * N + 8.0 * N);
+      launch_bicg_apply(c->s, B, k, 1, 4, A, 1);
+    }
+    launch_bicg_sigma(c->s, B, k);
+    {
+      ProfScope ps(c, "bicg_update", Bp * 72.0 * N);
+      launch_bicg_update(c->s, B, k, c->d_xhi, c->d_xlo);
+    }
+    launch_bicg_rho(c->s, B, k);
+  }
+}
+
+// One cycle of GMRES(m) in s-step form: m multigrid cycles and matvecs build
+// the basis, one Gram pass and a per-RHS Cholesky-QR least squares replace
+// the Arnoldi orthogonalisation.
+void sstep_basis(helm_ctx* c, int B) {
+  KrylovArgs& k = c->k;
+  const long long N0 = c->N0;
+  const LevelArgs A = fine_A(c);
+  const double Bp = c->prof_B, N = (double)N0;
+  for (int j = 0; j < k.m; ++j) {
+    VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
+    VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
+    mg_cycle(c, B, 0, vj, ScaleSet{k.vs + j, k.m + 1}, zj, true, k.active);
+    if (j + 1 < k.m) {
+      ProfScope ps(c, "sstep_matvec", Bp * 16.0 * N + 8.0 * N);
+      launch_sstep_matvec(c->s, B, k, j, A);
+    }
+  }
+  ProfScope ps(c, "sstep_gram", Bp * 8.0 * (k.m + 1.0) * N + 8.0 * N);
+  launch_sstep_gram_solve(c->s, B, k, A, c->d_gram);
+}
+
+bool use_sstep(const helm_ctx* c) { return c->o.krylov == HELM_KRYLOV_SSTEP && c->net == nullptr; }
+
+// The body of one restart cycle: m Arnoldi steps (or the s-step basis and its
+// least squares), x update, true residual, decision.
 void restart_cycle(helm_ctx* c, int B, int conj_rhs) {
-  for (int j = 0; j < c->k.m; ++j) arnoldi_step(c, B, j);
+  if (use_bicg(c)) {
+    bicg_iterations(c, B);
+    true_residual(c, B, 0, conj_rhs);
+    return;
+  }
+  if (use_sstep(c)) sstep_basis(c, B);
+  else
+    for (int j = 0; j < c->k.m; ++j) arnoldi_step(c, B, j);
   {
     ProfScope ps(c, "x_update", c->prof_B * (8.0 * c->k.m + 32.0) * c->N0);
     launch_x_update(c->s, B, c->k, c->d_xhi, c->d_xlo);
@@ -675,6 +794,7 @@ void helm_default_opts(helm_opts* o) {
   o->fused = 1;
   o->use_graph = 1;
   o->coarse_single_launch = 1;
+  o->krylov = HELM_KRYLOV_SSTEP;
 }
 
 int helm_extended_size(int n, int abl_width, int levels) { return helm_host::extended_size(n, abl_width, levels); }
@@ -692,6 +812,12 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
   if (opts) o = *opts;
   if (o.levels < 2 || o.levels > 12) return fail(nullptr, HELM_EINVAL, "levels must be in [2, 12]");
   if (o.restart < 1 || o.restart > krylov_max_restart()) return fail(nullptr, HELM_EINVAL, "restart must be in [1, 64]");
+  if (o.krylov != HELM_KRYLOV_FGMRES && o.krylov != HELM_KRYLOV_SSTEP && o.krylov != HELM_KRYLOV_BICGSTAB)
+    return fail(nullptr, HELM_EINVAL, "krylov must be HELM_KRYLOV_FGMRES, _SSTEP or _BICGSTAB");
+  if (o.krylov == HELM_KRYLOV_BICGSTAB && o.restart < 4)
+    return fail(nullptr, HELM_EINVAL, "Bi-CGSTAB takes restart >= 4 (iterations per status check)");
+  if (o.krylov == HELM_KRYLOV_SSTEP && o.restart > sstep_max_restart())
+    return fail(nullptr, HELM_EINVAL, "the s-step form takes restart <= 12");
   if (o.max_batch < 1 || o.nu1 < 0 || o.nu2 < 0 || o.cycle < 1 || o.cycle > 3 || o.max_iters < 1 || !(o.rtol > 0))
     return fail(nullptr, HELM_EINVAL, "bad solver options");
   helm_abl a{0.15, 1, 0};
@@ -782,6 +908,8 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     k.g = c->alloc<double2>((size_t)maxB * (m + 1));
     k.coef = c->alloc<c32>((size_t)maxB * (m + 1));
     k.y = c->alloc<c32>((size_t)maxB * m);
+    if (o.krylov == HELM_KRYLOV_SSTEP)
+      c->d_gram = c->alloc<double2>((size_t)maxB * k.nblk * sstep_gram_entries(m));
     k.active = c->alloc<int>(maxB);
     k.status = c->alloc<int>(maxB);
     k.jcount = c->alloc<int>(maxB);
@@ -1161,6 +1289,198 @@ int helm_tv(helm_ctx* c, const float* n_map, double eps, double scale, float* gr
     *value = v;
   }
   HELM_GUARD_END("tv")
+}
+
+// ---------------------------------------------------------------- inverse problem (Sec. V, Alg. 4)
+namespace {
+void inv_reserve(helm_ctx* c) {
+  if (c->d_inv_p) return;
+  const long long Ni = npts(c->n, c->dim);
+  c->d_inv_p = c->alloc<float>((size_t)c->dim * Ni);
+  c->d_inv_r = c->alloc<float>((size_t)c->dim * Ni);
+  c->d_inv_w = c->alloc<float>(Ni);
+  c->d_inv_v = c->alloc<float>(Ni);
+  c->d_inv_n = c->alloc<float>(Ni);
+}
+}  // namespace
+
+int helm_update_f(helm_ctx* c, const float* f_dev) {
+  if (!c || !f_dev) return fail(c, HELM_EINVAL, "null argument");
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    inv_reserve(c);
+    launch_index_from_f(c->s, npts(c->n, c->dim), f_dev, 1.0 / (c->k0 * c->k0), c->o.n_b * c->o.n_b, c->d_inv_n);
+    check(hipGetLastError(), "index_from_f");
+    check(hipStreamSynchronize(c->s), "sync");
+    upload_medium(c, c->d_inv_n);
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  } catch (const std::bad_alloc&) {
+    return fail(c, HELM_ENOMEM, "out of host memory");
+  }
+  return HELM_OK;
+}
+
+int helm_grad_f(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam, float* grad_f) {
+  if (!c || !u_sc || !lam || !grad_f) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
+  HELM_GUARD_BEGIN
+  launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_in, (const c32*)u_sc, (const c32*)lam, nullptr,
+                1.0f, grad_f);
+  HELM_GUARD_END("grad_f")
+}
+
+int helm_data_residual(helm_ctx* c, int B, int M, const int* idx_dev, const helm_c32* u, const helm_c32* y,
+                       helm_c32* res, double* loss_host) {
+  if (!c || !idx_dev || !u || !y || !res) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1 || M < 1) return fail(c, HELM_EINVAL, "B and M must be >= 1");
+  HELM_GUARD_BEGIN
+  std::vector<int> idx(M);
+  check(hipMemcpy(idx.data(), idx_dev, (size_t)M * sizeof(int), hipMemcpyDeviceToHost), "copy idx");
+  for (int i : idx)
+    if (i < 0 || (long long)i >= c->N0) return fail(c, HELM_EINVAL, "receiver index outside the grid");
+  const int nbk = data_residual_blocks(B, M);
+  if (nbk > c->inv_part_len) {
+    c->d_inv_part = c->alloc<double>(nbk);
+    c->inv_part_len = nbk;
+  }
+  launch_data_residual(c->s, B, M, c->N0, idx_dev, (const c32*)u, (const c32*)y, (c32*)res, c->d_inv_part);
+  if (loss_host) {
+    std::vector<double> part(nbk);
+    check(hipMemcpyAsync(part.data(), c->d_inv_part, nbk * sizeof(double), hipMemcpyDeviceToHost, c->s), "loss");
+    check(hipStreamSynchronize(c->s), "sync");
+    double sum = 0.0;
+    for (double v : part) sum += v;
+    *loss_host = 0.5 * sum;
+  }
+  HELM_GUARD_END("data_residual")
+}
+
+int helm_tv_prox(helm_ctx* c, const float* v_dev, double lam, double lo, int iters, float* w_dev) {
+  if (!c || !v_dev || !w_dev) return fail(c, HELM_EINVAL, "null argument");
+  if (iters < 0 || !(lam >= 0.0) || !std::isfinite(lam)) return fail(c, HELM_EINVAL, "bad lam or iters");
+  HELM_GUARD_BEGIN
+  inv_reserve(c);
+  launch_tv_prox(c->s, c->dim, c->n, v_dev, (float)lam, (float)lo, iters, c->d_inv_p, c->d_inv_r, c->d_inv_w);
+  check(hipMemcpyAsync(w_dev, c->d_inv_w, (size_t)npts(c->n, c->dim) * sizeof(float), hipMemcpyDeviceToDevice, c->s),
+        "copy w");
+  HELM_GUARD_END("tv_prox")
+}
+
+int helm_fbs_step(helm_ctx* c, float* f_dev, float* fbar_dev, const float* grad_dev, double gamma, double tau,
+                  double lo, int prox_iters, double* alpha_host) {
+  if (!c || !f_dev || !fbar_dev || !grad_dev || !alpha_host) return fail(c, HELM_EINVAL, "null argument");
+  if (!(gamma > 0.0) || !(tau >= 0.0) || prox_iters < 0 || !(*alpha_host >= 1.0))
+    return fail(c, HELM_EINVAL, "bad gamma, tau, prox_iters or alpha");
+  HELM_GUARD_BEGIN
+  inv_reserve(c);
+  const long long Ni = npts(c->n, c->dim);
+  launch_axmy(c->s, Ni, fbar_dev, (float)gamma, grad_dev, c->d_inv_v);
+  launch_tv_prox(c->s, c->dim, c->n, c->d_inv_v, (float)(gamma * tau), (float)lo, prox_iters, c->d_inv_p, c->d_inv_r,
+                 c->d_inv_w);
+  const double a = *alpha_host, an = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * a * a));
+  launch_fbs_momentum(c->s, Ni, c->d_inv_w, (float)((a - 1.0) / an), f_dev, fbar_dev);
+  *alpha_host = an;
+  HELM_GUARD_END("fbs_step")
+}
+
+// ---------------------------------------------------------------- sensor operator (eq. DiscreteForwardHelm)
+int helm_farfield_set(helm_ctx* c, int M, const double* sensors_host) {
+  if (!c || !sensors_host || M < 1) return fail(c, HELM_EINVAL, "bad argument");
+  const int dim = c->dim;
+  const double half = 0.5 * (c->n - 1);
+  double rmin = 1e300, rmax = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double d2 = 0.0, far2 = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      const double x = sensors_host[m * dim + a];
+      if (!std::isfinite(x)) return fail(c, HELM_EINVAL, "non-finite sensor coordinate");
+      const double out = std::fabs(x) - half;
+      if (out > 0) d2 += out * out;
+      far2 += (std::fabs(x) + half) * (std::fabs(x) + half);
+    }
+    if (d2 < 1.0) return fail(c, HELM_EINVAL, "a sensor lies within one cell of Omega");
+    rmin = std::min(rmin, std::sqrt(d2));
+    rmax = std::max(rmax, std::sqrt(far2));
+  }
+  HELM_GUARD_BEGIN
+  const long long Ni = npts(c->n, dim);
+  if (M > c->ff_M) {
+    c->d_ffG = c->alloc<c32>((size_t)M * Ni);
+    c->d_ff_part = c->alloc<c32>((size_t)ff_splits(Ni) * c->o.max_batch * M);
+    c->ff_M = M;
+  }
+  if (!c->d_ff_src) c->d_ff_src = c->alloc<c32>((size_t)c->o.max_batch * Ni);
+  // 2D: table of H0^(1) and its derivative -H1^(1) (FP64, host) on the argument range
+  std::vector<double2> tab;
+  double x0 = 0.0, dx = 1.0;
+  int ntab = 2;
+  if (dim == 2) {
+    dx = 1.0 / 256.0;
+    x0 = std::max(1e-3, c->kbh * rmin - 4 * dx);
+    ntab = (int)std::ceil((c->kbh * rmax + 4 * dx - x0) / dx) + 2;
+    tab.resize(2 * (size_t)ntab);
+    for (int k = 0; k < ntab; ++k) {
+      const double x = x0 + k * dx;
+      tab[2 * k] = make_double2(std::cyl_bessel_j(0.0, x), std::cyl_neumann(0.0, x));
+      tab[2 * k + 1] = make_double2(-std::cyl_bessel_j(1.0, x), -std::cyl_neumann(1.0, x));
+    }
+  } else {
+    tab.assign(4, make_double2(0.0, 0.0));
+  }
+  void* d_tab = nullptr;
+  void* d_sens = nullptr;
+  check(hipMalloc(&d_tab, tab.size() * sizeof(double2)), "hipMalloc");
+  if (hipMalloc(&d_sens, (size_t)M * dim * sizeof(double)) != hipSuccess) {
+    hipFree(d_tab);
+    throw HipError{hipErrorOutOfMemory, "hipMalloc"};
+  }
+  hipError_t e = hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_sens, sensors_host, (size_t)M * dim * sizeof(double), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) {
+    launch_ff_matrix(c->s, dim, c->n, M, (const double*)d_sens, c->kbh, c->h, (const double2*)d_tab, x0, dx, ntab,
+                     c->d_ffG);
+    e = hipStreamSynchronize(c->s);
+  }
+  hipFree(d_tab);
+  hipFree(d_sens);
+  check(e, "farfield matrix");
+  c->ff_M = std::max(c->ff_M, M);
+  c->ff_active_M = M;
+  HELM_GUARD_END("farfield_set")
+}
+
+int helm_farfield(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, helm_c32* y) {
+  if (!c || !u_sc || !y) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
+  if (!c->ff_active_M) return fail(c, HELM_ESTATE, "no sensors: call helm_farfield_set first");
+  HELM_GUARD_BEGIN
+  launch_ff_forward(c->s, c->dim, B, c->ff_active_M, c->ne, c->w, c->n, c->d_f, (const c32*)u_in, (const c32*)u_sc,
+                    c->d_ffG, c->d_ff_src, c->d_ff_part, (c32*)y);
+  HELM_GUARD_END("farfield")
+}
+
+int helm_farfield_adjoint(helm_ctx* c, int B, const helm_c32* r, helm_c32* s_ext, helm_c32* rhs_ext) {
+  if (!c || !r || !s_ext) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
+  if (!c->ff_active_M) return fail(c, HELM_ESTATE, "no sensors: call helm_farfield_set first");
+  HELM_GUARD_BEGIN
+  launch_zero(c->s, (long long)B * c->N0, (c32*)s_ext);
+  if (rhs_ext) launch_zero(c->s, (long long)B * c->N0, (c32*)rhs_ext);
+  launch_ff_adjoint(c->s, c->dim, B, c->ff_active_M, c->ne, c->w, c->n, c->d_ffG, (const c32*)r, c->d_f, (c32*)s_ext,
+                    (c32*)rhs_ext);
+  HELM_GUARD_END("farfield_adjoint")
+}
+
+int helm_grad_f_farfield(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                         const helm_c32* s_ext, float* grad_f) {
+  if (!c || !u_sc || !lam || !s_ext || !grad_f) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
+  HELM_GUARD_BEGIN
+  launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_in, (const c32*)u_sc, (const c32*)lam, nullptr,
+                1.0f, grad_f, (const c32*)s_ext);
+  HELM_GUARD_END("grad_f_farfield")
 }
 
 const char* helm_last_error(const helm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }

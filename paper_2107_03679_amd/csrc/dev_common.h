@@ -10,6 +10,32 @@
 
 #define HELM_WAVE 64
 
+// ------------------------------------------------------- workgroup order
+// gfx950 hands out the workgroups of a launch round-robin over its 8 XCDs,
+// each with a private L2.  xcd_tile() turns the hardware workgroup id into a
+// logical (right-hand side, tile) such that every XCD walks one contiguous
+// stretch of the order "groups of g right-hand sides; tiles in raster order;
+// the right-hand sides of a group fastest".  Neighbouring tiles of one field
+// (whose halos overlap) and one tile of g fields (which share the coefficient
+// tile) then run close together in time on the same L2.  Bijective on
+// [0, B T) for any B, T >= 1 and g >= 1.
+#define HELM_XCDS 8u
+struct TileId {
+  int b, t;
+};
+__host__ __device__ __forceinline__ TileId xcd_tile(unsigned id, unsigned B, unsigned T, unsigned g) {
+  const unsigned G = B * T, q = G / HELM_XCDS, r = G % HELM_XCDS, x = id % HELM_XCDS;
+  const unsigned l = x * q + (x < r ? x : r) + id / HELM_XCDS;
+  const unsigned span = g * T, grp = l / span, rem = l - grp * span;
+  const unsigned gs = B - grp * g < g ? B - grp * g : g;
+  TileId o;
+  o.b = (int)(grp * g + rem % gs);
+  o.t = (int)(rem / gs);
+  return o;
+}
+// right-hand sides per group in xcd_tile() for the field kernels
+#define HELM_RHS_GROUP 4u
+
 
 // ---------------------------------------------------------------- complex64
 __host__ __device__ __forceinline__ c32 cadd(c32 a, c32 b) { return make_float2(a.x + b.x, a.y + b.y); }

@@ -115,8 +115,126 @@ __global__ __launch_bounds__(CC_NT) void k_coarse_cycle(CoarseCycleArgs a) {
   }
 }
 
+// The same cycle with every level's right-hand side, solution and scratch in
+// LDS (dynamic shared memory, laid out level after level, then CC_NT
+// reduction slots): the input right-hand side is read once and the solution
+// written once; every other access of the cycle stays on the CU.  Used when
+// the levels fit (see coarse_cycle_lds_bytes).
+__global__ __launch_bounds__(CC_NT) void k_coarse_cycle_lds(CoarseCycleArgs a) {
+  extern __shared__ c32 lds[];
+  const int b = blockIdx.x;
+  if (a.active && !a.active[b]) return;
+  const int dim = a.dim;
+  const float om = a.omega;
+  c32* R[HELM_MAX_LEVELS];
+  c32* E[HELM_MAX_LEVELS];
+  c32* T[HELM_MAX_LEVELS];
+  {
+    c32* q = lds;
+    for (int l = a.lp; l < a.L; ++l) {
+      const int N = (int)a.lv[l].N;
+      R[l] = q;
+      E[l] = q + N;
+      T[l] = q + 2 * N;
+      q += (l < a.L - 1 ? 3 : 2) * N;
+    }
+    T[a.L - 1] = q;  // reduction slots of the coarsest solve
+  }
+  {
+    const CoarseLevel& F = a.lv[a.lp];
+    const c32* rg = F.rc + (long long)b * F.N;
+    for (int p = threadIdx.x; p < F.N; p += CC_NT) R[a.lp][p] = rg[p];
+  }
+  __syncthreads();
+  // ---- down ----
+  for (int l = a.lp; l < a.L - 1; ++l) {
+    const CoarseLevel& F = a.lv[l];
+    const CoarseLevel& C = a.lv[l + 1];
+    const int Nf = (int)F.N, Ncl = (int)C.N;
+    c32 *r = R[l], *e = E[l], *t = T[l];
+    for (int p = threadIdx.x; p < Nf; p += CC_NT) e[p] = cmul(F.wd[p], r[p]);
+    __syncthreads();
+    for (int p = threadIdx.x; p < Nf; p += CC_NT) {
+      const Coord c = coord_of32((unsigned)p, (unsigned)F.n, dim);
+      t[p] = cadd(cscale(r[p], 1.0f - om), neighbour_sum(e, p, c, F.n, dim));
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Ncl; q += CC_NT) {
+      const Coord cq = coord_of32((unsigned)q, (unsigned)C.n, dim);
+      R[l + 1][q] = fw4(t, cq, F.n, dim);
+    }
+    __syncthreads();
+  }
+  // ---- coarsest: e = M r, rows split over thread groups, partial sums reduced in LDS ----
+  {
+    const int Nc = (int)a.lv[a.L - 1].N;
+    const c32* r = R[a.L - 1];
+    c32* e = E[a.L - 1];
+    c32* red = T[a.L - 1];
+    const int groups = max(1, CC_NT / max(Nc, 1));
+    for (int row0 = 0; row0 < Nc; row0 += CC_NT / groups) {
+      const int rows = min(CC_NT / groups, Nc - row0);
+      const int g = threadIdx.x / (CC_NT / groups), rr = threadIdx.x % (CC_NT / groups);
+      c32 acc = make_float2(0.f, 0.f);
+      if (g < groups && rr < rows) {
+        for (int k = g; k < Nc; k += groups) acc = cfma(a.minvT[(long long)k * Nc + row0 + rr], r[k], acc);
+      }
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      if (threadIdx.x < rows) {
+        c32 s2 = make_float2(0.f, 0.f);
+        for (int q = 0; q < groups; ++q) s2 = cadd(s2, red[q * (CC_NT / groups) + threadIdx.x]);
+        e[row0 + threadIdx.x] = s2;
+      }
+      __syncthreads();
+    }
+    if (a.lp == a.L - 1) {  // the coarsest level alone
+      c32* eg = a.lv[a.lp].e + (long long)b * Nc;
+      for (int p = threadIdx.x; p < Nc; p += CC_NT) eg[p] = e[p];
+    }
+  }
+  // ---- up ----
+  for (int l = a.L - 2; l >= a.lp; --l) {
+    const CoarseLevel& F = a.lv[l];
+    const CoarseLevel& C = a.lv[l + 1];
+    const int Nf = (int)F.N;
+    c32 *r = R[l], *e = E[l], *t = T[l];
+    const c32* ec = E[l + 1];
+    for (int p = threadIdx.x; p < Nf; p += CC_NT) {
+      const Coord c = coord_of32((unsigned)p, (unsigned)F.n, dim);
+      t[p] = cadd(e[p], prolong_at(ec, c, C.n, dim));
+    }
+    __syncthreads();
+    if (l == a.lp) {
+      c32* eg = F.e + (long long)b * F.N;
+      for (int p = threadIdx.x; p < Nf; p += CC_NT) {
+        const Coord c = coord_of32((unsigned)p, (unsigned)F.n, dim);
+        eg[p] = cadd(cscale(t[p], 1.0f - om), cmul(F.wd[p], cadd(r[p], neighbour_sum(t, p, c, F.n, dim))));
+      }
+    } else {
+      for (int p = threadIdx.x; p < Nf; p += CC_NT) {
+        const Coord c = coord_of32((unsigned)p, (unsigned)F.n, dim);
+        e[p] = cadd(cscale(t[p], 1.0f - om), cmul(F.wd[p], cadd(r[p], neighbour_sum(t, p, c, F.n, dim))));
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
+// LDS bytes k_coarse_cycle_lds needs for levels lp .. L-1 (r, e, t per level,
+// r, e on the coarsest, CC_NT reduction slots)
+size_t coarse_cycle_lds_bytes(const CoarseCycleArgs& a) {
+  size_t n = CC_NT;
+  for (int l = a.lp; l < a.L; ++l) n += (size_t)(l < a.L - 1 ? 3 : 2) * (size_t)a.lv[l].N;
+  return n * sizeof(c32);
+}
+
 void launch_coarse_cycle(hipStream_t s, int B, const CoarseCycleArgs& a) {
-  hipLaunchKernelGGL(k_coarse_cycle, dim3(B), dim3(CC_NT), 0, s, a);
+  const size_t lds = coarse_cycle_lds_bytes(a);
+  if (lds <= kCoarseCycleMaxLds)
+    hipLaunchKernelGGL(k_coarse_cycle_lds, dim3(B), dim3(CC_NT), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_coarse_cycle, dim3(B), dim3(CC_NT), 0, s, a);
 }

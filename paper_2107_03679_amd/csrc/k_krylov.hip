@@ -22,6 +22,7 @@ constexpr int PPT = 8;        // points per thread
 constexpr int CH = NT * PPT;  // points per block
 constexpr int NWAVE = NT / HELM_WAVE;
 constexpr int MAXM = 64;
+constexpr int SSTEP_MAXM = 12;  // longest s-step cycle (the Gram matrix lives in registers)
 constexpr int VCH = 4;        // basis vectors streamed together
 
 __device__ __forceinline__ long long vidx(const KrylovArgs& k, int b, int i) {
@@ -32,10 +33,12 @@ __device__ __forceinline__ long long zidx(const KrylovArgs& k, int b, int i) {
 }
 
 
-__global__ __launch_bounds__(NT) void k_arnoldi_dots(KrylovArgs k, int j, LevelArgs fine, int with_matvec) {
+__global__ __launch_bounds__(NT) void k_arnoldi_dots(int nrhs, KrylovArgs k, int j, LevelArgs fine,
+                                                    int with_matvec) {
   __shared__ c32 red[NWAVE][MAXM + 1];
-  const int b = blockIdx.x;  // right-hand side fastest: the coefficient chunk is shared in L2
-  const int blk = blockIdx.y;
+  // consecutive chunks of one field share stencil rows, one chunk of a group shares the coefficient
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
+  const int b = id.b, blk = id.t;
   if (!k.active[b]) return;
   const long long p0 = (long long)blk * CH + threadIdx.x;
   c32* w_out = k.V + vidx(k, b, j + 1);
@@ -300,11 +303,11 @@ __global__ __launch_bounds__(NT) void k_x_update(KrylovArgs k, c32* x_hi, c32* x
   }
 }
 
-__global__ __launch_bounds__(NT) void k_residual_ff(KrylovArgs k, FFArgs a) {
+__global__ __launch_bounds__(NT) void k_residual_ff(int nrhs, KrylovArgs k, FFArgs a) {
   __shared__ float red[NWAVE];
-  const int b = blockIdx.x;  // right-hand side fastest: the coefficient chunk is shared in L2
-  const int blk = blockIdx.y;
-  if (k.status && k.status[b] != HELM_RUNNING) return;
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
+  const int b = id.b, blk = id.t;
+  if (k.status && (k.status[b] != HELM_RUNNING || (k.bicg && k.active[b]))) return;
   const long long p0 = (long long)blk * CH + threadIdx.x;
   const int n = k.n, dim = k.dim;
   const c32* rb = a.rhs + (long long)b * a.rhs_stride;
@@ -435,9 +438,215 @@ __global__ __launch_bounds__(HELM_WAVE) void k_finalize(KrylovArgs k, int first)
   }
   k.active[b] = 1;
   k.vs[b * (k.m + 1)] = (float)(1.0 / rn);
+  // the s-step basis W_1..W_m is used unscaled (the Arnoldi steps overwrite these)
+  for (int i = 1; i <= k.m; ++i) k.vs[b * (k.m + 1) + i] = 1.0f;
   double2* g = k.g + (long long)b * (k.m + 1);
   g[0] = make_double2(rn, 0.0);
   for (int i = 1; i <= k.m; ++i) g[i] = make_double2(0.0, 0.0);
+}
+
+// ------------------------------------------------------------ s-step GMRES
+// GMRES(m) with the same right preconditioner, written in s-step form: the
+// basis of the Krylov space of A M is built without orthogonalisation,
+//   W_0 = r / ||r||,  Z_j = M(W_j),  W_{j+1} = A Z_j   (j = 0 .. m-1),
+// then the Gram matrix G = W^H W (one pass) gives W = Q R by Cholesky
+// (G = R^H R) and the least-squares problem min ||r - sum_j y_j A Z_j|| becomes
+// min || ||r|| R_00 e_0 - R[:, 1:] y || with R[:, 1:] upper Hessenberg, solved
+// by the same Givens rotations as the Arnoldi form.  In exact arithmetic the
+// iterates are those of GMRES(m); the basis is never orthogonalised, so a
+// step costs one matvec (16 B per point) instead of two passes over the basis.
+
+// W_{j+1} = A Z_j
+__global__ __launch_bounds__(NT) void k_sstep_matvec(int nrhs, KrylovArgs k, int j, LevelArgs fine) {
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
+  const int b = id.b, blk = id.t;
+  if (!k.active[b]) return;
+  const long long p0 = (long long)blk * CH + threadIdx.x;
+  const c32* z = k.Z + zidx(k, b, j);
+  c32* w = k.V + vidx(k, b, j + 1);
+  Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p < k.N) w[p] = stencil_point(z, p, c, fine.n, k.dim, diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim));
+    coord_advance(c, NT, fine.n, k.dim);
+  }
+}
+
+// Block partials of the Gram matrix of (s_0 W_0, W_1, .., W_{M-1}, A Z_{M-1}):
+// the last basis vector is formed in registers and never stored.  Entry
+// (i, j), i <= j, in packed upper order, is sum conj(w_i) w_j, accumulated in
+// FP64 from the first product: the basis is far from orthogonal (condition
+// numbers up to ~1e6 at m = 12) and the Cholesky factor of G loses the
+// square of that, so G must be the Gram matrix of the stored vectors to
+// FP64 accuracy.
+template <int M>
+__global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, LevelArgs fine, double2* part) {
+  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
+  __shared__ double2 red[NWAVE][NE];
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
+  const int b = id.b, blk = id.t;
+  if (!k.active[b]) return;
+  const float s0 = k.vs[b * (k.m + 1)];
+  const long long p0 = (long long)blk * CH + threadIdx.x;
+  const c32* z = k.Z + zidx(k, b, M - 1);
+  double2 acc[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) acc[e] = make_double2(0.0, 0.0);
+  Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
+  for (int t = 0; t < PPT; ++t) {
+    const long long p = p0 + (long long)t * NT;
+    if (p < k.N) {
+      c32 w[NV];
+#pragma unroll
+      for (int i = 0; i < M; ++i) w[i] = k.V[vidx(k, b, i) + p];
+      w[0] = cscale(w[0], s0);
+      w[M] = stencil_point(z, p, c, fine.n, k.dim, diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim));
+      double2 wd[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) wd[i] = make_double2((double)w[i].x, (double)w[i].y);
+      int e = 0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = i; j < NV; ++j, ++e) {
+          acc[e].x = fma(wd[i].x, wd[j].x, fma(wd[i].y, wd[j].y, acc[e].x));
+          acc[e].y = fma(wd[i].x, wd[j].y, fma(-wd[i].y, wd[j].x, acc[e].y));
+        }
+    }
+    coord_advance(c, NT, fine.n, k.dim);
+  }
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const double sx = wave_sum_d(acc[e].x), sy = wave_sum_d(acc[e].y);
+    if (lane == 0) red[wave][e] = make_double2(sx, sy);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NE; e += NT) {
+    double2 sum = red[0][e];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) sum = make_double2(sum.x + red[q][e].x, sum.y + red[q][e].y);
+    part[((long long)b * k.nblk + blk) * NE + e] = sum;
+  }
+}
+
+// Per right-hand side (one wavefront): reduce the Gram partials (FP64, fixed
+// order), Cholesky G = R^H R, Givens rotations of the Hessenberg R[:, 1:],
+// the residual estimate of every leading size, and the least-squares solution
+// for the smallest size that meets the inner tolerance (else all usable
+// columns).  A column whose Cholesky pivot vanishes (the Krylov space is
+// exhausted to working precision) ends the usable basis there.
+template <int M>
+__global__ __launch_bounds__(HELM_WAVE) void k_sstep_solve(KrylovArgs k, const double2* part) {
+  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
+  __shared__ double2 G[NE];
+  const int b = blockIdx.x;
+  if (!k.active[b]) return;
+  for (int e = 0; e < NE; ++e) {
+    double sx = 0.0, sy = 0.0;
+    for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) {
+      const double2 v = part[((long long)b * k.nblk + blk) * NE + e];
+      sx += v.x;
+      sy += v.y;
+    }
+    sx = wave_sum_d(sx);
+    sy = wave_sum_d(sy);
+    if (threadIdx.x == 0) G[e] = make_double2(sx, sy);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int m = k.m;
+  // packed index of (i, j), i <= j
+  auto gi = [](int i, int j) { return i * NV - i * (i - 1) / 2 + (j - i); };
+  double2 R[NV][NV];
+  int keep = NV;  // usable leading columns of W
+  bool finite = true;
+  for (int j = 0; j < NV && keep == NV; ++j) {
+    double d = G[gi(j, j)].x;
+    const double gjj = d;
+    for (int i = 0; i < j; ++i) d -= R[i][j].x * R[i][j].x + R[i][j].y * R[i][j].y;
+    if (!isfinite(d) || !isfinite(gjj)) {
+      finite = false;
+      keep = j;
+      break;
+    }
+    if (!(d > 1e-13 * gjj) || !(gjj > 0.0)) {
+      keep = j;
+      break;
+    }
+    const double rjj = sqrt(d);
+    R[j][j] = make_double2(rjj, 0.0);
+    for (int l = j + 1; l < NV; ++l) {
+      double2 v = G[gi(j, l)];
+      for (int i = 0; i < j; ++i) {
+        const double2 t = zmul(zconj(R[i][j]), R[i][l]);
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      R[j][l] = make_double2(v.x / rjj, v.y / rjj);
+    }
+  }
+  const int mm = keep - 1;  // usable preconditioned directions
+  k.iters[b] += M;           // preconditioner applications performed
+  if (!finite || mm < 1) {
+    k.status[b] = HELM_STATUS_BREAKDOWN_DEV;
+    k.jcount[b] = 0;
+    k.active[b] = 0;
+    return;
+  }
+  double2* H = k.H + (long long)b * (m + 1) * m;
+  double* cs = k.cs + (long long)b * m;
+  double2* sn = k.sn + (long long)b * m;
+  double2* g = k.g + (long long)b * (m + 1);
+  const double rn = 1.0 / (double)k.vs[b * (m + 1)];
+  for (int i = 0; i <= m; ++i) g[i] = make_double2(0.0, 0.0);
+  g[0] = make_double2(rn * R[0][0].x, 0.0);
+  int kstar = mm;
+  for (int col = 0; col < mm; ++col) {
+    // column col of the Hessenberg: R[0..col+1][col+1]
+    for (int i = 0; i <= col + 1; ++i) H[i * m + col] = R[i][col + 1];
+    for (int i = 0; i < col; ++i) {
+      const double2 a = H[i * m + col], c2 = H[(i + 1) * m + col];
+      const double2 t1 = zmul(sn[i], c2);
+      const double2 t2 = zmul(zconj(sn[i]), a);
+      H[i * m + col] = make_double2(cs[i] * a.x + t1.x, cs[i] * a.y + t1.y);
+      H[(i + 1) * m + col] = make_double2(cs[i] * c2.x - t2.x, cs[i] * c2.y - t2.y);
+    }
+    const double2 a = H[col * m + col];
+    const double2 hb = H[(col + 1) * m + col];
+    const double aa = zabs(a), bb = zabs(hb);
+    double cr;
+    double2 sv;
+    if (bb == 0.0) {
+      cr = 1.0;
+      sv = make_double2(0.0, 0.0);
+    } else if (aa == 0.0) {
+      cr = 0.0;
+      sv = zconj(make_double2(hb.x / bb, hb.y / bb));
+    } else {
+      const double rho = hypot(aa, bb);
+      cr = aa / rho;
+      const double2 ph = make_double2(a.x / aa, a.y / aa);
+      sv = zmul(ph, make_double2(hb.x / rho, -hb.y / rho));  // (a/|a|) conj(hb) / rho
+    }
+    cs[col] = cr;
+    sn[col] = sv;
+    const double2 t = zmul(sv, hb);
+    H[col * m + col] = make_double2(cr * a.x + t.x, cr * a.y + t.y);
+    H[(col + 1) * m + col] = make_double2(0.0, 0.0);
+    const double2 gj = g[col];
+    const double2 t2 = zmul(zconj(sv), gj);
+    g[col + 1] = make_double2(-t2.x, -t2.y);
+    g[col] = make_double2(cr * gj.x, cr * gj.y);
+    if (zabs(g[col + 1]) <= k.tol[b]) {
+      kstar = col + 1;
+      break;
+    }
+  }
+  k.jcount[b] = kstar;
+  k.active[b] = 0;
+  back_substitute(k, b, kstar);
 }
 
 __global__ void k_status_init(KrylovArgs k, int B) {
@@ -456,10 +665,41 @@ inline unsigned nblk_of(long long N) { return (unsigned)((N + CH - 1) / CH); }
 
 int krylov_blocks_per_rhs(long long N) { return (int)nblk_of(N); }
 int krylov_max_restart() { return MAXM; }
+int sstep_max_restart() { return SSTEP_MAXM; }
+long long sstep_gram_entries(int m) { return (long long)(m + 1) * (m + 2) / 2; }
+
+void launch_sstep_matvec(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine) {
+  hipLaunchKernelGGL(k_sstep_matvec, dim3(B * k.nblk), dim3(NT), 0, s, B, k, j, fine);
+}
+
+namespace {
+template <int M>
+void sstep_tail(hipStream_t s, int B, const KrylovArgs& k, const LevelArgs& fine, double2* part) {
+  hipLaunchKernelGGL(k_sstep_gram<M>, dim3(B * k.nblk), dim3(NT), 0, s, B, k, fine, part);
+  hipLaunchKernelGGL(k_sstep_solve<M>, dim3(B), dim3(HELM_WAVE), 0, s, k, (const double2*)part);
+}
+}  // namespace
+
+void launch_sstep_gram_solve(hipStream_t s, int B, const KrylovArgs& k, const LevelArgs& fine, double2* part) {
+  switch (k.m) {
+    case 1: sstep_tail<1>(s, B, k, fine, part); break;
+    case 2: sstep_tail<2>(s, B, k, fine, part); break;
+    case 3: sstep_tail<3>(s, B, k, fine, part); break;
+    case 4: sstep_tail<4>(s, B, k, fine, part); break;
+    case 5: sstep_tail<5>(s, B, k, fine, part); break;
+    case 6: sstep_tail<6>(s, B, k, fine, part); break;
+    case 7: sstep_tail<7>(s, B, k, fine, part); break;
+    case 8: sstep_tail<8>(s, B, k, fine, part); break;
+    case 9: sstep_tail<9>(s, B, k, fine, part); break;
+    case 10: sstep_tail<10>(s, B, k, fine, part); break;
+    case 11: sstep_tail<11>(s, B, k, fine, part); break;
+    default: sstep_tail<12>(s, B, k, fine, part); break;
+  }
+}
 
 void launch_arnoldi_dots(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs* fine, int with_matvec) {
   LevelArgs lv = fine ? *fine : LevelArgs{};
-  hipLaunchKernelGGL(k_arnoldi_dots, dim3(B, k.nblk), dim3(NT), 0, s, k, j, lv, with_matvec);
+  hipLaunchKernelGGL(k_arnoldi_dots, dim3(B * k.nblk), dim3(NT), 0, s, B, k, j, lv, with_matvec);
 }
 void launch_arnoldi_reduce(hipStream_t s, int B, const KrylovArgs& k, int j, int accumulate) {
   hipLaunchKernelGGL(k_arnoldi_reduce, dim3(B), dim3(NT), 0, s, k, j, accumulate);
@@ -479,7 +719,7 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
                         long long r_stride, float out_scale) {
   FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, c_hi, c_lo, ghost_hi, ghost_lo, h2_hi, h2_lo, r_out,
            r_stride, out_scale};
-  hipLaunchKernelGGL(k_residual_ff, dim3(B, k.nblk), dim3(NT), 0, s, k, a);
+  hipLaunchKernelGGL(k_residual_ff, dim3(B * k.nblk), dim3(NT), 0, s, B, k, a);
 }
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);

@@ -21,25 +21,41 @@ namespace {
 //   stage 2: s = r - K v1 = (1 - w) r + sum of in-grid neighbours of v1 (D v1 = w r)
 //            on the (2 TCX + 1) x (2 TCY + 1) interior, by the thread that holds r
 //   stage 3: rc = 4 R s (scaled coarse right-hand side)
-template <int TCX, int TCY>
-__global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                           VecSet rc, int nc, const int* active) {
+// With RES the leg starts a repeated visit of the level from the current
+// solution e (Alg. 2 with a non-zero guess, written as e + MG(r - K e, 0)):
+// its right-hand side is r - K e, formed on the halo region from e on a
+// one-point wider ring, so that the residual is never stored.
+template <int TCX, int TCY, bool RES>
+__global__ __launch_bounds__(TCX* TCY) void k_down_fused2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
+                                                           float omega, VecSet rc, int nc, const int* active,
+                                                           VecSet ev) {
   constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3;
   constexpr int SX = 2 * TCX + 1, SY = 2 * TCY + 1;
   constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
+  constexpr int EX = RES ? RX + 2 : 1, EY = RES ? RY + 2 : 1;
   __shared__ c32 sV[RY][RX];
   __shared__ c32 sS[SY][SX];
-  // right-hand side fastest: the blocks of one tile run together and share its W in L2
-  const int b = blockIdx.x;
-  if (active && !active[b]) return;
+  __shared__ c32 sE[EY][EX];
   const int n = lv.n;
   const int tiles_x = (nc + TCX - 1) / TCX;
-  const int cx0 = (blockIdx.y % tiles_x) * TCX;
-  const int cy0 = (blockIdx.y / tiles_x) * TCY;
+  const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int cx0 = (id.t % tiles_x) * TCX;
+  const int cy0 = (id.t / tiles_x) * TCY;
   const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  c32 rv[IT], wv[IT];
+  c32 rv[IT], wv[IT], kv[RES ? IT : 1];
+  if constexpr (RES) {
+    const c32* eb = ev.p + (long long)b * ev.stride;
+    for (int idx = threadIdx.x; idx < EX * EY; idx += NT) {
+      const int gx = fx0 - 1 + idx % EX, gy = fy0 - 1 + idx / EX;
+      const bool ok = gx >= 0 && gx < n && gy >= 0 && gy < n;
+      sE[idx / EX][idx % EX] = ok ? eb[(long long)gy * n + gx] : make_float2(0.f, 0.f);
+    }
+  }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int idx = threadIdx.x + it * NT;
@@ -48,11 +64,24 @@ __global__ __launch_bounds__(TCX* TCY) void k_down_fused2(VecSet r, ScaleSet rs,
     const long long p = ok ? (long long)gy * n + gx : 0;
     rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
     wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
   }
+  if constexpr (RES) __syncthreads();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int idx = threadIdx.x + it * NT;
     rv[it] = cscale(rv[it], sc);
+    if constexpr (RES) {
+      // r - K e with K e = D e - (sum of in-grid neighbours); sE is zero outside the grid
+      const int lx = idx % RX + 1, ly = idx / RX + 1;
+      const int gx = fx0 + idx % RX, gy = fy0 + idx / RX;
+      if (idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n) {
+        const int ng = ghosts2(gx, gy, n);
+        const c32 D = make_float2(4.0f - kv[it].x - ng * lv.ghost.x, -kv[it].y - ng * lv.ghost.y);
+        const c32 nb = cadd(cadd(sE[ly][lx - 1], sE[ly][lx + 1]), cadd(sE[ly - 1][lx], sE[ly + 1][lx]));
+        rv[it] = cadd(csub(rv[it], cmul(D, sE[ly][lx])), nb);
+      }
+    }
     if (idx < NR) sV[idx / RX][idx % RX] = cmul(rv[it], wv[it]);
   }
   __syncthreads();
@@ -99,22 +128,30 @@ __device__ __forceinline__ c32 prolong_lds(const c32 (*sE)[CX], int gx, int gy, 
 // column segment and keeps r and W of its own points in registers:
 //   v2 = W r + P e on the (TX + 2) x (TY + 2) halo region (own points + a ring) -> LDS
 //   z  = v2 + W (r - K v2) = (1 - w) v2 + W (r + sum of in-grid neighbours of v2)
-template <int TX, int TY, int PY>
-__global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                             VecSet ec, int nc, VecSet z, const int* active) {
+// With RES (see k_down_fused2) the right-hand side is r - K e, formed from e
+// on a two-point ring, and the leg writes e + z: the result of the repeated
+// visit.  z must not alias e (other tiles read e's halo).
+template <int TX, int TY, int PY, bool RES>
+__global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
+                                                             float omega, VecSet ec, int nc, VecSet z,
+                                                             const int* active, VecSet ev) {
   constexpr int HX = TX + 2, HY = TY + 2;
   constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2;
   constexpr int NT = TX * (TY / PY);
   constexpr int NRING = 2 * HX + 2 * TY;
+  constexpr int FX = RES ? TX + 4 : 1, FY = RES ? TY + 4 : 1;
   static_assert(NRING <= NT, "one ring point per thread");
   __shared__ c32 sE[CY][CX];
   __shared__ c32 sV[HY][HX];
-  const int b = blockIdx.x;  // right-hand side fastest (see k_down_fused2)
-  if (active && !active[b]) return;
+  __shared__ c32 sF[FY][FX];
   const int n = lv.n;
   const int tiles_x = (n + TX - 1) / TX;
-  const int fx0 = (blockIdx.y % tiles_x) * TX;
-  const int fy0 = (blockIdx.y / tiles_x) * TY;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tiles_x) * TX;
+  const int fy0 = (id.t / tiles_x) * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const float sc = scale_of(rs, b);
@@ -140,13 +177,22 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
   }
   // issue every global load first
   constexpr int NE = CX * CY, ITE = (NE + NT - 1) / NT;
-  c32 ev[ITE], rv[PY + 1], wv[PY + 1];
+  c32 ev_c[ITE], rv[PY + 1], wv[PY + 1];
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
     const int idx = threadIdx.x + it * NT;
     const int I = cxs + idx % CX, J = cys + idx / CX;
     const bool ok = idx < NE && I >= 0 && I < nc && J >= 0 && J < nc;
-    ev[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+    ev_c[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  c32 kv[RES ? PY + 1 : 1];
+  if constexpr (RES) {
+    const c32* fb = ev.p + (long long)b * ev.stride;
+    for (int idx = threadIdx.x; idx < FX * FY; idx += NT) {
+      const int gx = fx0 - 2 + idx % FX, gy = fy0 - 2 + idx / FX;
+      const bool ok = gx >= 0 && gx < n && gy >= 0 && gy < n;
+      sF[idx / FX][idx % FX] = ok ? fb[(long long)gy * n + gx] : make_float2(0.f, 0.f);
+    }
   }
 #pragma unroll
   for (int k = 0; k <= PY; ++k) {
@@ -156,13 +202,28 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
     const long long p = ok ? (long long)gy * n + gx : 0;
     rv[k] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
     wv[k] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    if constexpr (RES) kv[k] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
   }
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
     const int idx = threadIdx.x + it * NT;
-    if (idx < NE) sE[idx / CX][idx % CX] = ev[it];
+    if (idx < NE) sE[idx / CX][idx % CX] = ev_c[it];
   }
   __syncthreads();
+  if constexpr (RES) {
+    // r - K e at the own and ring points (sF is zero outside the grid)
+#pragma unroll
+    for (int k = 0; k <= PY; ++k) {
+      const int lx = k < PY ? tx + 1 : rlx, ly = k < PY ? ty0 + k + 1 : rly;
+      const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
+      if ((k < PY || rlx >= 0) && gx >= 0 && gx < n && gy >= 0 && gy < n) {
+        const int ng = ghosts2(gx, gy, n);
+        const c32 D = make_float2(4.0f - kv[k].x - ng * lv.ghost.x, -kv[k].y - ng * lv.ghost.y);
+        const c32 nb = cadd(cadd(sF[ly + 1][lx], sF[ly + 1][lx + 2]), cadd(sF[ly][lx + 1], sF[ly + 2][lx + 1]));
+        rv[k] = cadd(csub(rv[k], cmul(D, sF[ly + 1][lx + 1])), nb);
+      }
+    }
+  }
   c32 v2own[PY];
 #pragma unroll
   for (int k = 0; k <= PY; ++k) {
@@ -182,7 +243,9 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(VecSet r, ScaleSet r
     const int gx = fx0 + tx, gy = fy0 + ty0 + k;
     if (gx < n && gy < n) {
       const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-      zb[(long long)gy * n + gx] = cadd(cscale(v2own[k], 1.0f - omega), cmul(wv[k], cadd(rv[k], nb)));
+      c32 zv = cadd(cscale(v2own[k], 1.0f - omega), cmul(wv[k], cadd(rv[k], nb)));
+      if constexpr (RES) zv = cadd(zv, sF[ly + 1][lx + 1]);
+      zb[(long long)gy * n + gx] = zv;
     }
   }
 }
@@ -346,17 +409,25 @@ constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64
 
 template <int TCX, int TCY>
 void down_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
-               const int* active) {
+               const int* active, VecSet e) {
   const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
-  hipLaunchKernelGGL((k_down_fused2<TCX, TCY>), dim3(B, tiles), dim3(TCX * TCY), 0, s, r, rs, lv, omega, rc, nc,
-                     active);
+  if (e.p)
+    hipLaunchKernelGGL((k_down_fused2<TCX, TCY, true>), dim3(B * tiles), dim3(TCX * TCY), 0, s, B, r, rs, lv, omega,
+                       rc, nc, active, e);
+  else
+    hipLaunchKernelGGL((k_down_fused2<TCX, TCY, false>), dim3(B * tiles), dim3(TCX * TCY), 0, s, B, r, rs, lv,
+                       omega, rc, nc, active, e);
 }
 template <int TX, int TY, int PY>
 void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc, VecSet z,
-             const int* active) {
+             const int* active, VecSet e) {
   const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_fused2<TX, TY, PY>), dim3(B, tiles), dim3(TX * (TY / PY)), 0, s, r, rs, lv, omega, ec,
-                     nc, z, active);
+  if (e.p)
+    hipLaunchKernelGGL((k_up_fused2<TX, TY, PY, true>), dim3(B * tiles), dim3(TX * (TY / PY)), 0, s, B, r, rs, lv,
+                       omega, ec, nc, z, active, e);
+  else
+    hipLaunchKernelGGL((k_up_fused2<TX, TY, PY, false>), dim3(B * tiles), dim3(TX * (TY / PY)), 0, s, B, r, rs, lv,
+                       omega, ec, nc, z, active, e);
 }
 }  // namespace
 
@@ -373,24 +444,24 @@ void mg_up_shape(int cfg, int* tx, int* ty, int* py) {
 }
 
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
-                        const int* active, int cfg) {
+                        const int* active, int cfg, VecSet e) {
   switch (cfg) {
-    case 1: down_tile<16, 16>(s, B, r, rs, lv, omega, rc, nc, active); break;
-    case 2: down_tile<64, 4>(s, B, r, rs, lv, omega, rc, nc, active); break;
-    case 3: down_tile<32, 4>(s, B, r, rs, lv, omega, rc, nc, active); break;
-    case 4: down_tile<16, 8>(s, B, r, rs, lv, omega, rc, nc, active); break;
-    default: down_tile<32, 8>(s, B, r, rs, lv, omega, rc, nc, active); break;
+    case 1: down_tile<16, 16>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
+    case 2: down_tile<64, 4>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
+    case 3: down_tile<32, 4>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
+    case 4: down_tile<16, 8>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
+    default: down_tile<32, 8>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
   }
 }
 
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active, int cfg) {
+                      VecSet z, const int* active, int cfg, VecSet e) {
   switch (cfg) {
-    case 1: up_tile<32, 16, 2>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
-    case 2: up_tile<64, 8, 2>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
-    case 3: up_tile<32, 32, 4>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
-    case 4: up_tile<64, 32, 8>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
-    default: up_tile<64, 16, 4>(s, B, r, rs, lv, omega, ec, nc, z, active); break;
+    case 1: up_tile<32, 16, 2>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
+    case 2: up_tile<64, 8, 2>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
+    case 3: up_tile<32, 32, 4>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
+    case 4: up_tile<64, 32, 8>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
+    default: up_tile<64, 16, 4>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
   }
 }
 

@@ -35,11 +35,13 @@ enum {
 };
 
 // ---- multigrid legs (2D) ----
-// fused 2D legs; cfg selects one of the tile shapes (0 = default, see mg_*_shape)
+// fused 2D legs; cfg selects one of the tile shapes (0 = default, see mg_*_shape).
+// e.p != NULL: repeated visit from the current solution e (right-hand side r - K e;
+// the up-leg writes e + correction to z, which must not alias e).
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
-                        const int* active, int cfg);
+                        const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active, int cfg);
+                      VecSet z, const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
 int mg_down_variants();
 int mg_up_variants();
 void mg_down_shape(int cfg, int* tcx, int* tcy);
@@ -75,6 +77,9 @@ struct CoarseCycleArgs {
   const int* active;
   CoarseLevel lv[HELM_MAX_LEVELS];
 };
+// LDS-resident variant when the levels' vectors fit in this many bytes, else through L2
+constexpr size_t kCoarseCycleMaxLds = 64 * 1024;
+size_t coarse_cycle_lds_bytes(const CoarseCycleArgs& a);
 void launch_coarse_cycle(hipStream_t s, int B, const CoarseCycleArgs& a);
 
 // ---- Krylov (FGMRES / float-float outer loop), flat over the fine grid ----
@@ -105,6 +110,7 @@ struct KrylovArgs {
   int max_iters;
   double rtol;
   double inner_factor;
+  int bicg;       // 1: Bi-CGSTAB (the true residual skips right-hand sides still iterating)
 };
 
 void launch_arnoldi_dots(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs* fine, int with_matvec);
@@ -125,7 +131,8 @@ void launch_reject_reset(hipStream_t s, int B, const KrylovArgs& k, int j, const
 void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane, const c32* tables, c32* rhs,
                        c32* uin);
 void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* uin, const c32* u,
-                   const c32* lam, const float* nmap, float scale, float* grad);
+                   const c32* lam, const float* nmap, float scale, float* grad,
+                   const c32* lam2 = nullptr);
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out);
 void launch_gather(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, c32* y);
 void launch_scatter(hipStream_t s, int B, int M, long long N, const int* idx, const c32* y, c32* u);
@@ -136,3 +143,37 @@ void launch_zero(hipStream_t s, long long count, c32* p);
 void launch_status_init(hipStream_t s, int B, const KrylovArgs& k);
 int krylov_blocks_per_rhs(long long N);
 int krylov_max_restart();
+// Bi-CGSTAB (Alg. 3), slots and scalars documented in k_bicgstab.hip
+void launch_bicg_dir(hipStream_t s, int B, const KrylovArgs& k);
+void launch_bicg_apply(hipStream_t s, int B, const KrylovArgs& k, int zs, int vs, const LevelArgs& fine, int second);
+void launch_bicg_alpha(hipStream_t s, int B, const KrylovArgs& k);
+void launch_bicg_s(hipStream_t s, int B, const KrylovArgs& k);
+void launch_bicg_sigma(hipStream_t s, int B, const KrylovArgs& k);
+void launch_bicg_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo);
+void launch_bicg_rho(hipStream_t s, int B, const KrylovArgs& k);
+void launch_bicg_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
+// s-step GMRES(m): basis matvec W_{j+1} = A Z_j; Gram pass (fused with the last
+// matvec) + per-RHS Cholesky-QR least squares.  part: [B][nblk][sstep_gram_entries(m)].
+int sstep_max_restart();
+long long sstep_gram_entries(int m);
+void launch_sstep_matvec(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine);
+void launch_sstep_gram_solve(hipStream_t s, int B, const KrylovArgs& k, const LevelArgs& fine, double2* part);
+
+// ---- inverse problem (Sec. V, Alg. 4), interior grid n^dim ----
+void launch_tv_prox(hipStream_t s, int dim, int n, const float* v, float lam, float lo, int iters, float* p, float* r,
+                    float* w);
+void launch_axmy(hipStream_t s, long long count, const float* a, float sc, const float* b, float* out);
+void launch_fbs_momentum(hipStream_t s, long long count, const float* f_new, float beta, float* f, float* fbar);
+int data_residual_blocks(int B, int M);
+void launch_data_residual(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, const c32* y,
+                          c32* res, double* part);
+void launch_index_from_f(hipStream_t s, long long count, const float* f, double inv_k02, double nb2, float* nmap);
+
+// ---- sensor operator (far field through the Lippmann-Schwinger integral) ----
+void launch_ff_matrix(hipStream_t s, int dim, int n, int M, const double* sens, double kbh, double h,
+                      const double2* tab, double x0, double dx, int ntab, c32* G);
+int ff_splits(long long Ni);
+void launch_ff_forward(hipStream_t s, int dim, int B, int M, int ne, int w, int n, const float* fpl, const c32* uin,
+                       const c32* usc, const c32* G, c32* src, c32* part, c32* y);
+void launch_ff_adjoint(hipStream_t s, int dim, int B, int M, int ne, int w, int n, const c32* G, const c32* r,
+                       const float* fpl, c32* s_ext, c32* rhs_ext);

@@ -22,6 +22,12 @@ HELM_NOT_CONVERGED = 1
 STATUS_NAMES = {0: "converged", 1: "not_converged", 2: "breakdown"}
 
 
+# helm_opts.krylov: GMRES(m) as FGMRES (Arnoldi) or in s-step form (Gram matrix + Cholesky QR)
+KRYLOV_FGMRES = 0
+KRYLOV_SSTEP = 1
+KRYLOV_BICGSTAB = 2  # the paper's Alg. 3
+
+
 class HelmGrid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("abl_width", ctypes.c_int), ("h", ctypes.c_double)]
 
@@ -37,7 +43,7 @@ class HelmOpts(ctypes.Structure):
         ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("cycle", ctypes.c_int),
         ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("reorth", ctypes.c_int), ("fused", ctypes.c_int), ("use_graph", ctypes.c_int),
-        ("coarse_single_launch", ctypes.c_int),
+        ("coarse_single_launch", ctypes.c_int), ("krylov", ctypes.c_int),
     ]
 
 
@@ -72,6 +78,8 @@ EXPORTS = [
     "helm_net_layers", "helm_net_layer_shape", "helm_net_create", "helm_net_destroy", "helm_net_last_error",
     "helm_net_set_layer", "helm_net_get_layer", "helm_net_get_grad", "helm_net_forward", "helm_net_backward",
     "helm_net_adam_step", "helm_net_set_loss", "helm_autotune", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
+    "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
+    "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield",
 ]
 
 _lib = None
@@ -130,6 +138,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_set_preconditioner.argtypes = [vp, vp, d, d, i]
     lib.helm_solve_snapshots.argtypes = [vp, i, vp, vp, ctypes.POINTER(HelmStats), i, i, vp, ctypes.POINTER(i)]
     lib.helm_net_examples.argtypes = [vp, i, vp, vp, vp, i, vp, i, d, vp, vp]
+    lib.helm_update_f.argtypes = [vp, vp]
+    lib.helm_grad_f.argtypes = [vp, i, vp, vp, vp, vp]
+    lib.helm_data_residual.argtypes = [vp, i, i, vp, vp, vp, vp, ctypes.POINTER(d)]
+    lib.helm_tv_prox.argtypes = [vp, vp, d, d, i, vp]
+    lib.helm_fbs_step.argtypes = [vp, vp, vp, vp, d, d, d, i, ctypes.POINTER(d)]
+    lib.helm_farfield_set.argtypes = [vp, i, vp]
+    lib.helm_farfield.argtypes = [vp, i, vp, vp, vp]
+    lib.helm_farfield_adjoint.argtypes = [vp, i, vp, vp, vp]
+    lib.helm_grad_f_farfield.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.helm_last_error.argtypes = [vp]
     lib.helm_last_error.restype = ctypes.c_char_p
     lib.helm_destroy.argtypes = [vp]
@@ -272,6 +289,69 @@ class Context:
         grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
         self._check(self.lib.helm_grad_n(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(grad)),
                     "helm_grad_n")
+        return grad
+
+    # -- inverse problem (Sec. V, Alg. 4): unknown f = k0^2 (n^2 - n_b^2) on Omega --------------
+    def update_f(self, f: torch.Tensor):
+        self._check(self.lib.helm_update_f(self._h, _ptr(f.to(torch.float32).contiguous())), "helm_update_f")
+
+    def grad_f(self, u_sc: torch.Tensor, lam: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
+        """sum_q Re(conj(u_in + u_sc) lam) on Omega."""
+        grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
+        self._check(self.lib.helm_grad_f(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(grad)),
+                    "helm_grad_f")
+        return grad
+
+    def data_residual(self, idx: torch.Tensor, u: torch.Tensor, y: torch.Tensor):
+        """(S u - y, 1/2 ||S u - y||^2)."""
+        res = torch.empty_like(y)
+        loss = ctypes.c_double()
+        self._check(self.lib.helm_data_residual(self._h, u.shape[0], idx.numel(), _ptr(idx), _ptr(u),
+                                                _ptr(y.contiguous()), _ptr(res), ctypes.byref(loss)),
+                    "helm_data_residual")
+        return res, loss.value
+
+    def tv_prox(self, v: torch.Tensor, lam: float, lo: float = 0.0, iters: int = 100) -> torch.Tensor:
+        v = v.to(torch.float32).contiguous()
+        w = torch.empty_like(v)
+        self._check(self.lib.helm_tv_prox(self._h, _ptr(v), float(lam), float(lo), int(iters), _ptr(w)),
+                    "helm_tv_prox")
+        return w
+
+    def fbs_step(self, f: torch.Tensor, fbar: torch.Tensor, grad: torch.Tensor, gamma: float, tau: float,
+                 alpha: float, lo: float = 0.0, prox_iters: int = 100) -> float:
+        """One update of Alg. 4 in place on f and fbar; returns the next alpha."""
+        a = ctypes.c_double(alpha)
+        self._check(self.lib.helm_fbs_step(self._h, _ptr(f), _ptr(fbar), _ptr(grad.contiguous()), float(gamma),
+                                           float(tau), float(lo), int(prox_iters), ctypes.byref(a)), "helm_fbs_step")
+        return a.value
+
+    # -- sensor operator G~ (far field through the Lippmann-Schwinger integral) ----------------
+    def farfield_set(self, sensors: np.ndarray):
+        """Sensors [M, dim] in grid cells relative to the centre of Omega (outside Omega)."""
+        sensors = np.ascontiguousarray(np.asarray(sensors, dtype=np.float64).reshape(-1, self.dim))
+        self._check(self.lib.helm_farfield_set(self._h, sensors.shape[0], sensors.ctypes.data_as(ctypes.c_void_p)),
+                    "helm_farfield_set")
+        self.n_sensors = sensors.shape[0]
+
+    def farfield(self, u_sc: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
+        y = torch.empty((u_sc.shape[0], self.n_sensors), dtype=torch.complex64, device=self.device)
+        self._check(self.lib.helm_farfield(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(y)), "helm_farfield")
+        return y
+
+    def farfield_adjoint(self, r: torch.Tensor):
+        """(G~^H r on Omega, f G~^H r) as fields on the extended grid."""
+        B = r.shape[0]
+        s, rhs = self.empty_fields(B), self.empty_fields(B)
+        self._check(self.lib.helm_farfield_adjoint(self._h, B, _ptr(r.contiguous()), _ptr(s), _ptr(rhs)),
+                    "helm_farfield_adjoint")
+        return s, rhs
+
+    def grad_f_farfield(self, u_sc: torch.Tensor, lam: torch.Tensor, s: torch.Tensor,
+                        u_in: torch.Tensor | None = None) -> torch.Tensor:
+        grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
+        self._check(self.lib.helm_grad_f_farfield(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(s),
+                                                  _ptr(grad)), "helm_grad_f_farfield")
         return grad
 
     def sample(self, idx: torch.Tensor, u: torch.Tensor) -> torch.Tensor:

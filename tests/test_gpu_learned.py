@@ -104,7 +104,8 @@ def test_fgmres_with_network_and_fallback():
     n, w, levels = 40, 8, 3
     nmap = medium(n, seed=13)
     prob = oracle_problem(nmap, w=w, levels=levels)
-    ctx = gpu_context(nmap, w=w, levels=levels, max_batch=3)
+    # FGMRES throughout, so that the multigrid-only solve is comparable step for step
+    ctx = gpu_context(nmap, w=w, levels=levels, max_batch=3, krylov=helm.KRYLOV_FGMRES)
     net = helm.Net(seed=3)  # untrained: its outputs fail the acceptance test and the V-cycle takes over
     ctx.set_preconditioner(net, accept_tol=0.5, gamma=1.0)
     rhs = ctx.plane_wave_rhs(synth.directions_2d(3))

@@ -6,7 +6,7 @@ import scipy.sparse.linalg as spla
 import synth
 from oracle import model
 from oracle.discretization import Problem, helmholtz_matrix
-from oracle.krylov import bicgstab, fgmres, givens
+from oracle.krylov import bicgstab, fgmres, givens, sstep_gmres
 from oracle.multigrid import Hierarchy
 
 KBH = 2 * np.pi / 10
@@ -73,6 +73,37 @@ def test_fgmres_matches_library_gmres_solution():
     x_lib, flag = spla.gmres(a, b, M=m, rtol=1e-12, restart=60, maxiter=50)
     assert flag == 0
     assert np.linalg.norm(x - x_lib) < 1e-9 * np.linalg.norm(x_lib)
+
+
+def test_sstep_gmres_iterates_equal_fgmres():
+    """The s-step form minimises over the same Krylov space as FGMRES(m) with a fixed
+    preconditioner: in FP64 the residual estimate after each basis size of each cycle
+    and the iterate after each cycle agree with FGMRES(m) (brute force pins FGMRES)."""
+    prob = problem(n=16, w=4)
+    hier = Hierarchy(prob)
+    a = helmholtz_matrix(prob)
+    b = synth.complex_field(prob.size, 13)
+    for m in (1, 3, 5):
+        x_f, info_f = fgmres(lambda v: a @ v, hier.vcycle, b, rtol=1e-10, restart=m, max_iters=m * 6)
+        x_s, info_s = sstep_gmres(lambda v: a @ v, hier.vcycle, b, rtol=1e-10, restart=m, max_iters=m * 6)
+        assert info_s.iters == info_f.iters == m * 6
+        np.testing.assert_allclose(info_s.history, info_f.history, rtol=1e-6, atol=1e-13)
+        assert np.linalg.norm(x_s - x_f) < 1e-8 * np.linalg.norm(x_f)
+
+
+def test_sstep_gmres_reaches_lu_solution_in_whole_cycles():
+    prob = problem()
+    ex = model.ExactSolver(prob)
+    hier = Hierarchy(prob)
+    b = prob.h ** 2 * model.rhs(prob, [0.0, 1.0]).ravel()
+    a = helmholtz_matrix(prob, scaled=True)
+    x, info = sstep_gmres(lambda v: a @ v, hier.vcycle, b, rtol=1e-9, restart=4)
+    assert info.converged and info.rel_res_true <= 1e-9 and info.iters % 4 == 0
+    u = ex.solve(model.rhs(prob, [0.0, 1.0]))
+    assert np.linalg.norm(x - u.ravel()) < 1e-7 * np.linalg.norm(u)
+    # whole cycles: the count is m times the cycles FGMRES(m) needs
+    _, info_f = fgmres(lambda v: a @ v, hier.vcycle, b, rtol=1e-9, restart=4)
+    assert info.iters == 4 * -(-info_f.iters // 4)
 
 
 def test_bicgstab_alg3_converges_to_lu_solution():
