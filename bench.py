@@ -34,7 +34,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="blobs512x60")
     p.add_argument("--levels", type=int, default=7)
-    p.add_argument("--restart", type=int, default=5)
+    p.add_argument("--restart", type=int, default=8)
     p.add_argument("--cycle", type=int, default=3, help="1 = V, 2 = W, 3 = two coarse corrections on the finest "
                                                           "level and V-cycles below")
     p.add_argument("--reorth", type=int, default=0)
@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
     p.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (for counter collection)")
+    p.add_argument("--fused-step", action="store_true",
+                   help="one kernel for the finest-level up-leg, basis matvec and next down-leg")
     p.add_argument("--copy-probe", type=float, default=256.0,
                    help="MiB of a plain device-to-device copy timed before the solve (0: skip); the same copy "
                         "calibrates the HBM byte counters")
@@ -114,6 +116,44 @@ def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
                    f"{el:.1f} s on 1 host thread, scaled by {iters_per_solve:.0f} iterations per solve "
                    f"(the GPU's mean at the same parameters); set-up excluded"),
     }
+
+
+def gradient_leg(ctx, dirs, nmap, reps=3):
+    """One data-term gradient evaluation of the inverse problem (Sec. V, Prop. 1) with on-grid
+    receivers on the transmission-side row: forward solves of all plane waves, data residual,
+    adjoint solves, grad_f.  Data: the forward field of a medium with half the contrast, so
+    that the residual is not trivial.  Reported: mean wall time over `reps` evaluations."""
+    import numpy as np
+    import torch
+
+    from paper_2107_03679_amd.autograd import receiver_line
+
+    dev = torch.device("cuda:0")
+    rx = receiver_line(ctx)
+    half = 1.333 + 0.5 * (nmap - 1.333)
+    ctx.update_n(torch.tensor(half, dtype=torch.float32, device=dev))
+    u, _ = ctx.solve(ctx.plane_wave_rhs(dirs))
+    y = ctx.sample(rx, u)
+    ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device=dev))
+    rhs, uin = ctx.plane_wave_rhs(dirs, with_uin=True)
+
+    def once():
+        usc, st = ctx.solve(rhs)
+        res, loss = ctx.data_residual(rx, usc, y)
+        lam, st_a = ctx.adjoint(ctx.sample_adjoint(rx, res))
+        g = ctx.grad_f(usc, lam, u_in=uin)
+        return st, st_a, loss, g
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, st_a, loss, g = once()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    return {"ms_per_gradient": 1e3 * el, "forward_iters_mean": float(st.iters.mean()),
+            "adjoint_iters_mean": float(st_a.iters.mean()), "converged": bool(st.converged and st_a.converged),
+            "loss": loss, "receivers": int(rx.numel()), "plane_waves": int(dirs.shape[0])}
 
 
 def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
@@ -208,7 +248,7 @@ def main():
     t_setup = time.perf_counter()
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
                        levels=args.levels, restart=args.restart, cycle=args.cycle, reorth=args.reorth, max_batch=B,
-                       max_iters=20000, use_graph=0 if args.no_graph else 1,
+                       max_iters=20000, use_graph=0 if args.no_graph else 1, fused_step=1 if args.fused_step else 0,
                        krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
                                "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
     torch.cuda.synchronize()
@@ -294,6 +334,8 @@ def main():
             k: {"ms": round(v[0], 3), "launches": v[1], "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0}
             for k, v in sorted(rep.items(), key=lambda kv: -kv[1][0])
         }
+    if args.workload == "inverse256x32":
+        out["gradient"] = gradient_leg(ctx, dirs, nmap)
     if not args.no_learned and wl["d"] == 2:
         out["learned"] = learned_leg(ctx, args, wl, nmap, dirs, float(iters.mean()), value)
     ctx.close()

@@ -104,6 +104,10 @@ typedef struct {
   int coarse_single_launch; /* 1 = V-cycle levels with <= 48^2 (2D) / 16^3 (3D) points run
                                in one launch, one workgroup per right-hand side (1) */
   int krylov;       /* HELM_KRYLOV_SSTEP (default), HELM_KRYLOV_FGMRES or HELM_KRYLOV_BICGSTAB */
+  int fused_step;   /* 1 = in the s-step form (2D, fused legs), the finest-level work between two
+                       coarse visits (up-leg, basis matvec, next down-leg) is one kernel; it moves
+                       36% fewer bytes but its six barrier stages leave it latency-bound, no faster
+                       than the separate kernels on MI355X (0) */
 } helm_opts;
 
 /* Krylov forms (helm_opts.krylov).  Both minimise the residual over the same
@@ -310,6 +314,10 @@ int helm_farfield_set(helm_ctx* ctx, int M, const double* sensors_host);
 /* y[q][m] (device [B][M]) for fields u_in, u_sc (device [B][grid]; u_in may be NULL:
  * u_sc is then the total field).  HELM_ESTATE without sensors. */
 int helm_farfield(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, helm_c32* y);
+/* y = G~ f (u_in + u_sc) as helm_farfield, res = y - y_meas (device [B][M]) and
+ * *loss_host = 1/2 sum |res|^2 (FP64) when non-NULL. */
+int helm_farfield_residual(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* y_meas,
+                           helm_c32* y, helm_c32* res, double* loss_host);
 /* s_ext = G~^H r on Omega, 0 in the layer (device [B][grid], overwritten); rhs_ext
  * (or NULL) = f s_ext, the right-hand side of the adjoint solve. r: device [B][M]. */
 int helm_farfield_adjoint(helm_ctx* ctx, int B, const helm_c32* r, helm_c32* s_ext, helm_c32* rhs_ext);

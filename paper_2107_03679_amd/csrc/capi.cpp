@@ -65,8 +65,9 @@ struct helm_ctx {
   float* d_nmap = nullptr;   // interior index (for the gradient)
   float* d_f = nullptr;      // f = k0^2 (eta^2 - eta_b^2) on Omega_e (0 in the layer), unscaled
   c32* d_chi = nullptr;      // c = (k0 h)^2 eta^2 alpha, hi part
-  c32* d_clo = nullptr;      // ... lo part (float-float)
-  c32 g0_hi{}, g0_lo{};      // fine ghost factor, float-float
+  c32* d_dhi = nullptr;      // diagonal of A' (with the Sommerfeld terms), float-float hi ...
+  c32* d_dlo = nullptr;      // ... and lo part (the true residual)
+  c32 g0_hi{};               // fine ghost factor 1 + j k_b h
   float h2_hi = 0, h2_lo = 0;
   std::vector<Level> lv;
   c32* d_minvT = nullptr;
@@ -99,6 +100,7 @@ struct helm_ctx {
   c32* d_ff_src = nullptr;   // [maxB][n^dim] induced source
   c32* d_ff_part = nullptr;  // [splits][maxB][M]
   int ff_active_M = 0;       // sensors of the current set
+  int* d_ff_iota = nullptr;  // 0 .. M-1 (the data residual of helm_farfield_residual)
   int* h_status = nullptr;  // pinned
   int* h_iters = nullptr;
   double* h_relres = nullptr;
@@ -248,13 +250,52 @@ bool legs_fused(const helm_ctx* c, int l) {
   return !single;
 }
 
+void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act,
+              VecSet eres = VecSet{nullptr, 0});
+
+// The coarse-grid corrections of one visit of level l (Alg. 2's CycleType; for
+// cycle = 3 two on the finest level and one below), from the right-hand side
+// already restricted into level l + 1's rc.  Returns the buffer that holds the
+// coarse solution afterwards (e or d of level l + 1).
+VecSet coarse_visits(helm_ctx* c, int B, int l, const int* act) {
+  const int gamma = c->o.cycle == 3 ? (l == 0 ? 2 : 1) : c->o.cycle;
+  Level& crs = c->lv[l + 1];
+  VecSet rc{crs.rc, crs.N}, ec{crs.e, crs.N};
+  const double Nc1 = (double)crs.N, Bp = c->prof_B;
+  const bool next_is_coarsest = (l + 1 == c->L - 1);
+  VecSet ecur = ec;
+  for (int cyc = 0; cyc < gamma; ++cyc) {
+    if (cyc == 0) {
+      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, true, act);
+      continue;
+    }
+    if (next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
+    // repeated visit from the current e: MG(rc, e) = e + MG(rc - K e, 0)
+    VecSet other{ecur.p == crs.e ? crs.d : crs.e, crs.N};
+    if (legs_fused(c, l + 1)) {
+      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, other, true, act, ecur);
+      ecur = other;
+      continue;
+    }
+    VecSet rr{crs.rr, crs.N};
+    {
+      ProfScope ps(c, lvl_name("level_residual", l + 1), Bp * 24.0 * Nc1 + 8.0 * Nc1);
+      launch_level_residual(c->s, c->dim, B, rc, ecur, level_K(c, l + 1), rr, act);
+    }
+    mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, other, true, act);
+    ProfScope ps(c, lvl_name("add", l + 1), Bp * 24.0 * Nc1);
+    launch_add(c->s, B, other, ecur, crs.N, act);
+  }
+  return ecur;
+}
+
 // Alg. 2 on level l for K'_l v = r, result in `out` (which holds the initial
 // guess when zero_guess is false).  Fused 2D legs serve the common case.
 // With eres.p set (only where legs_fused(l)), the visit starts from the
 // solution eres instead: out = eres + MG(r - K eres, 0), the residual formed
 // inside the legs; out must not alias eres.
 void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act,
-              VecSet eres = VecSet{nullptr, 0}) {
+              VecSet eres) {
   const int dim = c->dim;
   if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
     ProfScope ps(c, "coarse_solve", 8.0 * c->Nc * c->Nc + c->prof_B * 16.0 * c->Nc);
@@ -262,9 +303,6 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     return;
   }
   Level& fine = c->lv[l];
-  // coarse-grid corrections per visit of level l: Alg. 2's CycleType, or for
-  // cycle = 3 two on the finest level and one below
-  const int gamma = c->o.cycle == 3 ? (l == 0 ? 2 : 1) : c->o.cycle;
   const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
   const bool vcycle11 = c->o.fused && zero_guess && v_below && c->o.nu1 == 1 && c->o.nu2 == 1;
   const long long small = coarse_small(c);
@@ -317,30 +355,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
     ProfScope ps(c, lvl_name("restrict_residual", l), Bp * (16.0 * Nf + 8.0 * Nc1) + 8.0 * Nf);
     launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
   }
-  const bool next_is_coarsest = (l + 1 == c->L - 1);
-  VecSet ecur = ec;  // the coarse solution after the visits so far (e or d of level l + 1)
-  for (int cyc = 0; cyc < gamma; ++cyc) {
-    if (cyc == 0) {
-      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, ec, true, act);
-      continue;
-    }
-    if (next_is_coarsest) break;  // a repeated exact solve of the same system is idempotent
-    // repeated visit from the current e: MG(rc, e) = e + MG(rc - K e, 0)
-    VecSet other{ecur.p == crs.e ? crs.d : crs.e, crs.N};
-    if (legs_fused(c, l + 1)) {
-      mg_cycle(c, B, l + 1, rc, ScaleSet{nullptr, 0}, other, true, act, ecur);
-      ecur = other;
-      continue;
-    }
-    VecSet rr{crs.rr, crs.N};
-    {
-      ProfScope ps(c, lvl_name("level_residual", l + 1), Bp * 24.0 * Nc1 + 8.0 * Nc1);
-      launch_level_residual(c->s, dim, B, rc, ecur, level_K(c, l + 1), rr, act);
-    }
-    mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, other, true, act);
-    ProfScope ps(c, lvl_name("add", l + 1), Bp * 24.0 * Nc1);
-    launch_add(c->s, B, other, ecur, crs.N, act);
-  }
+  const VecSet ecur = coarse_visits(c, B, l, act);
   if (fused && eres.p) {
     ProfScope ps(c, lvl_name("up_fused_res", l), Bp * 8.0 * (3.0 * Nf + Nc1) + 16.0 * Nf);
     launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l], eres);
@@ -431,8 +446,8 @@ void true_residual(helm_ctx* c, int B, int first, int conj_rhs) {
   k.bicg = use_bicg(c) ? 1 : 0;
   {
     ProfScope ps(c, "residual_ff", c->prof_B * (first ? 16.0 : 32.0) * c->N0 + (first ? 0.0 : 16.0 * c->N0));
-    launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_chi, c->d_clo,
-                       c->g0_hi, c->g0_lo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
+    launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_dhi, c->d_dlo,
+                       c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
   }
   ProfScope ps(c, "finalize", c->prof_B * k.nblk * 4.0);
   if (k.bicg) launch_bicg_finalize(c->s, B, k, first);
@@ -484,6 +499,37 @@ void sstep_basis(helm_ctx* c, int B) {
   const long long N0 = c->N0;
   const LevelArgs A = fine_A(c);
   const double Bp = c->prof_B, N = (double)N0;
+  if (c->o.fused_step && c->dim == 2 && legs_fused(c, 0)) {
+    // finest level: one down-leg, then per step the coarse visits and one fused
+    // kernel (up-leg of Z_j, W_{j+1} = A Z_j, down-leg of W_{j+1}); the last up-leg alone
+    const Level& L1 = c->lv[1];
+    const VecSet rc{L1.rc, L1.N};
+    const float om = (float)c->o.omega_jac;
+    const double Nc1 = (double)L1.N;
+    const VecSet v0{k.V, (long long)(k.m + 1) * N0};
+    {
+      ProfScope ps(c, "down_fused_l0", Bp * 8.0 * (N + Nc1) + 8.0 * N);
+      launch_down_fused2(c->s, B, v0, ScaleSet{k.vs, k.m + 1}, level_K(c, 0), om, rc, L1.n, k.active,
+                         c->tune_down[0]);
+    }
+    for (int j = 0; j < k.m; ++j) {
+      const VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
+      const VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
+      const ScaleSet sj{k.vs + j, k.m + 1};
+      const VecSet ecur = coarse_visits(c, B, 0, k.active);
+      if (j + 1 < k.m) {
+        const VecSet vn{k.V + (long long)(j + 1) * N0, (long long)(k.m + 1) * N0};
+        ProfScope ps(c, "step_fused_l0", Bp * (28.0 * N + 4.0 * Nc1) + 16.0 * N);
+        launch_step_fused2(c->s, B, vj, sj, level_K(c, 0), A, om, ecur, L1.n, zj, vn, rc, k.active);
+      } else {
+        ProfScope ps(c, "up_fused_l0", Bp * 8.0 * (2.0 * N + Nc1) + 8.0 * N);
+        launch_up_fused2(c->s, B, vj, sj, level_K(c, 0), om, ecur, L1.n, zj, k.active, c->tune_up[0]);
+      }
+    }
+    ProfScope ps(c, "sstep_gram", Bp * 8.0 * (k.m + 1.0) * N + 8.0 * N);
+    launch_sstep_gram_solve(c->s, B, k, A, c->d_gram);
+    return;
+  }
   for (int j = 0; j < k.m; ++j) {
     VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
     VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
@@ -613,14 +659,22 @@ void upload_medium(helm_ctx* c, const float* n_map_dev) {
   const helm_host::Geometry& g = c->geo;
   std::vector<cd> cf = helm_host::fine_coefficient(g, nm);
   const long long N0 = c->N0;
-  std::vector<c32> hi(N0), lo(N0);
+  std::vector<c32> hi(N0), dhi(N0), dlo(N0);
+  const cd gh(1.0, c->kbh);
   for (long long p = 0; p < N0; ++p) {
-    const float hr = (float)cf[p].real(), hm = (float)cf[p].imag();
-    hi[p] = make_float2(hr, hm);
-    lo[p] = make_float2((float)(cf[p].real() - hr), (float)(cf[p].imag() - hm));
+    hi[p] = to_c32(cf[p]);
+    // diagonal of A' (2d - c - #ghosts (1 + j k_b h)) in FP64, split into float-float
+    const int x = (int)(p % c->ne), y = (int)((p / c->ne) % c->ne), z = c->dim == 3 ? (int)(p / ((long long)c->ne * c->ne)) : 0;
+    int ng = (x == 0) + (x == c->ne - 1) + (y == 0) + (y == c->ne - 1);
+    if (c->dim == 3) ng += (z == 0) + (z == c->ne - 1);
+    const cd D = 2.0 * c->dim - cf[p] - (double)ng * gh;
+    const float dr = (float)D.real(), dm = (float)D.imag();
+    dhi[p] = make_float2(dr, dm);
+    dlo[p] = make_float2((float)(D.real() - dr), (float)(D.imag() - dm));
   }
   check(hipMemcpy(c->d_chi, hi.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload c");
-  check(hipMemcpy(c->d_clo, lo.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload c");
+  check(hipMemcpy(c->d_dhi, dhi.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload D");
+  check(hipMemcpy(c->d_dlo, dlo.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload D");
   // unscaled scattering potential f = k0^2 (eta^2 - eta_b^2) on Omega
   std::vector<float> fpl(N0, 0.0f);
   const double k02 = c->k0 * c->k0;
@@ -795,6 +849,7 @@ void helm_default_opts(helm_opts* o) {
   o->use_graph = 1;
   o->coarse_single_launch = 1;
   o->krylov = HELM_KRYLOV_SSTEP;
+  o->fused_step = 0;
 }
 
 int helm_extended_size(int n, int abl_width, int levels) { return helm_host::extended_size(n, abl_width, levels); }
@@ -853,7 +908,6 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     c->h2_hi = (float)h2;
     c->h2_lo = (float)(h2 - (double)c->h2_hi);
     c->g0_hi = make_float2(1.0f, (float)c->kbh);
-    c->g0_lo = make_float2(0.0f, (float)(c->kbh - (double)(float)c->kbh));
     const int maxB = o.max_batch, m = o.restart;
     const long long N0 = c->N0;
     c->lv.resize(c->L);
@@ -879,7 +933,8 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     c->d_nmap = c->alloc<float>(npts(c->n, c->dim));
     c->d_f = c->alloc<float>(N0);
     c->d_chi = c->alloc<c32>(N0);
-    c->d_clo = c->alloc<c32>(N0);
+    c->d_dhi = c->alloc<c32>(N0);
+    c->d_dlo = c->alloc<c32>(N0);
     c->d_xhi = c->alloc<c32>((size_t)maxB * N0);
     c->d_xlo = c->alloc<c32>((size_t)maxB * N0);
     c->d_rhs = c->alloc<c32>((size_t)maxB * N0);
@@ -1107,8 +1162,8 @@ int helm_residual(helm_ctx* c, int B, const helm_c32* rhs, const helm_c32* x_hi,
   KrylovArgs k = c->k;
   k.status = nullptr;
   k.P2 = nullptr;
-  launch_residual_ff(c->s, B, k, (const c32*)rhs, c->N0, 0, (const c32*)x_hi, (const c32*)x_lo, 0, c->d_chi,
-                     c->d_clo, c->g0_hi, c->g0_lo, c->h2_hi, c->h2_lo, (c32*)r, c->N0, (float)(1.0 / (c->h * c->h)));
+  launch_residual_ff(c->s, B, k, (const c32*)rhs, c->N0, 0, (const c32*)x_hi, (const c32*)x_lo, 0, c->d_dhi,
+                     c->d_dlo, c->h2_hi, c->h2_lo, (c32*)r, c->N0, (float)(1.0 / (c->h * c->h)));
   HELM_GUARD_END("residual")
 }
 
@@ -1408,6 +1463,10 @@ int helm_farfield_set(helm_ctx* c, int M, const double* sensors_host) {
   if (M > c->ff_M) {
     c->d_ffG = c->alloc<c32>((size_t)M * Ni);
     c->d_ff_part = c->alloc<c32>((size_t)ff_splits(Ni) * c->o.max_batch * M);
+    c->d_ff_iota = c->alloc<int>(M);
+    std::vector<int> iota(M);
+    for (int m = 0; m < M; ++m) iota[m] = m;
+    check(hipMemcpy(c->d_ff_iota, iota.data(), (size_t)M * sizeof(int), hipMemcpyHostToDevice), "iota");
     c->ff_M = M;
   }
   if (!c->d_ff_src) c->d_ff_src = c->alloc<c32>((size_t)c->o.max_batch * Ni);
@@ -1459,6 +1518,33 @@ int helm_farfield(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc
   launch_ff_forward(c->s, c->dim, B, c->ff_active_M, c->ne, c->w, c->n, c->d_f, (const c32*)u_in, (const c32*)u_sc,
                     c->d_ffG, c->d_ff_src, c->d_ff_part, (c32*)y);
   HELM_GUARD_END("farfield")
+}
+
+int helm_farfield_residual(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* y_meas,
+                           helm_c32* y, helm_c32* res, double* loss_host) {
+  if (!c || !u_sc || !y_meas || !y || !res) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
+  if (!c->ff_active_M) return fail(c, HELM_ESTATE, "no sensors: call helm_farfield_set first");
+  const int M = c->ff_active_M;
+  HELM_GUARD_BEGIN
+  launch_ff_forward(c->s, c->dim, B, M, c->ne, c->w, c->n, c->d_f, (const c32*)u_in, (const c32*)u_sc, c->d_ffG,
+                    c->d_ff_src, c->d_ff_part, (c32*)y);
+  const int nbk = data_residual_blocks(B, M);
+  if (nbk > c->inv_part_len) {
+    c->d_inv_part = c->alloc<double>(nbk);
+    c->inv_part_len = nbk;
+  }
+  // res = y - y_meas as the data residual of the identity "receivers" 0 .. M-1 of y
+  launch_data_residual(c->s, B, M, M, c->d_ff_iota, (const c32*)y, (const c32*)y_meas, (c32*)res, c->d_inv_part);
+  if (loss_host) {
+    std::vector<double> part(nbk);
+    check(hipMemcpyAsync(part.data(), c->d_inv_part, nbk * sizeof(double), hipMemcpyDeviceToHost, c->s), "loss");
+    check(hipStreamSynchronize(c->s), "sync");
+    double sum = 0.0;
+    for (double v : part) sum += v;
+    *loss_host = 0.5 * sum;
+  }
+  HELM_GUARD_END("farfield_residual")
 }
 
 int helm_farfield_adjoint(helm_ctx* c, int B, const helm_c32* r, helm_c32* s_ext, helm_c32* rhs_ext) {

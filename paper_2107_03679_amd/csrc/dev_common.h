@@ -18,12 +18,18 @@
 // the right-hand sides of a group fastest".  Neighbouring tiles of one field
 // (whose halos overlap) and one tile of g fields (which share the coefficient
 // tile) then run close together in time on the same L2.  Bijective on
-// [0, B T) for any B, T >= 1 and g >= 1.
+// [0, B T) for any B, T >= 1 and g >= 0 (g = 0: right-hand side fastest, no remap).
 #define HELM_XCDS 8u
 struct TileId {
   int b, t;
 };
 __host__ __device__ __forceinline__ TileId xcd_tile(unsigned id, unsigned B, unsigned T, unsigned g) {
+  if (g == 0) {  // plain order: right-hand side fastest, tiles in raster order
+    TileId o;
+    o.b = (int)(id % B);
+    o.t = (int)(id / B);
+    return o;
+  }
   const unsigned G = B * T, q = G / HELM_XCDS, r = G % HELM_XCDS, x = id % HELM_XCDS;
   const unsigned l = x * q + (x < r ? x : r) + id / HELM_XCDS;
   const unsigned span = g * T, grp = l / span, rem = l - grp * span;
@@ -33,8 +39,10 @@ __host__ __device__ __forceinline__ TileId xcd_tile(unsigned id, unsigned B, uns
   o.t = (int)(rem / gs);
   return o;
 }
-// right-hand sides per group in xcd_tile() for the field kernels
+// right-hand sides per group in xcd_tile() for the field kernels (0: the plain order)
+#ifndef HELM_RHS_GROUP
 #define HELM_RHS_GROUP 4u
+#endif
 
 
 // ---------------------------------------------------------------- complex64

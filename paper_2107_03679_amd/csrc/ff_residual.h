@@ -12,9 +12,8 @@ struct FFArgs {
   const c32* x_hi;
   const c32* x_lo;
   int x_zero;
-  const c32* c_hi;
-  const c32* c_lo;
-  c32 g_hi, g_lo;
+  const c32* d_hi;  // diagonal of A' (2d - c - #ghosts (1 + j k_b h)), float-float
+  const c32* d_lo;
   float h2_hi, h2_lo;
   c32* r_out;
   long long r_stride;
@@ -33,12 +32,7 @@ __host__ __device__ inline c32 ff_residual_point(const FFArgs& a, const c32* rb,
   if (a.conj_rhs) bv.y = -bv.y;
   cff r = {ff_mul(ff_from(bv.x), h2), ff_mul(ff_from(bv.y), h2)};
   if (xh) {
-    const int ng = ghosts_of(c, n, dim);
-    // D = 2d - c - ng g, in float-float
-    const cff cc = cff_make(a.c_hi[p], a.c_lo[p]);
-    const cff gg = cff_make(a.g_hi, a.g_lo);
-    const cff ngg = {ff_mul(ff_from((float)ng), gg.re), ff_mul(ff_from((float)ng), gg.im)};
-    const cff D = cff_sub(cff_sub({ff_from(2.0f * dim), ff_from(0.f)}, cc), ngg);
+    const cff D = cff_make(a.d_hi[p], a.d_lo[p]);
     cff ax = cff_mul(D, ff_load_x(xh, xl, p));
     cff nb = {ff_from(0.f), ff_from(0.f)};
     if (c.x > 0) nb = cff_add(nb, ff_load_x(xh, xl, p - 1));

@@ -494,6 +494,7 @@ __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, Level
 #pragma unroll
   for (int e = 0; e < NE; ++e) acc[e] = make_double2(0.0, 0.0);
   Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
+#pragma unroll 2
   for (int t = 0; t < PPT; ++t) {
     const long long p = p0 + (long long)t * NT;
     if (p < k.N) {
@@ -714,11 +715,9 @@ void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* 
   hipLaunchKernelGGL(k_x_update, dim3(k.nblk, B), dim3(NT), 0, s, k, x_hi, x_lo);
 }
 void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
-                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* c_hi,
-                        const c32* c_lo, c32 ghost_hi, c32 ghost_lo, float h2_hi, float h2_lo, c32* r_out,
-                        long long r_stride, float out_scale) {
-  FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, c_hi, c_lo, ghost_hi, ghost_lo, h2_hi, h2_lo, r_out,
-           r_stride, out_scale};
+                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* d_hi,
+                        const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale) {
+  FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, d_hi, d_lo, h2_hi, h2_lo, r_out, r_stride, out_scale};
   hipLaunchKernelGGL(k_residual_ff, dim3(B * k.nblk), dim3(NT), 0, s, B, k, a);
 }
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {

@@ -250,6 +250,153 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
   }
 }
 
+// ------------------------------------------------- fused finest-level step
+// One kernel for the finest-level work between two coarse-grid visits of
+// consecutive s-step basis vectors: the up-leg of step j, the basis matvec
+// W_{j+1} = A Z_j, and the down-leg of step j+1:
+//   v2 = W r + P e;  z = (1 - w) v2 + W (r + sum nb v2)          (Z_j, written)
+//   w  = A z                                                     (W_{j+1}, written)
+//   v1 = W w;  s = (1 - w) w + sum nb v1;  rc = 4 R s            (next coarse rhs, written)
+// on a TCX x TCY tile of coarse points of the next down-leg.  Relative to the
+// tile's first owned fine point, s is needed on [-1, 2T-1], v1 and w on
+// [-2, 2T], z on [-3, 2T+1], v2 (and r, W) on [-4, 2T+2]: each thread keeps
+// r, W and w of its points of that widest region in registers; v2/s and z/v1
+// share two LDS planes.  Fine points [0, 2T) of the tile are owned (written).
+// r = s_j W_j with its per-RHS scale; W_{j+1} is unscaled.
+template <int TCX, int TCY>
+__global__ __launch_bounds__(TCX* TCY) void k_step_fused2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
+                                                           LevelArgs la, float omega, VecSet ec, int nc, VecSet zout,
+                                                           VecSet wout, VecSet rc, const int* active) {
+  constexpr int RX = 2 * TCX + 7, RY = 2 * TCY + 7;  // widest region, origin (-4, -4)
+  constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
+  constexpr int CX = TCX + 4, CY = TCY + 4;          // coarse correction, origin (cx0 - 2, cy0 - 2)
+  __shared__ c32 sA[RY][RX];  // v2, then s
+  __shared__ c32 sB[RY][RX];  // z, then v1
+  __shared__ c32 sE[CY][CX];
+  const int n = lv.n;
+  const int tiles_x = (nc + TCX - 1) / TCX;
+  const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int cx0 = (id.t % tiles_x) * TCX, cy0 = (id.t / tiles_x) * TCY;
+  const int fx0 = 2 * cx0, fy0 = 2 * cy0;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  // ---- loads: r and W on the widest region (registers), the coarse correction (LDS)
+  c32 rv[IT], wv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 - 4 + idx % RX, gy = fy0 - 4 + idx / RX;
+    const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
+    const int I = cx0 - 2 + idx % CX, J = cy0 - 2 + idx / CX;
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+    sE[idx / CX][idx % CX] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // ---- v2 = W r + P e on [-4, 2T+2]  (0 outside the grid)
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = idx / RX;
+    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
+    c32 v2 = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const int I = (gx >> 1) - (cx0 - 2), J = (gy >> 1) - (cy0 - 2);
+      const int ox = gx & 1, oy = gy & 1;
+      c32 pe = sE[J][I];
+      if (ox && oy) pe = cscale(cadd(cadd(pe, sE[J][I + 1]), cadd(sE[J + 1][I], sE[J + 1][I + 1])), 0.25f);
+      else if (ox) pe = cscale(cadd(pe, sE[J][I + 1]), 0.5f);
+      else if (oy) pe = cscale(cadd(pe, sE[J + 1][I]), 0.5f);
+      v2 = cadd(cmul(rv[it], wv[it]), pe);
+    }
+    sA[ly][lx] = v2;
+  }
+  __syncthreads();
+  // ---- z = (1 - w) v2 + W (r + sum nb v2) on [-3, 2T+1]; Z_j on the owned points
+  c32* zb = zout.p + (long long)b * zout.stride;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx < 1 || lx > RX - 2 || ly < 1 || ly > RY - 2) continue;
+    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
+    c32 z = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const c32 nb = cadd(cadd(sA[ly][lx - 1], sA[ly][lx + 1]), cadd(sA[ly - 1][lx], sA[ly + 1][lx]));
+      z = cadd(cscale(sA[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+      if (lx >= 4 && lx < 4 + 2 * TCX && ly >= 4 && ly < 4 + 2 * TCY) zb[(long long)gy * n + gx] = z;
+    }
+    sB[ly][lx] = z;
+  }
+  __syncthreads();
+  // ---- w = A z on [-2, 2T]; W_{j+1} on the owned points (w kept in registers)
+  c32* wb = wout.p + (long long)b * wout.stride;
+  c32 wa[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    wa[it] = make_float2(0.f, 0.f);
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx < 2 || lx > RX - 3 || ly < 2 || ly > RY - 3) continue;
+    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const long long p = (long long)gy * n + gx;
+      const c32 D = diag_at(la, p, ghosts2(gx, gy, n), 2);
+      const c32 nb = cadd(cadd(sB[ly][lx - 1], sB[ly][lx + 1]), cadd(sB[ly - 1][lx], sB[ly + 1][lx]));
+      wa[it] = csub(cmul(D, sB[ly][lx]), nb);
+      if (lx >= 4 && lx < 4 + 2 * TCX && ly >= 4 && ly < 4 + 2 * TCY) wb[p] = wa[it];
+    }
+  }
+  __syncthreads();
+  // ---- v1 = W w on [-2, 2T] (into the z plane)
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx < 2 || lx > RX - 3 || ly < 2 || ly > RY - 3) continue;
+    sB[ly][lx] = cmul(wv[it], wa[it]);
+  }
+  __syncthreads();
+  // ---- s = (1 - w) w + sum nb v1 on [-1, 2T-1] (into the v2 plane; 0 outside the grid)
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx < 3 || lx > RX - 4 || ly < 3 || ly > RY - 4) continue;
+    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
+    c32 sv = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const c32 nb = cadd(cadd(sB[ly][lx - 1], sB[ly][lx + 1]), cadd(sB[ly - 1][lx], sB[ly + 1][lx]));
+      sv = cadd(cscale(wa[it], 1.0f - omega), nb);
+    }
+    sA[ly][lx] = sv;
+  }
+  __syncthreads();
+  // ---- rc = 4 R s at the tile's coarse points
+  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  const int I = cx0 + tx, J = cy0 + ty;
+  if (I < nc && J < nc) {
+    const int sx = 4 + 2 * tx, sy = 4 + 2 * ty;
+    c32 acc = cscale(sA[sy][sx], 4.0f);
+    acc = cadd(acc, cscale(cadd(cadd(sA[sy][sx - 1], sA[sy][sx + 1]), cadd(sA[sy - 1][sx], sA[sy + 1][sx])), 2.0f));
+    acc = cadd(acc, cadd(cadd(sA[sy - 1][sx - 1], sA[sy - 1][sx + 1]), cadd(sA[sy + 1][sx - 1], sA[sy + 1][sx + 1])));
+    rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
+  }
+}
+
 // ------------------------------------------------------------ generic (2D/3D)
 __global__ void k_jacobi_zero(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
                               const int* active) {
@@ -430,6 +577,14 @@ void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float om
                        omega, ec, nc, z, active, e);
 }
 }  // namespace
+
+void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
+                        VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active) {
+  constexpr int TCX = 16, TCY = 16;
+  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+  hipLaunchKernelGGL((k_step_fused2<TCX, TCY>), dim3(B * tiles), dim3(TCX * TCY), 0, s, B, r, rs, lv, la, omega, ec,
+                     nc, z, w, rc, active);
+}
 
 int mg_down_variants() { return (int)(sizeof(kDown) / sizeof(kDown[0])); }
 int mg_up_variants() { return (int)(sizeof(kUp) / sizeof(kUp[0])); }

@@ -42,6 +42,10 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                         const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
+// finest-level step of the s-step basis (2D): up-leg of Z_j, W_{j+1} = A Z_j (la = the A
+// operator), down-leg of W_{j+1} into rc; one launch
+void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
+                        VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active);
 int mg_down_variants();
 int mg_up_variants();
 void mg_down_shape(int cfg, int* tcx, int* tcy);
@@ -119,9 +123,8 @@ void launch_arnoldi_update(hipStream_t s, int B, const KrylovArgs& k, int j);
 void launch_givens(hipStream_t s, int B, const KrylovArgs& k, int j);
 void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo);
 void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
-                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* c_hi,
-                        const c32* c_lo, c32 ghost_hi, c32 ghost_lo, float h2_hi, float h2_lo, c32* r_out,
-                        long long r_stride, float out_scale);
+                        int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* d_hi,
+                        const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale);
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
 void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
                    int* fallbacks, VecSet resid);

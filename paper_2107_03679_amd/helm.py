@@ -43,7 +43,7 @@ class HelmOpts(ctypes.Structure):
         ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("cycle", ctypes.c_int),
         ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("reorth", ctypes.c_int), ("fused", ctypes.c_int), ("use_graph", ctypes.c_int),
-        ("coarse_single_launch", ctypes.c_int), ("krylov", ctypes.c_int),
+        ("coarse_single_launch", ctypes.c_int), ("krylov", ctypes.c_int), ("fused_step", ctypes.c_int),
     ]
 
 
@@ -79,7 +79,7 @@ EXPORTS = [
     "helm_net_set_layer", "helm_net_get_layer", "helm_net_get_grad", "helm_net_forward", "helm_net_backward",
     "helm_net_adam_step", "helm_net_set_loss", "helm_autotune", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
     "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
-    "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield",
+    "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
 ]
 
 _lib = None
@@ -147,6 +147,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_farfield.argtypes = [vp, i, vp, vp, vp]
     lib.helm_farfield_adjoint.argtypes = [vp, i, vp, vp, vp]
     lib.helm_grad_f_farfield.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    lib.helm_farfield_residual.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(d)]
     lib.helm_last_error.argtypes = [vp]
     lib.helm_last_error.restype = ctypes.c_char_p
     lib.helm_destroy.argtypes = [vp]
@@ -338,6 +339,16 @@ class Context:
         y = torch.empty((u_sc.shape[0], self.n_sensors), dtype=torch.complex64, device=self.device)
         self._check(self.lib.helm_farfield(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(y)), "helm_farfield")
         return y
+
+    def farfield_residual(self, u_sc: torch.Tensor, y_meas: torch.Tensor, u_in: torch.Tensor | None = None):
+        """(y = G~ f u, y - y_meas, 1/2 ||y - y_meas||^2)."""
+        B = u_sc.shape[0]
+        y = torch.empty((B, self.n_sensors), dtype=torch.complex64, device=self.device)
+        res = torch.empty_like(y)
+        loss = ctypes.c_double()
+        self._check(self.lib.helm_farfield_residual(self._h, B, _ptr(u_in), _ptr(u_sc), _ptr(y_meas.contiguous()),
+                                                    _ptr(y), _ptr(res), ctypes.byref(loss)), "helm_farfield_residual")
+        return y, res, loss.value
 
     def farfield_adjoint(self, r: torch.Tensor):
         """(G~^H r on Omega, f G~^H r) as fields on the extended grid."""

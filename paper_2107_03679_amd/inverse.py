@@ -28,9 +28,11 @@ class FBSLog:
 
 
 class FBSReconstruction:
-    """State of Alg. 4: f, fbar, alpha; the data y [Q, M] at receivers rx_idx (flat grid indices)."""
+    """State of Alg. 4: f, fbar, alpha; the data y [Q, M] either at on-grid receivers rx_idx
+    (flat grid indices) or, with rx_idx None, at the far-field sensors of ctx.farfield_set
+    (the sensor operator G~ of eq. DiscreteForwardHelm)."""
 
-    def __init__(self, ctx: Context, dirs: np.ndarray, rx_idx: torch.Tensor, y: torch.Tensor, gamma: float,
+    def __init__(self, ctx: Context, dirs: np.ndarray, rx_idx: torch.Tensor | None, y: torch.Tensor, gamma: float,
                  tau: float, prox_iters: int = 50, subset: int | None = None, seed: int = 0,
                  f0: torch.Tensor | None = None):
         self.ctx, self.dirs, self.rx, self.y = ctx, np.asarray(dirs, dtype=np.float64), rx_idx, y
@@ -53,7 +55,15 @@ class FBSReconstruction:
         if not st.converged:
             raise RuntimeError(f"forward solves did not converge: {st}")
         sel_t = torch.as_tensor(sel, device=self.y.device)
-        res, loss = ctx.data_residual(self.rx, usc, self.y.index_select(0, sel_t).contiguous())
+        y_sel = self.y.index_select(0, sel_t).contiguous()
+        if self.rx is None:  # far-field sensors: grad = Re(conj(u) (s + A^-H f s)), s = G~^H r
+            _, res, loss = ctx.farfield_residual(usc, y_sel, u_in=uin)
+            s, arhs = ctx.farfield_adjoint(res)
+            lam, st_a = ctx.adjoint(arhs)
+            if not st_a.converged:
+                raise RuntimeError(f"adjoint solves did not converge: {st_a}")
+            return ctx.grad_f_farfield(usc, lam, s, u_in=uin), loss, float(st.iters.mean())
+        res, loss = ctx.data_residual(self.rx, usc, y_sel)
         lam, st_a = ctx.adjoint(ctx.sample_adjoint(self.rx, res))
         if not st_a.converged:
             raise RuntimeError(f"adjoint solves did not converge: {st_a}")

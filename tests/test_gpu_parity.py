@@ -200,6 +200,32 @@ def test_sstep_and_fgmres_reach_the_same_solution(case, m):
     assert abs(-(-out[helm.KRYLOV_FGMRES].iters[0] // m) - cycles) <= 1
 
 
+@pytest.mark.parametrize("case,cycle", [("small", 3), ("ragged", 3), ("ragged", 1)])
+def test_fused_finest_step_matches_separate_kernels(case, cycle):
+    """The s-step basis with its finest-level work fused into one kernel per step (up-leg,
+    basis matvec, next down-leg) against the same basis from the separate kernels: the
+    same exact solution and the same restart cycles (up to one: the matvec's sum order differs)."""
+    n, w, levels = CASES[case]
+    print(f"\n[fused finest step: {case} cycle={cycle}]", flush=True)
+    nmap = medium(n, seed=23)
+    prob = oracle_problem(nmap, w=w, levels=levels)
+    ex = model.ExactSolver(prob)
+    dirs = synth.directions_2d(3)
+    out = {}
+    for fs in (1, 0):
+        ctx = gpu_context(nmap, w=w, levels=levels, max_batch=3, restart=5, cycle=cycle, fused_step=fs)
+        rhs = ctx.plane_wave_rhs(dirs)
+        x, st = ctx.solve(rhs)
+        assert st.converged and np.all(st.rel_res_true <= 1e-6), (fs, st)
+        b = to_np(rhs)
+        for q in range(3):
+            assert rel(to_np(x)[q], ex.solve(b[q])) < 1e-5, (fs, q)
+        out[fs] = (to_np(x), st)
+        ctx.close()
+    assert rel(out[1][0], out[0][0]) < 2e-5
+    assert np.all(np.abs(out[1][1].iters - out[0][1].iters) <= 5), (out[1][1].iters, out[0][1].iters)
+
+
 @pytest.mark.parametrize("case", ["small", "ragged"])
 def test_bicgstab_alg3_matches_exact_solution(case):
     """The paper's Alg. 3 (batched Bi-CGSTAB, two cycles per iteration): the exact solution to
