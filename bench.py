@@ -42,6 +42,7 @@ def parse():
                    help="GMRES(m) in s-step form (Gram matrix + Cholesky QR), as FGMRES (Arnoldi), or the "
                         "paper's Bi-CGSTAB (restart = iterations between status checks)")
     p.add_argument("--rhs", type=int, default=None, help="override the number of plane waves")
+    p.add_argument("--max-iters", type=int, default=20000, help="cap on multigrid cycles per solve")
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--no-tune", action="store_true", help="keep the default multigrid launch shapes")
     p.add_argument("--tune-cache", default=None, help="JSON-lines cache of the autotuner's choices")
@@ -248,7 +249,7 @@ def main():
     t_setup = time.perf_counter()
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
                        levels=args.levels, restart=args.restart, cycle=args.cycle, reorth=args.reorth, max_batch=B,
-                       max_iters=20000, use_graph=0 if args.no_graph else 1, fused_step=1 if args.fused_step else 0,
+                       max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=1 if args.fused_step else 0,
                        krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
                                "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
     torch.cuda.synchronize()

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(HELM_WAVE) void k_bicg_sigma(KrylovArgs k) {
 
 // x += alpha y + sigma z (float-float);  r = s - sigma t;  partials <r^, r>, ||r||^2
 __global__ __launch_bounds__(NT) void k_bicg_update(int nrhs, KrylovArgs k, c32* x_hi, c32* x_lo) {
-  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, 1);
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
   const int b = id.b, blk = id.t;
   if (!k.active[b]) return;
   const long long p0 = (long long)blk * CH + threadIdx.x;
