@@ -60,6 +60,29 @@ def parse():
     return p.parse_args()
 
 
+def recorded_traffic(kernel, cfg):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE record in
+    profiles/ (scaled by the copy calibration); None unless the record is for this kernel and
+    launch configuration and the kernel sources are unchanged since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_blobs512x60.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("config") != cfg:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def copy_probe(mib):
     """Plain device copy of `mib` MiB, three times: achievable HBM bandwidth (read + write bytes / time)."""
     import torch
@@ -324,9 +347,13 @@ def main():
         total = sum(v[0] for v in rep.values())
         name, (ms, n, by) = max(rep.items(), key=lambda kv: kv[1][0])
         achieved = by / (ms * 1e-3) / 1e9
+        cfg = {"workload": args.workload, "rhs": B, "levels": args.levels, "restart": args.restart,
+               "cycle": args.cycle, "krylov": args.krylov, "fused_step": bool(args.fused_step)}
+        traffic = recorded_traffic(name, cfg)
         out["roofline"] = {
             "bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBs": None if traffic is None else traffic * n / (ms * 1e-3) / 1e9,
             "avg_launch_us": 1000.0 * ms / n, "bytes_per_launch": by / n, "share_of_step": ms / total,
         }
         if probe is not None:

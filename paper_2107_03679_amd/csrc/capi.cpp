@@ -352,8 +352,15 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
       }
     }
     relax(c, B, l, r, rs, out, sweeps, act);
-    ProfScope ps(c, lvl_name("restrict_residual", l), Bp * (16.0 * Nf + 8.0 * Nc1) + 8.0 * Nf);
-    launch_restrict_residual(c->s, dim, B, r, rs, out, level_K(c, l), rc, crs.n, act);
+    // residual once per fine point into the level scratch, then a plain full weighting
+    const VecSet t{l == 0 ? c->d_T0 : fine.t, fine.N};
+    {
+      ProfScope ps(c, lvl_name("level_residual", l), Bp * 24.0 * Nf + 8.0 * Nf);
+      launch_level_residual(c->s, dim, B, r, out, level_K(c, l), t, act, rs);
+    }
+    ProfScope ps(c, lvl_name("restrict", l), Bp * (8.0 * Nf + 8.0 * Nc1));
+    launch_restrict_residual(c->s, dim, B, t, ScaleSet{nullptr, 0}, VecSet{nullptr, 0}, level_K(c, l), rc, crs.n,
+                             act);
   }
   const VecSet ecur = coarse_visits(c, B, l, act);
   if (fused && eres.p) {
@@ -362,12 +369,21 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   } else if (fused) {
     ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
     launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l]);
-  } else {
+  } else if (c->o.nu2 > 0) {
+    // prolongation into the scratch, so that the first post-smoothing sweep writes `out` directly
+    const VecSet t{l == 0 ? c->d_T0 : fine.t, fine.N};
     {
       ProfScope ps(c, lvl_name("prolong_add", l), Bp * (16.0 * Nf + 8.0 * Nc1));
-      launch_prolong_add(c->s, dim, B, ecur, crs.n, out, fine.n, act);
+      launch_prolong_add(c->s, dim, B, ecur, crs.n, out, fine.n, act, t);
     }
-    relax(c, B, l, r, rs, out, c->o.nu2, act);
+    {
+      ProfScope ps(c, lvl_name("jacobi", l), Bp * 24.0 * Nf + 8.0 * Nf);
+      launch_jacobi(c->s, dim, B, r, rs, level_K(c, l), (float)c->o.omega_jac, t, out, act);
+    }
+    relax(c, B, l, r, rs, out, c->o.nu2 - 1, act);
+  } else {
+    ProfScope ps(c, lvl_name("prolong_add", l), Bp * (16.0 * Nf + 8.0 * Nc1));
+    launch_prolong_add(c->s, dim, B, ecur, crs.n, out, fine.n, act);
   }
 }
 

@@ -184,9 +184,9 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double zabs(double2 a) { return hypot(a.x, a.y); }
 
-// Back-substitution y = H(0:kk, 0:kk)^-1 g(0:kk) for right-hand side b (FP64, one thread).
-__device__ void back_substitute(const KrylovArgs& k, int b, int kk) {
-  double2 yd[MAXM];
+// Back-substitution y = H(0:kk, 0:kk)^-1 g(0:kk) for right-hand side b (FP64, one thread;
+// yd: kk FP64 slots in LDS, where a per-thread array indexed at run time would spill).
+__device__ void back_substitute(const KrylovArgs& k, int b, int kk, double2* yd) {
   const double2* H = k.H + (long long)b * (k.m + 1) * k.m;
   const double2* g = k.g + (long long)b * (k.m + 1);
   for (int i = kk - 1; i >= 0; --i) {
@@ -206,6 +206,7 @@ __device__ void back_substitute(const KrylovArgs& k, int b, int kk) {
 
 // Givens update of column j (FP64), residual estimate, stop decision, least squares at cycle end.
 __global__ __launch_bounds__(HELM_WAVE) void k_givens(KrylovArgs k, int j) {
+  __shared__ double2 yd[MAXM];
   const int b = blockIdx.x;
   if (!k.active[b]) return;
   double s = 0.0;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(HELM_WAVE) void k_givens(KrylovArgs k, int j) {
   k.vs[b * (m + 1) + j + 1] = hj1 > 0.0 ? (float)(1.0 / hj1) : 0.0f;
   const bool stop = est <= k.tol[b] || hj1 == 0.0 || it >= k.max_iters;
   if (stop) k.active[b] = 0;
-  if (stop || j == m - 1) back_substitute(k, b, j + 1);
+  if (stop || j == m - 1) back_substitute(k, b, j + 1, yd);
 }
 
 // x += sum_{i < jcount} y_i Z_i, accumulated into the float-float pair (x_hi, x_lo)
@@ -542,6 +543,8 @@ template <int M>
 __global__ __launch_bounds__(HELM_WAVE) void k_sstep_solve(KrylovArgs k, const double2* part) {
   constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
   __shared__ double2 G[NE];
+  __shared__ double2 R[NV][NV];  // Cholesky factor (LDS: a per-thread array of this size would spill)
+  __shared__ double2 yd[M];
   const int b = blockIdx.x;
   if (!k.active[b]) return;
   for (int e = 0; e < NE; ++e) {
@@ -560,7 +563,6 @@ __global__ __launch_bounds__(HELM_WAVE) void k_sstep_solve(KrylovArgs k, const d
   const int m = k.m;
   // packed index of (i, j), i <= j
   auto gi = [](int i, int j) { return i * NV - i * (i - 1) / 2 + (j - i); };
-  double2 R[NV][NV];
   int keep = NV;  // usable leading columns of W
   bool finite = true;
   for (int j = 0; j < NV && keep == NV; ++j) {
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(HELM_WAVE) void k_sstep_solve(KrylovArgs k, const d
   }
   k.jcount[b] = kstar;
   k.active[b] = 0;
-  back_substitute(k, b, kstar);
+  back_substitute(k, b, kstar, yd);
 }
 
 __global__ void k_status_init(KrylovArgs k, int B) {

@@ -456,7 +456,9 @@ __global__ void k_restrict_residual(int dim, VecSet r, ScaleSet rs, VecSet v, Le
   rc.p[(long long)b * rc.stride + q] = cscale(acc, 4.0f);
 }
 
-__global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, int n, long long N, const int* active) {
+// vout = v + P ec (vout may be v)
+__global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, VecSet vout, int n, long long N,
+                              const int* active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,13 +474,15 @@ __global__ void k_prolong_add(int dim, VecSet ec, int nc, VecSet v, int n, long 
         float wgt = ((f.x & 1) ? 0.5f : 1.0f) * ((f.y & 1) ? 0.5f : 1.0f) * (oz ? 0.5f : 1.0f);
         acc = cadd(acc, cscale(eb[((long long)K * nc + J) * nc + I], wgt));
       }
-  c32* vb = v.p + (long long)b * v.stride;
-  vb[p] = cadd(vb[p], acc);
+  const c32* vb = v.p + (long long)b * v.stride;
+  vout.p[(long long)b * vout.stride + p] = cadd(vb[p], acc);
 }
 
-// out = b - K v on a level (the right-hand side of a repeated coarse visit:
-// MG(b, v) = v + MG(b - K v, 0) for the affine multigrid cycle)
-__global__ void k_level_residual(int dim, VecSet bvec, VecSet v, LevelArgs lv, VecSet out, const int* active) {
+// out = s_b b - K v on a level (the right-hand side of a repeated coarse visit:
+// MG(b, v) = v + MG(b - K v, 0) for the affine multigrid cycle; the residual
+// ahead of a restriction in the generic legs)
+__global__ void k_level_residual(int dim, VecSet bvec, ScaleSet bs, VecSet v, LevelArgs lv, VecSet out,
+                                 const int* active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -487,7 +491,7 @@ __global__ void k_level_residual(int dim, VecSet bvec, VecSet v, LevelArgs lv, V
   const c32* vb = v.p + (long long)b * v.stride;
   const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
   const c32 kv = csub(cmul(D, vb[p]), neighbour_sum(vb, p, c, lv.n, dim));
-  out.p[(long long)b * out.stride + p] = csub(bvec.p[(long long)b * bvec.stride + p], kv);
+  out.p[(long long)b * out.stride + p] = csub(cscale(bvec.p[(long long)b * bvec.stride + p], scale_of(bs, b)), kv);
 }
 
 // y += x for every active right-hand side
@@ -638,9 +642,11 @@ void launch_restrict_residual(hipStream_t s, int dim, int B, VecSet r, ScaleSet 
                      active);
 }
 
-void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active) {
+void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active,
+                        VecSet vout) {
   const long long N = dim == 2 ? (long long)n * n : (long long)n * n * n;
-  hipLaunchKernelGGL(k_prolong_add, dim3(nblocks(N, 256), B), dim3(256), 0, s, dim, ec, nc, v, n, N, active);
+  hipLaunchKernelGGL(k_prolong_add, dim3(nblocks(N, 256), B), dim3(256), 0, s, dim, ec, nc, v, vout.p ? vout : v, n,
+                     N, active);
 }
 
 void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active) {
@@ -653,8 +659,9 @@ void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArg
 }
 
 void launch_level_residual(hipStream_t s, int dim, int B, VecSet bvec, VecSet v, LevelArgs lv, VecSet out,
-                           const int* active) {
-  hipLaunchKernelGGL(k_level_residual, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, bvec, v, lv, out, active);
+                           const int* active, ScaleSet bs) {
+  hipLaunchKernelGGL(k_level_residual, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, bvec, bs, v, lv, out,
+                     active);
 }
 
 void launch_add(hipStream_t s, int B, VecSet x, VecSet y, long long N, const int* active) {

@@ -56,12 +56,15 @@ void launch_jacobi(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelAr
                    VecSet vout, const int* active);
 void launch_restrict_residual(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, VecSet v, LevelArgs lv,
                               VecSet rc, int nc, const int* active);
-void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active);
+// v (or vout when given) = v + P ec
+void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active,
+                        VecSet vout = VecSet{nullptr, 0});
 void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active);
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active);
+// out = s_b bvec - K v (bs = per-RHS scale of bvec, NULL = 1)
 void launch_level_residual(hipStream_t s, int dim, int B, VecSet bvec, VecSet v, LevelArgs lv, VecSet out,
-                           const int* active);
+                           const int* active, ScaleSet bs = ScaleSet{nullptr, 0});
 void launch_add(hipStream_t s, int B, VecSet x, VecSet y, long long N, const int* active);
 
 // ---- coarse levels of a V-cycle in one launch (one workgroup per right-hand side) ----
