@@ -99,7 +99,7 @@ typedef struct {
   int max_iters;    /* max preconditioner applications per RHS (4000) */
   int max_batch;    /* largest B accepted by the solve calls (64) */
   int reorth;       /* 1 = one re-orthogonalisation pass (CGS2) (0) */
-  int fused;        /* 1 = fused multigrid leg kernels when nu1 = nu2 = 1 (1) */
+  int fused;        /* 1 = fused multigrid leg kernels (2D and 3D) when nu1 = nu2 = 1 (1) */
   int use_graph;    /* 1 = replay each restart cycle as a captured hipGraph (1) */
   int coarse_single_launch; /* 1 = V-cycle levels with <= 48^2 (2D) / 16^3 (3D) points run
                                in one launch, one workgroup per right-hand side (1) */

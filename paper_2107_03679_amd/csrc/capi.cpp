@@ -242,7 +242,9 @@ long long coarse_small(const helm_ctx* c) {
 }
 
 // True when a zero-guess visit of level l on the level's own (unscaled) buffers
-// runs the fused 2D legs (not the coarsest solve, not the single-launch coarse cycle).
+// runs the fused 2D legs (not the coarsest solve, not the single-launch coarse
+// cycle); repeated visits from a nonzero start use them.  The fused 3D legs take
+// zero-guess visits only.
 bool legs_fused(const helm_ctx* c, int l) {
   if (l >= c->L - 1 || !c->o.fused || c->dim != 2 || c->o.nu1 != 1 || c->o.nu2 != 1) return false;
   const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
@@ -331,10 +333,13 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   Level& crs = c->lv[l + 1];
   VecSet rc{crs.rc, crs.N}, ec{crs.e, crs.N};
   const float om = (float)c->o.omega_jac;
-  const bool fused = c->o.fused && dim == 2 && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
+  const bool fused = c->o.fused && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
   const double Nf = (double)fine.N, Nc1 = (double)crs.N, Bp = c->prof_B;
-  if (eres.p && !fused) throw HipError{hipErrorInvalidValue, "repeated visit outside the fused legs"};
-  if (fused && eres.p) {
+  if (eres.p && (!fused || dim != 2)) throw HipError{hipErrorInvalidValue, "repeated visit outside the fused 2D legs"};
+  if (fused && dim == 3) {
+    ProfScope ps(c, lvl_name("down_fused", l), Bp * 8.0 * (Nf + Nc1) + 8.0 * Nf);
+    launch_down_fused3(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act);
+  } else if (fused && eres.p) {
     ProfScope ps(c, lvl_name("down_fused_res", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 16.0 * Nf);
     launch_down_fused2(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act, c->tune_down[l], eres);
   } else if (fused) {
@@ -363,7 +368,10 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
                              act);
   }
   const VecSet ecur = coarse_visits(c, B, l, act);
-  if (fused && eres.p) {
+  if (fused && dim == 3) {
+    ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
+    launch_up_fused3(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act);
+  } else if (fused && eres.p) {
     ProfScope ps(c, lvl_name("up_fused_res", l), Bp * 8.0 * (3.0 * Nf + Nc1) + 16.0 * Nf);
     launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l], eres);
   } else if (fused) {

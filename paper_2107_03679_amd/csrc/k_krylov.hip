@@ -481,6 +481,133 @@ __global__ __launch_bounds__(NT) void k_sstep_matvec(int nrhs, KrylovArgs k, int
 // numbers up to ~1e6 at m = 12) and the Cholesky factor of G loses the
 // square of that, so G must be the Gram matrix of the stored vectors to
 // FP64 accuracy.
+#ifndef HELM_GRAM_LDS
+#define HELM_GRAM_LDS 1
+#endif
+#if HELM_GRAM_LDS
+// Entry e of the packed upper triangle of an nv x nv matrix is (packed_row,
+// packed_col); the loops fold to constants where e does.
+__host__ __device__ constexpr int packed_row(int e, int nv) {
+  int i = 0;
+  while (e >= nv - i) e -= nv - i++;
+  return i;
+}
+__host__ __device__ constexpr int packed_col(int e, int nv) {
+  int i = 0;
+  while (e >= nv - i) e -= nv - i++;
+  return i + e;
+}
+
+#ifndef HELM_GRAM_GP
+#define HELM_GRAM_GP 128
+#endif
+constexpr int GP = HELM_GRAM_GP;  // points staged per step
+
+// acc[U] += conj(w_i) w_j for the entry e = G + U NWAVE = (i, j) and the ones after it
+template <int NV, int G, int U>
+__device__ __forceinline__ void gram_entries(double2* acc, const double2* wd) {
+  constexpr int NE = NV * (NV + 1) / 2, e = G + U * NWAVE;
+  if constexpr (e < NE) {
+    constexpr int i = packed_row(e, NV), j = packed_col(e, NV);
+    acc[U].x = fma(wd[i].x, wd[j].x, fma(wd[i].y, wd[j].y, acc[U].x));
+    acc[U].y = fma(wd[i].x, wd[j].y, fma(-wd[i].y, wd[j].x, acc[U].y));
+    gram_entries<NV, G, U + 1>(acc, wd);
+  }
+}
+
+// Wave G of the block accumulates the entries e = G, G + NWAVE, ... of the
+// packed triangle over the staged points (lanes q and q + 64).
+template <int M, int G>
+__device__ __forceinline__ void gram_accumulate(double2* acc, const c32 (*buf)[GP], int lane) {
+  constexpr int NV = M + 1;
+#pragma unroll 1
+  for (int h = 0; h < GP / HELM_WAVE; ++h) {
+    const int q = lane + h * HELM_WAVE;
+    double2 wd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const c32 w = buf[v][q];
+      wd[v] = make_double2((double)w.x, (double)w.y);
+    }
+    gram_entries<NV, G, 0>(acc, wd);
+  }
+}
+
+// Block partials of the Gram matrix of (s_0 W_0, W_1, .., W_{M-1}, A Z_{M-1}):
+// the last basis vector is formed in registers and never stored.  Entry
+// (i, j), i <= j, in packed upper order, is sum conj(w_i) w_j, accumulated in
+// FP64 from the first product: the basis is far from orthogonal (condition
+// numbers up to ~1e6 at m = 12) and the Cholesky factor of G loses the
+// square of that, so G must be the Gram matrix of the stored vectors to
+// FP64 accuracy.  The block stages GP points of all M + 1 vectors in LDS
+// (the next step's loads in flight meanwhile); each wave keeps a quarter of
+// the entries, so the FP64 accumulators fit with several waves per SIMD.
+template <int M>
+__global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, LevelArgs fine, double2* part) {
+  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2, NU = (NE + NWAVE - 1) / NWAVE;
+  constexpr int ITEMS = (NV * GP + NT - 1) / NT, STEPS = CH / GP;
+  static_assert(CH % GP == 0 && GP % HELM_WAVE == 0, "staging shape");
+  __shared__ c32 buf[2][NV][GP];
+  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
+  const int b = id.b, blk = id.t;
+  if (!k.active[b]) return;
+  const float s0 = k.vs[b * (k.m + 1)];
+  const long long p0 = (long long)blk * CH;
+  const c32* z = k.Z + zidx(k, b, M - 1);
+  const c32* vb = k.V + vidx(k, b, 0);
+  // item it of this thread: vector v = idx / GP (uniform per wave), point q = idx % GP
+  auto load = [&](int step, c32* out) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int v = idx / GP, q = idx % GP;
+      const long long p = p0 + (long long)step * GP + q;
+      c32 w = make_float2(0.f, 0.f);
+      if (v < M) {
+        if (p < k.N) w = vb[(long long)v * k.N + p];
+        if (v == 0) w = cscale(w, s0);
+      } else if (v == M && p < k.N) {
+        const Coord c = coord_of32((unsigned)p, (unsigned)fine.n, k.dim);
+        w = stencil_point(z, p, c, fine.n, k.dim, diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim));
+      }
+      out[it] = w;
+    }
+  };
+  auto store = [&](int slot, const c32* in) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NV * GP) buf[slot][idx / GP][idx % GP] = in[it];
+    }
+  };
+  double2 acc[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) acc[u] = make_double2(0.0, 0.0);
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  const int steps = (int)min((long long)STEPS, (k.N - p0 + GP - 1) / GP);
+  c32 pre[ITEMS];
+  load(0, pre);
+  for (int st = 0; st < steps; ++st) {
+    store(st & 1, pre);
+    if (st + 1 < steps) load(st + 1, pre);
+    __syncthreads();
+    const c32(*cur)[GP] = buf[st & 1];
+    switch (wave) {
+      case 0: gram_accumulate<M, 0>(acc, cur, lane); break;
+      case 1: gram_accumulate<M, 1>(acc, cur, lane); break;
+      case 2: gram_accumulate<M, 2>(acc, cur, lane); break;
+      default: gram_accumulate<M, 3>(acc, cur, lane); break;
+    }
+  }
+  static_assert(NWAVE == 4, "one entry group per wave");
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = wave + u * NWAVE;
+    const double sx = wave_sum_d(acc[u].x), sy = wave_sum_d(acc[u].y);
+    if (lane == 0 && e < NE) part[((long long)b * k.nblk + blk) * NE + e] = make_double2(sx, sy);
+  }
+}
+#else
 template <int M>
 __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, LevelArgs fine, double2* part) {
   constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
@@ -532,6 +659,7 @@ __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, Level
     part[((long long)b * k.nblk + blk) * NE + e] = sum;
   }
 }
+#endif
 
 // Per right-hand side (one wavefront): reduce the Gram partials (FP64, fixed
 // order), Cholesky G = R^H R, Givens rotations of the Hessenberg R[:, 1:],

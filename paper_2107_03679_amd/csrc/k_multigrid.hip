@@ -250,6 +250,150 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
   }
 }
 
+// ------------------------------------------------------------ fused 3D legs
+// The 2D legs' arithmetic with the 7-point operator, 27-point full weighting
+// (weights (1/4, 1/2, 1/4) per axis) and trilinear prolongation.
+// Down-leg on a TCX x TCY x TCZ tile of coarse points: r, W on the fine region
+// with a two-point halo (origin 2 c0 - 2), v1 = W r -> LDS; s on the region's
+// interior -> LDS; rc = 4 R s.
+template <int TCX, int TCY, int TCZ>
+__global__ __launch_bounds__(TCX* TCY* TCZ) void k_down_fused3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
+                                                                float omega, VecSet rc, int nc, const int* active) {
+  constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3, RZ = 2 * TCZ + 3;
+  constexpr int SX = RX - 2, SY = RY - 2, SZ = RZ - 2;
+  constexpr int NT = TCX * TCY * TCZ, NR = RX * RY * RZ, IT = (NR + NT - 1) / NT;
+  __shared__ c32 sV[RZ][RY][RX];
+  __shared__ c32 sS[SZ][SY][SX];
+  const int n = lv.n;
+  const int tx_n = (nc + TCX - 1) / TCX, ty_n = (nc + TCY - 1) / TCY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((nc + TCZ - 1) / TCZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int cx0 = (id.t % tx_n) * TCX, cy0 = ((id.t / tx_n) % ty_n) * TCY, cz0 = (id.t / (tx_n * ty_n)) * TCZ;
+  const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2, fz0 = 2 * cz0 - 2;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const long long n2 = (long long)n * n;
+  c32 rv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
+    const int gx = fx0 + lx, gy = fy0 + ly, gz = fz0 + lz;
+    const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+    const long long p = ok ? gz * n2 + (long long)gy * n + gx : 0;
+    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    const c32 wv = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    if (idx < NR) sV[lz][ly][lx] = cmul(rv[it], wv);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NR) continue;
+    const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
+    if (lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1 || lz == 0 || lz == RZ - 1) continue;
+    const int gx = fx0 + lx, gy = fy0 + ly, gz = fz0 + lz;
+    c32 sv = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
+      const c32 nb = cadd(cadd(cadd(sV[lz][ly][lx - 1], sV[lz][ly][lx + 1]), cadd(sV[lz][ly - 1][lx], sV[lz][ly + 1][lx])),
+                          cadd(sV[lz - 1][ly][lx], sV[lz + 1][ly][lx]));
+      sv = cadd(cscale(rv[it], 1.0f - omega), nb);
+    }
+    sS[lz - 1][ly - 1][lx - 1] = sv;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TCX, ty = (threadIdx.x / TCX) % TCY, tz = threadIdx.x / (TCX * TCY);
+  const int I = cx0 + tx, J = cy0 + ty, K = cz0 + tz;
+  if (I < nc && J < nc && K < nc) {
+    const float w1[3] = {0.25f, 0.5f, 0.25f};
+    c32 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          acc = cadd(acc, cscale(sS[2 * tz + dz][2 * ty + dy][2 * tx + dx], w1[dx] * w1[dy] * w1[dz]));
+    rc.p[(long long)b * rc.stride + ((long long)K * nc + J) * nc + I] = cscale(acc, 4.0f);
+  }
+}
+
+// Up-leg on a TX x TY x TZ tile of fine points: v2 = W r + P e on the tile and a
+// one-point ring -> LDS; z = (1 - w) v2 + W (r + sum of the 6 neighbours of v2).
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_up_fused3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                    VecSet ec, int nc, VecSet z, const int* active) {
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2;
+  constexpr int NT = 256, NH = HX * HY * HZ, IT = (NH + NT - 1) / NT;
+  __shared__ c32 sE[CZ][CY][CX];
+  __shared__ c32 sV[HZ][HY][HX];
+  const int n = lv.n;
+  const int tx_n = (n + TX - 1) / TX, ty_n = (n + TY - 1) / TY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + TZ - 1) / TZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tx_n) * TX, fy0 = ((id.t / tx_n) % ty_n) * TY, fz0 = (id.t / (tx_n * ty_n)) * TZ;
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1, czs = fz0 / 2 - 1;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
+  for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
+    const int I = cxs + idx % CX, J = cys + (idx / CX) % CY, K = czs + idx / (CX * CY);
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
+    sE[idx / (CX * CY)][(idx / CX) % CY][idx % CX] = ok ? eb[K * nc2 + (long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  c32 rv[IT], wv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + (idx / HX) % HY, gz = fz0 - 1 + idx / (HX * HY);
+    const bool ok = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+    const long long p = ok ? gz * n2 + (long long)gy * n + gx : 0;
+    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NH) continue;
+    const int lx = idx % HX, ly = (idx / HX) % HY, lz = idx / (HX * HY);
+    const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
+    c32 v2 = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, K = (gz >> 1) - czs;
+      const int ox = gx & 1, oy = gy & 1, oz = gz & 1;
+      c32 pe = make_float2(0.f, 0.f);
+      for (int kz = 0; kz <= oz; ++kz)
+        for (int ky = 0; ky <= oy; ++ky)
+          for (int kx = 0; kx <= ox; ++kx) pe = cadd(pe, sE[K + kz][J + ky][I + kx]);
+      const float wgt = (ox ? 0.5f : 1.0f) * (oy ? 0.5f : 1.0f) * (oz ? 0.5f : 1.0f);
+      v2 = cadd(cmul(rv[it], wv[it]), cscale(pe, wgt));
+    }
+    sV[lz][ly][lx] = v2;
+  }
+  __syncthreads();
+  c32* zb = z.p + (long long)b * z.stride;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= NH) continue;
+    const int lx = idx % HX, ly = (idx / HX) % HY, lz = idx / (HX * HY);
+    if (lx == 0 || lx == HX - 1 || ly == 0 || ly == HY - 1 || lz == 0 || lz == HZ - 1) continue;
+    const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
+    if (gx >= n || gy >= n || gz >= n) continue;
+    const c32 nb = cadd(cadd(cadd(sV[lz][ly][lx - 1], sV[lz][ly][lx + 1]), cadd(sV[lz][ly - 1][lx], sV[lz][ly + 1][lx])),
+                        cadd(sV[lz - 1][ly][lx], sV[lz + 1][ly][lx]));
+    zb[gz * n2 + (long long)gy * n + gx] =
+        cadd(cscale(sV[lz][ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+  }
+}
+
 // ------------------------------------------------- fused finest-level step
 // One kernel for the finest-level work between two coarse-grid visits of
 // consecutive s-step basis vectors: the up-leg of step j, the basis matvec
@@ -581,6 +725,23 @@ void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float om
                        omega, ec, nc, z, active, e);
 }
 }  // namespace
+
+void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
+                        const int* active) {
+  constexpr int TCX = 8, TCY = 4, TCZ = 4;
+  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + TCZ - 1) / TCZ);
+  hipLaunchKernelGGL((k_down_fused3<TCX, TCY, TCZ>), dim3(B * tiles), dim3(TCX * TCY * TCZ), 0, s, B, r, rs, lv,
+                     omega, rc, nc, active);
+}
+
+void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
+                      VecSet z, const int* active) {
+  constexpr int TX = 16, TY = 8, TZ = 8;
+  const int n = lv.n;
+  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ);
+  hipLaunchKernelGGL((k_up_fused3<TX, TY, TZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                     active);
+}
 
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
                         VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active) {

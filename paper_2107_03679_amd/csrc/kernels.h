@@ -42,6 +42,11 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                         const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active, int cfg, VecSet e = VecSet{nullptr, 0});
+// fused 3D legs (same roles as the 2D legs; fixed tiles)
+void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
+                        const int* active);
+void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
+                      VecSet z, const int* active);
 // finest-level step of the s-step basis (2D): up-leg of Z_j, W_{j+1} = A Z_j (la = the A
 // operator), down-leg of W_{j+1} into rc; one launch
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,

@@ -78,3 +78,26 @@ def test_solve_adjoint_and_gradient_3d(cube):
     grad = ctx.grad_n(x, lam, u_in=uin).cpu().numpy().astype(np.float64)
     ref = model.scalar_field_gradient(prob, u + to_np(uin), lam_ref)
     assert np.linalg.norm(grad - ref) / np.linalg.norm(ref) < 1e-4
+
+
+@pytest.mark.parametrize("cycle", [1, 3])
+def test_fused_3d_legs_match_oracle_over_several_tiles(cycle):
+    """The fused 3D legs on three levels (the single-launch coarse cycle off), on a 49^3 grid:
+    down-leg tiles of 8x4x4 coarse points and up-leg tiles of 16x8x8 fine points, both ragged
+    at every level; the cycle equals the oracle's and the generic kernels' (fused off)."""
+    n, w, levels = 40, 4, 4
+    print(f"\n[3D fused legs n={n} levels={levels} cycle={cycle}]", flush=True)
+    nmap = medium(n, d=3, seed=9)
+    prob = oracle_problem(nmap, w=w, levels=levels)
+    hier = Hierarchy(prob)
+    r = synth.complex_field((3, *prob.shape), 31)
+    gamma = [2] + [1] * (levels - 1) if cycle == 3 else 1
+    ref = np.stack([hier.cycle(ri.ravel(), None, 0, gamma).reshape(prob.shape) for ri in r])
+    out = {}
+    for fused in (1, 0):
+        ctx = gpu_context(nmap, w=w, levels=levels, max_batch=3, cycle=cycle, fused=fused, coarse_single_launch=0)
+        assert ctx.n_e == prob.n_e == 49
+        out[fused] = to_np(ctx.precondition(to_dev(r)))
+        ctx.close()
+    assert rel(out[1], ref) < 1e-5
+    assert rel(out[1], out[0]) < 1e-5
