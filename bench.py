@@ -52,8 +52,9 @@ def parse():
     p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
     p.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (for counter collection)")
-    p.add_argument("--fused-step", action="store_true",
-                   help="one kernel for the finest-level up-leg, basis matvec and next down-leg")
+    p.add_argument("--fused-step", type=int, default=2, choices=(0, 1, 2),
+                   help="finest level of the s-step basis: 0 separate kernels, 1 one kernel for the up-leg, "
+                        "basis matvec and next down-leg, 2 the up-leg and basis matvec in one kernel")
     p.add_argument("--copy-probe", type=float, default=256.0,
                    help="MiB of a plain device-to-device copy timed before the solve (0: skip); the same copy "
                         "calibrates the HBM byte counters")
@@ -272,7 +273,7 @@ def main():
     t_setup = time.perf_counter()
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
                        levels=args.levels, restart=args.restart, cycle=args.cycle, reorth=args.reorth, max_batch=B,
-                       max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=1 if args.fused_step else 0,
+                       max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=args.fused_step,
                        krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
                                "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
     torch.cuda.synchronize()
@@ -348,7 +349,7 @@ def main():
         name, (ms, n, by) = max(rep.items(), key=lambda kv: kv[1][0])
         achieved = by / (ms * 1e-3) / 1e9
         cfg = {"workload": args.workload, "rhs": B, "levels": args.levels, "restart": args.restart,
-               "cycle": args.cycle, "krylov": args.krylov, "fused_step": bool(args.fused_step)}
+               "cycle": args.cycle, "krylov": args.krylov, "fused_step": args.fused_step}
         traffic = recorded_traffic(name, cfg)
         out["roofline"] = {
             "bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

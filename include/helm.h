@@ -104,10 +104,12 @@ typedef struct {
   int coarse_single_launch; /* 1 = V-cycle levels with <= 48^2 (2D) / 16^3 (3D) points run
                                in one launch, one workgroup per right-hand side (1) */
   int krylov;       /* HELM_KRYLOV_SSTEP (default), HELM_KRYLOV_FGMRES or HELM_KRYLOV_BICGSTAB */
-  int fused_step;   /* 1 = in the s-step form (2D, fused legs), the finest-level work between two
-                       coarse visits (up-leg, basis matvec, next down-leg) is one kernel; it moves
-                       36% fewer bytes but its six barrier stages leave it latency-bound, no faster
-                       than the separate kernels on MI355X (0) */
+  int fused_step;   /* finest level of the s-step form (2D, fused legs): 0 = separate kernels;
+                       1 = the work between two coarse visits (up-leg, basis matvec, next
+                       down-leg) is one kernel: 36% fewer bytes, but its six barrier stages leave
+                       it latency-bound, no faster than the separate kernels on MI355X;
+                       2 = the up-leg and the basis matvec W_{j+1} = A Z_j in one kernel, which
+                       saves the matvec's pass over Z_j (2) */
 } helm_opts;
 
 /* Krylov forms (helm_opts.krylov).  Both minimise the residual over the same

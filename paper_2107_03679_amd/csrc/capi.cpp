@@ -523,7 +523,36 @@ void sstep_basis(helm_ctx* c, int B) {
   const long long N0 = c->N0;
   const LevelArgs A = fine_A(c);
   const double Bp = c->prof_B, N = (double)N0;
-  if (c->o.fused_step && c->dim == 2 && legs_fused(c, 0)) {
+  if (c->o.fused_step == 2 && c->dim == 2 && legs_fused(c, 0)) {
+    // finest level: per step a down-leg, the coarse visits and the up-leg of Z_j
+    // fused with W_{j+1} = A Z_j (the last matvec is the Gram kernel's)
+    const Level& L1 = c->lv[1];
+    const VecSet rc{L1.rc, L1.N};
+    const float om = (float)c->o.omega_jac;
+    const double Nc1 = (double)L1.N;
+    for (int j = 0; j < k.m; ++j) {
+      const VecSet vj{k.V + (long long)j * N0, (long long)(k.m + 1) * N0};
+      const VecSet zj{k.Z + (long long)j * N0, (long long)k.m * N0};
+      const ScaleSet sj{k.vs + j, k.m + 1};
+      {
+        ProfScope ps(c, "down_fused_l0", Bp * 8.0 * (N + Nc1) + 8.0 * N);
+        launch_down_fused2(c->s, B, vj, sj, level_K(c, 0), om, rc, L1.n, k.active, c->tune_down[0]);
+      }
+      const VecSet ecur = coarse_visits(c, B, 0, k.active);
+      if (j + 1 < k.m) {
+        const VecSet vn{k.V + (long long)(j + 1) * N0, (long long)(k.m + 1) * N0};
+        ProfScope ps(c, "up_mv_l0", Bp * 8.0 * (3.0 * N + Nc1) + 16.0 * N);
+        launch_up_mv2(c->s, B, vj, sj, level_K(c, 0), A, om, ecur, L1.n, zj, vn, k.active);
+      } else {
+        ProfScope ps(c, "up_fused_l0", Bp * 8.0 * (2.0 * N + Nc1) + 8.0 * N);
+        launch_up_fused2(c->s, B, vj, sj, level_K(c, 0), om, ecur, L1.n, zj, k.active, c->tune_up[0]);
+      }
+    }
+    ProfScope ps(c, "sstep_gram", Bp * 8.0 * (k.m + 1.0) * N + 8.0 * N);
+    launch_sstep_gram_solve(c->s, B, k, A, c->d_gram);
+    return;
+  }
+  if (c->o.fused_step == 1 && c->dim == 2 && legs_fused(c, 0)) {
     // finest level: one down-leg, then per step the coarse visits and one fused
     // kernel (up-leg of Z_j, W_{j+1} = A Z_j, down-leg of W_{j+1}); the last up-leg alone
     const Level& L1 = c->lv[1];
@@ -873,7 +902,7 @@ void helm_default_opts(helm_opts* o) {
   o->use_graph = 1;
   o->coarse_single_launch = 1;
   o->krylov = HELM_KRYLOV_SSTEP;
-  o->fused_step = 0;
+  o->fused_step = 2;
 }
 
 int helm_extended_size(int n, int abl_width, int levels) { return helm_host::extended_size(n, abl_width, levels); }
@@ -897,6 +926,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     return fail(nullptr, HELM_EINVAL, "Bi-CGSTAB takes restart >= 4 (iterations per status check)");
   if (o.krylov == HELM_KRYLOV_SSTEP && o.restart > sstep_max_restart())
     return fail(nullptr, HELM_EINVAL, "the s-step form takes restart <= 12");
+  if (o.fused_step < 0 || o.fused_step > 2) return fail(nullptr, HELM_EINVAL, "fused_step must be 0, 1 or 2");
   if (o.max_batch < 1 || o.nu1 < 0 || o.nu2 < 0 || o.cycle < 1 || o.cycle > 3 || o.max_iters < 1 || !(o.rtol > 0))
     return fail(nullptr, HELM_EINVAL, "bad solver options");
   helm_abl a{0.15, 1, 0};

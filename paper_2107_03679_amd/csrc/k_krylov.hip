@@ -499,7 +499,7 @@ __host__ __device__ constexpr int packed_col(int e, int nv) {
 }
 
 #ifndef HELM_GRAM_GP
-#define HELM_GRAM_GP 128
+#define HELM_GRAM_GP 256
 #endif
 constexpr int GP = HELM_GRAM_GP;  // points staged per step
 

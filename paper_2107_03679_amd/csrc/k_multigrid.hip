@@ -250,6 +250,116 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
   }
 }
 
+// Up-leg of Z_j fused with the next basis vector W_{j+1} = A Z_j of the s-step
+// form, on a TX x TY tile of fine points:
+//   v2 = W r + P e on the tile and a two-point ring   -> LDS
+//   z  = (1 - w) v2 + W (r + neighbours of v2) on the tile and a one-point ring -> LDS
+//   Z_j = z and W_{j+1} = D_A z - (neighbours of z) on the tile
+// (la is the operator A, lv the level's preconditioning operator).  Saves the
+// separate matvec's pass over Z_j.
+template <int TX, int TY>
+__global__ __launch_bounds__(256) void k_up_mv2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
+                                                float omega, VecSet ec, int nc, VecSet z, VecSet w,
+                                                const int* active) {
+  constexpr int NT = 256;
+  constexpr int VX = TX + 4, VY = TY + 4, ZX = TX + 2, ZY = TY + 2;
+  constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3;
+  __shared__ c32 sE[CY][CX];
+  __shared__ c32 sV[VY][VX];
+  __shared__ c32 sZ[ZY][ZX];
+  const int n = lv.n;
+  const int tiles_x = (n + TX - 1) / TX;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  const c32* rb = r.p + (long long)b * r.stride;
+  const float sc = scale_of(rs, b);
+  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+    sE[idx / CX][idx % CX] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  constexpr int IV = (VX * VY + NT - 1) / NT, IZ = (ZX * ZY + NT - 1) / NT, IT = (TX * TY + NT - 1) / NT;
+  {
+    c32 rv[IV], wv[IV];
+#pragma unroll
+    for (int it = 0; it < IV; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int gx = fx0 - 2 + idx % VX, gy = fy0 - 2 + idx / VX;
+      const bool ok = idx < VX * VY && gx >= 0 && gx < n && gy >= 0 && gy < n;
+      const long long p = ok ? (long long)gy * n + gx : 0;
+      rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+      wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < IV; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx >= VX * VY) continue;
+      const int gx = fx0 - 2 + idx % VX, gy = fy0 - 2 + idx / VX;
+      c32 v2 = make_float2(0.f, 0.f);
+      if (gx >= 0 && gx < n && gy >= 0 && gy < n)
+        v2 = cadd(cmul(cscale(rv[it], sc), wv[it]), prolong_lds<CX>(sE, gx, gy, cxs, cys));
+      sV[idx / VX][idx % VX] = v2;
+    }
+  }
+  // r and W on the one-point ring region (cached: the loads above fetched them)
+  c32 rz[IZ], wz[IZ];
+#pragma unroll
+  for (int it = 0; it < IZ; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 - 1 + idx % ZX, gy = fy0 - 1 + idx / ZX;
+    const bool ok = idx < ZX * ZY && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rz[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+    wz[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IZ; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= ZX * ZY) continue;
+    const int lx = idx % ZX + 1, ly = idx / ZX + 1;  // sV coordinates
+    const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
+    c32 zv = make_float2(0.f, 0.f);
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+      zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wz[it], cadd(cscale(rz[it], sc), nb)));
+    }
+    sZ[idx / ZX][idx % ZX] = zv;
+  }
+  // the operator's coefficient at the own points
+  c32 kv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 + idx % TX, gy = fy0 + idx / TX;
+    const bool ok = idx < TX * TY && gx < n && gy < n;
+    kv[it] = ok ? la.coef[(long long)gy * n + gx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  c32* zb = z.p + (long long)b * z.stride;
+  c32* wb = w.p + (long long)b * w.stride;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int lx = idx % TX + 1, ly = idx / TX + 1;  // sZ coordinates
+    const int gx = fx0 + lx - 1, gy = fy0 + ly - 1;
+    if (idx >= TX * TY || gx >= n || gy >= n) continue;
+    const long long p = (long long)gy * n + gx;
+    const c32 zc = sZ[ly][lx];
+    const int ng = ghosts2(gx, gy, n);
+    const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
+    const c32 nb = cadd(cadd(sZ[ly][lx - 1], sZ[ly][lx + 1]), cadd(sZ[ly - 1][lx], sZ[ly + 1][lx]));
+    zb[p] = zc;
+    wb[p] = csub(cmul(D, zc), nb);
+  }
+}
+
 // ------------------------------------------------------------ fused 3D legs
 // The 2D legs' arithmetic with the 7-point operator, 27-point full weighting
 // (weights (1/4, 1/2, 1/4) per axis) and trilinear prolongation.
@@ -740,6 +850,19 @@ void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
   const int n = lv.n;
   const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ);
   hipLaunchKernelGGL((k_up_fused3<TX, TY, TZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                     active);
+}
+
+void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
+                   int nc, VecSet z, VecSet w, const int* active) {
+#ifndef HELM_UPMV_TILE
+#define HELM_UPMV_TILE 64, 16
+#endif
+  constexpr int T[2] = {HELM_UPMV_TILE};
+  constexpr int TX = T[0], TY = T[1];
+  const int n = lv.n;
+  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
+  hipLaunchKernelGGL((k_up_mv2<TX, TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
                      active);
 }
 

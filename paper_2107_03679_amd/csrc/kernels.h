@@ -47,6 +47,9 @@ void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                         const int* active);
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active);
+// up-leg of Z_j and W_{j+1} = A Z_j in one launch (2D; la = the A operator)
+void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
+                   int nc, VecSet z, VecSet w, const int* active);
 // finest-level step of the s-step basis (2D): up-leg of Z_j, W_{j+1} = A Z_j (la = the A
 // operator), down-leg of W_{j+1} into rc; one launch
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
