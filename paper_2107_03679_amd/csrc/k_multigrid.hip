@@ -430,6 +430,113 @@ __global__ __launch_bounds__(TCX* TCY* TCZ) void k_down_fused3(int nrhs, VecSet 
   }
 }
 
+// Down-leg marching in z: a TCX x TCY column of coarse points, coarse planes
+// [kz0, kz0 + KZ).  Per fine plane f (bottom to top): v1(f) = W r on the
+// plane's (2 TCX + 3) x (2 TCY + 3) region -> one of three LDS planes; then
+// s(f - 1) on the region's interior from v1(f - 2 .. f) -> LDS; then the
+// plane's in-plane full weighting is added to the coarse plane(s) it belongs
+// to (weight 1/2 for f - 1 = 2K, 1/4 to K - 1 and K for f - 1 = 2K - 1),
+// accumulated in registers; a coarse plane is written once complete.
+template <int TCX, int TCY, int KZ>
+__global__ __launch_bounds__(256) void k_down_march3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                     VecSet rc, int nc, const int* active) {
+  constexpr int NT = 256;
+  constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3, SX = RX - 2, SY = RY - 2;
+  constexpr int NR = RX * RY, IT = (NR + NT - 1) / NT;
+  static_assert(TCX * TCY <= NT, "one coarse point per thread");
+  __shared__ c32 sV[3][RY][RX];
+  __shared__ c32 sS[SY][SX];
+  const int n = lv.n;
+  const int tx_n = (nc + TCX - 1) / TCX, ty_n = (nc + TCY - 1) / TCY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((nc + KZ - 1) / KZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int cx0 = (id.t % tx_n) * TCX, cy0 = ((id.t / tx_n) % ty_n) * TCY, kz0 = (id.t / (tx_n * ty_n)) * KZ;
+  const int kz1 = min(nc, kz0 + KZ);
+  const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const long long n2 = (long long)n * n;
+  // this thread's region points: in-plane offset and whether it lies in the grid
+  long long off[IT];
+  bool inxy[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 + idx % RX, gy = fy0 + idx / RX;
+    inxy[it] = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    off[it] = inxy[it] ? (long long)gy * n + gx : 0;
+  }
+  const int f0 = 2 * kz0 - 2, f1 = 2 * kz1;  // fine planes whose v1 is needed
+  c32 rn[IT], wn[IT], rp[IT];
+  auto fetch = [&](int f) {
+    const bool inz = f >= 0 && f < n;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const bool ok = inz && inxy[it];
+      const long long p = ok ? f * n2 + off[it] : 0;
+      rn[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+      wn[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    }
+  };
+  fetch(f0);
+  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  const bool coarse = threadIdx.x < TCX * TCY && cx0 + tx < nc && cy0 + ty < nc;
+  c32 acc = make_float2(0.f, 0.f);
+  for (int f = f0; f <= f1; ++f) {
+    c32 rf[IT];
+    const int slot = (f - f0) % 3;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      rf[it] = cscale(rn[it], sc);
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NR) sV[slot][idx / RX][idx % RX] = cmul(rf[it], wn[it]);
+    }
+    if (f < f1) fetch(f + 1);
+    __syncthreads();
+    const int g = f - 1;  // the plane whose s is formed now
+    if (g >= f0 + 1) {
+      const int sm = (g - 1 - f0) % 3, s0 = (g - f0) % 3;
+      const bool ing = g >= 0 && g < n;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        const int lx = idx % RX, ly = idx / RX;
+        if (idx >= NR || lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1) continue;
+        c32 sv = make_float2(0.f, 0.f);
+        if (ing && inxy[it]) {
+          const c32 nb = cadd(cadd(cadd(sV[s0][ly][lx - 1], sV[s0][ly][lx + 1]),
+                                   cadd(sV[s0][ly - 1][lx], sV[s0][ly + 1][lx])),
+                              cadd(sV[sm][ly][lx], sV[slot][ly][lx]));
+          sv = cadd(cscale(rp[it], 1.0f - omega), nb);
+        }
+        sS[ly - 1][lx - 1] = sv;
+      }
+    }
+    __syncthreads();
+    if (g >= f0 + 1 && coarse) {
+      const int sx = 2 * tx + 1, sy = 2 * ty + 1;
+      c32 t = cscale(sS[sy][sx], 0.25f);
+      t = cadd(t, cscale(cadd(cadd(sS[sy][sx - 1], sS[sy][sx + 1]), cadd(sS[sy - 1][sx], sS[sy + 1][sx])), 0.125f));
+      t = cadd(t, cscale(cadd(cadd(sS[sy - 1][sx - 1], sS[sy - 1][sx + 1]), cadd(sS[sy + 1][sx - 1], sS[sy + 1][sx + 1])),
+                         0.0625f));
+      if (g & 1) {  // g = 2K + 1: closes K (unless g is the chunk's first plane), opens K + 1
+        if (g > f0 + 1) {
+          const int K = (g - 1) >> 1;
+          acc = cadd(acc, cscale(t, 0.25f));
+          rc.p[(long long)b * rc.stride + ((long long)K * nc + cy0 + ty) * nc + cx0 + tx] = cscale(acc, 4.0f);
+        }
+        acc = cscale(t, 0.25f);
+      } else {
+        acc = cadd(acc, cscale(t, 0.5f));
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) rp[it] = rf[it];
+  }
+}
+
 // Up-leg on a TX x TY x TZ tile of fine points: v2 = W r + P e on the tile and a
 // one-point ring -> LDS; z = (1 - w) v2 + W (r + sum of the 6 neighbours of v2).
 template <int TX, int TY, int TZ>
@@ -838,6 +945,16 @@ void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float om
 
 void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active) {
+#ifndef HELM_DOWN3_MARCH
+#define HELM_DOWN3_MARCH 1
+#endif
+  if (HELM_DOWN3_MARCH) {
+    constexpr int TCX = 16, TCY = 8, KZ = 8;
+    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + KZ - 1) / KZ);
+    hipLaunchKernelGGL((k_down_march3<TCX, TCY, KZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                       active);
+    return;
+  }
   constexpr int TCX = 8, TCY = 4, TCZ = 4;
   const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + TCZ - 1) / TCZ);
   hipLaunchKernelGGL((k_down_fused3<TCX, TCY, TCZ>), dim3(B * tiles), dim3(TCX * TCY * TCZ), 0, s, B, r, rs, lv,
