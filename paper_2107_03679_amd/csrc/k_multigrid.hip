@@ -611,6 +611,140 @@ __global__ __launch_bounds__(256) void k_up_fused3(int nrhs, VecSet r, ScaleSet 
   }
 }
 
+// Up-leg marching in z: a TX x TY column of fine points, output planes
+// [fz0, fz0 + FZ).  Per fine plane f: v2(f) = W r + P e on the column and a
+// one-point in-plane ring -> one of three LDS planes (the coarse planes that P
+// reads are kept two at a time in LDS); then z(f - 1) on the column from
+// v2(f - 2 .. f).
+template <int TX, int TY, int FZ>
+__global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                   VecSet ec, int nc, VecSet z, const int* active) {
+  constexpr int NT = 256, HX = TX + 2, HY = TY + 2, NH = HX * HY, IT = (NH + NT - 1) / NT;
+  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, NCP = CX * CY, ITC = (NCP + NT - 1) / NT;
+  __shared__ c32 sE[2][CY][CX];
+  __shared__ c32 sV[3][HY][HX];
+  const int n = lv.n;
+  const int tx_n = (n + TX - 1) / TX, ty_n = (n + TY - 1) / TY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + FZ - 1) / FZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tx_n) * TX, fy0 = ((id.t / tx_n) % ty_n) * TY, fz0 = (id.t / (tx_n * ty_n)) * FZ;
+  const int fz1 = min(n, fz0 + FZ);
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
+  long long off[IT];
+  bool inxy[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
+    inxy[it] = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    off[it] = inxy[it] ? (long long)gy * n + gx : 0;
+  }
+  long long coff[ITC];
+  bool cin[ITC];
+#pragma unroll
+  for (int it = 0; it < ITC; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    cin[it] = idx < NCP && I >= 0 && I < nc && J >= 0 && J < nc;
+    coff[it] = cin[it] ? (long long)J * nc + I : 0;
+  }
+  c32 rn[IT], wn[IT], rp[IT], wp[IT], cn[ITC];
+  auto fetch = [&](int f) {
+    const bool inz = f >= 0 && f < n;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const bool ok = inz && inxy[it];
+      const long long p = ok ? f * n2 + off[it] : 0;
+      rn[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+      wn[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    }
+  };
+  auto fetch_coarse = [&](int K) {
+    const bool inz = K >= 0 && K < nc;
+#pragma unroll
+    for (int it = 0; it < ITC; ++it) {
+      const bool ok = inz && cin[it];
+      cn[it] = ok ? eb[K * nc2 + coff[it]] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_coarse = [&](int K) {
+#pragma unroll
+    for (int it = 0; it < ITC; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < NCP) sE[K & 1][idx / CX][idx % CX] = cn[it];
+    }
+  };
+  const int fa = fz0 - 1, fb = fz1;  // planes whose v2 is needed
+  int khi = (max(fa, 0) >> 1) + 1;   // highest coarse plane in LDS
+  fetch_coarse(khi - 1);
+  store_coarse(khi - 1);
+  fetch_coarse(khi);
+  store_coarse(khi);
+  fetch(fa);
+  for (int f = fa; f <= fb; ++f) {
+    c32 rf[IT], wf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      rf[it] = cscale(rn[it], sc);
+      wf[it] = wn[it];
+    }
+    const int knext = (f + 2) >> 1;  // the higher coarse plane that v2(f + 1) reads
+    if (f < fb) {
+      fetch(f + 1);
+      if (knext > khi) fetch_coarse(knext);
+    }
+    __syncthreads();
+    {
+      const int slot = (f - fa) % 3;
+      const bool inz = f >= 0 && f < n;
+      const int klo = f >> 1;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        if (idx >= NH) continue;
+        const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
+        c32 v2 = make_float2(0.f, 0.f);
+        if (inz && inxy[it]) {
+          c32 pe = prolong_lds<CX>(sE[klo & 1], gx, gy, cxs, cys);
+          if (f & 1) pe = cscale(cadd(pe, prolong_lds<CX>(sE[(klo + 1) & 1], gx, gy, cxs, cys)), 0.5f);
+          v2 = cadd(cmul(rf[it], wf[it]), pe);
+        }
+        sV[slot][idx / HX][idx % HX] = v2;
+      }
+    }
+    __syncthreads();
+    if (f < fb && knext > khi) {  // the coarse plane that replaces one no longer read
+      store_coarse(knext);
+      khi = knext;
+    }
+    const int g = f - 1;  // output plane
+    if (g >= fz0) {
+      const int sm = (g - 1 - fa) % 3, s0 = (g - fa) % 3, sp = (f - fa) % 3;
+      c32* zb = z.p + (long long)b * z.stride + g * n2;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        const int lx = idx % HX, ly = idx / HX;
+        if (idx >= NH || lx == 0 || lx == HX - 1 || ly == 0 || ly == HY - 1 || !inxy[it]) continue;
+        const c32 nb = cadd(cadd(cadd(sV[s0][ly][lx - 1], sV[s0][ly][lx + 1]), cadd(sV[s0][ly - 1][lx], sV[s0][ly + 1][lx])),
+                            cadd(sV[sm][ly][lx], sV[sp][ly][lx]));
+        zb[off[it]] = cadd(cscale(sV[s0][ly][lx], 1.0f - omega), cmul(wp[it], cadd(rp[it], nb)));
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      rp[it] = rf[it];
+      wp[it] = wf[it];
+    }
+  }
+}
+
 // ------------------------------------------------- fused finest-level step
 // One kernel for the finest-level work between two coarse-grid visits of
 // consecutive s-step basis vectors: the up-leg of step j, the basis matvec
@@ -963,6 +1097,17 @@ void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
 
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active) {
+#ifndef HELM_UP3_MARCH
+#define HELM_UP3_MARCH 1
+#endif
+  if (HELM_UP3_MARCH) {
+    constexpr int TX = 32, TY = 16, FZ = 16;
+    const int n = lv.n;
+    const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + FZ - 1) / FZ);
+    hipLaunchKernelGGL((k_up_march3<TX, TY, FZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                       active);
+    return;
+  }
   constexpr int TX = 16, TY = 8, TZ = 8;
   const int n = lv.n;
   const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ);
