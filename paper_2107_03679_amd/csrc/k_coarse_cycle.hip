@@ -120,30 +120,46 @@ __global__ __launch_bounds__(CC_NT) void k_coarse_cycle(CoarseCycleArgs a) {
 // reduction slots): the input right-hand side is read once and the solution
 // written once; every other access of the cycle stays on the CU.  Used when
 // the levels fit (see coarse_cycle_lds_bytes).
+// Offset in the LDS layout of level l's block (r, e, t; r, e on the coarsest;
+// the reduction slots after the coarsest).  Uniform scalar arithmetic: the
+// per-level pointers are formed where used instead of living in a
+// dynamically indexed (scratch) array.
+__device__ __forceinline__ int lds_base(const CoarseCycleArgs& a, int l) {
+  int o = 0;
+  for (int q = a.lp; q < l; ++q) o += (q < a.L - 1 ? 3 : 2) * (int)a.lv[q].N;
+  return o;
+}
+
 __global__ __launch_bounds__(CC_NT) void k_coarse_cycle_lds(CoarseCycleArgs a) {
   extern __shared__ c32 lds[];
   const int b = blockIdx.x;
   if (a.active && !a.active[b]) return;
   const int dim = a.dim;
   const float om = a.omega;
-  c32* R[HELM_MAX_LEVELS];
-  c32* E[HELM_MAX_LEVELS];
-  c32* T[HELM_MAX_LEVELS];
-  {
-    c32* q = lds;
-    for (int l = a.lp; l < a.L; ++l) {
-      const int N = (int)a.lv[l].N;
-      R[l] = q;
-      E[l] = q + N;
-      T[l] = q + 2 * N;
-      q += (l < a.L - 1 ? 3 : 2) * N;
+  auto R = [&](int l) { return lds + lds_base(a, l); };
+  auto E = [&](int l) { return lds + lds_base(a, l) + (int)a.lv[l].N; };
+  auto T = [&](int l) { return l < a.L - 1 ? lds + lds_base(a, l) + 2 * (int)a.lv[l].N : lds + lds_base(a, a.L); };
+  // The coarsest solve's entries of this thread, loaded now when they fit in
+  // registers (one pass of rows, at most MK per thread), so that the solve
+  // waits on no global load.
+  constexpr int MK = 10;
+  const int Ncst = (int)a.lv[a.L - 1].N;
+  const int groups = max(1, CC_NT / max(Ncst, 1));
+  const bool pre = Ncst <= CC_NT && (Ncst + groups - 1) / groups <= MK;
+  c32 mk[MK];
+  if (pre) {
+    const int g = threadIdx.x / (CC_NT / groups), rr = threadIdx.x % (CC_NT / groups);
+    const bool mine = g < groups && rr < Ncst;
+#pragma unroll
+    for (int u = 0; u < MK; ++u) {
+      const int k = g + u * groups;
+      mk[u] = mine && k < Ncst ? a.minvT[(long long)k * Ncst + rr] : make_float2(0.f, 0.f);
     }
-    T[a.L - 1] = q;  // reduction slots of the coarsest solve
   }
   {
     const CoarseLevel& F = a.lv[a.lp];
     const c32* rg = F.rc + (long long)b * F.N;
-    for (int p = threadIdx.x; p < F.N; p += CC_NT) R[a.lp][p] = rg[p];
+    for (int p = threadIdx.x; p < F.N; p += CC_NT) R(a.lp)[p] = rg[p];
   }
   __syncthreads();
   // ---- down ----
@@ -151,7 +167,7 @@ __global__ __launch_bounds__(CC_NT) void k_coarse_cycle_lds(CoarseCycleArgs a) {
     const CoarseLevel& F = a.lv[l];
     const CoarseLevel& C = a.lv[l + 1];
     const int Nf = (int)F.N, Ncl = (int)C.N;
-    c32 *r = R[l], *e = E[l], *t = T[l];
+    c32 *r = R(l), *e = E(l), *t = T(l);
     for (int p = threadIdx.x; p < Nf; p += CC_NT) e[p] = cmul(F.wd[p], r[p]);
     __syncthreads();
     for (int p = threadIdx.x; p < Nf; p += CC_NT) {
@@ -161,23 +177,30 @@ __global__ __launch_bounds__(CC_NT) void k_coarse_cycle_lds(CoarseCycleArgs a) {
     __syncthreads();
     for (int q = threadIdx.x; q < Ncl; q += CC_NT) {
       const Coord cq = coord_of32((unsigned)q, (unsigned)C.n, dim);
-      R[l + 1][q] = fw4(t, cq, F.n, dim);
+      R(l + 1)[q] = fw4(t, cq, F.n, dim);
     }
     __syncthreads();
   }
   // ---- coarsest: e = M r, rows split over thread groups, partial sums reduced in LDS ----
   {
-    const int Nc = (int)a.lv[a.L - 1].N;
-    const c32* r = R[a.L - 1];
-    c32* e = E[a.L - 1];
-    c32* red = T[a.L - 1];
-    const int groups = max(1, CC_NT / max(Nc, 1));
+    const int Nc = Ncst;
+    const c32* r = R(a.L - 1);
+    c32* e = E(a.L - 1);
+    c32* red = T(a.L - 1);
     for (int row0 = 0; row0 < Nc; row0 += CC_NT / groups) {
       const int rows = min(CC_NT / groups, Nc - row0);
       const int g = threadIdx.x / (CC_NT / groups), rr = threadIdx.x % (CC_NT / groups);
       c32 acc = make_float2(0.f, 0.f);
       if (g < groups && rr < rows) {
-        for (int k = g; k < Nc; k += groups) acc = cfma(a.minvT[(long long)k * Nc + row0 + rr], r[k], acc);
+        if (pre) {
+#pragma unroll
+          for (int u = 0; u < MK; ++u) {
+            const int k = g + u * groups;
+            if (k < Nc) acc = cfma(mk[u], r[k], acc);
+          }
+        } else {
+          for (int k = g; k < Nc; k += groups) acc = cfma(a.minvT[(long long)k * Nc + row0 + rr], r[k], acc);
+        }
       }
       red[threadIdx.x] = acc;
       __syncthreads();
@@ -198,8 +221,8 @@ __global__ __launch_bounds__(CC_NT) void k_coarse_cycle_lds(CoarseCycleArgs a) {
     const CoarseLevel& F = a.lv[l];
     const CoarseLevel& C = a.lv[l + 1];
     const int Nf = (int)F.N;
-    c32 *r = R[l], *e = E[l], *t = T[l];
-    const c32* ec = E[l + 1];
+    c32 *r = R(l), *e = E(l), *t = T(l);
+    const c32* ec = E(l + 1);
     for (int p = threadIdx.x; p < Nf; p += CC_NT) {
       const Coord c = coord_of32((unsigned)p, (unsigned)F.n, dim);
       t[p] = cadd(e[p], prolong_at(ec, c, C.n, dim));
