@@ -67,7 +67,7 @@ def recorded_traffic(kernel, cfg):
     launch configuration and the kernel sources are unchanged since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "traffic_blobs512x60.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{cfg['workload']}.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -356,6 +356,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_GBs": None if traffic is None else traffic * n / (ms * 1e-3) / 1e9,
             "avg_launch_us": 1000.0 * ms / n, "bytes_per_launch": by / n, "share_of_step": ms / total,
+            "record_key": cfg,
         }
         if probe is not None:
             out["roofline"]["copy_probe"] = probe
