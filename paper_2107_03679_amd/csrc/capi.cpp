@@ -71,6 +71,7 @@ struct helm_ctx {
   float h2_hi = 0, h2_lo = 0;
   std::vector<Level> lv;
   c32* d_minvT = nullptr;
+  c32* d_cs_part = nullptr;  // slice partials of the coarsest solve as a matrix product
   int Nc = 0;
 
   // Krylov workspace
@@ -301,7 +302,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const int dim = c->dim;
   if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
     ProfScope ps(c, "coarse_solve", 8.0 * c->Nc * c->Nc + c->prof_B * 16.0 * c->Nc);
-    launch_coarse_solve(c->s, B, c->d_minvT, c->Nc, r, out, act);
+    launch_coarse_solve(c->s, B, c->d_minvT, c->Nc, r, out, act, c->d_cs_part);
     return;
   }
   Level& fine = c->lv[l];
@@ -984,6 +985,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     }
     c->Nc = (int)c->lv[c->L - 1].N;
     c->d_minvT = c->alloc<c32>((size_t)c->Nc * c->Nc);
+    c->d_cs_part = c->alloc<c32>(coarse_solve_part_size(maxB, c->Nc));
     c->d_nmap = c->alloc<float>(npts(c->n, c->dim));
     c->d_f = c->alloc<float>(N0);
     c->d_chi = c->alloc<c32>(N0);

@@ -1037,6 +1037,61 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const c32* minvT, int Nc, 
   z.p[(long long)b * z.stride + row] = cadd(acc0, acc1);
 }
 
+// The same product for all right-hand sides as one complex matrix product
+// Z = M R: a block computes 64 rows x 16 right-hand sides over one of
+// CS_KSPLIT slices of the inner index (tiles of 32 staged in LDS, 2 x 2
+// outputs per thread), writing its slice's partial sums; k_coarse_reduce adds
+// the slices in a fixed order.  The inverse is read once per 16 right-hand
+// sides instead of once per right-hand side.
+constexpr int CS_KSPLIT = 8, CS_RT = 64, CS_BT = 16, CS_KC = 32;
+__global__ __launch_bounds__(256) void k_coarse_gemm(const c32* minvT, int Nc, int B, VecSet r, c32* part) {
+  __shared__ c32 sA[CS_KC][CS_RT];
+  __shared__ c32 sR[CS_KC][CS_BT];
+  const int r0 = blockIdx.x * CS_RT, b0 = blockIdx.y * CS_BT;
+  const int klen = ((Nc + CS_KSPLIT - 1) / CS_KSPLIT + CS_KC - 1) / CS_KC * CS_KC;
+  const int kb = blockIdx.z * klen, ke = min(Nc, kb + klen);
+  const int ry = threadIdx.x % 32, bx = threadIdx.x / 32;
+  c32 a00 = make_float2(0.f, 0.f), a01 = a00, a10 = a00, a11 = a00;
+  for (int k0 = kb; k0 < ke; k0 += CS_KC) {
+    for (int i = threadIdx.x; i < CS_KC * CS_RT; i += 256) {
+      const int kk = i / CS_RT, rr = i % CS_RT;
+      const bool ok = k0 + kk < ke && r0 + rr < Nc;
+      sA[kk][rr] = ok ? minvT[(long long)(k0 + kk) * Nc + r0 + rr] : make_float2(0.f, 0.f);
+    }
+    for (int i = threadIdx.x; i < CS_KC * CS_BT; i += 256) {
+      const int q = i / CS_KC, kk = i % CS_KC;
+      const bool ok = k0 + kk < ke && b0 + q < B;
+      sR[kk][q] = ok ? r.p[(long long)(b0 + q) * r.stride + k0 + kk] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < CS_KC; ++kk) {
+      const c32 m0 = sA[kk][ry], m1 = sA[kk][ry + 32], v0 = sR[kk][bx], v1 = sR[kk][bx + 8];
+      a00 = cfma(m0, v0, a00);
+      a01 = cfma(m0, v1, a01);
+      a10 = cfma(m1, v0, a10);
+      a11 = cfma(m1, v1, a11);
+    }
+    __syncthreads();
+  }
+  c32* pp = part + (long long)blockIdx.z * B * Nc;
+  const int ra = r0 + ry, rb = r0 + ry + 32, ba = b0 + bx, bb = b0 + bx + 8;
+  if (ra < Nc && ba < B) pp[(long long)ba * Nc + ra] = a00;
+  if (ra < Nc && bb < B) pp[(long long)bb * Nc + ra] = a01;
+  if (rb < Nc && ba < B) pp[(long long)ba * Nc + rb] = a10;
+  if (rb < Nc && bb < B) pp[(long long)bb * Nc + rb] = a11;
+}
+
+__global__ __launch_bounds__(256) void k_coarse_reduce(const c32* part, int Nc, int B, VecSet z, const int* active) {
+  const int b = blockIdx.y;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= Nc || (active && !active[b])) return;
+  c32 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < CS_KSPLIT; ++q) acc = cadd(acc, part[((long long)q * B + b) * Nc + row]);
+  z.p[(long long)b * z.stride + row] = acc;
+}
+
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -1195,9 +1250,18 @@ void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet
                      N, active);
 }
 
-void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active) {
+void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active,
+                         c32* part) {
+  if (part && B >= 4) {  // as one matrix product (part: coarse_solve_part_size(B, Nc) entries)
+    hipLaunchKernelGGL(k_coarse_gemm, dim3(nblocks(Nc, CS_RT), nblocks(B, CS_BT), CS_KSPLIT), dim3(256), 0, s, minvT,
+                       Nc, B, r, part);
+    hipLaunchKernelGGL(k_coarse_reduce, dim3(nblocks(Nc, 256), B), dim3(256), 0, s, part, Nc, B, z, active);
+    return;
+  }
   hipLaunchKernelGGL(k_coarse_solve, dim3(nblocks(Nc, 256), B), dim3(256), 0, s, minvT, Nc, r, z, active);
 }
+
+size_t coarse_solve_part_size(int B, int Nc) { return (size_t)CS_KSPLIT * B * Nc; }
 
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active) {

@@ -67,7 +67,11 @@ void launch_restrict_residual(hipStream_t s, int dim, int B, VecSet r, ScaleSet 
 // v (or vout when given) = v + P ec
 void launch_prolong_add(hipStream_t s, int dim, int B, VecSet ec, int nc, VecSet v, int n, const int* active,
                         VecSet vout = VecSet{nullptr, 0});
-void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active);
+// z = M r with the explicit inverse (M^T stored); with `part` (coarse_solve_part_size
+// entries) and B >= 4 as one matrix product over all right-hand sides
+void launch_coarse_solve(hipStream_t s, int B, const c32* minvT, int Nc, VecSet r, VecSet z, const int* active,
+                         c32* part = nullptr);
+size_t coarse_solve_part_size(int B, int Nc);
 void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArgs lv, float out_scale, VecSet y,
                   const int* active);
 // out = s_b bvec - K v (bs = per-RHS scale of bvec, NULL = 1)

@@ -92,8 +92,11 @@ def test_vcycle_fused_matches_oracle(pair):
     assert rel(z, ref) < 1e-5
 
 
-@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle", "per_level_launch", "top_w", "generic_w"])
+@pytest.mark.parametrize("variant", ["generic_v", "generic_nu2", "w_cycle", "per_level_launch", "per_level_launch_b5",
+                                     "top_w", "generic_w"])
 def test_cycle_variants_match_oracle(variant):
+    """Cycle variants against the oracle's Alg. 2; per_level_launch_b5 runs the coarsest solve
+    as one matrix product over its 5 right-hand sides."""
     n, w, levels = CASES["ragged"]
     nmap = medium(n, seed=3)
     nu = 2 if variant == "generic_nu2" else 1
@@ -102,8 +105,9 @@ def test_cycle_variants_match_oracle(variant):
     prob = oracle_problem(nmap, w=w, levels=levels, nu=nu)
     hier = Hierarchy(prob)
     ctx = gpu_context(nmap, w=w, levels=levels, nu=nu, cycle=cyc, fused=0 if variant.startswith("generic") else 1,
-                      coarse_single_launch=0 if variant == "per_level_launch" else 1, max_batch=2)
-    r = fields(prob.shape, 2, 61)
+                      coarse_single_launch=0 if variant.startswith("per_level_launch") else 1,
+                      max_batch=5 if variant.endswith("b5") else 2)
+    r = fields(prob.shape, 5 if variant.endswith("b5") else 2, 61)
     z = to_np(ctx.precondition(to_dev(r)))
     oracle_ct = [2] + [1] * (levels - 2) if cyc == 3 else cyc
     ref = np.stack([hier.cycle(ri.ravel(), None, 0, oracle_ct).reshape(prob.shape) for ri in r])
