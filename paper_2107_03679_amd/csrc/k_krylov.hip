@@ -668,23 +668,44 @@ __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, Level
 // columns).  A column whose Cholesky pivot vanishes (the Krylov space is
 // exhausted to working precision) ends the usable basis there.
 template <int M>
-__global__ __launch_bounds__(HELM_WAVE) void k_sstep_solve(KrylovArgs k, const double2* part) {
-  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
+__global__ __launch_bounds__(NT) void k_sstep_solve(KrylovArgs k, const double2* part) {
+  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2, S = NT / NE;
+  static_assert(S >= 1, "one thread per entry at least");
   __shared__ double2 G[NE];
+  __shared__ double2 red[S][NE];
   __shared__ double2 R[NV][NV];  // Cholesky factor (LDS: a per-thread array of this size would spill)
   __shared__ double2 yd[M];
   const int b = blockIdx.x;
   if (!k.active[b]) return;
-  for (int e = 0; e < NE; ++e) {
-    double sx = 0.0, sy = 0.0;
-    for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) {
-      const double2 v = part[((long long)b * k.nblk + blk) * NE + e];
-      sx += v.x;
-      sy += v.y;
+  // thread (e, s) sums the partials of entry e over blocks s, s + S, ... (four loads in
+  // flight), then the S sums of each entry are added in a fixed order
+  if (threadIdx.x < NE * S) {
+    const int e = threadIdx.x % NE, s0 = threadIdx.x / NE;
+    const double2* pb = part + (long long)b * k.nblk * NE + e;
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = make_double2(0.0, 0.0);
+    int blk = s0;
+    for (; blk + 3 * S < k.nblk; blk += 4 * S) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 v = pb[(long long)(blk + u * S) * NE];
+        a[u].x += v.x;
+        a[u].y += v.y;
+      }
     }
-    sx = wave_sum_d(sx);
-    sy = wave_sum_d(sy);
-    if (threadIdx.x == 0) G[e] = make_double2(sx, sy);
+    for (; blk < k.nblk; blk += S) {
+      const double2 v = pb[(long long)blk * NE];
+      a[0].x += v.x;
+      a[0].y += v.y;
+    }
+    red[s0][e] = make_double2((a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y));
+  }
+  __syncthreads();
+  if (threadIdx.x < NE) {
+    double2 g = red[0][threadIdx.x];
+    for (int q = 1; q < S; ++q) g = make_double2(g.x + red[q][threadIdx.x].x, g.y + red[q][threadIdx.x].y);
+    G[threadIdx.x] = g;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -807,7 +828,7 @@ namespace {
 template <int M>
 void sstep_tail(hipStream_t s, int B, const KrylovArgs& k, const LevelArgs& fine, double2* part) {
   hipLaunchKernelGGL(k_sstep_gram<M>, dim3(B * k.nblk), dim3(NT), 0, s, B, k, fine, part);
-  hipLaunchKernelGGL(k_sstep_solve<M>, dim3(B), dim3(HELM_WAVE), 0, s, k, (const double2*)part);
+  hipLaunchKernelGGL(k_sstep_solve<M>, dim3(B), dim3(NT), 0, s, k, (const double2*)part);
 }
 }  // namespace
 
