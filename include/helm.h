@@ -405,7 +405,8 @@ typedef struct {
   int from_cache;                       /* 1: taken from the cache file, not re-timed */
   int levels;
   int down[HELM_TUNE_MAX_LEVELS][2];    /* fused down-leg tile per level: coarse TCX x TCY points */
-  int up[HELM_TUNE_MAX_LEVELS][3];      /* fused up-leg tile per level: fine TX x TY, PY points per thread */
+  int up[HELM_TUNE_MAX_LEVELS][3];      /* fused up-leg tile per level: fine TX x TY, PY points per thread
+                                           (PY 0: one column per lane, every fourth row) */
   long long coarse_max;                 /* levels with at most this many points run in one launch */
   double vcycle_ms;                     /* one preconditioner cycle for B right-hand sides, chosen shapes */
   double vcycle_default_ms;             /* ... with the default shapes (0 when from_cache) */

@@ -360,6 +360,237 @@ __global__ __launch_bounds__(256) void k_up_mv2(int nrhs, VecSet r, ScaleSet rs,
   }
 }
 
+// The same fused up-leg and matvec with a wavefront-wide column layout: the
+// region is 64 columns wide (a 60-column tile and a two-point ring), each
+// thread owns one column (lane) and every fourth row, so that the v2, z and
+// output stages are done by the thread that loaded the point's r, W and A
+// coefficient (kept in registers, no reloads), and no index needs a division.
+template <int TY>
+__global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
+                                                 float omega, VecSet ec, int nc, VecSet z, VecSet w,
+                                                 const int* active) {
+  constexpr int TX = 60, VX = 64, VY = TY + 4, ZY = TY + 2, RPI = 4, IV = VY / RPI;
+  static_assert(VY % RPI == 0, "whole row groups");
+  constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3;
+  __shared__ c32 sE[CY][CX];
+  __shared__ c32 sV[VY][VX];
+  __shared__ c32 sZ[ZY][VX];  // z of region point (lx, ly) at sZ[ly - 1][lx]
+  const int n = lv.n;
+  const int tiles_x = (n + TX - 1) / TX;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  const c32* rb = r.p + (long long)b * r.stride;
+  const float sc = scale_of(rs, b);
+  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int gx = fx0 - 2 + lx;
+  const bool inx = gx >= 0 && gx < n;
+  const bool tcol = lx >= 2 && lx < TX + 2 && gx < n;  // a column of the tile
+  // every global load first: the coarse tile, r, W and (tile points) the A coefficient
+  constexpr int IE = (CX * CY + 255) / 256;
+  c32 evc[IE];
+#pragma unroll
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
+    evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  c32 rv[IV], wv[IV], kv[IV];
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+    const bool ok = inx && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    kv[it] = ok && tcol && ly >= 2 && ly < TY + 2 ? la.coef[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    if (idx < CX * CY) sE[idx / CX][idx % CX] = evc[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {  // v2 = W r + P e (zero outside the grid)
+    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+    c32 v2 = make_float2(0.f, 0.f);
+    if (inx && gy >= 0 && gy < n) {
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
+      const c32 a = sE[J][I], bb = sE[J][I + ox], c = sE[J + oy][I], d = sE[J + oy][I + ox];
+      v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
+    }
+    sV[ly][lx] = v2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {  // z on the tile and a one-point ring (zero outside the grid)
+    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+    if (lx < 1 || lx > VX - 2 || ly < 1 || ly > VY - 2) continue;
+    c32 zv = make_float2(0.f, 0.f);
+    if (inx && gy >= 0 && gy < n) {
+      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+      zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+    }
+    sZ[ly - 1][lx] = zv;
+  }
+  __syncthreads();
+  c32* zb = z.p + (long long)b * z.stride;
+  c32* wb = w.p + (long long)b * w.stride;
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {  // Z_j and W_{j+1} = A Z_j on the tile
+    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+    if (!tcol || ly < 2 || ly >= TY + 2 || gy >= n) continue;
+    const long long p = (long long)gy * n + gx;
+    const c32 zc = sZ[ly - 1][lx];
+    const int ng = ghosts2(gx, gy, n);
+    const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
+    const c32 nb = cadd(cadd(sZ[ly - 1][lx - 1], sZ[ly - 1][lx + 1]), cadd(sZ[ly - 2][lx], sZ[ly][lx]));
+    zb[p] = zc;
+    wb[p] = csub(cmul(D, zc), nb);
+  }
+}
+
+// Column-layout legs (the autotuner's last variants): the fine region is one
+// wavefront wide, each thread owns a column (lane) and every fourth row, so
+// the stages need no division and reuse the registers of the loads.  Same
+// arithmetic per point as k_down_fused2 / k_up_fused2 (bit-identical results).
+// Down-leg: 30 x TCY coarse points, fine region 63 x (2 TCY + 3) at 2 c0 - 2.
+template <int TCY>
+__global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                  VecSet rc, int nc, const int* active) {
+  constexpr int TCX = 30, RXU = 2 * TCX + 3, RYU = 2 * TCY + 3, RPI = 4, VY = (RYU + RPI - 1) / RPI * RPI,
+                IV = VY / RPI;
+  __shared__ c32 sV[VY][64];
+  __shared__ c32 sS[VY][64];
+  const int n = lv.n;
+  const int tiles_x = (nc + TCX - 1) / TCX;
+  const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int cx0 = (id.t % tiles_x) * TCX, cy0 = (id.t / tiles_x) * TCY;
+  const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
+  const float sc = scale_of(rs, b);
+  const c32* rb = r.p + (long long)b * r.stride;
+  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int gx = fx0 + lx;
+  const bool inx = lx < RXU && gx >= 0 && gx < n;
+  c32 rv[IV], wv[IV];
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 + ly;
+    const bool ok = inx && ly < RYU && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    rv[it] = cscale(rv[it], sc);
+    sV[r0 + RPI * it][lx] = cmul(rv[it], wv[it]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 + ly;
+    if (lx < 1 || lx > RXU - 2 || ly < 1 || ly > RYU - 2) continue;
+    c32 sv = make_float2(0.f, 0.f);
+    if (inx && gy >= 0 && gy < n) {
+      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+      sv = cadd(cscale(rv[it], 1.0f - omega), nb);
+    }
+    sS[ly][lx] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < TCX * TCY) {
+    const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+    const int I = cx0 + tx, J = cy0 + ty;
+    if (I < nc && J < nc) {
+      const int sx = 2 * tx + 2, sy = 2 * ty + 2;
+      c32 acc = cscale(sS[sy][sx], 4.0f);
+      acc = cadd(acc, cscale(cadd(cadd(sS[sy][sx - 1], sS[sy][sx + 1]), cadd(sS[sy - 1][sx], sS[sy + 1][sx])), 2.0f));
+      acc = cadd(acc, cadd(cadd(sS[sy - 1][sx - 1], sS[sy - 1][sx + 1]), cadd(sS[sy + 1][sx - 1], sS[sy + 1][sx + 1])));
+      rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
+    }
+  }
+}
+
+// Up-leg: 62 x TY fine points, region (tile and a one-point ring) 64 x (TY + 2).
+template <int TY>
+__global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                VecSet ec, int nc, VecSet z, const int* active) {
+  constexpr int TX = 62, VY = TY + 2, RPI = 4, IV = VY / RPI;
+  static_assert(VY % RPI == 0 && TY % 2 == 0, "whole row groups, even tile origin");
+  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2;
+  __shared__ c32 sE[CY][CX];
+  __shared__ c32 sV[VY][64];
+  const int n = lv.n;
+  const int tiles_x = (n + TX - 1) / TX;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
+  const c32* eb = ec.p + (long long)b * ec.stride;
+  const c32* rb = r.p + (long long)b * r.stride;
+  const float sc = scale_of(rs, b);
+  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int gx = fx0 - 1 + lx;
+  const bool inx = gx >= 0 && gx < n;
+  constexpr int IE = (CX * CY + 255) / 256;
+  c32 evc[IE];
+#pragma unroll
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
+    evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  c32 rv[IV], wv[IV];
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int gy = fy0 - 1 + r0 + RPI * it;
+    const bool ok = inx && gy >= 0 && gy < n;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
+    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    if (idx < CX * CY) sE[idx / CX][idx % CX] = evc[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {  // v2 = W r + P e on the region (zero outside the grid)
+    const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
+    rv[it] = cscale(rv[it], sc);
+    c32 v2 = make_float2(0.f, 0.f);
+    if (inx && gy >= 0 && gy < n) {
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
+      const c32 a = sE[J][I], bb = sE[J][I + ox], c = sE[J + oy][I], d = sE[J + oy][I + ox];
+      v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
+    }
+    sV[ly][lx] = v2;
+  }
+  __syncthreads();
+  c32* zb = z.p + (long long)b * z.stride;
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
+    if (lx < 1 || lx > TX || ly < 1 || ly > TY || gx >= n || gy >= n) continue;
+    const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+    zb[(long long)gy * n + gx] = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+  }
+}
+
 // ------------------------------------------------------------ fused 3D legs
 // The 2D legs' arithmetic with the 7-point operator, 27-point full weighting
 // (weights (1/4, 1/2, 1/4) per axis) and trilinear prolongation.
@@ -1105,8 +1336,11 @@ struct DownTile {
 struct UpTile {
   int tx, ty, py;
 };
-constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}};
-constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}};
+// the last entry of each is the column-layout kernel (k_down_col / k_up_col; repeated
+// visits take the first entry's kernel there)
+constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}};
+constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}};
+constexpr int kDownCol = 5, kUpCol = 5;
 
 template <int TCX, int TCY>
 void down_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
@@ -1172,11 +1406,18 @@ void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
 
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
                    int nc, VecSet z, VecSet w, const int* active) {
-#ifndef HELM_UPMV_TILE
-#define HELM_UPMV_TILE 64, 16
+#ifndef HELM_UPMV_WIDE
+#define HELM_UPMV_WIDE 12
 #endif
-  constexpr int T[2] = {HELM_UPMV_TILE};
-  constexpr int TX = T[0], TY = T[1];
+  if (HELM_UPMV_WIDE > 0) {
+    constexpr int TX = 60, TY = HELM_UPMV_WIDE > 0 ? HELM_UPMV_WIDE : 16;
+    const int n = lv.n;
+    const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_mv2w<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
+                       active);
+    return;
+  }
+  constexpr int TX = 64, TY = 16;
   const int n = lv.n;
   const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
   hipLaunchKernelGGL((k_up_mv2<TX, TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
@@ -1205,6 +1446,12 @@ void mg_up_shape(int cfg, int* tx, int* ty, int* py) {
 
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active, int cfg, VecSet e) {
+  if (cfg == kDownCol && !e.p) {
+    constexpr int TCX = 30, TCY = 8;
+    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+    hipLaunchKernelGGL((k_down_col<TCY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc, active);
+    return;
+  }
   switch (cfg) {
     case 1: down_tile<16, 16>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
     case 2: down_tile<64, 4>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
@@ -1216,6 +1463,12 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
 
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active, int cfg, VecSet e) {
+  if (cfg == kUpCol && !e.p) {
+    constexpr int TX = 62, TY = 14;
+    const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+    hipLaunchKernelGGL((k_up_col<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active);
+    return;
+  }
   switch (cfg) {
     case 1: up_tile<32, 16, 2>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;
     case 2: up_tile<64, 8, 2>(s, B, r, rs, lv, omega, ec, nc, z, active, e); break;

@@ -76,7 +76,7 @@ def test_autotune_keeps_results_and_caches(case, tmp_path):
     assert len(cache.read_text().splitlines()) == 1
 
 
-@pytest.mark.parametrize("variant", range(5))
+@pytest.mark.parametrize("variant", range(6))
 def test_every_tile_variant_is_bit_identical(case, tmp_path, variant):
     nmap, prob, r, ref = case
     ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
