@@ -461,13 +461,17 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
 // the stages need no division and reuse the registers of the loads.  Same
 // arithmetic per point as k_down_fused2 / k_up_fused2 (bit-identical results).
 // Down-leg: 30 x TCY coarse points, fine region 63 x (2 TCY + 3) at 2 c0 - 2.
-template <int TCY>
+// With RES the right-hand side is r - K e (a repeated visit, as in k_down_fused2),
+// formed from e staged in LDS on the region and a one-point ring.
+template <int TCY, bool RES>
 __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                  VecSet rc, int nc, const int* active) {
+                                                  VecSet rc, int nc, const int* active, VecSet ev) {
   constexpr int TCX = 30, RXU = 2 * TCX + 3, RYU = 2 * TCY + 3, RPI = 4, VY = (RYU + RPI - 1) / RPI * RPI,
                 IV = VY / RPI;
+  constexpr int FX = RES ? RXU + 2 : 1, FY = RES ? RYU + 2 : 1;
   __shared__ c32 sV[VY][64];
   __shared__ c32 sS[VY][64];
+  __shared__ c32 sF[FY][FX];
   const int n = lv.n;
   const int tiles_x = (nc + TCX - 1) / TCX;
   const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
@@ -481,7 +485,15 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
   const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
   const int gx = fx0 + lx;
   const bool inx = lx < RXU && gx >= 0 && gx < n;
-  c32 rv[IV], wv[IV];
+  if constexpr (RES) {
+    const c32* fb = ev.p + (long long)b * ev.stride;
+    for (int idx = threadIdx.x; idx < FX * FY; idx += 256) {
+      const int fx = fx0 - 1 + idx % FX, fy = fy0 - 1 + idx / FX;
+      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
+      sF[idx / FX][idx % FX] = ok ? fb[(long long)fy * n + fx] : make_float2(0.f, 0.f);
+    }
+  }
+  c32 rv[IV], wv[IV], kv[RES ? IV : 1];
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int ly = r0 + RPI * it, gy = fy0 + ly;
@@ -489,11 +501,24 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
     const long long p = ok ? (long long)gy * n + gx : 0;
     rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
     wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
   }
+  if constexpr (RES) __syncthreads();
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 + ly;
     rv[it] = cscale(rv[it], sc);
-    sV[r0 + RPI * it][lx] = cmul(rv[it], wv[it]);
+    if constexpr (RES) {
+      // r - K e with K e = D e - (sum of in-grid neighbours); sF is zero outside the grid
+      if (inx && ly < RYU && gy >= 0 && gy < n) {
+        const int ng = ghosts2(gx, gy, n);
+        const c32 D = make_float2(4.0f - kv[it].x - ng * lv.ghost.x, -kv[it].y - ng * lv.ghost.y);
+        const int fx = lx + 1, fy = ly + 1;
+        const c32 nb = cadd(cadd(sF[fy][fx - 1], sF[fy][fx + 1]), cadd(sF[fy - 1][fx], sF[fy + 1][fx]));
+        rv[it] = cadd(csub(rv[it], cmul(D, sF[fy][fx])), nb);
+      }
+    }
+    sV[ly][lx] = cmul(rv[it], wv[it]);
   }
   __syncthreads();
 #pragma unroll
@@ -522,14 +547,18 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
 }
 
 // Up-leg: 62 x TY fine points, region (tile and a one-point ring) 64 x (TY + 2).
-template <int TY>
+// With RES the right-hand side is r - K e, formed from e on the region and a
+// one-point ring, and the leg writes e + z (as k_up_fused2).
+template <int TY, bool RES>
 __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                VecSet ec, int nc, VecSet z, const int* active) {
+                                                VecSet ec, int nc, VecSet z, const int* active, VecSet ev) {
   constexpr int TX = 62, VY = TY + 2, RPI = 4, IV = VY / RPI;
   static_assert(VY % RPI == 0 && TY % 2 == 0, "whole row groups, even tile origin");
   constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2;
+  constexpr int FX = RES ? 66 : 1, FY = RES ? VY + 2 : 1;
   __shared__ c32 sE[CY][CX];
   __shared__ c32 sV[VY][64];
+  __shared__ c32 sF[FY][FX];
   const int n = lv.n;
   const int tiles_x = (n + TX - 1) / TX;
   const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
@@ -553,7 +582,15 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
     const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
     evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
   }
-  c32 rv[IV], wv[IV];
+  if constexpr (RES) {
+    const c32* fb = ev.p + (long long)b * ev.stride;
+    for (int idx = threadIdx.x; idx < FX * FY; idx += 256) {
+      const int fx = fx0 - 2 + idx % FX, fy = fy0 - 2 + idx / FX;
+      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
+      sF[idx / FX][idx % FX] = ok ? fb[(long long)fy * n + fx] : make_float2(0.f, 0.f);
+    }
+  }
+  c32 rv[IV], wv[IV], kv[RES ? IV : 1];
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int gy = fy0 - 1 + r0 + RPI * it;
@@ -561,6 +598,7 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
     const long long p = ok ? (long long)gy * n + gx : 0;
     rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
     wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
   }
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
@@ -572,6 +610,15 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
   for (int it = 0; it < IV; ++it) {  // v2 = W r + P e on the region (zero outside the grid)
     const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
     rv[it] = cscale(rv[it], sc);
+    if constexpr (RES) {
+      if (inx && gy >= 0 && gy < n) {
+        const int ng = ghosts2(gx, gy, n);
+        const c32 D = make_float2(4.0f - kv[it].x - ng * lv.ghost.x, -kv[it].y - ng * lv.ghost.y);
+        const int fx = lx + 1, fy = ly + 1;
+        const c32 nb = cadd(cadd(sF[fy][fx - 1], sF[fy][fx + 1]), cadd(sF[fy - 1][fx], sF[fy + 1][fx]));
+        rv[it] = cadd(csub(rv[it], cmul(D, sF[fy][fx])), nb);
+      }
+    }
     c32 v2 = make_float2(0.f, 0.f);
     if (inx && gy >= 0 && gy < n) {
       const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
@@ -587,7 +634,9 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
     const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
     if (lx < 1 || lx > TX || ly < 1 || ly > TY || gx >= n || gy >= n) continue;
     const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-    zb[(long long)gy * n + gx] = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+    c32 zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+    if constexpr (RES) zv = cadd(zv, sF[ly + 1][lx + 1]);
+    zb[(long long)gy * n + gx] = zv;
   }
 }
 
@@ -1336,8 +1385,7 @@ struct DownTile {
 struct UpTile {
   int tx, ty, py;
 };
-// the last entry of each is the column-layout kernel (k_down_col / k_up_col; repeated
-// visits take the first entry's kernel there)
+// the last entry of each is the column-layout kernel (k_down_col / k_up_col)
 constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}};
 constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}};
 constexpr int kDownCol = 5, kUpCol = 5;
@@ -1446,10 +1494,15 @@ void mg_up_shape(int cfg, int* tx, int* ty, int* py) {
 
 void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active, int cfg, VecSet e) {
-  if (cfg == kDownCol && !e.p) {
+  if (cfg == kDownCol) {
     constexpr int TCX = 30, TCY = 8;
     const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
-    hipLaunchKernelGGL((k_down_col<TCY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc, active);
+    if (e.p)
+      hipLaunchKernelGGL((k_down_col<TCY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                         active, e);
+    else
+      hipLaunchKernelGGL((k_down_col<TCY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                         active, e);
     return;
   }
   switch (cfg) {
@@ -1463,10 +1516,15 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
 
 void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active, int cfg, VecSet e) {
-  if (cfg == kUpCol && !e.p) {
+  if (cfg == kUpCol) {
     constexpr int TX = 62, TY = 14;
     const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_col<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active);
+    if (e.p)
+      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                         active, e);
+    else
+      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                         active, e);
     return;
   }
   switch (cfg) {

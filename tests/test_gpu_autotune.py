@@ -76,10 +76,13 @@ def test_autotune_keeps_results_and_caches(case, tmp_path):
     assert len(cache.read_text().splitlines()) == 1
 
 
+@pytest.mark.parametrize("cycle", [1, 3])
 @pytest.mark.parametrize("variant", range(6))
-def test_every_tile_variant_is_bit_identical(case, tmp_path, variant):
+def test_every_tile_variant_is_bit_identical(case, tmp_path, variant, cycle):
+    """Forced tile shapes against the defaults; cycle 3 adds the repeated visit of level 1
+    (the legs that form r - K e themselves)."""
     nmap, prob, r, ref = case
-    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B, cycle=cycle)
     rd = to_dev(r)
     z0 = ctx.precondition(rd)
     first = tmp_path / "first.jsonl"
