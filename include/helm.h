@@ -106,8 +106,9 @@ typedef struct {
   int krylov;       /* HELM_KRYLOV_SSTEP (default), HELM_KRYLOV_FGMRES or HELM_KRYLOV_BICGSTAB */
   int fused_step;   /* finest level of the s-step form (2D, fused legs): 0 = separate kernels;
                        1 = the work between two coarse visits (up-leg, basis matvec, next
-                       down-leg) is one kernel: 36% fewer bytes, but its six barrier stages leave
-                       it latency-bound, no faster than the separate kernels on MI355X;
+                       down-leg) is one kernel: 36% fewer bytes, but the wider region and six
+                       barrier stages leave it slower than option 2 on MI355X (200 against
+                       138 + 56 us per step at 512^2 x 60);
                        2 = the up-leg and the basis matvec W_{j+1} = A Z_j in one kernel, which
                        saves the matvec's pass over Z_j (2) */
 } helm_opts;

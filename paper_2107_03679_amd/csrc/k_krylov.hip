@@ -481,10 +481,6 @@ __global__ __launch_bounds__(NT) void k_sstep_matvec(int nrhs, KrylovArgs k, int
 // numbers up to ~1e6 at m = 12) and the Cholesky factor of G loses the
 // square of that, so G must be the Gram matrix of the stored vectors to
 // FP64 accuracy.
-#ifndef HELM_GRAM_LDS
-#define HELM_GRAM_LDS 1
-#endif
-#if HELM_GRAM_LDS
 // Entry e of the packed upper triangle of an nv x nv matrix is (packed_row,
 // packed_col); the loops fold to constants where e does.
 __host__ __device__ constexpr int packed_row(int e, int nv) {
@@ -498,10 +494,7 @@ __host__ __device__ constexpr int packed_col(int e, int nv) {
   return i + e;
 }
 
-#ifndef HELM_GRAM_GP
-#define HELM_GRAM_GP 256
-#endif
-constexpr int GP = HELM_GRAM_GP;  // points staged per step
+constexpr int GP = 256;  // points staged per step (measured: 64 slower, 128 ~5% slower)
 
 // acc[U] += conj(w_i) w_j for the entry e = G + U NWAVE = (i, j) and the ones after it
 template <int NV, int G, int U>
@@ -607,59 +600,6 @@ __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, Level
     if (lane == 0 && e < NE) part[((long long)b * k.nblk + blk) * NE + e] = make_double2(sx, sy);
   }
 }
-#else
-template <int M>
-__global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, LevelArgs fine, double2* part) {
-  constexpr int NV = M + 1, NE = NV * (NV + 1) / 2;
-  __shared__ double2 red[NWAVE][NE];
-  const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
-  const int b = id.b, blk = id.t;
-  if (!k.active[b]) return;
-  const float s0 = k.vs[b * (k.m + 1)];
-  const long long p0 = (long long)blk * CH + threadIdx.x;
-  const c32* z = k.Z + zidx(k, b, M - 1);
-  double2 acc[NE];
-#pragma unroll
-  for (int e = 0; e < NE; ++e) acc[e] = make_double2(0.0, 0.0);
-  Coord c = coord_of32((unsigned)p0, (unsigned)fine.n, k.dim);
-#pragma unroll 2
-  for (int t = 0; t < PPT; ++t) {
-    const long long p = p0 + (long long)t * NT;
-    if (p < k.N) {
-      c32 w[NV];
-#pragma unroll
-      for (int i = 0; i < M; ++i) w[i] = k.V[vidx(k, b, i) + p];
-      w[0] = cscale(w[0], s0);
-      w[M] = stencil_point(z, p, c, fine.n, k.dim, diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim));
-      double2 wd[NV];
-#pragma unroll
-      for (int i = 0; i < NV; ++i) wd[i] = make_double2((double)w[i].x, (double)w[i].y);
-      int e = 0;
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = i; j < NV; ++j, ++e) {
-          acc[e].x = fma(wd[i].x, wd[j].x, fma(wd[i].y, wd[j].y, acc[e].x));
-          acc[e].y = fma(wd[i].x, wd[j].y, fma(-wd[i].y, wd[j].x, acc[e].y));
-        }
-    }
-    coord_advance(c, NT, fine.n, k.dim);
-  }
-  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
-#pragma unroll
-  for (int e = 0; e < NE; ++e) {
-    const double sx = wave_sum_d(acc[e].x), sy = wave_sum_d(acc[e].y);
-    if (lane == 0) red[wave][e] = make_double2(sx, sy);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += NT) {
-    double2 sum = red[0][e];
-#pragma unroll
-    for (int q = 1; q < NWAVE; ++q) sum = make_double2(sum.x + red[q][e].x, sum.y + red[q][e].y);
-    part[((long long)b * k.nblk + blk) * NE + e] = sum;
-  }
-}
-#endif
 
 // Per right-hand side (one wavefront): reduce the Gram partials (FP64, fixed
 // order), Cholesky G = R^H R, Givens rotations of the Hessenberg R[:, 1:],

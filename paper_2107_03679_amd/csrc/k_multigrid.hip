@@ -250,116 +250,6 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
   }
 }
 
-// Up-leg of Z_j fused with the next basis vector W_{j+1} = A Z_j of the s-step
-// form, on a TX x TY tile of fine points:
-//   v2 = W r + P e on the tile and a two-point ring   -> LDS
-//   z  = (1 - w) v2 + W (r + neighbours of v2) on the tile and a one-point ring -> LDS
-//   Z_j = z and W_{j+1} = D_A z - (neighbours of z) on the tile
-// (la is the operator A, lv the level's preconditioning operator).  Saves the
-// separate matvec's pass over Z_j.
-template <int TX, int TY>
-__global__ __launch_bounds__(256) void k_up_mv2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
-                                                float omega, VecSet ec, int nc, VecSet z, VecSet w,
-                                                const int* active) {
-  constexpr int NT = 256;
-  constexpr int VX = TX + 4, VY = TY + 4, ZX = TX + 2, ZY = TY + 2;
-  constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3;
-  __shared__ c32 sE[CY][CX];
-  __shared__ c32 sV[VY][VX];
-  __shared__ c32 sZ[ZY][ZX];
-  const int n = lv.n;
-  const int tiles_x = (n + TX - 1) / TX;
-  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
-  if (active && !active[b]) return;
-  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
-  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
-  const c32* eb = ec.p + (long long)b * ec.stride;
-  const c32* rb = r.p + (long long)b * r.stride;
-  const float sc = scale_of(rs, b);
-  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
-    const int I = cxs + idx % CX, J = cys + idx / CX;
-    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
-    sE[idx / CX][idx % CX] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  constexpr int IV = (VX * VY + NT - 1) / NT, IZ = (ZX * ZY + NT - 1) / NT, IT = (TX * TY + NT - 1) / NT;
-  {
-    c32 rv[IV], wv[IV];
-#pragma unroll
-    for (int it = 0; it < IV; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      const int gx = fx0 - 2 + idx % VX, gy = fy0 - 2 + idx / VX;
-      const bool ok = idx < VX * VY && gx >= 0 && gx < n && gy >= 0 && gy < n;
-      const long long p = ok ? (long long)gy * n + gx : 0;
-      rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-      wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int it = 0; it < IV; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx >= VX * VY) continue;
-      const int gx = fx0 - 2 + idx % VX, gy = fy0 - 2 + idx / VX;
-      c32 v2 = make_float2(0.f, 0.f);
-      if (gx >= 0 && gx < n && gy >= 0 && gy < n)
-        v2 = cadd(cmul(cscale(rv[it], sc), wv[it]), prolong_lds<CX>(sE, gx, gy, cxs, cys));
-      sV[idx / VX][idx % VX] = v2;
-    }
-  }
-  // r and W on the one-point ring region (cached: the loads above fetched them)
-  c32 rz[IZ], wz[IZ];
-#pragma unroll
-  for (int it = 0; it < IZ; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 - 1 + idx % ZX, gy = fy0 - 1 + idx / ZX;
-    const bool ok = idx < ZX * ZY && gx >= 0 && gx < n && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rz[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-    wz[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < IZ; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= ZX * ZY) continue;
-    const int lx = idx % ZX + 1, ly = idx / ZX + 1;  // sV coordinates
-    const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
-    c32 zv = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-      zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wz[it], cadd(cscale(rz[it], sc), nb)));
-    }
-    sZ[idx / ZX][idx % ZX] = zv;
-  }
-  // the operator's coefficient at the own points
-  c32 kv[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 + idx % TX, gy = fy0 + idx / TX;
-    const bool ok = idx < TX * TY && gx < n && gy < n;
-    kv[it] = ok ? la.coef[(long long)gy * n + gx] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  c32* zb = z.p + (long long)b * z.stride;
-  c32* wb = w.p + (long long)b * w.stride;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int lx = idx % TX + 1, ly = idx / TX + 1;  // sZ coordinates
-    const int gx = fx0 + lx - 1, gy = fy0 + ly - 1;
-    if (idx >= TX * TY || gx >= n || gy >= n) continue;
-    const long long p = (long long)gy * n + gx;
-    const c32 zc = sZ[ly][lx];
-    const int ng = ghosts2(gx, gy, n);
-    const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
-    const c32 nb = cadd(cadd(sZ[ly][lx - 1], sZ[ly][lx + 1]), cadd(sZ[ly - 1][lx], sZ[ly + 1][lx]));
-    zb[p] = zc;
-    wb[p] = csub(cmul(D, zc), nb);
-  }
-}
-
 // The same fused up-leg and matvec with a wavefront-wide column layout: the
 // region is 64 columns wide (a 60-column tile and a two-point ring), each
 // thread owns one column (lane) and every fourth row, so that the v2, z and
@@ -640,76 +530,136 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
   }
 }
 
-// ------------------------------------------------------------ fused 3D legs
-// The 2D legs' arithmetic with the 7-point operator, 27-point full weighting
-// (weights (1/4, 1/2, 1/4) per axis) and trilinear prolongation.
-// Down-leg on a TCX x TCY x TCZ tile of coarse points: r, W on the fine region
-// with a two-point halo (origin 2 c0 - 2), v1 = W r -> LDS; s on the region's
-// interior -> LDS; rc = 4 R s.
-template <int TCX, int TCY, int TCZ>
-__global__ __launch_bounds__(TCX* TCY* TCZ) void k_down_fused3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
-                                                                float omega, VecSet rc, int nc, const int* active) {
-  constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3, RZ = 2 * TCZ + 3;
-  constexpr int SX = RX - 2, SY = RY - 2, SZ = RZ - 2;
-  constexpr int NT = TCX * TCY * TCZ, NR = RX * RY * RZ, IT = (NR + NT - 1) / NT;
-  __shared__ c32 sV[RZ][RY][RX];
-  __shared__ c32 sS[SZ][SY][SX];
+// The finest-level step of the s-step basis in the column layout: up-leg of
+// Z_j, W_{j+1} = A Z_j and the down-leg of W_{j+1} in one launch.  A 56 x 12
+// tile; the region is 64 x 20 (a four-point ring): v2 on all of it, z on a
+// three-point ring, W_{j+1} on a two-point ring (its v1 = W W_{j+1}), s on a
+// one-point ring, and the coarse right-hand side of the 28 x 6 coarse points
+// whose fine points lie in the tile.  The basis vector W_{j+1} carries scale 1.
+// Same arithmetic per point as the separate kernels.
+__global__ __launch_bounds__(256) void k_step_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
+                                                  float omega, VecSet ec, int nc, VecSet z, VecSet w, VecSet rc,
+                                                  const int* active) {
+  constexpr int TX = 56, TY = 12, VY = TY + 8, RPI = 4, IV = VY / RPI;
+  constexpr int CX = 33, CY = TY / 2 + 5, KX = TX / 2, KY = TY / 2;
+  __shared__ c32 sE[CY][CX];
+  __shared__ c32 sA[VY][64];  // v2, then v1 = W W_{j+1}
+  __shared__ c32 sB[VY][64];  // z, then s
   const int n = lv.n;
-  const int tx_n = (nc + TCX - 1) / TCX, ty_n = (nc + TCY - 1) / TCY;
-  const unsigned tiles = (unsigned)(tx_n * ty_n * ((nc + TCZ - 1) / TCZ));
+  const int tiles_x = (n + TX - 1) / TX;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
   const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
   const int b = id.b;
   if (active && !active[b]) return;
-  const int cx0 = (id.t % tx_n) * TCX, cy0 = ((id.t / tx_n) % ty_n) * TCY, cz0 = (id.t / (tx_n * ty_n)) * TCZ;
-  const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2, fz0 = 2 * cz0 - 2;
-  const float sc = scale_of(rs, b);
+  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int cxs = fx0 / 2 - 2, cys = fy0 / 2 - 2;
+  const c32* eb = ec.p + (long long)b * ec.stride;
   const c32* rb = r.p + (long long)b * r.stride;
-  const long long n2 = (long long)n * n;
-  c32 rv[IT];
+  const float sc = scale_of(rs, b);
+  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int gx = fx0 - 4 + lx;
+  const bool inx = gx >= 0 && gx < n;
+  constexpr int IE = (CX * CY + 255) / 256;
+  c32 evc[IE];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
-    const int gx = fx0 + lx, gy = fy0 + ly, gz = fz0 + lz;
-    const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-    const long long p = ok ? gz * n2 + (long long)gy * n + gx : 0;
-    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
-    const c32 wv = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    if (idx < NR) sV[lz][ly][lx] = cmul(rv[it], wv);
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
+    evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+  }
+  c32 rv[IV], wv[IV], kv[IV];
+  bool ing[IV];
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 4 + ly;
+    ing[it] = inx && gy >= 0 && gy < n;
+    const long long p = ing[it] ? (long long)gy * n + gx : 0;
+    rv[it] = ing[it] ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
+    wv[it] = ing[it] ? lv.wd[p] : make_float2(0.f, 0.f);
+    kv[it] = ing[it] && lx >= 2 && lx <= 61 && ly >= 2 && ly <= VY - 3 ? la.coef[p] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IE; ++it) {
+    const int idx = threadIdx.x + it * 256;
+    if (idx < CX * CY) sE[idx / CX][idx % CX] = evc[it];
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
-    if (lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1 || lz == 0 || lz == RZ - 1) continue;
-    const int gx = fx0 + lx, gy = fy0 + ly, gz = fz0 + lz;
-    c32 sv = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
-      const c32 nb = cadd(cadd(cadd(sV[lz][ly][lx - 1], sV[lz][ly][lx + 1]), cadd(sV[lz][ly - 1][lx], sV[lz][ly + 1][lx])),
-                          cadd(sV[lz - 1][ly][lx], sV[lz + 1][ly][lx]));
-      sv = cadd(cscale(rv[it], 1.0f - omega), nb);
+  for (int it = 0; it < IV; ++it) {  // v2 = W r + P e
+    const int ly = r0 + RPI * it, gy = fy0 - 4 + ly;
+    c32 v2 = make_float2(0.f, 0.f);
+    if (ing[it]) {
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
+      const c32 a = sE[J][I], bb = sE[J][I + ox], c = sE[J + oy][I], d = sE[J + oy][I + ox];
+      v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
     }
-    sS[lz - 1][ly - 1][lx - 1] = sv;
+    sA[ly][lx] = v2;
   }
   __syncthreads();
-  const int tx = threadIdx.x % TCX, ty = (threadIdx.x / TCX) % TCY, tz = threadIdx.x / (TCX * TCY);
-  const int I = cx0 + tx, J = cy0 + ty, K = cz0 + tz;
-  if (I < nc && J < nc && K < nc) {
-    const float w1[3] = {0.25f, 0.5f, 0.25f};
-    c32 acc = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
+  for (int it = 0; it < IV; ++it) {  // z on the three-point ring
+    const int ly = r0 + RPI * it;
+    if (lx < 1 || lx > 62 || ly < 1 || ly > VY - 2) continue;
+    c32 zv = make_float2(0.f, 0.f);
+    if (ing[it]) {
+      const c32 nb = cadd(cadd(sA[ly][lx - 1], sA[ly][lx + 1]), cadd(sA[ly - 1][lx], sA[ly + 1][lx]));
+      zv = cadd(cscale(sA[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+    }
+    sB[ly][lx] = zv;
+  }
+  __syncthreads();
+  c32* zb = z.p + (long long)b * z.stride;
+  c32* wb = w.p + (long long)b * w.stride;
+  c32 wn[IV];
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
+  for (int it = 0; it < IV; ++it) {  // W_{j+1} = A z on the two-point ring; v1 = W W_{j+1}
+    const int ly = r0 + RPI * it, gy = fy0 - 4 + ly;
+    wn[it] = make_float2(0.f, 0.f);
+    if (lx < 2 || lx > 61 || ly < 2 || ly > VY - 3) continue;
+    c32 v1 = make_float2(0.f, 0.f);
+    if (ing[it]) {
+      const c32 zc = sB[ly][lx];
+      const int ng = ghosts2(gx, gy, n);
+      const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
+      const c32 nb = cadd(cadd(sB[ly][lx - 1], sB[ly][lx + 1]), cadd(sB[ly - 1][lx], sB[ly + 1][lx]));
+      wn[it] = csub(cmul(D, zc), nb);
+      v1 = cmul(wn[it], wv[it]);
+      if (lx >= 4 && lx < TX + 4 && ly >= 4 && ly < TY + 4) {
+        const long long p = (long long)gy * n + gx;
+        zb[p] = zc;
+        wb[p] = wn[it];
+      }
+    }
+    sA[ly][lx] = v1;
+  }
+  __syncthreads();
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-          acc = cadd(acc, cscale(sS[2 * tz + dz][2 * ty + dy][2 * tx + dx], w1[dx] * w1[dy] * w1[dz]));
-    rc.p[(long long)b * rc.stride + ((long long)K * nc + J) * nc + I] = cscale(acc, 4.0f);
+  for (int it = 0; it < IV; ++it) {  // s = W_{j+1} - K v1 on the one-point ring
+    const int ly = r0 + RPI * it;
+    if (lx < 3 || lx > 60 || ly < 3 || ly > VY - 4) continue;
+    c32 sv = make_float2(0.f, 0.f);
+    if (ing[it]) {
+      const c32 nb = cadd(cadd(sA[ly][lx - 1], sA[ly][lx + 1]), cadd(sA[ly - 1][lx], sA[ly + 1][lx]));
+      sv = cadd(cscale(wn[it], 1.0f - omega), nb);
+    }
+    sB[ly][lx] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < KX * KY) {  // the coarse right-hand side 4 R s
+    const int tx = threadIdx.x % KX, ty = threadIdx.x / KX;
+    const int I = fx0 / 2 + tx, J = fy0 / 2 + ty;
+    if (I < nc && J < nc) {
+      const int sx = 2 * tx + 4, sy = 2 * ty + 4;
+      c32 acc = cscale(sB[sy][sx], 4.0f);
+      acc = cadd(acc, cscale(cadd(cadd(sB[sy][sx - 1], sB[sy][sx + 1]), cadd(sB[sy - 1][sx], sB[sy + 1][sx])), 2.0f));
+      acc = cadd(acc, cadd(cadd(sB[sy - 1][sx - 1], sB[sy - 1][sx + 1]), cadd(sB[sy + 1][sx - 1], sB[sy + 1][sx + 1])));
+      rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
+    }
   }
 }
 
+// ------------------------------------------------------------ fused 3D legs
 // Down-leg marching in z: a TCX x TCY column of coarse points, coarse planes
 // [kz0, kz0 + KZ).  Per fine plane f (bottom to top): v1(f) = W r on the
 // plane's (2 TCX + 3) x (2 TCY + 3) region -> one of three LDS planes; then
@@ -814,80 +764,6 @@ __global__ __launch_bounds__(256) void k_down_march3(int nrhs, VecSet r, ScaleSe
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) rp[it] = rf[it];
-  }
-}
-
-// Up-leg on a TX x TY x TZ tile of fine points: v2 = W r + P e on the tile and a
-// one-point ring -> LDS; z = (1 - w) v2 + W (r + sum of the 6 neighbours of v2).
-template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_up_fused3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                    VecSet ec, int nc, VecSet z, const int* active) {
-  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
-  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2;
-  constexpr int NT = 256, NH = HX * HY * HZ, IT = (NH + NT - 1) / NT;
-  __shared__ c32 sE[CZ][CY][CX];
-  __shared__ c32 sV[HZ][HY][HX];
-  const int n = lv.n;
-  const int tx_n = (n + TX - 1) / TX, ty_n = (n + TY - 1) / TY;
-  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + TZ - 1) / TZ));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
-  if (active && !active[b]) return;
-  const int fx0 = (id.t % tx_n) * TX, fy0 = ((id.t / tx_n) % ty_n) * TY, fz0 = (id.t / (tx_n * ty_n)) * TZ;
-  const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1, czs = fz0 / 2 - 1;
-  const float sc = scale_of(rs, b);
-  const c32* rb = r.p + (long long)b * r.stride;
-  const c32* eb = ec.p + (long long)b * ec.stride;
-  const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
-  for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
-    const int I = cxs + idx % CX, J = cys + (idx / CX) % CY, K = czs + idx / (CX * CY);
-    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
-    sE[idx / (CX * CY)][(idx / CX) % CY][idx % CX] = ok ? eb[K * nc2 + (long long)J * nc + I] : make_float2(0.f, 0.f);
-  }
-  c32 rv[IT], wv[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + (idx / HX) % HY, gz = fz0 - 1 + idx / (HX * HY);
-    const bool ok = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-    const long long p = ok ? gz * n2 + (long long)gy * n + gx : 0;
-    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NH) continue;
-    const int lx = idx % HX, ly = (idx / HX) % HY, lz = idx / (HX * HY);
-    const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
-    c32 v2 = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
-      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, K = (gz >> 1) - czs;
-      const int ox = gx & 1, oy = gy & 1, oz = gz & 1;
-      c32 pe = make_float2(0.f, 0.f);
-      for (int kz = 0; kz <= oz; ++kz)
-        for (int ky = 0; ky <= oy; ++ky)
-          for (int kx = 0; kx <= ox; ++kx) pe = cadd(pe, sE[K + kz][J + ky][I + kx]);
-      const float wgt = (ox ? 0.5f : 1.0f) * (oy ? 0.5f : 1.0f) * (oz ? 0.5f : 1.0f);
-      v2 = cadd(cmul(rv[it], wv[it]), cscale(pe, wgt));
-    }
-    sV[lz][ly][lx] = v2;
-  }
-  __syncthreads();
-  c32* zb = z.p + (long long)b * z.stride;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NH) continue;
-    const int lx = idx % HX, ly = (idx / HX) % HY, lz = idx / (HX * HY);
-    if (lx == 0 || lx == HX - 1 || ly == 0 || ly == HY - 1 || lz == 0 || lz == HZ - 1) continue;
-    const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
-    if (gx >= n || gy >= n || gz >= n) continue;
-    const c32 nb = cadd(cadd(cadd(sV[lz][ly][lx - 1], sV[lz][ly][lx + 1]), cadd(sV[lz][ly - 1][lx], sV[lz][ly + 1][lx])),
-                        cadd(sV[lz - 1][ly][lx], sV[lz + 1][ly][lx]));
-    zb[gz * n2 + (long long)gy * n + gx] =
-        cadd(cscale(sV[lz][ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
   }
 }
 
@@ -1025,152 +901,6 @@ __global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet 
   }
 }
 
-// ------------------------------------------------- fused finest-level step
-// One kernel for the finest-level work between two coarse-grid visits of
-// consecutive s-step basis vectors: the up-leg of step j, the basis matvec
-// W_{j+1} = A Z_j, and the down-leg of step j+1:
-//   v2 = W r + P e;  z = (1 - w) v2 + W (r + sum nb v2)          (Z_j, written)
-//   w  = A z                                                     (W_{j+1}, written)
-//   v1 = W w;  s = (1 - w) w + sum nb v1;  rc = 4 R s            (next coarse rhs, written)
-// on a TCX x TCY tile of coarse points of the next down-leg.  Relative to the
-// tile's first owned fine point, s is needed on [-1, 2T-1], v1 and w on
-// [-2, 2T], z on [-3, 2T+1], v2 (and r, W) on [-4, 2T+2]: each thread keeps
-// r, W and w of its points of that widest region in registers; v2/s and z/v1
-// share two LDS planes.  Fine points [0, 2T) of the tile are owned (written).
-// r = s_j W_j with its per-RHS scale; W_{j+1} is unscaled.
-template <int TCX, int TCY>
-__global__ __launch_bounds__(TCX* TCY) void k_step_fused2(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv,
-                                                           LevelArgs la, float omega, VecSet ec, int nc, VecSet zout,
-                                                           VecSet wout, VecSet rc, const int* active) {
-  constexpr int RX = 2 * TCX + 7, RY = 2 * TCY + 7;  // widest region, origin (-4, -4)
-  constexpr int NT = TCX * TCY, NR = RX * RY, IT = (NR + NT - 1) / NT;
-  constexpr int CX = TCX + 4, CY = TCY + 4;          // coarse correction, origin (cx0 - 2, cy0 - 2)
-  __shared__ c32 sA[RY][RX];  // v2, then s
-  __shared__ c32 sB[RY][RX];  // z, then v1
-  __shared__ c32 sE[CY][CX];
-  const int n = lv.n;
-  const int tiles_x = (nc + TCX - 1) / TCX;
-  const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
-  if (active && !active[b]) return;
-  const int cx0 = (id.t % tiles_x) * TCX, cy0 = (id.t / tiles_x) * TCY;
-  const int fx0 = 2 * cx0, fy0 = 2 * cy0;
-  const float sc = scale_of(rs, b);
-  const c32* rb = r.p + (long long)b * r.stride;
-  const c32* eb = ec.p + (long long)b * ec.stride;
-  // ---- loads: r and W on the widest region (registers), the coarse correction (LDS)
-  c32 rv[IT], wv[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 - 4 + idx % RX, gy = fy0 - 4 + idx / RX;
-    const bool ok = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-  }
-  for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
-    const int I = cx0 - 2 + idx % CX, J = cy0 - 2 + idx / CX;
-    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
-    sE[idx / CX][idx % CX] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  // ---- v2 = W r + P e on [-4, 2T+2]  (0 outside the grid)
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = idx / RX;
-    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
-    c32 v2 = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const int I = (gx >> 1) - (cx0 - 2), J = (gy >> 1) - (cy0 - 2);
-      const int ox = gx & 1, oy = gy & 1;
-      c32 pe = sE[J][I];
-      if (ox && oy) pe = cscale(cadd(cadd(pe, sE[J][I + 1]), cadd(sE[J + 1][I], sE[J + 1][I + 1])), 0.25f);
-      else if (ox) pe = cscale(cadd(pe, sE[J][I + 1]), 0.5f);
-      else if (oy) pe = cscale(cadd(pe, sE[J + 1][I]), 0.5f);
-      v2 = cadd(cmul(rv[it], wv[it]), pe);
-    }
-    sA[ly][lx] = v2;
-  }
-  __syncthreads();
-  // ---- z = (1 - w) v2 + W (r + sum nb v2) on [-3, 2T+1]; Z_j on the owned points
-  c32* zb = zout.p + (long long)b * zout.stride;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = idx / RX;
-    if (lx < 1 || lx > RX - 2 || ly < 1 || ly > RY - 2) continue;
-    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
-    c32 z = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const c32 nb = cadd(cadd(sA[ly][lx - 1], sA[ly][lx + 1]), cadd(sA[ly - 1][lx], sA[ly + 1][lx]));
-      z = cadd(cscale(sA[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
-      if (lx >= 4 && lx < 4 + 2 * TCX && ly >= 4 && ly < 4 + 2 * TCY) zb[(long long)gy * n + gx] = z;
-    }
-    sB[ly][lx] = z;
-  }
-  __syncthreads();
-  // ---- w = A z on [-2, 2T]; W_{j+1} on the owned points (w kept in registers)
-  c32* wb = wout.p + (long long)b * wout.stride;
-  c32 wa[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    wa[it] = make_float2(0.f, 0.f);
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = idx / RX;
-    if (lx < 2 || lx > RX - 3 || ly < 2 || ly > RY - 3) continue;
-    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const long long p = (long long)gy * n + gx;
-      const c32 D = diag_at(la, p, ghosts2(gx, gy, n), 2);
-      const c32 nb = cadd(cadd(sB[ly][lx - 1], sB[ly][lx + 1]), cadd(sB[ly - 1][lx], sB[ly + 1][lx]));
-      wa[it] = csub(cmul(D, sB[ly][lx]), nb);
-      if (lx >= 4 && lx < 4 + 2 * TCX && ly >= 4 && ly < 4 + 2 * TCY) wb[p] = wa[it];
-    }
-  }
-  __syncthreads();
-  // ---- v1 = W w on [-2, 2T] (into the z plane)
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = idx / RX;
-    if (lx < 2 || lx > RX - 3 || ly < 2 || ly > RY - 3) continue;
-    sB[ly][lx] = cmul(wv[it], wa[it]);
-  }
-  __syncthreads();
-  // ---- s = (1 - w) w + sum nb v1 on [-1, 2T-1] (into the v2 plane; 0 outside the grid)
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (idx >= NR) continue;
-    const int lx = idx % RX, ly = idx / RX;
-    if (lx < 3 || lx > RX - 4 || ly < 3 || ly > RY - 4) continue;
-    const int gx = fx0 - 4 + lx, gy = fy0 - 4 + ly;
-    c32 sv = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const c32 nb = cadd(cadd(sB[ly][lx - 1], sB[ly][lx + 1]), cadd(sB[ly - 1][lx], sB[ly + 1][lx]));
-      sv = cadd(cscale(wa[it], 1.0f - omega), nb);
-    }
-    sA[ly][lx] = sv;
-  }
-  __syncthreads();
-  // ---- rc = 4 R s at the tile's coarse points
-  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
-  const int I = cx0 + tx, J = cy0 + ty;
-  if (I < nc && J < nc) {
-    const int sx = 4 + 2 * tx, sy = 4 + 2 * ty;
-    c32 acc = cscale(sA[sy][sx], 4.0f);
-    acc = cadd(acc, cscale(cadd(cadd(sA[sy][sx - 1], sA[sy][sx + 1]), cadd(sA[sy - 1][sx], sA[sy + 1][sx])), 2.0f));
-    acc = cadd(acc, cadd(cadd(sA[sy - 1][sx - 1], sA[sy - 1][sx + 1]), cadd(sA[sy + 1][sx - 1], sA[sy + 1][sx + 1])));
-    rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
-  }
-}
 
 // ------------------------------------------------------------ generic (2D/3D)
 __global__ void k_jacobi_zero(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
@@ -1416,68 +1146,36 @@ void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float om
 
 void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active) {
-#ifndef HELM_DOWN3_MARCH
-#define HELM_DOWN3_MARCH 1
-#endif
-  if (HELM_DOWN3_MARCH) {
-    constexpr int TCX = 16, TCY = 8, KZ = 8;
-    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + KZ - 1) / KZ);
-    hipLaunchKernelGGL((k_down_march3<TCX, TCY, KZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                       active);
-    return;
-  }
-  constexpr int TCX = 8, TCY = 4, TCZ = 4;
-  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + TCZ - 1) / TCZ);
-  hipLaunchKernelGGL((k_down_fused3<TCX, TCY, TCZ>), dim3(B * tiles), dim3(TCX * TCY * TCZ), 0, s, B, r, rs, lv,
-                     omega, rc, nc, active);
+  constexpr int TCX = 16, TCY = 8, KZ = 8;
+  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + KZ - 1) / KZ);
+  hipLaunchKernelGGL((k_down_march3<TCX, TCY, KZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                     active);
 }
 
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active) {
-#ifndef HELM_UP3_MARCH
-#define HELM_UP3_MARCH 1
-#endif
-  if (HELM_UP3_MARCH) {
-    constexpr int TX = 32, TY = 16, FZ = 16;
-    const int n = lv.n;
-    const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + FZ - 1) / FZ);
-    hipLaunchKernelGGL((k_up_march3<TX, TY, FZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                       active);
-    return;
-  }
-  constexpr int TX = 16, TY = 8, TZ = 8;
+  constexpr int TX = 32, TY = 16, FZ = 16;
   const int n = lv.n;
-  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ);
-  hipLaunchKernelGGL((k_up_fused3<TX, TY, TZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + FZ - 1) / FZ);
+  hipLaunchKernelGGL((k_up_march3<TX, TY, FZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
                      active);
 }
 
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
                    int nc, VecSet z, VecSet w, const int* active) {
-#ifndef HELM_UPMV_WIDE
-#define HELM_UPMV_WIDE 12
-#endif
-  if (HELM_UPMV_WIDE > 0) {
-    constexpr int TX = 60, TY = HELM_UPMV_WIDE > 0 ? HELM_UPMV_WIDE : 16;
-    const int n = lv.n;
-    const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-    hipLaunchKernelGGL((k_up_mv2w<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
-                       active);
-    return;
-  }
-  constexpr int TX = 64, TY = 16;
+  constexpr int TX = 60, TY = 12;  // 12 rows measured best of 8, 12, 16, 20, 28
   const int n = lv.n;
   const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_mv2<TX, TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
+  hipLaunchKernelGGL((k_up_mv2w<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
                      active);
 }
 
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
                         VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active) {
-  constexpr int TCX = 16, TCY = 16;
-  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
-  hipLaunchKernelGGL((k_step_fused2<TCX, TCY>), dim3(B * tiles), dim3(TCX * TCY), 0, s, B, r, rs, lv, la, omega, ec,
-                     nc, z, w, rc, active);
+  constexpr int TX = 56, TY = 12;
+  const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+  hipLaunchKernelGGL(k_step_col, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w, rc,
+                     active);
 }
 
 int mg_down_variants() { return (int)(sizeof(kDown) / sizeof(kDown[0])); }

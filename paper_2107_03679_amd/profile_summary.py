@@ -35,7 +35,7 @@ HIP_KERNEL = {
     "up_mv_l0": ("k_up_mv2w", "k_up_mv2"), "up_fused_l0": ("k_up_col", "k_up_fused2"),
     "down_fused_l0": ("k_down_col", "k_down_fused2"), "sstep_gram": ("k_sstep_gram",),
     "sstep_matvec": ("k_sstep_matvec",), "x_update": ("k_x_update",), "residual_ff": ("k_residual_ff",),
-    "step_fused_l0": ("k_step_fused2",),
+    "step_fused_l0": ("k_step_col",),
 }
 # sources the kernels are built from (any change voids a traffic record)
 SOURCES = ["paper_2107_03679_amd/csrc/k_multigrid.hip", "paper_2107_03679_amd/csrc/k_krylov.hip",
