@@ -760,7 +760,104 @@ int krylov_max_restart() { return MAXM; }
 int sstep_max_restart() { return SSTEP_MAXM; }
 long long sstep_gram_entries(int m) { return (long long)(m + 1) * (m + 2) / 2; }
 
+namespace {
+// W_{j+1} = A Z_j in 3D, marching in z: a 64 x 8 column over MZ planes, two
+// points per thread.  Each thread keeps its points' values of the planes
+// below, at and above in registers (the next plane's loads in flight while
+// the current one is formed); the in-plane neighbours come from an LDS copy
+// of the plane and a one-point ring.  Each plane of Z_j is read once per
+// column (the flat kernel's z-neighbours, a plane apart, mostly miss the L2).
+constexpr int MX = 64, MY = 8, MZ = 16, MT = 256;
+__global__ __launch_bounds__(MT) void k_matvec_march3(int nrhs, KrylovArgs k, int j, LevelArgs fine) {
+  __shared__ c32 sP[MY + 2][MX + 2];
+  const int n = fine.n;
+  const int tx_n = (n + MX - 1) / MX, ty_n = (n + MY - 1) / MY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + MZ - 1) / MZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (!k.active[b]) return;
+  const int x0 = (id.t % tx_n) * MX, y0 = ((id.t / tx_n) % ty_n) * MY, z0 = (id.t / (tx_n * ty_n)) * MZ;
+  const int z1 = min(n, z0 + MZ);
+  const c32* zv = k.Z + zidx(k, b, j);
+  c32* wv = k.V + vidx(k, b, j + 1);
+  const long long n2 = (long long)n * n;
+  // own points (tx + 32 h, ty), h = 0, 1
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  bool own[2];
+  long long o[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int gx = x0 + tx + 32 * h, gy = y0 + ty;
+    own[h] = gx < n && gy < n;
+    o[h] = own[h] ? (long long)gy * n + gx : 0;
+  }
+  // ring point of this thread (LDS coordinates), if any: 2 (MX + 2) + 2 MY of them
+  int rx = -1, ry = -1;
+  {
+    const int t = threadIdx.x;
+    if (t < MX + 2) rx = t, ry = 0;
+    else if (t < 2 * (MX + 2)) rx = t - (MX + 2), ry = MY + 1;
+    else if (t < 2 * (MX + 2) + MY) rx = 0, ry = t - 2 * (MX + 2) + 1;
+    else if (t < 2 * (MX + 2) + 2 * MY) rx = MX + 1, ry = t - 2 * (MX + 2) - MY + 1;
+  }
+  const int rgx = x0 - 1 + rx, rgy = y0 - 1 + ry;
+  const bool ring = rx >= 0 && rgx >= 0 && rgx < n && rgy >= 0 && rgy < n;
+  const long long ro = ring ? (long long)rgy * n + rgx : 0;
+  auto at = [&](bool ok, int z, long long off) {
+    return ok && z >= 0 && z < n ? zv[z * n2 + off] : make_float2(0.f, 0.f);
+  };
+  c32 zm[2], zc[2], zp[2], kc[2];
+  c32 zr = at(ring, z0, ro);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    zm[h] = at(own[h], z0 - 1, o[h]);
+    zc[h] = at(own[h], z0, o[h]);
+    zp[h] = at(own[h], z0 + 1, o[h]);
+    kc[h] = own[h] ? fine.coef[z0 * n2 + o[h]] : make_float2(0.f, 0.f);
+  }
+  for (int z = z0; z < z1; ++z) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) sP[ty + 1][tx + 1 + 32 * h] = zc[h];
+    if (rx >= 0) sP[ry][rx] = zr;
+    // the next plane's loads
+    c32 zn[2], kn[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      zn[h] = at(own[h], z + 2, o[h]);
+      kn[h] = own[h] && z + 1 < n ? fine.coef[(z + 1) * n2 + o[h]] : make_float2(0.f, 0.f);
+    }
+    const c32 zrn = at(ring, z + 1, ro);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!own[h]) continue;
+      const int lx = tx + 1 + 32 * h, ly = ty + 1;
+      const int ng = ghosts3(x0 + tx + 32 * h, y0 + ty, z, n);
+      const c32 D = make_float2(6.0f - kc[h].x - ng * fine.ghost.x, -kc[h].y - ng * fine.ghost.y);
+      const c32 nb = cadd(cadd(cadd(sP[ly][lx - 1], sP[ly][lx + 1]), cadd(sP[ly - 1][lx], sP[ly + 1][lx])),
+                          cadd(zm[h], zp[h]));
+      wv[z * n2 + o[h]] = csub(cmul(D, zc[h]), nb);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      zm[h] = zc[h];
+      zc[h] = zp[h];
+      zp[h] = zn[h];
+      kc[h] = kn[h];
+    }
+    zr = zrn;
+  }
+}
+}  // namespace
+
 void launch_sstep_matvec(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine) {
+  if (k.dim == 3) {
+    const int n = fine.n;
+    const int tiles = ((n + MX - 1) / MX) * ((n + MY - 1) / MY) * ((n + MZ - 1) / MZ);
+    hipLaunchKernelGGL(k_matvec_march3, dim3(B * tiles), dim3(MT), 0, s, B, k, j, fine);
+    return;
+  }
   hipLaunchKernelGGL(k_sstep_matvec, dim3(B * k.nblk), dim3(NT), 0, s, B, k, j, fine);
 }
 
