@@ -253,7 +253,7 @@ def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the batch of plane waves is the data-parallel "
+        print(json.dumps({"error": "this implementation runs on one GPU; the batch of plane waves is the data-parallel "
                                    "axis and multi-GPU runs are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

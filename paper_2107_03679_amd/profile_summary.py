@@ -46,11 +46,11 @@ PMC_REGEX = ("k_up_mv2|k_up_fused2|k_down_fused2|k_up_col|k_down_col|k_sstep|k_r
 
 def commands(workload: str) -> tuple[str, list[str]]:
     base = (f"python3 $R/bench.py --workload {workload} --steps 1 --warmup 0 --no-cpu-baseline --no-learned "
-            "--tune-cache $R/gpurun_out/tune.jsonl")
-    trace = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof -o run "
+            "--tune-cache $OUT/tune.jsonl")
+    trace = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -f csv -d $OUT/prof -o run "
              f"-- {base}")
     pmc = [(f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {ctr} --kernel-include-regex \"{PMC_REGEX}\" -f csv "
-            f"-d $R/gpurun_out/pmc_{ctr} -o run -- {base} --no-profile --no-graph") for ctr in ("FETCH_SIZE", "WRITE_SIZE")]
+            f"-d $OUT/pmc_{ctr} -o run -- {base} --no-profile --no-graph") for ctr in ("FETCH_SIZE", "WRITE_SIZE")]
     return trace, pmc
 
 
@@ -106,8 +106,9 @@ def main(argv=None) -> None:
     dom = max(cands, key=lambda k: (k[1], sum(trace[k])))
     trace_cmd, pmc_cmds = commands(args.workload)
     L = [f"# Kernel profile: {args.workload}\n",
-         "Commands, run from the repository root (`R`) on an MI355X; this file and the traffic record were "
-         "written by `python3 -m paper_2107_03679_amd.profile_summary gpurun_out` from the CSV files they leave.\n",
+         "Commands, run on an MI355X (`R` = the repository root, `OUT` = an output folder, the same for all "
+         "three runs, so that the tuned launch shapes of the first are reused); this file and the traffic record "
+         "were written by `python3 -m paper_2107_03679_amd.profile_summary $OUT` from the CSV files they leave.\n",
          f"Kernel trace:\n\n```\n{trace_cmd}\n```\n",
          "HBM counters (one run per counter, eager launches):\n\n```\n" + "\n".join(pmc_cmds) + "\n```\n",
          "The traced run is one graph-replayed step plus the profiled (eager) step of bench.py.  Durations per "

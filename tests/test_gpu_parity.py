@@ -3,7 +3,7 @@
 All calls go through the C ABI (libhelm.so via the ctypes binding).  Sizes
 span several LDS tiles with ragged tails (the fused kernels use 64 x 16 fine
 tiles); tolerances follow from complex64 arithmetic (unit roundoff 6e-8)
-and, for solves, from the 1e-6 residual target (spec field parity 1e-5).
+and, for solves, from the 1e-6 residual target (the field-parity target 1e-5).
 """
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Robustness experiments of Sec. VI-A on the GPU path, with this build's own numbers.
+"""Robustness experiments of Sec. VI-A on the GPU path, with this implementation's numbers.
 
 * The disk of Fig. 4 (eta 2.2 in air, radius 1.25 wavelengths, 256^2 samples
   at 80 points per wavelength, 32-point layer with beta = 0.15): the GPU
