@@ -186,9 +186,8 @@ __device__ __forceinline__ double zabs(double2 a) { return hypot(a.x, a.y); }
 
 // Back-substitution y = H(0:kk, 0:kk)^-1 g(0:kk) for right-hand side b (FP64, one thread;
 // yd: kk FP64 slots in LDS, where a per-thread array indexed at run time would spill).
-__device__ void back_substitute(const KrylovArgs& k, int b, int kk, double2* yd) {
-  const double2* H = k.H + (long long)b * (k.m + 1) * k.m;
-  const double2* g = k.g + (long long)b * (k.m + 1);
+// y of the kk-column triangular system H y = g (H row stride m), written to k.y
+__device__ void back_substitute(const KrylovArgs& k, int b, int kk, double2* yd, const double2* H, const double2* g) {
   for (int i = kk - 1; i >= 0; --i) {
     double2 s = g[i];
     for (int l = i + 1; l < kk; ++l) {
@@ -263,7 +262,7 @@ __global__ __launch_bounds__(HELM_WAVE) void k_givens(KrylovArgs k, int j) {
   k.vs[b * (m + 1) + j + 1] = hj1 > 0.0 ? (float)(1.0 / hj1) : 0.0f;
   const bool stop = est <= k.tol[b] || hj1 == 0.0 || it >= k.max_iters;
   if (stop) k.active[b] = 0;
-  if (stop || j == m - 1) back_substitute(k, b, j + 1, yd);
+  if (stop || j == m - 1) back_substitute(k, b, j + 1, yd, H, g);
 }
 
 // x += sum_{i < jcount} y_i Z_i, accumulated into the float-float pair (x_hi, x_lo)
@@ -687,10 +686,12 @@ __global__ __launch_bounds__(NT) void k_sstep_solve(KrylovArgs k, const double2*
     k.active[b] = 0;
     return;
   }
-  double2* H = k.H + (long long)b * (m + 1) * m;
-  double* cs = k.cs + (long long)b * m;
-  double2* sn = k.sn + (long long)b * m;
-  double2* g = k.g + (long long)b * (m + 1);
+  // the rotated Hessenberg, rotations and right-hand side stay in LDS (a single
+  // thread's chain of dependent global accesses would dominate the kernel)
+  __shared__ double2 H[(M + 1) * M];
+  __shared__ double cs[M];
+  __shared__ double2 sn[M];
+  __shared__ double2 g[M + 1];
   const double rn = 1.0 / (double)k.vs[b * (m + 1)];
   for (int i = 0; i <= m; ++i) g[i] = make_double2(0.0, 0.0);
   g[0] = make_double2(rn * R[0][0].x, 0.0);
@@ -738,7 +739,7 @@ __global__ __launch_bounds__(NT) void k_sstep_solve(KrylovArgs k, const double2*
   }
   k.jcount[b] = kstar;
   k.active[b] = 0;
-  back_substitute(k, b, kstar, yd);
+  back_substitute(k, b, kstar, yd, H, g);
 }
 
 __global__ void k_status_init(KrylovArgs k, int B) {
