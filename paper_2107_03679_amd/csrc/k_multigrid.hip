@@ -660,93 +660,92 @@ __global__ __launch_bounds__(256) void k_step_col(int nrhs, VecSet r, ScaleSet r
 }
 
 // ------------------------------------------------------------ fused 3D legs
-// Down-leg marching in z: a TCX x TCY column of coarse points, coarse planes
-// [kz0, kz0 + KZ).  Per fine plane f (bottom to top): v1(f) = W r on the
-// plane's (2 TCX + 3) x (2 TCY + 3) region -> one of three LDS planes; then
-// s(f - 1) on the region's interior from v1(f - 2 .. f) -> LDS; then the
-// plane's in-plane full weighting is added to the coarse plane(s) it belongs
-// to (weight 1/2 for f - 1 = 2K, 1/4 to K - 1 and K for f - 1 = 2K - 1),
-// accumulated in registers; a coarse plane is written once complete.
-template <int TCX, int TCY, int KZ>
-__global__ __launch_bounds__(256) void k_down_march3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                     VecSet rc, int nc, const int* active) {
-  constexpr int NT = 256;
-  constexpr int RX = 2 * TCX + 3, RY = 2 * TCY + 3, SX = RX - 2, SY = RY - 2;
-  constexpr int NR = RX * RY, IT = (NR + NT - 1) / NT;
-  static_assert(TCX * TCY <= NT, "one coarse point per thread");
-  __shared__ c32 sV[3][RY][RX];
-  __shared__ c32 sS[SY][SX];
+// The down-leg marching in z with a fixed thread map: 30 x 8 coarse points,
+// fine region 63 x 19 (2 c0 - 2 origin); each lane owns one region column and
+// every fourth row, keeping v1 of the planes f - 2 .. f and r of the plane it
+// forms s on in registers (the next plane's loads in flight); only in-plane
+// neighbours go through LDS.  Per fine plane f (bottom to top): v1(f) = W r;
+// then s(f - 1) = r - K v1 on the region's interior; then the plane's in-plane
+// full weighting is added to the coarse plane(s) it belongs to (weight 1/2 for
+// f - 1 = 2K, 1/4 to K - 1 and K for f - 1 = 2K - 1), accumulated in
+// registers; a coarse plane is written once complete.
+constexpr int DCX = 30, DCY = 8, DKZ = 8, DRX = 2 * DCX + 3, DRY = 2 * DCY + 3, DIV = (DRY + 3) / 4;
+__global__ __launch_bounds__(256) void k_down_march3c(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                      VecSet rc, int nc, const int* active) {
+  __shared__ c32 sV[2][4 * DIV][64];
+  __shared__ c32 sS[4 * DIV][64];
   const int n = lv.n;
-  const int tx_n = (nc + TCX - 1) / TCX, ty_n = (nc + TCY - 1) / TCY;
-  const unsigned tiles = (unsigned)(tx_n * ty_n * ((nc + KZ - 1) / KZ));
+  const int tx_n = (nc + DCX - 1) / DCX, ty_n = (nc + DCY - 1) / DCY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((nc + DKZ - 1) / DKZ));
   const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
   const int b = id.b;
   if (active && !active[b]) return;
-  const int cx0 = (id.t % tx_n) * TCX, cy0 = ((id.t / tx_n) % ty_n) * TCY, kz0 = (id.t / (tx_n * ty_n)) * KZ;
-  const int kz1 = min(nc, kz0 + KZ);
+  const int cx0 = (id.t % tx_n) * DCX, cy0 = ((id.t / tx_n) % ty_n) * DCY, kz0 = (id.t / (tx_n * ty_n)) * DKZ;
+  const int kz1 = min(nc, kz0 + DKZ);
   const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
   const long long n2 = (long long)n * n;
-  // this thread's region points: in-plane offset and whether it lies in the grid
-  long long off[IT];
-  bool inxy[IT];
+  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int gx = fx0 + lx;
+  const bool inx = lx < DRX && gx >= 0 && gx < n;
+  bool in[DIV];
+  long long off[DIV];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 + idx % RX, gy = fy0 + idx / RX;
-    inxy[it] = idx < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
-    off[it] = inxy[it] ? (long long)gy * n + gx : 0;
+  for (int it = 0; it < DIV; ++it) {
+    const int ly = r0 + 4 * it, gy = fy0 + ly;
+    in[it] = inx && ly < DRY && gy >= 0 && gy < n;
+    off[it] = in[it] ? (long long)gy * n + gx : 0;
   }
-  const int f0 = 2 * kz0 - 2, f1 = 2 * kz1;  // fine planes whose v1 is needed
-  c32 rn[IT], wn[IT], rp[IT];
+  c32 rn[DIV], wn[DIV];
   auto fetch = [&](int f) {
     const bool inz = f >= 0 && f < n;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const bool ok = inz && inxy[it];
+    for (int it = 0; it < DIV; ++it) {
+      const bool ok = inz && in[it];
       const long long p = ok ? f * n2 + off[it] : 0;
       rn[it] = ok ? rb[p] : make_float2(0.f, 0.f);
       wn[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
     }
   };
+  const int f0 = 2 * kz0 - 2, f1 = 2 * kz1;  // fine planes whose v1 is needed
   fetch(f0);
-  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
-  const bool coarse = threadIdx.x < TCX * TCY && cx0 + tx < nc && cy0 + ty < nc;
+  const int tx = threadIdx.x % DCX, ty = threadIdx.x / DCX;
+  const bool coarse = threadIdx.x < DCX * DCY && cx0 + tx < nc && cy0 + ty < nc;
   c32 acc = make_float2(0.f, 0.f);
-  for (int f = f0; f <= f1; ++f) {
-    c32 rf[IT];
-    const int slot = (f - f0) % 3;
+  c32 vm[DIV], vc[DIV], rp[DIV];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
+  for (int it = 0; it < DIV; ++it) vm[it] = vc[it] = rp[it] = make_float2(0.f, 0.f);
+  for (int f = f0; f <= f1; ++f) {
+    c32 rf[DIV], vf[DIV];
+#pragma unroll
+    for (int it = 0; it < DIV; ++it) {
       rf[it] = cscale(rn[it], sc);
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NR) sV[slot][idx / RX][idx % RX] = cmul(rf[it], wn[it]);
+      vf[it] = cmul(rf[it], wn[it]);
+      sV[f & 1][r0 + 4 * it][lx] = vf[it];
     }
     if (f < f1) fetch(f + 1);
     __syncthreads();
     const int g = f - 1;  // the plane whose s is formed now
     if (g >= f0 + 1) {
-      const int sm = (g - 1 - f0) % 3, s0 = (g - f0) % 3;
       const bool ing = g >= 0 && g < n;
+      const c32(*P)[64] = sV[g & 1];
 #pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
-        const int lx = idx % RX, ly = idx / RX;
-        if (idx >= NR || lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1) continue;
+      for (int it = 0; it < DIV; ++it) {
+        const int ly = r0 + 4 * it;
+        if (lx < 1 || lx > DRX - 2 || ly < 1 || ly > DRY - 2) continue;
         c32 sv = make_float2(0.f, 0.f);
-        if (ing && inxy[it]) {
-          const c32 nb = cadd(cadd(cadd(sV[s0][ly][lx - 1], sV[s0][ly][lx + 1]),
-                                   cadd(sV[s0][ly - 1][lx], sV[s0][ly + 1][lx])),
-                              cadd(sV[sm][ly][lx], sV[slot][ly][lx]));
+        if (ing && in[it]) {
+          const c32 nb = cadd(cadd(cadd(P[ly][lx - 1], P[ly][lx + 1]), cadd(P[ly - 1][lx], P[ly + 1][lx])),
+                              cadd(vm[it], vf[it]));
           sv = cadd(cscale(rp[it], 1.0f - omega), nb);
         }
-        sS[ly - 1][lx - 1] = sv;
+        sS[ly][lx] = sv;
       }
     }
     __syncthreads();
     if (g >= f0 + 1 && coarse) {
-      const int sx = 2 * tx + 1, sy = 2 * ty + 1;
+      const int sx = 2 * tx + 2, sy = 2 * ty + 2;
       c32 t = cscale(sS[sy][sx], 0.25f);
       t = cadd(t, cscale(cadd(cadd(sS[sy][sx - 1], sS[sy][sx + 1]), cadd(sS[sy - 1][sx], sS[sy + 1][sx])), 0.125f));
       t = cadd(t, cscale(cadd(cadd(sS[sy - 1][sx - 1], sS[sy - 1][sx + 1]), cadd(sS[sy + 1][sx - 1], sS[sy + 1][sx + 1])),
@@ -763,62 +762,80 @@ __global__ __launch_bounds__(256) void k_down_march3(int nrhs, VecSet r, ScaleSe
       }
     }
 #pragma unroll
-    for (int it = 0; it < IT; ++it) rp[it] = rf[it];
+    for (int it = 0; it < DIV; ++it) {
+      vm[it] = vc[it];
+      vc[it] = vf[it];
+      rp[it] = rf[it];
+    }
   }
 }
 
-// Up-leg marching in z: a TX x TY column of fine points, output planes
-// [fz0, fz0 + FZ).  Per fine plane f: v2(f) = W r + P e on the column and a
-// one-point in-plane ring -> one of three LDS planes (the coarse planes that P
-// reads are kept two at a time in LDS); then z(f - 1) on the column from
-// v2(f - 2 .. f).
-template <int TX, int TY, int FZ>
-__global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                   VecSet ec, int nc, VecSet z, const int* active) {
-  constexpr int NT = 256, HX = TX + 2, HY = TY + 2, NH = HX * HY, IT = (NH + NT - 1) / NT;
-  constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, NCP = CX * CY, ITC = (NCP + NT - 1) / NT;
+// The up-leg marching in z with a fixed thread map: a 64 x 8 column, two own
+// points per thread (x and x + 32) and a one-point in-plane ring (148 threads
+// take one ring point each).  Each thread keeps its own points' v2 of the
+// planes f - 2 .. f and r, W of the plane it smooths in registers, with the
+// next plane's loads in flight; only the in-plane neighbours go through LDS
+// (two planes).  Per fine plane f: v2(f) = W r + P e (the coarse planes that P
+// reads are kept two at a time in LDS), then z(f - 1) from v2(f - 2 .. f).
+constexpr int UX = 64, UY = 8, UZ = 16, URING = 2 * (UX + 2) + 2 * UY;
+__global__ __launch_bounds__(256) void k_up_march3c(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+                                                    VecSet ec, int nc, VecSet z, const int* active) {
+  constexpr int CX = UX / 2 + 2, CY = UY / 2 + 2, NCP = CX * CY, ITC = (NCP + 255) / 256;
   __shared__ c32 sE[2][CY][CX];
-  __shared__ c32 sV[3][HY][HX];
+  __shared__ c32 sV[2][UY + 2][UX + 2];
   const int n = lv.n;
-  const int tx_n = (n + TX - 1) / TX, ty_n = (n + TY - 1) / TY;
-  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + FZ - 1) / FZ));
+  const int tx_n = (n + UX - 1) / UX, ty_n = (n + UY - 1) / UY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + UZ - 1) / UZ));
   const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
   const int b = id.b;
   if (active && !active[b]) return;
-  const int fx0 = (id.t % tx_n) * TX, fy0 = ((id.t / tx_n) % ty_n) * TY, fz0 = (id.t / (tx_n * ty_n)) * FZ;
-  const int fz1 = min(n, fz0 + FZ);
+  const int fx0 = (id.t % tx_n) * UX, fy0 = ((id.t / tx_n) % ty_n) * UY, fz0 = (id.t / (tx_n * ty_n)) * UZ;
+  const int fz1 = min(n, fz0 + UZ);
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
-  long long off[IT];
-  bool inxy[IT];
+  // points of this thread: q = 0, 1 own, q = 2 the ring point (if any); LDS coordinates (lx, ly)
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  int lxq[3], lyq[3];
+  lxq[0] = tx + 1, lyq[0] = ty + 1, lxq[1] = tx + 33, lyq[1] = ty + 1;
+  {
+    const int t = threadIdx.x;
+    int rx = -1, ry = -1;
+    if (t < UX + 2) rx = t, ry = 0;
+    else if (t < 2 * (UX + 2)) rx = t - (UX + 2), ry = UY + 1;
+    else if (t < 2 * (UX + 2) + UY) rx = 0, ry = t - 2 * (UX + 2) + 1;
+    else if (t < URING) rx = UX + 1, ry = t - 2 * (UX + 2) - UY + 1;
+    lxq[2] = rx, lyq[2] = ry;
+  }
+  bool in[3];
+  long long off[3];
+  int gxq[3], gyq[3];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
-    inxy[it] = idx < NH && gx >= 0 && gx < n && gy >= 0 && gy < n;
-    off[it] = inxy[it] ? (long long)gy * n + gx : 0;
+  for (int q = 0; q < 3; ++q) {
+    gxq[q] = fx0 - 1 + lxq[q], gyq[q] = fy0 - 1 + lyq[q];
+    in[q] = lxq[q] >= 0 && gxq[q] >= 0 && gxq[q] < n && gyq[q] >= 0 && gyq[q] < n;
+    off[q] = in[q] ? (long long)gyq[q] * n + gxq[q] : 0;
   }
   long long coff[ITC];
   bool cin[ITC];
 #pragma unroll
   for (int it = 0; it < ITC; ++it) {
-    const int idx = threadIdx.x + it * NT;
+    const int idx = threadIdx.x + it * 256;
     const int I = cxs + idx % CX, J = cys + idx / CX;
     cin[it] = idx < NCP && I >= 0 && I < nc && J >= 0 && J < nc;
     coff[it] = cin[it] ? (long long)J * nc + I : 0;
   }
-  c32 rn[IT], wn[IT], rp[IT], wp[IT], cn[ITC];
+  c32 rn[3], wn[3], cn[ITC];
   auto fetch = [&](int f) {
     const bool inz = f >= 0 && f < n;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const bool ok = inz && inxy[it];
-      const long long p = ok ? f * n2 + off[it] : 0;
-      rn[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-      wn[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
+    for (int q = 0; q < 3; ++q) {
+      const bool ok = inz && in[q];
+      const long long p = ok ? f * n2 + off[q] : 0;
+      rn[q] = ok ? rb[p] : make_float2(0.f, 0.f);
+      wn[q] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
     }
   };
   auto fetch_coarse = [&](int K) {
@@ -832,7 +849,7 @@ __global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet 
   auto store_coarse = [&](int K) {
 #pragma unroll
     for (int it = 0; it < ITC; ++it) {
-      const int idx = threadIdx.x + it * NT;
+      const int idx = threadIdx.x + it * 256;
       if (idx < NCP) sE[K & 1][idx / CX][idx % CX] = cn[it];
     }
   };
@@ -843,36 +860,35 @@ __global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet 
   fetch_coarse(khi);
   store_coarse(khi);
   fetch(fa);
+  __syncthreads();
+  c32 vm[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)}, vc[2] = {vm[0], vm[1]};
+  c32 rc[2] = {vm[0], vm[1]}, wc[2] = {vm[0], vm[1]};  // r (scaled) and W of plane f - 1
+  c32* zb = z.p + (long long)b * z.stride;
   for (int f = fa; f <= fb; ++f) {
-    c32 rf[IT], wf[IT];
+    c32 rf[3], wf[3];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      rf[it] = cscale(rn[it], sc);
-      wf[it] = wn[it];
+    for (int q = 0; q < 3; ++q) {
+      rf[q] = cscale(rn[q], sc);
+      wf[q] = wn[q];
     }
     const int knext = (f + 2) >> 1;  // the higher coarse plane that v2(f + 1) reads
     if (f < fb) {
       fetch(f + 1);
       if (knext > khi) fetch_coarse(knext);
     }
-    __syncthreads();
-    {
-      const int slot = (f - fa) % 3;
-      const bool inz = f >= 0 && f < n;
-      const int klo = f >> 1;
+    // v2(f) = W r + P e at the own points and the ring point
+    c32 vf[3];
+    const bool inz = f >= 0 && f < n;
+    const int klo = f >> 1;
 #pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
-        if (idx >= NH) continue;
-        const int gx = fx0 - 1 + idx % HX, gy = fy0 - 1 + idx / HX;
-        c32 v2 = make_float2(0.f, 0.f);
-        if (inz && inxy[it]) {
-          c32 pe = prolong_lds<CX>(sE[klo & 1], gx, gy, cxs, cys);
-          if (f & 1) pe = cscale(cadd(pe, prolong_lds<CX>(sE[(klo + 1) & 1], gx, gy, cxs, cys)), 0.5f);
-          v2 = cadd(cmul(rf[it], wf[it]), pe);
-        }
-        sV[slot][idx / HX][idx % HX] = v2;
+    for (int q = 0; q < 3; ++q) {
+      vf[q] = make_float2(0.f, 0.f);
+      if (inz && in[q]) {
+        c32 pe = prolong_lds<CX>(sE[klo & 1], gxq[q], gyq[q], cxs, cys);
+        if (f & 1) pe = cscale(cadd(pe, prolong_lds<CX>(sE[(klo + 1) & 1], gxq[q], gyq[q], cxs, cys)), 0.5f);
+        vf[q] = cadd(cmul(rf[q], wf[q]), pe);
       }
+      if (lxq[q] >= 0) sV[f & 1][lyq[q]][lxq[q]] = vf[q];
     }
     __syncthreads();
     if (f < fb && knext > khi) {  // the coarse plane that replaces one no longer read
@@ -881,26 +897,26 @@ __global__ __launch_bounds__(256) void k_up_march3(int nrhs, VecSet r, ScaleSet 
     }
     const int g = f - 1;  // output plane
     if (g >= fz0) {
-      const int sm = (g - 1 - fa) % 3, s0 = (g - fa) % 3, sp = (f - fa) % 3;
-      c32* zb = z.p + (long long)b * z.stride + g * n2;
 #pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
-        const int lx = idx % HX, ly = idx / HX;
-        if (idx >= NH || lx == 0 || lx == HX - 1 || ly == 0 || ly == HY - 1 || !inxy[it]) continue;
-        const c32 nb = cadd(cadd(cadd(sV[s0][ly][lx - 1], sV[s0][ly][lx + 1]), cadd(sV[s0][ly - 1][lx], sV[s0][ly + 1][lx])),
-                            cadd(sV[sm][ly][lx], sV[sp][ly][lx]));
-        zb[off[it]] = cadd(cscale(sV[s0][ly][lx], 1.0f - omega), cmul(wp[it], cadd(rp[it], nb)));
+      for (int q = 0; q < 2; ++q) {
+        if (!in[q]) continue;
+        const int lx = lxq[q], ly = lyq[q];
+        const c32(*P)[UX + 2] = sV[g & 1];
+        const c32 nb = cadd(cadd(cadd(P[ly][lx - 1], P[ly][lx + 1]), cadd(P[ly - 1][lx], P[ly + 1][lx])),
+                            cadd(vm[q], vf[q]));
+        zb[g * n2 + off[q]] = cadd(cscale(vc[q], 1.0f - omega), cmul(wc[q], cadd(rc[q], nb)));
       }
     }
+    __syncthreads();
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      rp[it] = rf[it];
-      wp[it] = wf[it];
+    for (int q = 0; q < 2; ++q) {
+      vm[q] = vc[q];
+      vc[q] = vf[q];
+      rc[q] = rf[q];
+      wc[q] = wf[q];
     }
   }
 }
-
 
 // ------------------------------------------------------------ generic (2D/3D)
 __global__ void k_jacobi_zero(int dim, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,
@@ -1146,19 +1162,15 @@ void up_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float om
 
 void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active) {
-  constexpr int TCX = 16, TCY = 8, KZ = 8;
-  const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY) * ((nc + KZ - 1) / KZ);
-  hipLaunchKernelGGL((k_down_march3<TCX, TCY, KZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                     active);
+  const int tiles = ((nc + DCX - 1) / DCX) * ((nc + DCY - 1) / DCY) * ((nc + DKZ - 1) / DKZ);
+  hipLaunchKernelGGL(k_down_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc, active);
 }
 
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
                       VecSet z, const int* active) {
-  constexpr int TX = 32, TY = 16, FZ = 16;
   const int n = lv.n;
-  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + FZ - 1) / FZ);
-  hipLaunchKernelGGL((k_up_march3<TX, TY, FZ>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                     active);
+  const int tiles = ((n + UX - 1) / UX) * ((n + UY - 1) / UY) * ((n + UZ - 1) / UZ);
+  hipLaunchKernelGGL(k_up_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active);
 }
 
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
