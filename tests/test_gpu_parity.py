@@ -331,3 +331,32 @@ def test_options_restart_levels_and_no_graph():
         assert st.converged, opts
         assert rel(to_np(x)[0], ex.solve(to_np(rhs)[0])) < 1e-5, opts
         ctx.close()
+
+
+def test_graph_replays_match_eager_launches():
+    """One hipGraph per restart cycle, replayed every cycle: two solves in a row with the
+    graph (the second replays the first's capture) against the same solves launched eagerly,
+    with eager work (right-hand sides, a residual) and synchronisations in between.  The
+    kernels are the same, so the results must agree bit for bit after every replay."""
+    n, w, levels = CASES["ragged"]
+    nmap = medium(n, seed=29)
+    print("\n[graph replays vs eager]", flush=True)
+    dirs = synth.directions_2d(3)
+    out = {}
+    for graph in (1, 0):
+        ctx = gpu_context(nmap, w=w, levels=levels, max_batch=3, cycle=3, use_graph=graph)
+        res = []
+        for rep in range(2):
+            rhs = ctx.plane_wave_rhs(dirs if rep == 0 else dirs[::-1].copy())
+            x, st = ctx.solve(rhs)
+            assert st.converged, (graph, rep, st)
+            import torch
+
+            ctx.residual(rhs, x)  # eager work between the solves
+            torch.cuda.synchronize()
+            res.append((to_np(x), st.iters.copy()))
+        out[graph] = res
+        ctx.close()
+    for rep in range(2):
+        assert np.array_equal(out[1][rep][0], out[0][rep][0]), rep
+        assert np.array_equal(out[1][rep][1], out[0][rep][1]), rep
