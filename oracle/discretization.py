@@ -49,7 +49,7 @@ class Problem:
 
     n_map      interior refractive index, shape (n,)*d, on Omega
     k0h        free-space wavenumber times the fine mesh size, k0*h
-    h          fine mesh size (P:518 uses h = 1/(n_e - 1) of the unit square)
+    h          fine mesh size (Sec. IV-A normalises Omega_e to the unit square: h = 1/(n_e - 1))
     w          low-side absorbing-layer width in cells
     beta       absorbing-layer strength (Sec. IV-A)
     levels     number of multigrid levels

@@ -23,6 +23,9 @@ def jacobi_max_amplification(kh: float, omega: float) -> float:
     return 1.0 - omega + 4.0 * omega / (4.0 - kh * kh)
 
 
-def cgc_ratio(theta1, theta2, kh: complex):
-    """a^h(theta) / a^{2h}(2 theta): the coarse-grid-correction factor is 1 minus this ratio."""
-    return symbol_a(theta1, theta2, kh, 1.0) / symbol_a(2 * theta1, 2 * theta2, 2 * kh, 2.0)
+def cgc_ratio(theta1, theta2, kh: complex, kappa: complex = 1.0):
+    """a^h(theta) / a^{2h}(2 theta) of the operator -Lap - kappa k^2 (kappa = 1: A itself; a
+    complex kappa: the shifted operator of Sec. IV-B); the coarse-grid-correction factor is
+    1 minus this ratio."""
+    kh_eff = np.sqrt(complex(kappa)) * kh
+    return symbol_a(theta1, theta2, kh_eff, 1.0) / symbol_a(2 * theta1, 2 * theta2, 2 * kh_eff, 2.0)

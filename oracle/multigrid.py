@@ -1,9 +1,9 @@
 """Multigrid preconditioner for the shifted operator K_kappa (Sec. III, Sec. IV-B/C).
 
 * damped Jacobi, eq. (dampedJ), D = diag(K) including the ghost terms (A25)
-* full-weighting restriction R as printed in Sec. IV-C, neighbours outside
-  Omega_e counted as 0 (reading A6 of "the value of the points at the boundary
-  is set to 0")
+* full-weighting restriction R as printed in Sec. IV-C; Sec. IV-C zeroes the
+  values beyond the boundary, read here as fine neighbours outside Omega_e
+  counting as 0 (zero padding, reading A6)
 * prolongation P as printed in Sec. IV-C (the printed weights equal 2^d R^T;
   the text's "adjoint of R" is read as that printed formula, reading A7)
 * coarse operators by re-discretisation with mesh size 2h; the coefficient

@@ -160,3 +160,122 @@ def test_second_order_manufactured_solution():
     r1, r2_ = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.3 < r2_ < 4.7, errs
     assert r1 > 3.0, errs
+
+
+# ---- the absorbing-layer profile (Sec. IV-A, readings A3/A4), pinned by values worked out by hand ----
+#
+# Grid used below: n = 12 interior points, w = 4 layer cells, 2 levels, so n_e = 21 (the smallest odd
+# n_e >= 20 with n_e - 1 even), Omega = indices [4, 16) per axis, high-side layer indices 16..20
+# (5 cells), and the unit-square normalisation gives 1/(n_e - 1) = 1/20.  With d the distance in cells
+# from a point to its projection on Omega:
+#   profile 0: gamma = beta (d/20)^2 / (4/20) = beta d^2 / 80
+#   profile 1: gamma = beta (d/4)^2 = beta d^2 / 16
+# beta = 0.15.  Points are (y, x) index pairs; (y, x) = (8, 0) sits 4 cells left of Omega (d^2 = 16),
+# (8, 20) 5 cells right of it (d^2 = 25), (0, 0) is a layer corner (d^2 = 4^2 + 4^2 = 32), (20, 20)
+# the far corner (d^2 = 5^2 + 5^2 = 50), (15, 4) lies on the edge of Omega (d = 0).
+ALPHA_PINS_FINE = {
+    0: {(8, 0): 0.15 * 16 / 80, (8, 20): 0.15 * 25 / 80, (0, 0): 0.15 * 32 / 80, (20, 20): 0.15 * 50 / 80,
+        (15, 4): 0.0, (2, 9): 0.15 * 4 / 80},
+    1: {(8, 0): 0.15 * 16 / 16, (8, 20): 0.15 * 25 / 16, (0, 0): 0.15 * 32 / 16, (20, 20): 0.15 * 50 / 16,
+        (15, 4): 0.0, (2, 9): 0.15 * 4 / 16},
+}
+# Level 1 (stride 2, 11 points per axis): coarse (y, x) sits at fine (2y, 2x); coarse (4, 1) is fine
+# (8, 2) (d^2 = 4), coarse (10, 10) is fine (20, 20) (d^2 = 50), coarse (0, 5) is fine (0, 10) (d^2 = 16).
+ALPHA_PINS_COARSE = {
+    0: {(4, 1): 0.15 * 4 / 80, (10, 10): 0.15 * 50 / 80, (0, 5): 0.15 * 16 / 80},
+    1: {(4, 1): 0.15 * 4 / 16, (10, 10): 0.15 * 50 / 16, (0, 5): 0.15 * 16 / 16},
+}
+
+
+def _alpha_pin_failures(make_problem):
+    """Every (profile, sign, point) where alpha_at disagrees with the hand-worked value."""
+    bad = []
+    for profile in (0, 1):
+        for sign in (+1, -1):
+            prob = make_problem(profile, sign)
+            assert prob.n_e == 21
+            for pins, stride in ((ALPHA_PINS_FINE, 1), (ALPHA_PINS_COARSE, 2)):
+                for (y, x), gamma in pins[profile].items():
+                    got = complex(prob.alpha_at([np.array(y), np.array(x)], stride=stride))
+                    if abs(got - (1.0 + 1j * sign * gamma)) > 1e-14:
+                        bad.append((profile, sign, stride, (y, x), got, gamma))
+    return bad
+
+
+def _pin_problem(profile, sign, cls=Problem):
+    return cls(np.full((12, 12), 1.4), k0h=KBH / 1.333, w=4, levels=2, beta=0.15, abl_sign=sign,
+               abl_profile=profile)
+
+
+def test_layer_profile_matches_hand_worked_values():
+    assert _alpha_pin_failures(_pin_problem) == []
+
+
+def _planted(mistake):
+    """A Problem whose layer profile carries one planted mistake (for the test below only)."""
+
+    class Planted(Problem):
+        def alpha_at(self, idx_axes, stride=1):
+            lo, hi = self.w, self.w + self.n - 1
+            if mistake == "high side as wide as the low side":
+                hi = self.n_e - 1 - self.w
+            step = 1 if mistake == "coarse indices not scaled" else stride
+            d2 = 0.0
+            for ia in idx_axes:
+                x = np.asarray(ia, dtype=np.float64) * step
+                d2 = d2 + np.maximum(0.0, np.maximum(lo - x, x - hi)) ** 2
+            unit = 1.0 / (self.n_e - 1)
+            if mistake == "distance not squared":
+                d2 = np.sqrt(d2)
+            if mistake == "layer length in cells":
+                g = self.beta * d2 * unit * unit / self.w
+            elif self.abl_profile == 1:
+                g = self.beta * d2 / self.w ** 2
+            else:
+                g = self.beta * d2 * unit / self.w
+            sign = -self.abl_sign if mistake == "sign" else self.abl_sign
+            return 1.0 + 1j * sign * g
+
+    return Planted
+
+
+PLANTED = ("distance not squared", "layer length in cells", "coarse indices not scaled", "sign",
+           "high side as wide as the low side")
+
+
+def test_layer_profile_pins_catch_plausible_mistakes():
+    # the same pins fail for each planted mistake, and pass for the planted class without one
+    assert _alpha_pin_failures(lambda p, s: _pin_problem(p, s, _planted("none"))) == []
+    for mistake in PLANTED:
+        assert _alpha_pin_failures(lambda p, s: _pin_problem(p, s, _planted(mistake))), mistake
+
+
+def test_coefficient_in_the_layer_is_background_times_alpha():
+    # c = (k0 h)^2 n_b^2 (1 + j gamma) in the layer, (k0 h)^2 n^2 on Omega (Sec. IV-A)
+    for profile in (0, 1):
+        prob = _pin_problem(profile, +1)
+        c = prob.coefficient()
+        k0h2 = (KBH / 1.333) ** 2
+        for (y, x), gamma in ALPHA_PINS_FINE[profile].items():
+            inside = 4 <= y < 16 and 4 <= x < 16
+            nn = 1.4 if inside else 1.333
+            assert c[y, x] == pytest.approx(k0h2 * nn * nn * (1 + 1j * gamma), rel=1e-14, abs=1e-16)
+
+
+def test_cgc_ratio_positive_with_the_shift():
+    # Sec. IV-B: with kappa = 1 the ratio a^h(theta) / a^2h(2 theta) changes sign for smooth modes near
+    # the wavenumber (above); with the dissipative shift kappa = 1 + 0.5j both symbols share the
+    # imaginary part -0.5 (kh)^2 and the real part of the ratio stays positive everywhere
+    th = np.linspace(-np.pi / 2, np.pi / 2, 161)
+    t1, t2 = np.meshgrid(th, th)
+    ratio = lfa.cgc_ratio(t1, t2, KBH, kappa=1 + 0.5j)
+    assert np.all(np.real(ratio) > 0)
+    # the printed operator (kappa = 1) seen through the same function keeps its negative ratios
+    assert np.any(np.real(lfa.cgc_ratio(t1, t2, KBH, kappa=1.0)) < 0)
+    # closed form at the mode theta = (kh, 0), where the fine symbol of A vanishes to leading order:
+    # a^h = 2 - 2 cos(kh) - kappa (kh)^2, a^2h = (2 - 2 cos(2 kh) - 4 kappa (kh)^2) / 4
+    kh = KBH
+    for kappa in (1.0, 1 + 0.5j):
+        a1 = 2 - 2 * np.cos(kh) - kappa * kh * kh
+        a2 = (2 - 2 * np.cos(2 * kh) - 4 * kappa * kh * kh) / 4
+        assert lfa.cgc_ratio(kh, 0.0, KBH, kappa=kappa) == pytest.approx(a1 / a2, rel=1e-12)

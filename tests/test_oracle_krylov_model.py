@@ -191,3 +191,23 @@ def test_gradient_matches_central_differences():
         lm = model.loss_only(Problem(n_eval - e, k0h=KBH / n_b, w=4, levels=1, beta=0.0), dirs, data, **kw)
         fd = (lp - lm) / (2 * delta)
         assert grad[i, j] == pytest.approx(fd, rel=1e-5, abs=1e-7 * np.abs(grad).max())
+
+
+def test_shift_needed_at_ten_points_per_wavelength():
+    # Sec. IV-B: the paper preconditions with kappa = 1 and saw no benefit from a shift.  At 10 points
+    # per wavelength (every workload here) the unshifted preconditioner leaves MG-FGMRES stalled, and
+    # so does the shift of the other sign, while the dissipative shift kappa = 1 + 0.5j converges
+    # (64^2 interior, 20-cell layer, disk of contrast 0.05, normal incidence, FGMRES(20))
+    from oracle.discretization import Problem
+    from oracle import model
+
+    nmap = synth.disk_map(64, 10.0, 0.05)
+    its = {}
+    for kappa in (1.0, 1 - 0.5j, 1 + 0.5j):
+        prob = Problem(nmap, k0h=KBH / 1.333, w=20, levels=4, kappa=kappa)
+        b = prob.h ** 2 * model.rhs(prob, (0.0, 1.0)).ravel()
+        _, info = model.mg_fgmres_solve(prob, b, rtol=1e-6, restart=20, max_iters=300)
+        its[kappa] = info
+    assert its[1 + 0.5j].converged and its[1 + 0.5j].iters < 200
+    for kappa in (1.0, 1 - 0.5j):
+        assert not its[kappa].converged and its[kappa].rel_res_true > 1e-2, (kappa, its[kappa].rel_res_true)

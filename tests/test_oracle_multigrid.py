@@ -63,9 +63,16 @@ def test_coarse_coefficient_rule():
     blk = c0[2 * i - 1:2 * i + 2, 2 * j - 1:2 * j + 2]
     wts = np.outer([1, 2, 1], [1, 2, 1]) / 16.0
     assert c1[i, j] == pytest.approx(4.0 * np.sum(wts * blk))
-    ring_expected = (prob.kbh * 2) ** 2 * prob.alpha_at([np.array(0), np.array(4)], stride=2)
-    assert c1[0, 4] == pytest.approx(complex(ring_expected))
-    assert c1[n1 - 1, 0].imag > 0  # layer is dissipative at the far corner
+    # ring values by hand: n = 9, w = 4, 3 levels give n_e = 17, Omega = [4, 13) and the unit-square
+    # factor 1/16, so gamma = beta d^2 / (w 16) = 0.15 d^2 / 64.  Coarse (0, 4) is fine (0, 8): d = 4;
+    # coarse (8, 0) is fine (16, 0): d^2 = 4^2 + 4^2.  Level-1 background (k_b 2h)^2
+    assert prob.n_e == 17 and n1 == 9
+    cb1 = (KBH * 2) ** 2
+    assert c1[0, 4] == pytest.approx(cb1 * (1 + 1j * 0.15 * 16 / 64), rel=1e-13)
+    assert c1[n1 - 1, 0] == pytest.approx(cb1 * (1 + 1j * 0.15 * 32 / 64), rel=1e-13)
+    c2 = hier.coef[2]  # level 2: coarse (2, 0) is fine (8, 0), d = 4; (0, 0) is fine (0, 0), d^2 = 32
+    assert c2[2, 0] == pytest.approx((KBH * 4) ** 2 * (1 + 1j * 0.15 * 16 / 64), rel=1e-13)
+    assert c2[0, 0] == pytest.approx((KBH * 4) ** 2 * (1 + 1j * 0.15 * 32 / 64), rel=1e-13)
 
 
 def test_scaled_cycle_equals_unscaled_two_grid_matrix():
