@@ -211,7 +211,7 @@ def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
     t_collect = time.perf_counter() - t0
     ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device=dev))
     tr, val = sets
-    val = learned.Examples(val.feat, val.tgt * val.gamma / tr.gamma, tr.gamma, tr.cb)
+    val = learned.rescaled(ctx, val, tr.gamma)
     net = learned.new_network(11)
     log = learned.train(net, tr, steps=args.learned_steps, batch=16, lr=1e-4, seed=3, err_weight=0.0,
                         res_weight=1.0)

@@ -10,10 +10,12 @@
  *
  * (Sec. II-A eq. HelmScatterRightIncident; Sec. IV-A eq. discretizedHelm and
  * the first-order Sommerfeld ghost rows), one solve per incident plane wave,
- * batched over all waves of a scan, by restarted flexible GMRES preconditioned
- * with one multigrid V-cycle on the shifted operator
- * K_kappa = -Lap - kappa k0^2 eta^2 (Sec. IV-B/IV-C, Alg. 2), and the adjoint
- * solves and refractive-index gradient of Sec. V (Prop. 1).
+ * batched over all waves of a scan, by a Krylov method (restarted GMRES in
+ * s-step form by default, flexible GMRES, or the paper's Bi-CGSTAB of Alg. 3)
+ * preconditioned with one multigrid cycle (V, W, or two coarse-grid corrections
+ * on the finest level; Alg. 2) on the shifted operator
+ * K_kappa = -Lap - kappa k0^2 eta^2 (Sec. IV-B/IV-C), and the adjoint solves
+ * and refractive-index gradient of Sec. V (Prop. 1).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -95,7 +97,8 @@ typedef struct {
   int nu1, nu2;     /* pre/post relaxations (1, 1) */
   int cycle;        /* 1 = V-cycle, 2 = W-cycle (Alg. 2 CycleType); 3 = two coarse-grid
                        corrections on the finest level and V-cycles below (1) */
-  int restart;      /* FGMRES restart length m (10) */
+  int restart;      /* restart length m of GMRES (s-step form or FGMRES); for Bi-CGSTAB the
+                       iterations between status checks (10) */
   int max_iters;    /* max preconditioner applications per RHS (4000) */
   int max_batch;    /* largest B accepted by the solve calls (64) */
   int reorth;       /* 1 = one re-orthogonalisation pass (CGS2) (0) */
@@ -141,6 +144,9 @@ typedef struct {
   int status;           /* HELM_STATUS_* */
   double rel_res_true;  /* ||b - A x|| / ||b|| of the returned x (float-float evaluation) */
   int fallbacks;        /* learned-preconditioner outputs rejected for the V-cycle (0 without a network) */
+  double ms;            /* wall time of the whole batched call on the GPU (HIP events on the context
+                           stream, from the copy of the right-hand sides to the last status read);
+                           the same value for every right-hand side of the batch */
 } helm_stats;
 
 typedef struct {
@@ -216,10 +222,13 @@ int helm_grad_n(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc
 
 /* Receiver sampling S of the data term (Sec. V, eq. DataFidelityExplicit,
  * with on-grid receivers): y[q][i] = u[q][idx[i]] for M receiver flat indices
- * idx_dev (device int[M], distinct, on the extended grid). */
+ * idx_dev (device int[M], on the extended grid).  The indices are checked on
+ * the host first: HELM_EINVAL (nothing launched) for one outside the grid. */
 int helm_sample(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* u, helm_c32* y);
 
-/* S^T: u = 0 except u[q][idx[i]] = y[q][i]. */
+/* S^T: u = 0 except u[q][idx[i]] = y[q][i].  HELM_EINVAL (nothing launched) for
+ * an index outside the grid or a repeated index (S^T of repeated receivers would
+ * need a sum, and this form writes each point once). */
 int helm_sample_adjoint(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* y, helm_c32* u);
 
 /* Smoothed isotropic total variation of an interior map (the regulariser of
@@ -399,6 +408,19 @@ int helm_solve_snapshots(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x,
  * the solver gives the network: sqrt(N) times a unit-norm vector). */
 int helm_net_examples(helm_ctx* ctx, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,
                       const int* crops_host, int S, double gamma, float* feat_dev, float* tgt_dev);
+
+/* Root mean square of count FP32 values (device), sum of squares in FP64: the
+ * normalisation of the training targets (gamma of helm_set_preconditioner). */
+int helm_examples_rms(helm_ctx* ctx, const float* x_dev, long long count, double* rms_host);
+/* x *= factor in place for count FP32 values (device): rescaling of example targets. */
+int helm_examples_scale(helm_ctx* ctx, float* x_dev, long long count, double factor);
+
+/* Per-image residual ratio of the network on examples x [nimg][H][W][4] (H, W >= 3):
+ *   ratio_host[i] = ||r - gamma A' y||_2 / ||r||_2 over the image interior,
+ * y = network(x), with r, c (from cb = (k_b h)^2) and A' as in the residual term of
+ * helm_net_set_loss.  1 = no better than a zero correction.  Sums in FP64. */
+int helm_net_residual_ratio(helm_net* net, int nimg, int H, int W, const float* x_dev, double gamma, double cb,
+                            double* ratio_host);
 
 /* Launch shapes chosen by helm_autotune. */
 #define HELM_TUNE_MAX_LEVELS 12

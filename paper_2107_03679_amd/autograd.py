@@ -29,7 +29,7 @@ class HelmholtzScattering(torch.autograd.Function):
         usc, st = hctx.solve(rhs)
         if not st.converged:
             raise RuntimeError(f"forward solve did not converge: {st}")
-        fctx.hctx, fctx.rx_idx, fctx.n_map = hctx, rx_idx, nm
+        fctx.hctx, fctx.rx_idx, fctx.n_map, fctx.version = hctx, rx_idx, nm, hctx.medium_version
         fctx.save_for_backward(uin, usc)
         return hctx.sample(rx_idx, usc)
 
@@ -37,13 +37,50 @@ class HelmholtzScattering(torch.autograd.Function):
     def backward(fctx, grad_y: torch.Tensor):
         uin, usc = fctx.saved_tensors
         hctx = fctx.hctx
-        hctx.update_n(fctx.n_map)  # the context may have seen another medium since the forward pass
+        if hctx.medium_version != fctx.version:  # the context saw another medium since the forward pass
+            hctx.update_n(fctx.n_map)
         g = hctx.sample_adjoint(fctx.rx_idx, grad_y.to(torch.complex64).contiguous())
         lam, st = hctx.adjoint(g)
         if not st.converged:
             raise RuntimeError(f"adjoint solve did not converge: {st}")
         grad_n = hctx.grad_n(usc, lam, u_in=uin)
         return grad_n, None, None, None
+
+
+class HelmholtzDataTerm(torch.autograd.Function):
+    """L = sum_q 1/2 ||S u_sc,q(n) - y_q||^2 (eq. DataFidelityExplicit with on-grid receivers).
+
+    Forward: medium update, batched forward solves, and the data residual r_q = S u_sc,q - y_q
+    with L from the library (helm_data_residual).  Backward (Prop. 1): lam_q = A^-H S^T r_q by the
+    batched adjoint solve, dL/dn = sum_q 2 k0^2 n Re(conj(u_in,q + u_sc,q) lam_q) (helm_grad_n);
+    the residual that seeds the adjoint comes from the library, not from torch."""
+
+    @staticmethod
+    def forward(fctx, n_map: torch.Tensor, hctx: Context, dirs: np.ndarray, rx_idx: torch.Tensor,
+                data: torch.Tensor):
+        nm = n_map.detach().to(torch.float32).contiguous()
+        hctx.update_n(nm)
+        rhs, uin = hctx.plane_wave_rhs(dirs, with_uin=True)
+        usc, st = hctx.solve(rhs)
+        if not st.converged:
+            raise RuntimeError(f"forward solve did not converge: {st}")
+        res, loss = hctx.data_residual(rx_idx, usc, data.to(torch.complex64).contiguous())
+        fctx.hctx, fctx.rx_idx, fctx.n_map, fctx.version = hctx, rx_idx, nm, hctx.medium_version
+        fctx.save_for_backward(uin, usc, res)
+        return torch.tensor(loss, dtype=torch.float64, device=n_map.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        uin, usc, res = fctx.saved_tensors
+        hctx = fctx.hctx
+        if hctx.medium_version != fctx.version:  # the context saw another medium since the forward pass
+            hctx.update_n(fctx.n_map)
+        lam, st = hctx.adjoint(hctx.sample_adjoint(fctx.rx_idx, res))
+        if not st.converged:
+            raise RuntimeError(f"adjoint solve did not converge: {st}")
+        grad_n = hctx.grad_n(usc, lam, u_in=uin)
+        # chain rule through the scalar output (g = 1 for loss.backward())
+        return grad_n * g.to(grad_n.dtype), None, None, None, None
 
 
 class SmoothedTV(torch.autograd.Function):
@@ -73,10 +110,9 @@ def receiver_line(hctx: Context, row: int | None = None) -> torch.Tensor:
 
 def data_loss(n_map: torch.Tensor, hctx: Context, dirs, rx_idx, data: torch.Tensor, tau: float = 1e-3,
               tv_eps: float = 1e-4) -> torch.Tensor:
-    """sum_q 1/2 ||S u_sc,q(n) - y_q||^2 + tau TV_eps(n) (eq. MAPInverse with the quadratic data term)."""
-    y = HelmholtzScattering.apply(n_map, hctx, dirs, rx_idx)
-    r = y - data
-    loss = 0.5 * (r.real.double() ** 2 + r.imag.double() ** 2).sum()
+    """sum_q 1/2 ||S u_sc,q(n) - y_q||^2 + tau TV_eps(n) (eq. MAPInverse with the quadratic data term);
+    the data term and its gradient seed come from the library (HelmholtzDataTerm)."""
+    loss = HelmholtzDataTerm.apply(n_map, hctx, dirs, rx_idx, data)
     if tau:
         loss = loss + tau * SmoothedTV.apply(n_map, hctx, tv_eps)
     return loss

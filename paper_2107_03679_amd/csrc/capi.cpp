@@ -10,6 +10,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -110,6 +112,7 @@ struct helm_ctx {
 
   hipGraphExec_t graph = nullptr;
   int graph_B = 0;
+  hipEvent_t ev_solve[2] = {nullptr, nullptr};  // bracket of a solve call (helm_stats.ms)
 
   // launch shapes (helm_autotune): fused-leg tile per level, single-launch coarse threshold
   int tune_down[HELM_MAX_LEVELS] = {0};
@@ -118,6 +121,7 @@ struct helm_ctx {
 
   // learned preconditioner (NULL: multigrid only)
   helm_net* net = nullptr;
+  NetSolveBufs* net_bufs = nullptr;  // this context's activation buffers of the network (owned)
   double accept_tol = 0.9;
   double net_gamma = 1.0;
   int net_mode = HELM_NET_REPLACE;
@@ -410,8 +414,9 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
     const c32 cb = make_float2((float)(c->kbh * c->kbh), 0.0f);
     {
       ProfScope ps(c, "net_apply", 0.0);
-      net_apply(c->net, c->s, B, c->ne, vj.p, vj.stride, sj.p, sj.stride, (float)rootN, c->d_chi, cb,
-                (float)(c->net_gamma / rootN), zj.p, zj.stride, k.active);
+      check(net_apply(c->net, c->net_bufs, c->s, B, c->ne, vj.p, vj.stride, sj.p, sj.stride, (float)rootN,
+                      c->d_chi, cb, (float)(c->net_gamma / rootN), zj.p, zj.stride, k.active),
+            "network buffers do not fit this batch");
     }
     if (c->net_mode == HELM_NET_REPLACE) {
       {
@@ -629,8 +634,12 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
   if (B < 1 || B > c->o.max_batch) return fail(c, HELM_EINVAL, "B must be in [1, max_batch]");
   if (!rhs || !x) return fail(c, HELM_EINVAL, "null field pointer");
   const long long N0 = c->N0;
+  float call_ms = 0.f;
   try {
     check(hipStreamSynchronize(c->user_s), "caller stream");
+    for (hipEvent_t& e : c->ev_solve)
+      if (!e) check(hipEventCreate(&e), "hipEventCreate");
+    check(hipEventRecord(c->ev_solve[0], c->s), "hipEventRecord");
     check(hipMemcpyAsync(c->d_rhs, rhs, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy rhs");
     launch_status_init(c->s, B, c->k);
     check(hipMemcpyAsync(c->d_fallbacks, c->d_zero_ints, B * sizeof(int), hipMemcpyDeviceToDevice, c->s), "reset");
@@ -683,8 +692,10 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     check(hipMemcpyAsync(c->h_iters, c->k.iters, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "iters");
     check(hipMemcpyAsync(c->h_relres, c->k.relres, B * sizeof(double), hipMemcpyDeviceToHost, c->s), "relres");
     check(hipMemcpyAsync(c->h_fallbacks, c->d_fallbacks, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "fallbacks");
+    check(hipEventRecord(c->ev_solve[1], c->s), "hipEventRecord");
     check(hipStreamSynchronize(c->s), "hipStreamSynchronize");
     check(hipGetLastError(), "kernel launch");
+    check(hipEventElapsedTime(&call_ms, c->ev_solve[0], c->ev_solve[1]), "hipEventElapsedTime");
   } catch (const HipError& e) {
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
   }
@@ -698,19 +709,19 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
       stats[b].status = st;
       stats[b].rel_res_true = c->h_relres[b];
       stats[b].fallbacks = c->net ? c->h_fallbacks[b] : 0;
+      stats[b].ms = call_ms;
     }
   }
   return rc;
 }
 
-// Host set-up of coefficients and the coarsest inverse, uploaded to the device.
-void upload_medium(helm_ctx* c, const float* n_map_dev) {
-  const long long Ni = npts(c->n, c->dim);
-  std::vector<float> nf(Ni);
-  check(hipMemcpy(nf.data(), n_map_dev, Ni * sizeof(float), hipMemcpyDeviceToHost), "copy n_map");
-  check(hipMemcpy(c->d_nmap, n_map_dev, Ni * sizeof(float), hipMemcpyDeviceToDevice), "copy n_map");
-  std::vector<double> nm(nf.begin(), nf.end());
+// Medium-independent planes, once per context (host FP64): every level's coefficient with the
+// background index everywhere.  The absorbing layer, the float-float diagonal there and the
+// outermost coarse rings keep these values for every medium; the Omega values and the coarse
+// interiors are rewritten by update_medium.
+void upload_static(helm_ctx* c) {
   const helm_host::Geometry& g = c->geo;
+  std::vector<double> nm(npts(c->n, c->dim), c->o.n_b);
   std::vector<cd> cf = helm_host::fine_coefficient(g, nm);
   const long long N0 = c->N0;
   std::vector<c32> hi(N0), dhi(N0), dlo(N0);
@@ -729,15 +740,7 @@ void upload_medium(helm_ctx* c, const float* n_map_dev) {
   check(hipMemcpy(c->d_chi, hi.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload c");
   check(hipMemcpy(c->d_dhi, dhi.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload D");
   check(hipMemcpy(c->d_dlo, dlo.data(), N0 * sizeof(c32), hipMemcpyHostToDevice), "upload D");
-  // unscaled scattering potential f = k0^2 (eta^2 - eta_b^2) on Omega
-  std::vector<float> fpl(N0, 0.0f);
-  const double k02 = c->k0 * c->k0;
-  for (long long q = 0; q < Ni; ++q) {
-    const int ix = (int)(q % c->n), iy = (int)((q / c->n) % c->n), iz = c->dim == 3 ? (int)(q / ((long long)c->n * c->n)) : 0;
-    const long long p = c->dim == 2 ? (long long)(iy + c->w) * c->ne + (ix + c->w)
-                                    : ((long long)(iz + c->w) * c->ne + (iy + c->w)) * c->ne + (ix + c->w);
-    fpl[p] = (float)(k02 * (nm[q] * nm[q] - c->o.n_b * c->o.n_b));
-  }
+  std::vector<float> fpl(N0, 0.0f);  // f = 0 for the background medium
   check(hipMemcpy(c->d_f, fpl.data(), N0 * sizeof(float), hipMemcpyHostToDevice), "upload f");
   const cd kappa(c->o.kappa_re, c->o.kappa_im);
   std::vector<cd> cl = cf;
@@ -757,17 +760,65 @@ void upload_medium(helm_ctx* c, const float* n_map_dev) {
     check(hipMemcpy(c->lv[l].kc, kc.data(), kc.size() * sizeof(c32), hipMemcpyHostToDevice), "upload kc");
     check(hipMemcpy(c->lv[l].wd, wd.data(), wd.size() * sizeof(c32), hipMemcpyHostToDevice), "upload wd");
   }
+}
+
+std::pair<float, float> split_ff(double v) {
+  const float hi = (float)v;
+  return {hi, (float)(v - (double)hi)};
+}
+
+// Per medium: the Omega values of the fine planes and the coarse interiors on the GPU
+// (k_setup.hip), then the exact inverse of the coarsest shifted operator from that level's
+// coefficients (host FP64, a few hundred to a few thousand unknowns), uploaded.
+void update_medium(helm_ctx* c, const float* n_map_dev) {
+  const long long Ni = npts(c->n, c->dim);
+  check(hipMemcpyAsync(c->d_nmap, n_map_dev, Ni * sizeof(float), hipMemcpyDeviceToDevice, c->s), "copy n_map");
+  SetupFineArgs a{};
+  a.dim = c->dim;
+  a.n = c->n;
+  a.w = c->w;
+  a.ne = c->ne;
+  a.nmap = c->d_nmap;
+  std::tie(a.k2_hi, a.k2_lo) = split_ff(c->k0h * c->k0h);
+  std::tie(a.kbh_hi, a.kbh_lo) = split_ff(c->kbh);
+  std::tie(a.k02_hi, a.k02_lo) = split_ff(c->k0 * c->k0);
+  std::tie(a.nb2_hi, a.nb2_lo) = split_ff(c->o.n_b * c->o.n_b);
+  a.kappa = make_float2((float)c->o.kappa_re, (float)c->o.kappa_im);
+  a.g0 = c->lv[0].ghost;
+  a.omega = (float)c->o.omega_jac;
+  a.chi = c->d_chi;
+  a.dhi = c->d_dhi;
+  a.dlo = c->d_dlo;
+  a.kc0 = c->lv[0].kc;
+  a.wd0 = c->lv[0].wd;
+  a.f = c->d_f;
+  launch_setup_fine(c->s, a);
+  for (int l = 1; l < c->L; ++l)
+    launch_setup_coarse(c->s, c->dim, c->lv[l - 1].n, c->lv[l].n, c->lv[l - 1].kc, (float)c->o.omega_jac, c->lv[l].kc,
+                        c->lv[l].wd);
+  check(hipGetLastError(), "set-up kernels");
+  const Level& cl = c->lv[c->L - 1];
+  std::vector<c32> kc32(cl.N);
+  check(hipMemcpyAsync(kc32.data(), cl.kc, cl.N * sizeof(c32), hipMemcpyDeviceToHost, c->s), "coarsest kc");
+  check(hipStreamSynchronize(c->s), "set-up");
+  std::vector<cd> kc(cl.N);
+  for (long long p = 0; p < cl.N; ++p) kc[p] = cd(kc32[p].x, kc32[p].y);
   std::vector<cd> inv;
-  if (!helm_host::dense_inverse_transposed(g, cl, c->lv[c->L - 1].n, c->L - 1, kappa, inv))
+  if (!helm_host::dense_inverse_transposed(c->geo, kc, cl.n, c->L - 1, inv))
     throw HipError{hipErrorInvalidValue, "coarsest operator is singular"};
   std::vector<c32> inv32(inv.size());
   for (size_t p = 0; p < inv.size(); ++p) inv32[p] = to_c32(inv[p]);
-  check(hipMemcpy(c->d_minvT, inv32.data(), inv32.size() * sizeof(c32), hipMemcpyHostToDevice), "upload inverse");
+  check(hipMemcpyAsync(c->d_minvT, inv32.data(), inv32.size() * sizeof(c32), hipMemcpyHostToDevice, c->s),
+        "upload inverse");
+  check(hipStreamSynchronize(c->s), "set-up");
 }
 
 void free_ctx(helm_ctx* c) {
   if (!c) return;
   if (c->graph) hipGraphExecDestroy(c->graph);
+  net_bufs_destroy(c->net_bufs);
+  for (hipEvent_t e : c->ev_solve)
+    if (e) hipEventDestroy(e);
   for (auto& p : c->pending) {
     hipEventDestroy(p.e0);
     hipEventDestroy(p.e1);
@@ -1038,7 +1089,8 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     check(hipMemcpy(c->d_ones, ones.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload ones");
     check(hipMemcpy(c->d_zero_ints, zeros.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload zeros");
     check(hipHostMalloc((void**)&c->h_fallbacks, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
-    upload_medium(c, n_map_dev);
+    upload_static(c);
+    update_medium(c, n_map_dev);
     check(hipDeviceSynchronize(), "setup");
   } catch (const HipError& e) {
     std::string msg = std::string(e.what) + ": " + hipGetErrorString(e.code);
@@ -1057,7 +1109,7 @@ int helm_update_n(helm_ctx* c, const float* n_map_dev) {
   try {
     check(hipStreamSynchronize(c->user_s), "caller stream");
     check(hipStreamSynchronize(c->s), "sync");
-    upload_medium(c, n_map_dev);
+    update_medium(c, n_map_dev);
   } catch (const HipError& e) {
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
   } catch (const std::bad_alloc&) {
@@ -1125,15 +1177,19 @@ int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, doubl
   if (!(gamma > 0.0)) return fail(c, HELM_EINVAL, "gamma must be positive");
   try {
     check(hipStreamSynchronize(c->s), "sync");
-    if (net) net_reserve(net, c->o.max_batch, c->ne);
-    if (net && mode == HELM_NET_THEN_MG && !c->d_net_res) {
-      c->d_net_res = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
-      c->d_net_cor = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
-    }
-    if (c->graph) {
+    if (c->graph) {  // the captured cycle refers to the old preconditioner and its buffers
       hipGraphExecDestroy(c->graph);
       c->graph = nullptr;
       c->graph_B = 0;
+    }
+    // fresh buffers for this context (a network may also serve other contexts, each with its own)
+    c->net = nullptr;
+    net_bufs_destroy(c->net_bufs);
+    c->net_bufs = nullptr;
+    if (net) c->net_bufs = net_bufs_create(net, c->o.max_batch, c->ne);
+    if (net && mode == HELM_NET_THEN_MG && !c->d_net_res) {
+      c->d_net_res = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
+      c->d_net_cor = c->alloc<c32>((size_t)c->o.max_batch * c->N0);
     }
   } catch (const HipError& e) {
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
@@ -1172,6 +1228,31 @@ int helm_net_examples(helm_ctx* c, int B, const helm_c32* r, const helm_c32* x_f
                   c->d_chi, make_float2((float)(c->kbh * c->kbh), 0.0f), (float)(c->h * c->h), (float)(1.0 / gamma),
                   feat, tgt);
   HELM_GUARD_END("net_examples")
+}
+
+int helm_examples_rms(helm_ctx* c, const float* x_dev, long long count, double* rms_host) {
+  if (!c || !x_dev || !rms_host || count < 1) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  const int nbk = sumsq_blocks(count);
+  if (nbk > c->inv_part_len) {
+    c->d_inv_part = c->alloc<double>(nbk);
+    c->inv_part_len = nbk;
+  }
+  launch_sumsq(c->s, count, x_dev, c->d_inv_part);
+  std::vector<double> part(nbk);
+  check(hipMemcpyAsync(part.data(), c->d_inv_part, nbk * sizeof(double), hipMemcpyDeviceToHost, c->s), "sumsq");
+  check(hipStreamSynchronize(c->s), "sync");
+  double sum = 0.0;
+  for (double v : part) sum += v;
+  *rms_host = std::sqrt(sum / (double)count);
+  HELM_GUARD_END("examples_rms")
+}
+
+int helm_examples_scale(helm_ctx* c, float* x_dev, long long count, double factor) {
+  if (!c || !x_dev || count < 1 || !std::isfinite(factor)) return fail(c, HELM_EINVAL, "bad argument");
+  HELM_GUARD_BEGIN
+  launch_scale(c->s, count, x_dev, (float)factor);
+  HELM_GUARD_END("examples_scale")
 }
 
 int helm_adjoint_batch(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* lam, helm_stats* stats) {
@@ -1371,9 +1452,27 @@ int helm_profile_get(const helm_ctx* c, int i, char* name, int name_len, double*
   return HELM_OK;
 }
 
+namespace {
+// Receiver indices (device int[M]) checked on the host: each inside the extended grid and,
+// where S^T scatters into them, distinct.  Returns an empty string when they are valid.
+std::string receiver_error(helm_ctx* c, int M, const int* idx_dev, bool distinct) {
+  std::vector<int> idx(M);
+  check(hipMemcpy(idx.data(), idx_dev, (size_t)M * sizeof(int), hipMemcpyDeviceToHost), "copy idx");
+  for (int i : idx)
+    if (i < 0 || (long long)i >= c->N0) return "receiver index outside the grid";
+  if (distinct) {
+    std::sort(idx.begin(), idx.end());
+    if (std::adjacent_find(idx.begin(), idx.end()) != idx.end()) return "receiver indices must be distinct";
+  }
+  return std::string();
+}
+}  // namespace
+
 int helm_sample(helm_ctx* c, int B, int M, const int* idx, const helm_c32* u, helm_c32* y) {
   if (!c || !idx || !u || !y || B < 1 || M < 1) return fail(c, HELM_EINVAL, "bad argument");
   HELM_GUARD_BEGIN
+  const std::string bad = receiver_error(c, M, idx, false);
+  if (!bad.empty()) return fail(c, HELM_EINVAL, bad);
   launch_gather(c->s, B, M, c->N0, idx, (const c32*)u, (c32*)y);
   HELM_GUARD_END("sample")
 }
@@ -1381,6 +1480,8 @@ int helm_sample(helm_ctx* c, int B, int M, const int* idx, const helm_c32* u, he
 int helm_sample_adjoint(helm_ctx* c, int B, int M, const int* idx, const helm_c32* y, helm_c32* u) {
   if (!c || !idx || !u || !y || B < 1 || M < 1) return fail(c, HELM_EINVAL, "bad argument");
   HELM_GUARD_BEGIN
+  const std::string bad = receiver_error(c, M, idx, true);
+  if (!bad.empty()) return fail(c, HELM_EINVAL, bad);
   launch_zero(c->s, (long long)B * c->N0, (c32*)u);
   launch_scatter(c->s, B, M, c->N0, idx, (const c32*)y, (c32*)u);
   HELM_GUARD_END("sample_adjoint")
@@ -1423,7 +1524,7 @@ int helm_update_f(helm_ctx* c, const float* f_dev) {
     launch_index_from_f(c->s, npts(c->n, c->dim), f_dev, 1.0 / (c->k0 * c->k0), c->o.n_b * c->o.n_b, c->d_inv_n);
     check(hipGetLastError(), "index_from_f");
     check(hipStreamSynchronize(c->s), "sync");
-    upload_medium(c, c->d_inv_n);
+    update_medium(c, c->d_inv_n);
   } catch (const HipError& e) {
     return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
   } catch (const std::bad_alloc&) {
@@ -1446,10 +1547,8 @@ int helm_data_residual(helm_ctx* c, int B, int M, const int* idx_dev, const helm
   if (!c || !idx_dev || !u || !y || !res) return fail(c, HELM_EINVAL, "null argument");
   if (B < 1 || M < 1) return fail(c, HELM_EINVAL, "B and M must be >= 1");
   HELM_GUARD_BEGIN
-  std::vector<int> idx(M);
-  check(hipMemcpy(idx.data(), idx_dev, (size_t)M * sizeof(int), hipMemcpyDeviceToHost), "copy idx");
-  for (int i : idx)
-    if (i < 0 || (long long)i >= c->N0) return fail(c, HELM_EINVAL, "receiver index outside the grid");
+  const std::string bad = receiver_error(c, M, idx_dev, false);
+  if (!bad.empty()) return fail(c, HELM_EINVAL, bad);
   const int nbk = data_residual_blocks(B, M);
   if (nbk > c->inv_part_len) {
     c->d_inv_part = c->alloc<double>(nbk);

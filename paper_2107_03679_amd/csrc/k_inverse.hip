@@ -144,6 +144,37 @@ void launch_fbs_momentum(hipStream_t s, long long count, const float* f_new, flo
   hipLaunchKernelGGL(k_fbs_momentum, dim3(grid_of(count)), dim3(256), 0, s, count, f_new, beta, f, fbar);
 }
 
+namespace {
+// per-block partial sums of x[i]^2 (FP64), grid-stride
+__global__ void k_sumsq(long long n, const float* x, double* part) {
+  __shared__ double red[256 / HELM_WAVE];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += (double)x[i] * x[i];
+  s = wave_sum_d(s);
+  if (threadIdx.x % HELM_WAVE == 0) red[threadIdx.x / HELM_WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < 256 / HELM_WAVE; ++q) t += red[q];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_scale(long long n, float* x, float a) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+}  // namespace
+
+int sumsq_blocks(long long n) { return (int)grid_of(n); }
+void launch_sumsq(hipStream_t s, long long n, const float* x, double* part) {
+  hipLaunchKernelGGL(k_sumsq, dim3(sumsq_blocks(n)), dim3(256), 0, s, n, x, part);
+}
+void launch_scale(hipStream_t s, long long n, float* x, float a) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_of(n)), dim3(256), 0, s, n, x, a);
+}
+
 int data_residual_blocks(int B, int M) { return (int)grid_of((long long)B * M); }
 
 void launch_data_residual(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, const c32* y,

@@ -427,6 +427,40 @@ __global__ void k_res_grad(int nimg, int H, int W, const float* x, const float2*
   gy[p * 2 + 1] -= w * gamma * g.y;
 }
 
+// Per image: sums over the interior of |r - gamma A' y|^2 and |r|^2 (r, c, y as in k_res_q),
+// one block per image, fixed-order reduction; sums[2 img], sums[2 img + 1].
+__global__ __launch_bounds__(256) void k_res_ratio(int H, int W, const float* x, const float* y, float gamma, c32 cb,
+                                                   double* sums) {
+  __shared__ double red[2][256 / HELM_WAVE];
+  const long long img = blockIdx.x, base = img * H * W;
+  double sq = 0.0, sr = 0.0;
+  for (int t = threadIdx.x; t < (H - 2) * (W - 2); t += 256) {
+    const int py = 1 + t / (W - 2), px = 1 + t % (W - 2);
+    const long long p = base + (long long)py * W + px;
+    const float* xp = x + p * 4;
+    const c32 c = cmul(cb, make_float2(1.f + xp[2], xp[3]));
+    const c32 yc = make_float2(y[p * 2], y[p * 2 + 1]);
+    const c32 nbs = make_float2(y[(p - 1) * 2] + y[(p + 1) * 2] + y[(p - W) * 2] + y[(p + W) * 2],
+                                y[(p - 1) * 2 + 1] + y[(p + 1) * 2 + 1] + y[(p - W) * 2 + 1] + y[(p + W) * 2 + 1]);
+    const c32 ay = csub(cmul(make_float2(4.f - c.x, -c.y), yc), nbs);
+    const float qx = xp[0] - gamma * ay.x, qy = xp[1] - gamma * ay.y;
+    sq += (double)qx * qx + (double)qy * qy;
+    sr += (double)xp[0] * xp[0] + (double)xp[1] * xp[1];
+  }
+  sq = wave_sum_d(sq);
+  sr = wave_sum_d(sr);
+  if (threadIdx.x % HELM_WAVE == 0) {
+    red[0][threadIdx.x / HELM_WAVE] = sq;
+    red[1][threadIdx.x / HELM_WAVE] = sr;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double v = 0.0;
+    for (int w = 0; w < 256 / HELM_WAVE; ++w) v += red[threadIdx.x][w];
+    sums[2 * img + threadIdx.x] = v;
+  }
+}
+
 // Adam on the FP32 master weights (entries with mask 0 -- the padding -- stay 0)
 __global__ void k_adam(int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask, float lr,
                        float b1, float b2, float eps, float c1, float c2) {
@@ -622,6 +656,10 @@ void launch_res_loss(hipStream_t s, int nimg, int H, int W, const float* x, cons
   const long long P = (long long)nimg * H * W;
   hipLaunchKernelGGL(k_res_q, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, y, gamma, cb, w, q, part);
   hipLaunchKernelGGL(k_res_grad, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, q, gamma, cb, w, gy);
+}
+void launch_res_ratio(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
+                      double* sums) {
+  hipLaunchKernelGGL(k_res_ratio, dim3(nimg), dim3(256), 0, s, H, W, x, y, gamma, cb, sums);
 }
 void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
                  float lr, float b1, float b2, float eps, float c1, float c2) {

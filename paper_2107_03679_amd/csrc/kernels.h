@@ -182,6 +182,28 @@ void launch_tv_prox(hipStream_t s, int dim, int n, const float* v, float lam, fl
                     float* w);
 void launch_axmy(hipStream_t s, long long count, const float* a, float sc, const float* b, float* out);
 void launch_fbs_momentum(hipStream_t s, long long count, const float* f_new, float beta, float* f, float* fbar);
+// ---- medium-dependent set-up (k_setup.hip) ----
+struct SetupFineArgs {
+  int dim, n, w, ne;
+  const float* nmap;            // interior index [n^dim]
+  float k2_hi, k2_lo;           // (k0 h)^2, float-float
+  float kbh_hi, kbh_lo;         // k_b h (imaginary part of the fine ghost factor), float-float
+  float k02_hi, k02_lo;         // k0^2 (the unscaled f), float-float
+  float nb2_hi, nb2_lo;         // eta_b^2, float-float
+  c32 kappa, g0;                // shift; fine ghost factor 1 + j k_b h
+  float omega;                  // damped-Jacobi factor
+  c32 *chi, *dhi, *dlo, *kc0, *wd0;
+  float* f;
+};
+// Omega points of the fine level: c, float-float diagonal of A', f, kappa c, omega / diag(K_0)
+void launch_setup_fine(hipStream_t s, const SetupFineArgs& a);
+// interior points of a coarse level (nc per axis) from the finer level's kappa c (nf per axis)
+void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, float omega, c32* kcc, c32* wdc);
+
+// FP32 vector helpers: block partial sums of squares (FP64) and an in-place scaling
+int sumsq_blocks(long long n);
+void launch_sumsq(hipStream_t s, long long n, const float* x, double* part);
+void launch_scale(hipStream_t s, long long n, float* x, float a);
 int data_residual_blocks(int B, int M);
 void launch_data_residual(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, const c32* y,
                           c32* res, double* part);

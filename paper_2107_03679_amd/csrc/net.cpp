@@ -82,8 +82,8 @@ struct helm_net {
   // training loss: err_w / 2 sum (y - t)^2 + res_w / 2 sum |r - gamma A' y|^2, per image
   double err_w = 1.0, res_w = 0.0, gamma = 1.0, cb = 0.0;
   NetBufs tb;              // buffers of the user calls (forward / backward)
-  NetBufs sb;              // buffers of the solver's preconditioner applications
-  NetBufs* cur = &tb;      // the set the kernels of the current call use
+  NetBufs* cur = &tb;      // the set the kernels of the current call use (a solver
+                           // context's own set during its preconditioner applications)
 
   template <class T>
   T* alloc(size_t n, std::vector<void*>& list) {
@@ -308,18 +308,38 @@ int fail(helm_net* n, int code, const std::string& msg) {
 
 }  // namespace
 
-void net_reserve(helm_net* n, int B, int ngrid) {
-  n->cur = &n->sb;
-  ensure(n, B, ngrid, ngrid, false);
+struct NetSolveBufs {
+  NetBufs b;
+};
+
+NetSolveBufs* net_bufs_create(helm_net* n, int B, int ngrid) {
+  NetSolveBufs* sb = new NetSolveBufs();
+  n->cur = &sb->b;
+  try {
+    ensure(n, B, ngrid, ngrid, false);
+  } catch (...) {
+    free_bufs(n);
+    n->cur = &n->tb;
+    delete sb;
+    throw;
+  }
   n->cur = &n->tb;
+  return sb;
 }
 
-void net_apply(helm_net* n, hipStream_t s, int B, int ngrid, const c32* v, long long v_stride, const float* vscale,
-               int vs_stride, float in_gain, const c32* coef, c32 cb, float out_gain, c32* z, long long z_stride,
-               const int* mask) {
+void net_bufs_destroy(NetSolveBufs* sb) {
+  if (!sb) return;
+  for (void* p : sb->b.bufs) hipFree(p);
+  delete sb;
+}
+
+hipError_t net_apply(helm_net* n, NetSolveBufs* sb, hipStream_t s, int B, int ngrid, const c32* v,
+                     long long v_stride, const float* vscale, int vs_stride, float in_gain, const c32* coef, c32 cb,
+                     float out_gain, c32* z, long long z_stride, const int* mask) {
+  if (!sb || B > sb->b.cap_nimg || ngrid != sb->b.cap_H || ngrid != sb->b.cap_W) return hipErrorInvalidValue;
   hipStream_t keep = n->s;
   n->s = s;
-  n->cur = &n->sb;
+  n->cur = &sb->b;
   set_current(n, B, ngrid, ngrid);
   const long long N = (long long)ngrid * ngrid;
   launch_net_input(s, B, N, v, v_stride, vscale, vs_stride, in_gain, coef, cb, n->cur->x0, 8);
@@ -327,6 +347,7 @@ void net_apply(helm_net* n, hipStream_t s, int B, int ngrid, const c32* v, long 
   launch_net_output(s, B, N, n->cur->y, out_gain, z, z_stride, mask);
   n->s = keep;
   n->cur = &n->tb;
+  return hipSuccess;
 }
 
 extern "C" {
@@ -403,8 +424,6 @@ int helm_net_create(unsigned long long seed, void* hip_stream, helm_net** out) {
 void helm_net_destroy(helm_net* n) {
   if (!n) return;
   hipStreamSynchronize(n->s);
-  n->cur = &n->sb;
-  free_bufs(n);
   n->cur = &n->tb;
   free_bufs(n);
   for (void* p : n->allocs) hipFree(p);
@@ -499,6 +518,29 @@ int helm_net_backward(helm_net* n, int nimg, int H, int W, const float* x, const
     *loss = sum;
   }
   ck(hipStreamSynchronize(n->s), "sync");
+  NET_CATCH
+  return HELM_OK;
+}
+
+int helm_net_residual_ratio(helm_net* n, int nimg, int H, int W, const float* x, double gamma, double cb,
+                            double* ratio_host) {
+  if (!n || !x || !ratio_host || nimg < 1 || H < 3 || W < 3 || !(gamma > 0.0) || !(cb > 0.0))
+    return fail(n, HELM_EINVAL, "bad argument");
+  NET_TRY
+  ensure(n, nimg, H, W, n->cur->cap_train && n->cur->cap_nimg >= nimg && n->cur->cap_H == H && n->cur->cap_W == W);
+  set_current(n, nimg, H, W);
+  launch_to_bf16_pad(n->s, n->cur->P[0], 4, x, 8, n->cur->x0);
+  forward(n);
+  std::vector<double> sums(2 * (size_t)nimg);
+  double* d_sums = nullptr;
+  ck(hipMalloc((void**)&d_sums, sums.size() * sizeof(double)), "hipMalloc");
+  launch_res_ratio(n->s, nimg, H, W, x, n->cur->y, (float)gamma, make_float2((float)cb, 0.f), d_sums);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(sums.data(), d_sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost, n->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(n->s);
+  hipFree(d_sums);
+  ck(e, "residual ratio");
+  for (int i = 0; i < nimg; ++i) ratio_host[i] = sums[2 * i + 1] > 0.0 ? std::sqrt(sums[2 * i] / sums[2 * i + 1]) : 0.0;
   NET_CATCH
   return HELM_OK;
 }

@@ -60,6 +60,9 @@ void launch_loss(hipStream_t s, long long n, const float* y, const float* tgt, f
 // (part: loss_partials(P) block sums)
 void launch_res_loss(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
                      float w, float2* q, float* part, float* gy);
+// per image: interior sums of |r - gamma A' y|^2 and |r|^2 into sums[2 img], sums[2 img + 1] (FP64)
+void launch_res_ratio(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
+                      double* sums);
 void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
                  float lr, float b1, float b2, float eps, float c1, float c2);
 void launch_pack(hipStream_t s, int cout_pad, int cin, int kpad, int cob, int kbpad, const float* w, bf16* wt,

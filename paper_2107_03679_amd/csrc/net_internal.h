@@ -15,11 +15,17 @@ struct NetLayer {
 };
 
 struct helm_net;
+struct NetSolveBufs;  // activation buffers of one solver context's network applications
 
-// Preconditioner application on B solver-grid images (n x n, 2D): features from
-// the basis vectors v (scaled by vscale and in_gain) and the coefficient
-// contrast, z = out_gain * network output for the right-hand sides in `mask`.
-void net_reserve(helm_net* n, int B, int ngrid);
-void net_apply(helm_net* n, hipStream_t s, int B, int ngrid, const c32* v, long long v_stride, const float* vscale,
-               int vs_stride, float in_gain, const c32* coef, c32 cb, float out_gain, c32* z, long long z_stride,
-               const int* mask);
+// Buffers for network applications on up to B solver-grid images of ngrid x ngrid (2D),
+// owned by the solver context that reserves them (one network may serve several contexts
+// of different sizes); freed by net_bufs_destroy.
+NetSolveBufs* net_bufs_create(helm_net* n, int B, int ngrid);
+void net_bufs_destroy(NetSolveBufs* b);
+// Preconditioner application on B <= the reserved count of images (n x n, 2D): features
+// from the basis vectors v (scaled by vscale and in_gain) and the coefficient contrast,
+// z = out_gain * network output for the right-hand sides in `mask`.  Returns
+// hipErrorInvalidValue (and launches nothing) when B or ngrid do not fit the buffers.
+hipError_t net_apply(helm_net* n, NetSolveBufs* bufs, hipStream_t s, int B, int ngrid, const c32* v, long long v_stride,
+               const float* vscale, int vs_stride, float in_gain, const c32* coef, c32 cb, float out_gain, c32* z,
+               long long z_stride, const int* mask);

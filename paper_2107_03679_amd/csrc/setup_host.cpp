@@ -5,12 +5,15 @@
 //    coefficient at interior coarse points (the factor 4 = (2h)^2 / h^2 of the
 //    h_l^2-scaled operators), background value k_b^2 h_l^2 alpha(x) on the
 //    outermost ring;
-//  * the explicit inverse of the coarsest shifted operator (Gauss-Jordan with
-//    partial pivoting), which the GPU applies as a dense product.
+//  * the explicit inverse of the coarsest shifted operator, which the GPU applies
+//    as a dense product: banded LU without pivoting where the operator is
+//    diagonally dominant (the usual case: the shifted coefficient of the
+//    coarsest grid is large), else Gauss-Jordan with partial pivoting.
 #include "setup_host.h"
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace helm_host {
 
@@ -96,17 +99,74 @@ std::vector<cd> coarse_coefficient(const Geometry& g, const std::vector<cd>& cf,
   return cc;
 }
 
-bool dense_inverse_transposed(const Geometry& g, const std::vector<cd>& cl, int nl, int level, cd kappa,
+// Inverse of a matrix that is diagonally dominant by rows (so LU without pivoting is stable)
+// and banded with half-bandwidth bw (the h^2-scaled Laplacian plus a diagonal on an nl^d grid:
+// bw = nl^(d-1)).  LU in band storage costs N bw^2; column j of the inverse needs the forward
+// substitution from row j on and, since K is complex symmetric (so is its inverse), only the
+// back substitution down to row j: entry (i, j) for i >= j, mirrored to (j, i).  Columns are
+// split over host threads.  Returns the transposed inverse (row-major inv_t[k][r] = inv[r][k]).
+static void banded_inverse(const std::vector<cd>& a, long long N, long long bw, std::vector<cd>& inv_t) {
+  const long long W = 2 * bw + 1;  // band row: columns p - bw .. p + bw
+  std::vector<cd> band(N * W, cd(0.0));
+  auto B = [&](long long r, long long col) -> cd& { return band[r * W + (col - r + bw)]; };
+  for (long long r = 0; r < N; ++r)
+    for (long long col = std::max(0LL, r - bw); col <= std::min(N - 1, r + bw); ++col) B(r, col) = a[r * N + col];
+  // LU without pivoting: L (unit lower) below the diagonal, U on and above it, fill stays in the band
+  for (long long k = 0; k < N; ++k) {
+    const cd piv = B(k, k);
+    const long long end = std::min(N - 1, k + bw);
+    for (long long i = k + 1; i <= end; ++i) {
+      cd& lik = B(i, k);
+      if (lik == cd(0.0)) continue;
+      lik /= piv;
+      for (long long j = k + 1; j <= end; ++j) B(i, j) -= lik * B(k, j);
+    }
+  }
+  inv_t.assign(N * N, cd(0.0));
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t)
+    pool.emplace_back([&, t] {
+      std::vector<cd> v(N);
+      for (long long j = t; j < N; j += nth) {
+        // forward: L y = e_j (y_i = 0 for i < j)
+        std::fill(v.begin(), v.end(), cd(0.0));
+        v[j] = 1.0;
+        for (long long i = j + 1; i < N; ++i) {
+          cd s = 0.0;
+          for (long long k = std::max(j, i - bw); k < i; ++k) s += B(i, k) * v[k];
+          v[i] = -s;
+        }
+        // back: U x = y, rows N-1 down to j
+        for (long long i = N - 1; i >= j; --i) {
+          cd s = v[i];
+          const long long end = std::min(N - 1, i + bw);
+          for (long long k = i + 1; k <= end; ++k) s -= B(i, k) * v[k];
+          v[i] = s / B(i, i);
+        }
+        // inv[i][j] = inv[j][i] = v[i] for i >= j; inv_t[k][r] = inv[r][k]
+        for (long long i = j; i < N; ++i) {
+          inv_t[j * N + i] = v[i];
+          inv_t[i * N + j] = v[i];
+        }
+      }
+    });
+  for (auto& th : pool) th.join();
+}
+
+bool dense_inverse_transposed(const Geometry& g, const std::vector<cd>& kcl, int nl, int level,
                               std::vector<cd>& inv_t) {
   const long long N = npts(nl, g.dim);
   const cd ghost(1.0, g.k0h * g.n_b * std::ldexp(1.0, level));
-  // assemble K'_l = -Lap'_l - kappa c_l as a dense row-major matrix
+  // assemble K'_l = -Lap'_l - kappa c_l (kcl = kappa c_l) as a dense row-major matrix
   std::vector<cd> a(N * N, cd(0.0));
+  bool dominant = true;
   for (long long p = 0; p < N; ++p) {
     const int x = (int)(p % nl), y = (int)((p / nl) % nl), z = g.dim == 3 ? (int)(p / ((long long)nl * nl)) : 0;
     int ng = (x == 0) + (x == nl - 1) + (y == 0) + (y == nl - 1);
     if (g.dim == 3) ng += (z == 0) + (z == nl - 1);
-    a[p * N + p] = 2.0 * g.dim - kappa * cl[p] - (double)ng * ghost;
+    a[p * N + p] = 2.0 * g.dim - kcl[p] - (double)ng * ghost;
+    dominant = dominant && std::abs(a[p * N + p]) > 2.0 * g.dim - ng;  // off-diagonal row sum
     const long long s2 = (long long)nl * nl;
     if (x > 0) a[p * N + p - 1] = -1.0;
     if (x < nl - 1) a[p * N + p + 1] = -1.0;
@@ -116,6 +176,12 @@ bool dense_inverse_transposed(const Geometry& g, const std::vector<cd>& cl, int 
       if (z > 0) a[p * N + p - s2] = -1.0;
       if (z < nl - 1) a[p * N + p + s2] = -1.0;
     }
+  }
+  for (long long p = 0; p < N; ++p)
+    if (!std::isfinite(std::abs(a[p * N + p]))) return false;
+  if (dominant) {
+    banded_inverse(a, N, g.dim == 2 ? nl : (long long)nl * nl, inv_t);
+    return true;
   }
   // Gauss-Jordan with partial pivoting on [A | I]
   std::vector<cd> inv(N * N, cd(0.0));

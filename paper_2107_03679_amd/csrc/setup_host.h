@@ -23,7 +23,8 @@ struct Geometry {
 int extended_size(int n, int w, int levels);
 std::vector<cd> fine_coefficient(const Geometry& g, const std::vector<double>& nmap);
 std::vector<cd> coarse_coefficient(const Geometry& g, const std::vector<cd>& cf, int nf, int level);
-bool dense_inverse_transposed(const Geometry& g, const std::vector<cd>& cl, int nl, int level, cd kappa,
+// transposed inverse of K'_l = -Lap'_l (with the level's ghost rows) - kcl, kcl = kappa c_l
+bool dense_inverse_transposed(const Geometry& g, const std::vector<cd>& kcl, int nl, int level,
                               std::vector<cd>& inv_t);
 
 }  // namespace helm_host

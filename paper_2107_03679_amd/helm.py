@@ -49,7 +49,7 @@ class HelmOpts(ctypes.Structure):
 
 class HelmStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double),
-                ("fallbacks", ctypes.c_int)]
+                ("fallbacks", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 class HelmTune(ctypes.Structure):
@@ -80,6 +80,7 @@ EXPORTS = [
     "helm_net_adam_step", "helm_net_set_loss", "helm_autotune", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
     "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
     "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
+    "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio",
 ]
 
 _lib = None
@@ -148,6 +149,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_farfield_adjoint.argtypes = [vp, i, vp, vp, vp]
     lib.helm_grad_f_farfield.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.helm_farfield_residual.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(d)]
+    lib.helm_examples_rms.argtypes = [vp, vp, ctypes.c_longlong, ctypes.POINTER(d)]
+    lib.helm_examples_scale.argtypes = [vp, vp, ctypes.c_longlong, d]
+    lib.helm_net_residual_ratio.argtypes = [vp, i, i, i, vp, d, d, vp]
     lib.helm_last_error.argtypes = [vp]
     lib.helm_last_error.restype = ctypes.c_char_p
     lib.helm_destroy.argtypes = [vp]
@@ -180,6 +184,7 @@ class SolveStats:
     status: np.ndarray
     rel_res_true: np.ndarray
     fallbacks: np.ndarray | None = None
+    ms: float = 0.0  # GPU time of the batched call (HIP events on the library's stream)
 
     @property
     def converged(self) -> bool:
@@ -235,8 +240,33 @@ class Context:
         self.n_e = info.n_e
         self.levels = info.levels
         self.device = n_map.device
+        self.medium_version = 0  # incremented by every medium change (update_n / update_f)
 
     # -- helpers -------------------------------------------------------------
+    def _f(self, t: torch.Tensor | None, B: int | None = None, level: int = 0, name: str = "field") -> int | None:
+        """Pointer of a complex64 field tensor [B][grid of `level`] after checking dtype and shape
+        (the library reads its memory as exactly that)."""
+        if t is None:
+            return None
+        if t.dtype != torch.complex64:
+            raise HelmError(f"{name} must be complex64, got {t.dtype}")
+        shp = self.grid_shape(level)
+        if t.dim() != 1 + self.dim or tuple(t.shape[1:]) != shp or (B is not None and t.shape[0] != B):
+            raise HelmError(f"{name} must have shape [{B if B is not None else 'B'}, "
+                            f"{', '.join(map(str, shp))}], got {list(t.shape)}")
+        return _ptr(t)
+
+    def _idx(self, idx: torch.Tensor) -> int:
+        if idx.dtype != torch.int32 or idx.dim() != 1:
+            raise HelmError(f"receiver indices must be a 1-D int32 tensor, got {idx.dtype} {list(idx.shape)}")
+        return _ptr(idx)
+
+    def _interior(self, t: torch.Tensor, name: str = "map") -> int:
+        shp = (self.info.n,) * self.dim
+        if t.dtype != torch.float32 or tuple(t.shape) != shp:
+            raise HelmError(f"{name} must be float32 of shape {list(shp)}, got {t.dtype} {list(t.shape)}")
+        return _ptr(t)
+
     def _check(self, rc: int, what: str, soft_ok: bool = False):
         if rc == HELM_OK or (soft_ok and rc == HELM_NOT_CONVERGED):
             return
@@ -252,18 +282,22 @@ class Context:
     @staticmethod
     def _stats(st) -> SolveStats:
         return SolveStats(np.array([s.iters for s in st]), np.array([s.status for s in st]),
-                          np.array([s.rel_res_true for s in st]), np.array([s.fallbacks for s in st]))
+                          np.array([s.rel_res_true for s in st]), np.array([s.fallbacks for s in st]),
+                          float(st[0].ms) if len(st) else 0.0)
 
     # -- entry points --------------------------------------------------------
     def update_n(self, n_map: torch.Tensor):
-        self._check(self.lib.helm_update_n(self._h, _ptr(n_map.to(torch.float32).contiguous())), "helm_update_n")
+        self._check(self.lib.helm_update_n(self._h, self._interior(n_map.to(torch.float32).contiguous(), "n_map")),
+                    "helm_update_n")
+        self.medium_version += 1
 
     def plane_wave_rhs(self, dirs, with_uin: bool = False):
         dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, self.dim))
         B = dirs.shape[0]
         rhs = self.empty_fields(B)
         uin = self.empty_fields(B) if with_uin else None
-        rc = self.lib.helm_plane_wave_rhs(self._h, B, dirs.ctypes.data_as(ctypes.c_void_p), _ptr(rhs), _ptr(uin))
+        rc = self.lib.helm_plane_wave_rhs(self._h, B, dirs.ctypes.data_as(ctypes.c_void_p), self._f(rhs, B),
+                                          self._f(uin, B))
         self._check(rc, "helm_plane_wave_rhs")
         return (rhs, uin) if with_uin else rhs
 
@@ -272,14 +306,14 @@ class Context:
         x = self.empty_fields(B) if out is None else out
         st = (HelmStats * B)()
         fn = self.lib.helm_adjoint_batch if adjoint else self.lib.helm_solve_batch
-        rc = fn(self._h, B, _ptr(rhs), _ptr(x), st)
+        rc = fn(self._h, B, self._f(rhs, B, name="rhs"), self._f(x, B, name="out"), st)
         self._check(rc, "helm_adjoint_batch" if adjoint else "helm_solve_batch", soft_ok=True)
         return x, self._stats(st)
 
     def solution_lo(self, B: int) -> torch.Tensor:
         """Low part of the float-float iterate of the last solve (x = x_hi + x_lo)."""
         lo = self.empty_fields(B)
-        self._check(self.lib.helm_solution_lo(self._h, B, _ptr(lo)), "helm_solution_lo")
+        self._check(self.lib.helm_solution_lo(self._h, B, self._f(lo, B)), "helm_solution_lo")
         return lo
 
     def adjoint(self, rhs: torch.Tensor, out: torch.Tensor | None = None):
@@ -288,34 +322,41 @@ class Context:
     def grad_n(self, u_sc: torch.Tensor, lam: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
         """sum_q 2 k0^2 n Re(conj(u_in + u_sc) lam) on Omega (u_in None: u_sc is the total field)."""
         grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
-        self._check(self.lib.helm_grad_n(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(grad)),
-                    "helm_grad_n")
+        B = u_sc.shape[0]
+        self._check(self.lib.helm_grad_n(self._h, B, self._f(u_in, B, name="u_in"), self._f(u_sc, B, name="u_sc"),
+                                         self._f(lam, B, name="lam"), _ptr(grad)), "helm_grad_n")
         return grad
 
     # -- inverse problem (Sec. V, Alg. 4): unknown f = k0^2 (n^2 - n_b^2) on Omega --------------
     def update_f(self, f: torch.Tensor):
-        self._check(self.lib.helm_update_f(self._h, _ptr(f.to(torch.float32).contiguous())), "helm_update_f")
+        self._check(self.lib.helm_update_f(self._h, self._interior(f.to(torch.float32).contiguous(), "f")),
+                    "helm_update_f")
+        self.medium_version += 1
 
     def grad_f(self, u_sc: torch.Tensor, lam: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
         """sum_q Re(conj(u_in + u_sc) lam) on Omega."""
         grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
-        self._check(self.lib.helm_grad_f(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(grad)),
-                    "helm_grad_f")
+        B = u_sc.shape[0]
+        self._check(self.lib.helm_grad_f(self._h, B, self._f(u_in, B, name="u_in"), self._f(u_sc, B, name="u_sc"),
+                                         self._f(lam, B, name="lam"), _ptr(grad)), "helm_grad_f")
         return grad
 
     def data_residual(self, idx: torch.Tensor, u: torch.Tensor, y: torch.Tensor):
         """(S u - y, 1/2 ||S u - y||^2)."""
+        B, M = u.shape[0], idx.numel()
+        y = y.contiguous()
+        if y.dtype != torch.complex64 or tuple(y.shape) != (B, M):
+            raise HelmError(f"data must be complex64 [{B}, {M}], got {y.dtype} {list(y.shape)}")
         res = torch.empty_like(y)
         loss = ctypes.c_double()
-        self._check(self.lib.helm_data_residual(self._h, u.shape[0], idx.numel(), _ptr(idx), _ptr(u),
-                                                _ptr(y.contiguous()), _ptr(res), ctypes.byref(loss)),
-                    "helm_data_residual")
+        self._check(self.lib.helm_data_residual(self._h, B, M, self._idx(idx), self._f(u, B, name="u"), _ptr(y),
+                                                _ptr(res), ctypes.byref(loss)), "helm_data_residual")
         return res, loss.value
 
     def tv_prox(self, v: torch.Tensor, lam: float, lo: float = 0.0, iters: int = 100) -> torch.Tensor:
         v = v.to(torch.float32).contiguous()
         w = torch.empty_like(v)
-        self._check(self.lib.helm_tv_prox(self._h, _ptr(v), float(lam), float(lo), int(iters), _ptr(w)),
+        self._check(self.lib.helm_tv_prox(self._h, self._interior(v, "v"), float(lam), float(lo), int(iters), _ptr(w)),
                     "helm_tv_prox")
         return w
 
@@ -323,7 +364,8 @@ class Context:
                  alpha: float, lo: float = 0.0, prox_iters: int = 100) -> float:
         """One update of Alg. 4 in place on f and fbar; returns the next alpha."""
         a = ctypes.c_double(alpha)
-        self._check(self.lib.helm_fbs_step(self._h, _ptr(f), _ptr(fbar), _ptr(grad.contiguous()), float(gamma),
+        self._check(self.lib.helm_fbs_step(self._h, self._interior(f, "f"), self._interior(fbar, "fbar"),
+                                           self._interior(grad.contiguous(), "grad"), float(gamma),
                                            float(tau), float(lo), int(prox_iters), ctypes.byref(a)), "helm_fbs_step")
         return a.value
 
@@ -337,7 +379,8 @@ class Context:
 
     def farfield(self, u_sc: torch.Tensor, u_in: torch.Tensor | None = None) -> torch.Tensor:
         y = torch.empty((u_sc.shape[0], self.n_sensors), dtype=torch.complex64, device=self.device)
-        self._check(self.lib.helm_farfield(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(y)), "helm_farfield")
+        B = u_sc.shape[0]
+        self._check(self.lib.helm_farfield(self._h, B, self._f(u_in, B), self._f(u_sc, B), _ptr(y)), "helm_farfield")
         return y
 
     def farfield_residual(self, u_sc: torch.Tensor, y_meas: torch.Tensor, u_in: torch.Tensor | None = None):
@@ -346,7 +389,10 @@ class Context:
         y = torch.empty((B, self.n_sensors), dtype=torch.complex64, device=self.device)
         res = torch.empty_like(y)
         loss = ctypes.c_double()
-        self._check(self.lib.helm_farfield_residual(self._h, B, _ptr(u_in), _ptr(u_sc), _ptr(y_meas.contiguous()),
+        y_meas = y_meas.contiguous()
+        if y_meas.dtype != torch.complex64 or tuple(y_meas.shape) != (B, self.n_sensors):
+            raise HelmError(f"measurements must be complex64 [{B}, {self.n_sensors}]")
+        self._check(self.lib.helm_farfield_residual(self._h, B, self._f(u_in, B), self._f(u_sc, B), _ptr(y_meas),
                                                     _ptr(y), _ptr(res), ctypes.byref(loss)), "helm_farfield_residual")
         return y, res, loss.value
 
@@ -361,21 +407,25 @@ class Context:
     def grad_f_farfield(self, u_sc: torch.Tensor, lam: torch.Tensor, s: torch.Tensor,
                         u_in: torch.Tensor | None = None) -> torch.Tensor:
         grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device)
-        self._check(self.lib.helm_grad_f_farfield(self._h, u_sc.shape[0], _ptr(u_in), _ptr(u_sc), _ptr(lam), _ptr(s),
-                                                  _ptr(grad)), "helm_grad_f_farfield")
+        B = u_sc.shape[0]
+        self._check(self.lib.helm_grad_f_farfield(self._h, B, self._f(u_in, B), self._f(u_sc, B), self._f(lam, B),
+                                                  self._f(s, B), _ptr(grad)), "helm_grad_f_farfield")
         return grad
 
     def sample(self, idx: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
         """S u: values at receiver flat indices idx (int32 on the GPU) -> [B, M]."""
         y = torch.empty((u.shape[0], idx.numel()), dtype=torch.complex64, device=self.device)
-        self._check(self.lib.helm_sample(self._h, u.shape[0], idx.numel(), _ptr(idx), _ptr(u), _ptr(y)),
-                    "helm_sample")
+        self._check(self.lib.helm_sample(self._h, u.shape[0], idx.numel(), self._idx(idx), self._f(u, name="u"),
+                                         _ptr(y)), "helm_sample")
         return y
 
     def sample_adjoint(self, idx: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         """S^T y on the extended grid."""
         u = self.empty_fields(y.shape[0])
-        self._check(self.lib.helm_sample_adjoint(self._h, y.shape[0], idx.numel(), _ptr(idx), _ptr(y), _ptr(u)),
+        y = y.contiguous()
+        if y.dtype != torch.complex64 or tuple(y.shape) != (y.shape[0], idx.numel()):
+            raise HelmError(f"receiver values must be complex64 [B, {idx.numel()}], got {y.dtype} {list(y.shape)}")
+        self._check(self.lib.helm_sample_adjoint(self._h, y.shape[0], idx.numel(), self._idx(idx), _ptr(y), _ptr(u)),
                     "helm_sample_adjoint")
         return u
 
@@ -384,43 +434,50 @@ class Context:
         n_map = n_map.to(torch.float32).contiguous()
         grad = torch.empty_like(n_map)
         val = ctypes.c_double()
-        self._check(self.lib.helm_tv(self._h, _ptr(n_map), eps, scale, _ptr(grad), ctypes.byref(val)), "helm_tv")
+        self._check(self.lib.helm_tv(self._h, self._interior(n_map, "n_map"), eps, scale, _ptr(grad),
+                                     ctypes.byref(val)), "helm_tv")
         return val.value, grad
 
     def apply_A(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)
-        self._check(self.lib.helm_apply_A(self._h, x.shape[0], _ptr(x), _ptr(y)), "helm_apply_A")
+        self._check(self.lib.helm_apply_A(self._h, x.shape[0], self._f(x, name="x"), _ptr(y)), "helm_apply_A")
         return y
 
     def residual(self, rhs: torch.Tensor, x_hi: torch.Tensor, x_lo: torch.Tensor | None = None) -> torch.Tensor:
+        B = rhs.shape[0]
         r = torch.empty_like(rhs)
-        self._check(self.lib.helm_residual(self._h, rhs.shape[0], _ptr(rhs), _ptr(x_hi), _ptr(x_lo), _ptr(r)),
-                    "helm_residual")
+        self._check(self.lib.helm_residual(self._h, B, self._f(rhs, B, name="rhs"), self._f(x_hi, B, name="x_hi"),
+                                           self._f(x_lo, B, name="x_lo"), _ptr(r)), "helm_residual")
         return r
 
     def apply_K(self, level: int, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)
-        self._check(self.lib.helm_apply_K(self._h, level, x.shape[0], _ptr(x), _ptr(y)), "helm_apply_K")
+        self._check(self.lib.helm_apply_K(self._h, level, x.shape[0], self._f(x, level=level, name="x"), _ptr(y)),
+                    "helm_apply_K")
         return y
 
     def restrict(self, level: int, fine: torch.Tensor) -> torch.Tensor:
         coarse = self.empty_fields(fine.shape[0], level + 1)
-        self._check(self.lib.helm_restrict(self._h, level, fine.shape[0], _ptr(fine), _ptr(coarse)), "helm_restrict")
+        self._check(self.lib.helm_restrict(self._h, level, fine.shape[0], self._f(fine, level=level, name="fine"),
+                                           _ptr(coarse)), "helm_restrict")
         return coarse
 
     def prolong_add(self, level: int, coarse: torch.Tensor, fine: torch.Tensor) -> torch.Tensor:
-        self._check(self.lib.helm_prolong_add(self._h, level, coarse.shape[0], _ptr(coarse), _ptr(fine)),
-                    "helm_prolong_add")
+        B = coarse.shape[0]
+        self._check(self.lib.helm_prolong_add(self._h, level, B, self._f(coarse, B, level + 1, "coarse"),
+                                              self._f(fine, B, level, "fine")), "helm_prolong_add")
         return fine
 
     def coarse_solve(self, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty_like(r)
-        self._check(self.lib.helm_coarse_solve(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_coarse_solve")
+        self._check(self.lib.helm_coarse_solve(self._h, r.shape[0], self._f(r, level=self.levels - 1, name="r"),
+                                               _ptr(z)), "helm_coarse_solve")
         return z
 
     def precondition(self, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty_like(r)
-        self._check(self.lib.helm_precondition(self._h, r.shape[0], _ptr(r), _ptr(z)), "helm_precondition")
+        self._check(self.lib.helm_precondition(self._h, r.shape[0], self._f(r, name="r"), _ptr(z)),
+                    "helm_precondition")
         return z
 
     NET_MODES = {"replace": 0, "then_mg": 1}
@@ -444,8 +501,8 @@ class Context:
         snaps = torch.empty((max_snaps, B, *self.grid_shape()), dtype=torch.complex64, device=self.device)
         st = (HelmStats * B)()
         ns = ctypes.c_int()
-        rc = self.lib.helm_solve_snapshots(self._h, B, _ptr(rhs), _ptr(x), st, every_cycles, max_snaps, _ptr(snaps),
-                                           ctypes.byref(ns))
+        rc = self.lib.helm_solve_snapshots(self._h, B, self._f(rhs, B, name="rhs"), _ptr(x), st, every_cycles,
+                                           max_snaps, _ptr(snaps), ctypes.byref(ns))
         self._check(rc, "helm_solve_snapshots", soft_ok=True)
         return x, self._stats(st), snaps[: ns.value]
 
@@ -456,10 +513,26 @@ class Context:
         n = crops.shape[0]
         feat = torch.empty((n, size, size, 4), dtype=torch.float32, device=self.device)
         tgt = torch.empty((n, size, size, 2), dtype=torch.float32, device=self.device)
-        rc = self.lib.helm_net_examples(self._h, r.shape[0], _ptr(r), _ptr(x_final), _ptr(x_k), n,
+        B = r.shape[0]
+        rc = self.lib.helm_net_examples(self._h, B, self._f(r, B), self._f(x_final, B), self._f(x_k, B), n,
                                         crops.ctypes.data_as(ctypes.c_void_p), size, gamma, _ptr(feat), _ptr(tgt))
         self._check(rc, "helm_net_examples")
         return feat, tgt
+
+    def examples_rms(self, t: torch.Tensor) -> float:
+        """Root mean square of a float32 tensor (FP64 sum in the library)."""
+        if t.dtype != torch.float32:
+            raise HelmError("examples_rms takes float32")
+        v = ctypes.c_double()
+        self._check(self.lib.helm_examples_rms(self._h, _ptr(t), t.numel(), ctypes.byref(v)), "helm_examples_rms")
+        return v.value
+
+    def examples_scale(self, t: torch.Tensor, factor: float) -> torch.Tensor:
+        """t *= factor in place (float32), in the library."""
+        if t.dtype != torch.float32:
+            raise HelmError("examples_scale takes float32")
+        self._check(self.lib.helm_examples_scale(self._h, _ptr(t), t.numel(), float(factor)), "helm_examples_scale")
+        return t
 
     def autotune(self, B: int, cache: str | None = None) -> dict:
         """Time the multigrid launch shapes for B right-hand sides and keep the fastest
@@ -558,18 +631,40 @@ class Net:
     def grads(self) -> dict:
         return self._get(self.lib.helm_net_get_grad)
 
+    @staticmethod
+    def _input(x: torch.Tensor) -> torch.Tensor:
+        x = x.contiguous()
+        if x.dtype != torch.float32 or x.dim() != 4 or x.shape[3] != 4:
+            raise HelmError(f"network inputs must be float32 [n, H, W, 4], got {x.dtype} {list(x.shape)}")
+        return x
+
     def forward(self, x: torch.Tensor) -> torch.Tensor:
+        x = self._input(x)
         n, h, w, _ = x.shape
         y = torch.empty((n, h, w, 2), dtype=torch.float32, device=x.device)
         self._check(self.lib.helm_net_forward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(y)), "helm_net_forward")
         return y
 
     def backward(self, x: torch.Tensor, target: torch.Tensor) -> float:
+        x = self._input(x)
         n, h, w, _ = x.shape
+        if target.dtype != torch.float32 or tuple(target.shape) != (n, h, w, 2):
+            raise HelmError(f"targets must be float32 [{n}, {h}, {w}, 2], got {target.dtype} {list(target.shape)}")
         loss = ctypes.c_double()
         self._check(self.lib.helm_net_backward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(target.contiguous()),
                                                ctypes.byref(loss)), "helm_net_backward")
         return loss.value
+
+    def residual_ratio(self, x: torch.Tensor, gamma: float, cb: float) -> np.ndarray:
+        """Per example ||r - gamma A' net(x)|| / ||r|| over the image interior (library kernel)."""
+        x = x.contiguous()
+        if x.dtype != torch.float32 or x.dim() != 4 or x.shape[3] != 4:
+            raise HelmError("network inputs must be float32 [n, H, W, 4]")
+        n, h, w, _ = x.shape
+        out = np.zeros(n, dtype=np.float64)
+        self._check(self.lib.helm_net_residual_ratio(self._h, n, h, w, _ptr(x), float(gamma), float(cb),
+                                                     out.ctypes.data_as(ctypes.c_void_p)), "helm_net_residual_ratio")
+        return out
 
     def set_loss(self, err_weight: float = 1.0, res_weight: float = 0.0, gamma: float = 1.0, cb: float = 1.0):
         """Training loss weights: error term and residual term |r - gamma A' y|^2 (cb = (k_b h)^2)."""

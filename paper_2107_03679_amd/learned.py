@@ -56,14 +56,21 @@ def collect(ctx: helm.Context, rhs_batches, size: int, crops_per_snapshot: int, 
             tgts.append(t)
         del snaps
     feat = torch.cat(feats) if out is None else torch.cat([out.feat] + feats)
-    tgt = torch.cat(tgts) if out is None else torch.cat([out.tgt * out.gamma] + tgts)
+    tgt = torch.cat(tgts) if out is None else torch.cat([ctx.examples_scale(out.tgt, out.gamma)] + tgts)
     keep = torch.isfinite(feat).flatten(1).all(1) & torch.isfinite(tgt).flatten(1).all(1)
     feat, tgt = feat[keep].contiguous(), tgt[keep].contiguous()
-    gamma = float(tgt.square().mean().sqrt())
-    tgt /= gamma
+    gamma = ctx.examples_rms(tgt)
+    ctx.examples_scale(tgt, 1.0 / gamma)
     prev = out.solve_iters if out is not None else []
     cb = (ctx.info.k0 * ctx.info.n_b * ctx.info.h) ** 2
     return Examples(feat, tgt, gamma, cb, prev + iters)
+
+
+def rescaled(ctx: helm.Context, ex: Examples, gamma: float) -> Examples:
+    """The examples with targets expressed for another scale gamma (targets times ex.gamma / gamma, in
+    place, by the library), e.g. a validation set for a network trained at the training set's gamma."""
+    ctx.examples_scale(ex.tgt, ex.gamma / gamma)
+    return Examples(ex.feat, ex.tgt, gamma, ex.cb, ex.solve_iters)
 
 
 def _augment(x: torch.Tensor, y: torch.Tensor, k: int):
@@ -136,28 +143,7 @@ def train(net: helm.Net, ex: Examples, steps: int, batch: int, lr: float, seed: 
     return TrainLog(losses, time.perf_counter() - t0, steps, batch * S * S)
 
 
-def validation_loss(net: helm.Net, ex: Examples, batch: int = 64) -> float:
-    """Mean of 1/2 sum (y - t)^2 per example over `ex` (forward only)."""
-    tot, n = 0.0, ex.feat.shape[0]
-    for i in range(0, n, batch):
-        y = net.forward(ex.feat[i:i + batch].contiguous())
-        tot += 0.5 * float((y - ex.tgt[i:i + batch]).square().sum())
-    return tot / n
-
-
 def residual_ratio(ctx: helm.Context, net: helm.Net, ex: Examples, count: int = 64) -> float:
-    """Median over examples of ||r - gamma A' net(r)|| / ||r|| on crop interiors (1 = no better than zero)."""
-    feat = ex.feat[:count].contiguous()
-    y = net.forward(feat)
-    f = feat.double()
-    r = torch.complex(f[..., 0], f[..., 1])
-    c = ex.cb * (1 + torch.complex(f[..., 2], f[..., 3]))
-    yc = torch.complex(y[..., 0].double(), y[..., 1].double()) * ex.gamma
-    ay = (4 - c) * yc
-    ay[:, 1:] -= yc[:, :-1]
-    ay[:, :-1] -= yc[:, 1:]
-    ay[:, :, 1:] -= yc[:, :, :-1]
-    ay[:, :, :-1] -= yc[:, :, 1:]
-    q = (r - ay)[:, 1:-1, 1:-1]
-    ratio = q.abs().square().sum((1, 2)).sqrt() / r[:, 1:-1, 1:-1].abs().square().sum((1, 2)).sqrt()
-    return float(ratio.median())
+    """Median over examples of ||r - gamma A' net(r)|| / ||r|| on crop interiors (1 = no better than zero);
+    the ratios come from the library's kernel."""
+    return float(np.median(net.residual_ratio(ex.feat[:count], ex.gamma, ex.cb)))

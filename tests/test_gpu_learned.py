@@ -191,7 +191,7 @@ def test_trained_network_gain():
     ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device="cuda"))
     rhs = ctx.plane_wave_rhs(synth.directions_2d(B))
     val = train_lib.collect(ctx, [rhs], size=64, crops_per_snapshot=2, every_cycles=4, max_snaps=4, seed=5)
-    val = train_lib.Examples(val.feat, val.tgt * val.gamma / ex.gamma, ex.gamma, ex.cb)
+    val = train_lib.rescaled(ctx, val, ex.gamma)
     net = train_lib.new_network(4)
     train_lib.train(net, ex, steps=800, batch=16, lr=1e-4, seed=6, err_weight=0.0, res_weight=1.0)
     ratio = train_lib.residual_ratio(ctx, net, val)

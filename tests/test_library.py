@@ -48,3 +48,46 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_binding_checks_dtypes_and_shapes_before_calling():
+    # the binding refuses tensors the library would misread (wrong dtype, shape or device), on the CPU
+    import torch
+
+    from paper_2107_03679_amd import helm
+
+    ctx = object.__new__(helm.Context)  # no device context: only the argument checks run
+    ctx.dim, ctx.n_e, ctx.levels = 2, 21, 3
+    ctx.info = helm.HelmInfo()
+    ctx.info.n = 12
+    ok = torch.zeros((2, 21, 21), dtype=torch.complex64)
+    with pytest.raises(helm.HelmError, match="GPU"):
+        ctx._f(ok, 2)  # right dtype and shape, but host memory
+    with pytest.raises(helm.HelmError, match="complex64"):
+        ctx._f(ok.to(torch.complex128), 2)
+    with pytest.raises(helm.HelmError, match="shape"):
+        ctx._f(ok[:, :20, :].contiguous(), 2)
+    with pytest.raises(helm.HelmError, match="shape"):
+        ctx._f(ok, 3)
+    with pytest.raises(helm.HelmError, match="shape"):
+        ctx._f(torch.zeros((2, 11, 11), dtype=torch.complex64), 2, level=0)
+    with pytest.raises(helm.HelmError, match="int32"):
+        ctx._idx(torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(helm.HelmError, match="float32"):
+        ctx._interior(torch.zeros((12, 12), dtype=torch.float64))
+    with pytest.raises(helm.HelmError, match="float32"):
+        ctx._interior(torch.zeros((13, 12), dtype=torch.float32))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
+def test_null_arguments_return_einval_without_a_device():
+    # argument errors are reported before any HIP call
+    from paper_2107_03679_amd import helm
+
+    lib = helm.load_library()
+    assert lib.helm_sample(None, 1, 1, None, None, None) == -1
+    assert lib.helm_sample_adjoint(None, 1, 1, None, None, None) == -1
+    assert lib.helm_data_residual(None, 1, 1, None, None, None, None, None) == -1
+    assert lib.helm_examples_rms(None, None, 1, None) == -1
+    assert lib.helm_net_residual_ratio(None, 1, 8, 8, None, 1.0, 1.0, None) == -1
