@@ -47,7 +47,16 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="keep the default multigrid launch shapes")
     p.add_argument("--tune-cache", default=None, help="JSON-lines cache of the autotuner's choices")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="length of each bounded oracle run of the CPU baseline (one thread; one per core)")
+    p.add_argument("--no-c1", action="store_true", help="skip the disk128 CPU timing (set-up and solve, median of 5)")
+    p.add_argument("--kappa-im", type=float, default=0.5, help="imaginary part of the shift kappa (real part 1)")
+    p.add_argument("--omega", type=float, default=0.8, help="damped-Jacobi factor")
+    p.add_argument("--no-vcycle-leg", action="store_true",
+                   help="skip the same workload with the paper's V-cycle (Alg. 2, CycleType 1)")
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the benchmark line: solves/s and cycles per solve over the shift, the cycle "
+                        "type, the smoothing steps and factor, and the level count (one JSON line per setting)")
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
@@ -103,9 +112,103 @@ def copy_probe(mib):
     return {"bytes_per_copy": 2 * 4 * n, "ms": ms, "GB/s": 2 * 4 * n / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
-    """FP64 oracle MG-FGMRES on the host: time a bounded number of iterations on one
-    right-hand side, scale to the GPU's measured iterations per solve."""
+def host_cpu():
+    """(CPU model, usable host cores) of the machine running the benchmark."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta_deg=0.0):
+    """Seconds per MG-FGMRES iteration of the FP64 oracle on one right-hand side (one host thread):
+    a bounded run of about budget_s seconds."""
+    from threadpoolctl import threadpool_limits
+
+    import numpy as np
+
+    from oracle.discretization import Problem, helmholtz_matrix
+    from oracle.krylov import fgmres
+    from oracle.model import rhs
+    from oracle.multigrid import Hierarchy
+
+    with threadpool_limits(1):
+        prob = Problem(nmap, k0h=KBH / N_B, w=20, levels=levels, beta=0.15)
+        hier = Hierarchy(prob)
+        a = helmholtz_matrix(prob)
+        th = np.radians(theta_deg)
+        b = (prob.h ** 2 * rhs(prob, (np.sin(th), np.cos(th)))).ravel()
+        ct = [2] + [1] * (levels - 2) if cycle == 3 else cycle
+        pc = (lambda r: hier.cycle(r, None, 0, ct))
+        t0 = time.perf_counter()
+        fgmres(lambda v: a @ v, pc, b, rtol=1e-30, restart=restart, max_iters=2)
+        per_iter = (time.perf_counter() - t0) / 2
+        k = int(max(2, min(400, budget_s / max(per_iter, 1e-6))))
+        t0 = time.perf_counter()
+        _, info = fgmres(lambda v: a @ v, pc, b, rtol=1e-30, restart=restart, max_iters=k)
+        el = time.perf_counter() - t0
+    return el / info.iters, info.iters, el
+
+
+def _rate_worker(job):
+    nmap, levels, restart, cycle, budget_s, theta = job
+    return _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta)
+
+
+def cpu_rates(nmap, levels, restart, cycle, budget_s):
+    """The FP64 oracle's iteration rate on the host, before the GPU is touched (the all-cores leg
+    forks worker processes): one thread on one right-hand side, and one process per usable core,
+    each on its own right-hand side (angles spread over [-60, 60] degrees)."""
+    import multiprocessing as mp
+
+    model, cores = host_cpu()
+    one = _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s)
+    thetas = [(-60.0 + 120.0 * q / max(1, cores - 1)) for q in range(cores)]
+    jobs = [(nmap, levels, restart, cycle, budget_s, th) for th in thetas]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_rate_worker, jobs)
+    wall = time.perf_counter() - t0
+    iters_all = sum(r[1] for r in res)
+    return {"model": model, "cores": cores, "one_thread_s_per_iter": one[0], "one_thread_iters": one[1],
+            "one_thread_s": one[2], "all_cores_iters": iters_all, "all_cores_wall_s": wall}
+
+
+def cpu_baseline(rates, iters_per_solve, restart):
+    """Solves/s of the FP64 oracle MG-FGMRES on all host cores (one process per core, each solving its
+    own right-hand side), from bounded runs scaled by the GPU's iterations per solve."""
+    per_solve_all = rates["all_cores_wall_s"] / rates["all_cores_iters"] * iters_per_solve
+    one = 1.0 / (rates["one_thread_s_per_iter"] * iters_per_solve)
+    return {
+        "value": 1.0 / per_solve_all,
+        "unit": "solves/s",
+        "cores": rates["cores"],
+        "kind": "oracle",
+        "cpu_model": rates["model"],
+        "one_thread_value": one,
+        "sample": (f"FP64 oracle MG-FGMRES({restart}), one process per core on {rates['cores']} cores "
+                   f"({rates['model']}), each on its own right-hand side: {rates['all_cores_iters']} iterations "
+                   f"in {rates['all_cores_wall_s']:.1f} s wall; one thread alone: {rates['one_thread_iters']} "
+                   f"iterations in {rates['one_thread_s']:.1f} s; scaled by {iters_per_solve:.0f} iterations per "
+                   f"solve (the GPU's mean at the same parameters); set-up excluded"),
+    }
+
+
+def cpu_c1_protocol(reps=5):
+    """The small CPU configuration (disk128: 128^2 interior, 20-cell layer, disk of radius 20 cells and
+    contrast 0.05, one normal-incidence plane wave, complex128 MG-FGMRES(20), 4 levels, rel. residual
+    1e-6): set-up and solve timed separately, median of `reps` after a warm-up, with one BLAS thread
+    (the paper's one-thread protocol, Sec. VI) and with all usable cores."""
     from threadpoolctl import threadpool_limits
 
     import numpy as np
@@ -116,31 +219,29 @@ def cpu_baseline(nmap, levels, restart, cycle, iters_per_solve, budget_s):
     from oracle.model import rhs
     from oracle.multigrid import Hierarchy
 
-    with threadpool_limits(1):
-        prob = Problem(nmap, k0h=KBH / N_B, w=20, levels=levels, beta=0.15)
-        hier = Hierarchy(prob)
-        a = helmholtz_matrix(prob)
-        b = (prob.h ** 2 * rhs(prob, synth.directions_2d(1, 0.0, 0.0)[0])).ravel()
-        ct = [2] + [1] * (levels - 2) if cycle == 3 else cycle
-        pc = (lambda r: hier.cycle(r, None, 0, ct))
-        t0 = time.perf_counter()
-        fgmres(lambda v: a @ v, pc, b, rtol=1e-30, restart=restart, max_iters=2)
-        per_iter = (time.perf_counter() - t0) / 2
-        k = int(max(2, min(400, budget_s / max(per_iter, 1e-6))))
-        t0 = time.perf_counter()
-        _, info = fgmres(lambda v: a @ v, pc, b, rtol=1e-30, restart=restart, max_iters=k)
-        el = time.perf_counter() - t0
-    per_iter = el / info.iters
-    sec_per_solve = per_iter * iters_per_solve
-    return {
-        "value": 1.0 / sec_per_solve,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"FP64 oracle MG-FGMRES({restart}) on 1 of the RHS (theta=0), {info.iters} iterations in "
-                   f"{el:.1f} s on 1 host thread, scaled by {iters_per_solve:.0f} iterations per solve "
-                   f"(the GPU's mean at the same parameters); set-up excluded"),
-    }
+    model, cores = host_cpu()
+    nmap = synth.workload_medium("disk128")
+    out = {"workload": "disk128", "cpu_model": model, "repetitions": reps}
+    for label, nth in (("one_thread", 1), ("all_cores", cores)):
+        with threadpool_limits(nth):
+            ts, tv, its = [], [], []
+            for rep in range(reps + 1):
+                t0 = time.perf_counter()
+                prob = Problem(nmap, k0h=KBH / N_B, w=20, levels=4, beta=0.15)
+                hier = Hierarchy(prob)
+                a = helmholtz_matrix(prob)
+                b = (prob.h ** 2 * rhs(prob, (0.0, 1.0))).ravel()
+                t1 = time.perf_counter()
+                _, info = fgmres(lambda v: a @ v, hier.vcycle, b, rtol=1e-6, restart=20, max_iters=2000)
+                t2 = time.perf_counter()
+                if rep:  # the first pass warms up
+                    ts.append(t1 - t0)
+                    tv.append(t2 - t1)
+                    its.append(info.iters)
+        out[label] = {"threads": nth, "setup_s_median": float(np.median(ts)), "solve_s_median": float(np.median(tv)),
+                      "iterations": int(its[-1]), "converged": bool(info.converged),
+                      "rel_res_true": float(info.rel_res_true)}
+    return out
 
 
 def gradient_leg(ctx, dirs, nmap, reps=3):
@@ -257,25 +358,40 @@ def main():
                                    "axis and multi-GPU runs are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
-    import torch
 
     import synth
-    from paper_2107_03679_amd import helm
 
     wl = synth.WORKLOADS[args.workload]
     nmap = synth.workload_medium(args.workload).astype(np.float32).astype(np.float64)
     dirs = synth.workload_directions(args.workload, args.rhs)
     B = dirs.shape[0]
+    if args.sweep:
+        return sweep(args, wl, nmap, dirs)
+    # host legs first: the all-cores leg forks worker processes, which must happen before the GPU is used
+    rates = c1 = None
+    if not args.no_cpu_baseline and wl["d"] == 2:
+        rates = cpu_rates(nmap, args.levels, args.restart, args.cycle, args.cpu_seconds)
+        if not args.no_c1:
+            c1 = cpu_c1_protocol()
+    import torch
+
+    from paper_2107_03679_amd import helm
+
     w = 20
     ne = helm.extended_size(wl["n"], w, args.levels)
     k0 = (KBH / N_B) * (ne - 1)
     dev = torch.device("cuda:0")
+
+    def make_ctx(cycle):
+        return helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
+                            levels=args.levels, restart=args.restart, cycle=cycle, reorth=args.reorth, max_batch=B,
+                            max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=args.fused_step,
+                            kappa=complex(1.0, args.kappa_im), omega_jac=args.omega,
+                            krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
+                                    "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
+
     t_setup = time.perf_counter()
-    ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
-                       levels=args.levels, restart=args.restart, cycle=args.cycle, reorth=args.reorth, max_batch=B,
-                       max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=args.fused_step,
-                       krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
-                               "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
+    ctx = make_ctx(args.cycle)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     tune = None
@@ -322,7 +438,8 @@ def main():
         "config": {
             "workload": args.workload, "interior": wl["n"], "grid": ne, "rhs": B, "levels": args.levels,
             "coarsest": ctx.info.coarsest_n, "restart": args.restart, "cycle": {1: "V", 2: "W", 3: "W at the finest level, V below"}[args.cycle],
-            "kappa": "1+0.5j", "nu": [1, 1], "omega_jac": 0.8, "rtol": 1e-6, "preconditioner": "multigrid",
+            "kappa": f"1+{args.kappa_im:g}j", "nu": [1, 1], "omega_jac": args.omega, "rtol": 1e-6,
+            "preconditioner": "multigrid",
             "krylov": {"sstep": f"GMRES({args.restart}), s-step form (Gram + Cholesky QR)",
                        "fgmres": f"FGMRES({args.restart})" + (", CGS2" if args.reorth else ", CGS1"),
                        "bicgstab": "Bi-CGSTAB (Alg. 3)"}[args.krylov],
@@ -364,15 +481,88 @@ def main():
             k: {"ms": round(v[0], 3), "launches": v[1], "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0}
             for k, v in sorted(rep.items(), key=lambda kv: -kv[1][0])
         }
+    # the per-evaluation view of the inverse problem: a new medium (helm_update_n) before every batch
+    t_upd = []
+    nmap_t = torch.tensor(nmap, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, min(args.steps, 5))):
+        t1 = time.perf_counter()
+        ctx.update_n(nmap_t)
+        torch.cuda.synchronize()
+        t_upd.append(time.perf_counter() - t1)
+        st_u = step()
+    torch.cuda.synchronize()
+    el_u = (time.perf_counter() - t0) / len(t_upd)
+    out["with_update_n"] = {"value": B / el_u, "unit": "solves/s", "update_n_ms": 1e3 * float(np.median(t_upd)),
+                            "all_converged": bool(st_u.converged),
+                            "note": "helm_update_n (medium set-up on the GPU, coarsest inverse on the host) + "
+                                    "right-hand sides + batched solve, per step"}
     if args.workload == "inverse256x32":
         out["gradient"] = gradient_leg(ctx, dirs, nmap)
     if not args.no_learned and wl["d"] == 2:
         out["learned"] = learned_leg(ctx, args, wl, nmap, dirs, float(iters.mean()), value)
     ctx.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nmap, args.levels, args.restart, args.cycle, float(iters.mean()),
-                                           args.cpu_seconds)
+    if not args.no_vcycle_leg and args.cycle != 1:
+        # the paper's cycle (Alg. 2, CycleType 1: one V-cycle per preconditioner application)
+        vctx = make_ctx(1)
+        if not args.no_tune:
+            vctx.autotune(B, cache=args.tune_cache)
+        xv = vctx.empty_fields(B)
+        vctx.solve(vctx.plane_wave_rhs(dirs), out=xv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, min(args.steps, 5))):
+            _, st_v = vctx.solve(vctx.plane_wave_rhs(dirs), out=xv)
+        torch.cuda.synchronize()
+        el_v = (time.perf_counter() - t0) / max(1, min(args.steps, 5))
+        out["vcycle"] = {"value": B / el_v, "unit": "solves/s", "iters_mean": float(st_v.iters.mean()),
+                         "iters_max": int(st_v.iters.max()), "all_converged": bool(st_v.converged),
+                         "rel_res_true_max": float(st_v.rel_res_true.max())}
+        vctx.close()
+    if rates is not None:
+        out["cpu_baseline"] = cpu_baseline(rates, float(iters.mean()), args.restart)
+    if c1 is not None:
+        out["cpu_c1"] = c1
     print(json.dumps(out), flush=True)
+
+
+def sweep(args, wl, nmap, dirs):
+    """Solves/s, cycles per solve and the certified residual over the preconditioner's settings on one
+    workload (same batch, autotuned shapes per setting); one JSON line per setting."""
+    import numpy as np
+    import torch
+
+    from paper_2107_03679_amd import helm
+
+    B = dirs.shape[0]
+    grid = [dict(kim=k) for k in (0.2, 0.3, 0.35, 0.4, 0.5, 0.6, 0.7)]
+    grid += [dict(kim=k, om=o) for k in (0.3, 0.35, 0.4) for o in (0.85, 0.9, 0.95)]
+    grid += [dict(cycle=c, kim=k) for c in (1, 2) for k in (0.35, 0.5)]
+    grid += [dict(nu=2, kim=k) for k in (0.35, 0.5)]
+    grid += [dict(levels=L, kim=k) for L in (5, 6) for k in (0.35, 0.5)]
+    for g in grid:
+        L, cyc, nu = g.get("levels", args.levels), g.get("cycle", args.cycle), g.get("nu", 1)
+        ne = helm.extended_size(wl["n"], 20, L)
+        k0 = (KBH / N_B) * (ne - 1)
+        ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device="cuda:0"), k0, abl_width=20,
+                           beta=wl["beta"], levels=L, restart=args.restart, cycle=cyc, max_batch=B,
+                           max_iters=args.max_iters, kappa=complex(1.0, g["kim"]), omega_jac=g.get("om", 0.8),
+                           nu1=nu, nu2=nu)
+        ctx.autotune(B)
+        x = ctx.empty_fields(B)
+        ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.close()
+        print(json.dumps({"workload": args.workload, "levels": L, "cycle": cyc, "nu": nu, "kappa": [1.0, g["kim"]],
+                          "omega_jac": g.get("om", 0.8), "restart": args.restart, "solves_per_s": B / el,
+                          "iters_mean": float(st.iters.mean()), "iters_max": int(st.iters.max()),
+                          "all_converged": bool(st.converged), "rel_res_true_max": float(st.rel_res_true.max())}),
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -281,6 +281,19 @@ int helm_update_f(helm_ctx* ctx, const float* f_dev);
 int helm_grad_f(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
                 float* grad_f);
 
+/* Several frequencies (the paper's experimental reconstructions use four, Sec. VI-C) share
+ * one frequency-independent unknown, the contrast chi = eta^2 - eta_b^2 on Omega, with
+ * f = k0^2 chi in the context of each frequency (its own k0).
+ * helm_update_contrast: medium eta = sqrt(eta_b^2 + chi) (0 where the radicand is
+ * negative), then exactly helm_update_n.  chi: device float [n^dim]. */
+int helm_update_contrast(helm_ctx* ctx, const float* chi_dev);
+/* Data-fidelity gradient with respect to chi through Prop. 1 and df/dchi = k0^2:
+ *   g[i] = k0^2 sum_q Re(conj(u_q,i) lam_q,i) on Omega,
+ * written to grad (accumulate = 0) or added to it (accumulate = 1), so that the contexts
+ * of several frequencies sum their gradients in one buffer; arguments as helm_grad_f. */
+int helm_grad_contrast(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                       int accumulate, float* grad);
+
 /* Residual of the quadratic data term (eq. DataFidelityExplicit) at M on-grid
  * receivers: res[q][i] = u[q][idx[i]] - y[q][i] for q < B (u: device [B][grid],
  * y, res: device [B][M]); *loss_host = 1/2 sum |res|^2 (FP64) when non-NULL.

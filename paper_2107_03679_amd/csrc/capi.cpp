@@ -28,8 +28,9 @@ thread_local std::string g_setup_error;
 struct Level {
   int n = 0;
   long long N = 0;
-  c32* kc = nullptr;  // kappa * c_l
-  c32* wd = nullptr;  // omega / diag(K_kappa,l)
+  c32* kc = nullptr;    // kappa * c_l
+  c32* kclo = nullptr;  // low part of kappa * c_l as float-float (the set-up's coarse chain)
+  c32* wd = nullptr;    // omega / diag(K_kappa,l)
   c32 ghost{};
   c32* rc = nullptr;  // [maxB][N] right-hand side (levels >= 1)
   c32* e = nullptr;   // [maxB][N] solution (levels >= 1)
@@ -746,11 +747,13 @@ void upload_static(helm_ctx* c) {
   std::vector<cd> cl = cf;
   for (int l = 0; l < c->L; ++l) {
     if (l > 0) cl = helm_host::coarse_coefficient(g, cl, c->lv[l - 1].n, l);
-    std::vector<c32> kc(cl.size()), wd(cl.size());
+    std::vector<c32> kc(cl.size()), kclo(cl.size()), wd(cl.size());
     const int nl = c->lv[l].n;
     const cd gl(1.0, c->kbh * std::ldexp(1.0, l));
     for (size_t p = 0; p < cl.size(); ++p) {
-      kc[p] = to_c32(kappa * cl[p]);
+      const cd v = kappa * cl[p];
+      kc[p] = to_c32(v);
+      kclo[p] = make_float2((float)(v.real() - (double)kc[p].x), (float)(v.imag() - (double)kc[p].y));
       const int x = (int)(p % nl), y = (int)((p / nl) % nl), z = c->dim == 3 ? (int)(p / ((size_t)nl * nl)) : 0;
       int ng = (x == 0) + (x == nl - 1) + (y == 0) + (y == nl - 1);
       if (c->dim == 3) ng += (z == 0) + (z == nl - 1);
@@ -758,6 +761,7 @@ void upload_static(helm_ctx* c) {
       wd[p] = to_c32(c->o.omega_jac / D);
     }
     check(hipMemcpy(c->lv[l].kc, kc.data(), kc.size() * sizeof(c32), hipMemcpyHostToDevice), "upload kc");
+    check(hipMemcpy(c->lv[l].kclo, kclo.data(), kclo.size() * sizeof(c32), hipMemcpyHostToDevice), "upload kc");
     check(hipMemcpy(c->lv[l].wd, wd.data(), wd.size() * sizeof(c32), hipMemcpyHostToDevice), "upload wd");
   }
 }
@@ -790,19 +794,22 @@ void update_medium(helm_ctx* c, const float* n_map_dev) {
   a.dhi = c->d_dhi;
   a.dlo = c->d_dlo;
   a.kc0 = c->lv[0].kc;
+  a.kc0lo = c->lv[0].kclo;
   a.wd0 = c->lv[0].wd;
   a.f = c->d_f;
   launch_setup_fine(c->s, a);
   for (int l = 1; l < c->L; ++l)
-    launch_setup_coarse(c->s, c->dim, c->lv[l - 1].n, c->lv[l].n, c->lv[l - 1].kc, (float)c->o.omega_jac, c->lv[l].kc,
-                        c->lv[l].wd);
+    launch_setup_coarse(c->s, c->dim, c->lv[l - 1].n, c->lv[l].n, c->lv[l - 1].kc, c->lv[l - 1].kclo,
+                        (float)c->o.omega_jac, c->lv[l].kc, c->lv[l].kclo, c->lv[l].wd);
   check(hipGetLastError(), "set-up kernels");
   const Level& cl = c->lv[c->L - 1];
-  std::vector<c32> kc32(cl.N);
+  std::vector<c32> kc32(cl.N), kclo32(cl.N);
   check(hipMemcpyAsync(kc32.data(), cl.kc, cl.N * sizeof(c32), hipMemcpyDeviceToHost, c->s), "coarsest kc");
+  check(hipMemcpyAsync(kclo32.data(), cl.kclo, cl.N * sizeof(c32), hipMemcpyDeviceToHost, c->s), "coarsest kc");
   check(hipStreamSynchronize(c->s), "set-up");
   std::vector<cd> kc(cl.N);
-  for (long long p = 0; p < cl.N; ++p) kc[p] = cd(kc32[p].x, kc32[p].y);
+  for (long long p = 0; p < cl.N; ++p)
+    kc[p] = cd((double)kc32[p].x + kclo32[p].x, (double)kc32[p].y + kclo32[p].y);
   std::vector<cd> inv;
   if (!helm_host::dense_inverse_transposed(c->geo, kc, cl.n, c->L - 1, inv))
     throw HipError{hipErrorInvalidValue, "coarsest operator is singular"};
@@ -1023,6 +1030,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
       L.N = npts(L.n, c->dim);
       L.ghost = make_float2(1.0f, (float)(c->kbh * std::ldexp(1.0, l)));
       L.kc = c->alloc<c32>(L.N);
+      L.kclo = c->alloc<c32>(L.N);
       L.wd = c->alloc<c32>(L.N);
       if (l > 0) {
         L.rc = c->alloc<c32>((size_t)maxB * L.N);
@@ -1531,6 +1539,34 @@ int helm_update_f(helm_ctx* c, const float* f_dev) {
     return fail(c, HELM_ENOMEM, "out of host memory");
   }
   return HELM_OK;
+}
+
+int helm_update_contrast(helm_ctx* c, const float* chi_dev) {
+  if (!c || !chi_dev) return fail(c, HELM_EINVAL, "null argument");
+  try {
+    check(hipStreamSynchronize(c->user_s), "caller stream");
+    inv_reserve(c);
+    // eta = sqrt(eta_b^2 + chi): the map of helm_update_f with k0^2 = 1
+    launch_index_from_f(c->s, npts(c->n, c->dim), chi_dev, 1.0, c->o.n_b * c->o.n_b, c->d_inv_n);
+    check(hipGetLastError(), "index_from_contrast");
+    check(hipStreamSynchronize(c->s), "sync");
+    update_medium(c, c->d_inv_n);
+  } catch (const HipError& e) {
+    return fail(c, HELM_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.code));
+  } catch (const std::bad_alloc&) {
+    return fail(c, HELM_ENOMEM, "out of host memory");
+  }
+  return HELM_OK;
+}
+
+int helm_grad_contrast(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam,
+                       int accumulate, float* grad) {
+  if (!c || !u_sc || !lam || !grad) return fail(c, HELM_EINVAL, "null argument");
+  if (B < 1) return fail(c, HELM_EINVAL, "B must be >= 1");
+  HELM_GUARD_BEGIN
+  launch_grad_n(c->s, c->dim, B, c->ne, c->w, c->n, (const c32*)u_in, (const c32*)u_sc, (const c32*)lam, nullptr,
+                (float)(c->k0 * c->k0), grad, nullptr, accumulate ? 1 : 0);
+  HELM_GUARD_END("grad_contrast")
 }
 
 int helm_grad_f(helm_ctx* c, int B, const helm_c32* u_in, const helm_c32* u_sc, const helm_c32* lam, float* grad_f) {

@@ -24,7 +24,7 @@ __global__ void k_plane_wave(int dim, int n, long long N, const float* fplane, c
 // grad[i] = scale * n_i * sum_q Re(conj(u_in,q + u_sc,q) (lam_q + lam2_q)) at interior point i
 // (n_i = 1 without nmap, lam2 = 0 when NULL)
 __global__ void k_grad_n(int dim, int B, int ne, int w, int n, const c32* uin, const c32* u, const c32* lam,
-                         const c32* lam2, const float* nmap, float scale, float* grad) {
+                         const c32* lam2, const float* nmap, float scale, int accumulate, float* grad) {
   const long long Ni = dim == 2 ? (long long)n * n : (long long)n * n * n;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Ni) return;
@@ -40,7 +40,8 @@ __global__ void k_grad_n(int dim, int B, int ne, int w, int n, const c32* uin, c
     if (lam2) l = cadd(l, lam2[(long long)b * Ne + p]);
     s = fmaf(a.x, l.x, fmaf(a.y, l.y, s));
   }
-  grad[i] = scale * (nmap ? nmap[i] : 1.0f) * s;
+  const float g = scale * (nmap ? nmap[i] : 1.0f) * s;
+  grad[i] = accumulate ? grad[i] + g : g;
 }
 
 __global__ void k_conj_copy(long long count, const c32* in, c32* out) {
@@ -66,10 +67,10 @@ void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane
   hipLaunchKernelGGL(k_plane_wave, dim3(nb(N, 256), B), dim3(256), 0, s, dim, n, N, fplane, tables, rhs, uin);
 }
 void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* uin, const c32* u,
-                   const c32* lam, const float* nmap, float scale, float* grad, const c32* lam2) {
+                   const c32* lam, const float* nmap, float scale, float* grad, const c32* lam2, int accumulate) {
   const long long Ni = dim == 2 ? (long long)n * n : (long long)n * n * n;
   hipLaunchKernelGGL(k_grad_n, dim3(nb(Ni, 256)), dim3(256), 0, s, dim, B, n_e, w, n, uin, u, lam, lam2, nmap, scale,
-                     grad);
+                     accumulate, grad);
 }
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out) {
   hipLaunchKernelGGL(k_conj_copy, dim3(nb(count, 256)), dim3(256), 0, s, count, in, out);

@@ -40,35 +40,45 @@ __global__ void k_setup_fine(SetupFineArgs a) {
   const ff df = ff_sub(eta2, ff{a.nb2_hi, a.nb2_lo});
   const ff fv = ff_mul({a.k02_hi, a.k02_lo}, df);
   a.f[p] = fv.hi;
-  // finest level of the preconditioner: kappa c and omega / (2d - kappa c - ng g0)
-  const c32 kc = cscale(a.kappa, cf);
+  // finest level of the preconditioner: kappa c (float-float, the start of the coarse chain)
+  // and omega / (2d - kappa c - ng g0)
+  const ff kre = ff_mul(c, ff_from(a.kappa.x)), kim = ff_mul(c, ff_from(a.kappa.y));
+  const c32 kc = make_float2(kre.hi, kim.hi);
   a.kc0[p] = kc;
+  a.kc0lo[p] = make_float2(kre.lo, kim.lo);
   const c32 D = make_float2((float)(2 * a.dim) - kc.x - (float)ng * a.g0.x, -kc.y - (float)ng * a.g0.y);
   a.wd0[p] = cscale(crcp(D), a.omega);
 }
 
-// interior points of level l (ring excluded): kc = 4 FW(kc of level l - 1), wd = omega / (2d - kc)
-__global__ void k_setup_coarse(int dim, int nf, int nc, const c32* kcf, float omega, c32* kcc, c32* wdc) {
+// interior points of level l (ring excluded): kc = 4 FW(kc of level l - 1), wd = omega / (2d - kc).
+// kc is carried in float-float (hi, lo planes): the weights are powers of two, so every
+// weighted term is exact and only the float-float sums round (about 2^-44), which keeps
+// the chain over the levels as accurate as an FP64 one.
+__global__ void k_setup_coarse(int dim, int nf, int nc, const c32* kcf, const c32* kcflo, float omega, c32* kcc,
+                               c32* kcclo, c32* wdc) {
   const int m = nc - 2;  // interior points per axis
   const long long Nint = dim == 2 ? (long long)m * m : (long long)m * m * m;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Nint) return;
   const int X = 1 + (int)(t % m), Y = 1 + (int)((t / m) % m), Z = dim == 3 ? 1 + (int)(t / ((long long)m * m)) : 0;
   const float w1[3] = {0.25f, 0.5f, 0.25f};
-  c32 acc = make_float2(0.f, 0.f);
+  ff are = ff_from(0.f), aim = ff_from(0.f);
   const int zr = dim == 3 ? 1 : 0;
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         const long long fx = 2 * X + dx, fy = 2 * Y + dy, fz = dim == 3 ? 2 * Z + dz : 0;
-        const float wgt = w1[dx + 1] * w1[dy + 1] * (dim == 3 ? w1[dz + 1] : 1.f);
-        const c32 v = kcf[(fz * nf + fy) * nf + fx];
-        acc.x = fmaf(wgt, v.x, acc.x);
-        acc.y = fmaf(wgt, v.y, acc.y);
+        // 4 x the full-weighting weight: a power of two, so the products below are exact
+        const float wgt = 4.f * w1[dx + 1] * w1[dy + 1] * (dim == 3 ? w1[dz + 1] : 1.f);
+        const long long i = (fz * nf + fy) * nf + fx;
+        const c32 vh = kcf[i], vl = kcflo[i];
+        are = ff_add(are, ff_add(ff_from(wgt * vh.x), ff_from(wgt * vl.x)));
+        aim = ff_add(aim, ff_add(ff_from(wgt * vh.y), ff_from(wgt * vl.y)));
       }
-  const c32 kc = cscale(acc, 4.f);
   const long long q = dim == 2 ? (long long)Y * nc + X : ((long long)Z * nc + Y) * nc + X;
+  const c32 kc = make_float2(are.hi, aim.hi);
   kcc[q] = kc;
+  kcclo[q] = make_float2(are.lo, aim.lo);
   wdc[q] = cscale(crcp(make_float2((float)(2 * dim) - kc.x, -kc.y)), omega);
 }
 
@@ -79,10 +89,11 @@ void launch_setup_fine(hipStream_t s, const SetupFineArgs& a) {
   hipLaunchKernelGGL(k_setup_fine, dim3((unsigned)((Ni + 255) / 256)), dim3(256), 0, s, a);
 }
 
-void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, float omega, c32* kcc, c32* wdc) {
+void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, const c32* kcflo, float omega,
+                         c32* kcc, c32* kcclo, c32* wdc) {
   const long long m = nc - 2;
   if (m <= 0) return;
   const long long Nint = dim == 2 ? m * m : m * m * m;
-  hipLaunchKernelGGL(k_setup_coarse, dim3((unsigned)((Nint + 255) / 256)), dim3(256), 0, s, dim, nf, nc, kcf, omega,
-                     kcc, wdc);
+  hipLaunchKernelGGL(k_setup_coarse, dim3((unsigned)((Nint + 255) / 256)), dim3(256), 0, s, dim, nf, nc, kcf, kcflo,
+                     omega, kcc, kcclo, wdc);
 }

@@ -150,7 +150,7 @@ void launch_plane_wave(hipStream_t s, int dim, int B, int n, const float* fplane
                        c32* uin);
 void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c32* uin, const c32* u,
                    const c32* lam, const float* nmap, float scale, float* grad,
-                   const c32* lam2 = nullptr);
+                   const c32* lam2 = nullptr, int accumulate = 0);
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out);
 void launch_gather(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, c32* y);
 void launch_scatter(hipStream_t s, int B, int M, long long N, const int* idx, const c32* y, c32* u);
@@ -192,13 +192,15 @@ struct SetupFineArgs {
   float nb2_hi, nb2_lo;         // eta_b^2, float-float
   c32 kappa, g0;                // shift; fine ghost factor 1 + j k_b h
   float omega;                  // damped-Jacobi factor
-  c32 *chi, *dhi, *dlo, *kc0, *wd0;
+  c32 *chi, *dhi, *dlo, *kc0, *kc0lo, *wd0;
   float* f;
 };
 // Omega points of the fine level: c, float-float diagonal of A', f, kappa c, omega / diag(K_0)
 void launch_setup_fine(hipStream_t s, const SetupFineArgs& a);
-// interior points of a coarse level (nc per axis) from the finer level's kappa c (nf per axis)
-void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, float omega, c32* kcc, c32* wdc);
+// interior points of a coarse level (nc per axis) from the finer level's kappa c (nf per axis),
+// kappa c carried as float-float (hi, lo planes)
+void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, const c32* kcflo, float omega,
+                         c32* kcc, c32* kcclo, c32* wdc);
 
 // FP32 vector helpers: block partial sums of squares (FP64) and an in-place scaling
 int sumsq_blocks(long long n);

@@ -80,7 +80,8 @@ EXPORTS = [
     "helm_net_adam_step", "helm_net_set_loss", "helm_autotune", "helm_set_preconditioner", "helm_solve_snapshots", "helm_net_examples",
     "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
     "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
-    "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio",
+    "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio", "helm_update_contrast",
+    "helm_grad_contrast",
 ]
 
 _lib = None
@@ -149,6 +150,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_farfield_adjoint.argtypes = [vp, i, vp, vp, vp]
     lib.helm_grad_f_farfield.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.helm_farfield_residual.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(d)]
+    lib.helm_update_contrast.argtypes = [vp, vp]
+    lib.helm_grad_contrast.argtypes = [vp, i, vp, vp, vp, i, vp]
     lib.helm_examples_rms.argtypes = [vp, vp, ctypes.c_longlong, ctypes.POINTER(d)]
     lib.helm_examples_scale.argtypes = [vp, vp, ctypes.c_longlong, d]
     lib.helm_net_residual_ratio.argtypes = [vp, i, i, i, vp, d, d, vp]
@@ -339,6 +342,24 @@ class Context:
         B = u_sc.shape[0]
         self._check(self.lib.helm_grad_f(self._h, B, self._f(u_in, B, name="u_in"), self._f(u_sc, B, name="u_sc"),
                                          self._f(lam, B, name="lam"), _ptr(grad)), "helm_grad_f")
+        return grad
+
+    def update_contrast(self, chi: torch.Tensor):
+        """Medium from the frequency-independent contrast chi = n^2 - n_b^2 on Omega."""
+        self._check(self.lib.helm_update_contrast(self._h, self._interior(chi.to(torch.float32).contiguous(), "chi")),
+                    "helm_update_contrast")
+        self.medium_version += 1
+
+    def grad_contrast(self, u_sc: torch.Tensor, lam: torch.Tensor, u_in: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None, accumulate: bool = False) -> torch.Tensor:
+        """k0^2 sum_q Re(conj(u_in + u_sc) lam) on Omega, written to (or added to) `out`."""
+        B = u_sc.shape[0]
+        grad = torch.empty((self.info.n,) * self.dim, dtype=torch.float32, device=self.device) if out is None else out
+        if accumulate and out is None:
+            raise HelmError("accumulate needs an output buffer")
+        self._check(self.lib.helm_grad_contrast(self._h, B, self._f(u_in, B, name="u_in"), self._f(u_sc, B, name="u_sc"),
+                                                self._f(lam, B, name="lam"), int(bool(accumulate)),
+                                                self._interior(grad, "grad")), "helm_grad_contrast")
         return grad
 
     def data_residual(self, idx: torch.Tensor, u: torch.Tensor, y: torch.Tensor):

@@ -87,3 +87,77 @@ class FBSReconstruction:
         for _ in range(iterations):
             self.step()
         return self.f
+
+
+@dataclass
+class MultiFrequencyLog:
+    loss: list = field(default_factory=list)       # data term over all frequencies (selected subsets) at chibar
+    subsets: list = field(default_factory=list)    # per iteration: the selected plane waves of every frequency
+
+
+class MultiFrequencyFBS:
+    """Alg. 4 over several frequencies, as in the paper's experimental reconstructions (Sec. VI-C: four
+    frequencies, a subset of the sources per iteration).  One Context per frequency (its own k0, the same
+    grid), each with its plane waves, on-grid receivers and data.  The unknown is the
+    frequency-independent contrast chi = n^2 - n_b^2 >= 0 on Omega (f = k0^2 chi at each frequency); the
+    gradient is the sum over frequencies of k0^2 sum_q Re(conj(u_q) lam_q), accumulated in one buffer by
+    the library, and the update is the library's FBS step (TV prox, momentum) on chi."""
+
+    def __init__(self, ctxs, dirs, rx_idx, ys, gamma: float, tau: float, prox_iters: int = 50,
+                 subset: int | None = None, seed: int = 0, chi0: torch.Tensor | None = None):
+        assert len(ctxs) == len(dirs) == len(rx_idx) == len(ys) and len(ctxs) >= 1
+        self.ctxs, self.rx, self.ys = list(ctxs), list(rx_idx), list(ys)
+        self.dirs = [np.asarray(d, dtype=np.float64) for d in dirs]
+        self.gamma, self.tau, self.prox_iters, self.subset = gamma, tau, prox_iters, subset
+        self.rng = np.random.default_rng(seed)
+        c0 = self.ctxs[0]
+        shape = (c0.info.n,) * c0.dim
+        self.chi = (torch.zeros(shape, dtype=torch.float32, device=c0.device) if chi0 is None
+                    else chi0.to(torch.float32).contiguous().clone())
+        self.chibar = self.chi.clone()
+        self.grad = torch.empty_like(self.chi)
+        self.alpha = 1.0
+        self.log = MultiFrequencyLog()
+
+    def select(self):
+        """Alg. 4's stochastic selection, drawn per frequency (all plane waves when subset is None)."""
+        out = []
+        for d in self.dirs:
+            Q = d.shape[0]
+            if self.subset is None or self.subset >= Q:
+                out.append(np.arange(Q))
+            else:
+                out.append(np.sort(self.rng.choice(Q, size=self.subset, replace=False)))
+        return out
+
+    def gradient(self, chi: torch.Tensor, sels):
+        """(gradient with respect to chi summed over frequencies into self.grad, data term)."""
+        loss = 0.0
+        for i, (ctx, sel) in enumerate(zip(self.ctxs, sels)):
+            ctx.update_contrast(chi)
+            rhs, uin = ctx.plane_wave_rhs(self.dirs[i][sel], with_uin=True)
+            usc, st = ctx.solve(rhs)
+            if not st.converged:
+                raise RuntimeError(f"forward solves of frequency {i} did not converge: {st}")
+            y_sel = self.ys[i].index_select(0, torch.as_tensor(sel, device=self.ys[i].device)).contiguous()
+            res, li = ctx.data_residual(self.rx[i], usc, y_sel)
+            lam, st_a = ctx.adjoint(ctx.sample_adjoint(self.rx[i], res))
+            if not st_a.converged:
+                raise RuntimeError(f"adjoint solves of frequency {i} did not converge: {st_a}")
+            ctx.grad_contrast(usc, lam, u_in=uin, out=self.grad, accumulate=i > 0)
+            loss += li
+        return self.grad, loss
+
+    def step(self):
+        sels = self.select()
+        grad, loss = self.gradient(self.chibar, sels)
+        self.alpha = self.ctxs[0].fbs_step(self.chi, self.chibar, grad, self.gamma, self.tau, self.alpha, lo=0.0,
+                                           prox_iters=self.prox_iters)
+        self.log.loss.append(loss)
+        self.log.subsets.append(sels)
+        return loss
+
+    def run(self, iterations: int):
+        for _ in range(iterations):
+            self.step()
+        return self.chi
