@@ -302,6 +302,23 @@ int helm_grad_contrast(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_c3
 int helm_data_residual(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* u, const helm_c32* y,
                        helm_c32* res, double* loss_host);
 
+/* Allocation-free variant of helm_data_residual, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and arithmetic: res is identical and
+ * *loss_host equal to helm_data_residual's (the same block partial sums, added in the
+ * same order in FP64).  Its scratch (block partial sums, the total and an index-error
+ * flag) is a fixed device array of 4128 doubles (33 KB) that each GPU holds from the
+ * first context created on it until the process ends; no hipMalloc, hipFree or other
+ * allocating call is made and no error message is copied.  The receiver indices are
+ * checked on the device before any read through them: HELM_EINVAL for one outside the
+ * grid (res then unwritten).  Limit: B * M <= HELM_STATIC_MAX_SAMPLES (one partial sum
+ * per 256 samples), else HELM_EINVAL.  Every call on one GPU shares that GPU's array and
+ * keeps the last call's contents: calls that overlap on one GPU (other streams, other
+ * threads or contexts) race and must be serialised by the caller. */
+#define HELM_STATIC_MAX_SAMPLES 1048576
+int helm_data_residual_static(helm_ctx* ctx, int B, int M, const int* idx_dev, const helm_c32* u, const helm_c32* y,
+                              helm_c32* res, double* loss_host);
+
 /* Proximal operator of eq. proximalOpt with isotropic TV (forward
  * differences, zero across the last index of each axis) and a lower bound:
  *   w = argmin_{w >= lo} 1/2 ||w - v||^2 + lam TV(w),

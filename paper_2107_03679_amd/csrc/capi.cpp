@@ -63,6 +63,7 @@ struct helm_ctx {
   hipStream_t s = nullptr;       // the context's own stream (graphs cannot capture the null stream)
   hipStream_t user_s = nullptr;  // the caller's stream: work starts after it
   std::string err;
+  const char* err_lit = nullptr;  // message of the allocation-free entry point (no string copy)
 
   // fine-level data
   float* d_nmap = nullptr;   // interior index (for the gradient)
@@ -624,8 +625,18 @@ void restart_cycle(helm_ctx* c, int B, int conj_rhs) {
 }
 
 int fail(helm_ctx* c, int code, const std::string& msg) {
-  if (c) c->err = msg;
-  else g_setup_error = msg;
+  if (c) {
+    c->err = msg;
+    c->err_lit = nullptr;
+  } else {
+    g_setup_error = msg;
+  }
+  return code;
+}
+
+// error return that copies no string (the allocation-free entry point)
+int fail_lit(helm_ctx* c, int code, const char* msg) {
+  c->err_lit = msg;
   return code;
 }
 
@@ -1099,6 +1110,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     check(hipHostMalloc((void**)&c->h_fallbacks, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     upload_static(c);
     update_medium(c, n_map_dev);
+    check(static_scratch_init(), "device scratch address");
     check(hipDeviceSynchronize(), "setup");
   } catch (const HipError& e) {
     std::string msg = std::string(e.what) + ": " + hipGetErrorString(e.code);
@@ -1602,6 +1614,42 @@ int helm_data_residual(helm_ctx* c, int B, int M, const int* idx_dev, const helm
   HELM_GUARD_END("data_residual")
 }
 
+int helm_data_residual_static(helm_ctx* c, int B, int M, const int* idx_dev, const helm_c32* u, const helm_c32* y,
+                              helm_c32* res, double* loss_host) {
+  if (!c) return HELM_EINVAL;
+  if (!idx_dev || !u || !y || !res) return fail_lit(c, HELM_EINVAL, "null argument");
+  if (B < 1 || M < 1) return fail_lit(c, HELM_EINVAL, "B and M must be >= 1");
+  if ((long long)B * M > HELM_STATIC_MAX_SAMPLES)
+    return fail_lit(c, HELM_EINVAL, "B * M exceeds the fixed scratch of helm_data_residual_static (1048576 samples)");
+  const int nbk = data_residual_blocks(B, M);
+  if (nbk > static_scratch_partials()) return fail_lit(c, HELM_EINVAL, "too many partial sums for the fixed scratch");
+  hipError_t e = hipStreamSynchronize(c->user_s);
+  double* scr = static_scratch();
+  if (!scr && e == hipSuccess) {  // first call on this device
+    e = static_scratch_init();
+    scr = static_scratch();
+  }
+  if (e != hipSuccess || !scr) return fail_lit(c, HELM_EHIP, "device scratch address unavailable");
+  // receiver indices checked on the device (flag in the scratch), before any read through them
+  double flag = 0.0, total = 0.0;
+  launch_static_check(c->s, M, c->N0, idx_dev, scr);
+  e = hipMemcpyAsync(&flag, static_flag(scr), sizeof(double), hipMemcpyDeviceToHost, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return fail_lit(c, HELM_EHIP, "receiver index check failed");
+  if (flag != 0.0) return fail_lit(c, HELM_EINVAL, "receiver index outside the grid");
+  launch_data_residual(c->s, B, M, c->N0, idx_dev, (const c32*)u, (const c32*)y, (c32*)res, scr);
+  if (loss_host) {
+    launch_static_total(c->s, nbk, scr);
+    e = hipMemcpyAsync(&total, static_total(scr), sizeof(double), hipMemcpyDeviceToHost, c->s);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return fail_lit(c, HELM_EHIP, "data residual failed");
+  if (loss_host) *loss_host = 0.5 * total;
+  return HELM_OK;
+}
+
+
 int helm_tv_prox(helm_ctx* c, const float* v_dev, double lam, double lo, int iters, float* w_dev) {
   if (!c || !v_dev || !w_dev) return fail(c, HELM_EINVAL, "null argument");
   if (iters < 0 || !(lam >= 0.0) || !std::isfinite(lam)) return fail(c, HELM_EINVAL, "bad lam or iters");
@@ -1760,7 +1808,10 @@ int helm_grad_f_farfield(helm_ctx* c, int B, const helm_c32* u_in, const helm_c3
   HELM_GUARD_END("grad_f_farfield")
 }
 
-const char* helm_last_error(const helm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+const char* helm_last_error(const helm_ctx* c) {
+  if (!c) return g_setup_error.c_str();
+  return c->err_lit ? c->err_lit : c->err.c_str();
+}
 
 void helm_destroy(helm_ctx* c) {
   if (!c) return;

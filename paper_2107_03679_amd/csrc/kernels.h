@@ -202,6 +202,16 @@ void launch_setup_fine(hipStream_t s, const SetupFineArgs& a);
 void launch_setup_coarse(hipStream_t s, int dim, int nf, int nc, const c32* kcf, const c32* kcflo, float omega,
                          c32* kcc, c32* kcclo, c32* wdc);
 
+// Fixed device scratch of the allocation-free data residual (k_static.hip): per-device
+// address from hipGetSymbolAddress (static_scratch_init once per device, with it current),
+// partial capacity, and the check / total kernels working inside it.
+int static_scratch_partials();
+hipError_t static_scratch_init();
+double* static_scratch();  // current device's copy, nullptr before static_scratch_init
+void launch_static_check(hipStream_t s, int M, long long N, const int* idx, double* scr);
+void launch_static_total(hipStream_t s, int nbk, double* scr);
+const double* static_flag(const double* scr);
+const double* static_total(const double* scr);
 // FP32 vector helpers: block partial sums of squares (FP64) and an in-place scaling
 int sumsq_blocks(long long n);
 void launch_sumsq(hipStream_t s, long long n, const float* x, double* part);

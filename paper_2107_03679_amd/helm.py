@@ -81,7 +81,7 @@ EXPORTS = [
     "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
     "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
     "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio", "helm_update_contrast",
-    "helm_grad_contrast",
+    "helm_grad_contrast", "helm_data_residual_static",
 ]
 
 _lib = None
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_update_f.argtypes = [vp, vp]
     lib.helm_grad_f.argtypes = [vp, i, vp, vp, vp, vp]
     lib.helm_data_residual.argtypes = [vp, i, i, vp, vp, vp, vp, ctypes.POINTER(d)]
+    lib.helm_data_residual_static.argtypes = [vp, i, i, vp, vp, vp, vp, ctypes.POINTER(d)]
     lib.helm_tv_prox.argtypes = [vp, vp, d, d, i, vp]
     lib.helm_fbs_step.argtypes = [vp, vp, vp, vp, d, d, d, i, ctypes.POINTER(d)]
     lib.helm_farfield_set.argtypes = [vp, i, vp]
@@ -372,6 +373,19 @@ class Context:
         loss = ctypes.c_double()
         self._check(self.lib.helm_data_residual(self._h, B, M, self._idx(idx), self._f(u, B, name="u"), _ptr(y),
                                                 _ptr(res), ctypes.byref(loss)), "helm_data_residual")
+        return res, loss.value
+
+    def data_residual_static(self, idx: torch.Tensor, u: torch.Tensor, y: torch.Tensor, res: torch.Tensor):
+        """helm_data_residual_static: (S u - y) into the caller's `res`, and 1/2 ||S u - y||^2; the
+        library allocates nothing (fixed device scratch)."""
+        B, M = u.shape[0], idx.numel()
+        for t, name in ((y, "data"), (res, "res")):
+            if t.dtype != torch.complex64 or tuple(t.shape) != (B, M) or not t.is_contiguous():
+                raise HelmError(f"{name} must be contiguous complex64 [{B}, {M}]")
+        loss = ctypes.c_double()
+        self._check(self.lib.helm_data_residual_static(self._h, B, M, self._idx(idx), self._f(u, B, name="u"),
+                                                       _ptr(y), _ptr(res), ctypes.byref(loss)),
+                    "helm_data_residual_static")
         return res, loss.value
 
     def tv_prox(self, v: torch.Tensor, lam: float, lo: float = 0.0, iters: int = 100) -> torch.Tensor:
