@@ -50,8 +50,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="length of each bounded oracle run of the CPU baseline (one thread; one per core)")
     p.add_argument("--no-c1", action="store_true", help="skip the disk128 CPU timing (set-up and solve, median of 5)")
-    p.add_argument("--kappa-im", type=float, default=0.5, help="imaginary part of the shift kappa (real part 1)")
-    p.add_argument("--omega", type=float, default=0.8, help="damped-Jacobi factor")
+    p.add_argument("--kappa-im", type=float, default=0.4,
+                   help="imaginary part of the shift kappa (real part 1); 0.4 measured best with --omega 0.9")
+    p.add_argument("--omega", type=float, default=0.9, help="damped-Jacobi factor")
     p.add_argument("--no-vcycle-leg", action="store_true",
                    help="skip the same workload with the paper's V-cycle (Alg. 2, CycleType 1)")
     p.add_argument("--sweep", action="store_true",
@@ -130,7 +131,7 @@ def host_cpu():
     return model, cores
 
 
-def _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta_deg=0.0):
+def _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta_deg=0.0, kappa=1 + 0.5j, omega=0.8):
     """Seconds per MG-FGMRES iteration of the FP64 oracle on one right-hand side (one host thread):
     a bounded run of about budget_s seconds."""
     from threadpoolctl import threadpool_limits
@@ -143,7 +144,7 @@ def _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta_deg=0.0
     from oracle.multigrid import Hierarchy
 
     with threadpool_limits(1):
-        prob = Problem(nmap, k0h=KBH / N_B, w=20, levels=levels, beta=0.15)
+        prob = Problem(nmap, k0h=KBH / N_B, w=20, levels=levels, beta=0.15, kappa=kappa, omega_jac=omega)
         hier = Hierarchy(prob)
         a = helmholtz_matrix(prob)
         th = np.radians(theta_deg)
@@ -161,20 +162,20 @@ def _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta_deg=0.0
 
 
 def _rate_worker(job):
-    nmap, levels, restart, cycle, budget_s, theta = job
-    return _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta)
+    nmap, levels, restart, cycle, budget_s, theta, kappa, omega = job
+    return _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, theta, kappa, omega)
 
 
-def cpu_rates(nmap, levels, restart, cycle, budget_s):
+def cpu_rates(nmap, levels, restart, cycle, budget_s, kappa, omega):
     """The FP64 oracle's iteration rate on the host, before the GPU is touched (the all-cores leg
     forks worker processes): one thread on one right-hand side, and one process per usable core,
     each on its own right-hand side (angles spread over [-60, 60] degrees)."""
     import multiprocessing as mp
 
     model, cores = host_cpu()
-    one = _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s)
+    one = _oracle_iteration_rate(nmap, levels, restart, cycle, budget_s, 0.0, kappa, omega)
     thetas = [(-60.0 + 120.0 * q / max(1, cores - 1)) for q in range(cores)]
-    jobs = [(nmap, levels, restart, cycle, budget_s, th) for th in thetas]
+    jobs = [(nmap, levels, restart, cycle, budget_s, th, kappa, omega) for th in thetas]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         res = pool.map(_rate_worker, jobs)
@@ -370,7 +371,8 @@ def main():
     # host legs first: the all-cores leg forks worker processes, which must happen before the GPU is used
     rates = c1 = None
     if not args.no_cpu_baseline and wl["d"] == 2:
-        rates = cpu_rates(nmap, args.levels, args.restart, args.cycle, args.cpu_seconds)
+        rates = cpu_rates(nmap, args.levels, args.restart, args.cycle, args.cpu_seconds, complex(1.0, args.kappa_im),
+                          args.omega)
         if not args.no_c1:
             c1 = cpu_c1_protocol()
     import torch

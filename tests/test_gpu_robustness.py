@@ -113,3 +113,49 @@ def test_contrast_and_radius_sweep():
     assert it.max() < 6 * it.min(), rows
     for ctx in solvers.values():
         ctx.close()
+
+
+SETTINGS = [  # (Im kappa, cycle, levels, omega): the shift of Sec. IV-B, Alg. 2's cycle type, the depth
+    (0.3, 3, 4, 0.8), (0.5, 3, 4, 0.8), (0.7, 3, 4, 0.8), (0.5, 1, 4, 0.8), (0.5, 2, 4, 0.8), (0.5, 3, 5, 0.8),
+    (0.4, 3, 4, 0.9),
+]
+
+
+def test_settings_sweep_beside_the_oracle():
+    """Cycles per solve over the shift, the cycle type (V, W, two corrections on the finest level), the
+    level count and the smoothing factor, on the GPU (s-step GMRES(8)) and in the FP64 oracle (FGMRES(8),
+    same preconditioner): equal restart cycles up to one for every setting (128^2 blobs, 20-cell layer,
+    normal incidence).  The full-size sweep (512^2 x 60) is bench.py --sweep."""
+    from oracle.discretization import Problem
+
+    from .helpers import gpu_context, medium
+
+    n, w, m = 128, 20, 8
+    nmap = medium(n, seed=9)
+    print("\n[settings sweep 128^2 beside the oracle]", flush=True)
+    rows = []
+    for kim, cyc, L, om in SETTINGS:
+        ctx = gpu_context(nmap, w=w, levels=L, kappa=1 + 1j * kim, max_batch=1, restart=m, cycle=cyc,
+                          omega_jac=om)
+        rhs = ctx.plane_wave_rhs(synth.directions_2d(1, 0.0, 0.0))
+        _, st = ctx.solve(rhs)
+        ctx.close()
+        assert st.converged and st.rel_res_true[0] <= 1e-6
+        prob = Problem(nmap, k0h=KBH / N_B, w=w, levels=L, kappa=1 + 1j * kim, omega_jac=om)
+        b = model.rhs(prob, (0.0, 1.0))
+        from oracle.krylov import fgmres
+        from oracle.discretization import helmholtz_matrix
+        from oracle.multigrid import Hierarchy
+
+        hier = Hierarchy(prob)
+        a = helmholtz_matrix(prob)
+        ct = [2] + [1] * (L - 2) if cyc == 3 else cyc
+        _, info = fgmres(lambda v: a @ v, lambda r: hier.cycle(r, None, 0, ct), (prob.h ** 2 * b).ravel(),
+                         rtol=1e-6, restart=m, max_iters=4000)
+        assert info.converged
+        gpu_cycles, ora_cycles = int(st.iters[0]) // m, -(-info.iters // m)
+        rows.append((kim, cyc, L, om, int(st.iters[0]), info.iters))
+        assert abs(gpu_cycles - ora_cycles) <= 1, (kim, cyc, L, om, st.iters[0], info.iters)
+    for r in rows:
+        print(f"[sweep] Im kappa {r[0]} cycle {r[1]} levels {r[2]} omega {r[3]}: GPU {r[4]}, oracle {r[5]} "
+              f"preconditioner applications", flush=True)
