@@ -17,6 +17,8 @@ Modules
                   Jacobian (Prop. 1), data fidelity, smoothed TV, gradients
   lfa             local-Fourier-analysis symbols of Sec. IV-B
   cylinder        analytic field of a dielectric cylinder (Sec. VI-A pin)
+  learned         FP64 reference of the 2D learned-preconditioner network
+  learned3d       FP64 reference of the 3D (3x3x3) learned-preconditioner network
 
 Readings of passages where the paper is silent or inconsistent are listed in
 the module that applies them; the product implements the same readings
