@@ -6,16 +6,18 @@ only, and Sec. VII names 3D as future work); this is the reference the 3D
 BF16-MFMA kernels are checked against.  Parity with the paper is unpinned for
 this part; its pins are finite differences and closed-form special cases.
 
-Network (3D U-Net, 4 levels, channels 8/16/32/32, 3x3x3 convolutions, zero
+Network (3D U-Net, 4 levels, channels 16/16/32/32, 3x3x3 convolutions, zero
 padding, ReLU after every convolution but the last):
-    e0 = relu(conv(x, A0))                         4 -> 8    level 0
-    e1 = relu(conv(pool(e0), A1))                  8 -> 16   level 1
+    e0 = relu(conv(x, A0))                         4 -> 16   level 0
+    e1 = relu(conv(pool(e0), A1))                 16 -> 16   level 1
     e2 = relu(conv(pool(e1), A2))                 16 -> 32   level 2
     e3 = relu(conv(pool(e2), A3))                 32 -> 32   level 3
     d2 = relu(conv(cat(up(e3), e2), B2))          64 -> 32
     d1 = relu(conv(cat(up(d2), e1), B1))          48 -> 16
-    d0 = relu(conv(cat(up(d1), e0), B0))          24 -> 8
-    y  = conv(d0, O)                               8 -> 2
+    d0 = relu(conv(cat(up(d1), e0), B0))          32 -> 16
+    y  = conv(d0, O)                              16 -> 2
+(16 output channels fill one 16-wide matrix-core tile, so the finest level
+is no cheaper with 8.)
 pool: 2x2x2 sum / 8 with zero padding (output ceil(D/2) per axis); up: nearest
 neighbour back to the skip's size; cat: channel concatenation (up first).
 Arrays are [image][z][y][x][channel]; weights [3][3][3][cin][cout], tap
@@ -26,10 +28,10 @@ from __future__ import annotations
 
 import numpy as np
 
-CH = (8, 16, 32, 32)
+CH = (16, 16, 32, 32)
 LAYERS = [  # name, cin, cout, relu
-    ("A0", 4, 8, True), ("A1", 8, 16, True), ("A2", 16, 32, True), ("A3", 32, 32, True),
-    ("B2", 64, 32, True), ("B1", 48, 16, True), ("B0", 24, 8, True), ("O", 8, 2, False),
+    ("A0", 4, 16, True), ("A1", 16, 16, True), ("A2", 16, 32, True), ("A3", 32, 32, True),
+    ("B2", 64, 32, True), ("B1", 48, 16, True), ("B0", 32, 16, True), ("O", 16, 2, False),
 ]
 
 
