@@ -380,9 +380,18 @@ int helm_grad_f_farfield(helm_ctx* ctx, int B, const helm_c32* u_in, const helm_
  * Tensors are FP32 NHWC [nimg][H][W][channels] device arrays. */
 
 int helm_net_layers(void);                                 /* 8 */
-int helm_net_layer_shape(int layer, int* cin, int* cout);  /* real channel counts */
+int helm_net_layer_shape(int layer, int* cin, int* cout);  /* real channel counts of the 2D network */
 /* He-normal initial weights from `seed`, zero biases; work runs on hip_stream. */
 int helm_net_create(unsigned long long seed, void* hip_stream, helm_net** out);
+/* The 3D network for 3D contexts: the same eight layers with 3x3x3 convolutions, channels
+ * 16/16/32/32 (encoder A0..A3: 4->16, 16->16, 16->32, 32->32; decoder B2 64->32, B1 48->16,
+ * B0 32->16; O 16->2), 2x2x2 average pooling (zero padding, output ceil(n/2) per axis),
+ * nearest-neighbour upsampling; tensors NDHWC [nimg][D][H][W][channels].  Weights as host
+ * float[3][3][3][cin][cout] (tap (dz+1, dy+1, dx+1)).  Not part of the paper (Sec. VII
+ * names 3D as future work). */
+int helm_net_create3(unsigned long long seed, void* hip_stream, helm_net** out);
+int helm_net_dim(const helm_net* net);                                      /* 2 or 3 */
+int helm_net_shape(const helm_net* net, int layer, int* cin, int* cout);   /* this network's channels */
 void helm_net_destroy(helm_net* net);
 const char* helm_net_last_error(const helm_net* net);
 /* Weights as host float[3][3][cin][cout] (tap (dy+1, dx+1)) and bias float[cout]. */
@@ -395,6 +404,14 @@ int helm_net_forward(helm_net* net, int nimg, int H, int W, const float* x_dev, 
 /* Loss 1/2 sum (y - target)^2 / nimg and its parameter gradients. */
 int helm_net_backward(helm_net* net, int nimg, int H, int W, const float* x_dev, const float* target_dev,
                       double* loss_host);
+/* The same three calls for a 3D network on volumes of D x H x W (HELM_EINVAL for a 2D network,
+ * and the 2D calls refuse a 3D one); the residual term uses the 7-point operator
+ * (6 - c) y - (sum of the 6 neighbours) with the one-voxel border left out. */
+int helm_net_forward3(helm_net* net, int nimg, int D, int H, int W, const float* x_dev, float* y_dev);
+int helm_net_backward3(helm_net* net, int nimg, int D, int H, int W, const float* x_dev, const float* target_dev,
+                       double* loss_host);
+int helm_net_residual_ratio3(helm_net* net, int nimg, int D, int H, int W, const float* x_dev, double gamma,
+                             double cb, double* ratio_host);
 /* Training loss of helm_net_backward, per image:
  *   err_weight / 2 sum (y - target)^2
  * + res_weight / 2 sum over the image interior |r - gamma A' y|^2,
@@ -419,8 +436,9 @@ int helm_net_adam_step(helm_net* net, double lr);
  * step; the per-RHS count is helm_stats.fallbacks).  HELM_NET_THEN_MG follows
  * the network with a multigrid cycle of its residual and needs two extra
  * [max_batch][N] work vectors, allocated here on first use.  The context
- * keeps the pointer (not owned).  Errors: HELM_EINVAL for a 3D context, an
- * unknown mode or gamma <= 0. */
+ * keeps the pointer (not owned); the activation buffers of its applications belong
+ * to the context, so one network may serve several contexts.  Errors: HELM_EINVAL for
+ * a network of another dimension than the grid, an unknown mode or gamma <= 0. */
 int helm_set_preconditioner(helm_ctx* ctx, helm_net* net, double accept_tol, double gamma, int mode);
 
 /* helm_solve_batch that also copies the iterate x_hi after every
@@ -431,9 +449,10 @@ int helm_solve_snapshots(helm_ctx* ctx, int B, const helm_c32* rhs, helm_c32* x,
                          int every_cycles, int max_snaps, helm_c32* snaps_dev, int* n_snaps);
 
 /* Training examples from (residual r = b - A x_k, x_final, x_k) fields [B][grid]:
- * crop i = (rhs, y0, x0) from crops_host[3 i ..], S x S points; features
- * feat [ncrop][S][S][4] = (h^2 r / rms, Re and Im of (c - c_b) / c_b), targets
- * tgt [ncrop][S][S][2] = (x_final - x_k) / rms / gamma, where rms is the root
+ * crop i = (rhs, y0, x0) from crops_host[3 i ..] (3D: (rhs, z0, y0, x0) from
+ * crops_host[4 i ..]), S^dim points; features feat [ncrop][S]^dim[4] = (h^2 r / rms,
+ * Re and Im of (c - c_b) / c_b), targets tgt [ncrop][S]^dim[2] = (x_final - x_k) / rms
+ * / gamma, where rms is the root
  * mean square of h^2 r over the whole grid of that right-hand side (the scale
  * the solver gives the network: sqrt(N) times a unit-norm vector). */
 int helm_net_examples(helm_ctx* ctx, int B, const helm_c32* r, const helm_c32* x_final, const helm_c32* x_k, int ncrop,

@@ -1192,7 +1192,7 @@ int helm_solve_snapshots(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, h
 
 int helm_set_preconditioner(helm_ctx* c, helm_net* net, double accept_tol, double gamma, int mode) {
   if (!c) return HELM_EINVAL;
-  if (net && c->dim != 2) return fail(c, HELM_EINVAL, "the learned preconditioner is two-dimensional");
+  if (net && net_dim(net) != c->dim) return fail(c, HELM_EINVAL, "the network's dimension differs from the grid's");
   if (mode != HELM_NET_REPLACE && mode != HELM_NET_THEN_MG) return fail(c, HELM_EINVAL, "unknown mode");
   if (!(gamma > 0.0)) return fail(c, HELM_EINVAL, "gamma must be positive");
   try {
@@ -1227,10 +1227,12 @@ int helm_net_examples(helm_ctx* c, int B, const helm_c32* r, const helm_c32* x_f
                       const int* crops_host, int S, double gamma, float* feat, float* tgt) {
   if (!c || !r || !x_final || !x_k || !crops_host || !feat || !tgt || ncrop < 1 || S < 1 || S > c->ne)
     return fail(c, HELM_EINVAL, "bad argument");
+  const int cw = 1 + c->dim;  // (rhs, (z0,) y0, x0)
   for (int i = 0; i < ncrop; ++i) {
-    const int b = crops_host[3 * i], y0 = crops_host[3 * i + 1], x0 = crops_host[3 * i + 2];
-    if (b < 0 || b >= B || y0 < 0 || x0 < 0 || y0 + S > c->ne || x0 + S > c->ne)
-      return fail(c, HELM_EINVAL, "crop outside the grid");
+    const int b = crops_host[cw * i];
+    bool ok = b >= 0 && b < B;
+    for (int a = 1; a < cw; ++a) ok = ok && crops_host[cw * i + a] >= 0 && crops_host[cw * i + a] + S <= c->ne;
+    if (!ok) return fail(c, HELM_EINVAL, "crop outside the grid");
   }
   struct DevFree {
     void* p = nullptr;
@@ -1239,12 +1241,12 @@ int helm_net_examples(helm_ctx* c, int B, const helm_c32* r, const helm_c32* x_f
     }
   } crops_mem;
   HELM_GUARD_BEGIN
-  const size_t crop_bytes = ((size_t)ncrop * 3 * sizeof(int) + 255) / 256 * 256;
+  const size_t crop_bytes = ((size_t)ncrop * cw * sizeof(int) + 255) / 256 * 256;
   check(hipMalloc(&crops_mem.p, crop_bytes + (size_t)B * sizeof(float)), "hipMalloc");
   int* d_crops = (int*)crops_mem.p;
   float* d_ss = (float*)((char*)crops_mem.p + crop_bytes);
-  check(hipMemcpyAsync(d_crops, crops_host, (size_t)ncrop * 3 * sizeof(int), hipMemcpyHostToDevice, c->s), "crops");
-  launch_examples(c->s, B, ncrop, S, c->ne, d_crops, d_ss, (const c32*)r, (const c32*)x_final, (const c32*)x_k, c->N0,
+  check(hipMemcpyAsync(d_crops, crops_host, (size_t)ncrop * cw * sizeof(int), hipMemcpyHostToDevice, c->s), "crops");
+  launch_examples(c->s, c->dim, B, ncrop, S, c->ne, d_crops, d_ss, (const c32*)r, (const c32*)x_final, (const c32*)x_k, c->N0,
                   c->d_chi, make_float2((float)(c->kbh * c->kbh), 0.0f), (float)(c->h * c->h), (float)(1.0 / gamma),
                   feat, tgt);
   HELM_GUARD_END("net_examples")

@@ -1,11 +1,12 @@
 // Kernels of the learned preconditioner network (BF16 storage, FP32
 // accumulation, v_mfma_f32_16x16x32_bf16 on gfx950).
 //
-// Activations are NHWC: element (pixel p, channel c) of a buffer with
-// channel stride ct at channel offset off is buf[p * ct + off + c]; pixels
-// are flattened over (image, y, x).  A 3x3 convolution is an implicit GEMM
+// Activations are NHWC (NDHWC in 3D): element (pixel p, channel c) of a buffer
+// with channel stride ct at channel offset off is buf[p * ct + off + c]; pixels
+// are flattened over (image, z, y, x), with depth 1 for the 2D network.  A 3x3
+// (3x3x3) convolution is an implicit GEMM
 //     out[p][co] = bias[co] + sum_k in[p + shift(tap(k))][ci(k)] * Wt[co][k],
-//     k = tap * cin + ci,  tap = 3 (dy + 1) + (dx + 1),
+//     k = tap * cin + ci,  tap = 3 (dy + 1) + (dx + 1)  (+ 9 (dz + 1) in 3D),
 // with the weights packed as Wt[co][k] (k padded to a multiple of 32).
 // MFMA 16x16x32 operand layout (lane l, g = l / 16):
 //     A[i][k]: i = l % 16, k = 8 g + v (v = 0..7)      (16 pixels x 32 k)
@@ -32,60 +33,72 @@ __device__ __forceinline__ bf16x8 zero8() {
 }
 
 // ---------------------------------------------------------------- layer inputs
-// 8 input channels [ci0, ci0 + 8) of pixel (img, y, x) of an H x W layer.
-// Address of 8 input channels [ci0, ci0 + 8) of pixel (img, y, x) for the convolution's
-// halo staging (MODE 0: plain, 2: upsample + skip), with (y, x) clamped into the image;
-// for MODE 1 (pool) the first of the 2 x 2 source pixels, clamped likewise.
-template <int MODE>
-__device__ __forceinline__ const bf16* src_addr(const NetSrc& s, long long img, int H, int W, int y, int x, int ci0) {
+// Address of 8 input channels [ci0, ci0 + 8) of pixel (img, z, y, x) for the convolution's
+// halo staging (MODE 0: plain, 2: upsample + skip), with (z, y, x) clamped into the layer
+// (depth D, 1 in 2D); for MODE 1 (pool) the first of the 2^NDIM source pixels, clamped likewise.
+template <int MODE, int NDIM>
+__device__ __forceinline__ const bf16* src_addr(const NetSrc& s, long long img, int D, int H, int W, int z, int y,
+                                                int x, int ci0) {
+  const int zc = NDIM == 3 ? min(max(z, 0), D - 1) : 0;
   const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
-  if (MODE == 1) return s.in + ((img * s.Hs + 2 * yc) * s.Ws + 2 * xc) * s.in_ct + s.in_off + ci0;
+  if (MODE == 1)
+    return s.in + (((img * (NDIM == 3 ? s.Ds : 1) + (NDIM == 3 ? 2 * zc : 0)) * s.Hs + 2 * yc) * s.Ws + 2 * xc) *
+                      s.in_ct + s.in_off + ci0;
   if (MODE == 2 && ci0 < s.cup) {
-    const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
-    return s.up + ((img * Hu + (yc >> 1)) * Wu + (xc >> 1)) * s.up_ct + ci0;
+    const int Du = NDIM == 3 ? (D + 1) / 2 : 1, Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+    return s.up + (((img * Du + (zc >> 1)) * Hu + (yc >> 1)) * Wu + (xc >> 1)) * s.up_ct + ci0;
   }
-  return s.in + ((img * H + yc) * W + xc) * s.in_ct + s.in_off + (ci0 - s.cup);
+  return s.in + (((img * D + zc) * H + yc) * W + xc) * s.in_ct + s.in_off + (ci0 - s.cup);
 }
 
-// one input channel ci of pixel (img, y, x) inside the image, the same value fetch8_clamped gives
-__device__ __forceinline__ float fetch1(const NetSrc& s, long long img, int H, int W, int y, int x, int ci) {
+// one input channel ci of pixel (img, z, y, x) inside the layer, the value the staging gives
+template <int NDIM>
+__device__ __forceinline__ float fetch1(const NetSrc& s, long long img, int D, int H, int W, int z, int y, int x,
+                                        int ci) {
   if (ci < s.cup) {
-    const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
-    return (float)s.up[((img * Hu + (y >> 1)) * Wu + (x >> 1)) * s.up_ct + ci];
+    const int Du = NDIM == 3 ? (D + 1) / 2 : 1, Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+    return (float)s.up[(((img * Du + (z >> 1)) * Hu + (y >> 1)) * Wu + (x >> 1)) * s.up_ct + ci];
   }
   const int c = ci - s.cup;
-  if (!s.pool) return (float)s.in[((img * H + y) * W + x) * s.in_ct + s.in_off + c];
+  if (!s.pool) return (float)s.in[(((img * D + z) * H + y) * W + x) * s.in_ct + s.in_off + c];
+  const int Ds = NDIM == 3 ? s.Ds : 1;
   float acc = 0.f;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int yy = 2 * y + a, xx = 2 * x + b;
-      if (yy < s.Hs && xx < s.Ws) acc += (float)s.in[((img * s.Hs + yy) * s.Ws + xx) * s.in_ct + s.in_off + c];
-    }
-  return (float)(bf16)(0.25f * acc);
+  for (int e = 0; e < (NDIM == 3 ? 2 : 1); ++e)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int zz = NDIM == 3 ? 2 * z + e : 0, yy = 2 * y + a, xx = 2 * x + b;
+        if (zz < Ds && yy < s.Hs && xx < s.Ws)
+          acc += (float)s.in[(((img * Ds + zz) * s.Hs + yy) * s.Ws + xx) * s.in_ct + s.in_off + c];
+      }
+  return (float)(bf16)((NDIM == 3 ? 0.125f : 0.25f) * acc);
 }
 
 // ---------------------------------------------------------------- conv, LDS-tiled (MFMA)
-// Block = TH x TW output pixels of one image, all output channels (NCO tiles of
-// 16).  The (TH + 2) x (TW + 2) input halo tile, all cin channels, is staged
-// once in LDS (pixel stride PS channels, padded so that the 16-byte reads of
-// 8 consecutive lanes hit distinct bank groups); the four wavefronts then
-// take MT = TH TW / 64 row segments of 16 pixels each and run the implicit
-// GEMM over k = tap * cin + ci with A from LDS and B (weights) from global
-// memory (small, cache resident).  Pixels outside the image read zeros.
+// Block = TH x TW output pixels of one image plane, all output channels (NCO tiles
+// of 16).  The (TH + 2) x (TW + 2) input halo tile (in 3D: three planes of it,
+// z - 1 .. z + 1), all cin channels, is staged once in LDS (pixel stride PS channels,
+// padded so that the 16-byte reads of 8 consecutive lanes hit distinct bank groups);
+// the four wavefronts then take MT = TH TW / 64 row segments of 16 pixels each and
+// run the implicit GEMM over k = tap * cin + ci with A from LDS and B (weights) from
+// global memory (small, cache resident).  Pixels outside the layer read zeros.
 __device__ __forceinline__ int conv_pixel_stride(int cin) { return cin == 8 ? 8 : cin + 8; }
 
-template <int NCO, int TH, int TW, int MODE>
+template <int NCO, int TH, int TW, int MODE, int NDIM>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   extern __shared__ __align__(16) bf16 tile[];
   constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64;
+  constexpr int NZ = NDIM == 3 ? 3 : 1, NT = NDIM == 3 ? 27 : 9, PLANE = (TH + 2) * TW2;
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64, g = l / 16, i16 = l % 16;
   const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-  const long long img = blockIdx.z;
+  const int D = NDIM == 3 ? a.D : 1;
+  const long long img = NDIM == 3 ? (long long)blockIdx.z / D : (long long)blockIdx.z;
+  const int z0 = NDIM == 3 ? (int)(blockIdx.z % D) : 0;
   const int cin = a.cin, ps = conv_pixel_stride(cin), cg8 = cin / 8;
-  // stage the halo tile: (TH + 2)(TW + 2) pixels x cin / 8 chunks of 16 bytes; a batch of
-  // loads is in flight per thread before any is used (points outside the image store 0)
-  constexpr int BATCH = MODE == 1 ? 2 : 8, NSRC = MODE == 1 ? 4 : 1;
-  const int nchunk = (TH + 2) * TW2 * cg8;
+  // stage the halo tile: NZ (TH + 2)(TW + 2) pixels x cin / 8 chunks of 16 bytes; a batch
+  // of loads is in flight per thread before any is used (points outside the layer store 0)
+  constexpr int NSRC = MODE == 1 ? (NDIM == 3 ? 8 : 4) : 1;
+  constexpr int BATCH = MODE == 1 ? (NDIM == 3 ? 1 : 2) : 8;
+  const int nchunk = NZ * PLANE * cg8;
   for (int tb = 0; tb < nchunk; tb += 256 * BATCH) {
     const int t0 = tb + threadIdx.x;
     const int nslot = min(BATCH, (nchunk - tb + 255) / 256);  // uniform over the block
@@ -95,10 +108,11 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       if (u < nslot) {
         const int t = min(t0 + 256 * u, nchunk - 1);
         const int q = t / cg8, cg = t - q * cg8;
-        const int r = q / TW2, c = q - r * TW2;
-        const bf16* p = src_addr<MODE>(a.src, img, a.H, a.W, y0 - 1 + r, x0 - 1 + c, cg * 8);
+        const int pz = q / PLANE, rq = q - pz * PLANE, r = rq / TW2, c = rq - r * TW2;
+        const int zz = z0 - (NZ - 1) / 2 + pz;
+        const bf16* p = src_addr<MODE, NDIM>(a.src, img, D, a.H, a.W, zz, y0 - 1 + r, x0 - 1 + c, cg * 8);
         if (MODE == 1) {
-          // the 2 x 2 children, clamped into the source (weights applied below)
+          // the 2 x 2 (x 2) children, clamped into the source (weights applied below)
           const int yc = min(max(y0 - 1 + r, 0), a.H - 1), xc = min(max(x0 - 1 + c, 0), a.W - 1);
           const long long dx = (2 * xc + 1 < a.src.Ws) ? a.src.in_ct : 0;
           const long long dy = (2 * yc + 1 < a.src.Hs) ? (long long)a.src.Ws * a.src.in_ct : 0;
@@ -106,6 +120,14 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
           v[u][NSRC > 1 ? 1 : 0] = load8(p + dx);
           v[u][NSRC > 2 ? 2 : 0] = load8(p + dy);
           v[u][NSRC > 3 ? 3 : 0] = load8(p + dy + dx);
+          if (NDIM == 3) {
+            const int zc = min(max(zz, 0), D - 1);
+            const long long dz = (2 * zc + 1 < a.src.Ds) ? (long long)a.src.Hs * a.src.Ws * a.src.in_ct : 0;
+            v[u][NSRC > 4 ? 4 : 0] = load8(p + dz);
+            v[u][NSRC > 5 ? 5 : 0] = load8(p + dz + dx);
+            v[u][NSRC > 6 ? 6 : 0] = load8(p + dz + dy);
+            v[u][NSRC > 7 ? 7 : 0] = load8(p + dz + dy + dx);
+          }
         } else {
           v[u][0] = load8(p);
         }
@@ -116,21 +138,39 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       const int t = t0 + 256 * u;
       if (u < nslot && t < nchunk) {
         const int q = t / cg8, cg = t - q * cg8;
-        const int r = q / TW2, c = q - r * TW2;
-        const int yy = y0 - 1 + r, xx = x0 - 1 + c;
-        const bool valid = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const int pz = q / PLANE, rq = q - pz * PLANE, r = rq / TW2, c = rq - r * TW2;
+        const int zz = z0 - (NZ - 1) / 2 + pz, yy = y0 - 1 + r, xx = x0 - 1 + c;
+        const bool valid = zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
         bf16x8 o = zero8();
         if (MODE == 1) {
-          // 2 x 2 average with zero padding: children past the source edge count 0
+          // average with zero padding: children past the source edge count 0
           const bool hx = 2 * xx + 1 < a.src.Ws, hy = 2 * yy + 1 < a.src.Hs;
           const float w1 = hx ? 1.f : 0.f, w2 = hy ? 1.f : 0.f, w3 = (hx && hy) ? 1.f : 0.f;
+          if (NDIM == 3) {
+            const bool hz = 2 * zz + 1 < a.src.Ds;
+            const float w4 = hz ? 1.f : 0.f, w5 = hz && hx ? 1.f : 0.f, w6 = hz && hy ? 1.f : 0.f,
+                        w7 = hz && hx && hy ? 1.f : 0.f;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            float acc = (float)v[u][0][e];
-            acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
-            acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
-            acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
-            o[e] = (bf16)(0.25f * acc);
+            for (int e = 0; e < 8; ++e) {
+              float acc = (float)v[u][0][e];
+              acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
+              acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
+              acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
+              acc += w4 * (float)v[u][NSRC > 4 ? 4 : 0][e];
+              acc += w5 * (float)v[u][NSRC > 5 ? 5 : 0][e];
+              acc += w6 * (float)v[u][NSRC > 6 ? 6 : 0][e];
+              acc += w7 * (float)v[u][NSRC > 7 ? 7 : 0][e];
+              o[e] = (bf16)(0.125f * acc);
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              float acc = (float)v[u][0][e];
+              acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
+              acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
+              acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
+              o[e] = (bf16)(0.25f * acc);
+            }
           }
         } else {
           o = v[u][0];
@@ -145,7 +185,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // LDS offset of this lane's pixel in segment m (tap (0, 0) = top-left of the 3 x 3 window)
+  // LDS offset of this lane's pixel in segment m (tap (0, 0, 0) = the first plane's top-left)
   int base[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
@@ -154,18 +194,18 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   }
   // Two register sets, two k-steps per iteration: the operands of one step are read
   // (A from LDS, B = weights from global memory) while the MFMAs of the other run.
-  // Steps past the last tap (k >= 9 cin, up to the even step count) read A = 0.
+  // Steps past the last tap (k >= NT cin, up to the even step count) read A = 0.
   int tap = (8 * g) / cin, ci0 = 8 * g - tap * cin;  // k = 8 g at the first step
   const int dtap = cin < 32 ? 32 / cin : 0, dci = cin < 32 ? 0 : 32;
   const bf16* wrow = a.wt + (long long)i16 * a.kpad + 8 * g;
   const long long wstride = 16LL * a.kpad;
   auto read_step = [&](int kc, bf16x8* A, bf16x8* Bw) {
-    const int tc = min(tap, 8), dy = tc / 3, dx = tc - 3 * dy;
-    const int off = (dy * TW2 + dx) * ps + ci0;
+    const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
+    const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
-      A[m] = tap < 9 ? v : zero8();
+      A[m] = tap < NT ? v : zero8();
     }
     const int kw = min(kc, a.kpad - 32);
 #pragma unroll
@@ -203,7 +243,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     const int seg = wave * MT + m, r = seg / SEG;
     const int y = y0 + r, xo = x0 + (seg - r * SEG) * 16 + i16;
     if (y >= a.H || xo >= a.W) continue;
-    const long long p = (img * a.H + y) * a.W + xo;
+    const long long p = ((img * D + z0) * a.H + y) * a.W + xo;
 #pragma unroll
     for (int t = 0; t < NCO; ++t) {
       const int c0 = t * 16 + 4 * g;
@@ -237,16 +277,20 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
 // Block (k tile of 16, channel tile of 16, pixel chunk); each wavefront takes a
 // quarter of the chunk, the four partial tiles are summed in LDS and written
 // to part[chunk][co][k] (reduced in a fixed order by k_wgrad_reduce).
+template <int NDIM>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  constexpr int NT = NDIM == 3 ? 27 : 9;
   __shared__ float red[4][16][17];
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64, gq = l / 16, i16 = l % 16;
   const int kt = blockIdx.x, ct = blockIdx.y, chunk = blockIdx.z;
-  const long long P = (long long)a.nimg * a.H * a.W;
+  const int D = NDIM == 3 ? a.D : 1;
+  const long long P = (long long)a.nimg * D * a.H * a.W;
   const long long p_begin = (long long)chunk * a.chunk + (long long)wave * (a.chunk / 4);
   const long long p_end = min(p_begin + a.chunk / 4, P);
   const int krow = kt * 16 + i16;                  // A row of this lane
   const int tap = krow / a.cin, ci = krow - tap * a.cin;
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int dz = NDIM == 3 ? tap / 9 - 1 : 0, tp = NDIM == 3 ? tap % 9 : tap;
+  const int dy = tp / 3 - 1, dx = tp % 3 - 1;
   const int co = ct * 16 + i16;                    // B column of this lane
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (long long pc = p_begin; pc < p_end; pc += 32) {
@@ -259,8 +303,12 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         const int px = (int)(p % a.W);
         const long long r = p / a.W;
         const int py = (int)(r % a.H);
-        const int yy = py + dy, xx = px + dx;
-        if (tap < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) xa = fetch1(a.src, r / a.H, a.H, a.W, yy, xx, ci);
+        const long long r2 = r / a.H;
+        const int pz = NDIM == 3 ? (int)(r2 % D) : 0;
+        const long long img = NDIM == 3 ? r2 / D : r2;
+        const int zz = pz + dz, yy = py + dy, xx = px + dx;
+        if (tap < NT && zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          xa = fetch1<NDIM>(a.src, img, D, a.H, a.W, zz, yy, xx, ci);
         gb = (float)a.g[p * a.g_ct + co];
       }
       av[v] = (__bf16)xa;
@@ -316,39 +364,46 @@ __global__ void k_grad_prep(long long P, const float* g, int g_ct, int g_off, co
   gm[t] = (bf16)v;
 }
 
-// gin[p][off + c] += 1/4 g[parent(p)][c]   (fp32)
-__global__ void k_pool_back(int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
+// gin[p][off + c] += 2^-NDIM g[parent(p)][c]   (fp32; depth D = 1 in 2D)
+template <int NDIM>
+__global__ void k_pool_back(int nimg, int D, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
                             int gin_off) {
-  const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;
+  const int Dc = NDIM == 3 ? (D + 1) / 2 : 1, Hc = (H + 1) / 2, Wc = (W + 1) / 2;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nimg * H * W * C) return;
+  if (t >= (long long)nimg * D * H * W * C) return;
   const int c = (int)(t % C);
   const long long p = t / C;
   const int x = (int)(p % W);
   const long long r = p / W;
   const int y = (int)(r % H);
-  const long long img = r / H;
-  const long long q = (img * Hc + y / 2) * Wc + x / 2;
-  gin[p * gin_ct + gin_off + c] += 0.25f * g[q * g_ct + c];
+  const long long r2 = r / H;
+  const int z = NDIM == 3 ? (int)(r2 % D) : 0;
+  const long long img = NDIM == 3 ? r2 / D : r2;
+  const long long q = ((img * Dc + z / 2) * Hc + y / 2) * Wc + x / 2;
+  gin[p * gin_ct + gin_off + c] += (NDIM == 3 ? 0.125f : 0.25f) * g[q * g_ct + c];
 }
 
 // gc[q][c] = sum over the children p of q of g[p][off + c]   (fp32)
-__global__ void k_upsample_back(int nimg, int H, int W, int C, const float* g, int g_ct, int g_off, float* gc) {
-  const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;
+template <int NDIM>
+__global__ void k_upsample_back(int nimg, int D, int H, int W, int C, const float* g, int g_ct, int g_off, float* gc) {
+  const int Dc = NDIM == 3 ? (D + 1) / 2 : 1, Hc = (H + 1) / 2, Wc = (W + 1) / 2;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nimg * Hc * Wc * C) return;
+  if (t >= (long long)nimg * Dc * Hc * Wc * C) return;
   const int c = (int)(t % C);
   const long long q = t / C;
   const int X = (int)(q % Wc);
   const long long r = q / Wc;
   const int Y = (int)(r % Hc);
-  const long long img = r / Hc;
+  const long long r2 = r / Hc;
+  const int Z = NDIM == 3 ? (int)(r2 % Dc) : 0;
+  const long long img = NDIM == 3 ? r2 / Dc : r2;
   float s = 0.f;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int yy = 2 * Y + a, xx = 2 * X + b;
-      if (yy < H && xx < W) s += g[((img * H + yy) * W + xx) * g_ct + g_off + c];
-    }
+  for (int e = 0; e < (NDIM == 3 ? 2 : 1); ++e)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int zz = NDIM == 3 ? 2 * Z + e : 0, yy = 2 * Y + a, xx = 2 * X + b;
+        if (zz < D && yy < H && xx < W) s += g[(((img * D + zz) * H + yy) * W + xx) * g_ct + g_off + c];
+      }
   gc[q * C + c] = s;
 }
 
@@ -373,26 +428,46 @@ __global__ void k_loss(long long n, const float* y, const float* tgt, float inv_
 
 // Residual term of the training loss.  With r = (x0 + j x1), c = cb (1 + x2 + j x3)
 // taken from the FP32 network input x [P][4] and the output y [P][2] read as
-// complex, q = r - gamma A' y on the interior of every image (one-pixel
-// border excluded: the crop's neighbours outside it are unknown), where
-// A' y = (4 - c) y - (sum of the 4 neighbours).  part[block] = w/2 sum |q|^2.
-__global__ void k_res_q(int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb, float w,
+// complex, q = r - gamma A' y on the interior of every image (one-pixel border
+// excluded: the crop's neighbours outside it are unknown), where A' y =
+// (2 NDIM - c) y - (sum of the 2 NDIM neighbours).  part[block] = w/2 sum |q|^2.
+// Pixels are (image, z, y, x) with depth D (1 in 2D).
+template <int NDIM>
+__device__ __forceinline__ bool res_interior(long long p, int D, int H, int W) {
+  const int px = (int)(p % W), py = (int)((p / W) % H);
+  bool in = px > 0 && px < W - 1 && py > 0 && py < H - 1;
+  if (NDIM == 3) {
+    const int pz = (int)((p / ((long long)W * H)) % D);
+    in = in && pz > 0 && pz < D - 1;
+  }
+  return in;
+}
+
+// A' applied at an interior pixel p of the complex field f (interleaved pairs) with coefficient c
+template <int NDIM>
+__device__ __forceinline__ c32 res_apply(const float* f, long long p, int H, int W, c32 c) {
+  const long long sy = W, sz = (long long)W * H;
+  const c32 fc = make_float2(f[p * 2], f[p * 2 + 1]);
+  c32 nbs = make_float2(f[(p - 1) * 2] + f[(p + 1) * 2] + f[(p - sy) * 2] + f[(p + sy) * 2],
+                        f[(p - 1) * 2 + 1] + f[(p + 1) * 2 + 1] + f[(p - sy) * 2 + 1] + f[(p + sy) * 2 + 1]);
+  if (NDIM == 3)
+    nbs = cadd(nbs, make_float2(f[(p - sz) * 2] + f[(p + sz) * 2], f[(p - sz) * 2 + 1] + f[(p + sz) * 2 + 1]));
+  return csub(cmul(make_float2((float)(2 * NDIM) - c.x, -c.y), fc), nbs);
+}
+
+template <int NDIM>
+__global__ void k_res_q(int nimg, int D, int H, int W, const float* x, const float* y, float gamma, c32 cb, float w,
                         float2* q, float* part) {
   __shared__ float red[256];
-  const long long P = (long long)nimg * H * W;
+  const long long P = (long long)nimg * D * H * W;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   float s = 0.f;
   if (p < P) {
-    const int px = (int)(p % W), py = (int)((p / W) % H);
     float2 qq = make_float2(0.f, 0.f);
-    if (px > 0 && px < W - 1 && py > 0 && py < H - 1) {
+    if (res_interior<NDIM>(p, D, H, W)) {
       const float* xp = x + p * 4;
-      const c32 f = make_float2(xp[2], xp[3]);
-      const c32 c = cmul(cb, make_float2(1.f + f.x, f.y));
-      const c32 yc = make_float2(y[p * 2], y[p * 2 + 1]);
-      const c32 nbs = make_float2(y[(p - 1) * 2] + y[(p + 1) * 2] + y[(p - W) * 2] + y[(p + W) * 2],
-                                  y[(p - 1) * 2 + 1] + y[(p + 1) * 2 + 1] + y[(p - W) * 2 + 1] + y[(p + W) * 2 + 1]);
-      const c32 ay = csub(cmul(make_float2(4.f - c.x, -c.y), yc), nbs);
+      const c32 c = cmul(cb, make_float2(1.f + xp[2], xp[3]));
+      const c32 ay = res_apply<NDIM>(y, p, H, W, c);
       qq = make_float2(xp[0] - gamma * ay.x, xp[1] - gamma * ay.y);
       s = 0.5f * w * (qq.x * qq.x + qq.y * qq.y);
     }
@@ -407,11 +482,12 @@ __global__ void k_res_q(int nimg, int H, int W, const float* x, const float* y, 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// gy += -w gamma A'^H q, A'^H q = (4 - conj c) q - (sum of the neighbours of q); q is zero
+// gy += -w gamma A'^H q, A'^H q = (2 NDIM - conj c) q - (sum of the neighbours of q); q is zero
 // on the border, and neighbours outside the image count as zero.
-__global__ void k_res_grad(int nimg, int H, int W, const float* x, const float2* q, float gamma, c32 cb, float w,
-                           float* gy) {
-  const long long P = (long long)nimg * H * W;
+template <int NDIM>
+__global__ void k_res_grad(int nimg, int D, int H, int W, const float* x, const float2* q, float gamma, c32 cb,
+                           float w, float* gy) {
+  const long long P = (long long)nimg * D * H * W;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const int px = (int)(p % W), py = (int)((p / W) % H);
@@ -422,27 +498,31 @@ __global__ void k_res_grad(int nimg, int H, int W, const float* x, const float2*
   if (px < W - 1) nbs = cadd(nbs, q[p + 1]);
   if (py > 0) nbs = cadd(nbs, q[p - W]);
   if (py < H - 1) nbs = cadd(nbs, q[p + W]);
-  const c32 g = csub(cmul(make_float2(4.f - c.x, c.y), q[p]), nbs);
+  if (NDIM == 3) {
+    const long long sz = (long long)W * H;
+    const int pz = (int)((p / sz) % D);
+    if (pz > 0) nbs = cadd(nbs, q[p - sz]);
+    if (pz < D - 1) nbs = cadd(nbs, q[p + sz]);
+  }
+  const c32 g = csub(cmul(make_float2((float)(2 * NDIM) - c.x, c.y), q[p]), nbs);
   gy[p * 2] -= w * gamma * g.x;
   gy[p * 2 + 1] -= w * gamma * g.y;
 }
 
 // Per image: sums over the interior of |r - gamma A' y|^2 and |r|^2 (r, c, y as in k_res_q),
 // one block per image, fixed-order reduction; sums[2 img], sums[2 img + 1].
-__global__ __launch_bounds__(256) void k_res_ratio(int H, int W, const float* x, const float* y, float gamma, c32 cb,
-                                                   double* sums) {
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_res_ratio(int D, int H, int W, const float* x, const float* y, float gamma,
+                                                   c32 cb, double* sums) {
   __shared__ double red[2][256 / HELM_WAVE];
-  const long long img = blockIdx.x, base = img * H * W;
+  const long long img = blockIdx.x, npx = (long long)D * H * W, base = img * npx;
   double sq = 0.0, sr = 0.0;
-  for (int t = threadIdx.x; t < (H - 2) * (W - 2); t += 256) {
-    const int py = 1 + t / (W - 2), px = 1 + t % (W - 2);
-    const long long p = base + (long long)py * W + px;
+  for (long long t = threadIdx.x; t < npx; t += 256) {
+    const long long p = base + t;
+    if (!res_interior<NDIM>(p, D, H, W)) continue;
     const float* xp = x + p * 4;
     const c32 c = cmul(cb, make_float2(1.f + xp[2], xp[3]));
-    const c32 yc = make_float2(y[p * 2], y[p * 2 + 1]);
-    const c32 nbs = make_float2(y[(p - 1) * 2] + y[(p + 1) * 2] + y[(p - W) * 2] + y[(p + W) * 2],
-                                y[(p - 1) * 2 + 1] + y[(p + 1) * 2 + 1] + y[(p - W) * 2 + 1] + y[(p + W) * 2 + 1]);
-    const c32 ay = csub(cmul(make_float2(4.f - c.x, -c.y), yc), nbs);
+    const c32 ay = res_apply<NDIM>(y, p, H, W, c);
     const float qx = xp[0] - gamma * ay.x, qy = xp[1] - gamma * ay.y;
     sq += (double)qx * qx + (double)qy * qy;
     sr += (double)xp[0] * xp[0] + (double)xp[1] * xp[1];
@@ -478,16 +558,18 @@ __global__ void k_adam(int n, float* w, const float* dw, float* m, float* v, con
   w[t] -= lr * (mt * c1) / (sqrtf(vt * c2) + eps);
 }
 
-// Pack FP32 master weights W[co][k] (k = tap * cin + ci) into the BF16 forward
-// layout and the BF16 backward-data layout Wb[ci][tap' * cob + co] = W[co][(8 - tap') * cin + ci].
-__global__ void k_pack(int cout_pad, int cin, int kpad, int cob, int kbpad, const float* w, bf16* wt, bf16* wb) {
+// Pack FP32 master weights W[co][k] (k = tap * cin + ci) into the BF16 forward layout and the
+// BF16 backward-data layout Wb[ci][tap' * cob + co] = W[co][(ntaps - 1 - tap') * cin + ci]
+// (wb_rows >= cin rows; rows past cin, read by the last output tile, are zero).
+__global__ void k_pack(int ntaps, int cout_pad, int cin, int kpad, int cob, int kbpad, int wb_rows, const float* w,
+                       bf16* wt, bf16* wb) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < cout_pad * kpad) wt[t] = (bf16)w[t];
-  if (wb && t < cin * kbpad) {
+  if (wb && t < wb_rows * kbpad) {
     const int ci = t / kbpad, kb = t % kbpad;
     const int tapb = kb / cob, co = kb - tapb * cob;
     float v = 0.f;
-    if (tapb < 9 && co < cout_pad) v = w[(long long)co * kpad + (8 - tapb) * cin + ci];
+    if (ci < cin && tapb < ntaps && co < cout_pad) v = w[(long long)co * kpad + (ntaps - 1 - tapb) * cin + ci];
     wb[t] = (bf16)v;
   }
 }
@@ -557,27 +639,32 @@ __global__ __launch_bounds__(256) void k_field_sumsq(long long N, const c32* r, 
 
 // One block per crop: features (r_scale r / rms, contrast) and target (x* - x_k) / rms / gamma,
 // with rms the root mean square of r_scale r[b] over the whole grid of its right-hand side.
+// Crop c = (rhs, (z0,) y0, x0) of S^NDIM points.
+template <int NDIM>
 __global__ __launch_bounds__(256) void k_examples(int S, int n_e, const int* crops, const float* ss, const c32* r,
                                                   const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb,
                                                   float r_scale, float inv_gamma, float* feat, float* tgt) {
   const int c = blockIdx.x;
-  const int b = crops[3 * c], y0 = crops[3 * c + 1], x0 = crops[3 * c + 2];
+  const int* cr = crops + (1 + NDIM) * c;
+  const int b = cr[0], z0 = NDIM == 3 ? cr[1] : 0, y0 = cr[NDIM - 1], x0 = cr[NDIM];
   const long long base = (long long)b * N;
   const float rms = sqrtf(ss[b] / (float)N);
   const float inv = rms > 0.f ? 1.f / rms : 0.f;
   const float invc = 1.f / (cb.x * cb.x + cb.y * cb.y);
-  for (int t = threadIdx.x; t < S * S; t += 256) {
-    const long long p = (long long)(y0 + t / S) * n_e + (x0 + t % S);
+  const long long npx = NDIM == 3 ? (long long)S * S * S : (long long)S * S;
+  for (long long t = threadIdx.x; t < npx; t += 256) {
+    const int tx = (int)(t % S), ty = (int)((t / S) % S), tz = NDIM == 3 ? (int)(t / ((long long)S * S)) : 0;
+    const long long p = ((long long)(z0 + tz) * n_e + (y0 + ty)) * n_e + (x0 + tx);
     const c32 v = cscale(r[base + p], r_scale * inv);
     const c32 e = cscale(csub(xfin[base + p], xk[base + p]), inv * inv_gamma);
     const c32 cc = coef[p];
     const c32 d = make_float2(cc.x - cb.x, cc.y - cb.y);
-    float* f = feat + ((long long)c * S * S + t) * 4;
+    float* f = feat + ((long long)c * npx + t) * 4;
     f[0] = v.x;
     f[1] = v.y;
     f[2] = (d.x * cb.x + d.y * cb.y) * invc;
     f[3] = (d.y * cb.x - d.x * cb.y) * invc;
-    float* o = tgt + ((long long)c * S * S + t) * 2;
+    float* o = tgt + ((long long)c * npx + t) * 2;
     o[0] = e.x;
     o[1] = e.y;
   }
@@ -590,44 +677,62 @@ inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 void launch_to_bf16_pad(hipStream_t s, long long P, int cin, const float* x, int cpad, bf16* out) {
   hipLaunchKernelGGL(k_to_bf16_pad, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, cin, x, cpad, out);
 }
-void launch_examples(hipStream_t s, int B, int ncrop, int S, int n_e, const int* crops, float* ss, const c32* r,
-                     const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb, float r_scale,
-                     float inv_gamma, float* feat, float* tgt) {
+void launch_examples(hipStream_t s, int dim, int B, int ncrop, int S, int n_e, const int* crops, float* ss,
+                     const c32* r, const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb,
+                     float r_scale, float inv_gamma, float* feat, float* tgt) {
   hipLaunchKernelGGL(k_field_sumsq, dim3(B), dim3(256), 0, s, N, r, r_scale, ss);
-  hipLaunchKernelGGL(k_examples, dim3(ncrop), dim3(256), 0, s, S, n_e, crops, ss, r, xfin, xk, N, coef, cb, r_scale,
-                     inv_gamma, feat, tgt);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_examples<3>, dim3(ncrop), dim3(256), 0, s, S, n_e, crops, ss, r, xfin, xk, N, coef, cb,
+                       r_scale, inv_gamma, feat, tgt);
+  else
+    hipLaunchKernelGGL(k_examples<2>, dim3(ncrop), dim3(256), 0, s, S, n_e, crops, ss, r, xfin, xk, N, coef, cb,
+                       r_scale, inv_gamma, feat, tgt);
 }
 
-template <int NCO, int TH, int TW>
+template <int NCO, int TH, int TW, int NDIM>
 void conv_lds(hipStream_t s, const ConvArgs& a) {
-  const size_t lds = (size_t)(TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
-  const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg);
-  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1>), grid, dim3(256), lds, s, a);
-  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2>), grid, dim3(256), lds, s, a);
-  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0>), grid, dim3(256), lds, s, a);
+  const size_t lds = (size_t)(NDIM == 3 ? 3 : 1) * (TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
+  const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * (NDIM == 3 ? a.D : 1));
+  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM>), grid, dim3(256), lds, s, a);
+  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM>), grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM>), grid, dim3(256), lds, s, a);
 }
 
-// Tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile
-// stays within 50 KB of LDS and the accumulators within 64 registers, else 4 x 32.
-void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco) {
+// 2D tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile stays
+// within 50 KB of LDS and the accumulators within 64 registers, else 4 x 32.  3D: three
+// staged planes, so 4 x 32 up to 32 input channels and 2 x 32 above (under 60 KB).
+void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim) {
+  if (dim == 3) {
+    const bool wide = a.cin > 32;
+    switch (nco) {
+      case 1: wide ? conv_lds<1, 2, 32, 3>(s, a) : conv_lds<1, 4, 32, 3>(s, a); break;
+      case 2: wide ? conv_lds<2, 2, 32, 3>(s, a) : conv_lds<2, 4, 32, 3>(s, a); break;
+      case 3: wide ? conv_lds<3, 2, 32, 3>(s, a) : conv_lds<3, 4, 32, 3>(s, a); break;
+      case 4: wide ? conv_lds<4, 2, 32, 3>(s, a) : conv_lds<4, 4, 32, 3>(s, a); break;
+      default: break;
+    }
+    return;
+  }
   const bool big = a.cin > 64 || nco > 4;
   switch (nco) {
-    case 1: big ? conv_lds<1, 4, 32>(s, a) : conv_lds<1, 8, 32>(s, a); break;
-    case 2: big ? conv_lds<2, 4, 32>(s, a) : conv_lds<2, 8, 32>(s, a); break;
-    case 3: big ? conv_lds<3, 4, 32>(s, a) : conv_lds<3, 8, 32>(s, a); break;
-    case 4: big ? conv_lds<4, 4, 32>(s, a) : conv_lds<4, 8, 32>(s, a); break;
-    case 6: conv_lds<6, 4, 32>(s, a); break;
-    case 8: conv_lds<8, 4, 32>(s, a); break;
+    case 1: big ? conv_lds<1, 4, 32, 2>(s, a) : conv_lds<1, 8, 32, 2>(s, a); break;
+    case 2: big ? conv_lds<2, 4, 32, 2>(s, a) : conv_lds<2, 8, 32, 2>(s, a); break;
+    case 3: big ? conv_lds<3, 4, 32, 2>(s, a) : conv_lds<3, 8, 32, 2>(s, a); break;
+    case 4: big ? conv_lds<4, 4, 32, 2>(s, a) : conv_lds<4, 8, 32, 2>(s, a); break;
+    case 6: conv_lds<6, 4, 32, 2>(s, a); break;
+    case 8: conv_lds<8, 4, 32, 2>(s, a); break;
     default: break;
   }
 }
 
 void launch_wgrad(hipStream_t s, const WgradArgs& a, int nchunk, float* dw, const bf16* g_for_bias, float* db,
                   int cout_real) {
-  hipLaunchKernelGGL(k_wgrad, dim3(a.kpad / 16, a.cout_pad / 16, nchunk), dim3(256), 0, s, a);
+  const dim3 grid(a.kpad / 16, a.cout_pad / 16, nchunk);
+  if (a.dim == 3) hipLaunchKernelGGL(k_wgrad<3>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, a);
   const int n = a.cout_pad * a.kpad;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(n, 256)), dim3(256), 0, s, nchunk, n, a.part, dw);
-  const long long P = (long long)a.nimg * a.H * a.W;
+  const long long P = (long long)a.nimg * (a.dim == 3 ? a.D : 1) * a.H * a.W;
   hipLaunchKernelGGL(k_bias_grad, dim3(cout_real), dim3(256), 0, s, P, g_for_bias, a.g_ct, db);
 }
 
@@ -636,39 +741,54 @@ void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int 
   hipLaunchKernelGGL(k_grad_prep, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, g, g_ct, g_off, act, act_ct, act_off,
                      creal, cpad, gm);
 }
-void launch_pool_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, float* gin, int gin_ct,
-                      int gin_off) {
-  const long long n = (long long)nimg * H * W * C;
-  hipLaunchKernelGGL(k_pool_back, dim3(nb(n, 256)), dim3(256), 0, s, nimg, H, W, C, g, g_ct, gin, gin_ct, gin_off);
+void launch_pool_back(hipStream_t s, int dim, int nimg, int D, int H, int W, int C, const float* g, int g_ct,
+                      float* gin, int gin_ct, int gin_off) {
+  const long long n = (long long)nimg * D * H * W * C;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_pool_back<3>, dim3(nb(n, 256)), dim3(256), 0, s, nimg, D, H, W, C, g, g_ct, gin, gin_ct,
+                       gin_off);
+  else
+    hipLaunchKernelGGL(k_pool_back<2>, dim3(nb(n, 256)), dim3(256), 0, s, nimg, 1, H, W, C, g, g_ct, gin, gin_ct,
+                       gin_off);
 }
-void launch_upsample_back(hipStream_t s, int nimg, int H, int W, int C, const float* g, int g_ct, int g_off,
-                          float* gc) {
-  const long long n = (long long)nimg * ((H + 1) / 2) * ((W + 1) / 2) * C;
-  hipLaunchKernelGGL(k_upsample_back, dim3(nb(n, 256)), dim3(256), 0, s, nimg, H, W, C, g, g_ct, g_off, gc);
+void launch_upsample_back(hipStream_t s, int dim, int nimg, int D, int H, int W, int C, const float* g, int g_ct,
+                          int g_off, float* gc) {
+  const long long n = (long long)nimg * (dim == 3 ? (D + 1) / 2 : 1) * ((H + 1) / 2) * ((W + 1) / 2) * C;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_upsample_back<3>, dim3(nb(n, 256)), dim3(256), 0, s, nimg, D, H, W, C, g, g_ct, g_off, gc);
+  else
+    hipLaunchKernelGGL(k_upsample_back<2>, dim3(nb(n, 256)), dim3(256), 0, s, nimg, 1, H, W, C, g, g_ct, g_off, gc);
 }
 int loss_partials(long long n) { return (int)nb(n, 256); }
 void launch_loss(hipStream_t s, long long n, const float* y, const float* tgt, float inv_nimg, float* gy,
                  float* part) {
   hipLaunchKernelGGL(k_loss, dim3(nb(n, 256)), dim3(256), 0, s, n, y, tgt, inv_nimg, gy, part);
 }
-void launch_res_loss(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
-                     float w, float2* q, float* part, float* gy) {
-  const long long P = (long long)nimg * H * W;
-  hipLaunchKernelGGL(k_res_q, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, y, gamma, cb, w, q, part);
-  hipLaunchKernelGGL(k_res_grad, dim3(nb(P, 256)), dim3(256), 0, s, nimg, H, W, x, q, gamma, cb, w, gy);
+void launch_res_loss(hipStream_t s, int dim, int nimg, int D, int H, int W, const float* x, const float* y,
+                     float gamma, c32 cb, float w, float2* q, float* part, float* gy) {
+  const long long P = (long long)nimg * D * H * W;
+  if (dim == 3) {
+    hipLaunchKernelGGL(k_res_q<3>, dim3(nb(P, 256)), dim3(256), 0, s, nimg, D, H, W, x, y, gamma, cb, w, q, part);
+    hipLaunchKernelGGL(k_res_grad<3>, dim3(nb(P, 256)), dim3(256), 0, s, nimg, D, H, W, x, q, gamma, cb, w, gy);
+  } else {
+    hipLaunchKernelGGL(k_res_q<2>, dim3(nb(P, 256)), dim3(256), 0, s, nimg, 1, H, W, x, y, gamma, cb, w, q, part);
+    hipLaunchKernelGGL(k_res_grad<2>, dim3(nb(P, 256)), dim3(256), 0, s, nimg, 1, H, W, x, q, gamma, cb, w, gy);
+  }
 }
-void launch_res_ratio(hipStream_t s, int nimg, int H, int W, const float* x, const float* y, float gamma, c32 cb,
-                      double* sums) {
-  hipLaunchKernelGGL(k_res_ratio, dim3(nimg), dim3(256), 0, s, H, W, x, y, gamma, cb, sums);
+void launch_res_ratio(hipStream_t s, int dim, int nimg, int D, int H, int W, const float* x, const float* y,
+                      float gamma, c32 cb, double* sums) {
+  if (dim == 3) hipLaunchKernelGGL(k_res_ratio<3>, dim3(nimg), dim3(256), 0, s, D, H, W, x, y, gamma, cb, sums);
+  else hipLaunchKernelGGL(k_res_ratio<2>, dim3(nimg), dim3(256), 0, s, 1, H, W, x, y, gamma, cb, sums);
 }
 void launch_adam(hipStream_t s, int n, float* w, const float* dw, float* m, float* v, const unsigned char* mask,
                  float lr, float b1, float b2, float eps, float c1, float c2) {
   hipLaunchKernelGGL(k_adam, dim3(nb(n, 256)), dim3(256), 0, s, n, w, dw, m, v, mask, lr, b1, b2, eps, c1, c2);
 }
-void launch_pack(hipStream_t s, int cout_pad, int cin, int kpad, int cob, int kbpad, const float* w, bf16* wt,
-                 bf16* wb) {
-  const int n = std::max(cout_pad * kpad, wb ? cin * kbpad : 0);
-  hipLaunchKernelGGL(k_pack, dim3(nb(n, 256)), dim3(256), 0, s, cout_pad, cin, kpad, cob, kbpad, w, wt, wb);
+void launch_pack(hipStream_t s, int ntaps, int cout_pad, int cin, int kpad, int cob, int kbpad, int wb_rows,
+                 const float* w, bf16* wt, bf16* wb) {
+  const int n = std::max(cout_pad * kpad, wb ? wb_rows * kbpad : 0);
+  hipLaunchKernelGGL(k_pack, dim3(nb(n, 256)), dim3(256), 0, s, ntaps, cout_pad, cin, kpad, cob, kbpad, wb_rows, w,
+                     wt, wb);
 }
 void launch_net_input(hipStream_t s, int B, long long N, const c32* v, long long v_stride, const float* vscale,
                       int vs_stride, float gain, const c32* coef, c32 cb, bf16* x, int x_ct) {

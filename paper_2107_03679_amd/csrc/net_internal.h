@@ -15,14 +15,16 @@ struct NetLayer {
 };
 
 struct helm_net;
-struct NetSolveBufs;  // activation buffers of one solver context's network applications
+struct NetSolveBufs;
 
-// Buffers for network applications on up to B solver-grid images of ngrid x ngrid (2D),
+int net_dim(const helm_net* n);  // 2 or 3  // activation buffers of one solver context's network applications
+
+// Buffers for network applications on up to B solver-grid images of ngrid^dim points,
 // owned by the solver context that reserves them (one network may serve several contexts
 // of different sizes); freed by net_bufs_destroy.
 NetSolveBufs* net_bufs_create(helm_net* n, int B, int ngrid);
 void net_bufs_destroy(NetSolveBufs* b);
-// Preconditioner application on B <= the reserved count of images (n x n, 2D): features
+// Preconditioner application on B <= the reserved count of images (ngrid^dim): features
 // from the basis vectors v (scaled by vscale and in_gain) and the coefficient contrast,
 // z = out_gain * network output for the right-hand sides in `mask`.  Returns
 // hipErrorInvalidValue (and launches nothing) when B or ngrid do not fit the buffers.

@@ -81,7 +81,8 @@ EXPORTS = [
     "helm_update_f", "helm_grad_f", "helm_data_residual", "helm_tv_prox", "helm_fbs_step",
     "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
     "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio", "helm_update_contrast",
-    "helm_grad_contrast", "helm_data_residual_static",
+    "helm_grad_contrast", "helm_data_residual_static", "helm_net_create3", "helm_net_dim", "helm_net_shape",
+    "helm_net_forward3", "helm_net_backward3", "helm_net_residual_ratio3",
 ]
 
 _lib = None
@@ -125,6 +126,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      ctypes.POINTER(d)]
     lib.helm_net_layer_shape.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.helm_net_create.argtypes = [ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+    lib.helm_net_create3.argtypes = [ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+    lib.helm_net_dim.argtypes = [vp]
+    lib.helm_net_shape.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.helm_net_forward3.argtypes = [vp, i, i, i, i, vp, vp]
+    lib.helm_net_backward3.argtypes = [vp, i, i, i, i, vp, vp, ctypes.POINTER(d)]
+    lib.helm_net_residual_ratio3.argtypes = [vp, i, i, i, i, vp, d, d, vp]
     lib.helm_net_destroy.argtypes = [vp]
     lib.helm_net_destroy.restype = None
     lib.helm_net_last_error.argtypes = [vp]
@@ -544,10 +551,10 @@ class Context:
     def net_examples(self, r: torch.Tensor, x_final: torch.Tensor, x_k: torch.Tensor, crops: np.ndarray, size: int,
                      gamma: float):
         """Training examples (features [n][S][S][4], targets [n][S][S][2]) from solver snapshots."""
-        crops = np.ascontiguousarray(np.asarray(crops, dtype=np.int32).reshape(-1, 3))
+        crops = np.ascontiguousarray(np.asarray(crops, dtype=np.int32).reshape(-1, 1 + self.dim))
         n = crops.shape[0]
-        feat = torch.empty((n, size, size, 4), dtype=torch.float32, device=self.device)
-        tgt = torch.empty((n, size, size, 2), dtype=torch.float32, device=self.device)
+        feat = torch.empty((n, *((size,) * self.dim), 4), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((n, *((size,) * self.dim), 2), dtype=torch.float32, device=self.device)
         B = r.shape[0]
         rc = self.lib.helm_net_examples(self._h, B, self._f(r, B), self._f(x_final, B), self._f(x_k, B), n,
                                         crops.ctypes.data_as(ctypes.c_void_p), size, gamma, _ptr(feat), _ptr(tgt))
@@ -619,20 +626,26 @@ class Context:
 
 
 class Net:
-    """The learned-preconditioner U-Net (helm_net_*): BF16 MFMA kernels, FP32 master weights."""
+    """The learned-preconditioner U-Net (helm_net_*): BF16 MFMA kernels, FP32 master weights.
+    dim 2: 3x3 convolutions on images [n, H, W, 4]; dim 3: 3x3x3 convolutions on volumes
+    [n, D, H, W, 4]."""
 
-    def __init__(self, seed: int = 0, stream: torch.cuda.Stream | None = None):
+    def __init__(self, seed: int = 0, stream: torch.cuda.Stream | None = None, dim: int = 2):
+        if dim not in (2, 3):
+            raise HelmError("dim must be 2 or 3")
         self.lib = load_library()
+        self.dim = dim
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        rc = self.lib.helm_net_create(seed, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        create = self.lib.helm_net_create3 if dim == 3 else self.lib.helm_net_create
+        rc = create(seed, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if rc != HELM_OK:
             raise HelmError(f"helm_net_create failed ({rc})")
         self._h = h
         self.shapes = []
         for i in range(self.lib.helm_net_layers()):
             ci, co = ctypes.c_int(), ctypes.c_int()
-            self.lib.helm_net_layer_shape(i, ctypes.byref(ci), ctypes.byref(co))
+            self.lib.helm_net_shape(self._h, i, ctypes.byref(ci), ctypes.byref(co))
             self.shapes.append((ci.value, co.value))
 
     NAMES = ("A0", "A1", "A2", "A3", "B2", "B1", "B0", "O")
@@ -642,7 +655,7 @@ class Net:
             raise HelmError(f"{what} failed ({rc}): {self.lib.helm_net_last_error(self._h).decode()}")
 
     def set_params(self, params: dict):
-        """params: {name + '.w': [3][3][cin][cout], name + '.b': [cout]} (any float dtype)."""
+        """params: {name + '.w': [3][3]([3])[cin][cout], name + '.b': [cout]} (any float dtype)."""
         for i, name in enumerate(self.NAMES):
             w = np.ascontiguousarray(params[name + ".w"], dtype=np.float32)
             b = np.ascontiguousarray(params[name + ".b"], dtype=np.float32)
@@ -653,7 +666,7 @@ class Net:
         out = {}
         for i, name in enumerate(self.NAMES):
             ci, co = self.shapes[i]
-            w = np.zeros((3, 3, ci, co), dtype=np.float32)
+            w = np.zeros((3,) * self.dim + (ci, co), dtype=np.float32)
             b = np.zeros(co, dtype=np.float32)
             self._check(fn(self._h, i, w.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p)),
                         "helm_net_get")
@@ -666,39 +679,53 @@ class Net:
     def grads(self) -> dict:
         return self._get(self.lib.helm_net_get_grad)
 
-    @staticmethod
-    def _input(x: torch.Tensor) -> torch.Tensor:
+    def _input(self, x: torch.Tensor) -> torch.Tensor:
         x = x.contiguous()
-        if x.dtype != torch.float32 or x.dim() != 4 or x.shape[3] != 4:
-            raise HelmError(f"network inputs must be float32 [n, H, W, 4], got {x.dtype} {list(x.shape)}")
+        if x.dtype != torch.float32 or x.dim() != 2 + self.dim or x.shape[-1] != 4:
+            lay = "[n, H, W, 4]" if self.dim == 2 else "[n, D, H, W, 4]"
+            raise HelmError(f"network inputs must be float32 {lay}, got {x.dtype} {list(x.shape)}")
         return x
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         x = self._input(x)
-        n, h, w, _ = x.shape
-        y = torch.empty((n, h, w, 2), dtype=torch.float32, device=x.device)
-        self._check(self.lib.helm_net_forward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(y)), "helm_net_forward")
+        y = torch.empty((*x.shape[:-1], 2), dtype=torch.float32, device=x.device)
+        if self.dim == 3:
+            n, dd, h, w, _ = x.shape
+            rc = self.lib.helm_net_forward3(self._h, n, dd, h, w, _ptr(x), _ptr(y))
+        else:
+            n, h, w, _ = x.shape
+            rc = self.lib.helm_net_forward(self._h, n, h, w, _ptr(x), _ptr(y))
+        self._check(rc, "helm_net_forward")
         return y
 
     def backward(self, x: torch.Tensor, target: torch.Tensor) -> float:
         x = self._input(x)
-        n, h, w, _ = x.shape
-        if target.dtype != torch.float32 or tuple(target.shape) != (n, h, w, 2):
-            raise HelmError(f"targets must be float32 [{n}, {h}, {w}, 2], got {target.dtype} {list(target.shape)}")
+        target = target.contiguous()
+        if target.dtype != torch.float32 or tuple(target.shape) != (*x.shape[:-1], 2):
+            raise HelmError(f"targets must be float32 {list(x.shape[:-1]) + [2]}, got {target.dtype} "
+                            f"{list(target.shape)}")
         loss = ctypes.c_double()
-        self._check(self.lib.helm_net_backward(self._h, n, h, w, _ptr(x.contiguous()), _ptr(target.contiguous()),
-                                               ctypes.byref(loss)), "helm_net_backward")
+        if self.dim == 3:
+            n, dd, h, w, _ = x.shape
+            rc = self.lib.helm_net_backward3(self._h, n, dd, h, w, _ptr(x), _ptr(target), ctypes.byref(loss))
+        else:
+            n, h, w, _ = x.shape
+            rc = self.lib.helm_net_backward(self._h, n, h, w, _ptr(x), _ptr(target), ctypes.byref(loss))
+        self._check(rc, "helm_net_backward")
         return loss.value
 
     def residual_ratio(self, x: torch.Tensor, gamma: float, cb: float) -> np.ndarray:
         """Per example ||r - gamma A' net(x)|| / ||r|| over the image interior (library kernel)."""
-        x = x.contiguous()
-        if x.dtype != torch.float32 or x.dim() != 4 or x.shape[3] != 4:
-            raise HelmError("network inputs must be float32 [n, H, W, 4]")
-        n, h, w, _ = x.shape
-        out = np.zeros(n, dtype=np.float64)
-        self._check(self.lib.helm_net_residual_ratio(self._h, n, h, w, _ptr(x), float(gamma), float(cb),
-                                                     out.ctypes.data_as(ctypes.c_void_p)), "helm_net_residual_ratio")
+        x = self._input(x)
+        out = np.zeros(x.shape[0], dtype=np.float64)
+        ptr = out.ctypes.data_as(ctypes.c_void_p)
+        if self.dim == 3:
+            n, dd, h, w, _ = x.shape
+            rc = self.lib.helm_net_residual_ratio3(self._h, n, dd, h, w, _ptr(x), float(gamma), float(cb), ptr)
+        else:
+            n, h, w, _ = x.shape
+            rc = self.lib.helm_net_residual_ratio(self._h, n, h, w, _ptr(x), float(gamma), float(cb), ptr)
+        self._check(rc, "helm_net_residual_ratio")
         return out
 
     def set_loss(self, err_weight: float = 1.0, res_weight: float = 0.0, gamma: float = 1.0, cb: float = 1.0):

@@ -27,8 +27,8 @@ from . import helm
 
 @dataclass
 class Examples:
-    feat: torch.Tensor  # [n][S][S][4] float32: Re r, Im r, Re and Im of (c - c_b) / c_b
-    tgt: torch.Tensor   # [n][S][S][2] float32: Re e, Im e (divided by gamma)
+    feat: torch.Tensor  # [n][S]^dim[4] float32: Re r, Im r, Re and Im of (c - c_b) / c_b
+    tgt: torch.Tensor   # [n][S]^dim[2] float32: Re e, Im e (divided by gamma)
     gamma: float
     cb: float  # (k_b h)^2: the background coefficient the contrast features are relative to
     solve_iters: list = field(default_factory=list)
@@ -36,8 +36,8 @@ class Examples:
 
 def collect(ctx: helm.Context, rhs_batches, size: int, crops_per_snapshot: int, every_cycles: int,
             max_snaps: int, seed: int, out: Examples | None = None) -> Examples:
-    """Solve each batch in `rhs_batches` (device tensors [B][n_e][n_e]) with snapshots and
-    cut `crops_per_snapshot` random crops of size x size from every (snapshot, RHS)."""
+    """Solve each batch in `rhs_batches` (device tensors [B][n_e]^dim) with snapshots and
+    cut `crops_per_snapshot` random crops of size^dim from every (snapshot, RHS)."""
     rng = np.random.default_rng(seed)
     ne = ctx.info.n_e
     feats, tgts, iters = [], [], []
@@ -49,8 +49,8 @@ def collect(ctx: helm.Context, rhs_batches, size: int, crops_per_snapshot: int, 
             xk = snaps[k].contiguous()
             r = ctx.residual(rhs, xk)
             ncrop = B * crops_per_snapshot
-            crops = np.stack([np.repeat(np.arange(B), crops_per_snapshot),
-                              rng.integers(0, ne - size + 1, ncrop), rng.integers(0, ne - size + 1, ncrop)], axis=1)
+            crops = np.stack([np.repeat(np.arange(B), crops_per_snapshot)]
+                             + [rng.integers(0, ne - size + 1, ncrop) for _ in range(ctx.dim)], axis=1)
             f, t = ctx.net_examples(r, x, xk, crops, size, gamma=1.0)
             feats.append(f)
             tgts.append(t)
@@ -74,32 +74,40 @@ def rescaled(ctx: helm.Context, ex: Examples, gamma: float) -> Examples:
 
 
 def _augment(x: torch.Tensor, y: torch.Tensor, k: int):
-    """One of the 8 symmetries of the square (flips and transposition of the two image axes)."""
+    """One of 8 symmetries of the grid: in 2D the flips and the transposition of the two image axes,
+    in 3D the flips of the three axes."""
     if k & 1:
         x, y = x.flip(1), y.flip(1)
     if k & 2:
         x, y = x.flip(2), y.flip(2)
     if k & 4:
-        x, y = x.transpose(1, 2), y.transpose(1, 2)
+        if x.dim() == 5:
+            x, y = x.flip(3), y.flip(3)
+        else:
+            x, y = x.transpose(1, 2), y.transpose(1, 2)
     return x.contiguous(), y.contiguous()
 
 
 LAYERS = (("A0", 4, 16, 0), ("A1", 16, 32, 1), ("A2", 32, 64, 2), ("A3", 64, 64, 3),
           ("B2", 128, 64, 2), ("B1", 96, 32, 1), ("B0", 48, 16, 0), ("O", 16, 2, 0))
+LAYERS3 = (("A0", 4, 16, 0), ("A1", 16, 16, 1), ("A2", 16, 32, 2), ("A3", 32, 32, 3),
+           ("B2", 64, 32, 2), ("B1", 48, 16, 1), ("B0", 32, 16, 0), ("O", 16, 2, 0))
 
 
-def flops_per_image(H: int, W: int) -> float:
-    """Multiply-adds x 2 of the eight 3x3 convolutions for one H x W image (no padding counted)."""
-    sizes = [(H, W)]
+def flops_per_image(H: int, W: int, D: int | None = None) -> float:
+    """Multiply-adds x 2 of the eight 3x3 (3x3x3 with depth D) convolutions for one image (no
+    padding counted)."""
+    shape = [(H, W) if D is None else (D, H, W)]
     for _ in range(3):
-        sizes.append(((sizes[-1][0] + 1) // 2, (sizes[-1][1] + 1) // 2))
-    return float(sum(2 * 9 * ci * co * sizes[lvl][0] * sizes[lvl][1] for _, ci, co, lvl in LAYERS))
+        shape.append(tuple((s + 1) // 2 for s in shape[-1]))
+    taps, layers = (9, LAYERS) if D is None else (27, LAYERS3)
+    return float(sum(2 * taps * ci * co * int(np.prod(shape[lvl])) for _, ci, co, lvl in layers))
 
 
-def new_network(seed: int) -> helm.Net:
+def new_network(seed: int, dim: int = 2) -> helm.Net:
     """He-initialised network whose output layer starts at zero (the network first outputs 0,
     the zero correction, and training moves it from there)."""
-    net = helm.Net(seed=seed)
+    net = helm.Net(seed=seed, dim=dim)
     p = net.params()
     p["O.w"][:] = 0.0
     p["O.b"][:] = 0.0
@@ -139,8 +147,7 @@ def train(net: helm.Net, ex: Examples, steps: int, batch: int, lr: float, seed: 
         if log_every and (it % log_every == 0 or it == steps - 1):
             log(f"[train] step {it} loss {losses[-1]:.4f}")
     torch.cuda.synchronize()
-    S = ex.feat.shape[1]
-    return TrainLog(losses, time.perf_counter() - t0, steps, batch * S * S)
+    return TrainLog(losses, time.perf_counter() - t0, steps, batch * int(np.prod(ex.feat.shape[1:-1])))
 
 
 def residual_ratio(ctx: helm.Context, net: helm.Net, ex: Examples, count: int = 64) -> float:
