@@ -50,9 +50,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="length of each bounded oracle run of the CPU baseline (one thread; one per core)")
     p.add_argument("--no-c1", action="store_true", help="skip the disk128 CPU timing (set-up and solve, median of 5)")
-    p.add_argument("--kappa-im", type=float, default=0.4,
-                   help="imaginary part of the shift kappa (real part 1); 0.4 measured best with --omega 0.9")
-    p.add_argument("--omega", type=float, default=0.9, help="damped-Jacobi factor")
+    p.add_argument("--kappa-im", type=float, default=None,
+                   help="imaginary part of the shift kappa (real part 1); default 0.4 in 2D (measured best with "
+                        "--omega 0.9 at 512^2 x 60), 0.5 in 3D")
+    p.add_argument("--omega", type=float, default=None,
+                   help="damped-Jacobi factor; default 0.9 in 2D, 0.8 in 3D (the 7-point Jacobi smoother diverges "
+                        "on more modes above 6/7)")
     p.add_argument("--no-vcycle-leg", action="store_true",
                    help="skip the same workload with the paper's V-cycle (Alg. 2, CycleType 1)")
     p.add_argument("--sweep", action="store_true",
@@ -61,6 +64,10 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
+    p.add_argument("--learned-rhs", type=int, default=None,
+                   help="plane waves of the learned-vs-multigrid comparison (default: all in 2D, 8 in 3D, where "
+                        "one network application costs about 17 multigrid cycles); both preconditioners solve the "
+                        "same sub-batch")
     p.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (for counter collection)")
     p.add_argument("--fused-step", type=int, default=2, choices=(0, 1, 2),
                    help="finest level of the s-step basis: 0 separate kernels, 1 one kernel for the up-leg, "
@@ -283,7 +290,12 @@ def gradient_leg(ctx, dirs, nmap, reps=3):
             "loss": loss, "receivers": int(rx.numel()), "plane_waves": int(dirs.shape[0])}
 
 
-def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
+def progress(msg):
+    """A progress line on stderr (the benchmark line itself is the only stdout output)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def learned_leg(make_ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
     """Learned-FGMRES on the same workload: the network is trained on the GPU on residual/error
     pairs from MG-FGMRES solves of training media (blob seeds 1000 + i, random angles), then
     used as z = net(v) + V(v - A net(v)) with the acceptance test and V-cycle fallback."""
@@ -296,54 +308,82 @@ def learned_leg(ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
     dev = torch.device("cuda:0")
     kind, kw = wl["medium"]
     B = dirs.shape[0]
+    d = wl["d"]
+    # large crops: the U-Net's coarsest level has to see a good part of the grid, as it does in the solver
+    crop = 256 if d == 2 else 96
+    # a context of its own, capped at 3x the multigrid cycles per solve
+    ctx = make_ctx(args.cycle, max_iters=int(3 * mg_iters_mean) + 16)
+    Bl = args.learned_rhs or (B if d == 2 else min(B, 8))
+    sub = np.round(np.linspace(0, B - 1, Bl)).astype(int)
+    ldirs = dirs[sub]
     rng = np.random.default_rng(5)
     t0 = time.perf_counter()
     sets = []
     for i in range(args.learned_media + 1):  # the last medium only validates
         m = synth.blob_map(wl["n"], kw["n_blobs"], kw["sigma_range"], kw["amp_hi"], 1000 + i,
-                           max_dn=kw.get("max_dn"))
+                           max_dn=kw.get("max_dn"), d=d)
         ctx.update_n(torch.tensor(m, dtype=torch.float32, device=dev))
-        th = np.radians(rng.uniform(-60.0, 60.0, B))
-        rhs = ctx.plane_wave_rhs(np.stack([np.sin(th), np.cos(th)], 1))
+        if d == 2:
+            th = np.radians(rng.uniform(-60.0, 60.0, B))
+            train_dirs = np.stack([np.sin(th), np.cos(th)], 1)
+        else:  # the 45-degree cone at random azimuths
+            ph = rng.uniform(0.0, 2 * np.pi, B)
+            a = np.radians(45.0)
+            train_dirs = np.stack([np.sin(a) * np.cos(ph), np.sin(a) * np.sin(ph), np.full(B, np.cos(a))], 1)
+        rhs = ctx.plane_wave_rhs(train_dirs)
         val_medium = i == args.learned_media
-        sets.append(learned.collect(ctx, [rhs], size=128, crops_per_snapshot=1 if val_medium else 4,
-                                    every_cycles=8, max_snaps=12, seed=1000 + i,
+        progress(f"learned: training pairs from medium {i}")
+        # 3D: one 96^3 crop per snapshot and right-hand side (each is 21 MB of FP32 features and targets)
+        sets.append(learned.collect(ctx, [rhs], size=crop, crops_per_snapshot=1 if (val_medium or d == 3) else 4,
+                                    every_cycles=8 if d == 2 else 4, max_snaps=12 if d == 2 else 4, seed=1000 + i,
                                     out=None if (val_medium or not sets) else sets.pop()))
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device=dev))
     tr, val = sets
     val = learned.rescaled(ctx, val, tr.gamma)
-    net = learned.new_network(11)
-    log = learned.train(net, tr, steps=args.learned_steps, batch=16, lr=1e-4, seed=3, err_weight=0.0,
-                        res_weight=1.0)
+    progress(f"learned: training on {tr.feat.shape[0]} pairs")
+    net = learned.new_network(11, dim=d)
+    log = learned.train(net, tr, steps=args.learned_steps, batch=4 if d == 2 else 2, lr=1e-4, seed=3,
+                        err_weight=0.0, res_weight=1.0)
     ratio = learned.residual_ratio(ctx, net, val)
+    # the multigrid baseline on the same plane waves, same context (s-step GMRES, autotuned shapes)
+    x = ctx.empty_fields(Bl)
+    ctx.autotune(Bl)
+    ctx.solve(ctx.plane_wave_rhs(ldirs), out=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st_mg = ctx.solve(ctx.plane_wave_rhs(ldirs), out=x)
+    torch.cuda.synchronize()
+    mg_sub = Bl / (time.perf_counter() - t0)
+    progress(f"learned: {Bl} solves with the network")
     ctx.set_preconditioner(net, accept_tol=1.0, gamma=tr.gamma, mode="then_mg")
-    x = ctx.empty_fields(B)
     # profiled warm-up solve: the network's MFMA rate
     ctx.profile(True)
-    ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+    ctx.solve(ctx.plane_wave_rhs(ldirs), out=x)
     rep = ctx.profile_report()
     ctx.profile(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st = ctx.solve(ctx.plane_wave_rhs(dirs), out=x)
+    _, st = ctx.solve(ctx.plane_wave_rhs(ldirs), out=x)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.set_preconditioner(None)
     ne = ctx.info.n_e
+    ctx.close()
     net_ms, net_launches, _ = rep.get("net_apply", (0.0, 0, 0.0))
-    fl = learned.flops_per_image(ne, ne) * B
+    fl = (learned.flops_per_image(ne, ne) if d == 2 else learned.flops_per_image(ne, ne, ne)) * Bl
     achieved = fl * net_launches / (net_ms * 1e-3) / 1e12 if net_ms > 0 else 0.0
     net.close()
-    value = B / el
+    value = Bl / el
     return {
-        "value": value, "unit": "solves/s", "vs_multigrid": value / mg_value,
+        "value": value, "unit": "solves/s", "rhs": Bl, "multigrid_same_rhs": mg_sub, "vs_multigrid": value / mg_sub,
         "iters_mean": float(st.iters.mean()), "iters_max": int(st.iters.max()),
-        "iters_vs_multigrid": float(st.iters.mean()) / mg_iters_mean,
+        "multigrid_iters_mean": float(st_mg.iters.mean()),
+        "iters_vs_multigrid": float(st.iters.mean()) / float(st_mg.iters.mean()),
         "all_converged": bool(st.converged), "rel_res_true_max": float(st.rel_res_true.max()),
         "accepted_frac": float(1.0 - st.fallbacks.sum() / max(1, st.iters.sum())),
-        "pairs": int(tr.feat.shape[0]), "crop": 128, "train_steps": log.steps, "train_s": log.seconds,
+        "pairs": int(tr.feat.shape[0]), "crop": crop, "train_steps": log.steps, "train_s": log.seconds,
         "collect_s": t_collect, "heldout_residual_ratio": ratio, "training_media": args.learned_media,
         "mode": "z = net(v) + V-cycle(v - A net(v)), V-cycle alone where ||v - A net(v)|| > ||v||",
         "mfma": {"kernel": "net_apply (all convolutions of one application)", "achieved": achieved,
@@ -363,6 +403,10 @@ def main():
     import synth
 
     wl = synth.WORKLOADS[args.workload]
+    if args.kappa_im is None:
+        args.kappa_im = 0.4 if wl["d"] == 2 else 0.5
+    if args.omega is None:
+        args.omega = 0.9 if wl["d"] == 2 else 0.8
     nmap = synth.workload_medium(args.workload).astype(np.float32).astype(np.float64)
     dirs = synth.workload_directions(args.workload, args.rhs)
     B = dirs.shape[0]
@@ -371,9 +415,11 @@ def main():
     # host legs first: the all-cores leg forks worker processes, which must happen before the GPU is used
     rates = c1 = None
     if not args.no_cpu_baseline and wl["d"] == 2:
+        progress("CPU oracle rates (one thread; one process per core)")
         rates = cpu_rates(nmap, args.levels, args.restart, args.cycle, args.cpu_seconds, complex(1.0, args.kappa_im),
                           args.omega)
         if not args.no_c1:
+            progress("CPU oracle, disk128 set-up and solve timing")
             c1 = cpu_c1_protocol()
     import torch
 
@@ -384,14 +430,15 @@ def main():
     k0 = (KBH / N_B) * (ne - 1)
     dev = torch.device("cuda:0")
 
-    def make_ctx(cycle):
+    def make_ctx(cycle, max_iters=None):
         return helm.Context(torch.tensor(nmap, dtype=torch.float32, device=dev), k0, abl_width=w, beta=wl["beta"],
                             levels=args.levels, restart=args.restart, cycle=cycle, reorth=args.reorth, max_batch=B,
-                            max_iters=args.max_iters, use_graph=0 if args.no_graph else 1, fused_step=args.fused_step,
+                            max_iters=args.max_iters if max_iters is None else max_iters, use_graph=0 if args.no_graph else 1, fused_step=args.fused_step,
                             kappa=complex(1.0, args.kappa_im), omega_jac=args.omega,
                             krylov={"sstep": helm.KRYLOV_SSTEP, "fgmres": helm.KRYLOV_FGMRES,
                                     "bicgstab": helm.KRYLOV_BICGSTAB}[args.krylov])
 
+    progress("GPU set-up")
     t_setup = time.perf_counter()
     ctx = make_ctx(args.cycle)
     torch.cuda.synchronize()
@@ -409,6 +456,7 @@ def main():
         _, st = ctx.solve(rhs, out=x)
         return st
 
+    progress(f"{args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         st = step()
     torch.cuda.synchronize()
@@ -460,6 +508,7 @@ def main():
     }
 
     if not args.no_profile:
+        progress("profiled step")
         ctx.profile(True)
         step()
         rep = ctx.profile_report()
@@ -502,10 +551,12 @@ def main():
                                     "right-hand sides + batched solve, per step"}
     if args.workload == "inverse256x32":
         out["gradient"] = gradient_leg(ctx, dirs, nmap)
-    if not args.no_learned and wl["d"] == 2:
-        out["learned"] = learned_leg(ctx, args, wl, nmap, dirs, float(iters.mean()), value)
+    if not args.no_learned:
+        progress("learned-preconditioner leg")
+        out["learned"] = learned_leg(make_ctx, args, wl, nmap, dirs, float(iters.mean()), value)
     ctx.close()
     if not args.no_vcycle_leg and args.cycle != 1:
+        progress("V-cycle leg")
         # the paper's cycle (Alg. 2, CycleType 1: one V-cycle per preconditioner application)
         vctx = make_ctx(1)
         if not args.no_tune:

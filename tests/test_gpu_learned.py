@@ -170,14 +170,20 @@ def test_trained_network_gain():
     reduces the residual (||r - A' y|| < ||r||, the zero output gives 1),
     (ii) with the network (acceptance-gated, multigrid cycle after it) some
     outputs are accepted and the solve still reaches the exact solution, and
-    (iii) it takes no more iterations than multigrid alone, up to a margin.
+    (iii) it needs fewer preconditioner applications than multigrid alone in the
+    same Krylov method (FGMRES(5) for both).  The time per application is
+    another matter: the network costs about ten multigrid cycles at this size
+    (the benchmark reports both).
     """
     import torch
 
     from paper_2107_03679_amd import learned as train_lib
 
     n, w, levels, B = 96, 20, 4, 16
-    ctx = gpu_context(medium(n, seed=1000), w=w, levels=levels, max_batch=B, restart=5, cycle=3)
+    from paper_2107_03679_amd import helm
+
+    ctx = gpu_context(medium(n, seed=1000), w=w, levels=levels, max_batch=B, restart=5, cycle=3,
+                      krylov=helm.KRYLOV_FGMRES)
     rng = np.random.default_rng(21)
     ex = None
     for seed in (1000, 1001, 1002):
@@ -193,7 +199,7 @@ def test_trained_network_gain():
     val = train_lib.collect(ctx, [rhs], size=64, crops_per_snapshot=2, every_cycles=4, max_snaps=4, seed=5)
     val = train_lib.rescaled(ctx, val, ex.gamma)
     net = train_lib.new_network(4)
-    train_lib.train(net, ex, steps=800, batch=16, lr=1e-4, seed=6, err_weight=0.0, res_weight=1.0)
+    train_lib.train(net, ex, steps=1500, batch=16, lr=1e-4, seed=6, err_weight=0.0, res_weight=1.0)
     ratio = train_lib.residual_ratio(ctx, net, val)
     x_mg, st_mg = ctx.solve(rhs)
     ctx.set_preconditioner(net, accept_tol=1.0, gamma=ex.gamma, mode="then_mg")
@@ -210,6 +216,6 @@ def test_trained_network_gain():
     b = to_np(rhs)
     for q in (0, B // 2, B - 1):
         assert rel(to_np(x_nn)[q], ex_solver.solve(b[q])) < 1e-5
-    assert st_nn.iters.mean() <= 1.1 * st_mg.iters.mean() + 5
+    assert st_nn.iters.mean() < st_mg.iters.mean(), (st_nn.iters, st_mg.iters)
     ctx.close()
     net.close()
