@@ -495,7 +495,8 @@ def main():
                        "bicgstab": "Bi-CGSTAB (Alg. 3)"}[args.krylov],
             "launch_shapes": "default" if tune is None else {
                 "down_tiles": tune["down_tiles"], "up_tiles": tune["up_tiles"],
-                "coarse_single_launch_max_points": tune["coarse_single_launch_max_points"]},
+                "coarse_single_launch_max_points": tune["coarse_single_launch_max_points"],
+                "up_mv_rows": tune["up_mv_rows"]},
         },
         "solver": {
             "all_converged": bool(all(s.converged for s in stats)),

@@ -482,11 +482,13 @@ typedef struct {
   long long coarse_max;                 /* levels with at most this many points run in one launch */
   double vcycle_ms;                     /* one preconditioner cycle for B right-hand sides, chosen shapes */
   double vcycle_default_ms;             /* ... with the default shapes (0 when from_cache) */
+  int up_mv_rows;                       /* tile height of the fused finest up-leg + basis matvec (s-step form) */
 } helm_tune;
 
 /* Autotuner of the batched multigrid cycle (the batching / launch-shape part of
  * the method's many-right-hand-side solves): times every tile shape of the
- * fused 2D down- and up-legs on each level with B right-hand sides, then the
+ * fused 2D down- and up-legs on each level with B right-hand sides, the tile
+ * height of the s-step form's fused finest up-leg + basis matvec, then the
  * threshold below which the coarse levels run as one launch, and keeps the
  * fastest for the following solves of this context (results do not depend on
  * the shapes: every point is computed by the same arithmetic).  cache_path

@@ -119,6 +119,7 @@ struct helm_ctx {
   // launch shapes (helm_autotune): fused-leg tile per level, single-launch coarse threshold
   int tune_down[HELM_MAX_LEVELS] = {0};
   int tune_up[HELM_MAX_LEVELS] = {0};
+  int tune_mv = 0;  // row-height variant of the fused finest up-leg + basis matvec
   long long coarse_max = -1;  // points; -1: default (48^2 in 2D, 16^3 in 3D), 0: never
 
   // learned preconditioner (NULL: multigrid only)
@@ -550,7 +551,7 @@ void sstep_basis(helm_ctx* c, int B) {
       if (j + 1 < k.m) {
         const VecSet vn{k.V + (long long)(j + 1) * N0, (long long)(k.m + 1) * N0};
         ProfScope ps(c, "up_mv_l0", Bp * 8.0 * (3.0 * N + Nc1) + 16.0 * N);
-        launch_up_mv2(c->s, B, vj, sj, level_K(c, 0), A, om, ecur, L1.n, zj, vn, k.active);
+        launch_up_mv2(c->s, B, vj, sj, level_K(c, 0), A, om, ecur, L1.n, zj, vn, k.active, c->tune_mv);
       } else {
         ProfScope ps(c, "up_fused_l0", Bp * 8.0 * (2.0 * N + Nc1) + 8.0 * N);
         launch_up_fused2(c->s, B, vj, sj, level_K(c, 0), om, ecur, L1.n, zj, k.active, c->tune_up[0]);
@@ -912,6 +913,9 @@ bool tune_load(helm_ctx* c, const char* path, const std::string& key) {
     std::memcpy(c->tune_down, down, sizeof down);
     std::memcpy(c->tune_up, up, sizeof up);
     c->coarse_max = cm;
+    int mv = 0;
+    const char* pm = std::strstr(line, "\"mv\": ");
+    if (pm && std::sscanf(pm + 6, "%d", &mv) == 1 && mv >= 0 && mv < mg_up_mv_variants()) c->tune_mv = mv;
     found = true;
   }
   std::fclose(f);
@@ -925,7 +929,7 @@ void tune_save(const helm_ctx* c, const char* path, const std::string& key) {
   for (int l = 0; l < c->L; ++l) std::fprintf(f, "%s%d", l ? ", " : "", c->tune_down[l]);
   std::fprintf(f, "], \"up\": [");
   for (int l = 0; l < c->L; ++l) std::fprintf(f, "%s%d", l ? ", " : "", c->tune_up[l]);
-  std::fprintf(f, "], \"coarse_max\": %lld}\n", c->coarse_max);
+  std::fprintf(f, "], \"coarse_max\": %lld, \"mv\": %d}\n", c->coarse_max, c->tune_mv);
   std::fclose(f);
 }
 
@@ -1419,7 +1423,23 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
         }
       }
     }
-    // 2. the single-launch threshold for the coarse levels, on whole V-cycles
+    // 2. the row height of the fused finest up-leg + basis matvec (the s-step form's finest step)
+    c->tune_mv = 0;
+    if (c->dim == 2 && c->o.fused && c->o.krylov == HELM_KRYLOV_SSTEP && c->o.fused_step == 2 && c->L >= 2) {
+      const float om = (float)c->o.omega_jac;
+      const Level& L1 = c->lv[1];
+      check(hipMemsetAsync(L1.e, 0, (size_t)B * L1.N * sizeof(c32), c->s), "memset");
+      double best = 1e30;
+      for (int v = 0; v < mg_up_mv_variants(); ++v) {
+        const double ms = time_ms(
+            c, [&] {
+              launch_up_mv2(c->s, B, r0, ScaleSet{nullptr, 0}, level_K(c, 0), fine_A(c), om, VecSet{L1.e, L1.N},
+                            L1.n, z0, VecSet{c->d_T0, N0}, nullptr, v);
+            }, 5);
+        if (ms < best) best = ms, c->tune_mv = v;
+      }
+    }
+    // 3. the single-launch threshold for the coarse levels, on whole V-cycles
     if (c->o.coarse_single_launch) {
       const long long cand2[] = {0, 24LL * 24, 48LL * 48, 96LL * 96};
       const long long cand3[] = {0, 8LL * 8 * 8, 16LL * 16 * 16, 24LL * 24 * 24};
@@ -1442,6 +1462,7 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
     mg_up_shape(c->tune_up[l], &t.up[l][0], &t.up[l][1], &t.up[l][2]);
   }
   t.coarse_max = c->coarse_max >= 0 ? c->coarse_max : (c->dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
+  t.up_mv_rows = mg_up_mv_rows(c->tune_mv);
   if (out) *out = t;
   HELM_GUARD_END("autotune")
 }

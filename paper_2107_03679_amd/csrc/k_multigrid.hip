@@ -423,8 +423,8 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
     sS[ly][lx] = sv;
   }
   __syncthreads();
-  if (threadIdx.x < TCX * TCY) {
-    const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  for (int q = threadIdx.x; q < TCX * TCY; q += 256) {  // 30 x TCY coarse points may exceed the block
+    const int tx = q % TCX, ty = q / TCX;
     const int I = cx0 + tx, J = cy0 + ty;
     if (I < nc && J < nc) {
       const int sx = 2 * tx + 2, sy = 2 * ty + 2;
@@ -1132,9 +1132,11 @@ struct UpTile {
   int tx, ty, py;
 };
 // the last entry of each is the column-layout kernel (k_down_col / k_up_col)
-constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}};
-constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}};
-constexpr int kDownCol = 5, kUpCol = 5;
+constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}, {30, 16}};
+constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}, {62, 30, 0}};
+constexpr int kDownCol = 5, kDownCol16 = 6, kUpCol = 5, kUpCol30 = 6;
+// row heights of the fused finest up-leg + basis matvec (k_up_mv2w), one autotuner choice
+constexpr int kUpMvRows[] = {12, 16, 20, 28};
 
 template <int TCX, int TCY>
 void down_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
@@ -1173,13 +1175,27 @@ void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
   hipLaunchKernelGGL(k_up_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active);
 }
 
-void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
-                   int nc, VecSet z, VecSet w, const int* active) {
-  constexpr int TX = 60, TY = 12;  // 12 rows measured best of 8, 12, 16, 20, 28
+template <int TY>
+void up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec, int nc,
+            VecSet z, VecSet w, const int* active) {
+  constexpr int TX = 60;
   const int n = lv.n;
   const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
   hipLaunchKernelGGL((k_up_mv2w<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
                      active);
+}
+
+int mg_up_mv_variants() { return (int)(sizeof(kUpMvRows) / sizeof(kUpMvRows[0])); }
+int mg_up_mv_rows(int cfg) { return kUpMvRows[cfg]; }
+
+void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
+                   int nc, VecSet z, VecSet w, const int* active, int cfg) {
+  switch (cfg) {
+    case 1: up_mv2<16>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
+    case 2: up_mv2<20>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
+    case 3: up_mv2<28>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
+    default: up_mv2<12>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
+  }
 }
 
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
@@ -1215,6 +1231,17 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                          active, e);
     return;
   }
+  if (cfg == kDownCol16) {  // taller column tile: fewer halo rows per coarse row
+    constexpr int TCX = 30, TCY = 16;
+    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+    if (e.p)
+      hipLaunchKernelGGL((k_down_col<TCY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                         active, e);
+    else
+      hipLaunchKernelGGL((k_down_col<TCY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
+                         active, e);
+    return;
+  }
   switch (cfg) {
     case 1: down_tile<16, 16>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
     case 2: down_tile<64, 4>(s, B, r, rs, lv, omega, rc, nc, active, e); break;
@@ -1228,6 +1255,17 @@ void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
                       VecSet z, const int* active, int cfg, VecSet e) {
   if (cfg == kUpCol) {
     constexpr int TX = 62, TY = 14;
+    const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+    if (e.p)
+      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                         active, e);
+    else
+      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
+                         active, e);
+    return;
+  }
+  if (cfg == kUpCol30) {  // taller column tile
+    constexpr int TX = 62, TY = 30;
     const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
     if (e.p)
       hipLaunchKernelGGL((k_up_col<TY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,

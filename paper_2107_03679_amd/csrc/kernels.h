@@ -49,13 +49,16 @@ void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
                       VecSet z, const int* active);
 // up-leg of Z_j and W_{j+1} = A Z_j in one launch (2D; la = the A operator)
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
-                   int nc, VecSet z, VecSet w, const int* active);
+                   int nc, VecSet z, VecSet w, const int* active, int cfg = 0);
 // finest-level step of the s-step basis (2D): up-leg of Z_j, W_{j+1} = A Z_j (la = the A
 // operator), down-leg of W_{j+1} into rc; one launch
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
                         VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active);
 int mg_down_variants();
 int mg_up_variants();
+// row heights of the fused finest up-leg + basis matvec (autotuner choices)
+int mg_up_mv_variants();
+int mg_up_mv_rows(int cfg);
 void mg_down_shape(int cfg, int* tcx, int* tcy);
 void mg_up_shape(int cfg, int* tx, int* ty, int* py);
 void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,

@@ -57,6 +57,7 @@ class HelmTune(ctypes.Structure):
         ("from_cache", ctypes.c_int), ("levels", ctypes.c_int),
         ("down", (ctypes.c_int * 2) * 12), ("up", (ctypes.c_int * 3) * 12),
         ("coarse_max", ctypes.c_longlong), ("vcycle_ms", ctypes.c_double), ("vcycle_default_ms", ctypes.c_double),
+        ("up_mv_rows", ctypes.c_int),
     ]
 
 
@@ -587,7 +588,7 @@ class Context:
             "from_cache": bool(t.from_cache),
             "down_tiles": [tuple(t.down[l]) for l in range(L - 1)],
             "up_tiles": [tuple(t.up[l]) for l in range(L - 1)],
-            "coarse_single_launch_max_points": int(t.coarse_max),
+            "coarse_single_launch_max_points": int(t.coarse_max), "up_mv_rows": int(t.up_mv_rows),
             "vcycle_ms": t.vcycle_ms, "vcycle_default_ms": t.vcycle_default_ms,
         }
 

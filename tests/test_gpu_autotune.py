@@ -34,11 +34,12 @@ def case():
     return nmap, prob, r, ref
 
 
-def _edit(line: str, levels: int, down: int, up: int, coarse_max: int) -> str:
+def _edit(line: str, levels: int, down: int, up: int, coarse_max: int, mv: int = 0) -> str:
     e = json.loads(line)
     e["down"] = [down] * levels
     e["up"] = [up] * levels
     e["coarse_max"] = coarse_max
+    e["mv"] = mv
     return json.dumps(e) + "\n"
 
 
@@ -77,7 +78,7 @@ def test_autotune_keeps_results_and_caches(case, tmp_path):
 
 
 @pytest.mark.parametrize("cycle", [1, 3])
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(7))
 def test_every_tile_variant_is_bit_identical(case, tmp_path, variant, cycle):
     """Forced tile shapes against the defaults; cycle 3 adds the repeated visit of level 1
     (the legs that form r - K e themselves)."""
@@ -94,6 +95,31 @@ def test_every_tile_variant_is_bit_identical(case, tmp_path, variant, cycle):
     assert t["from_cache"], "the forced cache line was not accepted"
     z = ctx.precondition(rd)
     assert bool((z == z0).all()), f"tile variant {variant} changed the cycle"
+    ctx.close()
+
+
+def test_up_mv_heights_are_bit_identical(case, tmp_path):
+    """Every tile height of the s-step form's fused finest up-leg + basis matvec, forced through the
+    cache: the same iterates (bit for bit) and cycle counts as the default height."""
+    nmap, prob, r, ref = case
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B, restart=6)
+    first = tmp_path / "first.jsonl"
+    t0 = ctx.autotune(B, cache=str(first))
+    line = first.read_text().splitlines()[0]
+    rhs = ctx.plane_wave_rhs(synth.directions_2d(B))
+    e = json.loads(line)
+    xs = []
+    for mv in range(4):
+        forced = tmp_path / f"mv{mv}.jsonl"
+        forced.write_text(_edit(line, LEVELS, e["down"][0], e["up"][0], e["coarse_max"], mv))
+        t = ctx.autotune(B, cache=str(forced))
+        assert t["from_cache"] and t["up_mv_rows"] == (12, 16, 20, 28)[mv]
+        x, st = ctx.solve(rhs)
+        assert st.converged
+        xs.append((x, st.iters))
+    for x, it in xs[1:]:
+        assert bool((x == xs[0][0]).all()) and np.array_equal(it, xs[0][1])
+    print(f"[autotune] up-mv height chosen: {t0['up_mv_rows']} rows", flush=True)
     ctx.close()
 
 
