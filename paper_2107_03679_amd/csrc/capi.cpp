@@ -82,6 +82,9 @@ struct helm_ctx {
   KrylovArgs k{};
   c32* d_xhi = nullptr;  // internal x (hi), [maxB][N0]
   c32* d_xlo = nullptr;  // internal x (lo)
+  c32* d_xhi2 = nullptr;  // the second buffer of the iterate pair (2D: the fused update alternates)
+  c32* d_xlo2 = nullptr;
+  int* d_xpar = nullptr;  // [maxB] which buffer holds each right-hand side's x
   c32* d_rhs = nullptr;  // internal copy of the right-hand sides
   c32* d_T0 = nullptr;   // generic-path scratch on the fine level
   c32* d_tables = nullptr;
@@ -474,17 +477,30 @@ void arnoldi_step(helm_ctx* c, int B, int j) {
 
 bool use_bicg(const helm_ctx* c) { return c->o.krylov == HELM_KRYLOV_BICGSTAB && c->net == nullptr; }
 
-void true_residual(helm_ctx* c, int B, int first, int conj_rhs) {
+// The true residual of x (with fused_update on a 2D grid: the x update of the
+// cycle and the residual in one pass), then the convergence decision.
+void true_residual(helm_ctx* c, int B, int first, int conj_rhs, bool fused_update = false) {
   KrylovArgs& k = c->k;
   k.bicg = use_bicg(c) ? 1 : 0;
-  {
+  if (fused_update) {
+    ProfScope ps(c, "x_update_residual", c->prof_B * (8.0 * k.m + 48.0) * c->N0 + 16.0 * c->N0);
+    launch_x_update_residual(c->s, B, k, XPair{c->d_xhi, c->d_xlo}, XPair{c->d_xhi2, c->d_xlo2}, c->d_rhs, c->N0,
+                             conj_rhs, c->d_dhi, c->d_dlo, c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0);
+    k.nres = krylov_xres_tiles(k.n);
+    k.flip_x = 1;
+  } else {
     ProfScope ps(c, "residual_ff", c->prof_B * (first ? 16.0 : 32.0) * c->N0 + (first ? 0.0 : 16.0 * c->N0));
     launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_dhi, c->d_dlo,
                        c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
+    k.nres = k.nblk;
   }
-  ProfScope ps(c, "finalize", c->prof_B * k.nblk * 4.0);
-  if (k.bicg) launch_bicg_finalize(c->s, B, k, first);
-  else launch_finalize(c->s, B, k, first);
+  {
+    ProfScope ps(c, "finalize", c->prof_B * k.nres * 4.0);
+    if (k.bicg) launch_bicg_finalize(c->s, B, k, first);
+    else launch_finalize(c->s, B, k, first);
+  }
+  k.nres = k.nblk;
+  k.flip_x = 0;
 }
 
 // `restart` Bi-CGSTAB iterations (Alg. 3), two multigrid cycles each; the
@@ -618,6 +634,10 @@ void restart_cycle(helm_ctx* c, int B, int conj_rhs) {
   if (use_sstep(c)) sstep_basis(c, B);
   else
     for (int j = 0; j < c->k.m; ++j) arnoldi_step(c, B, j);
+  if (c->dim == 2) {
+    true_residual(c, B, 0, conj_rhs, true);
+    return;
+  }
   {
     ProfScope ps(c, "x_update", c->prof_B * (8.0 * c->k.m + 32.0) * c->N0);
     launch_x_update(c->s, B, c->k, c->d_xhi, c->d_xlo);
@@ -656,6 +676,7 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     check(hipMemcpyAsync(c->d_rhs, rhs, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy rhs");
     launch_status_init(c->s, B, c->k);
     check(hipMemcpyAsync(c->d_fallbacks, c->d_zero_ints, B * sizeof(int), hipMemcpyDeviceToDevice, c->s), "reset");
+    check(hipMemcpyAsync(c->d_xpar, c->d_zero_ints, B * sizeof(int), hipMemcpyDeviceToDevice, c->s), "reset");
     launch_zero(c->s, (long long)B * N0, c->d_xhi);
     launch_zero(c->s, (long long)B * N0, c->d_xlo);
     c->prof_B = B;
@@ -688,9 +709,8 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
       int running = 0;
       for (int b = 0; b < B; ++b) running += c->h_status[b] == HELM_RUNNING;
       if (snaps && running && (cyc + 1) % snap_every == 0 && *n_snaps < max_snaps) {
-        check(hipMemcpyAsync(snaps + (size_t)(*n_snaps) * B * N0, c->d_xhi, (size_t)B * N0 * sizeof(c32),
-                             hipMemcpyDeviceToDevice, c->s),
-              "snapshot");
+        launch_x_select(c->s, B, N0, c->d_xpar, c->d_xhi, c->d_xhi2, (c32*)(snaps + (size_t)(*n_snaps) * B * N0),
+                        0);
         ++*n_snaps;
       }
       if (c->prof_on) prof_resolve(c);
@@ -699,8 +719,7 @@ int run_solve(helm_ctx* c, int B, const helm_c32* rhs, helm_c32* x, helm_stats* 
     }
     c->last_B = B;
     c->last_conj = conj;
-    if (conj) launch_conj_copy(c->s, (long long)B * N0, c->d_xhi, (c32*)x);
-    else check(hipMemcpyAsync(x, c->d_xhi, (size_t)B * N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy x");
+    launch_x_select(c->s, B, N0, c->d_xpar, c->d_xhi, c->d_xhi2, (c32*)x, conj);
     check(hipMemcpyAsync(c->h_status, c->k.status, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "status");
     check(hipMemcpyAsync(c->h_iters, c->k.iters, B * sizeof(int), hipMemcpyDeviceToHost, c->s), "iters");
     check(hipMemcpyAsync(c->h_relres, c->k.relres, B * sizeof(double), hipMemcpyDeviceToHost, c->s), "relres");
@@ -1067,6 +1086,11 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     c->d_dlo = c->alloc<c32>(N0);
     c->d_xhi = c->alloc<c32>((size_t)maxB * N0);
     c->d_xlo = c->alloc<c32>((size_t)maxB * N0);
+    if (c->dim == 2) {
+      c->d_xhi2 = c->alloc<c32>((size_t)maxB * N0);
+      c->d_xlo2 = c->alloc<c32>((size_t)maxB * N0);
+    }
+    c->d_xpar = c->alloc<int>(maxB);
     c->d_rhs = c->alloc<c32>((size_t)maxB * N0);
     c->d_T0 = c->alloc<c32>((size_t)maxB * N0);
     c->d_tables = c->alloc<c32>((size_t)maxB * c->dim * ne);
@@ -1082,11 +1106,14 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     k.N = N0;
     k.m = m;
     k.nblk = krylov_blocks_per_rhs(N0);
+    k.nres = k.nblk;
+    k.xpar = c->d_xpar;
+    k.flip_x = 0;
     k.V = c->alloc<c32>((size_t)maxB * (m + 1) * N0);
     k.Z = c->alloc<c32>((size_t)maxB * m * N0);
     k.vs = c->alloc<float>((size_t)maxB * (m + 1));
     k.P1 = c->alloc<c32>((size_t)maxB * k.nblk * (m + 1));
-    k.P2 = c->alloc<float>((size_t)maxB * k.nblk);
+    k.P2 = c->alloc<float>((size_t)maxB * std::max(k.nblk, c->dim == 2 ? krylov_xres_tiles(ne) : 0));
     k.H = c->alloc<double2>((size_t)maxB * (m + 1) * m);
     k.cs = c->alloc<double>((size_t)maxB * m);
     k.sn = c->alloc<double2>((size_t)maxB * m);
@@ -1111,6 +1138,7 @@ int helm_setup(const helm_grid* grid, const float* n_map_dev, double k0, const h
     std::vector<int> ones(maxB, 1), zeros(maxB, 0);
     check(hipMemcpy(c->d_ones, ones.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload ones");
     check(hipMemcpy(c->d_zero_ints, zeros.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload zeros");
+    check(hipMemcpy(c->d_xpar, zeros.data(), maxB * sizeof(int), hipMemcpyHostToDevice), "upload zeros");
     check(hipHostMalloc((void**)&c->h_fallbacks, maxB * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
     upload_static(c);
     update_medium(c, n_map_dev);
@@ -1289,8 +1317,7 @@ int helm_solution_lo(helm_ctx* c, int B, helm_c32* x_lo) {
   if (!c || !x_lo) return fail(c, HELM_EINVAL, "null argument");
   if (B < 1 || B > c->last_B) return fail(c, HELM_EINVAL, "B must be in [1, B of the last solve]");
   HELM_GUARD_BEGIN
-  if (c->last_conj) launch_conj_copy(c->s, (long long)B * c->N0, c->d_xlo, (c32*)x_lo);
-  else check(hipMemcpyAsync(x_lo, c->d_xlo, (size_t)B * c->N0 * sizeof(c32), hipMemcpyDeviceToDevice, c->s), "copy");
+  launch_x_select(c->s, B, c->N0, c->d_xpar, c->d_xlo, c->d_xlo2, (c32*)x_lo, c->last_conj);
   HELM_GUARD_END("solution_lo")
 }
 

@@ -24,13 +24,21 @@ __host__ __device__ __forceinline__ cff ff_load_x(const c32* xh, const c32* xl, 
   return cff_make(xh[p], xl ? xl[p] : make_float2(0.f, 0.f));
 }
 
+// h^2 b (conjugated for the adjoint) as a float-float pair
+__host__ __device__ __forceinline__ cff ff_scaled_rhs(const FFArgs& a, c32 bv) {
+  const ff h2 = {a.h2_hi, a.h2_lo};
+  if (a.conj_rhs) bv.y = -bv.y;
+  return cff{ff_mul(ff_from(bv.x), h2), ff_mul(ff_from(bv.y), h2)};
+}
+
+__host__ __device__ __forceinline__ c32 ff_round(const cff& r) {
+  return make_float2(r.re.hi + r.re.lo, r.im.hi + r.im.lo);
+}
+
 // rb, xh, xl point at this right-hand side's vectors (xh == NULL: x = 0).
 __host__ __device__ inline c32 ff_residual_point(const FFArgs& a, const c32* rb, const c32* xh, const c32* xl,
                                                  long long p, const Coord& c, int n, int dim) {
-  const ff h2 = {a.h2_hi, a.h2_lo};
-  c32 bv = rb[p];
-  if (a.conj_rhs) bv.y = -bv.y;
-  cff r = {ff_mul(ff_from(bv.x), h2), ff_mul(ff_from(bv.y), h2)};
+  cff r = ff_scaled_rhs(a, rb[p]);
   if (xh) {
     const cff D = cff_make(a.d_hi[p], a.d_lo[p]);
     cff ax = cff_mul(D, ff_load_x(xh, xl, p));
@@ -47,5 +55,5 @@ __host__ __device__ inline c32 ff_residual_point(const FFArgs& a, const c32* rb,
     ax = cff_sub(ax, nb);
     r = cff_sub(r, ax);
   }
-  return make_float2(r.re.hi + r.re.lo, r.im.hi + r.im.lo);
+  return ff_round(r);
 }

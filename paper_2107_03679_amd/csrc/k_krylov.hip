@@ -339,6 +339,122 @@ __global__ __launch_bounds__(NT) void k_residual_ff(int nrhs, KrylovArgs k, FFAr
   }
 }
 
+// The end of a restart cycle on a 2D grid in one pass: x += sum_{i < jcount}
+// y_i Z_i (as k_x_update) and the true residual of the new x (as
+// k_residual_ff), on a 62 x TY tile with a one-point ring, one column per
+// lane.  The new float-float x of the region is kept in LDS for the stencil,
+// so x is not read a second time; Z is read on the region (the ring adds
+// 64 (TY + 2) / (62 TY) - 1 of it).  Every tile reads x on its ring, which
+// neighbouring tiles own, so the new x goes to the other buffer of the pair
+// (x0, x1): right-hand side b reads buffer xpar[b] and writes 1 - xpar[b],
+// and k_finalize flips xpar[b] after the pass.  Same arithmetic per point as
+// the two kernels; one partial squared norm per tile, k.P2[b][tile].
+template <int TY>
+__global__ __launch_bounds__(NT) void k_x_update_residual2(int nrhs, KrylovArgs k, FFArgs a, XPair x0, XPair x1) {
+  constexpr int TX = 62, VY = TY + 2, RPI = NT / HELM_WAVE, IV = VY / RPI;
+  static_assert(VY % RPI == 0, "whole row groups");
+  __shared__ c32 sH[VY][HELM_WAVE];
+  __shared__ c32 sL[VY][HELM_WAVE];
+  __shared__ float red[NWAVE];
+  const int n = k.n;
+  const int tiles_x = (n + TX - 1) / TX;
+  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (k.status[b] != HELM_RUNNING) return;
+  const int kk = k.jcount[b];
+  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int lx = threadIdx.x % HELM_WAVE, r0 = threadIdx.x / HELM_WAVE;
+  const int gx = fx0 - 1 + lx;
+  const bool inx = gx >= 0 && gx < n;
+  const bool tcol = lx >= 1 && lx <= TX && gx < n;
+  const XPair src = k.xpar[b] ? x1 : x0, dst = k.xpar[b] ? x0 : x1;
+  const c32* xh = src.hi + (long long)b * k.N;
+  const c32* xl = src.lo + (long long)b * k.N;
+  c32* oh = dst.hi + (long long)b * k.N;
+  c32* ol = dst.lo + (long long)b * k.N;
+  const c32* rb = a.rhs + (long long)b * a.rhs_stride;
+  c32 hv[IV], lv[IV], d[IV], bv[IV], dh[IV], dl[IV];
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
+    const bool ok = inx && gy >= 0 && gy < n;
+    const bool tp = ok && tcol && ly >= 1 && ly <= TY;
+    const long long p = ok ? (long long)gy * n + gx : 0;
+    hv[it] = ok ? xh[p] : make_float2(0.f, 0.f);
+    lv[it] = ok ? xl[p] : make_float2(0.f, 0.f);
+    bv[it] = tp ? rb[p] : make_float2(0.f, 0.f);
+    dh[it] = tp ? a.d_hi[p] : make_float2(0.f, 0.f);
+    dl[it] = tp ? a.d_lo[p] : make_float2(0.f, 0.f);
+    d[it] = make_float2(0.f, 0.f);
+  }
+  for (int i = 0; i < kk; ++i) {  // the sum in the order of i, as k_x_update
+    const c32 yi = k.y[b * k.m + i];
+    const c32* zi = k.Z + zidx(k, b, i);
+#pragma unroll
+    for (int it = 0; it < IV; ++it) {
+      const int gy = fy0 - 1 + r0 + RPI * it;
+      if (inx && gy >= 0 && gy < n) d[it] = cfma(yi, zi[(long long)gy * n + gx], d[it]);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
+    if (!inx || gy < 0 || gy >= n) {
+      sH[ly][lx] = make_float2(0.f, 0.f);
+      sL[ly][lx] = make_float2(0.f, 0.f);
+      continue;
+    }
+    if (kk > 0) {
+      const ff re = ff_add({hv[it].x, lv[it].x}, ff_from(d[it].x));
+      const ff im = ff_add({hv[it].y, lv[it].y}, ff_from(d[it].y));
+      hv[it] = make_float2(re.hi, im.hi);
+      lv[it] = make_float2(re.lo, im.lo);
+    }
+    if (tcol && ly >= 1 && ly <= TY) {  // the tile's points, updated or not, go to the other buffer
+      const long long p = (long long)gy * n + gx;
+      oh[p] = hv[it];
+      ol[p] = lv[it];
+    }
+    sH[ly][lx] = hv[it];
+    sL[ly][lx] = lv[it];
+  }
+  __syncthreads();
+  c32* ro = a.r_out + (long long)b * a.r_stride;
+  float nrm = 0.f;
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {
+    const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
+    if (!tcol || ly < 1 || ly > TY || gy >= n) continue;
+    cff r = ff_scaled_rhs(a, bv[it]);
+    cff ax = cff_mul(cff_make(dh[it], dl[it]), cff_make(sH[ly][lx], sL[ly][lx]));
+    cff nb = {ff_from(0.f), ff_from(0.f)};  // the in-grid neighbours in the order of ff_residual_point
+    if (gx > 0) nb = cff_add(nb, cff_make(sH[ly][lx - 1], sL[ly][lx - 1]));
+    if (gx < n - 1) nb = cff_add(nb, cff_make(sH[ly][lx + 1], sL[ly][lx + 1]));
+    if (gy > 0) nb = cff_add(nb, cff_make(sH[ly - 1][lx], sL[ly - 1][lx]));
+    if (gy < n - 1) nb = cff_add(nb, cff_make(sH[ly + 1][lx], sL[ly + 1][lx]));
+    ax = cff_sub(ax, nb);
+    r = cff_sub(r, ax);
+    const c32 rv = ff_round(r);
+    ro[(long long)gy * n + gx] = cscale(rv, a.out_scale);
+    nrm = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, nrm));
+  }
+  nrm = wave_sum(nrm);
+  if (lx == 0) red[r0] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) s += red[q];
+    k.P2[(long long)b * tiles + id.t] = s;
+  }
+}
+// tile rows of the fused update and residual
+#ifndef HELM_XRES_TY
+#define HELM_XRES_TY 10
+#endif
+constexpr int XRES_TX = 62, XRES_TY = HELM_XRES_TY;
+
 // Acceptance test of a learned preconditioner output z_j: partial sums of
 // |v_j - A' z_j|^2 (v_j = vs_j V_j has unit norm); the residual itself is
 // stored in resid[b] when resid is non-null.
@@ -410,9 +526,10 @@ __global__ __launch_bounds__(HELM_WAVE) void k_finalize(KrylovArgs k, int first)
   const int b = blockIdx.x;
   if (k.status[b] != HELM_RUNNING) return;
   double s = 0.0;
-  for (int blk = threadIdx.x; blk < k.nblk; blk += HELM_WAVE) s += k.P2[(long long)b * k.nblk + blk];
+  for (int blk = threadIdx.x; blk < k.nres; blk += HELM_WAVE) s += k.P2[(long long)b * k.nres + blk];
   s = wave_sum_d(s);
   if (threadIdx.x != 0) return;
+  if (k.flip_x) k.xpar[b] ^= 1;  // the pass wrote the new iterate to the other buffer
   const double rn = sqrt(s);
   k.jcount[b] = 0;
   k.active[b] = 0;
@@ -908,6 +1025,14 @@ void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rh
                         const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale) {
   FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, d_hi, d_lo, h2_hi, h2_lo, r_out, r_stride, out_scale};
   hipLaunchKernelGGL(k_residual_ff, dim3(B * k.nblk), dim3(NT), 0, s, B, k, a);
+}
+int krylov_xres_tiles(int n) { return ((n + XRES_TX - 1) / XRES_TX) * ((n + XRES_TY - 1) / XRES_TY); }
+void launch_x_update_residual(hipStream_t s, int B, const KrylovArgs& k, XPair x0, XPair x1, const c32* rhs,
+                              long long rhs_stride, int conj_rhs, const c32* d_hi, const c32* d_lo, float h2_hi,
+                              float h2_lo, c32* r_out, long long r_stride) {
+  FFArgs a{rhs, rhs_stride, conj_rhs, nullptr, nullptr, 0, d_hi, d_lo, h2_hi, h2_lo, r_out, r_stride, 1.0f};
+  hipLaunchKernelGGL(k_x_update_residual2<XRES_TY>, dim3(B * krylov_xres_tiles(k.n)), dim3(NT), 0, s, B, k, a, x0,
+                     x1);
 }
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first) {
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(HELM_WAVE), 0, s, k, first);

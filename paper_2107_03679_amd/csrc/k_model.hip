@@ -52,6 +52,17 @@ __global__ void k_conj_copy(long long count, const c32* in, c32* out) {
   }
 }
 
+// the iterate of each right-hand side from the buffer of the pair its last update wrote
+__global__ void k_x_select(long long N, const int* xpar, const c32* in0, const c32* in1, c32* out, int conj) {
+  const int b = blockIdx.y;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const c32* in = xpar && xpar[b] ? in1 : in0;
+  c32 v = in[(long long)b * N + i];
+  if (conj) v.y = -v.y;
+  out[(long long)b * N + i] = v;
+}
+
 __global__ void k_zero(long long count, c32* p) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = make_float2(0.f, 0.f);
@@ -74,6 +85,10 @@ void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c
 }
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out) {
   hipLaunchKernelGGL(k_conj_copy, dim3(nb(count, 256)), dim3(256), 0, s, count, in, out);
+}
+void launch_x_select(hipStream_t s, int B, long long N, const int* xpar, const c32* in0, const c32* in1, c32* out,
+                     int conj) {
+  hipLaunchKernelGGL(k_x_select, dim3(nb(N, 256), B), dim3(256), 0, s, N, xpar, in0, in1, out, conj);
 }
 void launch_zero(hipStream_t s, long long count, c32* p) {
   hipLaunchKernelGGL(k_zero, dim3(nb(count, 256)), dim3(256), 0, s, count, p);

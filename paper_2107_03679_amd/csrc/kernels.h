@@ -105,6 +105,12 @@ size_t coarse_cycle_lds_bytes(const CoarseCycleArgs& a);
 void launch_coarse_cycle(hipStream_t s, int B, const CoarseCycleArgs& a);
 
 // ---- Krylov (FGMRES / float-float outer loop), flat over the fine grid ----
+// a float-float field pair, [B][N] each
+struct XPair {
+  c32* hi;
+  c32* lo;
+};
+
 struct KrylovArgs {
   int dim;
   int n;
@@ -115,7 +121,10 @@ struct KrylovArgs {
   c32* Z;         // [B][m][N] preconditioned vectors
   float* vs;      // [B][m+1] scale of each basis vector
   c32* P1;        // [B][nblk][m+1] partial dots
-  float* P2;      // [B][nblk] partial squared norms
+  float* P2;      // [B][nblk] partial squared norms ([B][nres] after a true residual)
+  int nres;       // partial squared norms per right-hand side of the last true residual
+  int* xpar;      // [B] which buffer of the pair holds x (the fused update of 2D grids alternates)
+  int flip_x;     // 1: k_finalize flips xpar (after the fused update and residual)
   double2* H;     // [B][m+1][m] Hessenberg (rotated in place)
   double* cs;     // [B][m]
   double2* sn;    // [B][m]
@@ -143,6 +152,12 @@ void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* 
 void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
                         int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* d_hi,
                         const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale);
+// 2D grids: x += sum_i y_i Z_i and the true residual of the new x in one pass
+// (the partial norms of krylov_xres_tiles(n) tiles per right-hand side)
+int krylov_xres_tiles(int n);
+void launch_x_update_residual(hipStream_t s, int B, const KrylovArgs& k, XPair x0, XPair x1, const c32* rhs,
+                              long long rhs_stride, int conj_rhs, const c32* d_hi, const c32* d_lo, float h2_hi,
+                              float h2_lo, c32* r_out, long long r_stride);
 void launch_finalize(hipStream_t s, int B, const KrylovArgs& k, int first);
 void launch_accept(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine, double tol, int* mg_mask,
                    int* fallbacks, VecSet resid);
@@ -155,6 +170,9 @@ void launch_grad_n(hipStream_t s, int dim, int B, int n_e, int w, int n, const c
                    const c32* lam, const float* nmap, float scale, float* grad,
                    const c32* lam2 = nullptr, int accumulate = 0);
 void launch_conj_copy(hipStream_t s, long long count, const c32* in, c32* out);
+// out[b] = (xpar && xpar[b] ? in1 : in0)[b] for b < B, N points each, conjugated when conj
+void launch_x_select(hipStream_t s, int B, long long N, const int* xpar, const c32* in0, const c32* in1, c32* out,
+                     int conj);
 void launch_gather(hipStream_t s, int B, int M, long long N, const int* idx, const c32* u, c32* y);
 void launch_scatter(hipStream_t s, int B, int M, long long N, const int* idx, const c32* y, c32* u);
 int tv_partials(int dim, int n);
