@@ -588,6 +588,15 @@ __global__ void k_net_input(int B, long long N, const c32* v, long long v_stride
   const c32 d = make_float2(c.x - cb.x, c.y - cb.y);
   const c32 q = make_float2((d.x * cb.x + d.y * cb.y) * inv, (d.y * cb.x - d.x * cb.y) * inv);
   bf16* xp = x + ((long long)b * N + p) * x_ct;
+  if (x_ct == 8) {  // one 16-byte store per pixel
+    bf16x8 o = zero8();
+    o[0] = (bf16)r.x;
+    o[1] = (bf16)r.y;
+    o[2] = (bf16)q.x;
+    o[3] = (bf16)q.y;
+    *reinterpret_cast<bf16x8*>(xp) = o;
+    return;
+  }
   xp[0] = (bf16)r.x;
   xp[1] = (bf16)r.y;
   xp[2] = (bf16)q.x;
@@ -613,6 +622,18 @@ __global__ void k_to_bf16_pad(long long P, int cin, const float* x, int cpad, bf
   const long long p = t / cpad;
   const int c = (int)(t % cpad);
   out[t] = (bf16)(c < cin ? x[p * cin + c] : 0.f);
+}
+// the same for 4 input channels padded to 8: one pixel per thread, 16-byte load and store
+__global__ void k_to_bf16_pad48(long long P, const float4* x, bf16x8* out) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float4 v = x[p];
+  bf16x8 o = zero8();
+  o[0] = (bf16)v.x;
+  o[1] = (bf16)v.y;
+  o[2] = (bf16)v.z;
+  o[3] = (bf16)v.w;
+  out[p] = o;
 }
 
 // Training examples from solver snapshots: crop c = (rhs b, y0, x0) of size S x S;
@@ -675,7 +696,11 @@ inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 }  // namespace
 
 void launch_to_bf16_pad(hipStream_t s, long long P, int cin, const float* x, int cpad, bf16* out) {
-  hipLaunchKernelGGL(k_to_bf16_pad, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, cin, x, cpad, out);
+  if (cin == 4 && cpad == 8 && ((uintptr_t)x % 16) == 0 && ((uintptr_t)out % 16) == 0)
+    hipLaunchKernelGGL(k_to_bf16_pad48, dim3(nb(P, 256)), dim3(256), 0, s, P, reinterpret_cast<const float4*>(x),
+                       reinterpret_cast<bf16x8*>(out));
+  else
+    hipLaunchKernelGGL(k_to_bf16_pad, dim3(nb(P * cpad, 256)), dim3(256), 0, s, P, cin, x, cpad, out);
 }
 void launch_examples(hipStream_t s, int dim, int B, int ncrop, int S, int n_e, const int* crops, float* ss,
                      const c32* r, const c32* xfin, const c32* xk, long long N, const c32* coef, c32 cb,

@@ -35,7 +35,7 @@ HIP_KERNEL = {
     "up_mv_l0": ("k_up_mv2w", "k_up_mv2"), "up_fused_l0": ("k_up_col", "k_up_fused2"),
     "down_fused_l0": ("k_down_col", "k_down_fused2"), "sstep_gram": ("k_sstep_gram",),
     "sstep_matvec": ("k_sstep_matvec",), "x_update": ("k_x_update",), "residual_ff": ("k_residual_ff",),
-    "step_fused_l0": ("k_step_col",),
+    "step_fused_l0": ("k_step_col",), "x_update_residual": ("k_x_update_residual2",),
 }
 # sources the kernels are built from (any change voids a traffic record)
 SOURCES = ["paper_2107_03679_amd/csrc/k_multigrid.hip", "paper_2107_03679_amd/csrc/k_krylov.hip",
@@ -46,7 +46,7 @@ PMC_REGEX = ("k_up_mv2|k_up_fused2|k_down_fused2|k_up_col|k_down_col|k_sstep|k_r
 
 def commands(workload: str) -> tuple[str, list[str]]:
     base = (f"python3 $R/bench.py --workload {workload} --steps 1 --warmup 0 --no-cpu-baseline --no-learned "
-            "--tune-cache $OUT/tune.jsonl")
+            "--no-vcycle-leg --tune-cache $OUT/tune.jsonl")
     trace = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -f csv -d $OUT/prof -o run "
              f"-- {base}")
     pmc = [(f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {ctr} --kernel-include-regex \"{PMC_REGEX}\" -f csv "
