@@ -33,7 +33,9 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="blobs512x60")
-    p.add_argument("--levels", type=int, default=7)
+    p.add_argument("--levels", type=int, default=None,
+                   help="multigrid levels; default 7 in 2D (coarsest ~10^2 at 512^2), 5 in 3D (coarsest 12^3 at 128^3: "
+                        "more levels would enlarge the extended grid from 177^3 to 193^3)")
     p.add_argument("--restart", type=int, default=8)
     p.add_argument("--cycle", type=int, default=3, help="1 = V, 2 = W, 3 = two coarse corrections on the finest "
                                                           "level and V-cycles below")
@@ -407,6 +409,8 @@ def main():
         args.kappa_im = 0.4 if wl["d"] == 2 else 0.5
     if args.omega is None:
         args.omega = 0.9 if wl["d"] == 2 else 0.8
+    if args.levels is None:
+        args.levels = 7 if wl["d"] == 2 else 5
     nmap = synth.workload_medium(args.workload).astype(np.float32).astype(np.float64)
     dirs = synth.workload_directions(args.workload, args.rhs)
     B = dirs.shape[0]
