@@ -1,8 +1,9 @@
 """Parity at the benchmark's full size and launch configuration.
 
 The 512^2 interior with 60 plane waves in [-60, 60] degrees (blob medium,
-seed 0), 7 levels, GMRES(8) in s-step form, two coarse corrections on the
-finest level, autotuned launch shapes, hipGraph replay: the whole batch is
+seed 0), 7 levels, GMRES(10) in s-step form, shift 1 + 0.4j, damping 0.9, two
+coarse corrections on the finest level, autotuned launch shapes, hipGraph
+replay (the settings bench.py runs by default): the whole batch is
 solved as bench.py times it; the first, a middle and the last plane wave are
 compared with exact sparse-LU solves of the FP64 oracle (field error <= 1e-5
 over the extended grid), and their float-float iterates are certified by a
@@ -25,15 +26,15 @@ def test_benchmark_workload_matches_exact_solutions(tmp_path):
 
     from paper_2107_03679_amd import helm
 
-    print("\n[full size: blobs512x60, 7 levels, GMRES(8) s-step, cycle 3]", flush=True)
+    print("\n[full size: blobs512x60, 7 levels, GMRES(10) s-step, cycle 3, kappa 1 + 0.4j]", flush=True)
     wl = synth.WORKLOADS["blobs512x60"]
     nmap = synth.workload_medium("blobs512x60").astype(np.float32).astype(np.float64)
     dirs = synth.workload_directions("blobs512x60")
     levels, w = 7, 20
     ne = helm.extended_size(wl["n"], w, levels)
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device="cuda"), (KBH / N_B) * (ne - 1),
-                       abl_width=w, beta=wl["beta"], levels=levels, restart=8, cycle=3, max_batch=60,
-                       max_iters=20000)
+                       abl_width=w, beta=wl["beta"], levels=levels, restart=10, cycle=3, max_batch=60,
+                       max_iters=20000, kappa=complex(1.0, 0.4), omega_jac=0.9)
     ctx.autotune(60, cache=str(tmp_path / "tune.jsonl"))
     rhs = ctx.plane_wave_rhs(dirs)
     x, st = ctx.solve(rhs)
@@ -54,9 +55,10 @@ def test_benchmark_workload_matches_exact_solutions(tmp_path):
     ctx.close()
 
 
-def _certify_full_size(name, levels, samples, tmp_path):
+def _certify_full_size(name, levels, samples, tmp_path, restart, kappa_im, omega):
     """Solve a named workload at its full size as bench.py launches it (autotuned shapes,
-    GMRES(8) in s-step form, cycle 3, hipGraph replay) and certify sampled plane waves with
+    GMRES(m) in s-step form, cycle 3, the bench's shift and damping, hipGraph replay) and
+    certify sampled plane waves with
     the oracle's independently assembled FP64 operator: an exact LU is out of reach at these
     sizes, so the check is the property that defines the solution, relative residual
     ||b - A (x_hi + x_lo)|| / ||b|| <= 1.05e-6, with b the oracle's own right-hand side
@@ -67,14 +69,15 @@ def _certify_full_size(name, levels, samples, tmp_path):
     from paper_2107_03679_amd import helm
 
     wl = synth.WORKLOADS[name]
-    print(f"\n[full size: {name}, {levels} levels, GMRES(8) s-step, cycle 3]", flush=True)
+    print(f"\n[full size: {name}, {levels} levels, GMRES({restart}) s-step, cycle 3, kappa 1 + {kappa_im}j]",
+          flush=True)
     nmap = synth.workload_medium(name).astype(np.float32).astype(np.float64)
     dirs = synth.workload_directions(name)
     B, w = dirs.shape[0], 20
     ne = helm.extended_size(wl["n"], w, levels)
     ctx = helm.Context(torch.tensor(nmap, dtype=torch.float32, device="cuda"), (KBH / N_B) * (ne - 1),
-                       abl_width=w, beta=wl["beta"], levels=levels, restart=8, cycle=3, max_batch=B,
-                       max_iters=20000)
+                       abl_width=w, beta=wl["beta"], levels=levels, restart=restart, cycle=3, max_batch=B,
+                       max_iters=20000, kappa=complex(1.0, kappa_im), omega_jac=omega)
     ctx.autotune(B, cache=str(tmp_path / "tune.jsonl"))
     rhs = ctx.plane_wave_rhs(dirs)
     x, st = ctx.solve(rhs)
@@ -97,10 +100,12 @@ def _certify_full_size(name, levels, samples, tmp_path):
 
 
 def test_strong_scattering_workload_residuals_certified(tmp_path):
-    """strong1024x120: 1024^2 interior, 120 plane waves, blob contrast up to 0.4, 7 levels."""
-    _certify_full_size("strong1024x120", 7, (0, 60, 119), tmp_path)
+    """strong1024x120: 1024^2 interior, 120 plane waves, blob contrast up to 0.4, 7 levels,
+    GMRES(10), shift 1 + 0.5j, damping 0.8 (the bench's settings for this medium)."""
+    _certify_full_size("strong1024x120", 7, (0, 60, 119), tmp_path, 10, 0.5, 0.8)
 
 
 def test_3d_workload_residuals_certified(tmp_path):
-    """cube128x40: 128^3 interior (177^3 grid), 40 plane waves on a 45-degree cone, 5 levels."""
-    _certify_full_size("cube128x40", 5, (0, 39), tmp_path)
+    """cube128x40: 128^3 interior (177^3 grid), 40 plane waves on a 45-degree cone, 5 levels,
+    GMRES(8), shift 1 + 0.5j, damping 0.8."""
+    _certify_full_size("cube128x40", 5, (0, 39), tmp_path, 8, 0.5, 0.8)
