@@ -81,9 +81,14 @@ __device__ __forceinline__ float fetch1(const NetSrc& s, long long img, int D, i
 // the four wavefronts then take MT = TH TW / 64 row segments of 16 pixels each and
 // run the implicit GEMM over k = tap * cin + ci with A from LDS and B (weights) from
 // global memory (small, cache resident).  Pixels outside the layer read zeros.
+// With WL (weights larger than the L1), the weights pass through LDS instead, in
+// chunks of WKC k-values, double-buffered: the chunk after the current one is read
+// from global memory into registers while the current one is used, so no k-step
+// waits on an L2 round trip.  Same products in the same order either way.
 __device__ __forceinline__ int conv_pixel_stride(int cin) { return cin == 8 ? 8 : cin + 8; }
+constexpr int WKC = 64, WROW = WKC + 8;  // k per weight chunk; LDS row stride (bf16, padded against bank conflicts)
 
-template <int NCO, int TH, int TW, int MODE, int NDIM>
+template <int NCO, int TH, int TW, int MODE, int NDIM, bool WL>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   extern __shared__ __align__(16) bf16 tile[];
   constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64;
@@ -99,6 +104,28 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   constexpr int NSRC = MODE == 1 ? (NDIM == 3 ? 8 : 4) : 1;
   constexpr int BATCH = MODE == 1 ? (NDIM == 3 ? 1 : 2) : 8;
   const int nchunk = NZ * PLANE * cg8;
+  // weight chunks (WL): 16 NCO rows x WKC k, 16-byte pieces, zero past kpad
+  constexpr int WPC = 16 * NCO * (WKC / 8), WPT = (WPC + 255) / 256, WBUF = 16 * NCO * WROW;
+  bf16* wl = tile + NZ * PLANE * ps;
+  bf16x8 wreg[WPT];
+  auto wfetch = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = threadIdx.x + 256 * u, row = q / (WKC / 8), k = c * WKC + (q % (WKC / 8)) * 8;
+      wreg[u] = (q < WPC && k < a.kpad) ? load8(a.wt + (long long)row * a.kpad + k) : zero8();
+    }
+  };
+  auto wstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = threadIdx.x + 256 * u;
+      if (q < WPC) *reinterpret_cast<bf16x8*>(wl + buf * WBUF + (q / (WKC / 8)) * WROW + (q % (WKC / 8)) * 8) = wreg[u];
+    }
+  };
+  if constexpr (WL) {
+    wfetch(0);
+    wstore(0);
+  }
   for (int tb = 0; tb < nchunk; tb += 256 * BATCH) {
     const int t0 = tb + threadIdx.x;
     const int nslot = min(BATCH, (nchunk - tb + 255) / 256);  // uniform over the block
@@ -223,16 +250,48 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       for (int t = 0; t < NCO; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[t], A[m], acc[m][t], 0, 0, 0);
   };
   bf16x8 a0[MT], b0[NCO], a1[MT], b1[NCO];
-  read_step(0, a0, b0);
-  for (int kc = 0; kc < a.kpad; kc += 64) {
-    read_step(kc + 32, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs that do not need them
-    mfma_step(a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    read_step(kc + 64, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_step(a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
+  if constexpr (WL) {
+    // the same k-steps, two per chunk, with B from the chunk's LDS buffer
+    auto read_lds = [&](const bf16* wb, bf16x8* A, bf16x8* Bw) {
+      const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
+      const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
+        A[m] = tap < NT ? v : zero8();
+      }
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) Bw[t] = *reinterpret_cast<const bf16x8*>(wb + t * 16 * WROW);
+      ci0 += dci;
+      const int wrap = ci0 >= cin;
+      ci0 -= wrap * cin;
+      tap += dtap + wrap;
+    };
+    const int nwc = (a.kpad + WKC - 1) / WKC;
+    for (int c = 0; c < nwc; ++c) {
+      if (c + 1 < nwc) wfetch(c + 1);
+      const bf16* wb = wl + (c & 1) * WBUF + i16 * WROW + 8 * g;
+      read_lds(wb, a0, b0);
+      read_lds(wb + 32, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step(a0, b0);
+      mfma_step(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < nwc) wstore((c + 1) & 1);
+      __syncthreads();
+    }
+  } else {
+    read_step(0, a0, b0);
+    for (int kc = 0; kc < a.kpad; kc += 64) {
+      read_step(kc + 32, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs that do not need them
+      mfma_step(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      read_step(kc + 64, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   // epilogue: with the weights as the MFMA's first operand, acc[m][t][r] is output
   // channel t * 16 + 4 g + r of pixel i16 of segment m, so each lane writes four
@@ -718,9 +777,18 @@ template <int NCO, int TH, int TW, int NDIM>
 void conv_lds(hipStream_t s, const ConvArgs& a) {
   const size_t lds = (size_t)(NDIM == 3 ? 3 : 1) * (TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
   const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * (NDIM == 3 ? a.D : 1));
-  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM>), grid, dim3(256), lds, s, a);
-  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM>), grid, dim3(256), lds, s, a);
-  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM>), grid, dim3(256), lds, s, a);
+  // weights above the 32 KB L1 pass through LDS (two chunk buffers)
+  const bool wl = 16LL * NCO * a.kpad * (long long)sizeof(bf16) > 32768;
+  const size_t lw = lds + (wl ? 2 * 16 * NCO * WROW * sizeof(bf16) : 0);
+  if (wl) {
+    if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, true>), grid, dim3(256), lw, s, a);
+    else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, true>), grid, dim3(256), lw, s, a);
+    else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, true>), grid, dim3(256), lw, s, a);
+    return;
+  }
+  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, false>), grid, dim3(256), lds, s, a);
+  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, false>), grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, false>), grid, dim3(256), lds, s, a);
 }
 
 // 2D tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile stays
