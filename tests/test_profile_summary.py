@@ -42,3 +42,26 @@ def test_summary_calibrates_counters_and_writes_record(tmp_path):
     assert abs(rec["write_bytes_per_launch"] - 200.0 * 1024) < 1e-6
     md = (out / "kernels_toy.md").read_text()
     assert "10.00 us per launch in the trace" in md and "rocprofv3 --pmc FETCH_SIZE" in md
+
+
+def test_network_layer_table_and_summary(tmp_path):
+    """The network profile's FLOP count (2 x taps x cin x cout per output point, levels halving
+    with ceil) against a hand sum, and its summary of a synthetic trace (two warm-up and one
+    timed application, eight convolution dispatches each, in layer order)."""
+    from paper_2107_03679_amd import net_profile as npf
+
+    rows = npf.layer_table(2, 60, 577, npf.shapes_of(2))
+    sizes = [577, 289, 145, 73]
+    hand = 2 * 9 * 60 * (sizes[0] ** 2 * (4 * 16 + 48 * 16 + 16 * 2) + sizes[1] ** 2 * (16 * 32 + 96 * 32)
+                         + sizes[2] ** 2 * (32 * 64 + 128 * 64) + sizes[3] ** 2 * 64 * 64)
+    assert sum(r[5] for r in rows) == hand == 890042584320
+    rows3 = npf.layer_table(3, 8, 177, npf.shapes_of(3))
+    assert [r[3:5] for r in rows3] == [(4, 16), (16, 16), (16, 32), (32, 32), (64, 32), (48, 16), (32, 16), (16, 2)]
+    conv = "void (anonymous namespace)::k_conv_lds<1, 8, 32, 0, 2, false>(ConvArgs)"
+    trace = [[conv, 0, 1000 * (j + 1)] for j in range(16)] + [[conv, 0, 2000] for _ in range(8)]
+    _csv(str(tmp_path / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
+    npf.main(["summarize", str(tmp_path), "--dim", "2", "--nimg", "60", "--n", "577", "--warmup", "2", "--reps", "1",
+              "--out", str(tmp_path)])
+    text = (tmp_path / "net_layers_2d_60x577.md").read_text()
+    assert "| all | | | | 16.0 |" in text  # the timed application only: 8 layers x 2 us
+    assert "net_profile run --dim 2 --nimg 60 --n 577 --warmup 2 --reps 1" in text
