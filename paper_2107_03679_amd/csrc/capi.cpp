@@ -971,6 +971,17 @@ double time_ms(helm_ctx* c, F&& f, int reps) {
   return ms / reps;
 }
 
+// The fastest of nv launch variants: three interleaved rounds (clock ramps and drift
+// reach every variant alike), each variant's best mean over `reps` launches; ties go
+// to the lower index.
+template <class F>
+int fastest_variant(helm_ctx* c, int nv, F&& launch, int reps) {
+  std::vector<double> best((size_t)nv, 1e30);
+  for (int round = 0; round < 3; ++round)
+    for (int v = 0; v < nv; ++v) best[v] = std::min(best[v], time_ms(c, [&] { launch(v); }, reps));
+  return (int)(std::min_element(best.begin(), best.end()) - best.begin());
+}
+
 }  // namespace
 
 extern "C" {
@@ -1436,18 +1447,18 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
         const LevelArgs K = level_K(c, l);
         if (l > 0) check(hipMemsetAsync(f.rc, 0, (size_t)B * f.N * sizeof(c32), c->s), "memset");
         check(hipMemsetAsync(cr.e, 0, (size_t)B * cr.N * sizeof(c32), c->s), "memset");
-        double best = 1e30;
-        for (int v = 0; v < mg_down_variants(); ++v) {
-          const double ms = time_ms(
-              c, [&] { launch_down_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.rc, cr.N}, cr.n, nullptr, v); }, 5);
-          if (ms < best) best = ms, c->tune_down[l] = v;
-        }
-        best = 1e30;
-        for (int v = 0; v < mg_up_variants(); ++v) {
-          const double ms = time_ms(
-              c, [&] { launch_up_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.e, cr.N}, cr.n, out, nullptr, v); }, 5);
-          if (ms < best) best = ms, c->tune_up[l] = v;
-        }
+        c->tune_down[l] = fastest_variant(
+            c, mg_down_variants(),
+            [&](int v) {
+              launch_down_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.rc, cr.N}, cr.n, nullptr, v);
+            },
+            5);
+        c->tune_up[l] = fastest_variant(
+            c, mg_up_variants(),
+            [&](int v) {
+              launch_up_fused2(c->s, B, r, ScaleSet{nullptr, 0}, K, om, VecSet{cr.e, cr.N}, cr.n, out, nullptr, v);
+            },
+            5);
       }
     }
     // 2. the row height of the fused finest up-leg + basis matvec (the s-step form's finest step)
@@ -1456,29 +1467,27 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
       const float om = (float)c->o.omega_jac;
       const Level& L1 = c->lv[1];
       check(hipMemsetAsync(L1.e, 0, (size_t)B * L1.N * sizeof(c32), c->s), "memset");
-      double best = 1e30;
-      for (int v = 0; v < mg_up_mv_variants(); ++v) {
-        const double ms = time_ms(
-            c, [&] {
-              launch_up_mv2(c->s, B, r0, ScaleSet{nullptr, 0}, level_K(c, 0), fine_A(c), om, VecSet{L1.e, L1.N},
-                            L1.n, z0, VecSet{c->d_T0, N0}, nullptr, v);
-            }, 5);
-        if (ms < best) best = ms, c->tune_mv = v;
-      }
+      c->tune_mv = fastest_variant(
+          c, mg_up_mv_variants(),
+          [&](int v) {
+            launch_up_mv2(c->s, B, r0, ScaleSet{nullptr, 0}, level_K(c, 0), fine_A(c), om, VecSet{L1.e, L1.N}, L1.n,
+                          z0, VecSet{c->d_T0, N0}, nullptr, v);
+          },
+          5);
     }
     // 3. the single-launch threshold for the coarse levels, on whole V-cycles
     if (c->o.coarse_single_launch) {
       const long long cand2[] = {0, 24LL * 24, 48LL * 48, 96LL * 96};
       const long long cand3[] = {0, 8LL * 8 * 8, 16LL * 16 * 16, 24LL * 24 * 24};
       const long long* cand = c->dim == 2 ? cand2 : cand3;
-      double best = 1e30;
-      long long pick = -1;
-      for (int i = 0; i < 4; ++i) {
-        c->coarse_max = cand[i];
-        const double ms = time_ms(c, vcycle, 3);
-        if (ms < best) best = ms, pick = cand[i];
-      }
-      c->coarse_max = pick;
+      const int pick = fastest_variant(
+          c, 4,
+          [&](int i) {
+            c->coarse_max = cand[i];
+            vcycle();
+          },
+          3);
+      c->coarse_max = cand[pick];
     }
     if (cache_path) tune_save(c, cache_path, key);
   }
