@@ -263,8 +263,17 @@ bool legs_fused(const helm_ctx* c, int l) {
   return !single;
 }
 
+// True when a zero-guess visit of level l on the level's own buffers runs the fused
+// 3D legs (not the coarsest solve, not the single-launch coarse cycle), whose up-leg
+// can add its result to the output (a repeated visit without a separate add pass).
+bool legs3_fused(const helm_ctx* c, int l) {
+  if (l >= c->L - 1 || !c->o.fused || c->dim != 3 || c->o.nu1 != 1 || c->o.nu2 != 1) return false;
+  const bool v_below = c->o.cycle == 1 || c->o.cycle == 3;
+  return !(v_below && l >= 1 && c->o.coarse_single_launch && c->lv[l].N <= coarse_small(c));
+}
+
 void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act,
-              VecSet eres = VecSet{nullptr, 0});
+              VecSet eres = VecSet{nullptr, 0}, bool accumulate = false);
 
 // The coarse-grid corrections of one visit of level l (Alg. 2's CycleType; for
 // cycle = 3 two on the finest level and one below), from the right-hand side
@@ -295,6 +304,10 @@ VecSet coarse_visits(helm_ctx* c, int B, int l, const int* act) {
       ProfScope ps(c, lvl_name("level_residual", l + 1), Bp * 24.0 * Nc1 + 8.0 * Nc1);
       launch_level_residual(c->s, c->dim, B, rc, ecur, level_K(c, l + 1), rr, act);
     }
+    if (legs3_fused(c, l + 1)) {  // the up-leg adds MG(r - K e, 0) to e in place
+      mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, ecur, true, act, VecSet{nullptr, 0}, true);
+      continue;
+    }
     mg_cycle(c, B, l + 1, rr, ScaleSet{nullptr, 0}, other, true, act);
     ProfScope ps(c, lvl_name("add", l + 1), Bp * 24.0 * Nc1);
     launch_add(c->s, B, other, ecur, crs.N, act);
@@ -306,9 +319,10 @@ VecSet coarse_visits(helm_ctx* c, int B, int l, const int* act) {
 // guess when zero_guess is false).  Fused 2D legs serve the common case.
 // With eres.p set (only where legs_fused(l)), the visit starts from the
 // solution eres instead: out = eres + MG(r - K eres, 0), the residual formed
-// inside the legs; out must not alias eres.
+// inside the legs; out must not alias eres.  With accumulate (only where
+// legs3_fused(l)), out += MG(r, 0).
 void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool zero_guess, const int* act,
-              VecSet eres) {
+              VecSet eres, bool accumulate) {
   const int dim = c->dim;
   if (l == c->L - 1) {  // coarsest: exact solve (the guess is irrelevant)
     ProfScope ps(c, "coarse_solve", 8.0 * c->Nc * c->Nc + c->prof_B * 16.0 * c->Nc);
@@ -320,7 +334,7 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const bool vcycle11 = c->o.fused && zero_guess && v_below && c->o.nu1 == 1 && c->o.nu2 == 1;
   const long long small = coarse_small(c);
   if (vcycle11 && l >= 1 && c->o.coarse_single_launch && fine.N <= small && rs.p == nullptr && r.stride == fine.N &&
-      out.stride == fine.N && eres.p == nullptr) {
+      out.stride == fine.N && eres.p == nullptr && !accumulate) {
     // levels l .. L-1 in one launch, one workgroup per right-hand side
     CoarseCycleArgs a{};
     a.dim = dim;
@@ -347,6 +361,8 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   const bool fused = c->o.fused && zero_guess && c->o.nu1 == 1 && c->o.nu2 == 1;
   const double Nf = (double)fine.N, Nc1 = (double)crs.N, Bp = c->prof_B;
   if (eres.p && (!fused || dim != 2)) throw HipError{hipErrorInvalidValue, "repeated visit outside the fused 2D legs"};
+  if (accumulate && !(fused && dim == 3))
+    throw HipError{hipErrorInvalidValue, "accumulating visit outside the fused 3D legs"};
   if (fused && dim == 3) {
     ProfScope ps(c, lvl_name("down_fused", l), Bp * 8.0 * (Nf + Nc1) + 8.0 * Nf);
     launch_down_fused3(c->s, B, r, rs, level_K(c, l), om, rc, crs.n, act);
@@ -380,8 +396,9 @@ void mg_cycle(helm_ctx* c, int B, int l, VecSet r, ScaleSet rs, VecSet out, bool
   }
   const VecSet ecur = coarse_visits(c, B, l, act);
   if (fused && dim == 3) {
-    ProfScope ps(c, lvl_name("up_fused", l), Bp * 8.0 * (2.0 * Nf + Nc1) + 8.0 * Nf);
-    launch_up_fused3(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act);
+    ProfScope ps(c, lvl_name(accumulate ? "up_fused_acc" : "up_fused", l),
+                 Bp * 8.0 * ((accumulate ? 3.0 : 2.0) * Nf + Nc1) + 8.0 * Nf);
+    launch_up_fused3(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, accumulate ? 1 : 0);
   } else if (fused && eres.p) {
     ProfScope ps(c, lvl_name("up_fused_res", l), Bp * 8.0 * (3.0 * Nf + Nc1) + 16.0 * Nf);
     launch_up_fused2(c->s, B, r, rs, level_K(c, l), om, ecur, crs.n, out, act, c->tune_up[l], eres);

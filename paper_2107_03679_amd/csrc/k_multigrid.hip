@@ -776,10 +776,12 @@ __global__ __launch_bounds__(256) void k_down_march3c(int nrhs, VecSet r, ScaleS
 // planes f - 2 .. f and r, W of the plane it smooths in registers, with the
 // next plane's loads in flight; only the in-plane neighbours go through LDS
 // (two planes).  Per fine plane f: v2(f) = W r + P e (the coarse planes that P
-// reads are kept two at a time in LDS), then z(f - 1) from v2(f - 2 .. f).
+// reads are kept two at a time in LDS), then z(f - 1) from v2(f - 2 .. f).  With acc
+// the leg adds z to the output instead of overwriting it (a repeated coarse visit:
+// e + MG(r - K e, 0) without a separate pass).
 constexpr int UX = 64, UY = 8, UZ = 16, URING = 2 * (UX + 2) + 2 * UY;
 __global__ __launch_bounds__(256) void k_up_march3c(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
-                                                    VecSet ec, int nc, VecSet z, const int* active) {
+                                                    VecSet ec, int nc, VecSet z, const int* active, int acc) {
   constexpr int CX = UX / 2 + 2, CY = UY / 2 + 2, NCP = CX * CY, ITC = (NCP + 255) / 256;
   __shared__ c32 sE[2][CY][CX];
   __shared__ c32 sV[2][UY + 2][UX + 2];
@@ -904,7 +906,9 @@ __global__ __launch_bounds__(256) void k_up_march3c(int nrhs, VecSet r, ScaleSet
         const c32(*P)[UX + 2] = sV[g & 1];
         const c32 nb = cadd(cadd(cadd(P[ly][lx - 1], P[ly][lx + 1]), cadd(P[ly - 1][lx], P[ly + 1][lx])),
                             cadd(vm[q], vf[q]));
-        zb[g * n2 + off[q]] = cadd(cscale(vc[q], 1.0f - omega), cmul(wc[q], cadd(rc[q], nb)));
+        const c32 zv = cadd(cscale(vc[q], 1.0f - omega), cmul(wc[q], cadd(rc[q], nb)));
+        const long long p = g * n2 + off[q];
+        zb[p] = acc ? cadd(zb[p], zv) : zv;
       }
     }
     __syncthreads();
@@ -1013,6 +1017,103 @@ __global__ void k_level_residual(int dim, VecSet bvec, ScaleSet bs, VecSet v, Le
   const c32 D = diag_at(lv, p, ghosts_of(c, lv.n, dim), dim);
   const c32 kv = csub(cmul(D, vb[p]), neighbour_sum(vb, p, c, lv.n, dim));
   out.p[(long long)b * out.stride + p] = csub(cscale(bvec.p[(long long)b * bvec.stride + p], scale_of(bs, b)), kv);
+}
+
+// The same residual in 3D, marching in z: a 64 x 8 column over 16 planes, two
+// points per thread, the in-plane neighbours from an LDS copy of the plane and a
+// one-point ring, the planes below and above in registers with the next plane's
+// loads in flight (the flat kernel's z-neighbours, a plane apart, mostly miss the
+// L2).  Neighbours summed in the order of neighbour_sum (zero outside the grid).
+constexpr int RMX = 64, RMY = 8, RMZ = 16;
+__global__ __launch_bounds__(256) void k_level_residual_march3(int nrhs, VecSet bvec, ScaleSet bs, VecSet v,
+                                                               LevelArgs lv, VecSet out, const int* active) {
+  __shared__ c32 sP[RMY + 2][RMX + 2];
+  const int n = lv.n;
+  const int tx_n = (n + RMX - 1) / RMX, ty_n = (n + RMY - 1) / RMY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + RMZ - 1) / RMZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (active && !active[b]) return;
+  const int x0 = (id.t % tx_n) * RMX, y0 = ((id.t / tx_n) % ty_n) * RMY, z0 = (id.t / (tx_n * ty_n)) * RMZ;
+  const int z1 = min(n, z0 + RMZ);
+  const c32* vb = v.p + (long long)b * v.stride;
+  const c32* bb = bvec.p + (long long)b * bvec.stride;
+  c32* ob = out.p + (long long)b * out.stride;
+  const float sc = scale_of(bs, b);
+  const long long n2 = (long long)n * n;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  bool own[2];
+  long long o[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int gx = x0 + tx + 32 * h, gy = y0 + ty;
+    own[h] = gx < n && gy < n;
+    o[h] = own[h] ? (long long)gy * n + gx : 0;
+  }
+  int rx = -1, ry = -1;  // this thread's ring point (LDS coordinates), if any
+  {
+    const int t = threadIdx.x;
+    if (t < RMX + 2) rx = t, ry = 0;
+    else if (t < 2 * (RMX + 2)) rx = t - (RMX + 2), ry = RMY + 1;
+    else if (t < 2 * (RMX + 2) + RMY) rx = 0, ry = t - 2 * (RMX + 2) + 1;
+    else if (t < 2 * (RMX + 2) + 2 * RMY) rx = RMX + 1, ry = t - 2 * (RMX + 2) - RMY + 1;
+  }
+  const int rgx = x0 - 1 + rx, rgy = y0 - 1 + ry;
+  const bool ring = rx >= 0 && rgx >= 0 && rgx < n && rgy >= 0 && rgy < n;
+  const long long ro = ring ? (long long)rgy * n + rgx : 0;
+  auto at = [&](bool ok, int zz, long long off) {
+    return ok && zz >= 0 && zz < n ? vb[zz * n2 + off] : make_float2(0.f, 0.f);
+  };
+  c32 vm[2], vc[2], vp[2], kc[2], bc[2];
+  c32 vr = at(ring, z0, ro);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    vm[h] = at(own[h], z0 - 1, o[h]);
+    vc[h] = at(own[h], z0, o[h]);
+    vp[h] = at(own[h], z0 + 1, o[h]);
+    kc[h] = own[h] ? lv.coef[z0 * n2 + o[h]] : make_float2(0.f, 0.f);
+    bc[h] = own[h] ? bb[z0 * n2 + o[h]] : make_float2(0.f, 0.f);
+  }
+  for (int zz = z0; zz < z1; ++zz) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) sP[ty + 1][tx + 1 + 32 * h] = vc[h];
+    if (rx >= 0) sP[ry][rx] = vr;
+    c32 vn[2], kn[2], bn[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      vn[h] = at(own[h], zz + 2, o[h]);
+      const bool nx = own[h] && zz + 1 < n;
+      kn[h] = nx ? lv.coef[(zz + 1) * n2 + o[h]] : make_float2(0.f, 0.f);
+      bn[h] = nx ? bb[(zz + 1) * n2 + o[h]] : make_float2(0.f, 0.f);
+    }
+    const c32 vrn = at(ring, zz + 1, ro);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!own[h]) continue;
+      const int lx = tx + 1 + 32 * h, ly = ty + 1;
+      const int ng = ghosts3(x0 + tx + 32 * h, y0 + ty, zz, n);
+      const c32 D = make_float2(6.0f - kc[h].x - ng * lv.ghost.x, -kc[h].y - ng * lv.ghost.y);
+      c32 nb = make_float2(0.f, 0.f);
+      nb = cadd(nb, sP[ly][lx - 1]);
+      nb = cadd(nb, sP[ly][lx + 1]);
+      nb = cadd(nb, sP[ly - 1][lx]);
+      nb = cadd(nb, sP[ly + 1][lx]);
+      nb = cadd(nb, vm[h]);
+      nb = cadd(nb, vp[h]);
+      ob[zz * n2 + o[h]] = csub(cscale(bc[h], sc), csub(cmul(D, vc[h]), nb));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      vm[h] = vc[h];
+      vc[h] = vp[h];
+      vp[h] = vn[h];
+      kc[h] = kn[h];
+      bc[h] = bn[h];
+    }
+    vr = vrn;
+  }
 }
 
 // y += x for every active right-hand side
@@ -1169,10 +1270,10 @@ void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
 }
 
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active) {
+                      VecSet z, const int* active, int acc) {
   const int n = lv.n;
   const int tiles = ((n + UX - 1) / UX) * ((n + UY - 1) / UY) * ((n + UZ - 1) / UZ);
-  hipLaunchKernelGGL(k_up_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active);
+  hipLaunchKernelGGL(k_up_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active, acc);
 }
 
 template <int TY>
@@ -1329,6 +1430,12 @@ void launch_apply(hipStream_t s, int dim, int B, VecSet x, ScaleSet xs, LevelArg
 
 void launch_level_residual(hipStream_t s, int dim, int B, VecSet bvec, VecSet v, LevelArgs lv, VecSet out,
                            const int* active, ScaleSet bs) {
+  if (dim == 3) {
+    const int n = lv.n;
+    const int tiles = ((n + RMX - 1) / RMX) * ((n + RMY - 1) / RMY) * ((n + RMZ - 1) / RMZ);
+    hipLaunchKernelGGL(k_level_residual_march3, dim3(B * tiles), dim3(256), 0, s, B, bvec, bs, v, lv, out, active);
+    return;
+  }
   hipLaunchKernelGGL(k_level_residual, dim3(nblocks(lv.N, 256), B), dim3(256), 0, s, dim, bvec, bs, v, lv, out,
                      active);
 }

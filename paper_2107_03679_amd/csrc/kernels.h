@@ -46,7 +46,7 @@ void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
 void launch_down_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
                         const int* active);
 void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet ec, int nc,
-                      VecSet z, const int* active);
+                      VecSet z, const int* active, int acc = 0);  // acc: z += the leg's result
 // up-leg of Z_j and W_{j+1} = A Z_j in one launch (2D; la = the A operator)
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
                    int nc, VecSet z, VecSet w, const int* active, int cfg = 0);
