@@ -509,7 +509,7 @@ void true_residual(helm_ctx* c, int B, int first, int conj_rhs, bool fused_updat
     ProfScope ps(c, "residual_ff", c->prof_B * (first ? 16.0 : 32.0) * c->N0 + (first ? 0.0 : 16.0 * c->N0));
     launch_residual_ff(c->s, B, k, c->d_rhs, c->N0, conj_rhs, c->d_xhi, c->d_xlo, first, c->d_dhi, c->d_dlo,
                        c->h2_hi, c->h2_lo, k.V, (long long)(k.m + 1) * c->N0, 1.0f);
-    k.nres = k.nblk;
+    k.nres = krylov_residual_partials(k, first);
   }
   {
     ProfScope ps(c, "finalize", c->prof_B * k.nres * 4.0);

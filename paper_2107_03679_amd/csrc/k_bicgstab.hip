@@ -91,6 +91,13 @@ __device__ __forceinline__ double reduce_r(const KrylovArgs& k, int b) {
   return wave_sum_d(s);
 }
 
+// FP64 sum of the true residual's partial squared norms (k.nres of them)
+__device__ __forceinline__ double reduce_res(const KrylovArgs& k, int b) {
+  double s = 0.0;
+  for (int blk = threadIdx.x; blk < k.nres; blk += HELM_WAVE) s += k.P2[(long long)b * k.nres + blk];
+  return wave_sum_d(s);
+}
+
 __device__ __forceinline__ void breakdown(const KrylovArgs& k, int b) {
   k.status[b] = HELM_STATUS_BREAKDOWN_DEV;
   k.active[b] = 0;
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(HELM_WAVE) void k_bicg_rho(KrylovArgs k) {
 __global__ __launch_bounds__(HELM_WAVE) void k_bicg_finalize(KrylovArgs k, int first) {
   const int b = blockIdx.x;
   if (k.status[b] != HELM_RUNNING || k.active[b]) return;
-  const double s = reduce_r(k, b);
+  const double s = reduce_res(k, b);
   if (threadIdx.x != 0) return;
   const double rn = sqrt(s);
   if (first) {

@@ -967,6 +967,139 @@ __global__ __launch_bounds__(MT) void k_matvec_march3(int nrhs, KrylovArgs k, in
     zr = zrn;
   }
 }
+
+// The float-float true residual in 3D, marching in z (the layout of
+// k_matvec_march3): x_hi and x_lo of the planes below, at and above in registers,
+// the in-plane neighbours from LDS copies of the plane with a one-point ring.
+// Same arithmetic per point as ff_residual_point (in-grid neighbours in the same
+// order); one partial squared norm per column tile, k.P2[b][tile].
+__global__ __launch_bounds__(MT) void k_residual_ff_march3(int nrhs, KrylovArgs k, FFArgs a) {
+  __shared__ c32 sH[MY + 2][MX + 2];
+  __shared__ c32 sL[MY + 2][MX + 2];
+  __shared__ float red[NWAVE];
+  const int n = k.n;
+  const int tx_n = (n + MX - 1) / MX, ty_n = (n + MY - 1) / MY;
+  const unsigned tiles = (unsigned)(tx_n * ty_n * ((n + MZ - 1) / MZ));
+  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
+  const int b = id.b;
+  if (k.status && (k.status[b] != HELM_RUNNING || (k.bicg && k.active[b]))) return;
+  const int x0 = (id.t % tx_n) * MX, y0 = ((id.t / tx_n) % ty_n) * MY, z0 = (id.t / (tx_n * ty_n)) * MZ;
+  const int z1 = min(n, z0 + MZ);
+  const c32* xh = a.x_hi + (long long)b * k.N;
+  const c32* xl = a.x_lo ? a.x_lo + (long long)b * k.N : nullptr;
+  const c32* rb = a.rhs + (long long)b * a.rhs_stride;
+  c32* ro = a.r_out + (long long)b * a.r_stride;
+  const long long n2 = (long long)n * n;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  bool own[2];
+  long long o[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int gx = x0 + tx + 32 * h, gy = y0 + ty;
+    own[h] = gx < n && gy < n;
+    o[h] = own[h] ? (long long)gy * n + gx : 0;
+  }
+  int rx = -1, ry = -1;  // this thread's ring point (LDS coordinates), if any
+  {
+    const int t = threadIdx.x;
+    if (t < MX + 2) rx = t, ry = 0;
+    else if (t < 2 * (MX + 2)) rx = t - (MX + 2), ry = MY + 1;
+    else if (t < 2 * (MX + 2) + MY) rx = 0, ry = t - 2 * (MX + 2) + 1;
+    else if (t < 2 * (MX + 2) + 2 * MY) rx = MX + 1, ry = t - 2 * (MX + 2) - MY + 1;
+  }
+  const int rgx = x0 - 1 + rx, rgy = y0 - 1 + ry;
+  const bool ring = rx >= 0 && rgx >= 0 && rgx < n && rgy >= 0 && rgy < n;
+  const long long rof = ring ? (long long)rgy * n + rgx : 0;
+  const c32 zero = make_float2(0.f, 0.f);
+  auto hi = [&](bool ok, int z, long long off) { return ok && z >= 0 && z < n ? xh[z * n2 + off] : zero; };
+  auto lo = [&](bool ok, int z, long long off) { return ok && xl && z >= 0 && z < n ? xl[z * n2 + off] : zero; };
+  c32 hm[2], hc[2], hp[2], lm[2], lc[2], lp[2], dh[2], dl[2], bc[2];
+  c32 rh = hi(ring, z0, rof), rl = lo(ring, z0, rof);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    hm[h] = hi(own[h], z0 - 1, o[h]);
+    lm[h] = lo(own[h], z0 - 1, o[h]);
+    hc[h] = hi(own[h], z0, o[h]);
+    lc[h] = lo(own[h], z0, o[h]);
+    hp[h] = hi(own[h], z0 + 1, o[h]);
+    lp[h] = lo(own[h], z0 + 1, o[h]);
+    const long long p = z0 * n2 + o[h];
+    dh[h] = own[h] ? a.d_hi[p] : zero;
+    dl[h] = own[h] ? a.d_lo[p] : zero;
+    bc[h] = own[h] ? rb[p] : zero;
+  }
+  float nrm = 0.f;
+  for (int z = z0; z < z1; ++z) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      sH[ty + 1][tx + 1 + 32 * h] = hc[h];
+      sL[ty + 1][tx + 1 + 32 * h] = lc[h];
+    }
+    if (rx >= 0) {
+      sH[ry][rx] = rh;
+      sL[ry][rx] = rl;
+    }
+    // the next plane's loads
+    c32 hn[2], ln[2], dhn[2], dln[2], bn[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      hn[h] = hi(own[h], z + 2, o[h]);
+      ln[h] = lo(own[h], z + 2, o[h]);
+      const bool nx = own[h] && z + 1 < n;
+      const long long p = nx ? (z + 1) * n2 + o[h] : 0;
+      dhn[h] = nx ? a.d_hi[p] : zero;
+      dln[h] = nx ? a.d_lo[p] : zero;
+      bn[h] = nx ? rb[p] : zero;
+    }
+    const c32 rhn = hi(ring, z + 1, rof), rln = lo(ring, z + 1, rof);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!own[h]) continue;
+      const int lx = tx + 1 + 32 * h, ly = ty + 1, gx = x0 + tx + 32 * h, gy = y0 + ty;
+      cff r = ff_scaled_rhs(a, bc[h]);
+      cff ax = cff_mul(cff_make(dh[h], dl[h]), cff_make(hc[h], lc[h]));
+      cff nb = {ff_from(0.f), ff_from(0.f)};  // the in-grid neighbours in the order of ff_residual_point
+      if (gx > 0) nb = cff_add(nb, cff_make(sH[ly][lx - 1], sL[ly][lx - 1]));
+      if (gx < n - 1) nb = cff_add(nb, cff_make(sH[ly][lx + 1], sL[ly][lx + 1]));
+      if (gy > 0) nb = cff_add(nb, cff_make(sH[ly - 1][lx], sL[ly - 1][lx]));
+      if (gy < n - 1) nb = cff_add(nb, cff_make(sH[ly + 1][lx], sL[ly + 1][lx]));
+      if (z > 0) nb = cff_add(nb, cff_make(hm[h], lm[h]));
+      if (z < n - 1) nb = cff_add(nb, cff_make(hp[h], lp[h]));
+      ax = cff_sub(ax, nb);
+      r = cff_sub(r, ax);
+      const c32 rv = ff_round(r);
+      ro[z * n2 + o[h]] = cscale(rv, a.out_scale);
+      nrm = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, nrm));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      hm[h] = hc[h];
+      lm[h] = lc[h];
+      hc[h] = hp[h];
+      lc[h] = lp[h];
+      hp[h] = hn[h];
+      lp[h] = ln[h];
+      dh[h] = dhn[h];
+      dl[h] = dln[h];
+      bc[h] = bn[h];
+    }
+    rh = rhn;
+    rl = rln;
+  }
+  if (!k.P2) return;
+  nrm = wave_sum(nrm);
+  const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
+  if (lane == 0) red[wave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) s += red[q];
+    k.P2[(long long)b * tiles + id.t] = s;
+  }
+}
 }  // namespace
 
 void launch_sstep_matvec(hipStream_t s, int B, const KrylovArgs& k, int j, const LevelArgs& fine) {
@@ -1020,10 +1153,19 @@ void launch_givens(hipStream_t s, int B, const KrylovArgs& k, int j) {
 void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo) {
   hipLaunchKernelGGL(k_x_update, dim3(k.nblk, B), dim3(NT), 0, s, k, x_hi, x_lo);
 }
+int krylov_residual_partials(const KrylovArgs& k, int x_zero) {
+  if (k.dim != 3 || x_zero) return k.nblk;
+  const int n = k.n;
+  return ((n + MX - 1) / MX) * ((n + MY - 1) / MY) * ((n + MZ - 1) / MZ);
+}
 void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
                         int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* d_hi,
                         const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale) {
   FFArgs a{rhs, rhs_stride, conj_rhs, x_hi, x_lo, x_zero, d_hi, d_lo, h2_hi, h2_lo, r_out, r_stride, out_scale};
+  if (k.dim == 3 && !x_zero) {  // the stencil's z-neighbours through registers
+    hipLaunchKernelGGL(k_residual_ff_march3, dim3(B * krylov_residual_partials(k, 0)), dim3(MT), 0, s, B, k, a);
+    return;
+  }
   hipLaunchKernelGGL(k_residual_ff, dim3(B * k.nblk), dim3(NT), 0, s, B, k, a);
 }
 int krylov_xres_tiles(int n) { return ((n + XRES_TX - 1) / XRES_TX) * ((n + XRES_TY - 1) / XRES_TY); }

@@ -149,6 +149,8 @@ void launch_arnoldi_reduce(hipStream_t s, int B, const KrylovArgs& k, int j, int
 void launch_arnoldi_update(hipStream_t s, int B, const KrylovArgs& k, int j);
 void launch_givens(hipStream_t s, int B, const KrylovArgs& k, int j);
 void launch_x_update(hipStream_t s, int B, const KrylovArgs& k, c32* x_hi, c32* x_lo);
+// partial squared norms per right-hand side that launch_residual_ff writes (block or column tiles)
+int krylov_residual_partials(const KrylovArgs& k, int x_zero);
 void launch_residual_ff(hipStream_t s, int B, const KrylovArgs& k, const c32* rhs, long long rhs_stride,
                         int conj_rhs, const c32* x_hi, const c32* x_lo, int x_zero, const c32* d_hi,
                         const c32* d_lo, float h2_hi, float h2_lo, c32* r_out, long long r_stride, float out_scale);
