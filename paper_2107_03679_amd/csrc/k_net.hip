@@ -88,16 +88,24 @@ __device__ __forceinline__ float fetch1(const NetSrc& s, long long img, int D, i
 __device__ __forceinline__ int conv_pixel_stride(int cin) { return cin == 8 ? 8 : cin + 8; }
 constexpr int WKC = 64, WROW = WKC + 8;  // k per weight chunk; LDS row stride (bf16, padded against bank conflicts)
 
-template <int NCO, int TH, int TW, int MODE, int NDIM, bool WL>
+// With ZM > 0 (3D, plain or upsample-and-skip inputs of at most 64 channels) a block
+// marches through ZM output planes: four plane slots in LDS, the three a plane's
+// taps read and the next one, loaded into registers while the plane is computed
+// (a plane's halo is staged once instead of three times).
+template <int NCO, int TH, int TW, int MODE, int NDIM, bool WL, int ZM>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+  static_assert(ZM == 0 || (NDIM == 3 && MODE != 1 && !WL), "marching: 3D, no pooled input, weights in L1");
   extern __shared__ __align__(16) bf16 tile[];
   constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64;
   constexpr int NZ = NDIM == 3 ? 3 : 1, NT = NDIM == 3 ? 27 : 9, PLANE = (TH + 2) * TW2;
+  constexpr int NZS = ZM ? 4 : NZ;  // plane slots in LDS
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64, g = l / 16, i16 = l % 16;
   const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
   const int D = NDIM == 3 ? a.D : 1;
-  const long long img = NDIM == 3 ? (long long)blockIdx.z / D : (long long)blockIdx.z;
-  const int z0 = NDIM == 3 ? (int)(blockIdx.z % D) : 0;
+  const int nzb = ZM ? (D + ZM - 1) / ZM : D;  // blocks along z per image
+  const long long img = NDIM == 3 ? (long long)blockIdx.z / nzb : (long long)blockIdx.z;
+  const int z0 = NDIM == 3 ? (int)(blockIdx.z % nzb) * (ZM ? ZM : 1) : 0;
+  const int zend = ZM ? min(D, z0 + ZM) : z0 + 1;
   const int cin = a.cin, ps = conv_pixel_stride(cin), cg8 = cin / 8;
   // stage the halo tile: NZ (TH + 2)(TW + 2) pixels x cin / 8 chunks of 16 bytes; a batch
   // of loads is in flight per thread before any is used (points outside the layer store 0)
@@ -106,7 +114,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   const int nchunk = NZ * PLANE * cg8;
   // weight chunks (WL): 16 NCO rows x WKC k, 16-byte pieces, zero past kpad
   constexpr int WPC = 16 * NCO * (WKC / 8), WPT = (WPC + 255) / 256, WBUF = 16 * NCO * WROW;
-  bf16* wl = tile + NZ * PLANE * ps;
+  bf16* wl = tile + NZS * PLANE * ps;
   bf16x8 wreg[WPT];
   auto wfetch = [&](int c) {
 #pragma unroll
@@ -207,11 +215,6 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     }
   }
   __syncthreads();
-  f32x4 acc[MT][NCO];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   // LDS offset of this lane's pixel in segment m (tap (0, 0, 0) = the first plane's top-left)
   int base[MT];
 #pragma unroll
@@ -219,114 +222,158 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     const int seg = wave * MT + m, r = seg / SEG, c = (seg - r * SEG) * 16 + i16;
     base[m] = (r * TW2 + c) * ps;
   }
-  // Two register sets, two k-steps per iteration: the operands of one step are read
-  // (A from LDS, B = weights from global memory) while the MFMAs of the other run.
-  // Steps past the last tap (k >= NT cin, up to the even step count) read A = 0.
-  int tap = (8 * g) / cin, ci0 = 8 * g - tap * cin;  // k = 8 g at the first step
-  const int dtap = cin < 32 ? 32 / cin : 0, dci = cin < 32 ? 0 : 32;
-  const bf16* wrow = a.wt + (long long)i16 * a.kpad + 8 * g;
-  const long long wstride = 16LL * a.kpad;
-  auto read_step = [&](int kc, bf16x8* A, bf16x8* Bw) {
-    const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
-    const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
+  // marching (ZM): the next plane's halo, 16-byte pieces in registers (cin <= 64)
+  constexpr int SPT = ZM ? (PLANE * 8 + 255) / 256 : 1;
+  bf16x8 spre[SPT];
+  auto sfetch = [&](int zz) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
-      A[m] = tap < NT ? v : zero8();
+    for (int u = 0; u < SPT; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      spre[u] = zero8();
+      if (t < PLANE * cg8) {
+        const int q = t / cg8, cg = t - q * cg8, r = q / TW2, c = q - r * TW2;
+        const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+        if (zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          spre[u] = load8(src_addr<MODE, NDIM>(a.src, img, D, a.H, a.W, zz, yy, xx, cg * 8));
+      }
     }
-    const int kw = min(kc, a.kpad - 32);
-#pragma unroll
-    for (int t = 0; t < NCO; ++t) Bw[t] = load8(wrow + t * wstride + kw);
-    // advance k by 32: cin < 32 divides 32 (whole taps), else at most one wrap
-    ci0 += dci;
-    const int wrap = ci0 >= cin;
-    ci0 -= wrap * cin;
-    tap += dtap + wrap;
   };
-  auto mfma_step = [&](const bf16x8* A, const bf16x8* Bw) {
+  auto sstore = [&](int slot) {
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      if (t < PLANE * cg8) {
+        const int q = t / cg8, cg = t - q * cg8;
+        *reinterpret_cast<bf16x8*>(tile + (slot * PLANE + q) * ps + cg * 8) = spre[u];
+      }
+    }
+  };
+  for (int zc = z0; zc < zend; ++zc) {
+    if constexpr (ZM > 0) {
+      if (zc + 1 < zend) sfetch(zc + 2);  // the plane the next output plane adds
+    }
+    f32x4 acc[MT][NCO];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int t = 0; t < NCO; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[t], A[m], acc[m][t], 0, 0, 0);
-  };
-  bf16x8 a0[MT], b0[NCO], a1[MT], b1[NCO];
-  if constexpr (WL) {
-    // the same k-steps, two per chunk, with B from the chunk's LDS buffer
-    auto read_lds = [&](const bf16* wb, bf16x8* A, bf16x8* Bw) {
+      for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Two register sets, two k-steps per iteration: the operands of one step are read
+    // (A from LDS, B = weights from global memory) while the MFMAs of the other run.
+    // Steps past the last tap (k >= NT cin, up to the even step count) read A = 0.
+    int tap = (8 * g) / cin, ci0 = 8 * g - tap * cin;  // k = 8 g at the first step
+    const int dtap = cin < 32 ? 32 / cin : 0, dci = cin < 32 ? 0 : 32;
+    const bf16* wrow = a.wt + (long long)i16 * a.kpad + 8 * g;
+    const long long wstride = 16LL * a.kpad;
+    const int iz = zc - z0;  // slot of tap plane dz: (iz + dz) mod 4 when marching
+    auto read_step = [&](int kc, bf16x8* A, bf16x8* Bw) {
       const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
-      const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
+      const int pl = ZM ? ((iz + dz) & 3) : dz;
+      const int off = ((pl * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
         A[m] = tap < NT ? v : zero8();
       }
+      const int kw = min(kc, a.kpad - 32);
 #pragma unroll
-      for (int t = 0; t < NCO; ++t) Bw[t] = *reinterpret_cast<const bf16x8*>(wb + t * 16 * WROW);
+      for (int t = 0; t < NCO; ++t) Bw[t] = load8(wrow + t * wstride + kw);
+      // advance k by 32: cin < 32 divides 32 (whole taps), else at most one wrap
       ci0 += dci;
       const int wrap = ci0 >= cin;
       ci0 -= wrap * cin;
       tap += dtap + wrap;
     };
-    const int nwc = (a.kpad + WKC - 1) / WKC;
-    for (int c = 0; c < nwc; ++c) {
-      if (c + 1 < nwc) wfetch(c + 1);
-      const bf16* wb = wl + (c & 1) * WBUF + i16 * WROW + 8 * g;
-      read_lds(wb, a0, b0);
-      read_lds(wb + 32, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      mfma_step(a0, b0);
-      mfma_step(a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      if (c + 1 < nwc) wstore((c + 1) & 1);
+    auto mfma_step = [&](const bf16x8* A, const bf16x8* Bw) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NCO; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[t], A[m], acc[m][t], 0, 0, 0);
+    };
+    bf16x8 a0[MT], b0[NCO], a1[MT], b1[NCO];
+    if constexpr (WL) {
+      // the same k-steps, two per chunk, with B from the chunk's LDS buffer
+      auto read_lds = [&](const bf16* wb, bf16x8* A, bf16x8* Bw) {
+        const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
+        const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
+          A[m] = tap < NT ? v : zero8();
+        }
+#pragma unroll
+        for (int t = 0; t < NCO; ++t) Bw[t] = *reinterpret_cast<const bf16x8*>(wb + t * 16 * WROW);
+        ci0 += dci;
+        const int wrap = ci0 >= cin;
+        ci0 -= wrap * cin;
+        tap += dtap + wrap;
+      };
+      const int nwc = (a.kpad + WKC - 1) / WKC;
+      for (int c = 0; c < nwc; ++c) {
+        if (c + 1 < nwc) wfetch(c + 1);
+        const bf16* wb = wl + (c & 1) * WBUF + i16 * WROW + 8 * g;
+        read_lds(wb, a0, b0);
+        read_lds(wb + 32, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(a0, b0);
+        mfma_step(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (c + 1 < nwc) wstore((c + 1) & 1);
+        __syncthreads();
+      }
+    } else {
+      read_step(0, a0, b0);
+      for (int kc = 0; kc < a.kpad; kc += 64) {
+        read_step(kc + 32, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs that do not need them
+        mfma_step(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        read_step(kc + 64, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // epilogue: with the weights as the MFMA's first operand, acc[m][t][r] is output
+    // channel t * 16 + 4 g + r of pixel i16 of segment m, so each lane writes four
+    // consecutive channels of one pixel (8 bytes in BF16, 16 in FP32)
+    const int cout = a.cout;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int seg = wave * MT + m, r = seg / SEG;
+      const int y = y0 + r, xo = x0 + (seg - r * SEG) * 16 + i16;
+      if (y >= a.H || xo >= a.W) continue;
+      const long long p = ((img * D + zc) * a.H + y) * a.W + xo;
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) {
+        const int c0 = t * 16 + 4 * g;
+        if (c0 >= cout) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float bias = (a.bias && c0 + q < cout) ? a.bias[c0 + q] : 0.f;
+          v[q] = acc[m][t][q] + bias;
+          if (a.relu) v[q] = fmaxf(v[q], 0.f);
+        }
+        if (a.out32) {
+          float* dst = a.out32 + p * a.out_ct + a.out_off + c0;
+          if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+          else
+            for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
+        } else {
+          // BF16 outputs have a multiple of 8 channels
+          typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+          bf16x4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
+          *reinterpret_cast<bf16x4*>(a.out + p * a.out_ct + a.out_off + c0) = o;
+        }
+      }
+    }
+    if constexpr (ZM > 0) {
+      // the prefetched plane zc + 2 replaces plane zc - 2 (read by no output plane from here on)
+      if (zc + 1 < zend) sstore((iz + 3) & 3);
       __syncthreads();
-    }
-  } else {
-    read_step(0, a0, b0);
-    for (int kc = 0; kc < a.kpad; kc += 64) {
-      read_step(kc + 32, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs that do not need them
-      mfma_step(a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      read_step(kc + 64, a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      mfma_step(a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // epilogue: with the weights as the MFMA's first operand, acc[m][t][r] is output
-  // channel t * 16 + 4 g + r of pixel i16 of segment m, so each lane writes four
-  // consecutive channels of one pixel (8 bytes in BF16, 16 in FP32)
-  const int cout = a.cout;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int seg = wave * MT + m, r = seg / SEG;
-    const int y = y0 + r, xo = x0 + (seg - r * SEG) * 16 + i16;
-    if (y >= a.H || xo >= a.W) continue;
-    const long long p = ((img * D + z0) * a.H + y) * a.W + xo;
-#pragma unroll
-    for (int t = 0; t < NCO; ++t) {
-      const int c0 = t * 16 + 4 * g;
-      if (c0 >= cout) continue;
-      float v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float bias = (a.bias && c0 + q < cout) ? a.bias[c0 + q] : 0.f;
-        v[q] = acc[m][t][q] + bias;
-        if (a.relu) v[q] = fmaxf(v[q], 0.f);
-      }
-      if (a.out32) {
-        float* dst = a.out32 + p * a.out_ct + a.out_off + c0;
-        if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-        else
-          for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
-      } else {
-        // BF16 outputs have a multiple of 8 channels
-        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-        bf16x4 o;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
-        *reinterpret_cast<bf16x4*>(a.out + p * a.out_ct + a.out_off + c0) = o;
-      }
     }
   }
 }
@@ -775,20 +822,31 @@ void launch_examples(hipStream_t s, int dim, int B, int ncrop, int S, int n_e, c
 
 template <int NCO, int TH, int TW, int NDIM>
 void conv_lds(hipStream_t s, const ConvArgs& a) {
+  constexpr int ZM = 8;  // output planes per block of the marching 3D form
+  if constexpr (NDIM == 3) {
+    const bool wl3 = 16LL * NCO * a.kpad * (long long)sizeof(bf16) > 32768;
+    if (!a.src.pool && !wl3 && a.cin <= 64) {
+      const size_t lz = (size_t)4 * (TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
+      const dim3 gz((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * ((a.D + ZM - 1) / ZM));
+      if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, 3, false, ZM>), gz, dim3(256), lz, s, a);
+      else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, 3, false, ZM>), gz, dim3(256), lz, s, a);
+      return;
+    }
+  }
   const size_t lds = (size_t)(NDIM == 3 ? 3 : 1) * (TH + 2) * (TW + 2) * (a.cin == 8 ? 8 : a.cin + 8) * sizeof(bf16);
   const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * (NDIM == 3 ? a.D : 1));
   // weights above the 32 KB L1 pass through LDS (two chunk buffers)
   const bool wl = 16LL * NCO * a.kpad * (long long)sizeof(bf16) > 32768;
   const size_t lw = lds + (wl ? 2 * 16 * NCO * WROW * sizeof(bf16) : 0);
   if (wl) {
-    if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, true>), grid, dim3(256), lw, s, a);
-    else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, true>), grid, dim3(256), lw, s, a);
-    else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, true>), grid, dim3(256), lw, s, a);
+    if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, true, 0>), grid, dim3(256), lw, s, a);
+    else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, true, 0>), grid, dim3(256), lw, s, a);
+    else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, true, 0>), grid, dim3(256), lw, s, a);
     return;
   }
-  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, false>), grid, dim3(256), lds, s, a);
-  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, false>), grid, dim3(256), lds, s, a);
-  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, false>), grid, dim3(256), lds, s, a);
+  if (a.src.pool) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 1, NDIM, false, 0>), grid, dim3(256), lds, s, a);
+  else if (a.src.cup > 0) hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 2, NDIM, false, 0>), grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, false, 0>), grid, dim3(256), lds, s, a);
 }
 
 // 2D tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile stays
