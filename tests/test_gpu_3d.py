@@ -101,3 +101,45 @@ def test_fused_3d_legs_match_oracle_over_several_tiles(cycle):
         ctx.close()
     assert rel(out[1], ref) < 1e-5
     assert rel(out[1], out[0]) < 1e-5
+
+
+def test_float_float_residual_3d(cube):
+    """The 3D float-float true residual (z-marching kernel: 64 x 8 columns over 16 planes, here
+    ragged in x and y and split 16 + 9 in z on the 25^3 grid) against FP64: r = b - A (x_hi + x_lo)
+    to far below complex64 resolution."""
+    prob, ctx, _ = cube
+    ex = model.ExactSolver(prob)
+    b = np.stack([model.rhs(prob, d) for d in synth.directions_cone(2)])
+    u = np.stack([ex.solve(bi) for bi in b])
+    x_hi = u.astype(np.complex64)
+    x_lo = (u - x_hi.astype(np.complex128)).astype(np.complex64)
+    b32 = b.astype(np.complex64)
+    r = to_np(ctx.residual(to_dev(b32), to_dev(x_hi), to_dev(x_lo)))
+    xs = x_hi.astype(np.complex128) + x_lo.astype(np.complex128)
+    ref = np.stack([b32[q].astype(np.complex128).ravel() - ex.A @ xs[q].ravel() for q in range(2)]).reshape(r.shape)
+    bn = np.linalg.norm(b32.ravel())
+    assert np.linalg.norm((r - ref).ravel()) / bn < 1e-9
+    assert np.linalg.norm(ref.ravel()) / bn < 1e-7
+    r32 = to_np(ctx.residual(to_dev(b32), to_dev(x_hi)))
+    assert np.linalg.norm(r32.ravel()) / bn > 1e-8
+
+
+def test_bicgstab_3d(cube):
+    """The paper's Alg. 3 in 3D (its decision kernel sums the marching residual's per-tile partial
+    norms): converged, certified by the oracle's FP64 operator, and the exact solution."""
+    from paper_2107_03679_amd import helm
+
+    prob, _, _ = cube
+    nmap = medium(16, d=3, seed=4)
+    ctx = gpu_context(nmap, w=4, levels=3, max_batch=2, krylov=helm.KRYLOV_BICGSTAB, restart=8)
+    rhs = ctx.plane_wave_rhs(synth.directions_cone(2))
+    x, st = ctx.solve(rhs)
+    assert st.converged and np.all(st.rel_res_true <= 1e-6), st
+    lo = to_np(ctx.solution_lo(2))
+    b = to_np(rhs)
+    ex = model.ExactSolver(prob)
+    for q in range(2):
+        rq = np.linalg.norm(b[q].ravel() - ex.A @ (to_np(x)[q] + lo[q]).ravel()) / np.linalg.norm(b[q].ravel())
+        assert rq <= 1.05e-6, (q, rq)
+        assert rel(to_np(x)[q], ex.solve(b[q])) < 1e-5, q
+    ctx.close()
