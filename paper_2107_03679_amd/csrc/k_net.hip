@@ -33,22 +33,22 @@ __device__ __forceinline__ bf16x8 zero8() {
 }
 
 // ---------------------------------------------------------------- layer inputs
-// Address of 8 input channels [ci0, ci0 + 8) of pixel (img, z, y, x) for the convolution's
-// halo staging (MODE 0: plain, 2: upsample + skip), with (z, y, x) clamped into the layer
-// (depth D, 1 in 2D); for MODE 1 (pool) the first of the 2^NDIM source pixels, clamped likewise.
+// Address of 8 input channels [ci0, ci0 + 8) of pixel (z, y, x) of one image for the
+// convolution's halo staging (MODE 0: plain, 2: upsample + skip), with (z, y, x) clamped
+// into the layer (depth D, 1 in 2D); for MODE 1 (pool) the first of the 2^NDIM source
+// pixels, clamped likewise.  in_img: the input's image (in_off applied), up_img: the
+// upsampled tensor's image; offsets inside an image fit 32 bits.
 template <int MODE, int NDIM>
-__device__ __forceinline__ const bf16* src_addr(const NetSrc& s, long long img, int D, int H, int W, int z, int y,
-                                                int x, int ci0) {
+__device__ __forceinline__ const bf16* src_ptr(const bf16* in_img, const bf16* up_img, const NetSrc& s, int D, int H,
+                                               int W, int z, int y, int x, int ci0) {
   const int zc = NDIM == 3 ? min(max(z, 0), D - 1) : 0;
   const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
-  if (MODE == 1)
-    return s.in + (((img * (NDIM == 3 ? s.Ds : 1) + (NDIM == 3 ? 2 * zc : 0)) * s.Hs + 2 * yc) * s.Ws + 2 * xc) *
-                      s.in_ct + s.in_off + ci0;
+  if (MODE == 1) return in_img + (((NDIM == 3 ? 2 * zc : 0) * s.Hs + 2 * yc) * s.Ws + 2 * xc) * s.in_ct + ci0;
   if (MODE == 2 && ci0 < s.cup) {
-    const int Du = NDIM == 3 ? (D + 1) / 2 : 1, Hu = (H + 1) / 2, Wu = (W + 1) / 2;
-    return s.up + (((img * Du + (zc >> 1)) * Hu + (yc >> 1)) * Wu + (xc >> 1)) * s.up_ct + ci0;
+    const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+    return up_img + (((zc >> 1) * Hu + (yc >> 1)) * Wu + (xc >> 1)) * s.up_ct + ci0;
   }
-  return s.in + (((img * D + zc) * H + yc) * W + xc) * s.in_ct + s.in_off + (ci0 - s.cup);
+  return in_img + ((zc * H + yc) * W + xc) * s.in_ct + (ci0 - s.cup);
 }
 
 // one input channel ci of pixel (img, z, y, x) inside the layer, the value the staging gives
@@ -112,6 +112,18 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
   constexpr int NSRC = MODE == 1 ? (NDIM == 3 ? 8 : 4) : 1;
   constexpr int BATCH = MODE == 1 ? (NDIM == 3 ? 1 : 2) : 8;
   const int nchunk = NZ * PLANE * cg8;
+  // per-image base pointers (offsets inside an image fit 32 bits) and 1 / cg8 for the
+  // chunk index: (t + 1/2) / cg8 is at least 1 / 32 away from an integer, far above
+  // the rounding of the product for t < 2^20
+  const bf16* in_img;
+  if (MODE == 1)
+    in_img = a.src.in + img * ((long long)(NDIM == 3 ? a.src.Ds : 1) * a.src.Hs * a.src.Ws * a.src.in_ct) + a.src.in_off;
+  else
+    in_img = a.src.in + img * ((long long)D * a.H * a.W * a.src.in_ct) + a.src.in_off;
+  const bf16* up_img = MODE == 2 ? a.src.up + img * ((long long)(NDIM == 3 ? (D + 1) / 2 : 1) * ((a.H + 1) / 2) *
+                                                     ((a.W + 1) / 2) * a.src.up_ct)
+                                 : nullptr;
+  const float rcg = 1.0f / (float)cg8;
   // weight chunks (WL): 16 NCO rows x WKC k, 16-byte pieces, zero past kpad
   constexpr int WPC = 16 * NCO * (WKC / 8), WPT = (WPC + 255) / 256, WBUF = 16 * NCO * WROW;
   bf16* wl = tile + NZS * PLANE * ps;
@@ -138,80 +150,84 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     const int t0 = tb + threadIdx.x;
     const int nslot = min(BATCH, (nchunk - tb + 255) / 256);  // uniform over the block
     bf16x8 v[BATCH][NSRC];
+    int dst[BATCH];  // LDS element offset of the chunk (-1: none); bit 30 set: outside the layer
+    int pm[BATCH];   // pooled input: which children lie inside the source (x, y, z bits)
 #pragma unroll
     for (int u = 0; u < BATCH; ++u) {
+      dst[u] = -1;
+      pm[u] = 0;
       if (u < nslot) {
-        const int t = min(t0 + 256 * u, nchunk - 1);
-        const int q = t / cg8, cg = t - q * cg8;
+        const int t = t0 + 256 * u, tt = min(t, nchunk - 1);
+        const int q = __float2int_rd(((float)tt + 0.5f) * rcg), cg = tt - q * cg8;
         const int pz = q / PLANE, rq = q - pz * PLANE, r = rq / TW2, c = rq - r * TW2;
-        const int zz = z0 - (NZ - 1) / 2 + pz;
-        const bf16* p = src_addr<MODE, NDIM>(a.src, img, D, a.H, a.W, zz, y0 - 1 + r, x0 - 1 + c, cg * 8);
+        const int zz = z0 - (NZ - 1) / 2 + pz, yy = y0 - 1 + r, xx = x0 - 1 + c;
+        const bf16* p = src_ptr<MODE, NDIM>(in_img, up_img, a.src, D, a.H, a.W, zz, yy, xx, cg * 8);
         if (MODE == 1) {
           // the 2 x 2 (x 2) children, clamped into the source (weights applied below)
-          const int yc = min(max(y0 - 1 + r, 0), a.H - 1), xc = min(max(x0 - 1 + c, 0), a.W - 1);
-          const long long dx = (2 * xc + 1 < a.src.Ws) ? a.src.in_ct : 0;
-          const long long dy = (2 * yc + 1 < a.src.Hs) ? (long long)a.src.Ws * a.src.in_ct : 0;
+          const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+          const int dx = (2 * xc + 1 < a.src.Ws) ? a.src.in_ct : 0;
+          const int dy = (2 * yc + 1 < a.src.Hs) ? a.src.Ws * a.src.in_ct : 0;
           v[u][0] = load8(p);
           v[u][NSRC > 1 ? 1 : 0] = load8(p + dx);
           v[u][NSRC > 2 ? 2 : 0] = load8(p + dy);
           v[u][NSRC > 3 ? 3 : 0] = load8(p + dy + dx);
+          int zb = 0;
           if (NDIM == 3) {
             const int zc = min(max(zz, 0), D - 1);
-            const long long dz = (2 * zc + 1 < a.src.Ds) ? (long long)a.src.Hs * a.src.Ws * a.src.in_ct : 0;
+            const int dz = (2 * zc + 1 < a.src.Ds) ? a.src.Hs * a.src.Ws * a.src.in_ct : 0;
             v[u][NSRC > 4 ? 4 : 0] = load8(p + dz);
             v[u][NSRC > 5 ? 5 : 0] = load8(p + dz + dx);
             v[u][NSRC > 6 ? 6 : 0] = load8(p + dz + dy);
             v[u][NSRC > 7 ? 7 : 0] = load8(p + dz + dy + dx);
+            zb = 2 * zz + 1 < a.src.Ds ? 4 : 0;
           }
+          pm[u] = (2 * xx + 1 < a.src.Ws ? 1 : 0) | (2 * yy + 1 < a.src.Hs ? 2 : 0) | zb;
         } else {
           v[u][0] = load8(p);
         }
+        const bool valid = zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        if (t < nchunk) dst[u] = (q * ps + cg * 8) | (valid ? 0 : 1 << 30);
       }
     }
 #pragma unroll
     for (int u = 0; u < BATCH; ++u) {
-      const int t = t0 + 256 * u;
-      if (u < nslot && t < nchunk) {
-        const int q = t / cg8, cg = t - q * cg8;
-        const int pz = q / PLANE, rq = q - pz * PLANE, r = rq / TW2, c = rq - r * TW2;
-        const int zz = z0 - (NZ - 1) / 2 + pz, yy = y0 - 1 + r, xx = x0 - 1 + c;
-        const bool valid = zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-        bf16x8 o = zero8();
-        if (MODE == 1) {
-          // average with zero padding: children past the source edge count 0
-          const bool hx = 2 * xx + 1 < a.src.Ws, hy = 2 * yy + 1 < a.src.Hs;
-          const float w1 = hx ? 1.f : 0.f, w2 = hy ? 1.f : 0.f, w3 = (hx && hy) ? 1.f : 0.f;
-          if (NDIM == 3) {
-            const bool hz = 2 * zz + 1 < a.src.Ds;
-            const float w4 = hz ? 1.f : 0.f, w5 = hz && hx ? 1.f : 0.f, w6 = hz && hy ? 1.f : 0.f,
-                        w7 = hz && hx && hy ? 1.f : 0.f;
+      if (dst[u] < 0) continue;
+      const bool valid = !(dst[u] & (1 << 30));
+      bf16x8 o = zero8();
+      if (MODE == 1) {
+        // average with zero padding: children past the source edge count 0
+        const bool hx = pm[u] & 1, hy = pm[u] & 2;
+        const float w1 = hx ? 1.f : 0.f, w2 = hy ? 1.f : 0.f, w3 = (hx && hy) ? 1.f : 0.f;
+        if (NDIM == 3) {
+          const bool hz = pm[u] & 4;
+          const float w4 = hz ? 1.f : 0.f, w5 = hz && hx ? 1.f : 0.f, w6 = hz && hy ? 1.f : 0.f,
+                      w7 = hz && hx && hy ? 1.f : 0.f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              float acc = (float)v[u][0][e];
-              acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
-              acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
-              acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
-              acc += w4 * (float)v[u][NSRC > 4 ? 4 : 0][e];
-              acc += w5 * (float)v[u][NSRC > 5 ? 5 : 0][e];
-              acc += w6 * (float)v[u][NSRC > 6 ? 6 : 0][e];
-              acc += w7 * (float)v[u][NSRC > 7 ? 7 : 0][e];
-              o[e] = (bf16)(0.125f * acc);
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              float acc = (float)v[u][0][e];
-              acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
-              acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
-              acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
-              o[e] = (bf16)(0.25f * acc);
-            }
+          for (int e = 0; e < 8; ++e) {
+            float acc = (float)v[u][0][e];
+            acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
+            acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
+            acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
+            acc += w4 * (float)v[u][NSRC > 4 ? 4 : 0][e];
+            acc += w5 * (float)v[u][NSRC > 5 ? 5 : 0][e];
+            acc += w6 * (float)v[u][NSRC > 6 ? 6 : 0][e];
+            acc += w7 * (float)v[u][NSRC > 7 ? 7 : 0][e];
+            o[e] = (bf16)(0.125f * acc);
           }
         } else {
-          o = v[u][0];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float acc = (float)v[u][0][e];
+            acc += w1 * (float)v[u][NSRC > 1 ? 1 : 0][e];
+            acc += w2 * (float)v[u][NSRC > 2 ? 2 : 0][e];
+            acc += w3 * (float)v[u][NSRC > 3 ? 3 : 0][e];
+            o[e] = (bf16)(0.25f * acc);
+          }
         }
-        *reinterpret_cast<bf16x8*>(tile + q * ps + cg * 8) = valid ? o : zero8();
+      } else {
+        o = v[u][0];
       }
+      *reinterpret_cast<bf16x8*>(tile + (dst[u] & ((1 << 30) - 1))) = valid ? o : zero8();
     }
   }
   __syncthreads();
@@ -234,7 +250,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
         const int q = t / cg8, cg = t - q * cg8, r = q / TW2, c = q - r * TW2;
         const int yy = y0 - 1 + r, xx = x0 - 1 + c;
         if (zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          spre[u] = load8(src_addr<MODE, NDIM>(a.src, img, D, a.H, a.W, zz, yy, xx, cg * 8));
+          spre[u] = load8(src_ptr<MODE, NDIM>(in_img, up_img, a.src, D, a.H, a.W, zz, yy, xx, cg * 8));
       }
     }
   };
@@ -248,6 +264,17 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       }
     }
   };
+  // the epilogue's bias values and output image base
+  const int cout = a.cout;
+  float bsv[NCO][4];
+#pragma unroll
+  for (int t = 0; t < NCO; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = t * 16 + 4 * g + q;
+      bsv[t][q] = (a.bias && ch < cout) ? a.bias[ch] : 0.f;
+    }
+  const long long oimg = img * ((long long)D * a.H * a.W * a.out_ct) + a.out_off;
   for (int zc = z0; zc < zend; ++zc) {
     if constexpr (ZM > 0) {
       if (zc + 1 < zend) sfetch(zc + 2);  // the plane the next output plane adds
@@ -337,13 +364,12 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     // epilogue: with the weights as the MFMA's first operand, acc[m][t][r] is output
     // channel t * 16 + 4 g + r of pixel i16 of segment m, so each lane writes four
     // consecutive channels of one pixel (8 bytes in BF16, 16 in FP32)
-    const int cout = a.cout;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int seg = wave * MT + m, r = seg / SEG;
       const int y = y0 + r, xo = x0 + (seg - r * SEG) * 16 + i16;
       if (y >= a.H || xo >= a.W) continue;
-      const long long p = ((img * D + zc) * a.H + y) * a.W + xo;
+      const int po = ((zc * a.H + y) * a.W + xo) * a.out_ct;  // inside the image
 #pragma unroll
       for (int t = 0; t < NCO; ++t) {
         const int c0 = t * 16 + 4 * g;
@@ -351,12 +377,11 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float bias = (a.bias && c0 + q < cout) ? a.bias[c0 + q] : 0.f;
-          v[q] = acc[m][t][q] + bias;
+          v[q] = acc[m][t][q] + bsv[t][q];
           if (a.relu) v[q] = fmaxf(v[q], 0.f);
         }
         if (a.out32) {
-          float* dst = a.out32 + p * a.out_ct + a.out_off + c0;
+          float* dst = a.out32 + oimg + po + c0;
           if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
           else
             for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
@@ -366,7 +391,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
           bf16x4 o;
 #pragma unroll
           for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
-          *reinterpret_cast<bf16x4*>(a.out + p * a.out_ct + a.out_off + c0) = o;
+          *reinterpret_cast<bf16x4*>(a.out + oimg + po + c0) = o;
         }
       }
     }
