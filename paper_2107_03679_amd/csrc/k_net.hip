@@ -286,7 +286,9 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     // Two register sets, two k-steps per iteration: the operands of one step are read
     // (A from LDS, B = weights from global memory) while the MFMAs of the other run.
-    // Steps past the last tap (k >= NT cin, up to the even step count) read A = 0.
+    // Past the last tap (NT cin <= k < kpad) the packed weights are zero (the padding
+    // of every weight matrix stays zero) and past kpad B is set to zero, so those
+    // steps add exact zeros whatever A they read (a real pixel of the last tap).
     int tap = (8 * g) / cin, ci0 = 8 * g - tap * cin;  // k = 8 g at the first step
     const int dtap = cin < 32 ? 32 / cin : 0, dci = cin < 32 ? 0 : 32;
     const bf16* wrow = a.wt + (long long)i16 * a.kpad + 8 * g;
@@ -297,13 +299,10 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       const int pl = ZM ? ((iz + dz) & 3) : dz;
       const int off = ((pl * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
-        A[m] = tap < NT ? v : zero8();
-      }
-      const int kw = min(kc, a.kpad - 32);
+      for (int m = 0; m < MT; ++m) A[m] = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
+      const bool kin = kc < a.kpad;  // uniform over the block
 #pragma unroll
-      for (int t = 0; t < NCO; ++t) Bw[t] = load8(wrow + t * wstride + kw);
+      for (int t = 0; t < NCO; ++t) Bw[t] = kin ? load8(wrow + t * wstride + kc) : zero8();
       // advance k by 32: cin < 32 divides 32 (whole taps), else at most one wrap
       ci0 += dci;
       const int wrap = ci0 >= cin;
@@ -324,10 +323,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
         const int tc = min(tap, NT - 1), dz = NDIM == 3 ? tc / 9 : 0, tp = tc - 9 * dz, dy = tp / 3, dx = tp - 3 * dy;
         const int off = ((dz * (TH + 2) + dy) * TW2 + dx) * ps + ci0;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
-          A[m] = tap < NT ? v : zero8();
-        }
+        for (int m = 0; m < MT; ++m) A[m] = *reinterpret_cast<const bf16x8*>(tile + base[m] + off);
 #pragma unroll
         for (int t = 0; t < NCO; ++t) Bw[t] = *reinterpret_cast<const bf16x8*>(wb + t * 16 * WROW);
         ci0 += dci;
