@@ -159,6 +159,15 @@ __host__ __device__ __forceinline__ int ghosts3(int x, int y, int z, int n) {
   return (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
 }
 
+// Element at a byte offset from a base: a wavefront-uniform base and a 32-bit
+// per-lane offset let the loads and stores use the scalar-base address form.
+__device__ __forceinline__ const c32& at_byte(const c32* base, unsigned off) {
+  return *reinterpret_cast<const c32*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ c32& at_byte(c32* base, unsigned off) {
+  return *reinterpret_cast<c32*>(reinterpret_cast<char*>(base) + off);
+}
+
 __device__ __forceinline__ float scale_of(ScaleSet s, int b) { return s.p ? s.p[(long long)b * s.stride] : 1.0f; }
 
 // diagonal of the level operator: 2d - coef - g * #ghosts

@@ -255,10 +255,13 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
 // thread owns one column (lane) and every fourth row, so that the v2, z and
 // output stages are done by the thread that loaded the point's r, W and A
 // coefficient (kept in registers, no reloads), and no index needs a division.
+// The grid is (right-hand side, tile column, tile row), the plain order of
+// xcd_tile() without its divisions.  A wavefront's rows are uniform (its index
+// is read into a scalar register), so every row's base address is scalar and
+// all loads and stores of a lane share one 32-bit column offset.
 template <int TY>
-__global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
-                                                 float omega, VecSet ec, int nc, VecSet z, VecSet w,
-                                                 const int* active) {
+__global__ __launch_bounds__(256) void k_up_mv2w(VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
+                                                 VecSet ec, int nc, VecSet z, VecSet w, const int* active) {
   constexpr int TX = 60, VX = 64, VY = TY + 4, ZY = TY + 2, RPI = 4, IV = VY / RPI;
   static_assert(VY % RPI == 0, "whole row groups");
   constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3;
@@ -266,44 +269,48 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
   __shared__ c32 sV[VY][VX];
   __shared__ c32 sZ[ZY][VX];  // z of region point (lx, ly) at sZ[ly - 1][lx]
   const int n = lv.n;
-  const int tiles_x = (n + TX - 1) / TX;
-  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
+  const int b = blockIdx.x;
   if (active && !active[b]) return;
-  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int fx0 = blockIdx.y * TX, fy0 = blockIdx.z * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const c32* rb = r.p + (long long)b * r.stride;
   const float sc = scale_of(rs, b);
-  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int lx = threadIdx.x & 63;
+  const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's first region row
   const int gx = fx0 - 2 + lx;
   const bool inx = gx >= 0 && gx < n;
+  const unsigned ob = (inx ? (unsigned)gx : 0u) * (unsigned)sizeof(c32);  // the lane's byte offset in a row
   const bool tcol = lx >= 2 && lx < TX + 2 && gx < n;  // a column of the tile
-  // every global load first: the coarse tile, r, W and (tile points) the A coefficient
+  // every global load first, back to back: the coarse tile, r, W and (tile rows) the A
+  // coefficient.  Loads go to clamped in-grid addresses without lane predicates, so none
+  // of them waits for another; values of lanes outside the grid are never used (every
+  // later use is guarded by the same condition), and the scale of r is applied at its use.
   constexpr int IE = (CX * CY + 255) / 256;
   c32 evc[IE];
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
-    const int idx = threadIdx.x + it * 256;
-    const int I = cxs + idx % CX, J = cys + idx / CX;
-    const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
-    evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+    const int idx = min((int)threadIdx.x + it * 256, CX * CY - 1);
+    const int I = min(max(cxs + idx % CX, 0), nc - 1), J = min(max(cys + idx / CX, 0), nc - 1);
+    evc[it] = eb[(long long)J * nc + I];
   }
   c32 rv[IV], wv[IV], kv[IV];
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    const bool ok = inx && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[it] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    kv[it] = ok && tcol && ly >= 2 && ly < TY + 2 ? la.coef[p] : make_float2(0.f, 0.f);
+    if (gy >= 0 && gy < n) {
+      const long long row = (long long)gy * n;
+      rv[it] = at_byte(rb + row, ob);
+      wv[it] = at_byte(lv.wd + row, ob);
+      if (ly >= 2 && ly < TY + 2) kv[it] = at_byte(la.coef + row, ob);
+    }
   }
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
     const int idx = threadIdx.x + it * 256;
-    if (idx < CX * CY) sE[idx / CX][idx % CX] = evc[it];
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+    if (idx < CX * CY) sE[idx / CX][idx % CX] = ok ? evc[it] : make_float2(0.f, 0.f);
   }
   __syncthreads();
 #pragma unroll
@@ -311,8 +318,9 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
     const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
     c32 v2 = make_float2(0.f, 0.f);
     if (inx && gy >= 0 && gy < n) {
-      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
-      const c32 a = sE[J][I], bb = sE[J][I + ox], c = sE[J + oy][I], d = sE[J + oy][I + ox];
+      rv[it] = cscale(rv[it], sc);
+      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox1 = gx & 1, oy = gy & 1;
+      const c32 a = sE[J][I], bb = sE[J][I + ox1], c = sE[J + oy][I], d = sE[J + oy][I + ox1];
       v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
     }
     sV[ly][lx] = v2;
@@ -321,7 +329,8 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
 #pragma unroll
   for (int it = 0; it < IV; ++it) {  // z on the tile and a one-point ring (zero outside the grid)
     const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    if (lx < 1 || lx > VX - 2 || ly < 1 || ly > VY - 2) continue;
+    if (ly < 1 || ly > VY - 2) continue;
+    if (lx < 1 || lx > VX - 2) continue;
     c32 zv = make_float2(0.f, 0.f);
     if (inx && gy >= 0 && gy < n) {
       const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
@@ -335,14 +344,15 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
 #pragma unroll
   for (int it = 0; it < IV; ++it) {  // Z_j and W_{j+1} = A Z_j on the tile
     const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    if (!tcol || ly < 2 || ly >= TY + 2 || gy >= n) continue;
-    const long long p = (long long)gy * n + gx;
+    if (ly < 2 || ly >= TY + 2 || gy >= n) continue;
+    if (!tcol) continue;
+    const long long row = (long long)gy * n;
     const c32 zc = sZ[ly - 1][lx];
     const int ng = ghosts2(gx, gy, n);
     const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
     const c32 nb = cadd(cadd(sZ[ly - 1][lx - 1], sZ[ly - 1][lx + 1]), cadd(sZ[ly - 2][lx], sZ[ly][lx]));
-    zb[p] = zc;
-    wb[p] = csub(cmul(D, zc), nb);
+    at_byte(zb + row, ob) = zc;
+    at_byte(wb + row, ob) = csub(cmul(D, zc), nb);
   }
 }
 
@@ -375,12 +385,17 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
   const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
   const int gx = fx0 + lx;
   const bool inx = lx < RXU && gx >= 0 && gx < n;
+  // with RES the fine correction, loaded from clamped in-grid addresses back to back with
+  // the row loads; zeros outside the grid are put in at the LDS stores
+  constexpr int IF = RES ? (FX * FY + 255) / 256 : 0;
+  c32 fv[IF > 0 ? IF : 1];
   if constexpr (RES) {
     const c32* fb = ev.p + (long long)b * ev.stride;
-    for (int idx = threadIdx.x; idx < FX * FY; idx += 256) {
-      const int fx = fx0 - 1 + idx % FX, fy = fy0 - 1 + idx / FX;
-      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
-      sF[idx / FX][idx % FX] = ok ? fb[(long long)fy * n + fx] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = min((int)threadIdx.x + it * 256, FX * FY - 1);
+      const int fx = min(max(fx0 - 1 + idx % FX, 0), n - 1), fy = min(max(fy0 - 1 + idx / FX, 0), n - 1);
+      fv[it] = fb[(long long)fy * n + fx];
     }
   }
   c32 rv[IV], wv[IV], kv[RES ? IV : 1];
@@ -393,7 +408,16 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
     wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
     if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
   }
-  if constexpr (RES) __syncthreads();
+  if constexpr (RES) {
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int fx = fx0 - 1 + idx % FX, fy = fy0 - 1 + idx / FX;
+      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
+      if (idx < FX * FY) sF[idx / FX][idx % FX] = ok ? fv[it] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int ly = r0 + RPI * it, gy = fy0 + ly;
@@ -463,21 +487,24 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
   const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
   const int gx = fx0 - 1 + lx;
   const bool inx = gx >= 0 && gx < n;
-  constexpr int IE = (CX * CY + 255) / 256;
-  c32 evc[IE];
+  // the coarse tile (and with RES the fine correction) loaded from clamped in-grid
+  // addresses, back to back with the row loads; zeros outside the grid are put in at
+  // the LDS stores
+  constexpr int IE = (CX * CY + 255) / 256, IF = RES ? (FX * FY + 255) / 256 : 0;
+  c32 evc[IE], fv[IF > 0 ? IF : 1];
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
-    const int idx = threadIdx.x + it * 256;
-    const int I = cxs + idx % CX, J = cys + idx / CX;
-    const bool ok = idx < CX * CY && I >= 0 && I < nc && J >= 0 && J < nc;
-    evc[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+    const int idx = min((int)threadIdx.x + it * 256, CX * CY - 1);
+    const int I = min(max(cxs + idx % CX, 0), nc - 1), J = min(max(cys + idx / CX, 0), nc - 1);
+    evc[it] = eb[(long long)J * nc + I];
   }
   if constexpr (RES) {
     const c32* fb = ev.p + (long long)b * ev.stride;
-    for (int idx = threadIdx.x; idx < FX * FY; idx += 256) {
-      const int fx = fx0 - 2 + idx % FX, fy = fy0 - 2 + idx / FX;
-      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
-      sF[idx / FX][idx % FX] = ok ? fb[(long long)fy * n + fx] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = min((int)threadIdx.x + it * 256, FX * FY - 1);
+      const int fx = min(max(fx0 - 2 + idx % FX, 0), n - 1), fy = min(max(fy0 - 2 + idx / FX, 0), n - 1);
+      fv[it] = fb[(long long)fy * n + fx];
     }
   }
   c32 rv[IV], wv[IV], kv[RES ? IV : 1];
@@ -493,7 +520,18 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
     const int idx = threadIdx.x + it * 256;
-    if (idx < CX * CY) sE[idx / CX][idx % CX] = evc[it];
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+    if (idx < CX * CY) sE[idx / CX][idx % CX] = ok ? evc[it] : make_float2(0.f, 0.f);
+  }
+  if constexpr (RES) {
+#pragma unroll
+    for (int it = 0; it < IF; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int fx = fx0 - 2 + idx % FX, fy = fy0 - 2 + idx / FX;
+      const bool ok = fx >= 0 && fx < n && fy >= 0 && fy < n;
+      if (idx < FX * FY) sF[idx / FX][idx % FX] = ok ? fv[it] : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -1281,9 +1319,8 @@ void up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs
             VecSet z, VecSet w, const int* active) {
   constexpr int TX = 60;
   const int n = lv.n;
-  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_mv2w<TY>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w,
-                     active);
+  const dim3 grid(B, (n + TX - 1) / TX, (n + TY - 1) / TY);
+  hipLaunchKernelGGL((k_up_mv2w<TY>), grid, dim3(256), 0, s, r, rs, lv, la, omega, ec, nc, z, w, active);
 }
 
 int mg_up_mv_variants() { return (int)(sizeof(kUpMvRows) / sizeof(kUpMvRows[0])); }
