@@ -175,40 +175,55 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
       rly = t - 2 * HX - TY + 1;
     }
   }
-  // issue every global load first
-  constexpr int NE = CX * CY, ITE = (NE + NT - 1) / NT;
-  c32 ev_c[ITE], rv[PY + 1], wv[PY + 1];
+  // issue every global load first, back to back: clamped in-grid addresses without
+  // predicates, so that none waits for another; zeros outside the grid are put in at the
+  // LDS stores, and values of points outside the grid are never used (every use below is
+  // guarded by the same condition); the scale of r is applied after the loads
+  constexpr int NE = CX * CY, ITE = (NE + NT - 1) / NT, ITF = RES ? (FX * FY + NT - 1) / NT : 0;
+  c32 ev_c[ITE], fv[ITF > 0 ? ITF : 1], rv[PY + 1], wv[PY + 1];
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    const int I = cxs + idx % CX, J = cys + idx / CX;
-    const bool ok = idx < NE && I >= 0 && I < nc && J >= 0 && J < nc;
-    ev_c[it] = ok ? eb[(long long)J * nc + I] : make_float2(0.f, 0.f);
+    const int idx = min((int)threadIdx.x + it * NT, NE - 1);
+    const int I = min(max(cxs + idx % CX, 0), nc - 1), J = min(max(cys + idx / CX, 0), nc - 1);
+    ev_c[it] = eb[(long long)J * nc + I];
   }
   c32 kv[RES ? PY + 1 : 1];
   if constexpr (RES) {
     const c32* fb = ev.p + (long long)b * ev.stride;
-    for (int idx = threadIdx.x; idx < FX * FY; idx += NT) {
-      const int gx = fx0 - 2 + idx % FX, gy = fy0 - 2 + idx / FX;
-      const bool ok = gx >= 0 && gx < n && gy >= 0 && gy < n;
-      sF[idx / FX][idx % FX] = ok ? fb[(long long)gy * n + gx] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int it = 0; it < ITF; ++it) {
+      const int idx = min((int)threadIdx.x + it * NT, FX * FY - 1);
+      const int gx = min(max(fx0 - 2 + idx % FX, 0), n - 1), gy = min(max(fy0 - 2 + idx / FX, 0), n - 1);
+      fv[it] = fb[(long long)gy * n + gx];
     }
   }
 #pragma unroll
   for (int k = 0; k <= PY; ++k) {
-    const int gx = k < PY ? fx0 + tx : fx0 - 1 + rlx;
-    const int gy = k < PY ? fy0 + ty0 + k : fy0 - 1 + rly;
-    const bool ok = (k < PY || rlx >= 0) && gx >= 0 && gx < n && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[k] = ok ? cscale(rb[p], sc) : make_float2(0.f, 0.f);
-    wv[k] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    if constexpr (RES) kv[k] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
+    const int gx = min(max(k < PY ? fx0 + tx : fx0 - 1 + rlx, 0), n - 1);
+    const int gy = min(max(k < PY ? fy0 + ty0 + k : fy0 - 1 + rly, 0), n - 1);
+    const long long p = (long long)gy * n + gx;
+    rv[k] = rb[p];
+    wv[k] = lv.wd[p];
+    if constexpr (RES) kv[k] = lv.coef[p];
   }
 #pragma unroll
   for (int it = 0; it < ITE; ++it) {
     const int idx = threadIdx.x + it * NT;
-    if (idx < NE) sE[idx / CX][idx % CX] = ev_c[it];
+    const int I = cxs + idx % CX, J = cys + idx / CX;
+    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+    if (idx < NE) sE[idx / CX][idx % CX] = ok ? ev_c[it] : make_float2(0.f, 0.f);
   }
+  if constexpr (RES) {
+#pragma unroll
+    for (int it = 0; it < ITF; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int gx = fx0 - 2 + idx % FX, gy = fy0 - 2 + idx / FX;
+      const bool ok = gx >= 0 && gx < n && gy >= 0 && gy < n;
+      if (idx < FX * FY) sF[idx / FX][idx % FX] = ok ? fv[it] : make_float2(0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k <= PY; ++k) rv[k] = cscale(rv[k], sc);
   __syncthreads();
   if constexpr (RES) {
     // r - K e at the own and ring points (sF is zero outside the grid)
@@ -280,7 +295,7 @@ __global__ __launch_bounds__(256) void k_up_mv2w(VecSet r, ScaleSet rs, LevelArg
   const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's first region row
   const int gx = fx0 - 2 + lx;
   const bool inx = gx >= 0 && gx < n;
-  const unsigned ob = (inx ? (unsigned)gx : 0u) * (unsigned)sizeof(c32);  // the lane's byte offset in a row
+  const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);  // nearest in-grid column, bytes
   const bool tcol = lx >= 2 && lx < TX + 2 && gx < n;  // a column of the tile
   // every global load first, back to back: the coarse tile, r, W and (tile rows) the A
   // coefficient.  Loads go to clamped in-grid addresses without lane predicates, so none
@@ -364,7 +379,7 @@ __global__ __launch_bounds__(256) void k_up_mv2w(VecSet r, ScaleSet rs, LevelArg
 // With RES the right-hand side is r - K e (a repeated visit, as in k_down_fused2),
 // formed from e staged in LDS on the region and a one-point ring.
 template <int TCY, bool RES>
-__global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+__global__ __launch_bounds__(256) void k_down_col(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
                                                   VecSet rc, int nc, const int* active, VecSet ev) {
   constexpr int TCX = 30, RXU = 2 * TCX + 3, RYU = 2 * TCY + 3, RPI = 4, VY = (RYU + RPI - 1) / RPI * RPI,
                 IV = VY / RPI;
@@ -373,18 +388,17 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
   __shared__ c32 sS[VY][64];
   __shared__ c32 sF[FY][FX];
   const int n = lv.n;
-  const int tiles_x = (nc + TCX - 1) / TCX;
-  const unsigned tiles = (unsigned)(tiles_x * ((nc + TCY - 1) / TCY));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
+  const int b = blockIdx.x;  // grid (right-hand side, tile column, tile row)
   if (active && !active[b]) return;
-  const int cx0 = (id.t % tiles_x) * TCX, cy0 = (id.t / tiles_x) * TCY;
+  const int cx0 = blockIdx.y * TCX, cy0 = blockIdx.z * TCY;
   const int fx0 = 2 * cx0 - 2, fy0 = 2 * cy0 - 2;
   const float sc = scale_of(rs, b);
   const c32* rb = r.p + (long long)b * r.stride;
-  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int lx = threadIdx.x & 63;
+  const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's first region row
   const int gx = fx0 + lx;
   const bool inx = lx < RXU && gx >= 0 && gx < n;
+  const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);  // nearest in-grid column, bytes
   // with RES the fine correction, loaded from clamped in-grid addresses back to back with
   // the row loads; zeros outside the grid are put in at the LDS stores
   constexpr int IF = RES ? (FX * FY + 255) / 256 : 0;
@@ -398,15 +412,18 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
       fv[it] = fb[(long long)fy * n + fx];
     }
   }
+  // rows are loaded from clamped in-grid columns without lane predicates; values of lanes
+  // outside the grid are never used (every use below is guarded by the same condition)
   c32 rv[IV], wv[IV], kv[RES ? IV : 1];
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int ly = r0 + RPI * it, gy = fy0 + ly;
-    const bool ok = inx && ly < RYU && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
+    if (ly < RYU && gy >= 0 && gy < n) {
+      const long long row = (long long)gy * n;
+      rv[it] = at_byte(rb + row, ob);
+      wv[it] = at_byte(lv.wd + row, ob);
+      if constexpr (RES) kv[it] = at_byte(lv.coef + row, ob);
+    }
   }
   if constexpr (RES) {
 #pragma unroll
@@ -421,18 +438,20 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int ly = r0 + RPI * it, gy = fy0 + ly;
-    rv[it] = cscale(rv[it], sc);
-    if constexpr (RES) {
-      // r - K e with K e = D e - (sum of in-grid neighbours); sF is zero outside the grid
-      if (inx && ly < RYU && gy >= 0 && gy < n) {
+    c32 v1 = make_float2(0.f, 0.f);  // W r, zero outside the grid
+    if (inx && ly < RYU && gy >= 0 && gy < n) {
+      rv[it] = cscale(rv[it], sc);
+      if constexpr (RES) {
+        // r - K e with K e = D e - (sum of in-grid neighbours); sF is zero outside the grid
         const int ng = ghosts2(gx, gy, n);
         const c32 D = make_float2(4.0f - kv[it].x - ng * lv.ghost.x, -kv[it].y - ng * lv.ghost.y);
         const int fx = lx + 1, fy = ly + 1;
         const c32 nb = cadd(cadd(sF[fy][fx - 1], sF[fy][fx + 1]), cadd(sF[fy - 1][fx], sF[fy + 1][fx]));
         rv[it] = cadd(csub(rv[it], cmul(D, sF[fy][fx])), nb);
       }
+      v1 = cmul(rv[it], wv[it]);
     }
-    sV[ly][lx] = cmul(rv[it], wv[it]);
+    sV[ly][lx] = v1;
   }
   __syncthreads();
 #pragma unroll
@@ -455,7 +474,8 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
       c32 acc = cscale(sS[sy][sx], 4.0f);
       acc = cadd(acc, cscale(cadd(cadd(sS[sy][sx - 1], sS[sy][sx + 1]), cadd(sS[sy - 1][sx], sS[sy + 1][sx])), 2.0f));
       acc = cadd(acc, cadd(cadd(sS[sy - 1][sx - 1], sS[sy - 1][sx + 1]), cadd(sS[sy + 1][sx - 1], sS[sy + 1][sx + 1])));
-      rc.p[(long long)b * rc.stride + (long long)J * nc + I] = cscale(acc, 0.25f);
+      at_byte(rc.p + (long long)b * rc.stride + (long long)J * nc, (unsigned)I * (unsigned)sizeof(c32)) =
+          cscale(acc, 0.25f);
     }
   }
 }
@@ -464,7 +484,7 @@ __global__ __launch_bounds__(256) void k_down_col(int nrhs, VecSet r, ScaleSet r
 // With RES the right-hand side is r - K e, formed from e on the region and a
 // one-point ring, and the leg writes e + z (as k_up_fused2).
 template <int TY, bool RES>
-__global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+__global__ __launch_bounds__(256) void k_up_col(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
                                                 VecSet ec, int nc, VecSet z, const int* active, VecSet ev) {
   constexpr int TX = 62, VY = TY + 2, RPI = 4, IV = VY / RPI;
   static_assert(VY % RPI == 0 && TY % 2 == 0, "whole row groups, even tile origin");
@@ -474,19 +494,18 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
   __shared__ c32 sV[VY][64];
   __shared__ c32 sF[FY][FX];
   const int n = lv.n;
-  const int tiles_x = (n + TX - 1) / TX;
-  const unsigned tiles = (unsigned)(tiles_x * ((n + TY - 1) / TY));
-  const TileId id = xcd_tile(blockIdx.x, nrhs, tiles, HELM_RHS_GROUP);
-  const int b = id.b;
+  const int b = blockIdx.x;  // grid (right-hand side, tile column, tile row)
   if (active && !active[b]) return;
-  const int fx0 = (id.t % tiles_x) * TX, fy0 = (id.t / tiles_x) * TY;
+  const int fx0 = blockIdx.y * TX, fy0 = blockIdx.z * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const c32* rb = r.p + (long long)b * r.stride;
   const float sc = scale_of(rs, b);
-  const int lx = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int lx = threadIdx.x & 63;
+  const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's first region row
   const int gx = fx0 - 1 + lx;
   const bool inx = gx >= 0 && gx < n;
+  const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);  // nearest in-grid column, bytes
   // the coarse tile (and with RES the fine correction) loaded from clamped in-grid
   // addresses, back to back with the row loads; zeros outside the grid are put in at
   // the LDS stores
@@ -507,15 +526,18 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
       fv[it] = fb[(long long)fy * n + fx];
     }
   }
+  // rows from clamped in-grid columns without lane predicates; values of lanes outside
+  // the grid are never used (every use below is guarded by the same condition)
   c32 rv[IV], wv[IV], kv[RES ? IV : 1];
 #pragma unroll
   for (int it = 0; it < IV; ++it) {
     const int gy = fy0 - 1 + r0 + RPI * it;
-    const bool ok = inx && gy >= 0 && gy < n;
-    const long long p = ok ? (long long)gy * n + gx : 0;
-    rv[it] = ok ? rb[p] : make_float2(0.f, 0.f);
-    wv[it] = ok ? lv.wd[p] : make_float2(0.f, 0.f);
-    if constexpr (RES) kv[it] = ok ? lv.coef[p] : make_float2(0.f, 0.f);
+    if (gy >= 0 && gy < n) {
+      const long long row = (long long)gy * n;
+      rv[it] = at_byte(rb + row, ob);
+      wv[it] = at_byte(lv.wd + row, ob);
+      if constexpr (RES) kv[it] = at_byte(lv.coef + row, ob);
+    }
   }
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
@@ -537,18 +559,16 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
 #pragma unroll
   for (int it = 0; it < IV; ++it) {  // v2 = W r + P e on the region (zero outside the grid)
     const int ly = r0 + RPI * it, gy = fy0 - 1 + ly;
-    rv[it] = cscale(rv[it], sc);
-    if constexpr (RES) {
-      if (inx && gy >= 0 && gy < n) {
+    c32 v2 = make_float2(0.f, 0.f);
+    if (inx && gy >= 0 && gy < n) {
+      rv[it] = cscale(rv[it], sc);
+      if constexpr (RES) {
         const int ng = ghosts2(gx, gy, n);
         const c32 D = make_float2(4.0f - kv[it].x - ng * lv.ghost.x, -kv[it].y - ng * lv.ghost.y);
         const int fx = lx + 1, fy = ly + 1;
         const c32 nb = cadd(cadd(sF[fy][fx - 1], sF[fy][fx + 1]), cadd(sF[fy - 1][fx], sF[fy + 1][fx]));
         rv[it] = cadd(csub(rv[it], cmul(D, sF[fy][fx])), nb);
       }
-    }
-    c32 v2 = make_float2(0.f, 0.f);
-    if (inx && gy >= 0 && gy < n) {
       const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox = gx & 1, oy = gy & 1;
       const c32 a = sE[J][I], bb = sE[J][I + ox], c = sE[J + oy][I], d = sE[J + oy][I + ox];
       v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
@@ -564,7 +584,7 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
     const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
     c32 zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
     if constexpr (RES) zv = cadd(zv, sF[ly + 1][lx + 1]);
-    zb[(long long)gy * n + gx] = zv;
+    at_byte(zb + (long long)gy * n, ob) = zv;
   }
 }
 
@@ -1360,24 +1380,20 @@ void launch_down_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                         const int* active, int cfg, VecSet e) {
   if (cfg == kDownCol) {
     constexpr int TCX = 30, TCY = 8;
-    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+    const dim3 grid(B, (nc + TCX - 1) / TCX, (nc + TCY - 1) / TCY);
     if (e.p)
-      hipLaunchKernelGGL((k_down_col<TCY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                         active, e);
+      hipLaunchKernelGGL((k_down_col<TCY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, rc, nc, active, e);
     else
-      hipLaunchKernelGGL((k_down_col<TCY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                         active, e);
+      hipLaunchKernelGGL((k_down_col<TCY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, rc, nc, active, e);
     return;
   }
   if (cfg == kDownCol16) {  // taller column tile: fewer halo rows per coarse row
     constexpr int TCX = 30, TCY = 16;
-    const int tiles = ((nc + TCX - 1) / TCX) * ((nc + TCY - 1) / TCY);
+    const dim3 grid(B, (nc + TCX - 1) / TCX, (nc + TCY - 1) / TCY);
     if (e.p)
-      hipLaunchKernelGGL((k_down_col<TCY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                         active, e);
+      hipLaunchKernelGGL((k_down_col<TCY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, rc, nc, active, e);
     else
-      hipLaunchKernelGGL((k_down_col<TCY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, rc, nc,
-                         active, e);
+      hipLaunchKernelGGL((k_down_col<TCY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, rc, nc, active, e);
     return;
   }
   switch (cfg) {
@@ -1393,24 +1409,20 @@ void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
                       VecSet z, const int* active, int cfg, VecSet e) {
   if (cfg == kUpCol) {
     constexpr int TX = 62, TY = 14;
-    const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+    const dim3 grid(B, (lv.n + TX - 1) / TX, (lv.n + TY - 1) / TY);
     if (e.p)
-      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                         active, e);
+      hipLaunchKernelGGL((k_up_col<TY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
     else
-      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                         active, e);
+      hipLaunchKernelGGL((k_up_col<TY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
     return;
   }
   if (cfg == kUpCol30) {  // taller column tile
     constexpr int TX = 62, TY = 30;
-    const int tiles = ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
+    const dim3 grid(B, (lv.n + TX - 1) / TX, (lv.n + TY - 1) / TY);
     if (e.p)
-      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                         active, e);
+      hipLaunchKernelGGL((k_up_col<TY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
     else
-      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z,
-                         active, e);
+      hipLaunchKernelGGL((k_up_col<TY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
     return;
   }
   switch (cfg) {
