@@ -514,7 +514,7 @@ def main():
             "launch_shapes": "default" if tune is None else {
                 "down_tiles": tune["down_tiles"], "up_tiles": tune["up_tiles"],
                 "coarse_single_launch_max_points": tune["coarse_single_launch_max_points"],
-                "up_mv_rows": tune["up_mv_rows"]},
+                "up_mv_rows": tune["up_mv_rows"], "up_mv_rhs_per_block": tune["up_mv_rhs_per_block"]},
         },
         "solver": {
             "all_converged": bool(all(s.converged for s in stats)),

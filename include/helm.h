@@ -483,6 +483,7 @@ typedef struct {
   double vcycle_ms;                     /* one preconditioner cycle for B right-hand sides, chosen shapes */
   double vcycle_default_ms;             /* ... with the default shapes (0 when from_cache) */
   int up_mv_rows;                       /* tile height of the fused finest up-leg + basis matvec (s-step form) */
+  int up_mv_rhs_per_block;              /* ... and the right-hand sides one of its workgroups walks */
 } helm_tune;
 
 /* Autotuner of the batched multigrid cycle (the batching / launch-shape part of

@@ -122,7 +122,7 @@ struct helm_ctx {
   // launch shapes (helm_autotune): fused-leg tile per level, single-launch coarse threshold
   int tune_down[HELM_MAX_LEVELS] = {0};
   int tune_up[HELM_MAX_LEVELS] = {0};
-  int tune_mv = 0;  // row-height variant of the fused finest up-leg + basis matvec
+  int tune_mv = 0;  // launch-shape variant (rows, right-hand sides per block) of the fused finest up-leg + matvec
   long long coarse_max = -1;  // points; -1: default (48^2 in 2D, 16^3 in 3D), 0: never
 
   // learned preconditioner (NULL: multigrid only)
@@ -990,13 +990,15 @@ double time_ms(helm_ctx* c, F&& f, int reps) {
 
 // The fastest of nv launch variants: three interleaved rounds (clock ramps and drift
 // reach every variant alike), each variant's best mean over `reps` launches; ties go
-// to the lower index.
+// to the lower index.  With a margin, variant 0 (the default) is kept unless another
+// is faster by more than that fraction.
 template <class F>
-int fastest_variant(helm_ctx* c, int nv, F&& launch, int reps) {
+int fastest_variant(helm_ctx* c, int nv, F&& launch, int reps, double keep_default_within = 0.0) {
   std::vector<double> best((size_t)nv, 1e30);
   for (int round = 0; round < 3; ++round)
     for (int v = 0; v < nv; ++v) best[v] = std::min(best[v], time_ms(c, [&] { launch(v); }, reps));
-  return (int)(std::min_element(best.begin(), best.end()) - best.begin());
+  const int v = (int)(std::min_element(best.begin(), best.end()) - best.begin());
+  return best[v] < best[0] * (1.0 - keep_default_within) ? v : 0;
 }
 
 }  // namespace
@@ -1478,7 +1480,11 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
             5);
       }
     }
-    // 2. the row height of the fused finest up-leg + basis matvec (the s-step form's finest step)
+    // 2. the launch shape of the fused finest up-leg + basis matvec (the s-step form's finest
+    // step).  Timed alone (every right-hand side active, no graph) it ranks shapes within a
+    // few percent differently from inside the solve, where the default (16 rows, 4 right-hand
+    // sides per workgroup) measured fastest on MI355X at 512^2 x 60; the default is kept
+    // unless a variant is clearly faster.
     c->tune_mv = 0;
     if (c->dim == 2 && c->o.fused && c->o.krylov == HELM_KRYLOV_SSTEP && c->o.fused_step == 2 && c->L >= 2) {
       const float om = (float)c->o.omega_jac;
@@ -1490,7 +1496,7 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
             launch_up_mv2(c->s, B, r0, ScaleSet{nullptr, 0}, level_K(c, 0), fine_A(c), om, VecSet{L1.e, L1.N}, L1.n,
                           z0, VecSet{c->d_T0, N0}, nullptr, v);
           },
-          5);
+          5, 0.02);
     }
     // 3. the single-launch threshold for the coarse levels, on whole V-cycles
     if (c->o.coarse_single_launch) {
@@ -1516,6 +1522,7 @@ int helm_autotune(helm_ctx* c, int B, const char* cache_path, helm_tune* out) {
   }
   t.coarse_max = c->coarse_max >= 0 ? c->coarse_max : (c->dim == 2 ? 48LL * 48 : 16LL * 16 * 16);
   t.up_mv_rows = mg_up_mv_rows(c->tune_mv);
+  t.up_mv_rhs_per_block = mg_up_mv_rhs_per_block(c->tune_mv);
   if (out) *out = t;
   HELM_GUARD_END("autotune")
 }

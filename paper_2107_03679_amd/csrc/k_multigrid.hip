@@ -270,104 +270,149 @@ __global__ __launch_bounds__(TX*(TY / PY)) void k_up_fused2(int nrhs, VecSet r, 
 // thread owns one column (lane) and every fourth row, so that the v2, z and
 // output stages are done by the thread that loaded the point's r, W and A
 // coefficient (kept in registers, no reloads), and no index needs a division.
-// The grid is (right-hand side, tile column, tile row), the plain order of
-// xcd_tile() without its divisions.  A wavefront's rows are uniform (its index
-// is read into a scalar register), so every row's base address is scalar and
-// all loads and stores of a lane share one 32-bit column offset.
-template <int TY>
-__global__ __launch_bounds__(256) void k_up_mv2w(VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,
-                                                 VecSet ec, int nc, VecSet z, VecSet w, const int* active) {
+// A block walks K right-hand sides of one tile: the coefficient rows (shared by
+// the batch) are loaded once, and the next right-hand side's r and coarse tile
+// are loaded while the current one is computed, so that the memory system has
+// work in every stage.  A wavefront's rows are uniform (its index is read into
+// a scalar register), so every row's base address is scalar and all loads and
+// stores of a lane share one 32-bit column offset.  Loads go to the nearest
+// in-grid point without predicates; values of points outside the grid are
+// never used (every use is guarded by the same condition).
+template <int TY, int K>
+__global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la,
+                                                 float omega, VecSet ec, int nc, VecSet z, VecSet w,
+                                                 const int* active) {
   constexpr int TX = 60, VX = 64, VY = TY + 4, ZY = TY + 2, RPI = 4, IV = VY / RPI;
   static_assert(VY % RPI == 0, "whole row groups");
-  constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3;
+  constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3, IE = (CX * CY + 255) / 256;
   __shared__ c32 sE[CY][CX];
   __shared__ c32 sV[VY][VX];
   __shared__ c32 sZ[ZY][VX];  // z of region point (lx, ly) at sZ[ly - 1][lx]
   const int n = lv.n;
-  const int b = blockIdx.x;
-  if (active && !active[b]) return;
-  const int fx0 = blockIdx.y * TX, fy0 = blockIdx.z * TY;
+  // workgroup order: every XCD (the hardware hands out ids round-robin over the 8) walks one
+  // contiguous stretch of "groups of K right-hand sides fastest, then tiles in raster order",
+  // so that all groups of a tile (sharing its coefficient rows) and its horizontal and
+  // vertical neighbours (sharing halo rows) meet in one L2, with equal work per XCD
+  const unsigned groups = (unsigned)(nrhs + K - 1) / K, tiles_x = (unsigned)(n + TX - 1) / TX;
+  const unsigned G = gridDim.x, q = G / HELM_XCDS, rem = G % HELM_XCDS, x = blockIdx.x % HELM_XCDS;
+  const unsigned l = x * q + (x < rem ? x : rem) + blockIdx.x / HELM_XCDS;
+  const unsigned t = l / groups, grp = l - t * groups;
+  const int b_end = min(nrhs, (int)(grp + 1) * K);
+  int b = (int)grp * K;
+  if (active)
+    while (b < b_end && !active[b]) ++b;
+  if (b >= b_end) return;
+  const int fx0 = (int)(t % tiles_x) * TX, fy0 = (int)(t / tiles_x) * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
-  const c32* eb = ec.p + (long long)b * ec.stride;
-  const c32* rb = r.p + (long long)b * r.stride;
-  const float sc = scale_of(rs, b);
-  const int lx = threadIdx.x & 63;
+  const int lx0 = threadIdx.x & 63;
   const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's first region row
-  const int gx = fx0 - 2 + lx;
-  const bool inx = gx >= 0 && gx < n;
-  const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);  // nearest in-grid column, bytes
-  const bool tcol = lx >= 2 && lx < TX + 2 && gx < n;  // a column of the tile
-  // every global load first, back to back: the coarse tile, r, W and (tile rows) the A
-  // coefficient.  Loads go to clamped in-grid addresses without lane predicates, so none
-  // of them waits for another; values of lanes outside the grid are never used (every
-  // later use is guarded by the same condition), and the scale of r is applied at its use.
-  constexpr int IE = (CX * CY + 255) / 256;
-  c32 evc[IE];
+  const unsigned ob0 = (unsigned)min(max(fx0 - 2 + lx0, 0), n - 1) * (unsigned)sizeof(c32);  // nearest in-grid column
+  unsigned eo[IE];  // coarse-tile items of this thread: nearest in-grid coarse point
 #pragma unroll
   for (int it = 0; it < IE; ++it) {
     const int idx = min((int)threadIdx.x + it * 256, CX * CY - 1);
     const int I = min(max(cxs + idx % CX, 0), nc - 1), J = min(max(cys + idx / CX, 0), nc - 1);
-    evc[it] = eb[(long long)J * nc + I];
+    eo[it] = (unsigned)(J * nc + I);
   }
-  c32 rv[IV], wv[IV], kv[IV];
+  auto load_e = [&](int bb, c32* ev_) {  // the coarse tile of right-hand side bb
+    const c32* eb = ec.p + (long long)bb * ec.stride;
 #pragma unroll
-  for (int it = 0; it < IV; ++it) {
+    for (int it = 0; it < IE; ++it) ev_[it] = eb[eo[it]];
+  };
+  auto load_r = [&](int bb, c32* rv_) {  // r of right-hand side bb on the region
+    const c32* rb = r.p + (long long)bb * r.stride;
+#pragma unroll
+    for (int it = 0; it < IV; ++it) {
+      const int gy = fy0 - 2 + r0 + RPI * it;
+      if (gy >= 0 && gy < n) rv_[it] = at_byte(rb + (long long)gy * n, ob0);
+    }
+  };
+  c32 rv[IV], evc[IE], wv[IV], kv[IV];
+  load_e(b, evc);
+  load_r(b, rv);
+#pragma unroll
+  for (int it = 0; it < IV; ++it) {  // the coefficient rows, once for all right-hand sides
     const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
     if (gy >= 0 && gy < n) {
       const long long row = (long long)gy * n;
-      rv[it] = at_byte(rb + row, ob);
-      wv[it] = at_byte(lv.wd + row, ob);
-      if (ly >= 2 && ly < TY + 2) kv[it] = at_byte(la.coef + row, ob);
+      wv[it] = at_byte(lv.wd + row, ob0);
+      if (ly >= 2 && ly < TY + 2) kv[it] = at_byte(la.coef + row, ob0);
     }
   }
+  while (true) {
+    // the lane's geometry, recomputed every pass from an opaque copy of its column (cheaper
+    // than the registers the hoisted addresses and predicates would hold across the loop)
+    int lx = lx0;
+    asm volatile("" : "+v"(lx));
+    const int gx = fx0 - 2 + lx;
+    const bool inx = gx >= 0 && gx < n;
+    const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);
+    const bool tcol = lx >= 2 && lx < TX + 2 && gx < n;
+    int bn = b + 1;  // the next iterating right-hand side of the block
+    if (active)
+      while (bn < b_end && !active[bn]) ++bn;
 #pragma unroll
-  for (int it = 0; it < IE; ++it) {
-    const int idx = threadIdx.x + it * 256;
-    const int I = cxs + idx % CX, J = cys + idx / CX;
-    const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
-    if (idx < CX * CY) sE[idx / CX][idx % CX] = ok ? evc[it] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < IV; ++it) {  // v2 = W r + P e (zero outside the grid)
-    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    c32 v2 = make_float2(0.f, 0.f);
-    if (inx && gy >= 0 && gy < n) {
-      rv[it] = cscale(rv[it], sc);
-      const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox1 = gx & 1, oy = gy & 1;
-      const c32 a = sE[J][I], bb = sE[J][I + ox1], c = sE[J + oy][I], d = sE[J + oy][I + ox1];
-      v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
+    for (int it = 0; it < IE; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int I = cxs + idx % CX, J = cys + idx / CX;
+      const bool ok = I >= 0 && I < nc && J >= 0 && J < nc;
+      if (idx < CX * CY) sE[idx / CX][idx % CX] = ok ? evc[it] : make_float2(0.f, 0.f);
     }
-    sV[ly][lx] = v2;
-  }
-  __syncthreads();
+    __syncthreads();
+    c32 rn[IV], en[IE];  // the next right-hand side's r and coarse tile, loaded during the stages below
+    if constexpr (K > 1)
+      if (bn < b_end) {
+        load_e(bn, en);
+        load_r(bn, rn);
+      }
+    const float sc = scale_of(rs, b);
 #pragma unroll
-  for (int it = 0; it < IV; ++it) {  // z on the tile and a one-point ring (zero outside the grid)
-    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    if (ly < 1 || ly > VY - 2) continue;
-    if (lx < 1 || lx > VX - 2) continue;
-    c32 zv = make_float2(0.f, 0.f);
-    if (inx && gy >= 0 && gy < n) {
-      const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
-      zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+    for (int it = 0; it < IV; ++it) {  // v2 = W r + P e (zero outside the grid)
+      const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+      c32 v2 = make_float2(0.f, 0.f);
+      if (inx && gy >= 0 && gy < n) {
+        rv[it] = cscale(rv[it], sc);
+        const int I = (gx >> 1) - cxs, J = (gy >> 1) - cys, ox1 = gx & 1, oy = gy & 1;
+        const c32 a = sE[J][I], bb = sE[J][I + ox1], c = sE[J + oy][I], d = sE[J + oy][I + ox1];
+        v2 = cadd(cmul(rv[it], wv[it]), cscale(cadd(cadd(a, bb), cadd(c, d)), 0.25f));
+      }
+      sV[ly][lx] = v2;
     }
-    sZ[ly - 1][lx] = zv;
-  }
-  __syncthreads();
-  c32* zb = z.p + (long long)b * z.stride;
-  c32* wb = w.p + (long long)b * w.stride;
+    __syncthreads();
 #pragma unroll
-  for (int it = 0; it < IV; ++it) {  // Z_j and W_{j+1} = A Z_j on the tile
-    const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
-    if (ly < 2 || ly >= TY + 2 || gy >= n) continue;
-    if (!tcol) continue;
-    const long long row = (long long)gy * n;
-    const c32 zc = sZ[ly - 1][lx];
-    const int ng = ghosts2(gx, gy, n);
-    const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
-    const c32 nb = cadd(cadd(sZ[ly - 1][lx - 1], sZ[ly - 1][lx + 1]), cadd(sZ[ly - 2][lx], sZ[ly][lx]));
-    at_byte(zb + row, ob) = zc;
-    at_byte(wb + row, ob) = csub(cmul(D, zc), nb);
+    for (int it = 0; it < IV; ++it) {  // z on the tile and a one-point ring (zero outside the grid)
+      const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+      if (ly < 1 || ly > VY - 2) continue;
+      if (lx < 1 || lx > VX - 2) continue;
+      c32 zv = make_float2(0.f, 0.f);
+      if (inx && gy >= 0 && gy < n) {
+        const c32 nb = cadd(cadd(sV[ly][lx - 1], sV[ly][lx + 1]), cadd(sV[ly - 1][lx], sV[ly + 1][lx]));
+        zv = cadd(cscale(sV[ly][lx], 1.0f - omega), cmul(wv[it], cadd(rv[it], nb)));
+      }
+      sZ[ly - 1][lx] = zv;
+    }
+    __syncthreads();
+    c32* zb = z.p + (long long)b * z.stride;
+    c32* wb = w.p + (long long)b * w.stride;
+#pragma unroll
+    for (int it = 0; it < IV; ++it) {  // Z_j and W_{j+1} = A Z_j on the tile
+      const int ly = r0 + RPI * it, gy = fy0 - 2 + ly;
+      if (ly < 2 || ly >= TY + 2 || gy >= n) continue;
+      if (!tcol) continue;
+      const long long row = (long long)gy * n;
+      const c32 zc = sZ[ly - 1][lx];
+      const int ng = ghosts2(gx, gy, n);
+      const c32 D = make_float2(4.0f - kv[it].x - ng * la.ghost.x, -kv[it].y - ng * la.ghost.y);
+      const c32 nb = cadd(cadd(sZ[ly - 1][lx - 1], sZ[ly - 1][lx + 1]), cadd(sZ[ly - 2][lx], sZ[ly][lx]));
+      at_byte(zb + row, ob) = zc;
+      at_byte(wb + row, ob) = csub(cmul(D, zc), nb);
+    }
+    if (K == 1 || bn >= b_end) break;
+    b = bn;
+#pragma unroll
+    for (int it = 0; it < IV; ++it) rv[it] = rn[it];
+#pragma unroll
+    for (int it = 0; it < IE; ++it) evc[it] = en[it];
   }
 }
 
@@ -1294,8 +1339,12 @@ struct UpTile {
 constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}, {30, 16}};
 constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}, {62, 30, 0}};
 constexpr int kDownCol = 5, kDownCol16 = 6, kUpCol = 5, kUpCol30 = 6;
-// row heights of the fused finest up-leg + basis matvec (k_up_mv2w), one autotuner choice
-constexpr int kUpMvRows[] = {12, 16, 20, 28};
+// launch shapes of the fused finest up-leg + basis matvec (k_up_mv2w), one autotuner
+// choice: tile height and right-hand sides per block
+struct UpMvShape {
+  int rows, k;
+};
+constexpr UpMvShape kUpMv[] = {{16, 4}, {12, 1}, {20, 1}, {28, 1}, {12, 2}, {12, 4}, {12, 6}, {20, 2}, {20, 4}};
 
 template <int TCX, int TCY>
 void down_tile(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet rc, int nc,
@@ -1334,26 +1383,30 @@ void launch_up_fused3(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
   hipLaunchKernelGGL(k_up_march3c, dim3(B * tiles), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active, acc);
 }
 
-template <int TY>
+template <int TY, int K>
 void up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec, int nc,
             VecSet z, VecSet w, const int* active) {
   constexpr int TX = 60;
   const int n = lv.n;
-  const dim3 grid(B, (n + TX - 1) / TX, (n + TY - 1) / TY);
-  hipLaunchKernelGGL((k_up_mv2w<TY>), grid, dim3(256), 0, s, r, rs, lv, la, omega, ec, nc, z, w, active);
+  const int blocks = (B + K - 1) / K * ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
+  hipLaunchKernelGGL((k_up_mv2w<TY, K>), dim3(blocks), dim3(256), 0, s, B, r, rs, lv, la, omega, ec, nc, z, w, active);
 }
 
-int mg_up_mv_variants() { return (int)(sizeof(kUpMvRows) / sizeof(kUpMvRows[0])); }
-int mg_up_mv_rows(int cfg) { return kUpMvRows[cfg]; }
+int mg_up_mv_variants() { return (int)(sizeof(kUpMv) / sizeof(kUpMv[0])); }
+int mg_up_mv_rows(int cfg) { return kUpMv[cfg].rows; }
+int mg_up_mv_rhs_per_block(int cfg) { return kUpMv[cfg].k; }
 
 void launch_up_mv2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega, VecSet ec,
                    int nc, VecSet z, VecSet w, const int* active, int cfg) {
-  switch (cfg) {
-    case 1: up_mv2<16>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
-    case 2: up_mv2<20>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
-    case 3: up_mv2<28>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
-    default: up_mv2<12>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active); break;
+#define HELM_UP_MV(TY_, K_)                                                     \
+  if (kUpMv[cfg].rows == TY_ && kUpMv[cfg].k == K_) {                           \
+    up_mv2<TY_, K_>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active);          \
+    return;                                                                     \
   }
+  HELM_UP_MV(12, 1) HELM_UP_MV(20, 1) HELM_UP_MV(28, 1) HELM_UP_MV(12, 2) HELM_UP_MV(12, 4)
+  HELM_UP_MV(12, 6) HELM_UP_MV(20, 2) HELM_UP_MV(20, 4)
+#undef HELM_UP_MV
+  up_mv2<16, 4>(s, B, r, rs, lv, la, omega, ec, nc, z, w, active);
 }
 
 void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv, LevelArgs la, float omega,

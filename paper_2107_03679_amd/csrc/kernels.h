@@ -56,9 +56,11 @@ void launch_step_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs l
                         VecSet ec, int nc, VecSet z, VecSet w, VecSet rc, const int* active);
 int mg_down_variants();
 int mg_up_variants();
-// row heights of the fused finest up-leg + basis matvec (autotuner choices)
+// launch shapes of the fused finest up-leg + basis matvec (autotuner choices): tile
+// height and right-hand sides per block
 int mg_up_mv_variants();
 int mg_up_mv_rows(int cfg);
+int mg_up_mv_rhs_per_block(int cfg);
 void mg_down_shape(int cfg, int* tcx, int* tcy);
 void mg_up_shape(int cfg, int* tx, int* ty, int* py);
 void launch_jacobi_zero(hipStream_t s, int dim, int B, VecSet r, ScaleSet rs, LevelArgs lv, float omega, VecSet v,

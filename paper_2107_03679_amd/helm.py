@@ -58,6 +58,7 @@ class HelmTune(ctypes.Structure):
         ("down", (ctypes.c_int * 2) * 12), ("up", (ctypes.c_int * 3) * 12),
         ("coarse_max", ctypes.c_longlong), ("vcycle_ms", ctypes.c_double), ("vcycle_default_ms", ctypes.c_double),
         ("up_mv_rows", ctypes.c_int),
+        ("up_mv_rhs_per_block", ctypes.c_int),
     ]
 
 
@@ -589,6 +590,7 @@ class Context:
             "down_tiles": [tuple(t.down[l]) for l in range(L - 1)],
             "up_tiles": [tuple(t.up[l]) for l in range(L - 1)],
             "coarse_single_launch_max_points": int(t.coarse_max), "up_mv_rows": int(t.up_mv_rows),
+            "up_mv_rhs_per_block": int(t.up_mv_rhs_per_block),
             "vcycle_ms": t.vcycle_ms, "vcycle_default_ms": t.vcycle_default_ms,
         }
 

@@ -30,7 +30,7 @@ import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# profiling scope name -> HIP kernel (the finest-level launches are the ones with the largest grid)
+# profiling scope name -> HIP kernel (the launch shape of the finest level takes the most time)
 HIP_KERNEL = {
     "up_mv_l0": ("k_up_mv2w", "k_up_mv2"), "up_fused_l0": ("k_up_col", "k_up_fused2"),
     "down_fused_l0": ("k_down_col", "k_down_fused2"), "sstep_gram": ("k_sstep_gram",),
@@ -79,7 +79,8 @@ def main(argv=None) -> None:
     trace = collections.defaultdict(list)
     with open(os.path.join(g, "prof", "run_kernel_trace.csv")) as fh:
         for r in csv.DictReader(fh):
-            trace[(kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]))].append(
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])  # threads, as Grid_Size
+            trace[(kernel_name(r["Kernel_Name"]), grid)].append(
                 int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     pmc = {}
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -103,7 +104,7 @@ def main(argv=None) -> None:
 
     hip = HIP_KERNEL[roof["kernel"]]
     cands = [k for k in trace if k[0].split("<")[0].replace("void ", "") in hip]
-    dom = max(cands, key=lambda k: (k[1], sum(trace[k])))
+    dom = max(cands, key=lambda k: sum(trace[k]))  # the launch shape of the solve (the tuner's trials are few)
     trace_cmd, pmc_cmds = commands(args.workload)
     L = [f"# Kernel profile: {args.workload}\n",
          "Commands, run on an MI355X (`R` = the repository root, `OUT` = an output folder, the same for all "

@@ -99,8 +99,9 @@ def test_every_tile_variant_is_bit_identical(case, tmp_path, variant, cycle):
 
 
 def test_up_mv_heights_are_bit_identical(case, tmp_path):
-    """Every tile height of the s-step form's fused finest up-leg + basis matvec, forced through the
-    cache: the same iterates (bit for bit) and cycle counts as the default height."""
+    """Every launch shape (tile height, right-hand sides per workgroup) of the s-step form's fused
+    finest up-leg + basis matvec, forced through the cache: the same iterates (bit for bit) and cycle
+    counts as the default shape."""
     nmap, prob, r, ref = case
     ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B, restart=6)
     first = tmp_path / "first.jsonl"
@@ -109,17 +110,18 @@ def test_up_mv_heights_are_bit_identical(case, tmp_path):
     rhs = ctx.plane_wave_rhs(synth.directions_2d(B))
     e = json.loads(line)
     xs = []
-    for mv in range(4):
+    for mv in range(9):
         forced = tmp_path / f"mv{mv}.jsonl"
         forced.write_text(_edit(line, LEVELS, e["down"][0], e["up"][0], e["coarse_max"], mv))
         t = ctx.autotune(B, cache=str(forced))
-        assert t["from_cache"] and t["up_mv_rows"] == (12, 16, 20, 28)[mv]
+        assert t["from_cache"] and t["up_mv_rows"] == (16, 12, 20, 28, 12, 12, 12, 20, 20)[mv]
+        assert t["up_mv_rhs_per_block"] == (4, 1, 1, 1, 2, 4, 6, 2, 4)[mv]
         x, st = ctx.solve(rhs)
         assert st.converged
         xs.append((x, st.iters))
     for x, it in xs[1:]:
         assert bool((x == xs[0][0]).all()) and np.array_equal(it, xs[0][1])
-    print(f"[autotune] up-mv height chosen: {t0['up_mv_rows']} rows", flush=True)
+    print(f"[autotune] up-mv shape chosen: {t0['up_mv_rows']} rows, {t0['up_mv_rhs_per_block']} per block", flush=True)
     ctx.close()
 
 

@@ -24,8 +24,12 @@ def test_summary_calibrates_counters_and_writes_record(tmp_path):
     os.makedirs(g)
     (g / "bench.json").write_text(json.dumps(bench) + "\n")
     name = "void (anonymous namespace)::k_up_mv2<64, 16>(int, VecSet)"
-    _csv(str(g / "prof" / "run_kernel_trace.csv"), ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"],
-         [[name, 2048, 0, 10000], [name, 2048, 20000, 30000], [name, 256, 0, 5000]])
+    # the solve's launch shape (a 3D grid of 2048 threads) takes the most time; a tuner trial with a
+    # larger grid and a smaller shape run less
+    _csv(str(g / "prof" / "run_kernel_trace.csv"),
+         ["Kernel_Name", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Start_Timestamp", "End_Timestamp"],
+         [[name, 512, 2, 2, 0, 10000], [name, 512, 2, 2, 20000, 30000], [name, 256, 1, 1, 0, 5000],
+          [name, 4096, 1, 1, 0, 12000]])
     # the probe copies 1 MiB each way; the counters read half the fetched bytes, all the written ones
     copy = "__amd_rocclr_copyBuffer(char const*, char*)"
     rows = {"FETCH_SIZE": [[copy, 4096, 512.0]] * 4 + [[copy, 4096, 100.0], [name, 2048, 300.0], [name, 2048, 500.0]],
