@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void k_down_col(VecSet r, ScaleSet rs, LevelAr
 // With RES the right-hand side is r - K e, formed from e on the region and a
 // one-point ring, and the leg writes e + z (as k_up_fused2).
 template <int TY, bool RES>
-__global__ __launch_bounds__(256) void k_up_col(VecSet r, ScaleSet rs, LevelArgs lv, float omega,
+__global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs, LevelArgs lv, float omega,
                                                 VecSet ec, int nc, VecSet z, const int* active, VecSet ev) {
   constexpr int TX = 62, VY = TY + 2, RPI = 4, IV = VY / RPI;
   static_assert(VY % RPI == 0 && TY % 2 == 0, "whole row groups, even tile origin");
@@ -539,9 +539,17 @@ __global__ __launch_bounds__(256) void k_up_col(VecSet r, ScaleSet rs, LevelArgs
   __shared__ c32 sV[VY][64];
   __shared__ c32 sF[FY][FX];
   const int n = lv.n;
-  const int b = blockIdx.x;  // grid (right-hand side, tile column, tile row)
+  // each XCD walks one contiguous stretch of "right-hand sides fastest, then tiles in raster
+  // order" (the order of k_up_mv2w with one right-hand side per workgroup), so that the
+  // tiles of one field that share halo rows, and the workgroups that share a coefficient
+  // tile, meet in one L2
+  const unsigned tiles_x = (unsigned)(n + TX - 1) / TX;
+  const unsigned G = gridDim.x, q = G / HELM_XCDS, rem = G % HELM_XCDS, x = blockIdx.x % HELM_XCDS;
+  const unsigned l = x * q + (x < rem ? x : rem) + blockIdx.x / HELM_XCDS;
+  const unsigned t = l / (unsigned)nrhs;
+  const int b = (int)(l - t * (unsigned)nrhs);
   if (active && !active[b]) return;
-  const int fx0 = blockIdx.y * TX, fy0 = blockIdx.z * TY;
+  const int fx0 = (int)(t % tiles_x) * TX, fy0 = (int)(t / tiles_x) * TY;
   const int cxs = fx0 / 2 - 1, cys = fy0 / 2 - 1;
   const c32* eb = ec.p + (long long)b * ec.stride;
   const c32* rb = r.p + (long long)b * r.stride;
@@ -1339,6 +1347,7 @@ struct UpTile {
 constexpr DownTile kDown[] = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {30, 8}, {30, 16}};
 constexpr UpTile kUp[] = {{64, 16, 4}, {32, 16, 2}, {64, 8, 2}, {32, 32, 4}, {64, 32, 8}, {62, 14, 0}, {62, 30, 0}};
 constexpr int kDownCol = 5, kDownCol16 = 6, kUpCol = 5, kUpCol30 = 6;
+
 // launch shapes of the fused finest up-leg + basis matvec (k_up_mv2w), one autotuner
 // choice: tile height and right-hand sides per block
 struct UpMvShape {
@@ -1462,20 +1471,24 @@ void launch_up_fused2(hipStream_t s, int B, VecSet r, ScaleSet rs, LevelArgs lv,
                       VecSet z, const int* active, int cfg, VecSet e) {
   if (cfg == kUpCol) {
     constexpr int TX = 62, TY = 14;
-    const dim3 grid(B, (lv.n + TX - 1) / TX, (lv.n + TY - 1) / TY);
+    const int blocks = B * ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
     if (e.p)
-      hipLaunchKernelGGL((k_up_col<TY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
+      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(blocks), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active,
+                         e);
     else
-      hipLaunchKernelGGL((k_up_col<TY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
+      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(blocks), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active,
+                         e);
     return;
   }
   if (cfg == kUpCol30) {  // taller column tile
     constexpr int TX = 62, TY = 30;
-    const dim3 grid(B, (lv.n + TX - 1) / TX, (lv.n + TY - 1) / TY);
+    const int blocks = B * ((lv.n + TX - 1) / TX) * ((lv.n + TY - 1) / TY);
     if (e.p)
-      hipLaunchKernelGGL((k_up_col<TY, true>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
+      hipLaunchKernelGGL((k_up_col<TY, true>), dim3(blocks), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active,
+                         e);
     else
-      hipLaunchKernelGGL((k_up_col<TY, false>), grid, dim3(256), 0, s, r, rs, lv, omega, ec, nc, z, active, e);
+      hipLaunchKernelGGL((k_up_col<TY, false>), dim3(blocks), dim3(256), 0, s, B, r, rs, lv, omega, ec, nc, z, active,
+                         e);
     return;
   }
   switch (cfg) {
