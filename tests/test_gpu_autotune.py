@@ -125,6 +125,39 @@ def test_up_mv_heights_are_bit_identical(case, tmp_path):
     ctx.close()
 
 
+def test_up_mv_shapes_with_idle_right_hand_sides(tmp_path):
+    """Seven right-hand sides (groups of four and three in the shapes that walk four per
+    workgroup), the second and the fifth zero: inactive from the start and skipped inside
+    their groups.  Every launch shape of the fused finest up-leg gives the same iterates bit
+    for bit and the same cycle counts, and the zero right-hand sides keep a zero solution."""
+    nb = 7
+    print(f"\n[autotune up-mv shapes, B={nb} with two zero right-hand sides]", flush=True)
+    nmap = medium(N, seed=3)
+    ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=nb, restart=6)
+    first = tmp_path / "first.jsonl"
+    ctx.autotune(nb, cache=str(first))
+    line = first.read_text().splitlines()[0]
+    e = json.loads(line)
+    rhs = ctx.plane_wave_rhs(synth.directions_2d(nb))
+    rhs[1].zero_()
+    rhs[4].zero_()
+    xs = []
+    for mv in range(9):
+        forced = tmp_path / f"mv{mv}.jsonl"
+        forced.write_text(_edit(line, LEVELS, e["down"][0], e["up"][0], e["coarse_max"], mv))
+        t = ctx.autotune(nb, cache=str(forced))
+        assert t["from_cache"]
+        x, st = ctx.solve(rhs)
+        assert st.converged
+        xs.append((x.clone(), np.array(st.iters)))
+    x0, it0 = xs[0]
+    assert bool((x0[1] == 0).all()) and bool((x0[4] == 0).all())
+    assert it0[1] == 0 and it0[4] == 0 and np.all(np.delete(it0, [1, 4]) > 0)
+    for x, it in xs[1:]:
+        assert bool((x == x0).all()) and np.array_equal(it, it0)
+    ctx.close()
+
+
 def test_coarse_threshold_variants_match_oracle(case, tmp_path):
     nmap, prob, r, ref = case
     ctx = gpu_context(nmap, w=W, levels=LEVELS, max_batch=B)
