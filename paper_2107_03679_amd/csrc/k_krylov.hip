@@ -654,7 +654,7 @@ __device__ __forceinline__ void gram_accumulate(double2* acc, const c32 (*buf)[G
 template <int M>
 __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, LevelArgs fine, double2* part) {
   constexpr int NV = M + 1, NE = NV * (NV + 1) / 2, NU = (NE + NWAVE - 1) / NWAVE;
-  constexpr int ITEMS = (NV * GP + NT - 1) / NT, STEPS = CH / GP;
+  constexpr int STEPS = CH / GP;
   static_assert(CH % GP == 0 && GP % HELM_WAVE == 0, "staging shape");
   __shared__ c32 buf[2][NV][GP];
   const TileId id = xcd_tile(blockIdx.x, nrhs, k.nblk, HELM_RHS_GROUP);
@@ -664,37 +664,71 @@ __global__ __launch_bounds__(NT) void k_sstep_gram(int nrhs, KrylovArgs k, Level
   const long long p0 = (long long)blk * CH;
   const c32* z = k.Z + zidx(k, b, M - 1);
   const c32* vb = k.V + vidx(k, b, 0);
-  // item it of this thread: vector v = idx / GP (uniform per wave), point q = idx % GP
-  auto load = [&](int step, c32* out) {
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      const int v = idx / GP, q = idx % GP;
-      const long long p = p0 + (long long)step * GP + q;
-      c32 w = make_float2(0.f, 0.f);
-      if (v < M) {
-        if (p < k.N) w = vb[(long long)v * k.N + p];
-        if (v == 0) w = cscale(w, s0);
-      } else if (v == M && p < k.N) {
-        const Coord c = coord_of32((unsigned)p, (unsigned)fine.n, k.dim);
-        w = stencil_point(z, p, c, fine.n, k.dim, diag_at(fine, p, ghosts_of(c, fine.n, k.dim), k.dim));
-      }
-      out[it] = w;
-    }
+  // Item v of this thread is point q = threadIdx.x of basis vector v (NT == GP).  The
+  // prefetch of the next step only loads: the vectors at the nearest valid point and, for
+  // the last vector, Z's stencil values and the coefficient; the stencil, the zeros past N
+  // and the scale of W_0 are applied when the step is stored to LDS, after the current
+  // step's accumulation, so that no arithmetic waits on the loads in flight.
+  static_assert(NT == GP, "one point per thread and vector");
+  constexpr int NS = 7;  // stencil values of the last vector: centre, x-, x+, y-, y+, z-, z+
+  struct Pre {
+    c32 w[M];
+    c32 st[NS];
+    c32 coef;
+    long long p;
   };
-  auto store = [&](int slot, const c32* in) {
+  const int dim = k.dim, nf = fine.n;
+  const long long nf2 = (long long)nf * nf;
+  auto load = [&](int step, Pre& o) {
+    const long long p = p0 + (long long)step * GP + threadIdx.x;
+    const long long pc = p < k.N ? p : k.N - 1;  // nearest valid point
+    o.p = p;
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < NV * GP) buf[slot][idx / GP][idx % GP] = in[it];
+    for (int v = 0; v < M; ++v) o.w[v] = vb[(long long)v * k.N + pc];
+    const Coord c = coord_of32((unsigned)pc, (unsigned)nf, dim);
+    const int xm = c.x > 0, xp = c.x < nf - 1, ym = c.y > 0, yp = c.y < nf - 1;
+    o.st[0] = z[pc];
+    o.st[1] = z[pc - xm];
+    o.st[2] = z[pc + xp];
+    o.st[3] = z[pc - (long long)ym * nf];
+    o.st[4] = z[pc + (long long)yp * nf];
+    if (dim == 3) {
+      const int zm = c.z > 0, zp = c.z < nf - 1;
+      o.st[5] = z[pc - zm * nf2];
+      o.st[6] = z[pc + zp * nf2];
     }
+    o.coef = fine.coef[pc];
+  };
+  auto store = [&](int slot, const Pre& o) {
+    const bool ok = o.p < k.N;
+    const long long pc = ok ? o.p : k.N - 1;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      c32 w = ok ? o.w[v] : make_float2(0.f, 0.f);
+      if (v == 0) w = cscale(w, s0);
+      buf[slot][v][threadIdx.x] = w;
+    }
+    // the last basis vector A Z_{M-1} at the point: the arithmetic of stencil_point and
+    // diag_at on the values loaded above
+    const Coord c = coord_of32((unsigned)pc, (unsigned)nf, dim);
+    const int ng = ghosts_of(c, nf, dim);
+    const c32 D = make_float2(2.0f * dim - o.coef.x - ng * fine.ghost.x, -o.coef.y - ng * fine.ghost.y);
+    const int xm = c.x > 0, xp = c.x < nf - 1, ym = c.y > 0, yp = c.y < nf - 1;
+    const c32 a = o.st[1], bb = o.st[2], cc = o.st[3], d = o.st[4];
+    c32 nb = make_float2(xm * a.x + xp * bb.x + ym * cc.x + yp * d.x, xm * a.y + xp * bb.y + ym * cc.y + yp * d.y);
+    if (dim == 3) {
+      const int zm = c.z > 0, zp = c.z < nf - 1;
+      nb.x += zm * o.st[5].x + zp * o.st[6].x;
+      nb.y += zm * o.st[5].y + zp * o.st[6].y;
+    }
+    buf[slot][M][threadIdx.x] = ok ? csub(cmul(D, o.st[0]), nb) : make_float2(0.f, 0.f);
   };
   double2 acc[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) acc[u] = make_double2(0.0, 0.0);
   const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
   const int steps = (int)min((long long)STEPS, (k.N - p0 + GP - 1) / GP);
-  c32 pre[ITEMS];
+  Pre pre;
   load(0, pre);
   for (int st = 0; st < steps; ++st) {
     store(st & 1, pre);
