@@ -388,13 +388,33 @@ __global__ __launch_bounds__(NT) void k_x_update_residual2(int nrhs, KrylovArgs 
     dl[it] = tp ? a.d_lo[p] : make_float2(0.f, 0.f);
     d[it] = make_float2(0.f, 0.f);
   }
-  for (int i = 0; i < kk; ++i) {  // the sum in the order of i, as k_x_update
-    const c32 yi = k.y[b * k.m + i];
-    const c32* zi = k.Z + zidx(k, b, i);
+  // the sum in the order of i, as k_x_update; the rows of XG basis vectors are loaded
+  // together (nearest in-grid column, no lane predicate: d of a lane outside the grid is
+  // never used), then added in order
+  constexpr int XG = 4;
+  const unsigned ob = (unsigned)min(max(gx, 0), n - 1) * (unsigned)sizeof(c32);
+  const int r0u = __builtin_amdgcn_readfirstlane(r0);  // uniform rows: scalar row bases
+  for (int i0 = 0; i0 < kk; i0 += XG) {
+    c32 zv[XG][IV];
 #pragma unroll
-    for (int it = 0; it < IV; ++it) {
-      const int gy = fy0 - 1 + r0 + RPI * it;
-      if (inx && gy >= 0 && gy < n) d[it] = cfma(yi, zi[(long long)gy * n + gx], d[it]);
+    for (int u = 0; u < XG; ++u) {
+      if (i0 + u >= kk) break;
+      const c32* zi = k.Z + zidx(k, b, i0 + u);
+#pragma unroll
+      for (int it = 0; it < IV; ++it) {
+        const int gy = fy0 - 1 + r0u + RPI * it;
+        if (gy >= 0 && gy < n) zv[u][it] = at_byte(zi + (long long)gy * n, ob);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XG; ++u) {
+      if (i0 + u >= kk) break;
+      const c32 yi = k.y[b * k.m + i0 + u];
+#pragma unroll
+      for (int it = 0; it < IV; ++it) {
+        const int gy = fy0 - 1 + r0u + RPI * it;
+        if (gy >= 0 && gy < n) d[it] = cfma(yi, zv[u][it], d[it]);
+      }
     }
   }
 #pragma unroll
