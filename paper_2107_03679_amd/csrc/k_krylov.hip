@@ -23,7 +23,7 @@ constexpr int CH = NT * PPT;  // points per block
 constexpr int NWAVE = NT / HELM_WAVE;
 constexpr int MAXM = 64;
 constexpr int SSTEP_MAXM = 12;  // longest s-step cycle (the Gram matrix lives in registers)
-constexpr int VCH = 4;        // basis vectors streamed together
+constexpr int VCH = 4;        // basis vectors streamed together by k_x_update
 
 __device__ __forceinline__ long long vidx(const KrylovArgs& k, int b, int i) {
   return ((long long)b * (k.m + 1) + i) * k.N;
@@ -65,31 +65,29 @@ __global__ __launch_bounds__(NT) void k_arnoldi_dots(int nrhs, KrylovArgs k, int
     }
   }
   const int lane = threadIdx.x % HELM_WAVE, wave = threadIdx.x / HELM_WAVE;
-  // basis vectors in chunks of VCH: VCH * PPT independent loads in flight per thread
-  for (int i0 = 0; i0 <= j; i0 += VCH) {
-    c32 acc[VCH];
+  // one basis vector ahead: the next vector's points (from the nearest valid point, so that
+  // no load waits behind the guard of its product) are in flight while the current one's
+  // dot product is formed
+  auto ldv = [&](int i, c32* o) {
+    const c32* vi = k.V + vidx(k, b, i);
 #pragma unroll
-    for (int q = 0; q < VCH; ++q) {
-      acc[q] = make_float2(0.f, 0.f);
-      if (i0 + q <= j) {
-        const c32* vi = k.V + vidx(k, b, i0 + q);
+    for (int t = 0; t < PPT; ++t) o[t] = vi[min(p0 + (long long)t * NT, k.N - 1)];
+  };
+  c32 vc[PPT], vn[PPT];
+  ldv(0, vc);
+  for (int i = 0; i <= j; ++i) {
+    if (i + 1 <= j) ldv(i + 1, vn);
+    c32 acc = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-          const long long p = p0 + (long long)t * NT;
-          if (p < k.N) acc[q] = cadd(acc[q], cconjmul(vi[p], w[t]));
-        }
-      }
+    for (int t = 0; t < PPT; ++t) {
+      const long long p = p0 + (long long)t * NT;
+      if (p < k.N) acc = cadd(acc, cconjmul(vc[t], w[t]));
     }
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) red[wave][i] = acc;
 #pragma unroll
-    for (int q = 0; q < VCH; ++q) {
-      acc[q].x = wave_sum(acc[q].x);
-      acc[q].y = wave_sum(acc[q].y);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < VCH; ++q)
-        if (i0 + q <= j) red[wave][i0 + q] = acc[q];
-    }
+    for (int t = 0; t < PPT; ++t) vc[t] = vn[t];
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += NT) {
@@ -142,20 +140,24 @@ __global__ __launch_bounds__(NT) void k_arnoldi_update(KrylovArgs k, int j) {
     const long long p = p0 + (long long)t * NT;
     w[t] = p < k.N ? wv[p] : make_float2(0.f, 0.f);
   }
-  for (int i0 = 0; i0 <= j; i0 += VCH) {
+  // one basis vector ahead: the next vector's points (from the nearest valid point, so that
+  // no load waits behind a guard) are in flight while the current one is subtracted, in the
+  // order of i; w past N is never stored or summed
+  auto ldv = [&](int i, c32* o) {
+    const c32* vi = k.V + vidx(k, b, i);
 #pragma unroll
-    for (int q = 0; q < VCH; ++q) {
-      if (i0 + q <= j) {
-        const c32 ci = k.coef[b * (k.m + 1) + i0 + q];
-        const c32 nci = make_float2(-ci.x, -ci.y);
-        const c32* vi = k.V + vidx(k, b, i0 + q);
+    for (int t = 0; t < PPT; ++t) o[t] = vi[min(p0 + (long long)t * NT, k.N - 1)];
+  };
+  c32 vc[PPT], vn[PPT];
+  ldv(0, vc);
+  for (int i = 0; i <= j; ++i) {
+    if (i + 1 <= j) ldv(i + 1, vn);
+    const c32 ci = k.coef[b * (k.m + 1) + i];
+    const c32 nci = make_float2(-ci.x, -ci.y);
 #pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-          const long long p = p0 + (long long)t * NT;
-          if (p < k.N) w[t] = cfma(nci, vi[p], w[t]);
-        }
-      }
-    }
+    for (int t = 0; t < PPT; ++t) w[t] = cfma(nci, vc[t], w[t]);
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) vc[t] = vn[t];
   }
   float nrm = 0.f;
 #pragma unroll
