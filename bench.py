@@ -67,7 +67,8 @@ def parse():
                    help="instead of the benchmark line: solves/s and cycles per solve over the shift, the cycle "
                         "type, the smoothing steps and factor, and the level count (one JSON line per setting)")
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
-    p.add_argument("--learned-media", type=int, default=4, help="training media for the network")
+    p.add_argument("--learned-media", type=int, default=12,
+                   help="training media for the network (12: about 20k pairs at 512^2 x 60)")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
     p.add_argument("--learned-accept", type=float, default=None,
                    help="acceptance threshold: the network's output is used where ||v - A net(v)|| <= t ||v||; "
