@@ -42,6 +42,16 @@ __host__ __device__ __forceinline__ TileId xcd_tile(unsigned id, unsigned B, uns
   o.t = (int)(rem / gs);
   return o;
 }
+// The order of the up-legs (k_up_mv2w, k_up_col): workgroup id -> position l in one
+// logical order such that every XCD walks one contiguous stretch of it, of equal length
+// (+-1).  With "right-hand sides (or groups of them) fastest, then tiles in raster order"
+// the workgroups sharing a coefficient tile and the neighbouring tiles sharing halo rows
+// meet in one L2; for these two kernels it measured faster than the plain order.
+// Bijective on [0, G).
+__host__ __device__ __forceinline__ unsigned xcd_stretch(unsigned id, unsigned G) {
+  const unsigned q = G / HELM_XCDS, r = G % HELM_XCDS, x = id % HELM_XCDS;
+  return x * q + (x < r ? x : r) + id / HELM_XCDS;
+}
 // right-hand sides per group in xcd_tile() for the field kernels (0: the plain order)
 #ifndef HELM_RHS_GROUP
 #define HELM_RHS_GROUP 0u

@@ -289,13 +289,10 @@ __global__ __launch_bounds__(256) void k_up_mv2w(int nrhs, VecSet r, ScaleSet rs
   __shared__ c32 sV[VY][VX];
   __shared__ c32 sZ[ZY][VX];  // z of region point (lx, ly) at sZ[ly - 1][lx]
   const int n = lv.n;
-  // workgroup order: every XCD (the hardware hands out ids round-robin over the 8) walks one
-  // contiguous stretch of "groups of K right-hand sides fastest, then tiles in raster order",
-  // so that all groups of a tile (sharing its coefficient rows) and its horizontal and
-  // vertical neighbours (sharing halo rows) meet in one L2, with equal work per XCD
+  // workgroup order (xcd_stretch): "groups of K right-hand sides fastest, then tiles in
+  // raster order", one contiguous stretch per XCD
   const unsigned groups = (unsigned)(nrhs + K - 1) / K, tiles_x = (unsigned)(n + TX - 1) / TX;
-  const unsigned G = gridDim.x, q = G / HELM_XCDS, rem = G % HELM_XCDS, x = blockIdx.x % HELM_XCDS;
-  const unsigned l = x * q + (x < rem ? x : rem) + blockIdx.x / HELM_XCDS;
+  const unsigned l = xcd_stretch(blockIdx.x, gridDim.x);
   const unsigned t = l / groups, grp = l - t * groups;
   const int b_end = min(nrhs, (int)(grp + 1) * K);
   int b = (int)grp * K;
@@ -539,13 +536,10 @@ __global__ __launch_bounds__(256) void k_up_col(int nrhs, VecSet r, ScaleSet rs,
   __shared__ c32 sV[VY][64];
   __shared__ c32 sF[FY][FX];
   const int n = lv.n;
-  // each XCD walks one contiguous stretch of "right-hand sides fastest, then tiles in raster
-  // order" (the order of k_up_mv2w with one right-hand side per workgroup), so that the
-  // tiles of one field that share halo rows, and the workgroups that share a coefficient
-  // tile, meet in one L2
+  // workgroup order (xcd_stretch): "right-hand sides fastest, then tiles in raster order",
+  // one contiguous stretch per XCD
   const unsigned tiles_x = (unsigned)(n + TX - 1) / TX;
-  const unsigned G = gridDim.x, q = G / HELM_XCDS, rem = G % HELM_XCDS, x = blockIdx.x % HELM_XCDS;
-  const unsigned l = x * q + (x < rem ? x : rem) + blockIdx.x / HELM_XCDS;
+  const unsigned l = xcd_stretch(blockIdx.x, gridDim.x);
   const unsigned t = l / (unsigned)nrhs;
   const int b = (int)(l - t * (unsigned)nrhs);
   if (active && !active[b]) return;

@@ -91,3 +91,23 @@ def test_null_arguments_return_einval_without_a_device():
     assert lib.helm_data_residual(None, 1, 1, None, None, None, None, None) == -1
     assert lib.helm_examples_rms(None, None, 1, None) == -1
     assert lib.helm_net_residual_ratio(None, 1, 8, 8, None, 1.0, 1.0, None) == -1
+
+
+def test_workgroup_order_maps_are_bijections(tmp_path):
+    """The XCD-aware workgroup orders of the kernels (dev_common.h: xcd_stretch, xcd_tile) visit
+    every (right-hand side, tile) exactly once: a host program built from the same header."""
+    import shutil
+    import subprocess
+
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc) and shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "xcd_order_check")
+    cmd = [hipcc if os.path.exists(hipcc) else "hipcc", "-O1", "-std=c++17", "--offload-arch=gfx950",
+           "-I", os.path.join(root, "include"), "-I", os.path.join(root, "paper_2107_03679_amd", "csrc"),
+           os.path.join(root, "tests", "xcd_order_check.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
