@@ -53,7 +53,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="length of each bounded oracle run of the CPU baseline (one thread; one per core)")
-    p.add_argument("--no-c1", action="store_true", help="skip the disk128 CPU timing (set-up and solve, median of 5)")
+    p.add_argument("--no-disk128-timing", action="store_true",
+                   help="skip the disk128 CPU timing (set-up and solve, median of 5)")
     p.add_argument("--kappa-im", type=float, default=None,
                    help="imaginary part of the shift kappa (real part 1); default 0.4 for 2D media of contrast up to "
                         "0.1 (measured best with --omega 0.9 at 512^2 x 60), else 0.5 (strongly scattering 2D media "
@@ -222,7 +223,7 @@ def cpu_baseline(rates, iters_per_solve, restart):
     }
 
 
-def cpu_c1_protocol(reps=5):
+def cpu_disk128_timing(reps=5):
     """The small CPU configuration (disk128: 128^2 interior, 20-cell layer, disk of radius 20 cells and
     contrast 0.05, one normal-incidence plane wave, complex128 MG-FGMRES(20), 4 levels, rel. residual
     1e-6): set-up and solve timed separately, median of `reps` after a warm-up, with one BLAS thread
@@ -432,14 +433,14 @@ def main():
     if args.sweep:
         return sweep(args, wl, nmap, dirs)
     # host legs first: the all-cores leg forks worker processes, which must happen before the GPU is used
-    rates = c1 = None
+    rates = disk = None
     if not args.no_cpu_baseline and wl["d"] == 2:
         progress("CPU oracle rates (one thread; one process per core)")
         rates = cpu_rates(nmap, args.levels, args.restart, args.cycle, args.cpu_seconds, complex(1.0, args.kappa_im),
                           args.omega)
-        if not args.no_c1:
+        if not args.no_disk128_timing:
             progress("CPU oracle, disk128 set-up and solve timing")
-            c1 = cpu_c1_protocol()
+            disk = cpu_disk128_timing()
     import torch
 
     from paper_2107_03679_amd import helm
@@ -595,8 +596,8 @@ def main():
         vctx.close()
     if rates is not None:
         out["cpu_baseline"] = cpu_baseline(rates, float(iters.mean()), args.restart)
-    if c1 is not None:
-        out["cpu_c1"] = c1
+    if disk is not None:
+        out["cpu_disk128"] = disk
     print(json.dumps(out), flush=True)
 
 
