@@ -68,8 +68,9 @@ def parse():
                    help="instead of the benchmark line: solves/s and cycles per solve over the shift, the cycle "
                         "type, the smoothing steps and factor, and the level count (one JSON line per setting)")
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
-    p.add_argument("--learned-media", type=int, default=12,
-                   help="training media for the network (12: about 20k pairs at 512^2 x 60)")
+    p.add_argument("--learned-media", type=int, default=12, help="at most this many training media for the network")
+    p.add_argument("--learned-pairs", type=int, default=20000,
+                   help="training pairs the network is trained on at most: media are added until this many")
     p.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the network training")
     p.add_argument("--learned-accept", type=float, default=None,
                    help="acceptance threshold: the network's output is used where ||v - A net(v)|| <= t ||v||; "
@@ -330,7 +331,9 @@ def learned_leg(make_ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
     rng = np.random.default_rng(5)
     t0 = time.perf_counter()
     sets = []
-    for i in range(args.learned_media + 1):  # the last medium only validates
+    n_train, i = 0, 0
+    while True:  # training media until the pair budget (or the media count) is reached, then one to validate
+        val_medium = n_train >= args.learned_pairs or i == args.learned_media
         m = synth.blob_map(wl["n"], kw["n_blobs"], kw["sigma_range"], kw["amp_hi"], 1000 + i,
                            max_dn=kw.get("max_dn"), d=d)
         ctx.update_n(torch.tensor(m, dtype=torch.float32, device=dev))
@@ -342,12 +345,16 @@ def learned_leg(make_ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
             a = np.radians(45.0)
             train_dirs = np.stack([np.sin(a) * np.cos(ph), np.sin(a) * np.sin(ph), np.full(B, np.cos(a))], 1)
         rhs = ctx.plane_wave_rhs(train_dirs)
-        val_medium = i == args.learned_media
-        progress(f"learned: training pairs from medium {i}")
+        progress(f"learned: {'validation' if val_medium else 'training'} pairs from medium {i}")
         # 3D: one 96^3 crop per snapshot and right-hand side (each is 21 MB of FP32 features and targets)
         sets.append(learned.collect(ctx, [rhs], size=crop, crops_per_snapshot=1 if (val_medium or d == 3) else 4,
                                     every_cycles=8 if d == 2 else 4, max_snaps=12 if d == 2 else 4, seed=1000 + i,
                                     out=None if (val_medium or not sets) else sets.pop()))
+        if val_medium:
+            break
+        n_train = sets[-1].feat.shape[0]
+        i += 1
+    n_media = i
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     ctx.update_n(torch.tensor(nmap, dtype=torch.float32, device=dev))
@@ -395,7 +402,7 @@ def learned_leg(make_ctx, args, wl, nmap, dirs, mg_iters_mean, mg_value):
         "all_converged": bool(st.converged), "rel_res_true_max": float(st.rel_res_true.max()),
         "accepted_frac": float(1.0 - st.fallbacks.sum() / max(1, st.iters.sum())),
         "pairs": int(tr.feat.shape[0]), "crop": crop, "train_steps": log.steps, "train_s": log.seconds,
-        "collect_s": t_collect, "heldout_residual_ratio": ratio, "training_media": args.learned_media,
+        "collect_s": t_collect, "heldout_residual_ratio": ratio, "training_media": n_media,
         "mode": f"z = net(v) + V-cycle(v - A net(v)), V-cycle alone where ||v - A net(v)|| > "
                 f"{args.learned_accept:g} ||v||",
         "mfma": {"kernel": "net_apply (all convolutions of one application)", "achieved": achieved,
