@@ -15,6 +15,7 @@
 // The forward / backward-data convolution passes the weights as A and the
 // activations as B, so that D is [output channel][pixel].
 #include <algorithm>
+#include <type_traits>
 
 #include "dev_common.h"
 #include "net.h"
@@ -395,6 +396,285 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
       // the prefetched plane zc + 2 replaces plane zc - 2 (read by no output plane from here on)
       if (zc + 1 < zend) sstore((iz + 3) & 3);
       __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- conv, channel-specialised (2D)
+// The 2D layers with the input channel count CIN fixed at compile time.  Same implicit
+// GEMM as k_conv_lds, term for term: the same k order, products and sums, so the same
+// outputs bit for bit.  What changes is where the index arithmetic runs:
+//  * a k-step's 32 k-values fall on at most four taps, so the LDS offset of a lane's
+//    8 channels is one of four constants picked by its lane group (one constant plus
+//    8 g when the step stays on one tap), and the offsets of a wavefront's pixel
+//    segments from its first one are constants; the k-loop is unrolled;
+//  * the halo tile (pixel stride PS channels, as in k_conv_lds) is staged by halo row:
+//    each thread keeps one column chunk (its x clamp, source and channel offsets
+//    computed once) and walks the rows;
+//  * without WL every k-step's weight fragments sit in registers, loaded before the
+//    halo; with WL the 64-k chunks pass through LDS as in k_conv_lds, at constant
+//    offsets.
+// (Storing the halo tile by 8-channel group, [group][pixel][8], removes the LDS bank
+// conflicts of the padded pixel stride but made the level-0 decoder layer slower.)
+// A k-step past the last one with real k-values (k_conv_lds runs one when the step
+// count is odd) multiplies zero weights, so it is left out.
+template <int S, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (S < N) {
+    f(std::integral_constant<int, S>{});
+    static_for<S + 1, N>(f);
+  }
+}
+
+// LDS element offset, from the lane's pixel, of the 8 channels lane group g reads at
+// k-step s: k = 32 s + 8 g = tap * CIN + ci (k past the last tap reads the last tap)
+template <int CIN, int TW2, int PS>
+__host__ __device__ constexpr int conv_tap_off(int s, int g) {
+  const int k = 32 * s + 8 * g, tap = k / CIN < 8 ? k / CIN : 8;
+  return ((tap / 3) * TW2 + tap % 3) * PS + k % CIN;
+}
+
+template <int CIN, int NCO, int TH, int TW, int MODE, bool WL>
+__global__ __launch_bounds__(256) void k_conv2c(ConvArgs a) {
+  constexpr int PS = CIN == 8 ? 8 : CIN + 8, CG8 = CIN / 8;
+  constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64, PLANE = (TH + 2) * TW2;
+  constexpr int KS = (9 * CIN + 31) / 32, KPAD = 32 * KS;
+  static_assert(CIN % 8 == 0 && MT % SEG == 0, "whole 8-channel groups; a wavefront's segments fill tile rows");
+  extern __shared__ __align__(16) bf16 tile[];
+  const int tid = threadIdx.x, l = tid % 64, g = l / 16, i16 = l % 16;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH, H = a.H, W = a.W;
+  const long long img = blockIdx.z;
+  const NetSrc& sr = a.src;
+
+  // weights: all k-steps in registers, or (WL) 64-k chunks through two LDS buffers
+  // (issuing them after the first batch of halo loads, so that the halo's wait does not
+  // also wait for them, made the level-0 decoder layer 9% slower)
+  bf16x8 Bw[WL ? 1 : KS][NCO];
+  if constexpr (!WL) {
+    const bf16* wrow = a.wt + i16 * KPAD + 8 * g;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) Bw[s][t] = load8(wrow + t * 16 * KPAD + 32 * s);
+  }
+  constexpr int WPC = 16 * NCO * (WKC / 8), WPT = (WPC + 255) / 256, WBUF = 16 * NCO * WROW;
+  constexpr int NWC = (KPAD + WKC - 1) / WKC;
+  bf16* wl = tile + PLANE * PS;
+  bf16x8 wreg[WPT];
+  auto wfetch = [&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = tid + 256 * u, kq = (q % (WKC / 8)) * 8;
+      wreg[u] = (q < WPC && c * WKC + kq < KPAD) ? load8(a.wt + (q / (WKC / 8)) * KPAD + c * WKC + kq) : zero8();
+    }
+  };
+  auto wstore = [&](auto bc) {
+    constexpr int buf = decltype(bc)::value;
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = tid + 256 * u;
+      if (q < WPC) *reinterpret_cast<bf16x8*>(wl + buf * WBUF + (q / (WKC / 8)) * WROW + (q % (WKC / 8)) * 8) = wreg[u];
+    }
+  };
+  if constexpr (WL) {
+    wfetch(std::integral_constant<int, 0>{});
+    wstore(std::integral_constant<int, 0>{});
+  }
+
+  // ---- halo staging, by halo row: RW 16-byte chunks per row; a thread keeps the
+  // column chunk j (of each of NP passes over a row) and walks rows r0, r0 + RPP, ...
+  constexpr int RW = TW2 * CG8, NP = (RW + 255) / 256, RPP = RW <= 256 ? 256 / RW : 1;
+  constexpr int NRI = (TH + 2 + RPP - 1) / RPP;
+  constexpr int NSRC = MODE == 1 ? 4 : 1;
+  constexpr int RB0 = (WL ? 16 : 8) / (NP * NSRC), RB = RB0 < 1 ? 1 : (RB0 > NRI ? NRI : RB0);  // rows per load batch
+  const int r0 = RW <= 256 ? tid / RW : 0;
+  const bf16* in_img;
+  if (MODE == 1)
+    in_img = sr.in + img * ((long long)sr.Hs * sr.Ws * sr.in_ct) + sr.in_off;
+  else
+    in_img = sr.in + img * ((long long)H * W * sr.in_ct) + sr.in_off;
+  const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+  const bf16* up_img = MODE == 2 ? sr.up + img * ((long long)Hu * Wu * sr.up_ct) : nullptr;
+  const bf16* colp[NP];  // source of the column chunk at row 0 (MODE 2: of the source it reads)
+  int dst0[NP], dxp[NP];
+  bool act[NP], xin[NP], hx[NP], isup[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int j = RW <= 256 ? tid - r0 * RW : tid + 256 * p;
+    act[p] = RW <= 256 ? r0 < RPP : j < RW;
+    const int c = min(j / CG8, TW2 - 1), cg = j - (j / CG8) * CG8;
+    const int xx = x0 - 1 + c, xc = min(max(xx, 0), W - 1);
+    xin[p] = xx >= 0 && xx < W;
+    dst0[p] = (r0 * TW2 + c) * PS + cg * 8;
+    isup[p] = false;
+    dxp[p] = 0;
+    hx[p] = false;
+    if (MODE == 1) {
+      colp[p] = in_img + 2 * xc * sr.in_ct + cg * 8;
+      dxp[p] = (2 * xc + 1 < sr.Ws) ? sr.in_ct : 0;
+      hx[p] = 2 * xx + 1 < sr.Ws;
+    } else if (MODE == 2 && cg * 8 < sr.cup) {
+      isup[p] = true;
+      colp[p] = up_img + (xc >> 1) * sr.up_ct + cg * 8;
+    } else {
+      colp[p] = in_img + xc * sr.in_ct + (cg * 8 - sr.cup);
+    }
+  }
+  static_for<0, (NRI + RB - 1) / RB>([&](auto bc) {
+    constexpr int i0 = decltype(bc)::value * RB, i1 = i0 + RB < NRI ? i0 + RB : NRI;
+    bf16x8 v[RB][NP][NSRC];
+    bool yin[RB], hy[RB];
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      const int r = min(r0 + i * RPP, TH + 1), yy = y0 - 1 + r, yc = min(max(yy, 0), H - 1);
+      yin[i - i0] = yy >= 0 && yy < H;
+      hy[i - i0] = 2 * yy + 1 < sr.Hs;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (MODE == 1) {
+          const bf16* q = colp[p] + (long long)2 * yc * sr.Ws * sr.in_ct;
+          const int dy = (2 * yc + 1 < sr.Hs) ? sr.Ws * sr.in_ct : 0;
+          v[i - i0][p][0] = load8(q);
+          v[i - i0][p][NSRC > 1 ? 1 : 0] = load8(q + dxp[p]);
+          v[i - i0][p][NSRC > 2 ? 2 : 0] = load8(q + dy);
+          v[i - i0][p][NSRC > 3 ? 3 : 0] = load8(q + dy + dxp[p]);
+        } else {
+          const int ro = MODE == 2 && isup[p] ? (yc >> 1) * Wu * sr.up_ct : yc * W * sr.in_ct;
+          v[i - i0][p][0] = load8(colp[p] + ro);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      if (r0 + i * RPP >= TH + 2) continue;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (!act[p]) continue;
+        bf16x8 o;
+        if (MODE == 1) {
+          // average with zero padding: children past the source edge count 0
+          const float w1 = hx[p] ? 1.f : 0.f, w2 = hy[i - i0] ? 1.f : 0.f, w3 = (hx[p] && hy[i - i0]) ? 1.f : 0.f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float acc = (float)v[i - i0][p][0][e];
+            acc += w1 * (float)v[i - i0][p][NSRC > 1 ? 1 : 0][e];
+            acc += w2 * (float)v[i - i0][p][NSRC > 2 ? 2 : 0][e];
+            acc += w3 * (float)v[i - i0][p][NSRC > 3 ? 3 : 0][e];
+            o[e] = (bf16)(0.25f * acc);
+          }
+        } else {
+          o = v[i - i0][p][0];
+        }
+        *reinterpret_cast<bf16x8*>(tile + dst0[p] + i * RPP * TW2 * PS) = (xin[p] && yin[i - i0]) ? o : zero8();
+      }
+    }
+  });
+  __syncthreads();
+
+  // ---- implicit GEMM: segment m of this wavefront is tile row wave * MT / SEG + m / SEG,
+  // columns (m % SEG) * 16 + 0..15; its LDS offset from segment 0 is a constant
+  const int base0 = ((wave * (MT / SEG)) * TW2 + i16) * PS, base8 = base0 + 8 * g;
+  const bool g1 = g & 1, g2 = g & 2;
+  auto readA = [&](auto sc, bf16x8* A) {
+    constexpr int s = decltype(sc)::value;
+    constexpr int o0 = conv_tap_off<CIN, TW2, PS>(s, 0), o1 = conv_tap_off<CIN, TW2, PS>(s, 1);
+    constexpr int o2 = conv_tap_off<CIN, TW2, PS>(s, 2), o3 = conv_tap_off<CIN, TW2, PS>(s, 3);
+    int off;
+    if constexpr (o1 == o0 + 8 && o2 == o0 + 16 && o3 == o0 + 24)
+      off = base8 + o0;  // one tap, 32 consecutive channels
+    else
+      off = base0 + (g2 ? (g1 ? o3 : o2) : (g1 ? o1 : o0));
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      A[m] = *reinterpret_cast<const bf16x8*>(tile + off + ((m / SEG) * TW2 + (m % SEG) * 16) * PS);
+  };
+  f32x4 acc[MT][NCO];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto mfma_step = [&](const bf16x8* A, const bf16x8* Bv) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bv[t], A[m], acc[m][t], 0, 0, 0);
+  };
+  bf16x8 Ab[2][MT];
+  if constexpr (!WL) {
+    readA(std::integral_constant<int, 0>{}, Ab[0]);
+    static_for<0, KS>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if constexpr (s + 1 < KS) readA(std::integral_constant<int, s + 1>{}, Ab[(s + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step(Ab[s & 1], Bw[s]);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  } else {
+    const bf16* wlane = wl + i16 * WROW + 8 * g;
+    static_for<0, NWC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value, s0 = 2 * c;
+      constexpr bool two = s0 + 1 < KS;
+      if constexpr (c + 1 < NWC) wfetch(std::integral_constant<int, c + 1>{});
+      const bf16* wb = wlane + (c & 1) * WBUF;
+      bf16x8 b0[NCO], b1[NCO];
+      readA(std::integral_constant<int, s0>{}, Ab[0]);
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) b0[t] = *reinterpret_cast<const bf16x8*>(wb + t * 16 * WROW);
+      if constexpr (two) {
+        readA(std::integral_constant<int, s0 + 1>{}, Ab[1]);
+#pragma unroll
+        for (int t = 0; t < NCO; ++t) b1[t] = *reinterpret_cast<const bf16x8*>(wb + 32 + t * 16 * WROW);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step(Ab[0], b0);
+      if constexpr (two) mfma_step(Ab[1], b1);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (c + 1 < NWC) wstore(std::integral_constant<int, (c + 1) & 1>{});
+      __syncthreads();
+    });
+  }
+
+  // ---- epilogue, as in k_conv_lds: lane (i16, g) holds channels t * 16 + 4 g + 0..3 of
+  // pixel i16 of each segment
+  const int cout = a.cout;
+  float bsv[NCO][4];
+#pragma unroll
+  for (int t = 0; t < NCO; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = t * 16 + 4 * g + q;
+      bsv[t][q] = (a.bias && ch < cout) ? a.bias[ch] : 0.f;
+    }
+  const long long oimg = img * ((long long)H * W * a.out_ct) + a.out_off;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int y = y0 + wave * (MT / SEG) + m / SEG, xo = x0 + (m % SEG) * 16 + i16;
+    if (y >= H || xo >= W) continue;
+    const int po = (y * W + xo) * a.out_ct;  // inside the image
+#pragma unroll
+    for (int t = 0; t < NCO; ++t) {
+      const int c0 = t * 16 + 4 * g;
+      if (c0 >= cout) continue;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = acc[m][t][q] + bsv[t][q];
+        if (a.relu) v[q] = fmaxf(v[q], 0.f);
+      }
+      if (a.out32) {
+        float* dst = a.out32 + oimg + po + c0;
+        if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        else
+          for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
+      } else {
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
+        *reinterpret_cast<bf16x4*>(a.out + oimg + po + c0) = o;
+      }
     }
   }
 }
@@ -870,10 +1150,41 @@ void conv_lds(hipStream_t s, const ConvArgs& a) {
   else hipLaunchKernelGGL((k_conv_lds<NCO, TH, TW, 0, NDIM, false, 0>), grid, dim3(256), lds, s, a);
 }
 
+template <int CIN, int NCO, int TH, int MODE>
+void conv2c(hipStream_t s, const ConvArgs& a) {
+  constexpr int TW = 32, KPAD = (9 * CIN + 31) / 32 * 32;
+  constexpr bool WL = 16 * NCO * KPAD * (int)sizeof(bf16) > 32768;  // weights above the 32 KB L1
+  const size_t lds = (size_t)(TH + 2) * (TW + 2) * (CIN == 8 ? 8 : CIN + 8) * sizeof(bf16) + (WL ? 2 * 16 * NCO * WROW * sizeof(bf16) : 0);
+  const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg);
+  hipLaunchKernelGGL((k_conv2c<CIN, NCO, TH, TW, MODE, WL>), grid, dim3(256), lds, s, a);
+}
+
+// The channel-specialised kernels of the 2D network's forward layers (their tile shapes
+// those of the generic kernel); false when the layer has none.  The pooled 16-channel
+// layer (A1) stays on the generic kernel: its specialised form, holding 40 weight
+// registers beside four pooled sources per chunk, runs at 3 wavefronts per SIMD and was
+// slower (272-288 against 247 us at 60 x 577^2).
+bool conv2c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
+  if (a.kpad != (9 * a.cin + 31) / 32 * 32) return false;
+  const int mode = a.src.pool ? 1 : (a.src.cup > 0 ? 2 : 0);
+  switch ((a.cin << 8) | (nco << 4) | mode) {
+    case (8 << 8) | (1 << 4) | 0: conv2c<8, 1, 8, 0>(s, a); return true;       // A0
+    case (32 << 8) | (4 << 4) | 1: conv2c<32, 4, 8, 1>(s, a); return true;     // A2
+    case (64 << 8) | (4 << 4) | 1: conv2c<64, 4, 8, 1>(s, a); return true;     // A3
+    case (128 << 8) | (4 << 4) | 2: conv2c<128, 4, 4, 2>(s, a); return true;   // B2
+    case (96 << 8) | (2 << 4) | 2: conv2c<96, 2, 4, 2>(s, a); return true;     // B1
+    case (48 << 8) | (1 << 4) | 2: conv2c<48, 1, 8, 2>(s, a); return true;     // B0
+    case (16 << 8) | (1 << 4) | 0: conv2c<16, 1, 8, 0>(s, a); return true;     // O
+    default: return false;
+  }
+}
+
 // 2D tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile stays
 // within 50 KB of LDS and the accumulators within 64 registers, else 4 x 32.  3D: three
 // staged planes, so 4 x 32 up to 32 input channels and 2 x 32 above (under 60 KB).
-void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim) {
+// Unless `generic`, a 2D layer with a channel-specialised kernel runs that one (same result).
+void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim, bool generic) {
+  if (dim == 2 && !generic && conv2c_dispatch(s, a, nco)) return;
   if (dim == 3) {
     const bool wide = a.cin > 32;
     switch (nco) {

@@ -87,6 +87,7 @@ struct helm_net {
   std::vector<void*> allocs;
   std::string err;
   int step = 0;
+  bool generic_conv = false;  // channel-generic convolution kernels only (helm_net_set_conv_kernels)
   // training loss: err_w / 2 sum (y - t)^2 + res_w / 2 sum |r - gamma A' y|^2, per image
   double err_w = 1.0, res_w = 0.0, gamma = 1.0, cb = 0.0;
   NetBufs tb;              // buffers of the user calls (forward / backward)
@@ -217,7 +218,7 @@ void conv(helm_net* n, int i, const NetSrc& src, int lvl, bf16* out, float* out3
   a.out32 = out32;
   a.out_ct = out_ct;
   a.out_off = out_off;
-  launch_conv3x3(n->s, a, L.cout_pad / 16, n->dim);
+  launch_conv3x3(n->s, a, L.cout_pad / 16, n->dim, n->generic_conv);
 }
 
 // backward-data: g_in (fp32, cin channels at g_ct/g_off) = conv of the masked gradient n->cur->gm with flipped weights
@@ -239,7 +240,7 @@ void conv_back(helm_net* n, int i, int lvl, float* gin, int g_ct) {
   a.out32 = gin;
   a.out_ct = g_ct;
   a.out_off = 0;
-  launch_conv3x3(n->s, a, wb_rows(L) / 16, n->dim);
+  launch_conv3x3(n->s, a, wb_rows(L) / 16, n->dim, n->generic_conv);
 }
 
 void wgrad(helm_net* n, int i, const NetSrc& src, int lvl) {
@@ -527,6 +528,12 @@ int helm_net_layer_shape(int i, int* cin, int* cout) {
 }
 
 int helm_net_dim(const helm_net* n) { return n ? n->dim : HELM_EINVAL; }
+
+int helm_net_set_conv_kernels(helm_net* n, int generic) {
+  if (!n || (generic != 0 && generic != 1)) return HELM_EINVAL;
+  n->generic_conv = generic == 1;
+  return HELM_OK;
+}
 
 int helm_net_shape(const helm_net* n, int i, int* cin, int* cout) {
   if (!n || i < 0 || i >= HELM_NET_LAYERS) return HELM_EINVAL;

@@ -52,7 +52,8 @@ struct WgradArgs {
 };
 
 // 3x3 (dim 2) or 3x3x3 (dim 3) convolution, nco output tiles of 16 channels
-void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim);
+// generic: the channel-generic kernel even where a channel-specialised one exists
+void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim, bool generic);
 void launch_wgrad(hipStream_t s, const WgradArgs& a, int nchunk, float* dw, const bf16* g_for_bias, float* db,
                   int cout_real);
 void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int g_off, const bf16* act, int act_ct,

@@ -84,7 +84,7 @@ EXPORTS = [
     "helm_farfield_set", "helm_farfield", "helm_farfield_adjoint", "helm_grad_f_farfield", "helm_farfield_residual",
     "helm_examples_rms", "helm_examples_scale", "helm_net_residual_ratio", "helm_update_contrast",
     "helm_grad_contrast", "helm_data_residual_static", "helm_net_create3", "helm_net_dim", "helm_net_shape",
-    "helm_net_forward3", "helm_net_backward3", "helm_net_residual_ratio3",
+    "helm_net_forward3", "helm_net_backward3", "helm_net_residual_ratio3", "helm_net_set_conv_kernels",
 ]
 
 _lib = None
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helm_net_create.argtypes = [ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
     lib.helm_net_create3.argtypes = [ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
     lib.helm_net_dim.argtypes = [vp]
+    lib.helm_net_set_conv_kernels.argtypes = [vp, i]
     lib.helm_net_shape.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.helm_net_forward3.argtypes = [vp, i, i, i, i, vp, vp]
     lib.helm_net_backward3.argtypes = [vp, i, i, i, i, vp, vp, ctypes.POINTER(d)]
@@ -675,6 +676,10 @@ class Net:
                         "helm_net_get")
             out[name + ".w"], out[name + ".b"] = w, b
         return out
+
+    def set_conv_kernels(self, generic: bool):
+        """generic=True: the channel-generic convolution kernels for every layer (same outputs)."""
+        self._check(self.lib.helm_net_set_conv_kernels(self._h, 1 if generic else 0), "helm_net_set_conv_kernels")
 
     def params(self) -> dict:
         return self._get(self.lib.helm_net_get_layer)

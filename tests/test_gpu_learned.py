@@ -57,6 +57,24 @@ def test_forward_matches_reference(net_and_params, shape):
     assert rel(y, ref) < 3e-2
 
 
+@pytest.mark.parametrize("shape", [(3, 37, 45), (2, 130, 97), (1, 577, 577)])
+def test_specialised_convolutions_match_generic(net_and_params, shape):
+    """The channel-specialised 2D convolution kernels form the generic kernel's sums in the
+    same order, so the forward outputs agree bit for bit (ragged tiles on every level)."""
+    net, _ = net_and_params
+    n, h, w = shape
+    print(f"[specialised vs generic convolutions {shape}]", flush=True)
+    x = torch.tensor(np.random.default_rng(11).standard_normal((n, h, w, 4)), dtype=torch.float32, device="cuda")
+    net.set_conv_kernels(generic=True)
+    try:
+        y_gen = net.forward(x)
+    finally:
+        net.set_conv_kernels(generic=False)
+    y = net.forward(x)
+    assert torch.isfinite(y).all()
+    assert torch.equal(y, y_gen), float((y - y_gen).abs().max())
+
+
 @pytest.mark.parametrize("weights", [(1.0, 0.0), (0.5, 2.0)])
 def test_gradients_match_reference(net_and_params, weights):
     net, pq = net_and_params
