@@ -740,7 +740,27 @@ __global__ void k_wgrad_reduce(int nchunk, int n, const float* part, float* dw) 
   dw[t] = s;
 }
 
-// db[co] = sum_p g[p][co] (one block per channel, fixed-order reduction)
+// db[co] = sum_p g[p][co], first stage: block `chunk` sums its pixels [chunk * n, ...)
+// into part[chunk][co]; thread t takes channel t % g_ct of every (256 / g_ct)-th pixel, so
+// a block reads consecutive 512-byte rows of g.  The chunk partials are then summed in
+// chunk order (k_wgrad_reduce): the same order on every call.  g_ct divides 256.
+__global__ __launch_bounds__(256) void k_bias_part(long long P, int n, const bf16* g, int g_ct, int cout,
+                                                   float* part) {
+  __shared__ float red[256];
+  const int c = threadIdx.x % g_ct, lane = threadIdx.x / g_ct, lanes = 256 / g_ct;
+  const long long p0 = (long long)blockIdx.x * n, p1 = min(p0 + n, P);
+  float s = 0.f;
+  for (long long p = p0 + lane; p < p1; p += lanes) s += (float)g[p * g_ct + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    float t = 0.f;
+    for (int k = 0; k < lanes; ++k) t += red[k * g_ct + threadIdx.x];
+    part[(long long)blockIdx.x * cout + threadIdx.x] = t;
+  }
+}
+
+// db[co] = sum_p g[p][co] in one block per channel (channel strides that do not divide 256)
 __global__ void k_bias_grad(long long P, const bf16* g, int g_ct, float* db) {
   __shared__ float red[256];
   const int co = blockIdx.x;
@@ -1216,7 +1236,13 @@ void launch_wgrad(hipStream_t s, const WgradArgs& a, int nchunk, float* dw, cons
   const int n = a.cout_pad * a.kpad;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(n, 256)), dim3(256), 0, s, nchunk, n, a.part, dw);
   const long long P = (long long)a.nimg * (a.dim == 3 ? a.D : 1) * a.H * a.W;
-  hipLaunchKernelGGL(k_bias_grad, dim3(cout_real), dim3(256), 0, s, P, g_for_bias, a.g_ct, db);
+  if (256 % a.g_ct == 0 && cout_real <= a.g_ct) {
+    // the weight partials are consumed by now (stream order): reuse the buffer
+    hipLaunchKernelGGL(k_bias_part, dim3(nchunk), dim3(256), 0, s, P, a.chunk, g_for_bias, a.g_ct, cout_real, a.part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(cout_real, 256)), dim3(256), 0, s, nchunk, cout_real, a.part, db);
+  } else {
+    hipLaunchKernelGGL(k_bias_grad, dim3(cout_real), dim3(256), 0, s, P, g_for_bias, a.g_ct, db);
+  }
 }
 
 void launch_grad_prep(hipStream_t s, long long P, const float* g, int g_ct, int g_off, const bf16* act, int act_ct,
