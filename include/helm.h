@@ -391,11 +391,12 @@ int helm_net_create(unsigned long long seed, void* hip_stream, helm_net** out);
  * names 3D as future work). */
 int helm_net_create3(unsigned long long seed, void* hip_stream, helm_net** out);
 int helm_net_dim(const helm_net* net);                                      /* 2 or 3 */
-/* Convolution kernels of a 2D network: generic = 0 (default) runs each forward layer on
- * the kernel specialised for its input channel count, generic = 1 on the channel-generic
- * kernel.  Both compute the same sums in the same order, so outputs agree bit for bit;
- * the switch is for tests and measurements.  HELM_EINVAL for a generic value other
- * than 0 or 1.  3D networks always use the generic kernels. */
+/* Convolution kernels: generic = 0 (default) runs each layer that has one on a kernel
+ * specialised for its input channel count (the 2D network's forward layers but the
+ * pooled 16-channel one; the 3D network's marching layers A0, B0 and O), generic = 1
+ * every layer on the channel-generic kernels.  Both compute the same sums in the same
+ * order, so outputs agree bit for bit; the switch is for tests and measurements.
+ * HELM_EINVAL for a generic value other than 0 or 1. */
 int helm_net_set_conv_kernels(helm_net* net, int generic);
 int helm_net_shape(const helm_net* net, int layer, int* cin, int* cout);   /* this network's channels */
 void helm_net_destroy(helm_net* net);

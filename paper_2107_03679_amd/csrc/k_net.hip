@@ -679,6 +679,204 @@ __global__ __launch_bounds__(256) void k_conv2c(ConvArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- conv, channel-specialised (3D)
+// The marching 3D layers (plain or upsample-and-skip inputs, weights within the L1)
+// with CIN fixed at compile time: the products and sums of k_conv_lds's marching form
+// in the same order (outputs equal bit for bit), with the index arithmetic at compile
+// time as in k_conv2c.  A block computes ZM output planes of a TH x TW tile; four plane
+// slots hold the halo planes z - 1, z, z + 1 and the prefetched z + 2.  A k-step's lane
+// group reads tap (dz, dy, dx), channel ci: its LDS offset is the (uniform, per output
+// plane) base of slot (z - z0 + dz) mod 4 plus a compile-time constant.  The weights of
+// every k-step sit in registers.
+template <int CIN>
+__host__ __device__ constexpr int conv3_tap(int s, int g) {  // tap of lane group g at k-step s
+  return (32 * s + 8 * g) / CIN < 26 ? (32 * s + 8 * g) / CIN : 26;
+}
+template <int CIN, int TW2, int PS>
+__host__ __device__ constexpr int conv3_off(int s, int g) {  // in-plane offset of that read
+  const int k = 32 * s + 8 * g, tp = conv3_tap<CIN>(s, g) % 9;
+  return ((tp / 3) * TW2 + tp % 3) * PS + k % CIN;
+}
+
+template <int CIN, int NCO, int TH, int TW, int MODE, int ZM>
+__global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
+  constexpr int PS = CIN == 8 ? 8 : CIN + 8, CG8 = CIN / 8;
+  constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64, PLANE = (TH + 2) * TW2, SLOT = PLANE * PS;
+  constexpr int KS = (27 * CIN + 31) / 32, KPAD = 32 * KS;
+  static_assert(CIN % 8 == 0 && MT % SEG == 0 && MODE != 1, "whole channel groups and tile rows; no pooled input");
+  extern __shared__ __align__(16) bf16 tile[];
+  const int tid = threadIdx.x, l = tid % 64, g = l / 16, i16 = l % 16;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int D = a.D, H = a.H, W = a.W, x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const int nzb = (D + ZM - 1) / ZM;
+  const long long img = blockIdx.z / nzb;
+  const int z0 = (int)(blockIdx.z % nzb) * ZM, zend = min(D, z0 + ZM);
+  const NetSrc& sr = a.src;
+  const bf16* in_img = sr.in + img * ((long long)D * H * W * sr.in_ct) + sr.in_off;
+  const int Du = (D + 1) / 2, Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+  const bf16* up_img = MODE == 2 ? sr.up + img * ((long long)Du * Hu * Wu * sr.up_ct) : nullptr;
+  // every k-step's weight fragments in registers, loaded once per block (the LDS of the
+  // four plane slots allows two blocks per CU, so there is room for them)
+  bf16x8 Bw[KS][NCO];
+  {
+    const bf16* wrow = a.wt + i16 * KPAD + 8 * g;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) Bw[s][t] = load8(wrow + t * 16 * KPAD + 32 * s);
+  }
+
+  // ---- plane staging, by halo row (as in k_conv2c), every row of a plane in one batch
+  constexpr int RW = TW2 * CG8, NP = (RW + 255) / 256, RPP = RW <= 256 ? 256 / RW : 1;
+  constexpr int NRI = (TH + 2 + RPP - 1) / RPP;
+  const int r0 = RW <= 256 ? tid / RW : 0;
+  const bf16* colp[NP];
+  int dst0[NP];
+  bool act[NP], xin[NP], isup[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int j = RW <= 256 ? tid - r0 * RW : tid + 256 * p;
+    act[p] = RW <= 256 ? r0 < RPP : j < RW;
+    const int c = min(j / CG8, TW2 - 1), cg = j - (j / CG8) * CG8;
+    const int xx = x0 - 1 + c, xc = min(max(xx, 0), W - 1);
+    xin[p] = xx >= 0 && xx < W;
+    dst0[p] = (r0 * TW2 + c) * PS + cg * 8;
+    isup[p] = MODE == 2 && cg * 8 < sr.cup;
+    colp[p] = isup[p] ? up_img + (xc >> 1) * sr.up_ct + cg * 8 : in_img + xc * sr.in_ct + (cg * 8 - sr.cup);
+  }
+  typedef bf16x8 PlaneRegs[NRI][NP];
+  auto load_plane = [&](int zz, PlaneRegs& v, bool (&ok)[NRI]) {
+    const int zc = min(max(zz, 0), D - 1);
+    const bool zin = zz >= 0 && zz < D;
+#pragma unroll
+    for (int i = 0; i < NRI; ++i) {
+      const int r = min(r0 + i * RPP, TH + 1), yy = y0 - 1 + r, yc = min(max(yy, 0), H - 1);
+      ok[i] = zin && yy >= 0 && yy < H;
+      const long long oin = ((long long)zc * H + yc) * W * sr.in_ct;
+      const long long oup = MODE == 2 ? ((long long)(zc >> 1) * Hu + (yc >> 1)) * Wu * sr.up_ct : 0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) v[i][p] = load8(colp[p] + (isup[p] ? oup : oin));
+    }
+  };
+  auto store_plane = [&](int slot, const PlaneRegs& v, const bool (&ok)[NRI]) {
+#pragma unroll
+    for (int i = 0; i < NRI; ++i) {
+      if (r0 + i * RPP >= TH + 2) continue;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        if (act[p])
+          *reinterpret_cast<bf16x8*>(tile + slot * SLOT + dst0[p] + i * RPP * TW2 * PS) =
+              (xin[p] && ok[i]) ? v[i][p] : zero8();
+    }
+  };
+  {
+    PlaneRegs v0, v1, v2;
+    bool k0[NRI], k1[NRI], k2[NRI];
+    load_plane(z0 - 1, v0, k0);
+    load_plane(z0, v1, k1);
+    load_plane(z0 + 1, v2, k2);
+    store_plane(0, v0, k0);
+    store_plane(1, v1, k1);
+    store_plane(2, v2, k2);
+  }
+  __syncthreads();
+
+  const int base0 = ((wave * (MT / SEG)) * TW2 + i16) * PS;
+  const bool g1 = g & 1, g2 = g & 2;
+  const int cout = a.cout;
+  const long long oimg = img * ((long long)D * H * W * a.out_ct) + a.out_off;
+  PlaneRegs vn;
+  bool kn[NRI];
+  for (int zc = z0; zc < zend; ++zc) {
+    const int iz = zc - z0;
+    const bool more = zc + 1 < zend;  // uniform
+    if (more) load_plane(zc + 2, vn, kn);  // the plane the next output plane adds
+    // per tap plane dz: the LDS base of its slot for this lane, plus 8 g / 8 (g & 1)
+    int sb[3], sb8[3], sbh[3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      sb[dz] = base0 + ((iz + dz) & 3) * SLOT;
+      sb8[dz] = sb[dz] + 8 * g;
+      sbh[dz] = sb[dz] + 8 * (g & 1);
+    }
+    auto readA = [&](auto sc, bf16x8* A) {
+      constexpr int s = decltype(sc)::value;
+      constexpr int t0 = conv3_tap<CIN>(s, 0), t1 = conv3_tap<CIN>(s, 1);
+      constexpr int t2 = conv3_tap<CIN>(s, 2), t3 = conv3_tap<CIN>(s, 3);
+      constexpr int o0 = conv3_off<CIN, TW2, PS>(s, 0), o1 = conv3_off<CIN, TW2, PS>(s, 1);
+      constexpr int o2 = conv3_off<CIN, TW2, PS>(s, 2), o3 = conv3_off<CIN, TW2, PS>(s, 3);
+      int off;
+      if constexpr (t0 == t3 && o1 == o0 + 8 && o2 == o0 + 16 && o3 == o0 + 24)
+        off = sb8[t0 / 9] + o0;  // one tap, 32 consecutive channels
+      else if constexpr (t0 == t1 && t2 == t3 && o1 == o0 + 8 && o3 == o2 + 8)
+        off = g2 ? sbh[t2 / 9] + o2 : sbh[t0 / 9] + o0;  // two taps, 16 channels each
+      else
+        off = g2 ? (g1 ? sb[t3 / 9] + o3 : sb[t2 / 9] + o2) : (g1 ? sb[t1 / 9] + o1 : sb[t0 / 9] + o0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        A[m] = *reinterpret_cast<const bf16x8*>(tile + off + ((m / SEG) * TW2 + (m % SEG) * 16) * PS);
+    };
+    f32x4 acc[MT][NCO];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 Ab[2][MT];
+    readA(std::integral_constant<int, 0>{}, Ab[0]);
+    static_for<0, KS>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if constexpr (s + 1 < KS) readA(std::integral_constant<int, s + 1>{}, Ab[(s + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NCO; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[s][t], Ab[s & 1][m], acc[m][t], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    // epilogue, as in k_conv_lds
+    float bsv[NCO][4];
+#pragma unroll
+    for (int t = 0; t < NCO; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = t * 16 + 4 * g + q;
+        bsv[t][q] = (a.bias && ch < cout) ? a.bias[ch] : 0.f;
+      }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int y = y0 + wave * (MT / SEG) + m / SEG, xo = x0 + (m % SEG) * 16 + i16;
+      if (y >= H || xo >= W) continue;
+      const int po = ((zc * H + y) * W + xo) * a.out_ct;  // inside the image
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) {
+        const int c0 = t * 16 + 4 * g;
+        if (c0 >= cout) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = acc[m][t][q] + bsv[t][q];
+          if (a.relu) v[q] = fmaxf(v[q], 0.f);
+        }
+        if (a.out32) {
+          float* dst = a.out32 + oimg + po + c0;
+          if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+          else
+            for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
+        } else {
+          typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+          bf16x4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
+          *reinterpret_cast<bf16x4*>(a.out + oimg + po + c0) = o;
+        }
+      }
+    }
+    if (more) store_plane((iz + 3) & 3, vn, kn);  // plane zc + 2 replaces plane zc - 2
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- weight gradient (MFMA)
 // dW[co][k] = sum_p in[p + shift(tap(k))][ci(k)] * g[p][co]: a GEMM over pixels.
 // Block (k tile of 16, channel tile of 16, pixel chunk); each wavefront takes a
@@ -1199,12 +1397,34 @@ bool conv2c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
   }
 }
 
+template <int CIN, int MODE>
+void conv3c(hipStream_t s, const ConvArgs& a) {
+  constexpr int TH = 4, TW = 32, ZM = 8;
+  const size_t lds = (size_t)4 * (TH + 2) * (TW + 2) * (CIN == 8 ? 8 : CIN + 8) * sizeof(bf16);
+  const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * ((a.D + ZM - 1) / ZM));
+  hipLaunchKernelGGL((k_conv3c<CIN, 1, TH, TW, MODE, ZM>), grid, dim3(256), lds, s, a);
+}
+
+// The channel-specialised kernels of the 3D network's marching layers (the generic
+// kernel's 4 x 32 tile and 8 planes per block); false when the layer has none.
+bool conv3c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
+  if (a.kpad != (27 * a.cin + 31) / 32 * 32 || nco != 1 || a.src.pool) return false;
+  const int mode = a.src.cup > 0 ? 2 : 0;
+  switch ((a.cin << 4) | mode) {
+    case (8 << 4) | 0: conv3c<8, 0>(s, a); return true;    // A0
+    case (32 << 4) | 2: conv3c<32, 2>(s, a); return true;  // B0
+    case (16 << 4) | 0: conv3c<16, 0>(s, a); return true;  // O
+    default: return false;
+  }
+}
+
 // 2D tile: 8 x 32 pixels (four 16-pixel segments per wavefront) while the halo tile stays
 // within 50 KB of LDS and the accumulators within 64 registers, else 4 x 32.  3D: three
 // staged planes, so 4 x 32 up to 32 input channels and 2 x 32 above (under 60 KB).
-// Unless `generic`, a 2D layer with a channel-specialised kernel runs that one (same result).
+// Unless `generic`, a layer with a channel-specialised kernel runs that one (same result).
 void launch_conv3x3(hipStream_t s, const ConvArgs& a, int nco, int dim, bool generic) {
   if (dim == 2 && !generic && conv2c_dispatch(s, a, nco)) return;
+  if (dim == 3 && !generic && conv3c_dispatch(s, a, nco)) return;
   if (dim == 3) {
     const bool wide = a.cin > 32;
     switch (nco) {

@@ -52,6 +52,25 @@ def test_forward_matches_reference(net3, shape):
     assert rel(y, ref) < 3e-2
 
 
+@pytest.mark.parametrize("shape", [(2, 9, 11, 13), (1, 19, 22, 37), (1, 64, 64, 64)])
+def test_specialised_convolutions_match_generic_3d(net3, shape):
+    """The channel-specialised marching 3D convolutions (A0, B0, O) form the generic
+    kernel's sums in the same order: forward outputs agree bit for bit (depths that are
+    not multiples of the 8 planes a block marches through, ragged tiles)."""
+    net, _ = net3
+    n, d, h, w = shape
+    print(f"[specialised vs generic 3D convolutions {shape}]", flush=True)
+    x = torch.tensor(np.random.default_rng(12).standard_normal((n, d, h, w, 4)), dtype=torch.float32, device="cuda")
+    net.set_conv_kernels(generic=True)
+    try:
+        y_gen = net.forward(x)
+    finally:
+        net.set_conv_kernels(generic=False)
+    y = net.forward(x)
+    assert torch.isfinite(y).all()
+    assert torch.equal(y, y_gen), float((y - y_gen).abs().max())
+
+
 @pytest.mark.parametrize("weights", [(1.0, 0.0), (0.5, 2.0)])
 def test_gradients_match_reference(net3, weights):
     net, pq = net3
