@@ -73,6 +73,7 @@ def test_specialised_convolutions_match_generic(net_and_params, shape):
     y = net.forward(x)
     assert torch.isfinite(y).all()
     assert torch.equal(y, y_gen), float((y - y_gen).abs().max())
+    assert net.lib.helm_net_set_conv_kernels(net._h, 2) == -1  # only 0 and 1
 
 
 @pytest.mark.parametrize("weights", [(1.0, 0.0), (0.5, 2.0)])

@@ -91,6 +91,7 @@ def test_null_arguments_return_einval_without_a_device():
     assert lib.helm_data_residual(None, 1, 1, None, None, None, None, None) == -1
     assert lib.helm_examples_rms(None, None, 1, None) == -1
     assert lib.helm_net_residual_ratio(None, 1, 8, 8, None, 1.0, 1.0, None) == -1
+    assert lib.helm_net_set_conv_kernels(None, 0) == -1
 
 
 def test_workgroup_order_maps_are_bijections(tmp_path):
