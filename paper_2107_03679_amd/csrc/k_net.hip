@@ -680,14 +680,14 @@ __global__ __launch_bounds__(256) void k_conv2c(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------- conv, channel-specialised (3D)
-// The marching 3D layers (plain or upsample-and-skip inputs, weights within the L1)
-// with CIN fixed at compile time: the products and sums of k_conv_lds's marching form
-// in the same order (outputs equal bit for bit), with the index arithmetic at compile
-// time as in k_conv2c.  A block computes ZM output planes of a TH x TW tile; four plane
-// slots hold the halo planes z - 1, z, z + 1 and the prefetched z + 2.  A k-step's lane
-// group reads tap (dz, dy, dx), channel ci: its LDS offset is the (uniform, per output
-// plane) base of slot (z - z0 + dz) mod 4 plus a compile-time constant.  The weights of
-// every k-step sit in registers.
+// 3D layers with plain or upsample-and-skip inputs, CIN fixed at compile time: the
+// products and sums of k_conv_lds (whose marching form these follow) in the same order,
+// so the outputs are equal bit for bit, with the index arithmetic at compile time as in
+// k_conv2c.  A block computes ZM output planes of a TH x TW tile; four plane slots hold
+// the halo planes z - 1, z, z + 1 and the prefetched z + 2.  A k-step's lane group reads
+// tap (dz, dy, dx), channel ci: its LDS offset is the (uniform, per output plane) base of
+// slot (z - z0 + dz) mod 4 plus a compile-time constant.  The weights of every k-step
+// sit in registers; the A operands are read PD k-steps ahead.
 template <int CIN>
 __host__ __device__ constexpr int conv3_tap(int s, int g) {  // tap of lane group g at k-step s
   return (32 * s + 8 * g) / CIN < 26 ? (32 * s + 8 * g) / CIN : 26;
@@ -698,7 +698,7 @@ __host__ __device__ constexpr int conv3_off(int s, int g) {  // in-plane offset 
   return ((tp / 3) * TW2 + tp % 3) * PS + k % CIN;
 }
 
-template <int CIN, int NCO, int TH, int TW, int MODE, int ZM>
+template <int CIN, int NCO, int TH, int TW, int MODE, int ZM, int PD>
 __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
   constexpr int PS = CIN == 8 ? 8 : CIN + 8, CG8 = CIN / 8;
   constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64, PLANE = (TH + 2) * TW2, SLOT = PLANE * PS;
@@ -821,17 +821,19 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 Ab[2][MT];
-    readA(std::integral_constant<int, 0>{}, Ab[0]);
+    // A read PD k-steps ahead of the MFMAs that use it
+    constexpr int NB = PD + 1;
+    bf16x8 Ab[NB][MT];
+    static_for<0, (PD < KS ? PD : KS)>([&](auto sc) { readA(sc, Ab[decltype(sc)::value]); });
     static_for<0, KS>([&](auto sc) {
       constexpr int s = decltype(sc)::value;
-      if constexpr (s + 1 < KS) readA(std::integral_constant<int, s + 1>{}, Ab[(s + 1) & 1]);
+      if constexpr (s + PD < KS) readA(std::integral_constant<int, s + PD>{}, Ab[(s + PD) % NB]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NCO; ++t)
-          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[s][t], Ab[s & 1][m], acc[m][t], 0, 0, 0);
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[s][t], Ab[s % NB][m], acc[m][t], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     });
     // epilogue, as in k_conv_lds
@@ -1397,22 +1399,25 @@ bool conv2c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
   }
 }
 
-template <int CIN, int MODE>
+template <int CIN, int MODE, int PD = 1>
 void conv3c(hipStream_t s, const ConvArgs& a) {
   constexpr int TH = 4, TW = 32, ZM = 8;
   const size_t lds = (size_t)4 * (TH + 2) * (TW + 2) * (CIN == 8 ? 8 : CIN + 8) * sizeof(bf16);
   const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * ((a.D + ZM - 1) / ZM));
-  hipLaunchKernelGGL((k_conv3c<CIN, 1, TH, TW, MODE, ZM>), grid, dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_conv3c<CIN, 1, TH, TW, MODE, ZM, PD>), grid, dim3(256), lds, s, a);
 }
 
-// The channel-specialised kernels of the 3D network's marching layers (the generic
-// kernel's 4 x 32 tile and 8 planes per block); false when the layer has none.
+// The channel-specialised kernels of the 3D network's layers with plain or
+// upsample-and-skip inputs (the generic marching kernel's 4 x 32 tile and 8 planes per
+// block; B1, whose weights exceed the L1, marches here too, with one wavefront per SIMD
+// and its operands read three k-steps ahead); false when the layer has none.
 bool conv3c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
   if (a.kpad != (27 * a.cin + 31) / 32 * 32 || nco != 1 || a.src.pool) return false;
   const int mode = a.src.cup > 0 ? 2 : 0;
   switch ((a.cin << 4) | mode) {
     case (8 << 4) | 0: conv3c<8, 0>(s, a); return true;    // A0
     case (32 << 4) | 2: conv3c<32, 2>(s, a); return true;  // B0
+    case (48 << 4) | 2: conv3c<48, 2, 3>(s, a); return true;  // B1
     case (16 << 4) | 0: conv3c<16, 0>(s, a); return true;  // O
     default: return false;
   }
