@@ -679,6 +679,176 @@ __global__ __launch_bounds__(256) void k_conv2c(ConvArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- conv, 2D marching form
+// k_conv2c's sums (outputs equal bit for bit) for 2D layers with plain or
+// upsample-and-skip inputs: every k-step's weights sit in registers (loaded once per
+// block), a block walks NIT tiles down one column, the next tile's halo is loaded into
+// registers while the current tile is computed, and the A operands are read PD k-steps
+// ahead.  Used for the level-0 decoder layer (48 -> 16), whose halo loads k_conv2c
+// waits for: 783 -> 701 us at 60 x 577^2 with 16 tiles per block.  The first layer and
+// the output layer ran slower marching (238 -> 328 and 317 -> 323 us), and so did the
+// 96 -> 32 layer with its 27 k-steps of weights in registers at one wavefront per SIMD
+// (534 -> 710 us, against k_conv2c's weights through LDS at three blocks per CU).
+template <int CIN, int NCO, int TH, int TW, int MODE, int NIT, int PD>
+__global__ __launch_bounds__(256) void k_conv2m(ConvArgs a) {
+  constexpr int PS = CIN == 8 ? 8 : CIN + 8, CG8 = CIN / 8;
+  constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64;
+  constexpr int KS = (9 * CIN + 31) / 32, KPAD = 32 * KS;
+  static_assert(CIN % 8 == 0 && MT % SEG == 0 && MODE != 1, "whole channel groups and tile rows; no pooled input");
+  extern __shared__ __align__(16) bf16 tile[];
+  const int tid = threadIdx.x, l = tid % 64, g = l / 16, i16 = l % 16;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int H = a.H, W = a.W, x0 = blockIdx.x * TW, ty0 = blockIdx.y * NIT;
+  const int ntile = min(NIT, (H + TH - 1) / TH - ty0);  // uniform
+  const long long img = blockIdx.z;
+  const NetSrc& sr = a.src;
+  const bf16* in_img = sr.in + img * ((long long)H * W * sr.in_ct) + sr.in_off;
+  const int Hu = (H + 1) / 2, Wu = (W + 1) / 2;
+  const bf16* up_img = MODE == 2 ? sr.up + img * ((long long)Hu * Wu * sr.up_ct) : nullptr;
+  bf16x8 Bw[KS][NCO];
+  {
+    const bf16* wrow = a.wt + i16 * KPAD + 8 * g;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) Bw[s][t] = load8(wrow + t * 16 * KPAD + 32 * s);
+  }
+
+  // ---- halo staging by halo row, as in k_conv2c (all rows in one batch)
+  constexpr int RW = TW2 * CG8, NP = (RW + 255) / 256, RPP = RW <= 256 ? 256 / RW : 1;
+  constexpr int NRI = (TH + 2 + RPP - 1) / RPP;
+  const int r0 = RW <= 256 ? tid / RW : 0;
+  const bf16* colp[NP];
+  int dst0[NP];
+  bool act[NP], xin[NP], isup[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int j = RW <= 256 ? tid - r0 * RW : tid + 256 * p;
+    act[p] = RW <= 256 ? r0 < RPP : j < RW;
+    const int c = min(j / CG8, TW2 - 1), cg = j - (j / CG8) * CG8;
+    const int xx = x0 - 1 + c, xc = min(max(xx, 0), W - 1);
+    xin[p] = xx >= 0 && xx < W;
+    dst0[p] = (r0 * TW2 + c) * PS + cg * 8;
+    isup[p] = MODE == 2 && cg * 8 < sr.cup;
+    colp[p] = isup[p] ? up_img + (xc >> 1) * sr.up_ct + cg * 8 : in_img + xc * sr.in_ct + (cg * 8 - sr.cup);
+  }
+  typedef bf16x8 HaloRegs[NRI][NP];
+  auto load_tile = [&](int y0, HaloRegs& v, bool (&ok)[NRI]) {
+#pragma unroll
+    for (int i = 0; i < NRI; ++i) {
+      const int r = min(r0 + i * RPP, TH + 1), yy = y0 - 1 + r, yc = min(max(yy, 0), H - 1);
+      ok[i] = yy >= 0 && yy < H;
+      const int oin = yc * W * sr.in_ct, oup = MODE == 2 ? (yc >> 1) * Wu * sr.up_ct : 0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) v[i][p] = load8(colp[p] + (isup[p] ? oup : oin));
+    }
+  };
+  auto store_tile = [&](const HaloRegs& v, const bool (&ok)[NRI]) {
+#pragma unroll
+    for (int i = 0; i < NRI; ++i) {
+      if (r0 + i * RPP >= TH + 2) continue;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        if (act[p])
+          *reinterpret_cast<bf16x8*>(tile + dst0[p] + i * RPP * TW2 * PS) = (xin[p] && ok[i]) ? v[i][p] : zero8();
+    }
+  };
+  {
+    HaloRegs v;
+    bool ok[NRI];
+    load_tile(ty0 * TH, v, ok);
+    store_tile(v, ok);
+  }
+  __syncthreads();
+
+  const int base0 = ((wave * (MT / SEG)) * TW2 + i16) * PS, base8 = base0 + 8 * g;
+  const bool g1 = g & 1, g2 = g & 2;
+  auto readA = [&](auto sc, bf16x8* A) {
+    constexpr int s = decltype(sc)::value;
+    constexpr int o0 = conv_tap_off<CIN, TW2, PS>(s, 0), o1 = conv_tap_off<CIN, TW2, PS>(s, 1);
+    constexpr int o2 = conv_tap_off<CIN, TW2, PS>(s, 2), o3 = conv_tap_off<CIN, TW2, PS>(s, 3);
+    int off;
+    if constexpr (o1 == o0 + 8 && o2 == o0 + 16 && o3 == o0 + 24)
+      off = base8 + o0;
+    else
+      off = base0 + (g2 ? (g1 ? o3 : o2) : (g1 ? o1 : o0));
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      A[m] = *reinterpret_cast<const bf16x8*>(tile + off + ((m / SEG) * TW2 + (m % SEG) * 16) * PS);
+  };
+  const int cout = a.cout;
+  const long long oimg = img * ((long long)H * W * a.out_ct) + a.out_off;
+  HaloRegs vn;
+  bool kn[NRI];
+  for (int it = 0; it < ntile; ++it) {
+    const int y0 = (ty0 + it) * TH;
+    const bool more = it + 1 < ntile;  // uniform
+    if (more) load_tile(y0 + TH, vn, kn);  // in flight during the tile's GEMM
+    f32x4 acc[MT][NCO];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    constexpr int NB = PD + 1;
+    bf16x8 Ab[NB][MT];
+    static_for<0, (PD < KS ? PD : KS)>([&](auto sc) { readA(sc, Ab[decltype(sc)::value]); });
+    static_for<0, KS>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if constexpr (s + PD < KS) readA(std::integral_constant<int, s + PD>{}, Ab[(s + PD) % NB]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NCO; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bw[s][t], Ab[s % NB][m], acc[m][t], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    // epilogue, as in k_conv_lds
+    float bsv[NCO][4];
+#pragma unroll
+    for (int t = 0; t < NCO; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = t * 16 + 4 * g + q;
+        bsv[t][q] = (a.bias && ch < cout) ? a.bias[ch] : 0.f;
+      }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int y = y0 + wave * (MT / SEG) + m / SEG, xo = x0 + (m % SEG) * 16 + i16;
+      if (y >= H || xo >= W) continue;
+      const int po = (y * W + xo) * a.out_ct;  // inside the image
+#pragma unroll
+      for (int t = 0; t < NCO; ++t) {
+        const int c0 = t * 16 + 4 * g;
+        if (c0 >= cout) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = acc[m][t][q] + bsv[t][q];
+          if (a.relu) v[q] = fmaxf(v[q], 0.f);
+        }
+        if (a.out32) {
+          float* dst = a.out32 + oimg + po + c0;
+          if (c0 + 4 <= cout) *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+          else
+            for (int q = 0; q < cout - c0; ++q) dst[q] = v[q];
+        } else {
+          typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+          bf16x4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o[q] = (bf16)v[q];
+          *reinterpret_cast<bf16x4*>(a.out + oimg + po + c0) = o;
+        }
+      }
+    }
+    __syncthreads();  // every wavefront done with the tile's halo
+    if (more) {
+      store_tile(vn, kn);
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- conv, channel-specialised (3D)
 // 3D layers with plain or upsample-and-skip inputs, CIN fixed at compile time: the
 // products and sums of k_conv_lds (whose marching form these follow) in the same order,
@@ -1379,6 +1549,15 @@ void conv2c(hipStream_t s, const ConvArgs& a) {
   hipLaunchKernelGGL((k_conv2c<CIN, NCO, TH, TW, MODE, WL>), grid, dim3(256), lds, s, a);
 }
 
+template <int CIN, int NCO, int TH, int MODE, int NIT, int PD>
+void conv2m(hipStream_t s, const ConvArgs& a) {
+  constexpr int TW = 32;
+  const size_t lds = (size_t)(TH + 2) * (TW + 2) * (CIN == 8 ? 8 : CIN + 8) * sizeof(bf16);
+  const int ty = (a.H + TH - 1) / TH;
+  const dim3 grid((a.W + TW - 1) / TW, (ty + NIT - 1) / NIT, a.nimg);
+  hipLaunchKernelGGL((k_conv2m<CIN, NCO, TH, TW, MODE, NIT, PD>), grid, dim3(256), lds, s, a);
+}
+
 // The channel-specialised kernels of the 2D network's forward layers (their tile shapes
 // those of the generic kernel); false when the layer has none.  The pooled 16-channel
 // layer (A1) stays on the generic kernel: its specialised form, holding 40 weight
@@ -1393,7 +1572,7 @@ bool conv2c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
     case (64 << 8) | (4 << 4) | 1: conv2c<64, 4, 8, 1>(s, a); return true;     // A3
     case (128 << 8) | (4 << 4) | 2: conv2c<128, 4, 4, 2>(s, a); return true;   // B2
     case (96 << 8) | (2 << 4) | 2: conv2c<96, 2, 4, 2>(s, a); return true;     // B1
-    case (48 << 8) | (1 << 4) | 2: conv2c<48, 1, 8, 2>(s, a); return true;     // B0
+    case (48 << 8) | (1 << 4) | 2: conv2m<48, 1, 8, 2, 16, 1>(s, a); return true;     // B0 (marching)
     case (16 << 8) | (1 << 4) | 0: conv2c<16, 1, 8, 0>(s, a); return true;     // O
     default: return false;
   }

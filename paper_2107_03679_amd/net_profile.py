@@ -95,7 +95,7 @@ def summarize(args) -> None:
     convs = []
     with open(path) as fh:
         for r in csv.DictReader(fh):
-            if any(k in r["Kernel_Name"] for k in ("k_conv_lds", "k_conv2c", "k_conv3c")):
+            if any(k in r["Kernel_Name"] for k in ("k_conv_lds", "k_conv2c", "k_conv2m", "k_conv3c")):
                 convs.append((r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0],
                               int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     napp = len(convs) // len(LAYERS)
