@@ -850,7 +850,7 @@ __global__ __launch_bounds__(256) void k_conv2m(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------- conv, channel-specialised (3D)
-// 3D layers with plain or upsample-and-skip inputs, CIN fixed at compile time: the
+// 3D layers (plain, pooled or upsample-and-skip inputs), CIN fixed at compile time: the
 // products and sums of k_conv_lds (whose marching form these follow) in the same order,
 // so the outputs are equal bit for bit, with the index arithmetic at compile time as in
 // k_conv2c.  A block computes ZM output planes of a TH x TW tile; four plane slots hold
@@ -873,7 +873,7 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
   constexpr int PS = CIN == 8 ? 8 : CIN + 8, CG8 = CIN / 8;
   constexpr int TW2 = TW + 2, SEG = TW / 16, MT = TH * TW / 64, PLANE = (TH + 2) * TW2, SLOT = PLANE * PS;
   constexpr int KS = (27 * CIN + 31) / 32, KPAD = 32 * KS;
-  static_assert(CIN % 8 == 0 && MT % SEG == 0 && MODE != 1, "whole channel groups and tile rows; no pooled input");
+  static_assert(CIN % 8 == 0 && MT % SEG == 0, "whole channel groups and tile rows");
   extern __shared__ __align__(16) bf16 tile[];
   const int tid = threadIdx.x, l = tid % 64, g = l / 16, i16 = l % 16;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -882,7 +882,8 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
   const long long img = blockIdx.z / nzb;
   const int z0 = (int)(blockIdx.z % nzb) * ZM, zend = min(D, z0 + ZM);
   const NetSrc& sr = a.src;
-  const bf16* in_img = sr.in + img * ((long long)D * H * W * sr.in_ct) + sr.in_off;
+  // MODE 1: the 2 x 2 x 2 average (zero padding) of the source at Ds x Hs x Ws
+  const bf16* in_img = sr.in + img * ((long long)(MODE == 1 ? (long long)sr.Ds * sr.Hs * sr.Ws : (long long)D * H * W) * sr.in_ct) + sr.in_off;
   const int Du = (D + 1) / 2, Hu = (H + 1) / 2, Wu = (W + 1) / 2;
   const bf16* up_img = MODE == 2 ? sr.up + img * ((long long)Du * Hu * Wu * sr.up_ct) : nullptr;
   // every k-step's weight fragments in registers, loaded once per block (the LDS of the
@@ -900,9 +901,10 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
   constexpr int RW = TW2 * CG8, NP = (RW + 255) / 256, RPP = RW <= 256 ? 256 / RW : 1;
   constexpr int NRI = (TH + 2 + RPP - 1) / RPP;
   const int r0 = RW <= 256 ? tid / RW : 0;
+  constexpr int NSRC = MODE == 1 ? 8 : 1;
   const bf16* colp[NP];
-  int dst0[NP];
-  bool act[NP], xin[NP], isup[NP];
+  int dst0[NP], dxp[NP];
+  bool act[NP], xin[NP], isup[NP], hx[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int j = RW <= 256 ? tid - r0 * RW : tid + 256 * p;
@@ -912,36 +914,93 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
     xin[p] = xx >= 0 && xx < W;
     dst0[p] = (r0 * TW2 + c) * PS + cg * 8;
     isup[p] = MODE == 2 && cg * 8 < sr.cup;
-    colp[p] = isup[p] ? up_img + (xc >> 1) * sr.up_ct + cg * 8 : in_img + xc * sr.in_ct + (cg * 8 - sr.cup);
+    dxp[p] = MODE == 1 && 2 * xc + 1 < sr.Ws ? sr.in_ct : 0;
+    hx[p] = 2 * xx + 1 < sr.Ws;
+    if (MODE == 1)
+      colp[p] = in_img + 2 * xc * sr.in_ct + cg * 8;
+    else
+      colp[p] = isup[p] ? up_img + (xc >> 1) * sr.up_ct + cg * 8 : in_img + xc * sr.in_ct + (cg * 8 - sr.cup);
   }
-  typedef bf16x8 PlaneRegs[NRI][NP];
-  auto load_plane = [&](int zz, PlaneRegs& v, bool (&ok)[NRI]) {
+  // a plane's loads; fl[i]: bit 0 the row is inside the layer, bits 1 and 2 (pooled input)
+  // the second child along y and along z lies inside the source
+  typedef bf16x8 PlaneRegs[NRI][NP][NSRC];
+  auto load_plane = [&](int zz, PlaneRegs& v, int (&fl)[NRI]) {
     const int zc = min(max(zz, 0), D - 1);
     const bool zin = zz >= 0 && zz < D;
+    const long long dz = MODE == 1 && 2 * zc + 1 < sr.Ds ? (long long)sr.Hs * sr.Ws * sr.in_ct : 0;
+    const int hz = MODE == 1 && 2 * zz + 1 < sr.Ds ? 4 : 0;
 #pragma unroll
     for (int i = 0; i < NRI; ++i) {
       const int r = min(r0 + i * RPP, TH + 1), yy = y0 - 1 + r, yc = min(max(yy, 0), H - 1);
-      ok[i] = zin && yy >= 0 && yy < H;
-      const long long oin = ((long long)zc * H + yc) * W * sr.in_ct;
-      const long long oup = MODE == 2 ? ((long long)(zc >> 1) * Hu + (yc >> 1)) * Wu * sr.up_ct : 0;
+      fl[i] = (zin && yy >= 0 && yy < H ? 1 : 0) | (MODE == 1 && 2 * yy + 1 < sr.Hs ? 2 : 0) | hz;
+      if (MODE == 1) {
+        const long long dy = 2 * yc + 1 < sr.Hs ? (long long)sr.Ws * sr.in_ct : 0;
+        const long long o = ((long long)2 * zc * sr.Hs + 2 * yc) * sr.Ws * sr.in_ct;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) v[i][p] = load8(colp[p] + (isup[p] ? oup : oin));
+        for (int p = 0; p < NP; ++p) {
+          const bf16* q = colp[p] + o;
+          v[i][p][0] = load8(q);
+          v[i][p][NSRC > 1 ? 1 : 0] = load8(q + dxp[p]);
+          v[i][p][NSRC > 2 ? 2 : 0] = load8(q + dy);
+          v[i][p][NSRC > 3 ? 3 : 0] = load8(q + dy + dxp[p]);
+          v[i][p][NSRC > 4 ? 4 : 0] = load8(q + dz);
+          v[i][p][NSRC > 5 ? 5 : 0] = load8(q + dz + dxp[p]);
+          v[i][p][NSRC > 6 ? 6 : 0] = load8(q + dz + dy);
+          v[i][p][NSRC > 7 ? 7 : 0] = load8(q + dz + dy + dxp[p]);
+        }
+      } else {
+        const long long oin = ((long long)zc * H + yc) * W * sr.in_ct;
+        const long long oup = MODE == 2 ? ((long long)(zc >> 1) * Hu + (yc >> 1)) * Wu * sr.up_ct : 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) v[i][p][0] = load8(colp[p] + (isup[p] ? oup : oin));
+      }
     }
   };
-  auto store_plane = [&](int slot, const PlaneRegs& v, const bool (&ok)[NRI]) {
+  auto store_plane = [&](int slot, const PlaneRegs& v, const int (&fl)[NRI]) {
 #pragma unroll
     for (int i = 0; i < NRI; ++i) {
       if (r0 + i * RPP >= TH + 2) continue;
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
-        if (act[p])
-          *reinterpret_cast<bf16x8*>(tile + slot * SLOT + dst0[p] + i * RPP * TW2 * PS) =
-              (xin[p] && ok[i]) ? v[i][p] : zero8();
+      for (int p = 0; p < NP; ++p) {
+        if (!act[p]) continue;
+        bf16x8 o;
+        if (MODE == 1) {
+          // average with zero padding, as in k_conv_lds: children past the source edge count 0
+          const bool bx = hx[p], by = fl[i] & 2, bz = fl[i] & 4;
+          const float w1 = bx ? 1.f : 0.f, w2 = by ? 1.f : 0.f, w3 = (bx && by) ? 1.f : 0.f;
+          const float w4 = bz ? 1.f : 0.f, w5 = bz && bx ? 1.f : 0.f, w6 = bz && by ? 1.f : 0.f,
+                      w7 = bz && bx && by ? 1.f : 0.f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float acc = (float)v[i][p][0][e];
+            acc += w1 * (float)v[i][p][NSRC > 1 ? 1 : 0][e];
+            acc += w2 * (float)v[i][p][NSRC > 2 ? 2 : 0][e];
+            acc += w3 * (float)v[i][p][NSRC > 3 ? 3 : 0][e];
+            acc += w4 * (float)v[i][p][NSRC > 4 ? 4 : 0][e];
+            acc += w5 * (float)v[i][p][NSRC > 5 ? 5 : 0][e];
+            acc += w6 * (float)v[i][p][NSRC > 6 ? 6 : 0][e];
+            acc += w7 * (float)v[i][p][NSRC > 7 ? 7 : 0][e];
+            o[e] = (bf16)(0.125f * acc);
+          }
+        } else {
+          o = v[i][p][0];
+        }
+        *reinterpret_cast<bf16x8*>(tile + slot * SLOT + dst0[p] + i * RPP * TW2 * PS) =
+            (xin[p] && (fl[i] & 1)) ? o : zero8();
+      }
     }
   };
-  {
+  if constexpr (MODE == 1) {
+    // eight sources per chunk: one plane at a time
+    for (int k = 0; k < 3; ++k) {
+      PlaneRegs v;
+      int f[NRI];
+      load_plane(z0 - 1 + k, v, f);
+      store_plane(k, v, f);
+    }
+  } else {
     PlaneRegs v0, v1, v2;
-    bool k0[NRI], k1[NRI], k2[NRI];
+    int k0[NRI], k1[NRI], k2[NRI];
     load_plane(z0 - 1, v0, k0);
     load_plane(z0, v1, k1);
     load_plane(z0 + 1, v2, k2);
@@ -956,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_conv3c(ConvArgs a) {
   const int cout = a.cout;
   const long long oimg = img * ((long long)D * H * W * a.out_ct) + a.out_off;
   PlaneRegs vn;
-  bool kn[NRI];
+  int kn[NRI];
   for (int zc = z0; zc < zend; ++zc) {
     const int iz = zc - z0;
     const bool more = zc + 1 < zend;  // uniform
@@ -1586,14 +1645,16 @@ void conv3c(hipStream_t s, const ConvArgs& a) {
   hipLaunchKernelGGL((k_conv3c<CIN, 1, TH, TW, MODE, ZM, PD>), grid, dim3(256), lds, s, a);
 }
 
-// The channel-specialised kernels of the 3D network's layers with plain or
-// upsample-and-skip inputs (the generic marching kernel's 4 x 32 tile and 8 planes per
-// block; B1, whose weights exceed the L1, marches here too, with one wavefront per SIMD
-// and its operands read three k-steps ahead); false when the layer has none.
+// The channel-specialised kernels of the 3D network's layers of one 16-channel output
+// tile (the generic marching kernel's 4 x 32 tile and 8 planes per block).  B1, whose
+// weights exceed the L1, and the pooled A1 march here too, where the generic kernel
+// stages three planes per output plane; B1 runs one wavefront per SIMD and reads its
+// operands three k-steps ahead.  False when the layer has none.
 bool conv3c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
-  if (a.kpad != (27 * a.cin + 31) / 32 * 32 || nco != 1 || a.src.pool) return false;
-  const int mode = a.src.cup > 0 ? 2 : 0;
+  if (a.kpad != (27 * a.cin + 31) / 32 * 32 || nco != 1) return false;
+  const int mode = a.src.pool ? 1 : (a.src.cup > 0 ? 2 : 0);
   switch ((a.cin << 4) | mode) {
+    case (16 << 4) | 1: conv3c<16, 1>(s, a); return true;  // A1 (pooled input)
     case (8 << 4) | 0: conv3c<8, 0>(s, a); return true;    // A0
     case (32 << 4) | 2: conv3c<32, 2>(s, a); return true;  // B0
     case (48 << 4) | 2: conv3c<48, 2, 3>(s, a); return true;  // B1
