@@ -393,7 +393,7 @@ int helm_net_create3(unsigned long long seed, void* hip_stream, helm_net** out);
 int helm_net_dim(const helm_net* net);                                      /* 2 or 3 */
 /* Convolution kernels: generic = 0 (default) runs each layer that has one on a kernel
  * specialised for its input channel count (the 2D network's forward layers but the
- * pooled 16-channel one; the 3D network's layers A0, A1, B1, B0 and O), generic = 1
+ * pooled 16-channel one; the 3D network's layers but A3 and B2), generic = 1
  * every layer on the channel-generic kernels.  Both compute the same sums in the same
  * order, so outputs agree bit for bit; the switch is for tests and measurements.
  * HELM_EINVAL for a generic value other than 0 or 1. */

@@ -1637,22 +1637,30 @@ bool conv2c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
   }
 }
 
-template <int CIN, int MODE, int PD = 1>
+template <int CIN, int MODE, int PD = 1, int NCO = 1>
 void conv3c(hipStream_t s, const ConvArgs& a) {
   constexpr int TH = 4, TW = 32, ZM = 8;
   const size_t lds = (size_t)4 * (TH + 2) * (TW + 2) * (CIN == 8 ? 8 : CIN + 8) * sizeof(bf16);
   const dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, a.nimg * ((a.D + ZM - 1) / ZM));
-  hipLaunchKernelGGL((k_conv3c<CIN, 1, TH, TW, MODE, ZM, PD>), grid, dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_conv3c<CIN, NCO, TH, TW, MODE, ZM, PD>), grid, dim3(256), lds, s, a);
 }
 
-// The channel-specialised kernels of the 3D network's layers of one 16-channel output
-// tile (the generic marching kernel's 4 x 32 tile and 8 planes per block).  B1, whose
-// weights exceed the L1, and the pooled A1 march here too, where the generic kernel
-// stages three planes per output plane; B1 runs one wavefront per SIMD and reads its
-// operands three k-steps ahead.  False when the layer has none.
+// The channel-specialised kernels of the 3D network's layers (the generic marching
+// kernel's 4 x 32 tile and 8 planes per block).  B1, whose weights exceed the L1, and
+// the pooled A1 and A2 march here too, where the generic kernel stages three planes per
+// output plane; B1 runs one wavefront per SIMD and reads its operands three k-steps
+// ahead.  False when the layer has none (A3 and B2: weights of 55 and 110 KB).
 bool conv3c_dispatch(hipStream_t s, const ConvArgs& a, int nco) {
-  if (a.kpad != (27 * a.cin + 31) / 32 * 32 || nco != 1) return false;
+  if (a.kpad != (27 * a.cin + 31) / 32 * 32) return false;
   const int mode = a.src.pool ? 1 : (a.src.cup > 0 ? 2 : 0);
+  if (nco == 2) {
+    if (a.cin == 16 && mode == 1) {
+      conv3c<16, 1, 1, 2>(s, a);  // A2 (pooled input, two output tiles)
+      return true;
+    }
+    return false;
+  }
+  if (nco != 1) return false;
   switch ((a.cin << 4) | mode) {
     case (16 << 4) | 1: conv3c<16, 1>(s, a); return true;  // A1 (pooled input)
     case (8 << 4) | 0: conv3c<8, 0>(s, a); return true;    // A0

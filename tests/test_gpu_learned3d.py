@@ -54,7 +54,7 @@ def test_forward_matches_reference(net3, shape):
 
 @pytest.mark.parametrize("shape", [(2, 9, 11, 13), (1, 19, 22, 37), (1, 64, 64, 64)])
 def test_specialised_convolutions_match_generic_3d(net3, shape):
-    """The channel-specialised marching 3D convolutions (A0, A1, B1, B0, O) form the generic
+    """The channel-specialised marching 3D convolutions (all layers but A3 and B2) form the generic
     kernel's sums in the same order: forward outputs agree bit for bit (depths that are
     not multiples of the 8 planes a block marches through, ragged tiles)."""
     net, _ = net3
