@@ -1129,19 +1129,36 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   const int dy = tp / 3 - 1, dx = tp % 3 - 1;
   const int co = ct * 16 + i16;                    // B column of this lane
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // pixel (img, pz, py, px) of this lane's first element, advanced by one pixel per
+  // element and by 32 per step instead of divided out of p each time
+  long long img0;
+  int px0, py0, pz0;
+  {
+    const long long p = p_begin + 8 * gq;
+    px0 = (int)(p % a.W);
+    const long long r = p / a.W;
+    py0 = (int)(r % a.H);
+    const long long r2 = r / a.H;
+    pz0 = NDIM == 3 ? (int)(r2 % D) : 0;
+    img0 = NDIM == 3 ? r2 / D : r2;
+  }
+  auto next_row = [&](int& py, int& pz, long long& img) {
+    if (++py == a.H) {
+      py = 0;
+      if (NDIM == 3 && ++pz < D) return;
+      pz = 0;
+      ++img;
+    }
+  };
   for (long long pc = p_begin; pc < p_end; pc += 32) {
     bf16x8 av, bv;
+    int px = px0, py = py0, pz = pz0;
+    long long img = img0;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const long long p = pc + 8 * gq + v;
       float xa = 0.f, gb = 0.f;
       if (p < p_end) {
-        const int px = (int)(p % a.W);
-        const long long r = p / a.W;
-        const int py = (int)(r % a.H);
-        const long long r2 = r / a.H;
-        const int pz = NDIM == 3 ? (int)(r2 % D) : 0;
-        const long long img = NDIM == 3 ? r2 / D : r2;
         const int zz = pz + dz, yy = py + dy, xx = px + dx;
         if (tap < NT && zz >= 0 && zz < D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
           xa = fetch1<NDIM>(a.src, img, D, a.H, a.W, zz, yy, xx, ci);
@@ -1149,8 +1166,17 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       }
       av[v] = (__bf16)xa;
       bv[v] = (__bf16)gb;
+      if (++px == a.W) {
+        px = 0;
+        next_row(py, pz, img);
+      }
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    px0 += 32;
+    while (px0 >= a.W) {
+      px0 -= a.W;
+      next_row(py0, pz0, img0);
+    }
   }
   // D[i][j]: i = k row (4 gq + r), j = co column (i16)
 #pragma unroll
@@ -1179,7 +1205,16 @@ __global__ __launch_bounds__(256) void k_bias_part(long long P, int n, const bf1
   const int c = threadIdx.x % g_ct, lane = threadIdx.x / g_ct, lanes = 256 / g_ct;
   const long long p0 = (long long)blockIdx.x * n, p1 = min(p0 + n, P);
   float s = 0.f;
-  for (long long p = p0 + lane; p < p1; p += lanes) s += (float)g[p * g_ct + c];
+  long long p = p0 + lane;
+  // 16 loads in flight, added in the order of p
+  for (; p + 15 * lanes < p1; p += 16 * lanes) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = (float)g[(p + u * lanes) * g_ct + c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  for (; p < p1; p += lanes) s += (float)g[p * g_ct + c];
   red[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x < cout) {
